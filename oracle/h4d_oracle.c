@@ -1,0 +1,661 @@
+/*
+ * h4d_oracle.c -- plain FP64 CPU reference of the H4D ion-pair exchange
+ * (Kim, Belloni & Rotenberg, arXiv 2307.11447).
+ *
+ * TEST INFRASTRUCTURE ONLY: called by the tests, the smoke check and the
+ * CPU-baseline leg of the benchmark; never by the product library.  It
+ * shares no code with the GPU path.  Slow on purpose: every energy or force
+ * evaluation re-enumerates the pairs, all sums run left to right in FP64.
+ *
+ * Physics (one pair i<j, minimum image r_ij):
+ *   s^2 = |r_ij|^2 + (w_i - w_j)^2, w = altitude of a flyer, 0 otherwise
+ *     (the 4D distance of Sec. I and Sec. II D);
+ *   truncated and shifted Lennard-Jones, Eq. (19), force not shifted,
+ *     Lorentz-Berthelot mixing (Sec. II E 2);
+ *   damped shifted force Coulomb (Fennell & Gezelter 2006), the
+ *     Wolf-family real-space-only electrostatics mentioned in Sec. II B 2,
+ *     multiplied by g = exp(-kappa_sr * w) when exactly one of i, j is
+ *     flying (short-range screening, Eq. 11);
+ *   intramolecular pairs of a rigid water are excluded.
+ */
+#include "h4d_oracle.h"
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------ */
+/* Philox4x64-10 from its published definition (Salmon, Moraes, Dror & */
+/* Shaw, "Parallel random numbers: as easy as 1, 2, 3", SC'11).        */
+/* ------------------------------------------------------------------ */
+void or_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4])
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+    uint64_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { k0 += W0; k1 += W1; }
+        __uint128_t p0 = (__uint128_t)M0 * x0;
+        __uint128_t p1 = (__uint128_t)M1 * x2;
+        uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+        uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+        uint64_t y0 = hi1 ^ x1 ^ k0;
+        uint64_t y1 = lo1;
+        uint64_t y2 = hi0 ^ x3 ^ k1;
+        uint64_t y3 = lo0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* The top 52 random bits -> uniform in the open interval (0, 1): the
+ * midpoints (m + 1/2) 2^-52 are exact doubles, the largest is 1 - 2^-53. */
+double or_u01(uint64_t bits)
+{
+    return ((double)(bits >> 12) + 0.5) * 0x1p-52;
+}
+
+static void draw4(const or_params *p, uint64_t a, uint64_t b, uint64_t c, double u[4])
+{
+    uint64_t ctr[4] = {a, b, c, 0}, key[2] = {p->seed, p->stream}, o[4];
+    or_philox4x64(ctr, key, o);
+    for (int i = 0; i < 4; ++i) u[i] = or_u01(o[i]);
+}
+
+/* Counter purposes. */
+enum { PURPOSE_SELECT = 1, PURPOSE_MB = 2, PURPOSE_NSTEPS = 3 };
+
+/* ------------------------------------------------------------------ */
+/* Geometry                                                            */
+/* ------------------------------------------------------------------ */
+static double wrap1(double x, double L)
+{
+    double y = x - L * floor(x / L);
+    if (y >= L) y -= L;
+    return y;
+}
+
+static double minimg(double d, double L)
+{
+    return d - L * nearbyint(d / L);
+}
+
+/* ------------------------------------------------------------------ */
+/* Pair potential                                                      */
+/* ------------------------------------------------------------------ */
+int or_pair(const or_params *p, int ti, int tj, double s2, double g,
+            double *u_lj, double *u_c, double *dlj_ds, double *dc_ds)
+{
+    *u_lj = 0.0; *u_c = 0.0; *dlj_ds = 0.0; *dc_ds = 0.0;
+    if (ti < 0 || tj < 0 || ti >= p->n_types || tj >= p->n_types) return -1;
+    const double s = sqrt(s2);
+    /* Eq. (19): truncated and shifted LJ, Lorentz-Berthelot mixing. */
+    const double sig = 0.5 * (p->sigma[ti] + p->sigma[tj]);
+    const double eps = sqrt(p->eps[ti] * p->eps[tj]);
+    if (eps > 0.0 && s < p->rc_lj) {
+        const double a = pow(sig / s, 6.0);
+        const double ac = pow(sig / p->rc_lj, 6.0);
+        *u_lj = 4.0 * eps * (a * a - a - ac * ac + ac);
+        *dlj_ds = 4.0 * eps * (-12.0 * a * a + 6.0 * a) / s;
+    }
+    /* Damped shifted force Coulomb. */
+    const double qq = p->charge[ti] * p->charge[tj];
+    if (qq != 0.0 && s < p->rc_coul) {
+        const double al = p->alpha, Rc = p->rc_coul;
+        const double erfc_c = erfc(al * Rc);
+        const double Sc = erfc_c / (Rc * Rc) + 2.0 * al / sqrt(M_PI) * exp(-al * al * Rc * Rc) / Rc;
+        const double u = p->ke * qq * (erfc(al * s) / s - erfc_c / Rc + Sc * (s - Rc));
+        const double du = p->ke * qq * (-erfc(al * s) / (s * s)
+                                        - 2.0 * al / sqrt(M_PI) * exp(-al * al * s * s) / s + Sc);
+        *u_c = g * u;
+        *dc_ds = g * du;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Pair enumeration: all pairs i<j with 3D minimum-image r < rcut      */
+/* (a superset of the pairs within the 4D cutoff, since s >= r).       */
+/* ------------------------------------------------------------------ */
+typedef struct { int32_t *i, *j; int64_t n, cap; } pairlist;
+
+static int pl_push(pairlist *pl, int i, int j)
+{
+    if (pl->n == pl->cap) {
+        int64_t nc = pl->cap ? 2 * pl->cap : 4096;
+        int32_t *ni = realloc(pl->i, nc * sizeof(int32_t));
+        if (!ni) return -1;
+        pl->i = ni;
+        int32_t *nj = realloc(pl->j, nc * sizeof(int32_t));
+        if (!nj) return -1;
+        pl->j = nj;
+        pl->cap = nc;
+    }
+    pl->i[pl->n] = i; pl->j[pl->n] = j; pl->n++;
+    return 0;
+}
+
+static void pl_free(pairlist *pl) { free(pl->i); free(pl->j); }
+
+static int excluded(const or_state *s, int i, int j)
+{
+    return s->mol[i] >= 0 && s->mol[i] == s->mol[j];
+}
+
+static double r2_of(const or_params *p, const or_state *s, int i, int j)
+{
+    double r2 = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        double dd = minimg(s->x[3 * i + d] - s->x[3 * j + d], p->box[d]);
+        r2 += dd * dd;
+    }
+    return r2;
+}
+
+static int enumerate_pairs(const or_params *p, const or_state *s, double rcut, pairlist *pl)
+{
+    const int n = s->n;
+    const double rc2 = rcut * rcut;
+    int nc[3];
+    int cells = p->use_cells;
+    for (int d = 0; d < 3; ++d) {
+        nc[d] = (int)floor(p->box[d] / rcut);
+        if (nc[d] < 3) cells = 0;
+    }
+    if (!cells) {
+        for (int i = 0; i < n; ++i)
+            for (int j = i + 1; j < n; ++j)
+                if (!excluded(s, i, j) && r2_of(p, s, i, j) < rc2)
+                    if (pl_push(pl, i, j)) return -1;
+        return 0;
+    }
+    /* Linked cells (Allen & Tildesley): head/next lists, 27-cell stencil. */
+    const int ncell = nc[0] * nc[1] * nc[2];
+    int *head = malloc(ncell * sizeof(int));
+    int *next = malloc((n > 0 ? n : 1) * sizeof(int));
+    int *cid = malloc((n > 0 ? n : 1) * sizeof(int));
+    if (!head || !next || !cid) { free(head); free(next); free(cid); return -1; }
+    for (int c = 0; c < ncell; ++c) head[c] = -1;
+    for (int i = n - 1; i >= 0; --i) {
+        int c3[3];
+        for (int d = 0; d < 3; ++d) {
+            int k = (int)floor(s->x[3 * i + d] / p->box[d] * nc[d]);
+            if (k < 0) k = 0;
+            if (k >= nc[d]) k = nc[d] - 1;
+            c3[d] = k;
+        }
+        int c = (c3[2] * nc[1] + c3[1]) * nc[0] + c3[0];
+        cid[i] = c;
+        next[i] = head[c];
+        head[c] = i;
+    }
+    for (int i = 0; i < n; ++i) {
+        int c = cid[i];
+        int cx = c % nc[0], cy = (c / nc[0]) % nc[1], cz = c / (nc[0] * nc[1]);
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    int ax = (cx + dx + nc[0]) % nc[0];
+                    int ay = (cy + dy + nc[1]) % nc[1];
+                    int az = (cz + dz + nc[2]) % nc[2];
+                    int cc = (az * nc[1] + ay) * nc[0] + ax;
+                    for (int j = head[cc]; j >= 0; j = next[j])
+                        if (j > i && !excluded(s, i, j) && r2_of(p, s, i, j) < rc2)
+                            if (pl_push(pl, i, j)) { free(head); free(next); free(cid); return -1; }
+                }
+    }
+    free(head); free(next); free(cid);
+    return 0;
+}
+
+/* Pairs that involve a flyer: flyer x every other atom, flyer-flyer once. */
+static int enumerate_fly_pairs(const or_params *p, const or_state *s, double rcut, pairlist *pl)
+{
+    const double rc2 = rcut * rcut;
+    for (int i = 0; i < s->n; ++i) {
+        if (!s->flying[i]) continue;
+        for (int j = 0; j < s->n; ++j) {
+            if (j == i) continue;
+            if (s->flying[j] && j < i) continue;
+            if (!excluded(s, i, j) && r2_of(p, s, i, j) < rc2)
+                if (pl_push(pl, i < j ? i : j, i < j ? j : i)) return -1;
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Energy and forces                                                   */
+/* ------------------------------------------------------------------ */
+int or_compute(const or_params *p, const or_state *s, double w, int mode,
+               double *F, or_energy *e)
+{
+    memset(e, 0, sizeof(*e));
+    if (F) memset(F, 0, 3 * (size_t)s->n * sizeof(double));
+    const double rcut = p->rc_lj > p->rc_coul ? p->rc_lj : p->rc_coul;
+    /* minimum image is the whole periodic sum only if every edge >= 2 r_cut */
+    for (int d = 0; d < 3; ++d)
+        if (p->box[d] < 2.0 * rcut) return -7;
+    pairlist pl = {0};
+    int rc = (mode == OR_MODE_FLY) ? enumerate_fly_pairs(p, s, rcut, &pl)
+                                   : enumerate_pairs(p, s, rcut, &pl);
+    if (rc) { pl_free(&pl); return -1; }
+    const double gscr = exp(-p->kappa_sr * w);
+    for (int64_t k = 0; k < pl.n; ++k) {
+        const int i = pl.i[k], j = pl.j[k];
+        const int fi = s->flying[i], fj = s->flying[j];
+        if (mode == OR_MODE_EXCL && (fi || fj)) continue;
+        if (mode == OR_MODE_FLY && !(fi || fj)) continue;
+        double r[3], r2 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            r[d] = minimg(s->x[3 * i + d] - s->x[3 * j + d], p->box[d]);
+            r2 += r[d] * r[d];
+        }
+        const double wi = fi ? w : 0.0, wj = fj ? w : 0.0;
+        const double dw = wi - wj;
+        const double s2 = r2 + dw * dw;
+        const int one_flying = (fi != fj);
+        const double g = one_flying ? gscr : 1.0;
+        double ulj, uc, dlj, dc;
+        or_pair(p, s->type[i], s->type[j], s2, g, &ulj, &uc, &dlj, &dc);
+        const double sd = sqrt(s2);
+        const double duds = dlj + dc;
+        e->U_lj += ulj;
+        e->U_c += uc;
+        e->U += ulj + uc;
+        /* F_i = -du/ds * (r_i - r_j)/s, virial sum r_ij . F_ij (3D part). */
+        const double fs = -duds / sd;
+        e->virial += fs * r2;
+        if (F) {
+            for (int d = 0; d < 3; ++d) {
+                F[3 * i + d] += fs * r[d];
+                F[3 * j + d] -= fs * r[d];
+            }
+        }
+        /* dU/dw: ds/dw = w/s for one flyer; dg/dw = -kappa_sr g. */
+        if (one_flying) e->dUdw += duds * (w / sd) - p->kappa_sr * uc;
+    }
+    pl_free(&pl);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Momenta                                                             */
+/* ------------------------------------------------------------------ */
+int or_mb_velocities(const or_params *p, or_state *s, uint64_t trial)
+{
+    /* Maxwell-Boltzmann: each 3D component ~ N(0, kT/m) (Sec. II A);
+     * normals from the Box-Muller transform of two uniforms. */
+    for (int i = 0; i < s->n; ++i) {
+        double u[4];
+        draw4(p, trial, PURPOSE_MB, (uint64_t)s->tag[i], u);
+        const double r01 = sqrt(-2.0 * log(u[0]));
+        const double r23 = sqrt(-2.0 * log(u[2]));
+        const double z[3] = {r01 * cos(2.0 * M_PI * u[1]),
+                             r01 * sin(2.0 * M_PI * u[1]),
+                             r23 * cos(2.0 * M_PI * u[3])};
+        const double sd = sqrt(p->accel * p->kT / p->mass[s->type[i]]);
+        for (int d = 0; d < 3; ++d) s->v[3 * i + d] = sd * z[d];
+    }
+    if (p->water) return or_constrain_velocities(p, s);
+    return 0;
+}
+
+double or_kinetic(const or_params *p, const or_state *s)
+{
+    double K = 0.0;
+    for (int i = 0; i < s->n; ++i) {
+        if (s->flying[i]) continue;
+        const double m = p->mass[s->type[i]];
+        for (int d = 0; d < 3; ++d) K += 0.5 * m * s->v[3 * i + d] * s->v[3 * i + d] / p->accel;
+    }
+    return K;
+}
+
+/* ------------------------------------------------------------------ */
+/* Rigid water: the three distance constraints O-H1, O-H2, H1-H2.      */
+/* Positions: iterate the bond-by-bond correction along the reference  */
+/* bond vectors until every constraint holds to 1e-14 relative (the    */
+/* constraint problem that an analytic solver also solves).            */
+/* ------------------------------------------------------------------ */
+static void bond_list(const or_params *p, int m, int a[3], int b[3], double d[3])
+{
+    const int o = 3 * m;
+    a[0] = o; b[0] = o + 1; d[0] = p->d_oh;
+    a[1] = o; b[1] = o + 2; d[1] = p->d_oh;
+    a[2] = o + 1; b[2] = o + 2; d[2] = p->d_hh;
+}
+
+int or_constrain_positions(const or_params *p, or_state *s, const double *xref)
+{
+    for (int m = 0; m < s->n_mol; ++m) {
+        int a[3], b[3];
+        double d[3], corr[9] = {0};
+        bond_list(p, m, a, b, d);
+        double xl[9];  /* local unwrapped copy, relative to the oxygen */
+        const int o = 3 * m;
+        for (int k = 0; k < 3; ++k)
+            for (int c = 0; c < 3; ++c)
+                xl[3 * k + c] = s->x[3 * o + c] +
+                    (k ? minimg(s->x[3 * (o + k) + c] - s->x[3 * o + c], p->box[c]) : 0.0);
+        int it;
+        for (it = 0; it < 1000; ++it) {
+            int done = 1;
+            for (int q = 0; q < 3; ++q) {
+                const int la = a[q] - o, lb = b[q] - o;
+                double sv[3], rr[3], ss = 0.0, sr = 0.0;
+                for (int c = 0; c < 3; ++c) {
+                    sv[c] = xl[3 * la + c] - xl[3 * lb + c];
+                    rr[c] = minimg(xref[3 * a[q] + c] - xref[3 * b[q] + c], p->box[c]);
+                    ss += sv[c] * sv[c];
+                    sr += sv[c] * rr[c];
+                }
+                const double diff = d[q] * d[q] - ss;
+                if (fabs(diff) > 1e-14 * d[q] * d[q]) done = 0;
+                const double ima = 1.0 / p->mass[s->type[a[q]]], imb = 1.0 / p->mass[s->type[b[q]]];
+                const double gq = diff / (2.0 * sr * (ima + imb));
+                for (int c = 0; c < 3; ++c) {
+                    xl[3 * la + c] += gq * rr[c] * ima;
+                    xl[3 * lb + c] -= gq * rr[c] * imb;
+                    corr[3 * la + c] += gq * rr[c] * ima;
+                    corr[3 * lb + c] -= gq * rr[c] * imb;
+                }
+            }
+            if (done) break;
+        }
+        if (it == 1000) return -2;
+        for (int k = 0; k < 3; ++k)
+            for (int c = 0; c < 3; ++c) {
+                const int i = o + k;
+                s->x[3 * i + c] = wrap1(s->x[3 * i + c] + corr[3 * k + c], p->box[c]);
+                s->v[3 * i + c] += corr[3 * k + c] / p->dt;
+            }
+    }
+    return 0;
+}
+
+/* Velocities: find the three multipliers that make every bond's relative
+ * velocity orthogonal to the bond (a 3x3 linear system, Gaussian
+ * elimination with partial pivoting). */
+int or_constrain_velocities(const or_params *p, or_state *s)
+{
+    for (int m = 0; m < s->n_mol; ++m) {
+        int a[3], b[3];
+        double d[3], r[3][3], A[3][4];
+        bond_list(p, m, a, b, d);
+        for (int q = 0; q < 3; ++q)
+            for (int c = 0; c < 3; ++c)
+                r[q][c] = minimg(s->x[3 * a[q] + c] - s->x[3 * b[q] + c], p->box[c]);
+        for (int k = 0; k < 3; ++k) {
+            /* row k: (v_a' - v_b') . r_k = 0, v_x' = v_x + sum_l lam_l c_{x,l} r_l / m_x */
+            const int pk = a[k], qk = b[k];
+            const double ip = 1.0 / p->mass[s->type[pk]], iq = 1.0 / p->mass[s->type[qk]];
+            for (int l = 0; l < 3; ++l) {
+                const double cp = (pk == a[l]) ? 1.0 : (pk == b[l] ? -1.0 : 0.0);
+                const double cq = (qk == a[l]) ? 1.0 : (qk == b[l] ? -1.0 : 0.0);
+                double dot = 0.0;
+                for (int c = 0; c < 3; ++c) dot += r[l][c] * r[k][c];
+                A[k][l] = dot * (cp * ip - cq * iq);
+            }
+            double rhs = 0.0;
+            for (int c = 0; c < 3; ++c) rhs -= (s->v[3 * pk + c] - s->v[3 * qk + c]) * r[k][c];
+            A[k][3] = rhs;
+        }
+        for (int col = 0; col < 3; ++col) {
+            int piv = col;
+            for (int rr = col + 1; rr < 3; ++rr)
+                if (fabs(A[rr][col]) > fabs(A[piv][col])) piv = rr;
+            if (A[piv][col] == 0.0) return -2;
+            if (piv != col)
+                for (int c = 0; c < 4; ++c) { double t = A[col][c]; A[col][c] = A[piv][c]; A[piv][c] = t; }
+            for (int rr = 0; rr < 3; ++rr) {
+                if (rr == col) continue;
+                const double f = A[rr][col] / A[col][col];
+                for (int c = col; c < 4; ++c) A[rr][c] -= f * A[col][c];
+            }
+        }
+        double lam[3];
+        for (int q = 0; q < 3; ++q) lam[q] = A[q][3] / A[q][q];
+        for (int l = 0; l < 3; ++l) {
+            const double ia = 1.0 / p->mass[s->type[a[l]]], ib = 1.0 / p->mass[s->type[b[l]]];
+            for (int c = 0; c < 3; ++c) {
+                s->v[3 * a[l] + c] += lam[l] * r[l][c] * ia;
+                s->v[3 * b[l] + c] -= lam[l] * r[l][c] * ib;
+            }
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* NEMD                                                                */
+/* ------------------------------------------------------------------ */
+double or_altitude(const or_params *p, int move, int k, int nf)
+{
+    /* Eq. (2), constant vertical velocity: insertion from w_max down to 0,
+     * deletion from 0 up to w_max. */
+    if (move > 0) return p->w_max * (double)(nf - k) / (double)nf;
+    return p->w_max * (double)k / (double)nf;
+}
+
+static double u_fly(const or_params *p, const or_state *s, double w)
+{
+    or_energy e;
+    if (or_compute(p, s, w, OR_MODE_FLY, NULL, &e)) return NAN;
+    return e.U;
+}
+
+int or_nemd(const or_params *p, or_state *s, int move, int nf, double *W)
+{
+    const int n = s->n;
+    double *F = malloc(3 * (size_t)(n > 0 ? n : 1) * sizeof(double));
+    double *xref = p->water ? malloc(3 * (size_t)(n > 0 ? n : 1) * sizeof(double)) : NULL;
+    if (!F || (p->water && !xref)) { free(F); free(xref); return -1; }
+    or_energy e;
+    double Wp = 0.0;
+    int rc = 0;
+    if (or_compute(p, s, or_altitude(p, move, 0, nf), OR_MODE_NEMD, F, &e)) {
+        free(F); free(xref); return -7;
+    }
+    for (int k = 0; k < nf; ++k) {
+        const double h = 0.5 * p->dt;
+        const double dU_start = u_fly(p, s, or_altitude(p, move, k + 1, nf)) -
+                                u_fly(p, s, or_altitude(p, move, k, nf));
+        /* half kick with F(x_k; w_k), then drift; flyers stay fixed in 3D */
+        for (int i = 0; i < n; ++i) {
+            if (s->flying[i]) continue;
+            const double m = p->mass[s->type[i]];
+            for (int d = 0; d < 3; ++d) s->v[3 * i + d] += h * p->accel * F[3 * i + d] / m;
+        }
+        if (xref) memcpy(xref, s->x, 3 * (size_t)n * sizeof(double));
+        for (int i = 0; i < n; ++i) {
+            if (s->flying[i]) continue;
+            for (int d = 0; d < 3; ++d)
+                s->x[3 * i + d] = wrap1(s->x[3 * i + d] + p->dt * s->v[3 * i + d], p->box[d]);
+        }
+        if (xref && (rc = or_constrain_positions(p, s, xref))) break;
+        /* protocol work of the step: the altitude increment w_k -> w_{k+1}
+         * of U_fly, averaged over the two ends x_k and x_{k+1} (trapezoid,
+         * the quadrature that matches the symmetric kick-drift-kick) */
+        const double wk = or_altitude(p, move, k, nf), wk1 = or_altitude(p, move, k + 1, nf);
+        Wp += 0.5 * (dU_start + (u_fly(p, s, wk1) - u_fly(p, s, wk)));
+        /* second half kick with F(x_{k+1}; w_{k+1}) */
+        or_compute(p, s, wk1, OR_MODE_NEMD, F, &e);
+        for (int i = 0; i < n; ++i) {
+            if (s->flying[i]) continue;
+            const double m = p->mass[s->type[i]];
+            for (int d = 0; d < 3; ++d) s->v[3 * i + d] += h * p->accel * F[3 * i + d] / m;
+        }
+        if (p->water && (rc = or_constrain_velocities(p, s))) break;
+    }
+    free(F); free(xref);
+    *W = Wp;
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* One grand-canonical trial                                           */
+/* ------------------------------------------------------------------ */
+static int pick_rank(const or_state *s, int type, int rank)
+{
+    /* the atom of the given type whose tag has the given rank (ascending) */
+    int best = -1;
+    for (int i = 0; i < s->n; ++i) {
+        if (s->type[i] != type) continue;
+        int below = 0;
+        for (int j = 0; j < s->n; ++j)
+            if (s->type[j] == type && s->tag[j] < s->tag[i]) ++below;
+        if (below == rank) { best = i; break; }
+    }
+    return best;
+}
+
+static void remove_atom(or_state *s, int i)
+{
+    for (int k = i; k < s->n - 1; ++k) {
+        for (int d = 0; d < 3; ++d) {
+            s->x[3 * k + d] = s->x[3 * (k + 1) + d];
+            s->v[3 * k + d] = s->v[3 * (k + 1) + d];
+        }
+        s->type[k] = s->type[k + 1];
+        s->mol[k] = s->mol[k + 1];
+        s->tag[k] = s->tag[k + 1];
+        s->flying[k] = s->flying[k + 1];
+    }
+    s->n--;
+}
+
+int or_trial(const or_params *p, or_state *s, uint64_t trial, int force_move,
+             or_trial_rec *rec)
+{
+    memset(rec, 0, sizeof(*rec));
+    rec->trial = (int64_t)trial;
+    const double beta = 1.0 / p->kT;
+    const double V = p->box[0] * p->box[1] * p->box[2];
+    double u[8];
+    draw4(p, trial, PURPOSE_SELECT, 0, u);
+    draw4(p, trial, PURPOSE_SELECT, 1, u + 4);
+    int nf = p->n_steps;
+    if (p->n_steps_max > 0) {
+        double un[4];
+        draw4(p, trial, PURPOSE_NSTEPS, 0, un);
+        nf = p->n_steps_min + (int)floor(un[0] * (double)(p->n_steps_max - p->n_steps_min + 1));
+    }
+    const int move = force_move ? force_move : (u[0] < 0.5 ? +1 : -1);
+    const int Ns = s->nsalt;
+    rec->move = move;
+    rec->n_salt_before = Ns;
+    rec->n_salt_after = Ns;
+    rec->n_steps = nf;
+    rec->ln_u = log(u[7]);
+    if (move < 0 && Ns == 0) {
+        rec->flags |= OR_FLAG_EMPTY;
+        rec->ln_ratio = -INFINITY;
+        return 0;
+    }
+    const int n_orig = s->n;
+    int ic, ia;
+    if (move > 0) {
+        /* Eq. (4): both flying ions placed uniformly in the box (1/V each). */
+        if (s->n + 2 > s->cap) return -3;
+        ic = s->n; ia = s->n + 1;
+        for (int d = 0; d < 3; ++d) {
+            s->x[3 * ic + d] = wrap1(p->box[d] * u[1 + d], p->box[d]);
+            s->x[3 * ia + d] = wrap1(p->box[d] * u[4 + d], p->box[d]);
+        }
+        s->type[ic] = p->cation_type; s->type[ia] = p->anion_type;
+        s->mol[ic] = -1; s->mol[ia] = -1;
+        s->tag[ic] = s->next_tag; s->tag[ia] = s->next_tag + 1;
+        s->flying[ic] = 1; s->flying[ia] = 1;
+        s->n += 2;
+    } else {
+        /* Eq. (3): one of the N+1 cations and one of the N+1 anions. */
+        ic = pick_rank(s, p->cation_type, (int)floor(u[1] * Ns));
+        ia = pick_rank(s, p->anion_type, (int)floor(u[2] * Ns));
+        if (ic < 0 || ia < 0) return -4;
+        s->flying[ic] = 1; s->flying[ia] = 1;
+    }
+    rec->tag_c = s->tag[ic];
+    rec->tag_a = s->tag[ia];
+    const int n_small = (move > 0) ? Ns : Ns - 1;
+
+    if (or_mb_velocities(p, s, trial)) return -5;
+    or_energy e;
+    /* H at the start: the N-state (ghosts left out) for an insertion, the
+     * physical (N+1)-state for a deletion. */
+    if (move > 0) or_compute(p, s, 0.0, OR_MODE_EXCL, NULL, &e);
+    else or_compute(p, s, 0.0, OR_MODE_NEMD, NULL, &e);
+    const double U0 = e.U, K0 = or_kinetic(p, s);
+    double E_switch = 0.0;
+    if (move > 0) E_switch = u_fly(p, s, p->w_max);
+
+    double *x0 = malloc(3 * (size_t)s->n * sizeof(double));
+    if (!x0) return -1;
+    memcpy(x0, s->x, 3 * (size_t)s->n * sizeof(double));
+    double W = 0.0;
+    int rc = or_nemd(p, s, move, nf, &W);
+    if (rc) { free(x0); return -6; }
+
+    if (move > 0) or_compute(p, s, 0.0, OR_MODE_NEMD, NULL, &e);
+    else or_compute(p, s, 0.0, OR_MODE_EXCL, NULL, &e);
+    const double U1 = e.U, K1 = or_kinetic(p, s);
+    if (move < 0) E_switch = -u_fly(p, s, p->w_max);
+
+    const double dH = (U1 + K1) - (U0 + K0);
+    /* Eqs. (6) and (8) with Lambda_s: ln of (V / (Lambda^3 (N+1)))^2. */
+    const double lam3 = p->lambda_s * p->lambda_s * p->lambda_s;
+    const double I = 2.0 * log(V / (lam3 * (double)(n_small + 1)));
+    double lnR;
+    if (move > 0) lnR = -beta * dH + p->beta_mu + I;
+    else lnR = -beta * dH - p->beta_mu - I;
+    rec->dH = dH; rec->dU = U1 - U0; rec->dK = K1 - K0;
+    rec->W_prot = W; rec->E_switch = E_switch;
+    rec->H0 = U0 + K0; rec->H1 = U1 + K1;
+    rec->dM = (move > 0) ? dH - I / beta : -dH - I / beta;
+    rec->ln_ratio = lnR;
+    int acc = 0;
+    if (!isfinite(dH)) { rec->flags |= OR_FLAG_NONFINITE; acc = 0; }
+    else acc = rec->ln_u < lnR;
+    rec->accepted = acc;
+
+    if (acc) {
+        if (move > 0) {
+            s->flying[ic] = 0; s->flying[ia] = 0;
+            s->next_tag += 2;
+            s->nsalt = Ns + 1;
+        } else {
+            const int hi = ic > ia ? ic : ia, lo = ic > ia ? ia : ic;
+            remove_atom(s, hi);
+            remove_atom(s, lo);
+            s->nsalt = Ns - 1;
+        }
+    } else {
+        memcpy(s->x, x0, 3 * (size_t)s->n * sizeof(double));
+        if (move > 0) s->n = n_orig;
+        else { s->flying[ic] = 0; s->flying[ia] = 0; }
+    }
+    rec->n_salt_after = s->nsalt;
+    free(x0);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Multiple-try factor of the learned proposal.                        */
+/* The k candidates of a move carry log weights logw[0..k-1]; for an   */
+/* insertion, sel is the chosen one and the factor is                  */
+/*     ln(W/k) - logw[sel],     W = sum_j exp(logw[j]);                */
+/* for a deletion logw[0] belongs to the removed pair, logw[1..k-1] to  */
+/* fresh candidates drawn on the post-trajectory state, and the factor  */
+/* is logw[0] - ln(W/k).                                               */
+/* ------------------------------------------------------------------ */
+int or_mtm_log_factor(int move, int k, const double *logw, int sel, double *out)
+{
+    if (k < 1 || (move > 0 && (sel < 0 || sel >= k))) return -1;
+    double mx = logw[0];
+    for (int j = 1; j < k; ++j) if (logw[j] > mx) mx = logw[j];
+    double acc = 0.0;
+    for (int j = 0; j < k; ++j) acc += exp(logw[j] - mx);
+    const double lnW_over_k = mx + log(acc) - log((double)k);
+    *out = (move > 0) ? lnW_over_k - logw[sel] : logw[0] - lnW_over_k;
+    return 0;
+}

@@ -1,0 +1,228 @@
+"""ctypes wrapper of the FP64 CPU oracle (test infrastructure only).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+import this module.  It loads ``liboracle.so`` built from
+``h4d_oracle.c`` by ``oracle/build.py`` and shares nothing with the GPU
+library except the seeded workload generators that feed both.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+MAXT = 8
+
+MODE_NEMD, MODE_EXCL, MODE_FLY = 0, 1, 2
+FLAG_EMPTY, FLAG_NONFINITE = 1, 2
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("n_types", C.c_int32), ("cation_type", C.c_int32), ("anion_type", C.c_int32),
+        ("n_steps", C.c_int32), ("n_steps_min", C.c_int32), ("n_steps_max", C.c_int32),
+        ("water", C.c_int32), ("use_cells", C.c_int32),
+        ("mass", C.c_double * MAXT), ("charge", C.c_double * MAXT),
+        ("sigma", C.c_double * MAXT), ("eps", C.c_double * MAXT),
+        ("box", C.c_double * 3),
+        ("kT", C.c_double), ("dt", C.c_double), ("w_max", C.c_double), ("kappa_sr", C.c_double),
+        ("rc_lj", C.c_double), ("rc_coul", C.c_double), ("alpha", C.c_double), ("ke", C.c_double),
+        ("beta_mu", C.c_double), ("lambda_s", C.c_double),
+        ("d_oh", C.c_double), ("d_hh", C.c_double), ("accel", C.c_double),
+        ("seed", C.c_uint64), ("stream", C.c_uint64),
+    ]
+
+
+class State(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32), ("cap", C.c_int32), ("nsalt", C.c_int32), ("n_mol", C.c_int32),
+        ("next_tag", C.c_int64),
+        ("x", C.POINTER(C.c_double)), ("v", C.POINTER(C.c_double)),
+        ("type", C.POINTER(C.c_int32)), ("mol", C.POINTER(C.c_int32)),
+        ("tag", C.POINTER(C.c_int64)), ("flying", C.POINTER(C.c_int32)),
+    ]
+
+
+class TrialRec(C.Structure):
+    _fields_ = [
+        ("move", C.c_int32), ("accepted", C.c_int32), ("n_salt_before", C.c_int32),
+        ("n_salt_after", C.c_int32), ("n_steps", C.c_int32), ("flags", C.c_int32),
+        ("trial", C.c_int64), ("tag_c", C.c_int64), ("tag_a", C.c_int64),
+        ("dH", C.c_double), ("dU", C.c_double), ("dK", C.c_double), ("W_prot", C.c_double),
+        ("E_switch", C.c_double), ("dM", C.c_double), ("ln_ratio", C.c_double),
+        ("ln_u", C.c_double), ("ln_proposal", C.c_double), ("H0", C.c_double), ("H1", C.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Energy(C.Structure):
+    _fields_ = [("U", C.c_double), ("U_lj", C.c_double), ("U_c", C.c_double),
+                ("virial", C.c_double), ("dUdw", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _b  # type: ignore
+            _b.build()
+        L = C.CDLL(LIB_PATH)
+        P, S = C.POINTER(Params), C.POINTER(State)
+        L.or_philox4x64.argtypes = [C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
+        L.or_u01.argtypes = [C.c_uint64]
+        L.or_u01.restype = C.c_double
+        L.or_pair.argtypes = [P, C.c_int, C.c_int, C.c_double, C.c_double] + [C.POINTER(C.c_double)] * 4
+        L.or_compute.argtypes = [P, S, C.c_double, C.c_int, C.POINTER(C.c_double), C.POINTER(Energy)]
+        L.or_mb_velocities.argtypes = [P, S, C.c_uint64]
+        L.or_constrain_positions.argtypes = [P, S, C.POINTER(C.c_double)]
+        L.or_constrain_velocities.argtypes = [P, S]
+        L.or_kinetic.argtypes = [P, S]
+        L.or_kinetic.restype = C.c_double
+        L.or_altitude.argtypes = [P, C.c_int, C.c_int, C.c_int]
+        L.or_altitude.restype = C.c_double
+        L.or_nemd.argtypes = [P, S, C.c_int, C.c_int, C.POINTER(C.c_double)]
+        L.or_trial.argtypes = [P, S, C.c_uint64, C.c_int, C.POINTER(TrialRec)]
+        L.or_mtm_log_factor.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_double), C.c_int,
+                                        C.POINTER(C.c_double)]
+        _lib = L
+    return _lib
+
+
+def make_params(d: dict, use_cells: bool = True) -> Params:
+    p = Params()
+    p.n_types = d["n_types"]
+    p.cation_type, p.anion_type = d["cation_type"], d["anion_type"]
+    p.n_steps = d["n_steps"]
+    p.n_steps_min, p.n_steps_max = d.get("n_steps_min", 0), d.get("n_steps_max", 0)
+    p.water = d.get("water", 0)
+    p.use_cells = 1 if use_cells else 0
+    for name in ("mass", "charge", "sigma", "eps"):
+        arr = getattr(p, name)
+        for i, v in enumerate(d[name]):
+            arr[i] = v
+    for i in range(3):
+        p.box[i] = d["box"][i]
+    for k in ("kT", "dt", "w_max", "kappa_sr", "rc_lj", "rc_coul", "alpha",
+              "beta_mu", "lambda_s", "d_oh", "d_hh"):
+        setattr(p, k, d[k])
+    p.ke = d["coulomb_k"]
+    p.accel = d.get("accel", 1.0)
+    p.seed, p.stream = d["seed"], d.get("stream", 0)
+    return p
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _lp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int64))
+
+
+class OracleSystem:
+    """A configuration plus model parameters, advanced by the C oracle."""
+
+    def __init__(self, params: dict, x, type_, mol, tag, nsalt: int, n_mol: int = 0,
+                 cap: int | None = None, use_cells: bool = True):
+        n = len(type_)
+        cap = cap or (n + 64)
+        self.pd = dict(params)
+        self.p = make_params(params, use_cells)
+        self.x = np.zeros((cap, 3)); self.x[:n] = x
+        self.v = np.zeros((cap, 3))
+        self.type = np.zeros(cap, np.int32); self.type[:n] = type_
+        self.mol = np.full(cap, -1, np.int32); self.mol[:n] = mol
+        self.tag = np.zeros(cap, np.int64); self.tag[:n] = tag
+        self.flying = np.zeros(cap, np.int32)
+        self.s = State()
+        self.s.n, self.s.cap, self.s.nsalt, self.s.n_mol = n, cap, nsalt, n_mol
+        self.s.next_tag = int(tag.max()) + 1 if n else 0
+        self.s.x, self.s.v = _dp(self.x), _dp(self.v)
+        self.s.type, self.s.mol = _ip(self.type), _ip(self.mol)
+        self.s.tag, self.s.flying = _lp(self.tag), _ip(self.flying)
+
+    @classmethod
+    def from_workload(cls, w, cap=None, use_cells=True):
+        return cls(w.params, w.x, w.type, w.mol, w.tag, w.nsalt, w.n_mol, cap, use_cells)
+
+    @property
+    def n(self):
+        return self.s.n
+
+    @property
+    def nsalt(self):
+        return self.s.nsalt
+
+    def compute(self, w: float = 0.0, mode: int = MODE_NEMD, forces: bool = True):
+        F = np.zeros((self.n, 3)) if forces else None
+        e = Energy()
+        rc = lib().or_compute(C.byref(self.p), C.byref(self.s), w, mode,
+                              _dp(F) if forces else None, C.byref(e))
+        if rc:
+            raise RuntimeError(f"or_compute failed: {rc}")
+        return e, F
+
+    def trial(self, t: int, force_move: int = 0) -> dict:
+        rec = TrialRec()
+        rc = lib().or_trial(C.byref(self.p), C.byref(self.s), t, force_move, C.byref(rec))
+        if rc:
+            raise RuntimeError(f"or_trial failed: {rc}")
+        return rec.as_dict()
+
+    def mb(self, t: int):
+        rc = lib().or_mb_velocities(C.byref(self.p), C.byref(self.s), t)
+        if rc:
+            raise RuntimeError(f"or_mb_velocities failed: {rc}")
+
+    def kinetic(self) -> float:
+        return lib().or_kinetic(C.byref(self.p), C.byref(self.s))
+
+    def nemd(self, move: int, nf: int) -> float:
+        W = C.c_double()
+        rc = lib().or_nemd(C.byref(self.p), C.byref(self.s), move, nf, C.byref(W))
+        if rc:
+            raise RuntimeError(f"or_nemd failed: {rc}")
+        return W.value
+
+    def positions(self):
+        return self.x[: self.n].copy()
+
+
+def philox4x64(ctr, key):
+    c = (C.c_uint64 * 4)(*ctr)
+    k = (C.c_uint64 * 2)(*key)
+    o = (C.c_uint64 * 4)()
+    lib().or_philox4x64(c, k, o)
+    return [int(v) for v in o]
+
+
+def u01(bits: int) -> float:
+    return lib().or_u01(bits)
+
+
+def pair(params: dict, ti: int, tj: int, s: float, g: float = 1.0):
+    p = make_params(params)
+    out = [C.c_double() for _ in range(4)]
+    lib().or_pair(C.byref(p), ti, tj, s * s, g, *[C.byref(o) for o in out])
+    return tuple(o.value for o in out)
+
+
+def mtm_log_factor(move: int, logw, sel: int) -> float:
+    a = np.ascontiguousarray(logw, dtype=np.float64)
+    out = C.c_double()
+    rc = lib().or_mtm_log_factor(move, len(a), _dp(a), sel, C.byref(out))
+    if rc:
+        raise ValueError("bad arguments")
+    return out.value
