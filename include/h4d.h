@@ -1,0 +1,216 @@
+/*
+ * h4d.h -- C ABI of the MI355X (gfx950) library for hybrid 4D
+ * nonequilibrium MD/MC (H4D) grand-canonical ion-pair exchange, after
+ * Kim, Belloni & Rotenberg, "Grand-canonical molecular dynamics simulations
+ * powered by a hybrid 4D nonequilibrium MD/MC method" (arXiv 2307.11447).
+ *
+ * One call of h4d_run_nemd_trial is one exchange attempt of the paper's
+ * GCMD cycle (Sec. II A, Fig. 1): choose insertion or deletion of a
+ * cation-anion pair, fly the pair along the fourth coordinate w with the
+ * constant-velocity schedule of Eq. (2) during an NVE velocity-Verlet
+ * trajectory, and accept or reject with the Metropolis ratio of
+ * Eqs. (6) and (8).
+ *
+ * Conventions shared by every entry point:
+ *  - Every function returns an h4d_status; none aborts or throws.  On an
+ *    error, h4d_last_error() returns a message (thread local, valid until
+ *    the next call on the same thread).
+ *  - Host arrays passed in are read during the call and copied; the
+ *    library never keeps a pointer to caller memory.  Device memory is
+ *    allocated and owned by the library and released by the matching
+ *    destroy call.
+ *  - All GPU work of a handle is enqueued on the hipStream_t given at
+ *    creation (NULL: the default stream).  A call that returns host results
+ *    synchronises that stream only.
+ *  - One host thread may use a handle at a time.
+ *  - Units are the caller's: coulomb_k is the Coulomb constant
+ *    (k_e q_i q_j / r), accel converts force/mass into acceleration
+ *    (1 in reduced units; 4.184e-4 A/fs^2 per (kcal/mol/A)/amu in real
+ *    units), kT the thermal energy.
+ *  - Results depend only on the starting state, the parameters, the seed
+ *    and the trial index: all random numbers come from the counter-based
+ *    generator Philox4x64-10 keyed by (seed, stream) with counters
+ *    (trial, purpose, tag, 0); the order of atoms in memory is not
+ *    observable.
+ */
+#ifndef H4D_H
+#define H4D_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define H4D_MAX_TYPES 8
+
+/* Status codes. */
+#define H4D_OK          0
+#define H4D_EINVAL     -1   /* bad argument (message says which)              */
+#define H4D_ENOMEM     -2   /* device allocation failed                        */
+#define H4D_EHIP       -3   /* a HIP runtime call failed                       */
+#define H4D_ECAPACITY  -4   /* atom capacity exhausted                         */
+#define H4D_ENONFINITE -5   /* NaN energy; the state was rolled back           */
+#define H4D_ENODEV     -6   /* no usable gfx950 device                         */
+
+/* Trial moves. */
+#define H4D_MOVE_AUTO    0  /* insertion or deletion with probability 1/2    */
+#define H4D_MOVE_INSERT  1
+#define H4D_MOVE_DELETE -1
+
+/* Arithmetic of the pair pass. */
+#define H4D_PREC_FP64 0     /* everything in FP64                               */
+#define H4D_PREC_FP32 1     /* FP32 pair arithmetic on 32-bit fixed-point
+                               coordinates; FP64 positions, velocities,
+                               energies, work and Metropolis ratio             */
+
+/* Trial flags. */
+#define H4D_FLAG_EMPTY     0x1u  /* deletion drawn with no pair present: rejected */
+#define H4D_FLAG_NONFINITE 0x2u  /* dH not finite: rejected                       */
+#define H4D_FLAG_RETRIED   0x4u  /* the trial was recomputed after a list resize   */
+
+/*
+ * Model and protocol.  Types index the per-type tables; pair parameters
+ * follow Lorentz-Berthelot mixing (Sec. II E 2).
+ *   Lennard-Jones, Eq. (19): truncated and shifted at rc_lj, force not
+ *     shifted.
+ *   Coulomb: damped shifted force (erfc-screened, real space only; the
+ *     Wolf-family option of Sec. II B 2) with damping dsf_alpha and cutoff
+ *     rc_coul; between a flying and a non-flying atom it is multiplied by
+ *     exp(-kappa_sr w) (Eq. 11).
+ *   A pair that involves exactly one flying atom uses the 4D distance
+ *     sqrt(r^2 + w^2) (Sec. I, Sec. II D); both cutoffs apply to it.
+ *   w follows Eq. (2): w_max -> 0 for an insertion, 0 -> w_max for a
+ *     deletion, in n_steps steps of dt; the flying ions stay fixed in 3D
+ *     (trick (i) of Sec. II B).
+ *   water = 1: the first 3*n_mol atoms are rigid 3-site waters (O, H, H),
+ *     bond lengths d_oh and d_hh, intramolecular pairs excluded.
+ */
+typedef struct h4d_params {
+    int32_t n_types;
+    int32_t cation_type, anion_type;
+    int32_t n_steps;            /* N_f                                         */
+    int32_t n_steps_min;        /* n_steps_max > 0: N_f ~ U{min..max} per trial */
+    int32_t n_steps_max;
+    int32_t water;
+    int32_t precision;          /* H4D_PREC_*                                   */
+    int32_t capacity;           /* maximum atoms (0: n_atoms + 4096)            */
+    int32_t rebuild_every;      /* neighbour-list rebuild interval (0: auto)   */
+    double mass[H4D_MAX_TYPES], charge[H4D_MAX_TYPES];
+    double sigma[H4D_MAX_TYPES], eps[H4D_MAX_TYPES];
+    double box[3];              /* orthorhombic edges; each >= 2 max cutoff     */
+    double kT, dt, w_max, kappa_sr;
+    double rc_lj, rc_coul, dsf_alpha, coulomb_k;
+    double beta_mu;             /* beta * mu_salt                               */
+    double lambda_s;            /* sqrt(Lambda_+ Lambda_-), Eq. (6)             */
+    double skin;                /* Verlet-list skin                              */
+    double d_oh, d_hh;          /* rigid-water geometry                          */
+    double accel;               /* acceleration per force/mass                   */
+    uint64_t seed, stream;      /* Philox key                                    */
+} h4d_params;
+
+/* One trial (move +1 insertion, -1 deletion). */
+typedef struct h4d_trial {
+    int32_t move, accepted, n_salt_before, n_salt_after, n_steps;
+    uint32_t flags;
+    int32_t n_atoms;    /* atoms integrated (state size at the start)          */
+    int32_t n_rebuilds; /* neighbour-list builds during the trajectory          */
+    int64_t trial, tag_c, tag_a;
+    double dH;          /* H_end - H_start, H = U_physical + K_non-flying          */
+    double dU, dK;
+    double W_prot;      /* protocol work: sum of altitude increments of U_fly     */
+    double E_switch;    /* U_fly switched on at w_max (insertion) / off (deletion) */
+    double dM;          /* insertion-signed work of Eqs. (6)/(8)                   */
+    double ln_ratio;    /* ln of the Metropolis ratio                              */
+    double ln_u;        /* ln of the uniform it is compared with                   */
+    double ln_proposal; /* proposal factor (0 for the uniform proposal)            */
+    double H0, H1;
+} h4d_trial;
+
+/* Observables of the current state (Eq. 1 statistics over the trials run). */
+typedef struct h4d_observables {
+    int64_t n_atoms, n_salt, n_trials, n_ins, n_ins_acc, n_del, n_del_acc;
+    double U, U_lj, U_coul, virial, pressure_virial;
+    double N_mean, N2_mean, chi;   /* running <N_salt>, <N_salt^2>, Var/<N>     */
+} h4d_observables;
+
+typedef struct h4d_system h4d_system;   /* opaque, library-owned */
+
+/*
+ * Create a system from a host configuration.
+ *   pos[3*n_atoms] positions (wrapped into the box), type[n_atoms],
+ *   mol[n_atoms] (molecule id, -1 for ions), tag[n_atoms] (unique,
+ *   ascending in array order).  n_salt cations and n_salt anions must be
+ *   present.  With water = 1 the waters come first, molecule k at atoms
+ *   3k, 3k+1, 3k+2 (O, H, H).
+ *   hip_stream: a hipStream_t or NULL.
+ * The neighbour list is built before return.  *out receives the handle.
+ */
+int32_t h4d_init_system(const h4d_params *params, int32_t n_atoms, int32_t n_salt,
+                        int32_t n_mol, const double *pos, const int32_t *type,
+                        const int32_t *mol, const int64_t *tag, void *hip_stream,
+                        h4d_system **out);
+
+/* Rebuild the cell and Verlet lists of the current state (cells of edge
+ * >= max cutoff + skin; all pairs when a box edge holds fewer than 3). */
+int32_t h4d_build_neighbors(h4d_system *sys);
+
+/*
+ * Run exchange trials on the device.  Trial t (the handle's counter, then
+ * t+1, ...) draws its move, sites and momenta from the generator, runs the
+ * NEMD trajectory and the Metropolis test (Eqs. 6 and 8 with Lambda_s),
+ * and commits or rolls back.  out[n] receives the records (host memory).
+ * move forces every trial's direction (H4D_MOVE_*).
+ */
+int32_t h4d_run_nemd_trial(h4d_system *sys, int32_t move, h4d_trial *out);
+int32_t h4d_run_trials(h4d_system *sys, int32_t n, int32_t move, h4d_trial *out);
+
+/* FP64 energies and virial of the current state, plus the running
+ * particle-number statistics of the trials run so far. */
+int32_t h4d_sample_observables(h4d_system *sys, h4d_observables *out);
+
+/* Copy the current state to host arrays of length >= cap (positions 3*cap).
+ * Any pointer may be NULL.  *n receives the number of atoms. */
+int32_t h4d_get_state(h4d_system *sys, int32_t cap, int32_t *n, int32_t *n_salt,
+                      double *pos, double *vel, int32_t *type, int32_t *mol, int64_t *tag);
+
+/* Set the next trial index (default 0). */
+int32_t h4d_set_trial_index(h4d_system *sys, uint64_t trial);
+
+/*
+ * Test hook: forces and FP64 energy of the current state with atoms
+ * flying[0], flying[1] (-1: none) lifted to altitude w, as in the NEMD pass.
+ * forces[3*n] (host) receives F on every non-flying atom (0 on flyers),
+ * computed in the handle's precision; energy[3] receives U, U_lj, U_coul.
+ */
+int32_t h4d_forces_at(h4d_system *sys, const int32_t flying[2], double w,
+                      double *forces, double *energy);
+
+/*
+ * Kernel timing for roofline measurements.  While enabled, every launch of
+ * the fused NEMD step kernel is bracketed by HIP events on the handle's
+ * stream (hipExtLaunchKernelGGL); h4d_get_timing returns the accumulated
+ * device time of those launches, their count, and the mean Verlet-list
+ * length of the current state.
+ */
+typedef struct h4d_timing {
+    int64_t step_launches;
+    double step_ms;        /* summed device time of the step kernel            */
+    double mean_nbr;       /* mean list entries per atom, current state        */
+    int32_t rebuild_every; /* current list rebuild interval (steps)            */
+    int32_t nbr_cap;       /* list capacity per atom                           */
+} h4d_timing;
+
+int32_t h4d_set_timing(h4d_system *sys, int32_t on);
+int32_t h4d_get_timing(h4d_system *sys, h4d_timing *out);
+
+/* Release every resource of the handle. */
+int32_t h4d_destroy(h4d_system *sys);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *h4d_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* H4D_H */

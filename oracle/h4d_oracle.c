@@ -525,13 +525,16 @@ static void remove_atom(or_state *s, int i)
     s->n--;
 }
 
-int or_trial(const or_params *p, or_state *s, uint64_t trial, int force_move,
-             or_trial_rec *rec)
+/* Start of a trial: move choice and proposal (Eqs. 3-4), momenta, the
+ * starting Hamiltonian and, for an insertion, the switch-on energy.  On
+ * return the flyers are marked (an insertion has appended its ghost pair).
+ * Returns 0 if the trial ends here (deletion from an empty box), 1 if the
+ * trajectory follows, negative on error. */
+int or_trial_begin(const or_params *p, or_state *s, uint64_t trial, int force_move,
+                   or_trial_rec *rec, int *ic_out, int *ia_out, int *nf_out)
 {
     memset(rec, 0, sizeof(*rec));
     rec->trial = (int64_t)trial;
-    const double beta = 1.0 / p->kT;
-    const double V = p->box[0] * p->box[1] * p->box[2];
     double u[8];
     draw4(p, trial, PURPOSE_SELECT, 0, u);
     draw4(p, trial, PURPOSE_SELECT, 1, u + 4);
@@ -548,12 +551,13 @@ int or_trial(const or_params *p, or_state *s, uint64_t trial, int force_move,
     rec->n_salt_after = Ns;
     rec->n_steps = nf;
     rec->ln_u = log(u[7]);
+    *nf_out = nf;
+    *ic_out = *ia_out = -1;
     if (move < 0 && Ns == 0) {
         rec->flags |= OR_FLAG_EMPTY;
         rec->ln_ratio = -INFINITY;
         return 0;
     }
-    const int n_orig = s->n;
     int ic, ia;
     if (move > 0) {
         /* Eq. (4): both flying ions placed uniformly in the box (1/V each). */
@@ -577,17 +581,36 @@ int or_trial(const or_params *p, or_state *s, uint64_t trial, int force_move,
     }
     rec->tag_c = s->tag[ic];
     rec->tag_a = s->tag[ia];
-    const int n_small = (move > 0) ? Ns : Ns - 1;
+    *ic_out = ic; *ia_out = ia;
 
     if (or_mb_velocities(p, s, trial)) return -5;
     or_energy e;
     /* H at the start: the N-state (ghosts left out) for an insertion, the
      * physical (N+1)-state for a deletion. */
-    if (move > 0) or_compute(p, s, 0.0, OR_MODE_EXCL, NULL, &e);
-    else or_compute(p, s, 0.0, OR_MODE_NEMD, NULL, &e);
-    const double U0 = e.U, K0 = or_kinetic(p, s);
-    double E_switch = 0.0;
-    if (move > 0) E_switch = u_fly(p, s, p->w_max);
+    if (or_compute(p, s, 0.0, move > 0 ? OR_MODE_EXCL : OR_MODE_NEMD, NULL, &e)) return -7;
+    /* until the trial completes, dU and dK hold U and K of the start state */
+    rec->dU = e.U;
+    rec->dK = or_kinetic(p, s);
+    rec->H0 = rec->dU + rec->dK;
+    if (move > 0) rec->E_switch = u_fly(p, s, p->w_max);
+    return 1;
+}
+
+int or_trial(const or_params *p, or_state *s, uint64_t trial, int force_move,
+             or_trial_rec *rec)
+{
+    const double beta = 1.0 / p->kT;
+    const double V = p->box[0] * p->box[1] * p->box[2];
+    const int Ns = s->nsalt;
+    const int n_orig = s->n;
+    int ic, ia, nf;
+    const int st = or_trial_begin(p, s, trial, force_move, rec, &ic, &ia, &nf);
+    if (st <= 0) return st;
+    const int move = rec->move;
+    const int n_small = (move > 0) ? Ns : Ns - 1;
+    const double H0 = rec->H0;
+    double E_switch = rec->E_switch;
+    or_energy e;
 
     double *x0 = malloc(3 * (size_t)s->n * sizeof(double));
     if (!x0) return -1;
@@ -601,16 +624,18 @@ int or_trial(const or_params *p, or_state *s, uint64_t trial, int force_move,
     const double U1 = e.U, K1 = or_kinetic(p, s);
     if (move < 0) E_switch = -u_fly(p, s, p->w_max);
 
-    const double dH = (U1 + K1) - (U0 + K0);
+    const double dH = (U1 + K1) - H0;
     /* Eqs. (6) and (8) with Lambda_s: ln of (V / (Lambda^3 (N+1)))^2. */
     const double lam3 = p->lambda_s * p->lambda_s * p->lambda_s;
     const double I = 2.0 * log(V / (lam3 * (double)(n_small + 1)));
     double lnR;
     if (move > 0) lnR = -beta * dH + p->beta_mu + I;
     else lnR = -beta * dH - p->beta_mu - I;
-    rec->dH = dH; rec->dU = U1 - U0; rec->dK = K1 - K0;
+    rec->dU = U1 - rec->dU;
+    rec->dK = K1 - rec->dK;
+    rec->dH = dH;
     rec->W_prot = W; rec->E_switch = E_switch;
-    rec->H0 = U0 + K0; rec->H1 = U1 + K1;
+    rec->H1 = U1 + K1;
     rec->dM = (move > 0) ? dH - I / beta : -dH - I / beta;
     rec->ln_ratio = lnR;
     int acc = 0;

@@ -101,6 +101,12 @@ double or_altitude(const or_params *p, int move, int k, int nf);
  * protocol work W (sum of altitude increments of U_fly). */
 int or_nemd(const or_params *p, or_state *s, int move, int nf, double *W);
 
+/* Start of a trial: proposal, momenta, H_start (rec->H0) and, for an
+ * insertion, the switch-on energy (rec->E_switch).  Returns 1 if the
+ * trajectory follows, 0 if the trial ends (empty deletion), <0 on error. */
+int or_trial_begin(const or_params *p, or_state *s, uint64_t trial, int force_move,
+                   or_trial_rec *rec, int *ic, int *ia, int *nf);
+
 /* One full trial (move choice, proposal, momenta, NEMD, Metropolis,
  * commit or rollback).  force_move: 0 = random, +1 / -1 forced. */
 int or_trial(const or_params *p, or_state *s, uint64_t trial, int force_move,

@@ -90,6 +90,8 @@ def lib():
         L.or_altitude.restype = C.c_double
         L.or_nemd.argtypes = [P, S, C.c_int, C.c_int, C.POINTER(C.c_double)]
         L.or_trial.argtypes = [P, S, C.c_uint64, C.c_int, C.POINTER(TrialRec)]
+        L.or_trial_begin.argtypes = [P, S, C.c_uint64, C.c_int, C.POINTER(TrialRec),
+                                     C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.or_mtm_log_factor.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_double), C.c_int,
                                         C.POINTER(C.c_double)]
         _lib = L
@@ -180,6 +182,19 @@ class OracleSystem:
         if rc:
             raise RuntimeError(f"or_trial failed: {rc}")
         return rec.as_dict()
+
+    def trial_begin(self, t: int, force_move: int = 0) -> dict:
+        """Proposal, momenta, H_start and (insertion) switch-on energy of
+        trial t; leaves the flyers marked in this state."""
+        rec = TrialRec()
+        ic, ia, nf = C.c_int(), C.c_int(), C.c_int()
+        rc = lib().or_trial_begin(C.byref(self.p), C.byref(self.s), t, force_move, C.byref(rec),
+                                  C.byref(ic), C.byref(ia), C.byref(nf))
+        if rc < 0:
+            raise RuntimeError(f"or_trial_begin failed: {rc}")
+        d = rec.as_dict()
+        d.update(ic=ic.value, ia=ia.value, nf=nf.value, proceeds=rc)
+        return d
 
     def mb(self, t: int):
         rc = lib().or_mb_velocities(C.byref(self.p), C.byref(self.s), t)

@@ -1,0 +1,194 @@
+// h4d_device.hpp -- device-side building blocks of the H4D library (gfx950).
+//
+// Counter-based random numbers, the pair potentials at the 4D distance, the
+// altitude schedule and wavefront reductions.  Included by the kernels only.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace h4d {
+
+constexpr int kMaxTypes = 8;
+constexpr int kBlock = 256;          // threads per block of the atom kernels
+constexpr int kWave = 64;            // gfx950 wavefront
+
+// meta word of an atom (packed next to its coordinates): type and flags
+constexpr int kTypeMask = 0xF;
+constexpr int kFlyBit = 0x10;
+
+// error bits of the control block
+constexpr unsigned kErrNbr = 0x1u;    // neighbour list capacity exceeded
+constexpr unsigned kErrCell = 0x2u;   // cell capacity exceeded
+constexpr unsigned kErrSkin = 0x4u;   // an atom moved more than skin/2 before a rebuild
+constexpr unsigned kErrCap = 0x8u;    // atom capacity exceeded
+
+// purposes of the counter-based generator
+constexpr uint64_t kPurposeSelect = 1, kPurposeMB = 2, kPurposeNsteps = 3;
+
+// --------------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of two
+// 64x64->128 multiplies with Weyl-sequence key bumps.
+// --------------------------------------------------------------------------
+struct u64x4 { uint64_t v[4]; };
+
+__device__ __forceinline__ u64x4 philox(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                        uint64_t k0, uint64_t k1) {
+    const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+        const uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+        const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += W0; k1 += W1;
+    }
+    u64x4 o;
+    o.v[0] = c0; o.v[1] = c1; o.v[2] = c2; o.v[3] = c3;
+    return o;
+}
+
+// top 52 bits -> (m + 1/2) 2^-52, strictly inside (0, 1)
+__device__ __forceinline__ double unit_open(uint64_t b) {
+    return ((double)(b >> 12) + 0.5) * 0x1p-52;
+}
+
+// --------------------------------------------------------------------------
+// Geometry and model constants, passed by value to every kernel.
+// --------------------------------------------------------------------------
+struct Geo {
+    double L[3];
+    double fx_inv[3];        // 2^32 / L: FP64 coordinate -> 32-bit fixed point
+    float fx_scale[3];       // L / 2^32
+    double rc_lj2, rc_c2, rc_max2, rlist2, half_skin2;
+    float rc_lj2f, rc_c2f, rc_max2f;
+    double alpha, alpha2, cex, Sc, erfc_rc_over_rc, rc_coul;   // damped shifted force
+    float alphaf, alpha2f, cexf, Scf;
+    double dt, half_dt, accel, kT, w_max, kappa;
+    double volume, lambda3, beta, beta_mu;
+    int ncell[3];
+    int use_cells;
+    int n_types;
+    int water;
+    double d_oh, d_hh;
+};
+
+// per type-pair coefficients, indexed ti * kMaxTypes + tj
+struct PairCoef {
+    double sig2, eps, qqk, lj_shift;     // lj_shift = (s/rc)^12 - (s/rc)^6
+    float sig2f, eps24f, qqkf, pad;
+};
+
+// --------------------------------------------------------------------------
+// Altitude schedule, Eq. (2): constant vertical velocity.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ double altitude(double w_max, int move, int k, int nf) {
+    return move > 0 ? w_max * (double)(nf - k) / (double)nf : w_max * (double)k / (double)nf;
+}
+
+__device__ __forceinline__ double wrap_coord(double x, double L) {
+    double y = x - L * floor(x / L);
+    if (y >= L) y -= L;
+    return y;
+}
+
+__device__ __forceinline__ double min_image(double d, double L) {
+    return d - L * rint(d / L);
+}
+
+__device__ __forceinline__ uint32_t to_fixed(double x, double fx_inv) {
+    return (uint32_t)(unsigned long long)(x * fx_inv);
+}
+
+__device__ __forceinline__ int meta_of(const double4 &p) {
+    return (int)__double_as_longlong(p.w);
+}
+
+__device__ __forceinline__ double4 with_meta(double x, double y, double z, int meta) {
+    return make_double4(x, y, z, __longlong_as_double((long long)meta));
+}
+
+// --------------------------------------------------------------------------
+// erfc in FP32 from Abramowitz & Stegun 7.1.26 (|error| <= 1.5e-7), sharing
+// exp(-x^2) with the force term.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ float erfc_as(float x, float ex) {
+    const float t = __frcp_rn(1.0f + 0.3275911f * x);
+    const float poly = t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f +
+                       t * (-1.453152027f + t * 1.061405429f))));
+    return poly * ex;
+}
+
+// Radial force over distance, -(du/ds)/s, of one pair at squared 4D
+// distance s2 (FP32).  g screens the Coulomb part.
+__device__ __forceinline__ float pair_fs_f32(const Geo &G, const PairCoef &c, float s2, float g) {
+    float fs = 0.0f;
+    const float inv = __frcp_rn(s2);
+    if (s2 < G.rc_lj2f) {
+        const float sr2 = c.sig2f * inv;
+        const float sr6 = sr2 * sr2 * sr2;
+        fs += c.eps24f * sr6 * (2.0f * sr6 - 1.0f) * inv;
+    }
+    if (s2 < G.rc_c2f) {
+        const float rs = __frsqrt_rn(s2);
+        const float s = s2 * rs;
+        const float ex = __expf(-G.alpha2f * s2);
+        const float ec = erfc_as(G.alphaf * s, ex);
+        fs += g * c.qqkf * (ec * inv + G.cexf * ex * rs - G.Scf) * rs;
+    }
+    return fs;
+}
+
+// Same in FP64 with the library erfc.
+__device__ __forceinline__ double pair_fs_f64(const Geo &G, const PairCoef &c, double s2, double g) {
+    double fs = 0.0;
+    const double inv = 1.0 / s2;
+    if (s2 < G.rc_lj2) {
+        const double sr2 = c.sig2 * inv;
+        const double sr6 = sr2 * sr2 * sr2;
+        fs += 24.0 * c.eps * sr6 * (2.0 * sr6 - 1.0) * inv;
+    }
+    if (s2 < G.rc_c2) {
+        const double s = sqrt(s2);
+        const double ex = exp(-G.alpha2 * s2);
+        fs += g * c.qqk * (erfc(G.alpha * s) * inv + G.cex * ex / s - G.Sc) / s;
+    }
+    return fs;
+}
+
+// FP64 pair energies (LJ and Coulomb parts) and -(du/ds)/s.
+__device__ __forceinline__ void pair_u_f64(const Geo &G, const PairCoef &c, double s2, double g,
+                                           double &ulj, double &uc, double &fs) {
+    ulj = 0.0; uc = 0.0; fs = 0.0;
+    const double inv = 1.0 / s2;
+    if (s2 < G.rc_lj2) {
+        const double sr2 = c.sig2 * inv;
+        const double sr6 = sr2 * sr2 * sr2;
+        ulj = 4.0 * c.eps * (sr6 * sr6 - sr6 - c.lj_shift);
+        fs += 24.0 * c.eps * sr6 * (2.0 * sr6 - 1.0) * inv;
+    }
+    if (s2 < G.rc_c2) {
+        const double s = sqrt(s2);
+        const double ex = exp(-G.alpha2 * s2);
+        const double ec = erfc(G.alpha * s);
+        uc = g * c.qqk * (ec / s - G.erfc_rc_over_rc + G.Sc * (s - G.rc_coul));
+        fs += g * c.qqk * (ec * inv + G.cex * ex / s - G.Sc) / s;
+    }
+}
+
+// --------------------------------------------------------------------------
+// Wavefront reductions (fixed butterfly order: bitwise reproducible).
+// --------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+
+}  // namespace h4d

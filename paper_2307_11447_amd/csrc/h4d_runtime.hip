@@ -1,0 +1,684 @@
+// h4d_runtime.hip -- host side of the C ABI declared in include/h4d.h.
+//
+// Owns the device buffers of a system, enqueues the kernels of each trial
+// on the caller's stream, and reads back one small record per trial (the
+// only synchronisation of a trial).
+#include <hip/hip_ext.h>
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "h4d.h"
+#include "h4d_kernels.hpp"
+
+using namespace h4d;
+
+static_assert(sizeof(TrialRec) == sizeof(h4d_trial), "record layout");
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPC(x)                                                                                   \
+    do {                                                                                          \
+        hipError_t e_ = (x);                                                                      \
+        if (e_ != hipSuccess) return fail(H4D_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+int blocks_for(int n) { return std::max(1, (n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+struct h4d_system {
+    h4d_params p{};
+    hipStream_t stream = nullptr;
+    KArgs a{};
+    PairCoef coef_h[kMaxTypes * kMaxTypes]{};
+    int cap = 0;
+    int n_host = 0, nsalt_host = 0, n_mol = 0;
+    int rebuild_every = 1;
+    int clean_trials = 0;
+    int partial_blocks = 0;
+    TrialRec *h_rec = nullptr;
+    Ctl *h_ctl = nullptr;
+    // step-kernel timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev;
+    int64_t step_launches = 0;
+    double step_ms = 0.0;
+    int trial_rebuilds = 0;
+    std::vector<void *> allocs;
+    // running statistics (Eq. 1)
+    int64_t n_trials = 0, n_ins = 0, n_ins_acc = 0, n_del = 0, n_del_acc = 0;
+    double N_sum = 0.0, N2_sum = 0.0;
+
+    template <class T>
+    int alloc(T **ptr, size_t count) {
+        void *q = nullptr;
+        if (hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess)
+            return fail(H4D_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+        allocs.push_back(q);
+        *ptr = static_cast<T *>(q);
+        return H4D_OK;
+    }
+    void release(void *q) {
+        auto it = std::find(allocs.begin(), allocs.end(), q);
+        if (it != allocs.end()) { (void)hipFree(q); allocs.erase(it); }
+    }
+    ~h4d_system() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        for (void *q : allocs) (void)hipFree(q);
+        if (h_rec) (void)hipHostFree(h_rec);
+        if (h_ctl) (void)hipHostFree(h_ctl);
+    }
+};
+
+namespace {
+
+int check_params(const h4d_params &p) {
+    if (p.n_types < 1 || p.n_types > kMaxTypes) return fail(H4D_EINVAL, "n_types must be in [1, 8]");
+    if (p.cation_type < 0 || p.cation_type >= p.n_types || p.anion_type < 0 || p.anion_type >= p.n_types ||
+        p.cation_type == p.anion_type)
+        return fail(H4D_EINVAL, "cation_type / anion_type invalid");
+    if (p.n_steps_max > 0) {
+        if (p.n_steps_min < 1 || p.n_steps_max < p.n_steps_min)
+            return fail(H4D_EINVAL, "need 1 <= n_steps_min <= n_steps_max");
+    } else if (p.n_steps < 1) {
+        return fail(H4D_EINVAL, "n_steps must be >= 1");
+    }
+    if (p.precision != H4D_PREC_FP64 && p.precision != H4D_PREC_FP32)
+        return fail(H4D_EINVAL, "precision must be H4D_PREC_FP64 or H4D_PREC_FP32");
+    for (int t = 0; t < p.n_types; ++t)
+        if (!(p.mass[t] > 0.0)) return fail(H4D_EINVAL, "masses must be positive");
+    if (!(p.kT > 0.0) || !(p.dt > 0.0) || !(p.accel > 0.0) || !(p.lambda_s > 0.0))
+        return fail(H4D_EINVAL, "kT, dt, accel and lambda_s must be positive");
+    if (!(p.rc_lj > 0.0) || !(p.rc_coul > 0.0) || !(p.skin >= 0.0) || !(p.w_max >= 0.0) ||
+        !(p.dsf_alpha >= 0.0))
+        return fail(H4D_EINVAL, "cutoffs must be positive, skin, w_max and dsf_alpha non-negative");
+    const double rc = std::max(p.rc_lj, p.rc_coul);
+    for (int d = 0; d < 3; ++d)
+        if (!(p.box[d] >= 2.0 * rc))
+            return fail(H4D_EINVAL, "every box edge must be at least twice the largest cutoff");
+    if (p.water) return fail(H4D_EINVAL, "rigid water is not supported by this build");
+    return H4D_OK;
+}
+
+void setup_geo(h4d_system *s) {
+    const h4d_params &p = s->p;
+    Geo &G = s->a.G;
+    const double two32 = 4294967296.0;
+    for (int d = 0; d < 3; ++d) {
+        G.L[d] = p.box[d];
+        G.fx_inv[d] = two32 / p.box[d];
+        G.fx_scale[d] = (float)(p.box[d] / two32);
+    }
+    const double rc = std::max(p.rc_lj, p.rc_coul);
+    const double rlist = rc + p.skin;
+    G.rc_lj2 = p.rc_lj * p.rc_lj;
+    G.rc_c2 = p.rc_coul * p.rc_coul;
+    G.rc_max2 = rc * rc;
+    G.rlist2 = rlist * rlist;
+    G.half_skin2 = 0.25 * p.skin * p.skin;
+    G.rc_lj2f = (float)G.rc_lj2;
+    G.rc_c2f = (float)G.rc_c2;
+    G.rc_max2f = (float)G.rc_max2;
+    const double al = p.dsf_alpha, Rc = p.rc_coul;
+    const double two_over_sqrtpi = 1.1283791670955125739;
+    G.alpha = al;
+    G.alpha2 = al * al;
+    G.cex = two_over_sqrtpi * al;
+    G.erfc_rc_over_rc = std::erfc(al * Rc) / Rc;
+    G.Sc = std::erfc(al * Rc) / (Rc * Rc) + two_over_sqrtpi * al * std::exp(-al * al * Rc * Rc) / Rc;
+    G.rc_coul = Rc;
+    G.alphaf = (float)G.alpha;
+    G.alpha2f = (float)G.alpha2;
+    G.cexf = (float)G.cex;
+    G.Scf = (float)G.Sc;
+    G.dt = p.dt;
+    G.half_dt = 0.5 * p.dt;
+    G.accel = p.accel;
+    G.kT = p.kT;
+    G.w_max = p.w_max;
+    G.kappa = p.kappa_sr;
+    G.volume = p.box[0] * p.box[1] * p.box[2];
+    G.lambda3 = p.lambda_s * p.lambda_s * p.lambda_s;
+    G.beta = 1.0 / p.kT;
+    G.beta_mu = p.beta_mu;
+    G.use_cells = 1;
+    for (int d = 0; d < 3; ++d) {
+        G.ncell[d] = (int)std::floor(p.box[d] / rlist);
+        if (G.ncell[d] < 3) G.use_cells = 0;
+    }
+    if (!G.use_cells) G.ncell[0] = G.ncell[1] = G.ncell[2] = 1;
+    G.n_types = p.n_types;
+    G.water = p.water;
+    G.d_oh = p.d_oh;
+    G.d_hh = p.d_hh;
+    // Lorentz-Berthelot pair table
+    for (int i = 0; i < kMaxTypes; ++i)
+        for (int j = 0; j < kMaxTypes; ++j) {
+            PairCoef &c = s->coef_h[i * kMaxTypes + j];
+            c = PairCoef{};
+            if (i >= p.n_types || j >= p.n_types) continue;
+            const double sig = 0.5 * (p.sigma[i] + p.sigma[j]);
+            const double eps = std::sqrt(p.eps[i] * p.eps[j]);
+            const double a6 = std::pow(sig / p.rc_lj, 6.0);
+            c.sig2 = sig * sig;
+            c.eps = eps;
+            c.qqk = p.coulomb_k * p.charge[i] * p.charge[j];
+            c.lj_shift = a6 * a6 - a6;
+            c.sig2f = (float)c.sig2;
+            c.eps24f = (float)(24.0 * eps);
+            c.qqkf = (float)c.qqk;
+        }
+}
+
+// Neighbour and cell capacities from the density (grown on overflow).
+void initial_capacities(h4d_system *s, int n) {
+    const h4d_params &p = s->p;
+    const double V = p.box[0] * p.box[1] * p.box[2];
+    const double rho = std::max(1.0, (double)n) / V;
+    const double rlist = std::max(p.rc_lj, p.rc_coul) + p.skin;
+    const double nb = 4.18879020478639 * rlist * rlist * rlist * rho;
+    int cap = (int)(1.5 * nb) + 32;
+    cap = (cap + 7) & ~7;
+    s->a.nbr_cap = std::min(cap, std::max(8, s->cap));
+    const Geo &G = s->a.G;
+    const double cell_vol = V / ((double)G.ncell[0] * G.ncell[1] * G.ncell[2]);
+    int cc = (int)(2.0 * rho * cell_vol) + 32;
+    s->a.cell_cap = G.use_cells ? std::min(cc, std::max(32, s->cap)) : 1;
+    s->a.ncell_total = G.ncell[0] * G.ncell[1] * G.ncell[2];
+}
+
+int alloc_lists(h4d_system *s) {
+    int rc;
+    if ((rc = s->alloc(&s->a.nbr, (size_t)s->a.nbr_cap * s->cap))) return rc;
+    if ((rc = s->alloc(&s->a.cell_cnt, (size_t)s->a.ncell_total))) return rc;
+    if ((rc = s->alloc(&s->a.cell_atoms, (size_t)s->a.ncell_total * s->a.cell_cap))) return rc;
+    return H4D_OK;
+}
+
+int rebuild(h4d_system *s, int b, int k, int G) {
+    KArgs &a = s->a;
+    hipStream_t st = s->stream;
+    if (a.G.use_cells) {
+        hipLaunchKernelGGL(k_cell_clear, dim3(blocks_for(a.ncell_total)), dim3(kBlock), 0, st, a, k);
+        hipLaunchKernelGGL(k_cell_bin, dim3(G), dim3(kBlock), 0, st, a, b, k);
+        hipLaunchKernelGGL(k_cell_sort, dim3(a.ncell_total), dim3(kWave), a.cell_cap * sizeof(int), st, a, k);
+    }
+    hipLaunchKernelGGL(k_list, dim3(G), dim3(kBlock), 0, st, a, b, k);
+    HIPC(hipGetLastError());
+    return H4D_OK;
+}
+
+int read_ctl(h4d_system *s) {
+    HIPC(hipMemcpyAsync(s->h_ctl, s->a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s->stream));
+    HIPC(hipStreamSynchronize(s->stream));
+    return H4D_OK;
+}
+
+int clear_errors(h4d_system *s) {
+    Ctl *c = s->h_ctl;
+    c->err = 0;
+    c->retry = 0;
+    c->max_nbr = 0;
+    c->max_cell = 0;
+    HIPC(hipMemcpyAsync(s->a.ctl, c, sizeof(Ctl), hipMemcpyHostToDevice, s->stream));
+    HIPC(hipStreamSynchronize(s->stream));
+    return H4D_OK;
+}
+
+// Grow the list storage after an overflow.
+int grow_lists(h4d_system *s, unsigned err) {
+    KArgs &a = s->a;
+    const Ctl *c = s->h_ctl;
+    if (err & kErrNbr) {
+        int need = std::max(c->max_nbr, a.nbr_cap + 8);
+        need = ((int)(need * 1.25) + 7) & ~7;
+        s->release(a.nbr);
+        a.nbr_cap = need;
+        int rc = s->alloc(&a.nbr, (size_t)a.nbr_cap * s->cap);
+        if (rc) return rc;
+    }
+    if (err & kErrCell) {
+        int need = std::max(c->max_cell, a.cell_cap + 8);
+        need = (int)(need * 1.25) + 8;
+        s->release(a.cell_atoms);
+        a.cell_cap = need;
+        int rc = s->alloc(&a.cell_atoms, (size_t)a.ncell_total * a.cell_cap);
+        if (rc) return rc;
+    }
+    return H4D_OK;
+}
+
+int launch_trial(h4d_system *s, int move) {
+    KArgs &a = s->a;
+    hipStream_t st = s->stream;
+    const int G = blocks_for(s->n_host + 2);
+    int rc;
+    hipLaunchKernelGGL(k_propose, dim3(1), dim3(kBlock), 0, st, a, move);
+    hipLaunchKernelGGL(k_mb, dim3(G), dim3(kBlock), 0, st, a);
+    if ((rc = rebuild(s, 0, 0, G))) return rc;
+    hipLaunchKernelGGL(k_energy, dim3(G), dim3(kBlock), 0, st, a, 0, -1, 0.0, 0);
+    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kBlock), 0, st, a, 0, G);
+    hipLaunchKernelGGL(k_snapshot, dim3(G), dim3(kBlock), 0, st, a);
+    const int nf_launch = s->p.n_steps_max > 0 ? s->p.n_steps_max : s->p.n_steps;
+    const int M = std::max(1, s->rebuild_every);
+    s->trial_rebuilds = 0;
+    if (s->timing && (int)s->ev.size() < 2 * (nf_launch + 1)) {
+        while ((int)s->ev.size() < 2 * (nf_launch + 1)) {
+            hipEvent_t e;
+            HIPC(hipEventCreate(&e));
+            s->ev.push_back(e);
+        }
+    }
+    for (int k = 0; k <= nf_launch; ++k) {
+        if (k > 0 && k % M == 0) {
+            if ((rc = rebuild(s, k & 1, k, G))) return rc;
+            s->trial_rebuilds += 1;
+        }
+        hipEvent_t e0 = s->timing ? s->ev[2 * k] : nullptr, e1 = s->timing ? s->ev[2 * k + 1] : nullptr;
+        if (s->p.precision == H4D_PREC_FP32)
+            hipExtLaunchKernelGGL(k_step<1>, dim3(G + 1), dim3(kBlock), 0, st, e0, e1, 0, a, k, k & 1);
+        else
+            hipExtLaunchKernelGGL(k_step<0>, dim3(G + 1), dim3(kBlock), 0, st, e0, e1, 0, a, k, k & 1);
+    }
+    hipLaunchKernelGGL(k_energy, dim3(G), dim3(kBlock), 0, st, a, 1, -1, 0.0, -1);
+    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kBlock), 0, st, a, 1, G);
+    hipLaunchKernelGGL(k_metropolis, dim3(1), dim3(1), 0, st, a);
+    hipLaunchKernelGGL(k_commit, dim3(G), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL(k_commit2, dim3(G), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL(k_commit_ctl, dim3(1), dim3(1), 0, st, a);
+    HIPC(hipGetLastError());
+    HIPC(hipMemcpyAsync(s->h_rec, a.rec, sizeof(TrialRec), hipMemcpyDeviceToHost, st));
+    HIPC(hipMemcpyAsync(s->h_ctl, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    if (s->timing) {
+        const int nf_dev = std::min(s->h_ctl->nf, nf_launch);
+        for (int k = 0; k <= nf_dev; ++k) {
+            float ms = 0.f;
+            HIPC(hipEventElapsedTime(&ms, s->ev[2 * k], s->ev[2 * k + 1]));
+            s->step_ms += ms;
+            s->step_launches += 1;
+        }
+    }
+    return H4D_OK;
+}
+
+int run_one(h4d_system *s, int move, h4d_trial *out) {
+    bool retried = false;
+    for (int attempt = 0; attempt < 16; ++attempt) {
+        int rc = launch_trial(s, move);
+        if (rc) return rc;
+        const Ctl *c = s->h_ctl;
+        if (c->retry) {
+            const unsigned err = c->err;
+            if (err & kErrCap) return fail(H4D_ECAPACITY, "atom capacity exhausted");
+            if ((rc = grow_lists(s, err))) return rc;
+            if (err & kErrSkin) {
+                s->rebuild_every = std::max(1, (s->rebuild_every * 3) / 4);
+                s->clean_trials = 0;
+            }
+            if ((rc = clear_errors(s))) return rc;
+            retried = true;
+            continue;
+        }
+        h4d_trial r;
+        std::memcpy(&r, s->h_rec, sizeof(r));
+        if (retried) r.flags |= H4D_FLAG_RETRIED;
+        r.n_rebuilds = s->trial_rebuilds;
+        if (out) *out = r;
+        s->n_host = c->n;
+        s->nsalt_host = c->nsalt;
+        s->n_trials += 1;
+        if (r.move > 0) { s->n_ins += 1; s->n_ins_acc += r.accepted; }
+        else { s->n_del += 1; s->n_del_acc += r.accepted; }
+        s->N_sum += (double)c->nsalt;
+        s->N2_sum += (double)c->nsalt * (double)c->nsalt;
+        if (++s->clean_trials >= 100 && s->p.rebuild_every == 0) {
+            s->rebuild_every += 1;
+            s->clean_trials = 0;
+        }
+        if (r.flags & H4D_FLAG_NONFINITE) {
+            if (!(r.dH == r.dH)) return fail(H4D_ENONFINITE, "NaN energy; the trial was rolled back");
+        }
+        return H4D_OK;
+    }
+    return fail(H4D_EHIP, "trial could not be completed after resizing the lists");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *h4d_last_error(void) { return g_err.c_str(); }
+
+int32_t h4d_init_system(const h4d_params *params, int32_t n_atoms, int32_t n_salt, int32_t n_mol,
+                        const double *pos, const int32_t *type, const int32_t *mol, const int64_t *tag,
+                        void *hip_stream, h4d_system **out) {
+    g_err.clear();
+    if (!params || !out || n_atoms < 0 || n_salt < 0 || (n_atoms > 0 && (!pos || !type || !tag)))
+        return fail(H4D_EINVAL, "null argument or negative size");
+    *out = nullptr;
+    int rc = check_params(*params);
+    if (rc) return rc;
+    int ndev = 0;
+    const hipError_t de = hipGetDeviceCount(&ndev);
+    if (de != hipSuccess || ndev < 1)
+        return fail(H4D_ENODEV, std::string("no HIP device (hipGetDeviceCount: ") + hipGetErrorString(de) +
+                                    ", count " + std::to_string(ndev) + ")");
+    // validate the configuration
+    int ncat = 0, nan_ = 0;
+    for (int i = 0; i < n_atoms; ++i) {
+        if (type[i] < 0 || type[i] >= params->n_types) return fail(H4D_EINVAL, "atom type out of range");
+        ncat += type[i] == params->cation_type;
+        nan_ += type[i] == params->anion_type;
+        if (i > 0 && tag[i] <= tag[i - 1]) return fail(H4D_EINVAL, "tags must ascend in array order");
+        for (int d = 0; d < 3; ++d)
+            if (!(pos[3 * i + d] >= 0.0 && pos[3 * i + d] < params->box[d]))
+                return fail(H4D_EINVAL, "positions must lie in [0, L)");
+    }
+    if (ncat != n_salt || nan_ != n_salt) return fail(H4D_EINVAL, "n_salt must equal the cation and anion counts");
+
+    auto *s = new h4d_system();
+    s->p = *params;
+    s->stream = static_cast<hipStream_t>(hip_stream);
+    s->cap = params->capacity > 0 ? params->capacity : n_atoms + 4096;
+    if (s->cap < n_atoms + 2) { delete s; return fail(H4D_EINVAL, "capacity below n_atoms + 2"); }
+    s->n_host = n_atoms;
+    s->nsalt_host = n_salt;
+    s->n_mol = n_mol;
+    setup_geo(s);
+    initial_capacities(s, n_atoms);
+    KArgs &a = s->a;
+    a.cap = s->cap;
+    a.seed = params->seed;
+    a.stream = params->stream;
+    a.n_steps = params->n_steps;
+    a.n_steps_min = params->n_steps_min;
+    a.n_steps_max = params->n_steps_max;
+    a.cation_type = params->cation_type;
+    a.anion_type = params->anion_type;
+    s->partial_blocks = blocks_for(s->cap + 2) + 1;   // every grid of the trial fits
+    const size_t C = (size_t)s->cap;
+    PairCoef *coef_d = nullptr;
+    double *mass_d = nullptr;
+    if ((rc = s->alloc(&a.pos[0], C)) || (rc = s->alloc(&a.pos[1], C)) || (rc = s->alloc(&a.fx[0], C)) ||
+        (rc = s->alloc(&a.fx[1], C)) || (rc = s->alloc(&a.vel, C)) || (rc = s->alloc(&a.pos0, C)) ||
+        (rc = s->alloc(&a.posb, C)) || (rc = s->alloc(&a.force, C)) || (rc = s->alloc(&a.tag, C)) ||
+        (rc = s->alloc(&a.type, C)) || (rc = s->alloc(&a.mol, C)) || (rc = s->alloc(&a.tpos, C)) ||
+        (rc = s->alloc(&a.ttag, C)) || (rc = s->alloc(&a.ttype, C)) || (rc = s->alloc(&a.tmol, C)) ||
+        (rc = s->alloc(&a.nnbr, C)) || (rc = s->alloc(&a.partial, (size_t)s->partial_blocks * 4)) ||
+        (rc = s->alloc(&a.ctl, 1)) || (rc = s->alloc(&a.rec, 1)) ||
+        (rc = s->alloc(&coef_d, (size_t)kMaxTypes * kMaxTypes)) || (rc = s->alloc(&mass_d, kMaxTypes)) ||
+        (rc = alloc_lists(s))) {
+        delete s;
+        return rc;
+    }
+    a.coef = coef_d;
+    a.mass = mass_d;
+    if (hipHostMalloc((void **)&s->h_rec, sizeof(TrialRec)) != hipSuccess ||
+        hipHostMalloc((void **)&s->h_ctl, sizeof(Ctl)) != hipSuccess) {
+        delete s;
+        return fail(H4D_ENOMEM, "pinned host allocation failed");
+    }
+    // upload
+    std::vector<double4> hp(std::max(1, n_atoms));
+    std::vector<int> hm(std::max(1, n_atoms), -1);
+    for (int i = 0; i < n_atoms; ++i) {
+        long long meta = type[i];
+        double wbits;
+        std::memcpy(&wbits, &meta, sizeof(wbits));
+        hp[i] = make_double4(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], wbits);
+        if (mol) hm[i] = mol[i];
+    }
+    std::memset(s->h_ctl, 0, sizeof(Ctl));
+    Ctl &c = *s->h_ctl;
+    c.n = n_atoms;
+    c.n_all = n_atoms;
+    c.nsalt = n_salt;
+    c.next_tag = n_atoms ? tag[n_atoms - 1] + 1 : 0;
+    c.trial = 0;
+    c.nf = 0;
+    c.ic = c.ia = -1;
+    double mass_h[kMaxTypes] = {0};
+    for (int t = 0; t < params->n_types; ++t) mass_h[t] = params->mass[t];
+#define UPLOAD(dst, src, bytes)                                                                        \
+    if (hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess) {                           \
+        delete s;                                                                                      \
+        return fail(H4D_EHIP, "upload failed");                                                       \
+    }
+    if (n_atoms > 0) {
+        UPLOAD(a.pos[0], hp.data(), sizeof(double4) * n_atoms);
+        UPLOAD(a.type, type, sizeof(int) * n_atoms);
+        UPLOAD(a.mol, hm.data(), sizeof(int) * n_atoms);
+        UPLOAD(a.tag, tag, sizeof(long long) * n_atoms);
+    }
+    UPLOAD(a.ctl, &c, sizeof(Ctl));
+    UPLOAD(coef_d, s->coef_h, sizeof(s->coef_h));
+    UPLOAD(mass_d, mass_h, sizeof(mass_h));
+#undef UPLOAD
+    // rebuild interval: the fastest atoms (5 standard deviations) cover half
+    // the skin; adapted on overflow
+    double m_min = params->mass[0];
+    for (int t = 1; t < params->n_types; ++t) m_min = std::min(m_min, params->mass[t]);
+    const double vmax = 5.0 * std::sqrt(params->accel * params->kT / m_min);
+    s->rebuild_every = params->rebuild_every > 0
+                           ? params->rebuild_every
+                           : std::max(1, (int)std::floor(0.5 * params->skin / (vmax * params->dt)));
+    if ((rc = h4d_build_neighbors(s))) { delete s; return rc; }
+    *out = s;
+    return H4D_OK;
+}
+
+int32_t h4d_build_neighbors(h4d_system *s) {
+    if (!s) return fail(H4D_EINVAL, "null handle");
+    for (int attempt = 0; attempt < 8; ++attempt) {
+        int rc = rebuild(s, 0, 0, blocks_for(s->n_host));
+        if (rc) return rc;
+        if ((rc = read_ctl(s))) return rc;
+        const unsigned err = s->h_ctl->err;
+        if (!(err & (kErrNbr | kErrCell))) return H4D_OK;
+        if ((rc = grow_lists(s, err))) return rc;
+        if ((rc = clear_errors(s))) return rc;
+    }
+    return fail(H4D_ECAPACITY, "neighbour lists could not be sized");
+}
+
+int32_t h4d_run_nemd_trial(h4d_system *s, int32_t move, h4d_trial *out) {
+    if (!s) return fail(H4D_EINVAL, "null handle");
+    if (move < -1 || move > 1) return fail(H4D_EINVAL, "move must be -1, 0 or +1");
+    return run_one(s, move, out);
+}
+
+int32_t h4d_run_trials(h4d_system *s, int32_t n, int32_t move, h4d_trial *out) {
+    if (!s || n < 0) return fail(H4D_EINVAL, "null handle or negative count");
+    if (move < -1 || move > 1) return fail(H4D_EINVAL, "move must be -1, 0 or +1");
+    for (int q = 0; q < n; ++q) {
+        int rc = run_one(s, move, out ? out + q : nullptr);
+        if (rc) return rc;
+    }
+    return H4D_OK;
+}
+
+int32_t h4d_set_trial_index(h4d_system *s, uint64_t trial) {
+    if (!s) return fail(H4D_EINVAL, "null handle");
+    int rc = read_ctl(s);
+    if (rc) return rc;
+    s->h_ctl->trial = (long long)trial;
+    HIPC(hipMemcpyAsync(s->a.ctl, s->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, s->stream));
+    HIPC(hipStreamSynchronize(s->stream));
+    return H4D_OK;
+}
+
+int32_t h4d_get_state(h4d_system *s, int32_t cap, int32_t *n, int32_t *n_salt, double *pos, double *vel,
+                      int32_t *type, int32_t *mol, int64_t *tag) {
+    if (!s) return fail(H4D_EINVAL, "null handle");
+    int rc = read_ctl(s);
+    if (rc) return rc;
+    const int nn = s->h_ctl->n;
+    if (n) *n = nn;
+    if (n_salt) *n_salt = s->h_ctl->nsalt;
+    if ((pos || vel || type || mol || tag) && cap < nn) return fail(H4D_EINVAL, "cap smaller than the atom count");
+    std::vector<double4> buf(std::max(1, nn));
+    if (pos && nn) {
+        HIPC(hipMemcpy(buf.data(), s->a.pos[0], sizeof(double4) * nn, hipMemcpyDeviceToHost));
+        for (int i = 0; i < nn; ++i) { pos[3 * i] = buf[i].x; pos[3 * i + 1] = buf[i].y; pos[3 * i + 2] = buf[i].z; }
+    }
+    if (vel && nn) {
+        HIPC(hipMemcpy(buf.data(), s->a.vel, sizeof(double4) * nn, hipMemcpyDeviceToHost));
+        for (int i = 0; i < nn; ++i) { vel[3 * i] = buf[i].x; vel[3 * i + 1] = buf[i].y; vel[3 * i + 2] = buf[i].z; }
+    }
+    if (type && nn) HIPC(hipMemcpy(type, s->a.type, sizeof(int) * nn, hipMemcpyDeviceToHost));
+    if (mol && nn) HIPC(hipMemcpy(mol, s->a.mol, sizeof(int) * nn, hipMemcpyDeviceToHost));
+    if (tag && nn) HIPC(hipMemcpy(tag, s->a.tag, sizeof(long long) * nn, hipMemcpyDeviceToHost));
+    return H4D_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+__global__ void k_set_fly(KArgs a, int i, int on) {
+    double4 p = a.pos[0][i];
+    int m = meta_of(p);
+    m = on ? (m | kFlyBit) : (m & ~kFlyBit);
+    a.pos[0][i] = with_meta(p.x, p.y, p.z, m);
+}
+
+__global__ __launch_bounds__(kBlock) void k_refresh_fx(KArgs a) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= a.ctl->n_all) return;
+    const double4 p = a.pos[0][i];
+    a.fx[0][i] = make_uint4(to_fixed(p.x, a.G.fx_inv[0]), to_fixed(p.y, a.G.fx_inv[1]),
+                            to_fixed(p.z, a.G.fx_inv[2]), (unsigned)meta_of(p));
+}
+
+int energies(h4d_system *s, int mode, double w, double out[4]) {
+    KArgs &a = s->a;
+    const int G = blocks_for(s->n_host);
+    hipLaunchKernelGGL(k_energy, dim3(G), dim3(kBlock), 0, s->stream, a, 2, mode, w, 0);
+    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kBlock), 0, s->stream, a, 2, G);
+    HIPC(hipGetLastError());
+    int rc = read_ctl(s);
+    if (rc) return rc;
+    out[0] = s->h_ctl->Ulj + s->h_ctl->Uc;
+    out[1] = s->h_ctl->Ulj;
+    out[2] = s->h_ctl->Uc;
+    out[3] = s->h_ctl->vir;
+    return H4D_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t h4d_forces_at(h4d_system *s, const int32_t flying[2], double w, double *forces, double *energy) {
+    if (!s || !flying) return fail(H4D_EINVAL, "null argument");
+    const int n = s->n_host;
+    for (int q = 0; q < 2; ++q)
+        if (flying[q] < -1 || flying[q] >= n) return fail(H4D_EINVAL, "flying index out of range");
+    KArgs &a = s->a;
+    const int G = blocks_for(n);
+    for (int q = 0; q < 2; ++q)
+        if (flying[q] >= 0) hipLaunchKernelGGL(k_set_fly, dim3(1), dim3(1), 0, s->stream, a, flying[q], 1);
+    hipLaunchKernelGGL(k_refresh_fx, dim3(G), dim3(kBlock), 0, s->stream, a);
+    int rc = h4d_build_neighbors(s);
+    if (rc) return rc;
+    if (s->p.precision == H4D_PREC_FP32)
+        hipLaunchKernelGGL(k_forces<1>, dim3(G), dim3(kBlock), 0, s->stream, a, w);
+    else
+        hipLaunchKernelGGL(k_forces<0>, dim3(G), dim3(kBlock), 0, s->stream, a, w);
+    HIPC(hipGetLastError());
+    double e[4];
+    if ((rc = energies(s, 0, w, e))) return rc;
+    if (forces && n) {
+        std::vector<double4> buf(n);
+        HIPC(hipMemcpy(buf.data(), a.force, sizeof(double4) * n, hipMemcpyDeviceToHost));
+        for (int i = 0; i < n; ++i) {
+            forces[3 * i] = buf[i].x;
+            forces[3 * i + 1] = buf[i].y;
+            forces[3 * i + 2] = buf[i].z;
+        }
+    }
+    if (energy) { energy[0] = e[0]; energy[1] = e[1]; energy[2] = e[2]; }
+    for (int q = 0; q < 2; ++q)
+        if (flying[q] >= 0) hipLaunchKernelGGL(k_set_fly, dim3(1), dim3(1), 0, s->stream, a, flying[q], 0);
+    HIPC(hipGetLastError());
+    HIPC(hipStreamSynchronize(s->stream));
+    return H4D_OK;
+}
+
+int32_t h4d_sample_observables(h4d_system *s, h4d_observables *out) {
+    if (!s || !out) return fail(H4D_EINVAL, "null argument");
+    double e[4];
+    int rc = energies(s, 0, 0.0, e);
+    if (rc) return rc;
+    std::memset(out, 0, sizeof(*out));
+    const Ctl *c = s->h_ctl;
+    out->n_atoms = c->n;
+    out->n_salt = c->nsalt;
+    out->n_trials = s->n_trials;
+    out->n_ins = s->n_ins;
+    out->n_ins_acc = s->n_ins_acc;
+    out->n_del = s->n_del;
+    out->n_del_acc = s->n_del_acc;
+    out->U = e[0];
+    out->U_lj = e[1];
+    out->U_coul = e[2];
+    out->virial = e[3];
+    out->pressure_virial = ((double)c->n * s->p.kT + e[3] / 3.0) / s->a.G.volume;
+    if (s->n_trials > 0) {
+        out->N_mean = s->N_sum / (double)s->n_trials;
+        out->N2_mean = s->N2_sum / (double)s->n_trials;
+        out->chi = out->N_mean > 0.0 ? (out->N2_mean - out->N_mean * out->N_mean) / out->N_mean : 0.0;
+    }
+    return H4D_OK;
+}
+
+int32_t h4d_set_timing(h4d_system *s, int32_t on) {
+    if (!s) return fail(H4D_EINVAL, "null handle");
+    s->timing = on != 0;
+    s->step_launches = 0;
+    s->step_ms = 0.0;
+    return H4D_OK;
+}
+
+int32_t h4d_get_timing(h4d_system *s, h4d_timing *out) {
+    if (!s || !out) return fail(H4D_EINVAL, "null argument");
+    unsigned long long *d = nullptr;
+    int rc = s->alloc(&d, 1);
+    if (rc) return rc;
+    HIPC(hipMemsetAsync(d, 0, sizeof(*d), s->stream));
+    hipLaunchKernelGGL(k_sum_nbr, dim3(blocks_for(s->n_host)), dim3(kBlock), 0, s->stream, s->a, d);
+    unsigned long long sum = 0;
+    HIPC(hipMemcpyAsync(&sum, d, sizeof(sum), hipMemcpyDeviceToHost, s->stream));
+    HIPC(hipStreamSynchronize(s->stream));
+    s->release(d);
+    out->step_launches = s->step_launches;
+    out->step_ms = s->step_ms;
+    out->mean_nbr = s->n_host > 0 ? (double)sum / (double)s->n_host : 0.0;
+    out->rebuild_every = s->rebuild_every;
+    out->nbr_cap = s->a.nbr_cap;
+    return H4D_OK;
+}
+
+int32_t h4d_destroy(h4d_system *s) {
+    if (!s) return H4D_OK;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    else (void)hipDeviceSynchronize();
+    delete s;
+    return H4D_OK;
+}
+
+}  // extern "C"

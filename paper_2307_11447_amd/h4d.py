@@ -1,0 +1,259 @@
+"""ctypes binding of the C ABI in include/h4d.h (argument marshalling only).
+
+Every computation runs in the HIP library ``libh4d.so`` next to this file;
+if it is missing, or no GPU is present, the calls raise: there is no CPU
+fallback.  PyTorch, when importable, only supplies the current HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libh4d.so")
+MAX_TYPES = 8
+
+H4D_OK, H4D_EINVAL, H4D_ENOMEM, H4D_EHIP, H4D_ECAPACITY, H4D_ENONFINITE, H4D_ENODEV = 0, -1, -2, -3, -4, -5, -6
+MOVE_AUTO, MOVE_INSERT, MOVE_DELETE = 0, 1, -1
+PREC_FP64, PREC_FP32 = 0, 1
+FLAG_EMPTY, FLAG_NONFINITE, FLAG_RETRIED = 0x1, 0x2, 0x4
+
+
+class H4DError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"h4d error {code}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("n_types", C.c_int32), ("cation_type", C.c_int32), ("anion_type", C.c_int32),
+        ("n_steps", C.c_int32), ("n_steps_min", C.c_int32), ("n_steps_max", C.c_int32),
+        ("water", C.c_int32), ("precision", C.c_int32), ("capacity", C.c_int32),
+        ("rebuild_every", C.c_int32),
+        ("mass", C.c_double * MAX_TYPES), ("charge", C.c_double * MAX_TYPES),
+        ("sigma", C.c_double * MAX_TYPES), ("eps", C.c_double * MAX_TYPES),
+        ("box", C.c_double * 3),
+        ("kT", C.c_double), ("dt", C.c_double), ("w_max", C.c_double), ("kappa_sr", C.c_double),
+        ("rc_lj", C.c_double), ("rc_coul", C.c_double), ("dsf_alpha", C.c_double),
+        ("coulomb_k", C.c_double), ("beta_mu", C.c_double), ("lambda_s", C.c_double),
+        ("skin", C.c_double), ("d_oh", C.c_double), ("d_hh", C.c_double), ("accel", C.c_double),
+        ("seed", C.c_uint64), ("stream", C.c_uint64),
+    ]
+
+
+class Trial(C.Structure):
+    _fields_ = [
+        ("move", C.c_int32), ("accepted", C.c_int32), ("n_salt_before", C.c_int32),
+        ("n_salt_after", C.c_int32), ("n_steps", C.c_int32), ("flags", C.c_uint32),
+        ("n_atoms", C.c_int32), ("n_rebuilds", C.c_int32),
+        ("trial", C.c_int64), ("tag_c", C.c_int64), ("tag_a", C.c_int64),
+        ("dH", C.c_double), ("dU", C.c_double), ("dK", C.c_double), ("W_prot", C.c_double),
+        ("E_switch", C.c_double), ("dM", C.c_double), ("ln_ratio", C.c_double),
+        ("ln_u", C.c_double), ("ln_proposal", C.c_double), ("H0", C.c_double), ("H1", C.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Observables(C.Structure):
+    _fields_ = [
+        ("n_atoms", C.c_int64), ("n_salt", C.c_int64), ("n_trials", C.c_int64),
+        ("n_ins", C.c_int64), ("n_ins_acc", C.c_int64), ("n_del", C.c_int64), ("n_del_acc", C.c_int64),
+        ("U", C.c_double), ("U_lj", C.c_double), ("U_coul", C.c_double), ("virial", C.c_double),
+        ("pressure_virial", C.c_double), ("N_mean", C.c_double), ("N2_mean", C.c_double),
+        ("chi", C.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Timing(C.Structure):
+    _fields_ = [("step_launches", C.c_int64), ("step_ms", C.c_double), ("mean_nbr", C.c_double),
+                ("rebuild_every", C.c_int32), ("nbr_cap", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libh4d.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2307_11447_amd/build.py")
+        # One HIP runtime per process: if PyTorch is present, let it load its
+        # runtime first so that libh4d.so binds to the same libamdhip64.so.7
+        # instead of pulling in a second copy.
+        try:
+            import torch  # noqa: F401
+            torch.cuda.is_available()
+        except ImportError:
+            pass
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.h4d_last_error.restype = C.c_char_p
+        L.h4d_init_system.argtypes = [C.POINTER(Params), C.c_int32, C.c_int32, C.c_int32,
+                                      C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_int64), vp, C.POINTER(vp)]
+        L.h4d_build_neighbors.argtypes = [vp]
+        L.h4d_run_nemd_trial.argtypes = [vp, C.c_int32, C.POINTER(Trial)]
+        L.h4d_run_trials.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(Trial)]
+        L.h4d_sample_observables.argtypes = [vp, C.POINTER(Observables)]
+        L.h4d_get_state.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
+        L.h4d_set_trial_index.argtypes = [vp, C.c_uint64]
+        L.h4d_forces_at.argtypes = [vp, C.POINTER(C.c_int32), C.c_double, C.POINTER(C.c_double),
+                                    C.POINTER(C.c_double)]
+        L.h4d_destroy.argtypes = [vp]
+        L.h4d_set_timing.argtypes = [vp, C.c_int32]
+        L.h4d_get_timing.argtypes = [vp, C.POINTER(Timing)]
+        for name in ("h4d_set_timing", "h4d_get_timing", "h4d_init_system", "h4d_build_neighbors", "h4d_run_nemd_trial", "h4d_run_trials",
+                     "h4d_sample_observables", "h4d_get_state", "h4d_set_trial_index", "h4d_forces_at",
+                     "h4d_destroy"):
+            getattr(L, name).restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def _check(code: int):
+    if code != H4D_OK:
+        raise H4DError(code, lib().h4d_last_error().decode())
+
+
+def make_params(d: dict) -> Params:
+    p = Params()
+    p.n_types = d["n_types"]
+    p.cation_type, p.anion_type = d["cation_type"], d["anion_type"]
+    p.n_steps = d["n_steps"]
+    p.n_steps_min, p.n_steps_max = d.get("n_steps_min", 0), d.get("n_steps_max", 0)
+    p.water = d.get("water", 0)
+    prec = d.get("precision", "fp64")
+    p.precision = PREC_FP32 if prec in ("fp32", PREC_FP32) else PREC_FP64
+    p.capacity = d.get("capacity", 0)
+    p.rebuild_every = d.get("rebuild_every", 0)
+    for name in ("mass", "charge", "sigma", "eps"):
+        arr = getattr(p, name)
+        for i, v in enumerate(d[name]):
+            arr[i] = v
+    for i in range(3):
+        p.box[i] = d["box"][i]
+    for k in ("kT", "dt", "w_max", "kappa_sr", "rc_lj", "rc_coul", "coulomb_k", "beta_mu",
+              "lambda_s", "skin", "d_oh", "d_hh"):
+        setattr(p, k, d[k])
+    p.dsf_alpha = d["alpha"]
+    p.accel = d.get("accel", 1.0)
+    p.seed, p.stream = d["seed"], d.get("stream", 0)
+    return p
+
+
+def current_stream():
+    """The current torch HIP stream handle, or None."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return None
+
+
+class System:
+    """One simulation box on the GPU."""
+
+    def __init__(self, params: dict, x, type_, mol, tag, nsalt: int, n_mol: int = 0, stream=None):
+        self._h = None
+        self.params = dict(params)
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 3)
+        t = np.ascontiguousarray(type_, dtype=np.int32)
+        m = np.ascontiguousarray(mol, dtype=np.int32)
+        g = np.ascontiguousarray(tag, dtype=np.int64)
+        h = C.c_void_p()
+        p = make_params(params)
+        _check(lib().h4d_init_system(
+            C.byref(p), len(t), nsalt, n_mol,
+            x.ctypes.data_as(C.POINTER(C.c_double)), t.ctypes.data_as(C.POINTER(C.c_int32)),
+            m.ctypes.data_as(C.POINTER(C.c_int32)), g.ctypes.data_as(C.POINTER(C.c_int64)),
+            stream if stream is not None else current_stream(), C.byref(h)))
+        self._h = h
+
+    @classmethod
+    def from_workload(cls, w, **overrides):
+        params = dict(w.params)
+        params.update(overrides)
+        return cls(params, w.x, w.type, w.mol, w.tag, w.nsalt, w.n_mol)
+
+    def close(self):
+        if self._h is not None:
+            lib().h4d_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def build_neighbors(self):
+        _check(lib().h4d_build_neighbors(self._h))
+
+    def trial(self, move: int = MOVE_AUTO) -> dict:
+        r = Trial()
+        _check(lib().h4d_run_nemd_trial(self._h, move, C.byref(r)))
+        return r.as_dict()
+
+    def trials(self, n: int, move: int = MOVE_AUTO, as_array: bool = False):
+        recs = (Trial * max(n, 1))()
+        _check(lib().h4d_run_trials(self._h, n, move, recs))
+        if as_array:
+            return recs
+        return [recs[q].as_dict() for q in range(n)]
+
+    def set_trial_index(self, t: int):
+        _check(lib().h4d_set_trial_index(self._h, t))
+
+    def state(self) -> dict:
+        n = C.c_int32()
+        ns = C.c_int32()
+        _check(lib().h4d_get_state(self._h, 0, C.byref(n), C.byref(ns), None, None, None, None, None))
+        cap = n.value
+        x = np.zeros((max(cap, 1), 3)); v = np.zeros((max(cap, 1), 3))
+        t = np.zeros(max(cap, 1), np.int32); m = np.zeros(max(cap, 1), np.int32)
+        g = np.zeros(max(cap, 1), np.int64)
+        _check(lib().h4d_get_state(self._h, max(cap, 1), C.byref(n), C.byref(ns),
+                                   x.ctypes.data_as(C.POINTER(C.c_double)),
+                                   v.ctypes.data_as(C.POINTER(C.c_double)),
+                                   t.ctypes.data_as(C.POINTER(C.c_int32)),
+                                   m.ctypes.data_as(C.POINTER(C.c_int32)),
+                                   g.ctypes.data_as(C.POINTER(C.c_int64))))
+        k = n.value
+        return dict(n=k, nsalt=ns.value, x=x[:k], v=v[:k], type=t[:k], mol=m[:k], tag=g[:k])
+
+    def forces_at(self, flying=(-1, -1), w: float = 0.0):
+        st = self.state()
+        F = np.zeros((max(st["n"], 1), 3))
+        e = np.zeros(3)
+        fl = (C.c_int32 * 2)(*flying)
+        _check(lib().h4d_forces_at(self._h, fl, w, F.ctypes.data_as(C.POINTER(C.c_double)),
+                                   e.ctypes.data_as(C.POINTER(C.c_double))))
+        return F[: st["n"]], dict(U=e[0], U_lj=e[1], U_c=e[2])
+
+    def set_timing(self, on: bool = True):
+        _check(lib().h4d_set_timing(self._h, 1 if on else 0))
+
+    def timing(self) -> dict:
+        t = Timing()
+        _check(lib().h4d_get_timing(self._h, C.byref(t)))
+        return t.as_dict()
+
+    def observables(self) -> dict:
+        o = Observables()
+        _check(lib().h4d_sample_observables(self._h, C.byref(o)))
+        return o.as_dict()
