@@ -24,6 +24,26 @@ sys.path.insert(0, ROOT)
 
 METRIC = "accepted salt-pair exchanges/s + NEMD atom-steps/s (1 GPU), learned vs plain"
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_lj32k_traffic.txt")
+
+
+def counted_traffic():
+    """HBM bytes per step launch from the committed rocprofv3 counter summary,
+    or None if it is missing or was taken on different kernel sources."""
+    from paper_2307_11447_amd import rocprof_summary
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip().split()[0] if v.strip() else ""
+    if kv.get("kernel_source_sha256") != rocprof_summary.kernel_source_hash():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def wilson(k, n, z=1.96):
@@ -60,8 +80,15 @@ def main():
     ap.add_argument("--steps", type=int, default=2000, help="timed exchange trials")
     ap.add_argument("--warmup", type=int, default=20, help="untimed trials first")
     ap.add_argument("--beta-mu", type=float, default=-4.0)
+    ap.add_argument("--timing-trials", type=int, default=20,
+                    help="trials run after the timed region with HIP events on the step kernel")
     ap.add_argument("--cpu-steps", type=int, default=12, help="oracle sample length (NEMD steps)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--rebuild-every", type=int, default=0, help="list rebuild interval (0: library default)")
+    ap.add_argument("--lanes", type=int, default=0, help="lanes per atom (0: library default)")
+    ap.add_argument("--skin", type=float, default=0.0, help="Verlet skin (0: workload default)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run the stream-copy probe on MIB mebibytes and print its bandwidth")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -74,34 +101,52 @@ def main():
     from paper_2307_11447_amd import h4d
     from paper_2307_11447_amd import workloads as W
 
+    if args.copy_probe:
+        nbytes = args.copy_probe << 20
+        ms = h4d.stream_copy(nbytes, 20)
+        print(json.dumps({"probe": "stream_copy", "bytes": nbytes, "ms": ms,
+                          "GB_per_s": 2 * nbytes / (ms * 1e-3) / 1e9}), flush=True)
+        return
+
     w = W.config_lj_32k()
-    w.params.update(beta_mu=args.beta_mu)
+    w.params.update(beta_mu=args.beta_mu, rebuild_every=args.rebuild_every, lanes_per_atom=args.lanes)
+    if args.skin > 0:
+        w.params.update(skin=args.skin)
     sys_ = h4d.System.from_workload(w)
     if args.warmup:
         sys_.trials(args.warmup)
-    sys_.set_timing(True)
+    # timed region: every trial launched as one captured HIP graph
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     recs = sys_.trials(args.steps, as_array=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     wall = t1 - t0
+    # step-kernel duration: the same trials continue with HIP events around
+    # every launch of the fused step kernel (on the library's stream)
+    sys_.set_timing(True)
+    sys_.trials(args.timing_trials)
     timing = sys_.timing()
+    sys_.set_timing(False)
     n = args.steps
     atom_steps = sum(recs[q].n_atoms * recs[q].n_steps for q in range(n))
     acc = sum(recs[q].accepted for q in range(n))
     n_ins = sum(1 for q in range(n) if recs[q].move > 0)
     n_ins_acc = sum(recs[q].accepted for q in range(n) if recs[q].move > 0)
+    retried = sum(1 for q in range(n) if recs[q].flags & h4d.FLAG_RETRIED)
     lo, hi = wilson(acc, n)
     mean_nbr = timing["mean_nbr"]
     n_atoms_mean = atom_steps / max(1, sum(recs[q].n_steps for q in range(n)))
-    # algorithmic bytes of one fused step launch: per atom 4 B per list entry,
-    # 4 B count, 16 B own fixed-point record, 32 B own FP64 position, 32 B
-    # position at list build, 64 B velocity in+out, 48 B new position (FP64 +
-    # fixed point); neighbour gathers counted as cache hits
-    bytes_per_atom = 4.0 * mean_nbr + 196.0
+    # algorithmic bytes of one fused step launch, per atom: 4 B per list
+    # entry, 4 B list length, 16 B own fixed-point record, 32 B own FP64
+    # position, 16 B fixed-point position at the list build, 64 B velocity in
+    # and out, 48 B new position (FP64 + fixed point); neighbour records are
+    # gathered through the caches and not counted
+    bytes_per_atom = 4.0 * mean_nbr + 184.0
     avg_ms = timing["step_ms"] / max(1, timing["step_launches"])
     achieved = bytes_per_atom * n_atoms_mean / (avg_ms * 1e-3) / 1e9
+    tb = counted_traffic()
+    traffic = None if tb is None else tb / (avg_ms * 1e-3) / 1e9
     out = {
         "metric": METRIC,
         "value": atom_steps / wall,
@@ -131,11 +176,15 @@ def main():
         "roofline": {
             "kernel": "k_step<1> (fused pair force + velocity Verlet)",
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "traffic_bytes_per_launch": tb,
             "bytes_per_atom_step": bytes_per_atom, "mean_list_entries": mean_nbr,
             "avg_kernel_us": avg_ms * 1e3, "launches": timing["step_launches"],
+            "timing": "HIP events around each step launch over the timing trials",
         },
-        "rebuild_every": timing["rebuild_every"],
+        "rebuild_every": timing["rebuild_every"], "lanes_per_atom": timing["lanes"],
+        "cell_cap": timing["cell_cap"], "list_cap": timing["nbr_cap"],
+        "retried_trials": retried,
     }
     sys_.close()
     if not args.no_cpu_baseline:

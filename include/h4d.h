@@ -96,6 +96,9 @@ typedef struct h4d_params {
     int32_t precision;          /* H4D_PREC_*                                   */
     int32_t capacity;           /* maximum atoms (0: n_atoms + 4096)            */
     int32_t rebuild_every;      /* neighbour-list rebuild interval (0: auto)   */
+    int32_t lanes_per_atom;     /* lanes per atom in list traversals: 4, 8, 16
+                                   (0: chosen from the atom count)              */
+    int32_t reserved0;
     double mass[H4D_MAX_TYPES], charge[H4D_MAX_TYPES];
     double sigma[H4D_MAX_TYPES], eps[H4D_MAX_TYPES];
     double box[3];              /* orthorhombic edges; each >= 2 max cutoff     */
@@ -195,14 +198,27 @@ int32_t h4d_forces_at(h4d_system *sys, const int32_t flying[2], double w,
  */
 typedef struct h4d_timing {
     int64_t step_launches;
+    int64_t retries;       /* trials recomputed with a shorter rebuild interval */
     double step_ms;        /* summed device time of the step kernel            */
     double mean_nbr;       /* mean list entries per atom, current state        */
-    int32_t rebuild_every; /* current list rebuild interval (steps)            */
+    int32_t rebuild_every; /* list rebuild interval (steps)                     */
     int32_t nbr_cap;       /* list capacity per atom                           */
+    int32_t lanes;         /* lanes per atom                                   */
+    int32_t cell_cap;      /* atoms per cell capacity                          */
 } h4d_timing;
 
 int32_t h4d_set_timing(h4d_system *sys, int32_t on);
 int32_t h4d_get_timing(h4d_system *sys, h4d_timing *out);
+
+/*
+ * Stream-copy probe (no handle needed): copies `bytes` bytes between two
+ * device buffers with a plain 16-byte-per-lane copy kernel `reps` times and
+ * returns the mean kernel time in *ms (HIP events).  Used to measure the
+ * achievable HBM bandwidth and to calibrate hardware byte counters against a
+ * kernel whose traffic is known (read `bytes`, write `bytes` per launch).
+ * Allocates and frees its buffers; bytes must be a positive multiple of 16.
+ */
+int32_t h4d_stream_copy(int64_t bytes, int32_t reps, double *ms);
 
 /* Release every resource of the handle. */
 int32_t h4d_destroy(h4d_system *sys);

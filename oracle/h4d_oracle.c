@@ -68,11 +68,16 @@ enum { PURPOSE_SELECT = 1, PURPOSE_MB = 2, PURPOSE_NSTEPS = 3 };
 /* ------------------------------------------------------------------ */
 /* Geometry                                                            */
 /* ------------------------------------------------------------------ */
+/* Periodic wrap into [0, L).  Coordinates are never more than one edge
+ * outside the box, so one shift is exact; the floor form is kept for the
+ * general case. */
 static double wrap1(double x, double L)
 {
+    if (x >= L) x -= L;
+    else if (x < 0.0) x += L;
+    if (x >= 0.0 && x < L) return x;
     double y = x - L * floor(x / L);
-    if (y >= L) y -= L;
-    return y;
+    return (y >= L || y < 0.0) ? 0.0 : y;
 }
 
 static double minimg(double d, double L)

@@ -15,12 +15,15 @@ constexpr int kWave = 64;            // gfx950 wavefront
 // meta word of an atom (packed next to its coordinates): type and flags
 constexpr int kTypeMask = 0xF;
 constexpr int kFlyBit = 0x10;
+constexpr int kFastBit = 0x20;       // moved beyond half the skin since the list build
+constexpr int kFastCap = 256;        // capacity of the fast-atom list
 
 // error bits of the control block
 constexpr unsigned kErrNbr = 0x1u;    // neighbour list capacity exceeded
 constexpr unsigned kErrCell = 0x2u;   // cell capacity exceeded
 constexpr unsigned kErrSkin = 0x4u;   // an atom moved more than skin/2 before a rebuild
 constexpr unsigned kErrCap = 0x8u;    // atom capacity exceeded
+constexpr unsigned kErrFast = 0x10u;  // fast-atom list full
 
 // purposes of the counter-based generator
 constexpr uint64_t kPurposeSelect = 1, kPurposeMB = 2, kPurposeNsteps = 3;
@@ -63,7 +66,9 @@ struct Geo {
     double rc_lj2, rc_c2, rc_max2, rlist2, half_skin2;
     float rc_lj2f, rc_c2f, rc_max2f;
     double alpha, alpha2, cex, Sc, erfc_rc_over_rc, rc_coul;   // damped shifted force
-    float alphaf, alpha2f, cexf, Scf;
+    float alphaf, alpha2f, cexf, Scf, erfc_rc_over_rcf, rc_coulf;
+    float nalpha2_log2e;     // -alpha^2 log2(e): exp(-alpha^2 s^2) = 2^(nalpha2_log2e s^2)
+    float p_alpha;           // 0.3275911 alpha (argument scale of the erfc fit)
     double dt, half_dt, accel, kT, w_max, kappa;
     double volume, lambda3, beta, beta_mu;
     int ncell[3];
@@ -76,7 +81,7 @@ struct Geo {
 // per type-pair coefficients, indexed ti * kMaxTypes + tj
 struct PairCoef {
     double sig2, eps, qqk, lj_shift;     // lj_shift = (s/rc)^12 - (s/rc)^6
-    float sig2f, eps24f, qqkf, pad;
+    float sig2f, eps24f, qqkf, lj_shiftf;
 };
 
 // --------------------------------------------------------------------------
@@ -86,14 +91,19 @@ __device__ __forceinline__ double altitude(double w_max, int move, int k, int nf
     return move > 0 ? w_max * (double)(nf - k) / (double)nf : w_max * (double)k / (double)nf;
 }
 
+// Periodic wrap into [0, L) of a coordinate less than one box edge outside
+// it (atoms move far less than L per step); exact, no division.
 __device__ __forceinline__ double wrap_coord(double x, double L) {
-    double y = x - L * floor(x / L);
-    if (y >= L) y -= L;
-    return y;
+    if (x >= L) x -= L;
+    else if (x < 0.0) x += L;
+    return x;
 }
 
+// Minimum image of a difference of two wrapped coordinates (|d| < L).
 __device__ __forceinline__ double min_image(double d, double L) {
-    return d - L * rint(d / L);
+    if (d > 0.5 * L) d -= L;
+    else if (d < -0.5 * L) d += L;
+    return d;
 }
 
 __device__ __forceinline__ uint32_t to_fixed(double x, double fx_inv) {
@@ -120,23 +130,22 @@ __device__ __forceinline__ float erfc_as(float x, float ex) {
 }
 
 // Radial force over distance, -(du/ds)/s, of one pair at squared 4D
-// distance s2 (FP32).  g screens the Coulomb part.
+// distance s2 (FP32), without branches (both cutoffs by select), with the
+// hardware reciprocal, reciprocal square root and exp2.  g screens the
+// Coulomb part.  s2 must be positive.
 __device__ __forceinline__ float pair_fs_f32(const Geo &G, const PairCoef &c, float s2, float g) {
-    float fs = 0.0f;
-    const float inv = __frcp_rn(s2);
-    if (s2 < G.rc_lj2f) {
-        const float sr2 = c.sig2f * inv;
-        const float sr6 = sr2 * sr2 * sr2;
-        fs += c.eps24f * sr6 * (2.0f * sr6 - 1.0f) * inv;
-    }
-    if (s2 < G.rc_c2f) {
-        const float rs = __frsqrt_rn(s2);
-        const float s = s2 * rs;
-        const float ex = __expf(-G.alpha2f * s2);
-        const float ec = erfc_as(G.alphaf * s, ex);
-        fs += g * c.qqkf * (ec * inv + G.cexf * ex * rs - G.Scf) * rs;
-    }
-    return fs;
+    const float inv = __builtin_amdgcn_rcpf(s2);
+    const float sr2 = c.sig2f * inv;
+    const float sr6 = sr2 * sr2 * sr2;
+    const float flj = c.eps24f * sr6 * (2.0f * sr6 - 1.0f) * inv;
+    const float rs = __builtin_amdgcn_rsqf(s2);
+    const float s = s2 * rs;
+    const float ex = __builtin_amdgcn_exp2f(G.nalpha2_log2e * s2);
+    const float t = __builtin_amdgcn_rcpf(1.0f + G.p_alpha * s);
+    const float poly = t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f +
+                       t * (-1.453152027f + t * 1.061405429f))));
+    const float fc = g * c.qqkf * ((poly * inv + G.cexf * rs) * ex - G.Scf) * rs;
+    return (s2 < G.rc_lj2f ? flj : 0.0f) + (s2 < G.rc_c2f ? fc : 0.0f);
 }
 
 // Same in FP64 with the library erfc.
@@ -154,6 +163,23 @@ __device__ __forceinline__ double pair_fs_f64(const Geo &G, const PairCoef &c, d
         fs += g * c.qqk * (erfc(G.alpha * s) * inv + G.cex * ex / s - G.Sc) / s;
     }
     return fs;
+}
+
+// FP32 pair energy (LJ plus screened Coulomb), for accumulation in FP64.
+__device__ __forceinline__ float pair_u_f32(const Geo &G, const PairCoef &c, float s2, float g) {
+    float u = 0.0f;
+    if (s2 < G.rc_lj2f) {
+        const float sr2 = c.sig2f * __frcp_rn(s2);
+        const float sr6 = sr2 * sr2 * sr2;
+        u += c.eps24f * (1.0f / 6.0f) * (sr6 * sr6 - sr6 - c.lj_shiftf);
+    }
+    if (s2 < G.rc_c2f) {
+        const float rs = __frsqrt_rn(s2);
+        const float s = s2 * rs;
+        const float ec = erfc_as(G.alphaf * s, __expf(-G.alpha2f * s2));
+        u += g * c.qqkf * (ec * rs - G.erfc_rc_over_rcf + G.Scf * (s - G.rc_coulf));
+    }
+    return u;
 }
 
 // FP64 pair energies (LJ and Coulomb parts) and -(du/ds)/s.

@@ -1,37 +1,46 @@
 // h4d_kernels.hpp -- HIP kernels of one H4D exchange trial on gfx950.
 //
-// Layout in HBM (capacity cap atoms, structure of arrays):
-//   pos[2]   double4 ping-pong buffers: x, y, z (FP64, wrapped) + meta word
-//   fx[2]    uint4 ping-pong buffers: 32-bit fixed-point x, y, z + meta word
-//            (FP32 mode: the pair pass gathers these 16-byte records)
-//   vel      double4
-//   tag/type/mol  per atom; array order = ascending tag order
-//   nbr      column-major ELL Verlet list nbr[q * cap + i], counts nnbr[i]
-//   cells    cell_cnt[c], cell_atoms[c * cell_cap + slot] (sorted per cell)
-// Every kernel reads the atom counts from the control block, so a trial's
-// launches never wait on the host.
+// Two copies of the configuration live in HBM:
+//   canonical  cpos/ctag/ctype/cmol in ascending tag order: the state
+//              between trials and the rollback snapshot during a trial;
+//   working    the trial's atoms sorted by cell (spatial order) at its start:
+//              pos[2] double4 (FP64 x, y, z + meta word), fx[2] uint4 (32-bit
+//              fixed-point x, y, z + meta word), vel[2] double4, perm (working
+//              -> canonical index), wmol.  pos/fx/vel ping-pong every step.
+// Verlet list: full list, blocked for wavefront-contiguous reads: atom w's
+//   entry q sits at nbr[((w / A) * KQ + q / L) * 64 + (w % A) * L + q % L],
+//   with L lanes per atom (4, 8 or 16, chosen per system), A = 64 / L atoms
+//   per wavefront, KQ = cap_nbr / L.
+// Every kernel reads the atom counts from the control block, so the launches
+// of a trial never wait on the host.
 #pragma once
 #include "h4d_device.hpp"
 
 namespace h4d {
+
+constexpr int kMaxLanes = 16;             // largest lanes-per-atom choice
 
 struct Ctl {
     int n;            // atoms of the physical state
     int n_all;        // atoms including the two ghosts of an insertion
     int nsalt;
     int move;         // +1 insertion, -1 deletion, 0 nothing to do
-    int ic, ia;       // indices of the flying cation / anion
+    int ic, ia;       // canonical indices of the flying cation / anion
+    int wic, wia;     // their working indices
     int nf;           // NEMD steps of this trial
     int accepted;
     unsigned err;     // kErr* bits of this trial
     unsigned retry;   // 1: the trial must be recomputed
     int max_nbr, max_cell;
+    int nfast[3];     // fast-atom list lengths (list k % 3 is read by step k)
+    int max_fast;     // largest fast list of the trial
     long long next_tag;
     long long trial;
     double u[8];
     double U0, K0, U1, K1;
     double Ulj, Uc, vir;
-    double Wf[2], Esw[2], Esw_pair;
+    double Wf[2];
+    double Ufly0, Ufly1;   // U_fly(w_max) at the start / end state (FP64)
 };
 
 // Trial record, same layout as h4d_trial of the C ABI.
@@ -46,43 +55,79 @@ struct TrialRec {
 struct KArgs {
     Geo G;
     const PairCoef *coef;
+    const double *mass;       // per type
+    // canonical state
+    double4 *cpos;
+    long long *ctag;
+    int *ctype, *cmol;
+    // working state
     double4 *pos[2];
     uint4 *fx[2];
-    double4 *vel;
-    double4 *pos0;       // snapshot of the trial's starting positions
-    double4 *posb;       // positions at the last list build
-    double4 *force;      // test hook output / rigid-water scratch
-    long long *tag;
-    int *type;
-    int *mol;
-    double4 *tpos;       // compaction scratch
+    double4 *vel[2];
+    int *perm, *wmol;
+    uint4 *posb;              // fixed-point positions at the last list build
+    double4 *force;           // test hook output
+    // compaction scratch (canonical order)
+    double4 *tpos;
     long long *ttag;
     int *ttype, *tmol;
+    // lists
     int *nbr, *nnbr;
-    int *cell_cnt, *cell_atoms;
-    double *partial;     // per-block FP64 partial sums, 4 per block
+    int *cell_cnt[2], *cell_atoms[2], *cell_off;
+    int *fast;                // 3 lists of kFastCap working indices
+    double *partial;          // per-block FP64 partial sums, 4 per block
     Ctl *ctl;
     TrialRec *rec;
-    const double *mass;  // per type
     int cap, nbr_cap, cell_cap, ncell_total;
+    int lanes, lanes_log2;    // lanes per atom in list traversals (4, 8 or 16)
     uint64_t seed, stream;
     int n_steps, n_steps_min, n_steps_max;
     int cation_type, anion_type;
 };
+
+// slot of entry q of atom w in the blocked list (L = a.lanes, A = 64 / L)
+__device__ __forceinline__ size_t nbr_slot(const KArgs &a, int w, int q) {
+    const int ll = a.lanes_log2, la = 6 - ll;
+    return ((size_t)(w >> la) * (size_t)(a.nbr_cap >> ll) + (size_t)(q >> ll)) * kWave +
+           (size_t)((w & ((1 << la) - 1)) << ll) + (size_t)(q & ((1 << ll) - 1));
+}
 
 // Coefficients are staged in LDS once per block.
 struct CoefLds {
     PairCoef c[kMaxTypes * kMaxTypes];
 };
 
-__device__ __forceinline__ void load_coef(CoefLds &s, const PairCoef *g, int nt) {
+__device__ __forceinline__ void load_coef(CoefLds &s, const PairCoef *g) {
     for (int q = threadIdx.x; q < kMaxTypes * kMaxTypes; q += blockDim.x) s.c[q] = g[q];
-    (void)nt;
+}
+
+__device__ __forceinline__ uint4 fixed_of(const Geo &G, double x, double y, double z, int meta) {
+    return make_uint4(to_fixed(x, G.fx_inv[0]), to_fixed(y, G.fx_inv[1]), to_fixed(z, G.fx_inv[2]),
+                      (unsigned)meta);
+}
+
+__device__ __forceinline__ int cell_coord(double x, double L, int nc) {
+    int k = (int)(x / L * (double)nc);
+    return k < 0 ? 0 : (k >= nc ? nc - 1 : k);
+}
+
+__device__ __forceinline__ int cell_of(const Geo &G, const double4 &p) {
+    const int cx = cell_coord(p.x, G.L[0], G.ncell[0]);
+    const int cy = cell_coord(p.y, G.L[1], G.ncell[1]);
+    const int cz = cell_coord(p.z, G.L[2], G.ncell[2]);
+    return (cz * G.ncell[1] + cy) * G.ncell[0] + cx;
+}
+
+__device__ __forceinline__ void bin_atom(const KArgs &a, int cb, int w, const double4 &p) {
+    const int cc = a.G.use_cells ? cell_of(a.G, p) : 0;
+    const int slot = atomicAdd(&a.cell_cnt[cb][cc], 1);
+    if (slot < a.cell_cap) a.cell_atoms[cb][(size_t)cc * a.cell_cap + slot] = w;
+    else { atomicOr(&a.ctl->err, kErrCell); atomicMax(&a.ctl->max_cell, slot + 1); }
 }
 
 // ==========================================================================
-// Proposal: move choice, ghost pair for an insertion, rank selection for a
-// deletion (Eqs. 3-4; uniform 1/2 between the two moves).
+// Proposal on the canonical state: move choice, ghost pair of an insertion,
+// rank selection of a deletion (Eqs. 3-4; insertion or deletion with 1/2).
 // ==========================================================================
 __global__ __launch_bounds__(kBlock) void k_propose(KArgs a, int force_move) {
     Ctl *c = a.ctl;
@@ -104,8 +149,10 @@ __global__ __launch_bounds__(kBlock) void k_propose(KArgs a, int force_move) {
         if (move < 0 && c->nsalt == 0) move = 0;
         c->move = move;
         c->err = 0; c->retry = 0; c->accepted = 0;
-        c->Wf[0] = c->Wf[1] = 0.0; c->Esw[0] = c->Esw[1] = 0.0; c->Esw_pair = 0.0;
-        c->ic = c->ia = -1;
+        c->Wf[0] = c->Wf[1] = 0.0; c->Ufly0 = c->Ufly1 = 0.0;
+        c->ic = c->ia = c->wic = c->wia = -1;
+        c->nfast[0] = c->nfast[1] = c->nfast[2] = 0;
+        c->max_fast = 0;
         c->n_all = c->n;
         s_move = move; s_n = c->n;
         s_kc = (int)floor(c->u[1] * (double)c->nsalt);
@@ -118,17 +165,15 @@ __global__ __launch_bounds__(kBlock) void k_propose(KArgs a, int force_move) {
             } else {
                 const int ic = n, ia = n + 1;
                 const int tcat = a.cation_type, tan = a.anion_type;
-                const double xc[3] = {wrap_coord(a.G.L[0] * c->u[1], a.G.L[0]),
-                                      wrap_coord(a.G.L[1] * c->u[2], a.G.L[1]),
-                                      wrap_coord(a.G.L[2] * c->u[3], a.G.L[2])};
-                const double xa[3] = {wrap_coord(a.G.L[0] * c->u[4], a.G.L[0]),
-                                      wrap_coord(a.G.L[1] * c->u[5], a.G.L[1]),
-                                      wrap_coord(a.G.L[2] * c->u[6], a.G.L[2])};
-                a.pos[0][ic] = with_meta(xc[0], xc[1], xc[2], tcat | kFlyBit);
-                a.pos[0][ia] = with_meta(xa[0], xa[1], xa[2], tan | kFlyBit);
-                a.tag[ic] = c->next_tag; a.tag[ia] = c->next_tag + 1;
-                a.type[ic] = tcat; a.type[ia] = tan;
-                a.mol[ic] = -1; a.mol[ia] = -1;
+                a.cpos[ic] = with_meta(wrap_coord(a.G.L[0] * c->u[1], a.G.L[0]),
+                                       wrap_coord(a.G.L[1] * c->u[2], a.G.L[1]),
+                                       wrap_coord(a.G.L[2] * c->u[3], a.G.L[2]), tcat | kFlyBit);
+                a.cpos[ia] = with_meta(wrap_coord(a.G.L[0] * c->u[4], a.G.L[0]),
+                                       wrap_coord(a.G.L[1] * c->u[5], a.G.L[1]),
+                                       wrap_coord(a.G.L[2] * c->u[6], a.G.L[2]), tan | kFlyBit);
+                a.ctag[ic] = c->next_tag; a.ctag[ia] = c->next_tag + 1;
+                a.ctype[ic] = tcat; a.ctype[ia] = tan;
+                a.cmol[ic] = -1; a.cmol[ia] = -1;
                 c->ic = ic; c->ia = ia; c->n_all = n + 2;
             }
         }
@@ -136,13 +181,13 @@ __global__ __launch_bounds__(kBlock) void k_propose(KArgs a, int force_move) {
     __syncthreads();
     if (s_move >= 0) return;
     // deletion: the atom of each species with the drawn rank in tag order;
-    // array order is tag order, so count species members per chunk and scan
+    // canonical order is tag order, so count species members per chunk and scan
     const int n = s_n;
     const int chunk = (n + kBlock - 1) / kBlock;
     const int lo = tid * chunk, hi = min(n, lo + chunk);
     int nc = 0, na = 0;
     for (int i = lo; i < hi; ++i) {
-        const int ty = a.type[i];
+        const int ty = a.ctype[i];
         nc += (ty == a.cation_type);
         na += (ty == a.anion_type);
     }
@@ -157,16 +202,16 @@ __global__ __launch_bounds__(kBlock) void k_propose(KArgs a, int force_move) {
         }
     }
     __syncthreads();
-    int pc = s_cnt[0][tid], pa = s_cnt[1][tid];
+    const int pc = s_cnt[0][tid], pa = s_cnt[1][tid];
     if (s_kc >= pc && s_kc < pc + nc) {
         int r = pc;
         for (int i = lo; i < hi; ++i)
-            if (a.type[i] == a.cation_type) { if (r == s_kc) { s_ic = i; break; } ++r; }
+            if (a.ctype[i] == a.cation_type) { if (r == s_kc) { s_ic = i; break; } ++r; }
     }
     if (s_ka >= pa && s_ka < pa + na) {
         int r = pa;
         for (int i = lo; i < hi; ++i)
-            if (a.type[i] == a.anion_type) { if (r == s_ka) { s_ia = i; break; } ++r; }
+            if (a.ctype[i] == a.anion_type) { if (r == s_ka) { s_ia = i; break; } ++r; }
     }
     __syncthreads();
     if (tid == 0) {
@@ -176,73 +221,34 @@ __global__ __launch_bounds__(kBlock) void k_propose(KArgs a, int force_move) {
             return;
         }
         c->ic = ic; c->ia = ia;
-        double4 p = a.pos[0][ic];
-        a.pos[0][ic] = with_meta(p.x, p.y, p.z, meta_of(p) | kFlyBit);
-        p = a.pos[0][ia];
-        a.pos[0][ia] = with_meta(p.x, p.y, p.z, meta_of(p) | kFlyBit);
+        double4 p = a.cpos[ic];
+        a.cpos[ic] = with_meta(p.x, p.y, p.z, meta_of(p) | kFlyBit);
+        p = a.cpos[ia];
+        a.cpos[ia] = with_meta(p.x, p.y, p.z, meta_of(p) | kFlyBit);
     }
 }
 
 // ==========================================================================
-// Maxwell-Boltzmann momenta keyed by tag (Box-Muller on Philox uniforms);
-// also refreshes the fixed-point coordinates of buffer 0.
+// Cells.  Binning uses atomics; each cell's members are then sorted by index
+// so that every list is built in a fixed order (bitwise reproducible).
 // ==========================================================================
-__global__ __launch_bounds__(kBlock) void k_mb(KArgs a) {
-    const Ctl *c = a.ctl;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= c->n_all) return;
-    const uint64_t t = (uint64_t)c->trial;
-    const u64x4 r = philox(t, kPurposeMB, (uint64_t)a.tag[i], 0, a.seed, a.stream);
-    const double u0 = unit_open(r.v[0]), u1 = unit_open(r.v[1]);
-    const double u2 = unit_open(r.v[2]), u3 = unit_open(r.v[3]);
-    const double r01 = sqrt(-2.0 * log(u0)), r23 = sqrt(-2.0 * log(u2));
-    const double twopi = 6.283185307179586476925286766559;
-    const double4 p = a.pos[0][i];
-    const int ty = meta_of(p) & kTypeMask;
-    const double sd = sqrt(a.G.accel * a.G.kT / a.mass[ty]);
-    a.vel[i] = make_double4(sd * (r01 * cos(twopi * u1)), sd * (r01 * sin(twopi * u1)),
-                            sd * (r23 * cos(twopi * u3)), 0.0);
-    a.fx[0][i] = make_uint4(to_fixed(p.x, a.G.fx_inv[0]), to_fixed(p.y, a.G.fx_inv[1]),
-                            to_fixed(p.z, a.G.fx_inv[2]), (unsigned)meta_of(p));
-}
-
-// ==========================================================================
-// Cell and Verlet lists.
-// ==========================================================================
-__device__ __forceinline__ int cell_coord(double x, double L, int nc) {
-    int k = (int)(x / L * (double)nc);
-    return k < 0 ? 0 : (k >= nc ? nc - 1 : k);
-}
-
-__global__ void k_cell_clear(KArgs a, int k_step) {
-    if (k_step > a.ctl->nf) return;
+__global__ void k_cell_clear(KArgs a, int cb) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < a.ncell_total) a.cell_cnt[q] = 0;
+    if (q < a.ncell_total) a.cell_cnt[cb][q] = 0;
 }
 
-__global__ __launch_bounds__(kBlock) void k_cell_bin(KArgs a, int b, int k_step) {
-    const Ctl *c = a.ctl;
-    if (k_step > c->nf) return;
+// bin the canonical atoms (trial start)
+__global__ __launch_bounds__(kBlock) void k_bin_canonical(KArgs a, int cb) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= c->n_all) return;
-    const double4 p = a.pos[b][i];
-    const int cx = cell_coord(p.x, a.G.L[0], a.G.ncell[0]);
-    const int cy = cell_coord(p.y, a.G.L[1], a.G.ncell[1]);
-    const int cz = cell_coord(p.z, a.G.L[2], a.G.ncell[2]);
-    const int cc = (cz * a.G.ncell[1] + cy) * a.G.ncell[0] + cx;
-    const int slot = atomicAdd(&a.cell_cnt[cc], 1);
-    if (slot < a.cell_cap) a.cell_atoms[(size_t)cc * a.cell_cap + slot] = i;
-    else { atomicOr(&a.ctl->err, kErrCell); atomicMax(&a.ctl->max_cell, slot + 1); }
+    if (i >= a.ctl->n_all) return;
+    bin_atom(a, cb, i, a.cpos[i]);
 }
 
-// Sort each cell's atom indices ascending (rank sort in LDS), so the list
-// order does not depend on the order of the binning atomics.
-__global__ __launch_bounds__(kWave) void k_cell_sort(KArgs a, int k_step) {
-    if (k_step > a.ctl->nf) return;
+__global__ __launch_bounds__(kWave) void k_cell_sort(KArgs a, int cb) {
     extern __shared__ int buf[];
     const int cc = blockIdx.x;
-    const int cnt = min(a.cell_cnt[cc], a.cell_cap);
-    int *row = a.cell_atoms + (size_t)cc * a.cell_cap;
+    const int cnt = min(a.cell_cnt[cb][cc], a.cell_cap);
+    int *row = a.cell_atoms[cb] + (size_t)cc * a.cell_cap;
     for (int q = threadIdx.x; q < cnt; q += kWave) buf[q] = row[q];
     __syncthreads();
     for (int q = threadIdx.x; q < cnt; q += kWave) {
@@ -253,94 +259,359 @@ __global__ __launch_bounds__(kWave) void k_cell_sort(KArgs a, int k_step) {
     }
 }
 
-__device__ __forceinline__ void list_try(const KArgs &a, int i, int j, int mi, const double4 &pi,
-                                         const double4 *P, int &cnt) {
-    if (j == i) return;
-    if (mi >= 0 && a.mol[j] == mi) return;
-    const double4 pj = P[j];
-    const double dx = min_image(pi.x - pj.x, a.G.L[0]);
-    const double dy = min_image(pi.y - pj.y, a.G.L[1]);
-    const double dz = min_image(pi.z - pj.z, a.G.L[2]);
-    if (dx * dx + dy * dy + dz * dz < a.G.rlist2) {
-        if (cnt < a.nbr_cap) a.nbr[(size_t)cnt * a.cap + i] = j;
-        ++cnt;
+// exclusive scan of the cell counts (one block)
+__global__ __launch_bounds__(1024) void k_cell_scan(KArgs a, int cb) {
+    __shared__ int part[1024];
+    const int nc = a.ncell_total;
+    const int per = (nc + 1023) / 1024;
+    const int lo = threadIdx.x * per, hi = min(nc, lo + per);
+    int s = 0;
+    for (int q = lo; q < hi; ++q) s += min(a.cell_cnt[cb][q], a.cell_cap);
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int run = threadIdx.x ? part[threadIdx.x - 1] : 0;
+    for (int q = lo; q < hi; ++q) {
+        a.cell_off[q] = run;
+        run += min(a.cell_cnt[cb][q], a.cell_cap);
+    }
+    if (threadIdx.x == 1023) a.cell_off[nc] = part[1023];
+}
+
+// Trial start: gather the canonical atoms into cell order (working buffer 0),
+// draw the Maxwell-Boltzmann momenta (keyed by tag, Box-Muller on Philox
+// uniforms), and rewrite the cell rows with working indices.
+__global__ __launch_bounds__(kWave) void k_gather_in(KArgs a, int cb) {
+    Ctl *c = a.ctl;
+    const int cc = blockIdx.x;
+    const int cnt = min(a.cell_cnt[cb][cc], a.cell_cap);
+    const int off = a.cell_off[cc];
+    int *row = a.cell_atoms[cb] + (size_t)cc * a.cell_cap;
+    const uint64_t t = (uint64_t)c->trial;
+    const double twopi = 6.283185307179586476925286766559;
+    for (int s = threadIdx.x; s < cnt; s += kWave) {
+        const int src = row[s];
+        const int w = off + s;
+        const double4 p = a.cpos[src];
+        const int meta = meta_of(p);
+        const int ty = meta & kTypeMask;
+        a.pos[0][w] = p;
+        const uint4 q = fixed_of(a.G, p.x, p.y, p.z, meta);
+        a.posb[w] = q;
+        a.fx[0][w] = q;
+        a.perm[w] = src;
+        a.wmol[w] = a.cmol[src];
+        const u64x4 r = philox(t, kPurposeMB, (uint64_t)a.ctag[src], 0, a.seed, a.stream);
+        const double u0 = unit_open(r.v[0]), u1 = unit_open(r.v[1]);
+        const double u2 = unit_open(r.v[2]), u3 = unit_open(r.v[3]);
+        const double r01 = sqrt(-2.0 * log(u0)), r23 = sqrt(-2.0 * log(u2));
+        const double sd = sqrt(a.G.accel * a.G.kT / a.mass[ty]);
+        a.vel[0][w] = make_double4(sd * (r01 * cos(twopi * u1)), sd * (r01 * sin(twopi * u1)),
+                                   sd * (r23 * cos(twopi * u3)), 0.0);
+        if (src == c->ic) c->wic = w;
+        if (src == c->ia) c->wia = w;
+        row[s] = w;
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_list(KArgs a, int b, int k_step) {
+// After a list build every atom is within the skin again: clear its fast flag.
+__device__ __forceinline__ void unflag_fast(const KArgs &a, int b, int w, unsigned meta) {
+    if (meta & kFastBit) {
+        const unsigned m = meta & ~(unsigned)kFastBit;
+        a.fx[b][w].w = m;
+        double4 p = a.pos[b][w];
+        a.pos[b][w] = with_meta(p.x, p.y, p.z, (int)m);
+    }
+}
+
+__device__ __forceinline__ void reset_fast_lists(const KArgs &a) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->nfast[0] = a.ctl->nfast[1] = a.ctl->nfast[2] = 0;
+}
+
+// ==========================================================================
+// Verlet list (full, within r_list = max cutoff + skin), all-pairs form for
+// boxes with fewer than 3 cells per edge: L lanes per atom test consecutive
+// candidates; a ballot keeps the sequential order.
+// ==========================================================================
+__device__ __forceinline__ bool list_accepts(const KArgs &a, const uint4 &qi, int mi, int wi, int j,
+                                             const uint4 &qj, int mj, float rl2) {
+    if (j == wi) return false;
+    if (mi >= 0 && mj == mi) return false;
+    const float dx = (float)(int)(qi.x - qj.x) * a.G.fx_scale[0];
+    const float dy = (float)(int)(qi.y - qj.y) * a.G.fx_scale[1];
+    const float dz = (float)(int)(qi.z - qj.z) * a.G.fx_scale[2];
+    return dx * dx + dy * dy + dz * dz < rl2;
+}
+
+__global__ __launch_bounds__(kBlock) void k_list_allpairs(KArgs a, int b, int cb) {
     const Ctl *c = a.ctl;
-    if (k_step > c->nf) return;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
     const int n_all = c->n_all;
-    if (i >= n_all) return;
-    const double4 *P = a.pos[b];
-    const double4 pi = P[i];
-    const int mi = a.mol[i];
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.cell_cnt[cb ^ 1][0] = 0;
+    const int L = a.lanes;
+    const int lane = threadIdx.x % kWave;
+    const int s = lane & (L - 1);
+    const int w = (blockIdx.x * kBlock + threadIdx.x) >> a.lanes_log2;
+    if (w >= n_all) return;
+    const uint4 qi = a.fx[b][w];
+    const int mi = a.wmol[w];
+    const float rl2 = (float)a.G.rlist2 * 1.00001f;     // superset margin for FP32 distances
+    const int gshift = lane - s;
+    const unsigned long long gmask = (L == 64) ? ~0ull : ((1ull << L) - 1ull);
+    const unsigned long long below = (1ull << s) - 1ull;
     int cnt = 0;
-    if (!a.G.use_cells) {
-        for (int j = 0; j < n_all; ++j) list_try(a, i, j, mi, pi, P, cnt);
-    } else {
-        const int nx = a.G.ncell[0], ny = a.G.ncell[1], nz = a.G.ncell[2];
-        const int cx = cell_coord(pi.x, a.G.L[0], nx);
-        const int cy = cell_coord(pi.y, a.G.L[1], ny);
-        const int cz = cell_coord(pi.z, a.G.L[2], nz);
-        for (int dz = -1; dz <= 1; ++dz)
-            for (int dy = -1; dy <= 1; ++dy)
-                for (int dx = -1; dx <= 1; ++dx) {
-                    const int ax = (cx + dx + nx) % nx, ay = (cy + dy + ny) % ny, az = (cz + dz + nz) % nz;
-                    const int cc = (az * ny + ay) * nx + ax;
-                    const int m = min(a.cell_cnt[cc], a.cell_cap);
-                    const int *row = a.cell_atoms + (size_t)cc * a.cell_cap;
-                    for (int q = 0; q < m; ++q) list_try(a, i, row[q], mi, pi, P, cnt);
-                }
+    for (int base = 0; base < n_all; base += L) {
+        const int j = base + s;
+        bool acc = false;
+        if (j < n_all) acc = list_accepts(a, qi, mi, w, j, a.fx[b][j], a.wmol[j], rl2);
+        const unsigned long long m = (__ballot(acc) >> gshift) & gmask;
+        if (acc) {
+            const int q = cnt + __popcll(m & below);
+            if (q < a.nbr_cap) a.nbr[nbr_slot(a, w, q)] = j;
+        }
+        cnt += __popcll(m);
     }
-    a.nnbr[i] = min(cnt, a.nbr_cap);
-    a.posb[i] = pi;
-    if (cnt > a.nbr_cap) { atomicOr(&a.ctl->err, kErrNbr); atomicMax(&a.ctl->max_nbr, cnt); }
+    if (s == 0) {
+        a.nnbr[w] = min(cnt, a.nbr_cap);
+        a.posb[w] = qi;
+        unflag_fast(a, b, w, qi.w);
+        if (cnt > a.nbr_cap) { atomicOr(&a.ctl->err, kErrNbr); atomicMax(&a.ctl->max_nbr, cnt); }
+    }
+    reset_fast_lists(a);
+}
+
+// Cell form: one block per centre cell.  The atoms of all 27 stencil cells
+// are staged in LDS (fixed-point coordinates + working index) in stencil
+// order; each wavefront takes a share of the centre atoms and tests 64
+// candidates per ballot, appending in stencil order.  Dynamic LDS:
+// 27 * cell_cap * 16 bytes.  Also records the build positions and clears this
+// cell's count in the other buffer.
+__global__ __launch_bounds__(kBlock) void k_list_cells(KArgs a, int b, int cb) {
+    extern __shared__ uint4 cand[];
+    __shared__ int cidx[27], cnt27[27], off[28];
+    const int cap = a.cell_cap;
+    const int cc = blockIdx.x;
+    const int nx = a.G.ncell[0], ny = a.G.ncell[1], nz = a.G.ncell[2];
+    if (threadIdx.x < 27) {
+        const int t = threadIdx.x;
+        const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+        const int cx = cc % nx, cy = (cc / nx) % ny, cz = cc / (nx * ny);
+        const int c2 = (((cz + dz + nz) % nz) * ny + (cy + dy + ny) % ny) * nx + (cx + dx + nx) % nx;
+        cidx[t] = c2;
+        cnt27[t] = min(a.cell_cnt[cb][c2], cap);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int t = 0; t < 27; ++t) { off[t] = run; run += cnt27[t]; }
+        off[27] = run;
+    }
+    __syncthreads();
+    const int total = off[27];
+    // one pass of loads over all stencil candidates
+    for (int u = threadIdx.x; u < total; u += kBlock) {
+        int t = 0;
+        while (off[t + 1] <= u) ++t;
+        const int j = a.cell_atoms[cb][(size_t)cidx[t] * cap + (u - off[t])];
+        const uint4 q = a.fx[b][j];
+        cand[u] = make_uint4(q.x, q.y, q.z, (unsigned)j);
+    }
+    __syncthreads();
+    // the centre atoms' meta words (fast flags are cleared below)
+    __shared__ unsigned cmeta[1024];
+    for (int u = threadIdx.x; u < off[14] - off[13] && u < 1024; u += kBlock)
+        cmeta[u] = a.fx[b][cand[off[13] + u].w].w;
+    __syncthreads();
+    const int c0 = off[13], mc = off[14] - off[13];      // the centre cell itself
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const float rl2 = (float)a.G.rlist2 * 1.00001f;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const bool molecules = a.G.water != 0;
+    for (int t = wave; t < mc; t += kBlock / kWave) {
+        const uint4 qi = cand[c0 + t];
+        const int wi = (int)qi.w;
+        const int mi = molecules ? a.wmol[wi] : -1;
+        int cnt = 0;
+        for (int base = 0; base < total; base += kWave) {
+            const int u = base + lane;
+            bool acc = false;
+            int j = 0;
+            if (u < total) {
+                const uint4 qj = cand[u];
+                j = (int)qj.w;
+                if (j != wi) {
+                    const float dx = (float)(int)(qi.x - qj.x) * a.G.fx_scale[0];
+                    const float dy = (float)(int)(qi.y - qj.y) * a.G.fx_scale[1];
+                    const float dz = (float)(int)(qi.z - qj.z) * a.G.fx_scale[2];
+                    acc = dx * dx + dy * dy + dz * dz < rl2;
+                    if (acc && mi >= 0 && a.wmol[j] == mi) acc = false;
+                }
+            }
+            const unsigned long long m = __ballot(acc);
+            if (acc) {
+                const int q = cnt + __popcll(m & below);
+                if (q < a.nbr_cap) a.nbr[nbr_slot(a, wi, q)] = j;
+            }
+            cnt += __popcll(m);
+        }
+        if (lane == 0) {
+            a.nnbr[wi] = min(cnt, a.nbr_cap);
+            a.posb[wi] = qi;
+            if (t < 1024) unflag_fast(a, b, wi, cmeta[t]);
+            if (cnt > a.nbr_cap) { atomicOr(&a.ctl->err, kErrNbr); atomicMax(&a.ctl->max_nbr, cnt); }
+        }
+    }
+    if (threadIdx.x == 0) a.cell_cnt[cb ^ 1][cc] = 0;
+    reset_fast_lists(a);
+}
+
+// Cell form for cells too large to stage in LDS: L lanes per atom walk the
+// 27 stencil cells directly from global memory.
+__global__ __launch_bounds__(kBlock) void k_list_lanes(KArgs a, int b, int cb) {
+    const Ctl *c = a.ctl;
+    const int n_all = c->n_all;
+    for (int q = blockIdx.x * kBlock + threadIdx.x; q < a.ncell_total; q += gridDim.x * kBlock)
+        a.cell_cnt[cb ^ 1][q] = 0;
+    const int L = a.lanes;
+    const int lane = threadIdx.x % kWave;
+    const int s = lane & (L - 1);
+    const int w = (blockIdx.x * kBlock + threadIdx.x) >> a.lanes_log2;
+    if (w >= n_all) return;
+    const uint4 qi = a.fx[b][w];
+    const int mi = a.wmol[w];
+    const float rl2 = (float)a.G.rlist2 * 1.00001f;
+    const int gshift = lane - s;
+    const unsigned long long gmask = (1ull << L) - 1ull;
+    const unsigned long long below = (1ull << s) - 1ull;
+    const int nx = a.G.ncell[0], ny = a.G.ncell[1], nz = a.G.ncell[2];
+    const double4 pi = a.pos[b][w];
+    const int cx = cell_coord(pi.x, a.G.L[0], nx);
+    const int cy = cell_coord(pi.y, a.G.L[1], ny);
+    const int cz = cell_coord(pi.z, a.G.L[2], nz);
+    int cnt = 0;
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int c2 = (((cz + dz + nz) % nz) * ny + (cy + dy + ny) % ny) * nx + (cx + dx + nx) % nx;
+                const int m = min(a.cell_cnt[cb][c2], a.cell_cap);
+                const int *row = a.cell_atoms[cb] + (size_t)c2 * a.cell_cap;
+                for (int base = 0; base < m; base += L) {
+                    const int u = base + s;
+                    bool acc = false;
+                    int j = 0;
+                    if (u < m) {
+                        j = row[u];
+                        acc = list_accepts(a, qi, mi, w, j, a.fx[b][j], a.wmol[j], rl2);
+                    }
+                    const unsigned long long mm = (__ballot(acc) >> gshift) & gmask;
+                    if (acc) {
+                        const int q = cnt + __popcll(mm & below);
+                        if (q < a.nbr_cap) a.nbr[nbr_slot(a, w, q)] = j;
+                    }
+                    cnt += __popcll(mm);
+                }
+            }
+    if (s == 0) {
+        a.nnbr[w] = min(cnt, a.nbr_cap);
+        a.posb[w] = qi;
+        unflag_fast(a, b, w, qi.w);
+        if (cnt > a.nbr_cap) { atomicOr(&a.ctl->err, kErrNbr); atomicMax(&a.ctl->max_nbr, cnt); }
+    }
+    reset_fast_lists(a);
 }
 
 // ==========================================================================
-// Force on one non-flying atom from its list, at altitude w (flyers at w).
+// Force on one atom at altitude w (flyers at w), by the L lanes of its group,
+// reduced over the group in a fixed order.  An atom that has moved beyond
+// half the skin since the list build is "fast": pairs with fast atoms come
+// from the fast list instead of the Verlet list, and a fast atom's own
+// partners come from the 27 cells of the last build (cell edge >= r_c +
+// skin covers every partner within r_c).  Every pair is counted once.
 // ==========================================================================
-template <int PREC>
-__device__ __forceinline__ void lane_force(const KArgs &a, const CoefLds &cf, int b, int i,
-                                           const double4 &pi, int ti, double w, double gscr,
-                                           double &fx, double &fy, double &fz) {
-    const int nn = a.nnbr[i];
-    const int *nl = a.nbr + i;
-    const size_t stride = (size_t)a.cap;
+template <int PREC, int L>
+__device__ __forceinline__ void group_force(const KArgs &a, const CoefLds &cf, int b, int cl, int w, int s,
+                                            const double4 &pi, int mi, double wv, double gscr, const int *flist,
+                                            int nfast, double &fx, double &fy, double &fz) {
+    constexpr int A = kWave / L;
+    const int ti = mi & kTypeMask;
+    const bool own_fast = (mi & kFastBit) != 0;
     const PairCoef *crow = cf.c + ti * kMaxTypes;
+    const int nx = a.G.ncell[0], ny = a.G.ncell[1], nz = a.G.ncell[2];
     if (PREC == 1) {
         const uint4 *F = a.fx[b];
-        const uint4 qi = F[i];
-        const float sx = a.G.fx_scale[0], sy = a.G.fx_scale[1], sz = a.G.fx_scale[2];
-        const float w2 = (float)(w * w), g = (float)gscr;
+        const uint4 qi = F[w];
+        const float w2 = (float)(wv * wv), g = (float)gscr;
         float ax = 0.f, ay = 0.f, az = 0.f;
-#pragma unroll 4
-        for (int q = 0; q < nn; ++q) {
-            const int j = nl[q * stride];
-            const uint4 qj = F[j];
-            const float dx = (float)(int)(qi.x - qj.x) * sx;
-            const float dy = (float)(int)(qi.y - qj.y) * sy;
-            const float dz = (float)(int)(qi.z - qj.z) * sz;
+        auto pair = [&](const uint4 &qj, bool valid) {
+            const float dx = (float)(int)(qi.x - qj.x) * a.G.fx_scale[0];
+            const float dy = (float)(int)(qi.y - qj.y) * a.G.fx_scale[1];
+            const float dz = (float)(int)(qi.z - qj.z) * a.G.fx_scale[2];
             const int mj = (int)qj.w;
             const bool fj = (mj & kFlyBit) != 0;
             const float r2 = dx * dx + dy * dy + dz * dz;
             const float s2 = fj ? r2 + w2 : r2;
-            if (s2 < a.G.rc_max2f) {
-                const float fs = pair_fs_f32(a.G, crow[mj & kTypeMask], s2, fj ? g : 1.0f);
-                ax += fs * dx; ay += fs * dy; az += fs * dz;
+            const bool ok = valid && s2 < a.G.rc_max2f;
+            const float fs = pair_fs_f32(a.G, crow[mj & kTypeMask], ok ? s2 : a.G.rc_max2f, fj ? g : 1.0f);
+            const float f = ok ? fs : 0.0f;
+            ax += f * dx; ay += f * dy; az += f * dz;
+        };
+        if (!own_fast) {
+            const int nn = a.nnbr[w];
+            const int *base = a.nbr + ((size_t)(w / A) * (size_t)(a.nbr_cap / L)) * kWave + (size_t)(w % A) * L + s;
+            const int nq = nn > s ? (nn - s + L - 1) / L : 0;
+            for (int k = 0; k < nq; k += 4) {
+                int j[4];
+                uint4 q[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) j[u] = (k + u < nq) ? base[(size_t)(k + u) * kWave] : w;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) q[u] = F[j[u]];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) pair(q[u], k + u < nq && !(q[u].w & kFastBit));
             }
+        } else if (a.G.use_cells) {
+            const int cx = cell_coord(pi.x, a.G.L[0], nx);
+            const int cy = cell_coord(pi.y, a.G.L[1], ny);
+            const int cz = cell_coord(pi.z, a.G.L[2], nz);
+            for (int t = 0; t < 27; ++t) {
+                const int c2 = (((cz + t / 9 - 1 + nz) % nz) * ny + (cy + (t / 3) % 3 - 1 + ny) % ny) * nx +
+                               (cx + t % 3 - 1 + nx) % nx;
+                const int m = min(a.cell_cnt[cl][c2], a.cell_cap);
+                const int *row = a.cell_atoms[cl] + (size_t)c2 * a.cell_cap;
+                for (int u = s; u < m; u += L) {
+                    const int j = row[u];
+                    const uint4 qj = F[j];
+                    pair(qj, j != w && !(qj.w & kFastBit));
+                }
+            }
+        } else {
+            const int n_all = a.ctl->n_all;
+            for (int j = s; j < n_all; j += L) {
+                const uint4 qj = F[j];
+                pair(qj, j != w && !(qj.w & kFastBit));
+            }
+        }
+        for (int q = s; q < nfast; q += L) {
+            const int j = flist[q];
+            pair(F[j], j != w);
+        }
+#pragma unroll
+        for (int off = L / 2; off > 0; off >>= 1) {
+            ax += __shfl_xor(ax, off, kWave);
+            ay += __shfl_xor(ay, off, kWave);
+            az += __shfl_xor(az, off, kWave);
         }
         fx = ax; fy = ay; fz = az;
     } else {
         const double4 *P = a.pos[b];
         double ax = 0.0, ay = 0.0, az = 0.0;
-        const double w2 = w * w;
-#pragma unroll 2
-        for (int q = 0; q < nn; ++q) {
-            const int j = nl[q * stride];
-            const double4 pj = P[j];
+        const double w2 = wv * wv;
+        auto pair = [&](const double4 &pj, bool valid) {
+            if (!valid) return;
             const double dx = min_image(pi.x - pj.x, a.G.L[0]);
             const double dy = min_image(pi.y - pj.y, a.G.L[1]);
             const double dz = min_image(pi.z - pj.z, a.G.L[2]);
@@ -352,137 +623,220 @@ __device__ __forceinline__ void lane_force(const KArgs &a, const CoefLds &cf, in
                 const double fs = pair_fs_f64(a.G, crow[mj & kTypeMask], s2, fj ? gscr : 1.0);
                 ax += fs * dx; ay += fs * dy; az += fs * dz;
             }
+        };
+        if (!own_fast) {
+            const int nn = a.nnbr[w];
+            const int *base = a.nbr + ((size_t)(w / A) * (size_t)(a.nbr_cap / L)) * kWave + (size_t)(w % A) * L + s;
+            for (int q = s, k = 0; q < nn; q += L, ++k) {
+                const double4 pj = P[base[(size_t)k * kWave]];
+                pair(pj, !(meta_of(pj) & kFastBit));
+            }
+        } else if (a.G.use_cells) {
+            const int cx = cell_coord(pi.x, a.G.L[0], nx);
+            const int cy = cell_coord(pi.y, a.G.L[1], ny);
+            const int cz = cell_coord(pi.z, a.G.L[2], nz);
+            for (int t = 0; t < 27; ++t) {
+                const int c2 = (((cz + t / 9 - 1 + nz) % nz) * ny + (cy + (t / 3) % 3 - 1 + ny) % ny) * nx +
+                               (cx + t % 3 - 1 + nx) % nx;
+                const int m = min(a.cell_cnt[cl][c2], a.cell_cap);
+                const int *row = a.cell_atoms[cl] + (size_t)c2 * a.cell_cap;
+                for (int u = s; u < m; u += L) {
+                    const int j = row[u];
+                    const double4 pj = P[j];
+                    pair(pj, j != w && !(meta_of(pj) & kFastBit));
+                }
+            }
+        } else {
+            const int n_all = a.ctl->n_all;
+            for (int j = s; j < n_all; j += L) {
+                const double4 pj = P[j];
+                pair(pj, j != w && !(meta_of(pj) & kFastBit));
+            }
+        }
+        for (int q = s; q < nfast; q += L) {
+            const int j = flist[q];
+            pair(P[j], j != w);
+        }
+#pragma unroll
+        for (int off = L / 2; off > 0; off >>= 1) {
+            ax += __shfl_xor(ax, off, kWave);
+            ay += __shfl_xor(ay, off, kWave);
+            az += __shfl_xor(az, off, kWave);
         }
         fx = ax; fy = ay; fz = az;
     }
-    (void)ti;
 }
 
-__device__ __forceinline__ bool moved_beyond_half_skin(const KArgs &a, const double4 &p, const double4 &pb) {
-    const double dx = min_image(p.x - pb.x, a.G.L[0]);
-    const double dy = min_image(p.y - pb.y, a.G.L[1]);
-    const double dz = min_image(p.z - pb.z, a.G.L[2]);
-    return dx * dx + dy * dy + dz * dz > a.G.half_skin2;
+// Displacement since the last list build, from the fixed-point coordinates
+// (flagged slightly early: the threshold is lowered by 1e-5 relative).
+__device__ __forceinline__ bool moved_beyond_half_skin(const KArgs &a, const uint4 &q, const uint4 &qb) {
+    const float dx = (float)(int)(q.x - qb.x) * a.G.fx_scale[0];
+    const float dy = (float)(int)(q.y - qb.y) * a.G.fx_scale[1];
+    const float dz = (float)(int)(q.z - qb.z) * a.G.fx_scale[2];
+    return dx * dx + dy * dy + dz * dz > (float)a.G.half_skin2 * 0.99999f;
 }
 
 // --------------------------------------------------------------------------
 // Flying work of one flyer at x_k (one wavefront per flyer): the trapezoid
 // share 1/2 [U_fly(x_k; w_{k+1}) - U_fly(x_k; w_{k-1})] (endpoints clamped),
-// plus the switch energy U_fly(w_max) at the end where the pair sits at w_max.
+// accumulated in FP64 (pair energies in the precision of the pass).
 // --------------------------------------------------------------------------
-__device__ void flyer_work(const KArgs &a, const CoefLds &cf, int b, int k) {
+template <int PREC>
+__device__ void flyer_work(const KArgs &a, const CoefLds &cf, int b, int k, const int *flist, int nfast) {
     Ctl *c = a.ctl;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     if (wave > 1) return;
     const int move = c->move, nf = c->nf;
     if (move == 0 || k > nf) return;
-    const int f = wave == 0 ? c->ic : c->ia;
-    const int other = wave == 0 ? c->ia : c->ic;
-    const double4 *P = a.pos[b];
-    const double4 pf = P[f];
-    const int tf = meta_of(pf) & kTypeMask;
+    const int f = wave == 0 ? c->wic : c->wia;
+    const int other = wave == 0 ? c->wia : c->wic;
     const double wlo = altitude(a.G.w_max, move, k > 0 ? k - 1 : 0, nf);
     const double whi = altitude(a.G.w_max, move, k < nf ? k + 1 : nf, nf);
-    const double glo = exp(-a.G.kappa * wlo), ghi = exp(-a.G.kappa * whi);
-    double slo = 0.0, shi = 0.0;
+    double dsum = 0.0;
     const int nn = a.nnbr[f];
-    for (int q = lane; q < nn; q += kWave) {
-        const int j = a.nbr[(size_t)q * a.cap + f];
-        if (j == other) continue;
-        const double4 pj = P[j];
-        const double dx = min_image(pf.x - pj.x, a.G.L[0]);
-        const double dy = min_image(pf.y - pj.y, a.G.L[1]);
-        const double dz = min_image(pf.z - pj.z, a.G.L[2]);
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        const PairCoef &cc = cf.c[tf * kMaxTypes + (meta_of(pj) & kTypeMask)];
-        double ulj, uc, fs;
-        const double s2lo = r2 + wlo * wlo;
-        if (s2lo < a.G.rc_max2) { pair_u_f64(a.G, cc, s2lo, glo, ulj, uc, fs); slo += ulj + uc; }
-        const double s2hi = r2 + whi * whi;
-        if (s2hi < a.G.rc_max2) { pair_u_f64(a.G, cc, s2hi, ghi, ulj, uc, fs); shi += ulj + uc; }
-    }
-    slo = wave_sum(slo);
-    shi = wave_sum(shi);
-    if (lane == 0) {
-        c->Wf[wave] += 0.5 * (shi - slo);
-        if (k == 0 && move > 0) c->Esw[wave] = slo;        // U_fly(x_0; w_max)
-        if (k == nf && move < 0) c->Esw[wave] = -shi;      // -U_fly(x_end; w_max)
-        if (wave == 0 && ((k == 0 && move > 0) || (k == nf && move < 0))) {
-            // the flyer-flyer pair: same altitude, 3D distance, unscreened
-            const double4 po = P[other];
-            const double dx = min_image(pf.x - po.x, a.G.L[0]);
-            const double dy = min_image(pf.y - po.y, a.G.L[1]);
-            const double dz = min_image(pf.z - po.z, a.G.L[2]);
+    // the flyer's list (partners that are now fast are taken from the fast list)
+    const int ntot = nn + nfast;
+    if (PREC == 1) {
+        const uint4 qf = a.fx[b][f];
+        const int tf = (int)qf.w & kTypeMask;
+        const float wl2 = (float)(wlo * wlo), wh2 = (float)(whi * whi);
+        const float glo = (float)exp(-a.G.kappa * wlo), ghi = (float)exp(-a.G.kappa * whi);
+        for (int q = lane; q < ntot; q += kWave) {
+            const int j = q < nn ? a.nbr[nbr_slot(a, f, q)] : flist[q - nn];
+            if (j == other) continue;
+            const uint4 qj = a.fx[b][j];
+            if (q < nn && (qj.w & kFastBit)) continue;
+            const float dx = (float)(int)(qf.x - qj.x) * a.G.fx_scale[0];
+            const float dy = (float)(int)(qf.y - qj.y) * a.G.fx_scale[1];
+            const float dz = (float)(int)(qf.z - qj.z) * a.G.fx_scale[2];
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            const PairCoef &cc = cf.c[tf * kMaxTypes + ((int)qj.w & kTypeMask)];
+            const float ulo = (r2 + wl2 < a.G.rc_max2f) ? pair_u_f32(a.G, cc, r2 + wl2, glo) : 0.0f;
+            const float uhi = (r2 + wh2 < a.G.rc_max2f) ? pair_u_f32(a.G, cc, r2 + wh2, ghi) : 0.0f;
+            dsum += (double)uhi - (double)ulo;
+        }
+    } else {
+        const double4 *P = a.pos[b];
+        const double4 pf = P[f];
+        const int tf = meta_of(pf) & kTypeMask;
+        const double glo = exp(-a.G.kappa * wlo), ghi = exp(-a.G.kappa * whi);
+        for (int q = lane; q < ntot; q += kWave) {
+            const int j = q < nn ? a.nbr[nbr_slot(a, f, q)] : flist[q - nn];
+            if (j == other) continue;
+            const double4 pj = P[j];
+            if (q < nn && (meta_of(pj) & kFastBit)) continue;
+            const double dx = min_image(pf.x - pj.x, a.G.L[0]);
+            const double dy = min_image(pf.y - pj.y, a.G.L[1]);
+            const double dz = min_image(pf.z - pj.z, a.G.L[2]);
             const double r2 = dx * dx + dy * dy + dz * dz;
-            double ulj = 0.0, uc = 0.0, fs;
-            if (r2 < a.G.rc_max2)
-                pair_u_f64(a.G, cf.c[tf * kMaxTypes + (meta_of(po) & kTypeMask)], r2, 1.0, ulj, uc, fs);
-            c->Esw_pair = (move > 0 ? 1.0 : -1.0) * (ulj + uc);
+            const PairCoef &cc = cf.c[tf * kMaxTypes + (meta_of(pj) & kTypeMask)];
+            double ulj, uc, fs, ulo = 0.0, uhi = 0.0;
+            if (r2 + wlo * wlo < a.G.rc_max2) { pair_u_f64(a.G, cc, r2 + wlo * wlo, glo, ulj, uc, fs); ulo = ulj + uc; }
+            if (r2 + whi * whi < a.G.rc_max2) { pair_u_f64(a.G, cc, r2 + whi * whi, ghi, ulj, uc, fs); uhi = ulj + uc; }
+            dsum += uhi - ulo;
         }
     }
+    dsum = wave_sum(dsum);
+    if (lane == 0) c->Wf[wave] += 0.5 * dsum;
 }
 
 // ==========================================================================
-// One NEMD step k (k = 0..nf), fused: F(x_k; w_k) from the list; the second
-// half kick of step k-1 (k > 0); the first half kick and drift of step k
-// (k < nf) into the other buffer.  Flyers stay fixed in 3D.  The last block
-// evaluates the flying work.
+// One NEMD step k (k = 0..nf), fused: F(x_k; w_k) from the list (L lanes per
+// atom); the second half kick of step k-1 (k > 0); the first half kick and
+// drift of step k (k < nf) into the other buffer.  Flyers stay fixed in 3D.
+// bin != 0: also bin the new positions for the rebuild before step k+1.
+// The last block evaluates the flying work.
 // ==========================================================================
-template <int PREC>
-__global__ __launch_bounds__(kBlock) void k_step(KArgs a, int k, int b) {
+template <int PREC, int L>
+__global__ __launch_bounds__(kBlock) void k_step(KArgs a, int k, int b, int bin, int cl) {
     __shared__ CoefLds cf;
-    load_coef(cf, a.coef, a.G.n_types);
+    load_coef(cf, a.coef);
     __syncthreads();
-    if (blockIdx.x == gridDim.x - 1) { flyer_work(a, cf, b, k); return; }
-    const Ctl *c = a.ctl;
-    const int move = c->move, nf = c->nf, n_all = c->n_all;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (move == 0 || k > nf || i >= n_all) return;
-    const double4 pi = a.pos[b][i];
-    const int mi = meta_of(pi);
-    if (mi & kFlyBit) {
-        if (k < nf) {
-            a.pos[b ^ 1][i] = pi;
-            if (PREC == 1) a.fx[b ^ 1][i] = a.fx[b][i];
+    Ctl *c = a.ctl;
+    const int lr = k % 3, lw = (k + 1) % 3;       // fast list read / written by this step
+    const int nfast = min(c->nfast[lr], kFastCap);
+    // the list was appended to in atomic order: sort it (fixed summation order)
+    __shared__ int sfast_in[kFastCap], sfast[kFastCap];
+    if (nfast > 0) {
+        for (int q = threadIdx.x; q < nfast; q += kBlock) sfast_in[q] = a.fast[lr * kFastCap + q];
+        __syncthreads();
+        for (int q = threadIdx.x; q < nfast; q += kBlock) {
+            const int e = sfast_in[q];
+            int r = 0;
+            for (int p = 0; p < nfast; ++p) r += (sfast_in[p] < e);
+            sfast[r] = e;
         }
+        __syncthreads();
+    }
+    const int *flist = sfast;
+    if (blockIdx.x == gridDim.x - 1) {
+        if (threadIdx.x == 0) c->nfast[(k + 2) % 3] = 0;
+        flyer_work<PREC>(a, cf, b, k, flist, nfast);
         return;
     }
-    if (moved_beyond_half_skin(a, pi, a.posb[i])) atomicOr(&a.ctl->err, kErrSkin);
+    const int move = c->move, nf = c->nf, n_all = c->n_all;
+    if (move == 0 || k > nf) return;
+    const int lane = threadIdx.x % kWave;
+    const int s = lane % L;
+    const int w = (blockIdx.x * kBlock + threadIdx.x) / L;
+    const bool act = w < n_all;
+    const int wc = act ? w : 0;
+    const double4 pi = a.pos[b][wc];
+    const int mi = meta_of(pi);
+    const bool fly = (mi & kFlyBit) != 0;
     const int ti = mi & kTypeMask;
-    const double w = altitude(a.G.w_max, move, k, nf);
-    const double gscr = exp(-a.G.kappa * w);
-    double fx, fy, fz;
-    lane_force<PREC>(a, cf, b, i, pi, ti, w, gscr, fx, fy, fz);
-    double4 v = a.vel[i];
-    const double hm = a.G.half_dt * a.G.accel / a.mass[ti];
-    if (k > 0) { v.x += hm * fx; v.y += hm * fy; v.z += hm * fz; }
-    if (k < nf) {
-        v.x += hm * fx; v.y += hm * fy; v.z += hm * fz;
-        const double x = wrap_coord(pi.x + a.G.dt * v.x, a.G.L[0]);
-        const double y = wrap_coord(pi.y + a.G.dt * v.y, a.G.L[1]);
-        const double z = wrap_coord(pi.z + a.G.dt * v.z, a.G.L[2]);
-        a.pos[b ^ 1][i] = with_meta(x, y, z, mi);
-        if (PREC == 1)
-            a.fx[b ^ 1][i] = make_uint4(to_fixed(x, a.G.fx_inv[0]), to_fixed(y, a.G.fx_inv[1]),
-                                        to_fixed(z, a.G.fx_inv[2]), (unsigned)mi);
+    const double wv = altitude(a.G.w_max, move, k, nf);
+    const double gscr = exp(-a.G.kappa * wv);
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    if (act && !fly) group_force<PREC, L>(a, cf, b, cl, wc, s, pi, mi, wv, gscr, flist, nfast, fx, fy, fz);
+    if (!act || s != 0) return;
+    double4 v = a.vel[b][wc];
+    double x = pi.x, y = pi.y, z = pi.z;
+    int mo = mi;
+    if (!fly) {
+        const double hm = a.G.half_dt * a.G.accel / a.mass[ti];
+        if (k > 0) { v.x += hm * fx; v.y += hm * fy; v.z += hm * fz; }
+        if (k < nf) {
+            v.x += hm * fx; v.y += hm * fy; v.z += hm * fz;
+            x = wrap_coord(pi.x + a.G.dt * v.x, a.G.L[0]);
+            y = wrap_coord(pi.y + a.G.dt * v.y, a.G.L[1]);
+            z = wrap_coord(pi.z + a.G.dt * v.z, a.G.L[2]);
+        }
     }
-    a.vel[i] = v;
+    uint4 qn = fixed_of(a.G, x, y, z, mi);
+    if (!fly && (mo & kFastBit) == 0 && moved_beyond_half_skin(a, qn, a.posb[wc])) mo |= kFastBit;
+    if (mo & kFastBit) {   // (re-)register in the list read by the next step
+        const int slot = atomicAdd(&c->nfast[lw], 1);
+        if (slot < kFastCap) a.fast[lw * kFastCap + slot] = wc;
+        else atomicOr(&c->err, kErrFast);
+        atomicMax(&c->max_fast, slot + 1);
+    }
+    qn.w = (unsigned)mo;
+    const double4 pn = with_meta(x, y, z, mo);
+    a.pos[b ^ 1][wc] = pn;
+    a.vel[b ^ 1][wc] = v;
+    a.fx[b ^ 1][wc] = qn;
+    if (bin) bin_atom(a, cl ^ 1, wc, pn);
 }
 
-// Test hook: forces of the current buffer-0 state with the flags it carries.
-template <int PREC>
-__global__ __launch_bounds__(kBlock) void k_forces(KArgs a, double w) {
+// Test hook: forces of the working buffer-0 state with the flags it carries;
+// written in canonical order.
+template <int PREC, int L>
+__global__ __launch_bounds__(kBlock) void k_forces(KArgs a, double wv) {
     __shared__ CoefLds cf;
-    load_coef(cf, a.coef, a.G.n_types);
+    load_coef(cf, a.coef);
     __syncthreads();
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= a.ctl->n_all) return;
-    const double4 pi = a.pos[0][i];
+    const int lane = threadIdx.x % kWave;
+    const int s = lane % L;
+    const int w = (blockIdx.x * kBlock + threadIdx.x) / L;
+    const bool act = w < a.ctl->n_all;
+    const int wc = act ? w : 0;
+    const double4 pi = a.pos[0][wc];
     const int mi = meta_of(pi);
-    if (mi & kFlyBit) { a.force[i] = make_double4(0, 0, 0, 0); return; }
-    double fx, fy, fz;
-    lane_force<PREC>(a, cf, 0, i, pi, mi & kTypeMask, w, exp(-a.G.kappa * w), fx, fy, fz);
-    a.force[i] = make_double4(fx, fy, fz, 0.0);
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    if (act && !(mi & kFlyBit))
+        group_force<PREC, L>(a, cf, 0, 0, wc, s, pi, mi, wv, exp(-a.G.kappa * wv), a.fast, 0, fx, fy, fz);
+    if (act && s == 0) a.force[a.perm[wc]] = make_double4(fx, fy, fz, 0.0);
 }
 
 // ==========================================================================
@@ -492,92 +846,102 @@ __global__ __launch_bounds__(kBlock) void k_forces(KArgs a, double w) {
 // atoms at w = 0).  Each pair is counted half from each side.
 // which: 0 start of trial, 1 end, 2 observables / test hook.
 // ==========================================================================
-__global__ __launch_bounds__(kBlock) void k_energy(KArgs a, int which, int mode, double w, int b) {
+__global__ __launch_bounds__(kBlock) void k_energy(KArgs a, int which, int mode, double wv, int b) {
     __shared__ CoefLds cf;
-    __shared__ double red[4][kBlock / kWave];
-    load_coef(cf, a.coef, a.G.n_types);
+    __shared__ double red[5][kBlock / kWave];
+    load_coef(cf, a.coef);
     __syncthreads();
     const Ctl *c = a.ctl;
     const int move = c->move;
     if (mode < 0) mode = ((which == 0 && move > 0) || (which == 1 && move < 0)) ? 1 : 0;
-    if (b < 0) b = (which == 1 && move != 0) ? (c->nf & 1) : 0;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    double ulj_s = 0.0, uc_s = 0.0, k_s = 0.0, vir_s = 0.0;
-    if (i < c->n_all) {
+    const int lane = threadIdx.x % kWave;
+    const int s = lane & (a.lanes - 1);
+    const int w = (blockIdx.x * kBlock + threadIdx.x) >> a.lanes_log2;
+    double ulj_s = 0.0, uc_s = 0.0, k_s = 0.0, vir_s = 0.0, fly_s = 0.0;
+    if (w < c->n_all) {
         const double4 *P = a.pos[b];
-        const double4 pi = P[i];
+        const double4 pi = P[w];
         const int mi = meta_of(pi);
         const bool fi = (mi & kFlyBit) != 0;
-        if (which == 1 && move != 0 && !fi && moved_beyond_half_skin(a, pi, a.posb[i]))
-            atomicOr(&a.ctl->err, kErrSkin);
         const int ti = mi & kTypeMask;
-        if (!(mode == 1 && fi)) {
-            const double wi = (mode == 0 && fi) ? w : 0.0;
-            const double gs = exp(-a.G.kappa * w);
-            const int nn = a.nnbr[i];
-            for (int q = 0; q < nn; ++q) {
-                const int j = a.nbr[(size_t)q * a.cap + i];
-                const double4 pj = P[j];
-                const int mj = meta_of(pj);
-                const bool fj = (mj & kFlyBit) != 0;
-                if (mode == 1 && fj) continue;
-                const double wj = (mode == 0 && fj) ? w : 0.0;
-                const double dx = min_image(pi.x - pj.x, a.G.L[0]);
-                const double dy = min_image(pi.y - pj.y, a.G.L[1]);
-                const double dz = min_image(pi.z - pj.z, a.G.L[2]);
-                const double r2 = dx * dx + dy * dy + dz * dz;
-                const double dw = wi - wj;
-                const double s2 = r2 + dw * dw;
-                if (s2 >= a.G.rc_max2) continue;
-                const double g = (mode == 0 && fi != fj) ? gs : 1.0;
-                double ulj, uc, fs;
-                pair_u_f64(a.G, cf.c[ti * kMaxTypes + (mj & kTypeMask)], s2, g, ulj, uc, fs);
-                ulj_s += 0.5 * ulj;
-                uc_s += 0.5 * uc;
-                vir_s += 0.5 * fs * r2;
+        const double gs = exp(-a.G.kappa * wv);
+        const double gmax = exp(-a.G.kappa * a.G.w_max);
+        const double wmax2 = a.G.w_max * a.G.w_max;
+        const int nn = a.nnbr[w];
+        for (int q = s; q < nn; q += a.lanes) {
+            const int j = a.nbr[nbr_slot(a, w, q)];
+            const double4 pj = P[j];
+            const int mj = meta_of(pj);
+            const bool fj = (mj & kFlyBit) != 0;
+            const double dx = min_image(pi.x - pj.x, a.G.L[0]);
+            const double dy = min_image(pi.y - pj.y, a.G.L[1]);
+            const double dz = min_image(pi.z - pj.z, a.G.L[2]);
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            const PairCoef &cc = cf.c[ti * kMaxTypes + (mj & kTypeMask)];
+            double ulj, uc, fs;
+            // switch energy U_fly(w_max), counted from the flyer's side:
+            // flyer-nonflyer at the 4D distance, flyer-flyer half from each
+            if (fi && which < 2) {
+                if (!fj && r2 + wmax2 < a.G.rc_max2) {
+                    pair_u_f64(a.G, cc, r2 + wmax2, gmax, ulj, uc, fs);
+                    fly_s += ulj + uc;
+                } else if (fj && r2 < a.G.rc_max2) {
+                    pair_u_f64(a.G, cc, r2, 1.0, ulj, uc, fs);
+                    fly_s += 0.5 * (ulj + uc);
+                }
             }
+            if (mode == 1 && (fi || fj)) continue;
+            const double wi = (mode == 0 && fi) ? wv : 0.0;
+            const double wj = (mode == 0 && fj) ? wv : 0.0;
+            const double dw = wi - wj;
+            const double s2 = r2 + dw * dw;
+            if (s2 >= a.G.rc_max2) continue;
+            const double g = (mode == 0 && fi != fj) ? gs : 1.0;
+            pair_u_f64(a.G, cc, s2, g, ulj, uc, fs);
+            ulj_s += 0.5 * ulj;
+            uc_s += 0.5 * uc;
+            vir_s += 0.5 * fs * r2;
         }
-        if (!fi) {
-            const double4 v = a.vel[i];
+        if (s == 0 && !fi) {
+            const double4 v = a.vel[b][w];
             k_s = 0.5 * a.mass[ti] * (v.x * v.x + v.y * v.y + v.z * v.z) / a.G.accel;
         }
     }
-    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int wave = threadIdx.x / kWave;
     ulj_s = wave_sum(ulj_s); uc_s = wave_sum(uc_s); k_s = wave_sum(k_s); vir_s = wave_sum(vir_s);
-    if (lane == 0) { red[0][wave] = ulj_s; red[1][wave] = uc_s; red[2][wave] = k_s; red[3][wave] = vir_s; }
+    fly_s = wave_sum(fly_s);
+    if (lane == 0) {
+        red[0][wave] = ulj_s; red[1][wave] = uc_s; red[2][wave] = k_s; red[3][wave] = vir_s;
+        red[4][wave] = fly_s;
+    }
     __syncthreads();
-    if (threadIdx.x < 4) {
-        double s = 0.0;
-        for (int q = 0; q < kBlock / kWave; ++q) s += red[threadIdx.x][q];
-        a.partial[(size_t)blockIdx.x * 4 + threadIdx.x] = s;
+    if (threadIdx.x < 5) {
+        double sum = 0.0;
+        for (int q = 0; q < kBlock / kWave; ++q) sum += red[threadIdx.x][q];
+        a.partial[(size_t)blockIdx.x * 5 + threadIdx.x] = sum;
     }
 }
 
 __global__ __launch_bounds__(kBlock) void k_energy_final(KArgs a, int which, int nblocks) {
-    __shared__ double red[4][kBlock];
-    for (int comp = 0; comp < 4; ++comp) {
+    __shared__ double red[5][kBlock];
+    for (int comp = 0; comp < 5; ++comp) {
         double s = 0.0;
-        for (int q = threadIdx.x; q < nblocks; q += kBlock) s += a.partial[(size_t)q * 4 + comp];
+        for (int q = threadIdx.x; q < nblocks; q += kBlock) s += a.partial[(size_t)q * 5 + comp];
         red[comp][threadIdx.x] = s;
     }
     __syncthreads();
     for (int off = kBlock / 2; off > 0; off >>= 1) {
         if (threadIdx.x < off)
-            for (int comp = 0; comp < 4; ++comp) red[comp][threadIdx.x] += red[comp][threadIdx.x + off];
+            for (int comp = 0; comp < 5; ++comp) red[comp][threadIdx.x] += red[comp][threadIdx.x + off];
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         Ctl *c = a.ctl;
         const double U = red[0][0] + red[1][0];
-        if (which == 0) { c->U0 = U; c->K0 = red[2][0]; }
-        else if (which == 1) { c->U1 = U; c->K1 = red[2][0]; }
+        if (which == 0) { c->U0 = U; c->K0 = red[2][0]; c->Ufly0 = red[4][0]; }
+        else if (which == 1) { c->U1 = U; c->K1 = red[2][0]; c->Ufly1 = red[4][0]; }
         c->Ulj = red[0][0]; c->Uc = red[1][0]; c->vir = red[3][0];
     }
-}
-
-__global__ __launch_bounds__(kBlock) void k_snapshot(KArgs a) {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < a.ctl->n_all) a.pos0[i] = a.pos[0][i];
 }
 
 // ==========================================================================
@@ -598,7 +962,7 @@ __global__ void k_metropolis(KArgs a) {
     r->flags = 0;
     r->accepted = 0;
     c->accepted = 0;
-    if (c->err & (kErrNbr | kErrCell | kErrSkin | kErrCap)) c->retry = 1;
+    if (c->err & (kErrNbr | kErrCell | kErrSkin | kErrCap | kErrFast)) c->retry = 1;
     if (move == 0) {
         r->move = -1;
         r->flags = c->retry ? 0u : 1u;   // H4D_FLAG_EMPTY
@@ -609,8 +973,8 @@ __global__ void k_metropolis(KArgs a) {
         return;
     }
     r->move = move;
-    r->tag_c = a.tag[c->ic];
-    r->tag_a = a.tag[c->ia];
+    r->tag_c = a.ctag[c->ic];
+    r->tag_a = a.ctag[c->ia];
     const double H0 = c->U0 + c->K0, H1 = c->U1 + c->K1;
     const double dH = H1 - H0;
     const int n_small = move > 0 ? c->nsalt : c->nsalt - 1;
@@ -619,7 +983,7 @@ __global__ void k_metropolis(KArgs a) {
     r->dH = dH; r->dU = c->U1 - c->U0; r->dK = c->K1 - c->K0;
     r->H0 = H0; r->H1 = H1;
     r->W_prot = c->Wf[0] + c->Wf[1];
-    r->E_switch = c->Esw[0] + c->Esw[1] + c->Esw_pair;
+    r->E_switch = move > 0 ? c->Ufly0 : -c->Ufly1;
     r->dM = move > 0 ? dH - I / a.G.beta : -dH - I / a.G.beta;
     r->ln_ratio = lnR;
     int acc = 0;
@@ -630,46 +994,51 @@ __global__ void k_metropolis(KArgs a) {
     c->accepted = acc;
 }
 
-// Commit or roll back (data).  Accepted insertion: the ghosts become
-// physical; accepted deletion: stable compaction without the pair;
-// rejection: restore the snapshot.  The canonical state ends in buffer 0.
-__global__ __launch_bounds__(kBlock) void k_commit(KArgs a) {
+// Commit (accepted: the working positions go back to canonical order, ghosts
+// become physical, a deleted pair is compacted out) or roll back (the
+// canonical arrays are the snapshot; only a deletion's flags are cleared).
+__global__ __launch_bounds__(kBlock) void k_commit(KArgs a, int bf) {
     const Ctl *c = a.ctl;
     const int move = c->move;
     if (move == 0) return;
     const int i = blockIdx.x * kBlock + threadIdx.x;
-    const int bf = c->nf & 1;
-    if (c->accepted && move > 0) {
+    if (c->accepted) {
         if (i < c->n_all) {
             const double4 p = a.pos[bf][i];
-            a.pos[0][i] = with_meta(p.x, p.y, p.z, meta_of(p) & ~kFlyBit);
+            a.cpos[a.perm[i]] = with_meta(p.x, p.y, p.z, meta_of(p) & ~kFlyBit);
         }
-    } else if (c->accepted && move < 0) {
-        const int ic = c->ic, ia = c->ia;
-        if (i < c->n_all && i != ic && i != ia) {
-            const int d = i - (i > ic) - (i > ia);
-            a.tpos[d] = a.pos[bf][i];
-            a.ttag[d] = a.tag[i];
-            a.ttype[d] = a.type[i];
-            a.tmol[d] = a.mol[i];
-        }
-    } else {
-        if (i < c->n) {
-            const double4 p = a.pos0[i];
-            a.pos[0][i] = with_meta(p.x, p.y, p.z, meta_of(p) & ~kFlyBit);
-        }
+    } else if (move < 0 && i == 0) {
+        double4 p = a.cpos[c->ic];
+        a.cpos[c->ic] = with_meta(p.x, p.y, p.z, meta_of(p) & ~kFlyBit);
+        p = a.cpos[c->ia];
+        a.cpos[c->ia] = with_meta(p.x, p.y, p.z, meta_of(p) & ~kFlyBit);
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_commit2(KArgs a) {
+// accepted deletion: stable compaction of the canonical arrays without the pair
+__global__ __launch_bounds__(kBlock) void k_compact1(KArgs a) {
+    const Ctl *c = a.ctl;
+    if (!(c->accepted && c->move < 0)) return;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const int ic = c->ic, ia = c->ia;
+    if (i < c->n_all && i != ic && i != ia) {
+        const int d = i - (i > ic) - (i > ia);
+        a.tpos[d] = a.cpos[i];
+        a.ttag[d] = a.ctag[i];
+        a.ttype[d] = a.ctype[i];
+        a.tmol[d] = a.cmol[i];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_compact2(KArgs a) {
     const Ctl *c = a.ctl;
     if (!(c->accepted && c->move < 0)) return;
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i < c->n_all - 2) {
-        a.pos[0][i] = a.tpos[i];
-        a.tag[i] = a.ttag[i];
-        a.type[i] = a.ttype[i];
-        a.mol[i] = a.tmol[i];
+        a.cpos[i] = a.tpos[i];
+        a.ctag[i] = a.ttag[i];
+        a.ctype[i] = a.ttype[i];
+        a.cmol[i] = a.tmol[i];
     }
 }
 
@@ -692,6 +1061,14 @@ __global__ __launch_bounds__(kBlock) void k_sum_nbr(KArgs a, unsigned long long 
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
     if ((threadIdx.x % kWave) == 0) atomicAdd(out, v);
+}
+
+// Test hooks on the canonical state: flag an atom as flying or not.
+__global__ void k_set_fly(KArgs a, int i, int on) {
+    double4 p = a.cpos[i];
+    int m = meta_of(p);
+    m = on ? (m | kFlyBit) : (m & ~kFlyBit);
+    a.cpos[i] = with_meta(p.x, p.y, p.z, m);
 }
 
 }  // namespace h4d

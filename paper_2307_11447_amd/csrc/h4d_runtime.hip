@@ -7,8 +7,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <tuple>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -57,6 +60,14 @@ struct h4d_system {
     int64_t step_launches = 0;
     double step_ms = 0.0;
     int trial_rebuilds = 0;
+    int64_t retries = 0;
+    int trial_M = 1;            // rebuild interval of the trial being run
+    int cl = 0;                 // cell buffer of the current list (the next binning uses cl ^ 1)
+    // captured trial graphs, keyed by launch shape; dropped when buffers move
+    hipStream_t cap_stream = nullptr;
+    std::map<std::tuple<int, int, int, int, int, int, int>, hipGraphExec_t> graphs;
+    bool graphs_ok[2] = {true, false};  // timed trials launch eagerly (events per step kernel)
+    int last_buf = 0;           // working buffer that holds the last trajectory's end
     std::vector<void *> allocs;
     // running statistics (Eq. 1)
     int64_t n_trials = 0, n_ins = 0, n_ins_acc = 0, n_del = 0, n_del_acc = 0;
@@ -72,10 +83,17 @@ struct h4d_system {
         return H4D_OK;
     }
     void release(void *q) {
+        drop_graphs();
         auto it = std::find(allocs.begin(), allocs.end(), q);
         if (it != allocs.end()) { (void)hipFree(q); allocs.erase(it); }
     }
+    void drop_graphs() {
+        for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        graphs.clear();
+    }
     ~h4d_system() {
+        drop_graphs();
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
         for (void *q : allocs) (void)hipFree(q);
         if (h_rec) (void)hipHostFree(h_rec);
@@ -96,6 +114,8 @@ int check_params(const h4d_params &p) {
     } else if (p.n_steps < 1) {
         return fail(H4D_EINVAL, "n_steps must be >= 1");
     }
+    if (p.lanes_per_atom != 0 && p.lanes_per_atom != 4 && p.lanes_per_atom != 8 && p.lanes_per_atom != 16)
+        return fail(H4D_EINVAL, "lanes_per_atom must be 0, 4, 8 or 16");
     if (p.precision != H4D_PREC_FP64 && p.precision != H4D_PREC_FP32)
         return fail(H4D_EINVAL, "precision must be H4D_PREC_FP64 or H4D_PREC_FP32");
     for (int t = 0; t < p.n_types; ++t)
@@ -144,6 +164,10 @@ void setup_geo(h4d_system *s) {
     G.alpha2f = (float)G.alpha2;
     G.cexf = (float)G.cex;
     G.Scf = (float)G.Sc;
+    G.erfc_rc_over_rcf = (float)G.erfc_rc_over_rc;
+    G.nalpha2_log2e = (float)(-al * al * 1.4426950408889634074);
+    G.p_alpha = (float)(0.3275911 * al);
+    G.rc_coulf = (float)G.rc_coul;
     G.dt = p.dt;
     G.half_dt = 0.5 * p.dt;
     G.accel = p.accel;
@@ -180,6 +204,7 @@ void setup_geo(h4d_system *s) {
             c.sig2f = (float)c.sig2;
             c.eps24f = (float)(24.0 * eps);
             c.qqkf = (float)c.qqk;
+            c.lj_shiftf = (float)c.lj_shift;
         }
 }
 
@@ -191,32 +216,100 @@ void initial_capacities(h4d_system *s, int n) {
     const double rlist = std::max(p.rc_lj, p.rc_coul) + p.skin;
     const double nb = 4.18879020478639 * rlist * rlist * rlist * rho;
     int cap = (int)(1.5 * nb) + 32;
-    cap = (cap + 7) & ~7;
-    s->a.nbr_cap = std::min(cap, std::max(8, s->cap));
+    cap = std::min(cap, s->cap + kMaxLanes);
+    s->a.nbr_cap = (cap + kMaxLanes - 1) / kMaxLanes * kMaxLanes;
     const Geo &G = s->a.G;
     const double cell_vol = V / ((double)G.ncell[0] * G.ncell[1] * G.ncell[2]);
-    int cc = (int)(2.0 * rho * cell_vol) + 32;
-    s->a.cell_cap = G.use_cells ? std::min(cc, std::max(32, s->cap)) : 1;
+    int cc = (int)(1.6 * rho * cell_vol) + 16;
+    s->a.cell_cap = G.use_cells ? std::min(cc, std::max(32, s->cap)) : s->cap;
     s->a.ncell_total = G.ncell[0] * G.ncell[1] * G.ncell[2];
+}
+
+size_t nbr_elems(const h4d_system *s) {
+    const int A = kWave / s->a.lanes;
+    const size_t groups = (size_t)(s->cap + A - 1) / A;
+    return groups * (size_t)(s->a.nbr_cap / s->a.lanes) * kWave;
 }
 
 int alloc_lists(h4d_system *s) {
     int rc;
-    if ((rc = s->alloc(&s->a.nbr, (size_t)s->a.nbr_cap * s->cap))) return rc;
-    if ((rc = s->alloc(&s->a.cell_cnt, (size_t)s->a.ncell_total))) return rc;
-    if ((rc = s->alloc(&s->a.cell_atoms, (size_t)s->a.ncell_total * s->a.cell_cap))) return rc;
+    if ((rc = s->alloc(&s->a.nbr, nbr_elems(s)))) return rc;
+    for (int q = 0; q < 2; ++q) {
+        if ((rc = s->alloc(&s->a.cell_cnt[q], (size_t)s->a.ncell_total))) return rc;
+        if ((rc = s->alloc(&s->a.cell_atoms[q], (size_t)s->a.ncell_total * s->a.cell_cap))) return rc;
+        HIPC(hipMemset(s->a.cell_cnt[q], 0, sizeof(int) * s->a.ncell_total));
+    }
+    if ((rc = s->alloc(&s->a.cell_off, (size_t)s->a.ncell_total + 1))) return rc;
+    if ((rc = s->alloc(&s->a.fast, (size_t)3 * kFastCap))) return rc;
     return H4D_OK;
 }
 
-int rebuild(h4d_system *s, int b, int k, int G) {
+int atom_blocks_l(int n, int lanes) { return std::max(1, (n * lanes + kBlock - 1) / kBlock); }
+
+size_t list_cells_lds(const h4d_system *s) { return (size_t)s->a.cell_cap * 27 * sizeof(uint4); }
+
+void launch_list(h4d_system *s, int b, int cb, int n_all_max, hipStream_t st) {
     KArgs &a = s->a;
-    hipStream_t st = s->stream;
-    if (a.G.use_cells) {
-        hipLaunchKernelGGL(k_cell_clear, dim3(blocks_for(a.ncell_total)), dim3(kBlock), 0, st, a, k);
-        hipLaunchKernelGGL(k_cell_bin, dim3(G), dim3(kBlock), 0, st, a, b, k);
-        hipLaunchKernelGGL(k_cell_sort, dim3(a.ncell_total), dim3(kWave), a.cell_cap * sizeof(int), st, a, k);
+    if (a.G.use_cells && list_cells_lds(s) <= 56 * 1024)
+        hipLaunchKernelGGL(k_list_cells, dim3(a.ncell_total), dim3(kBlock), list_cells_lds(s), st, a, b, cb);
+    else if (a.G.use_cells)
+        hipLaunchKernelGGL(k_list_lanes, dim3(atom_blocks_l(n_all_max, a.lanes)), dim3(kBlock), 0, st, a, b, cb);
+    else
+        hipLaunchKernelGGL(k_list_allpairs, dim3(atom_blocks_l(n_all_max, a.lanes)), dim3(kBlock), 0, st, a, b, cb);
+}
+
+template <int PREC, int L>
+void launch_step_l(h4d_system *s, hipStream_t st, int G, hipEvent_t e0, hipEvent_t e1, int k, int b, int bin) {
+    KArgs &a = s->a;
+    if (e0) hipExtLaunchKernelGGL(k_step<PREC, L>, dim3(G), dim3(kBlock), 0, st, e0, e1, 0, a, k, b, bin, s->cl);
+    else hipLaunchKernelGGL((k_step<PREC, L>), dim3(G), dim3(kBlock), 0, st, a, k, b, bin, s->cl);
+}
+
+template <int PREC>
+void launch_step(h4d_system *s, hipStream_t st, int G, hipEvent_t e0, hipEvent_t e1, int k, int b, int bin) {
+    switch (s->a.lanes) {
+        case 4: launch_step_l<PREC, 4>(s, st, G, e0, e1, k, b, bin); break;
+        case 8: launch_step_l<PREC, 8>(s, st, G, e0, e1, k, b, bin); break;
+        default: launch_step_l<PREC, 16>(s, st, G, e0, e1, k, b, bin); break;
     }
-    hipLaunchKernelGGL(k_list, dim3(G), dim3(kBlock), 0, st, a, b, k);
+}
+
+template <int PREC>
+void launch_forces(h4d_system *s, int G, double w) {
+    KArgs &a = s->a;
+    switch (a.lanes) {
+        case 4: hipLaunchKernelGGL((k_forces<PREC, 4>), dim3(G), dim3(kBlock), 0, s->stream, a, w); break;
+        case 8: hipLaunchKernelGGL((k_forces<PREC, 8>), dim3(G), dim3(kBlock), 0, s->stream, a, w); break;
+        default: hipLaunchKernelGGL((k_forces<PREC, 16>), dim3(G), dim3(kBlock), 0, s->stream, a, w); break;
+    }
+}
+
+// Sort the canonical atoms into cell order (working buffer 0), draw the
+// momenta of the current trial index, and build the list (cell buffer 0).
+int sort_in(h4d_system *s, int n_all_max, hipStream_t st) {
+    KArgs &a = s->a;
+    const int G1 = blocks_for(n_all_max);
+    const int nc = a.ncell_total;
+    hipLaunchKernelGGL(k_cell_clear, dim3(blocks_for(nc)), dim3(kBlock), 0, st, a, 0);
+    hipLaunchKernelGGL(k_bin_canonical, dim3(G1), dim3(kBlock), 0, st, a, 0);
+    hipLaunchKernelGGL(k_cell_sort, dim3(nc), dim3(kWave), a.cell_cap * sizeof(int), st, a, 0);
+    hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, st, a, 0);
+    hipLaunchKernelGGL(k_gather_in, dim3(nc), dim3(kWave), 0, st, a, 0);
+    launch_list(s, 0, 0, n_all_max, st);
+    s->cl = 0;
+    HIPC(hipGetLastError());
+    return H4D_OK;
+}
+
+// Mid-trajectory rebuild: the preceding step binned the atoms into cell
+// buffer cl ^ 1.
+int rebuild_mid(h4d_system *s, int b, int n_all_max, hipStream_t st) {
+    KArgs &a = s->a;
+    const int cb = s->cl ^ 1;
+    if (a.G.use_cells)
+        hipLaunchKernelGGL(k_cell_sort, dim3(a.ncell_total), dim3(kWave), a.cell_cap * sizeof(int), st, a, cb);
+    launch_list(s, b, cb, n_all_max, st);
+    s->cl = cb;
     HIPC(hipGetLastError());
     return H4D_OK;
 }
@@ -243,68 +336,111 @@ int grow_lists(h4d_system *s, unsigned err) {
     KArgs &a = s->a;
     const Ctl *c = s->h_ctl;
     if (err & kErrNbr) {
-        int need = std::max(c->max_nbr, a.nbr_cap + 8);
-        need = ((int)(need * 1.25) + 7) & ~7;
+        int need = std::max(c->max_nbr, a.nbr_cap + kMaxLanes);
+        need = (int)(need * 1.25) + kMaxLanes;
+        need = (need + kMaxLanes - 1) / kMaxLanes * kMaxLanes;
         s->release(a.nbr);
         a.nbr_cap = need;
-        int rc = s->alloc(&a.nbr, (size_t)a.nbr_cap * s->cap);
+        int rc = s->alloc(&a.nbr, nbr_elems(s));
         if (rc) return rc;
     }
     if (err & kErrCell) {
         int need = std::max(c->max_cell, a.cell_cap + 8);
         need = (int)(need * 1.25) + 8;
-        s->release(a.cell_atoms);
+        s->release(a.cell_atoms[0]);
+        s->release(a.cell_atoms[1]);
         a.cell_cap = need;
-        int rc = s->alloc(&a.cell_atoms, (size_t)a.ncell_total * a.cell_cap);
-        if (rc) return rc;
+        int rc;
+        if ((rc = s->alloc(&a.cell_atoms[0], (size_t)a.ncell_total * a.cell_cap))) return rc;
+        if ((rc = s->alloc(&a.cell_atoms[1], (size_t)a.ncell_total * a.cell_cap))) return rc;
     }
+    return H4D_OK;
+}
+
+// Enqueue every kernel of one trial on st (the trial's shape is fixed by the
+// host-side atom bound, the rebuild interval and N_f; the kernels read
+// everything else from the control block).  With timing, HIP events bracket
+// each step kernel.
+int enqueue_trial(h4d_system *s, int move, hipStream_t st, int nf, int M, bool timing) {
+    KArgs &a = s->a;
+    const int n_all_max = s->n_host + 2;
+    const int G = blocks_for(n_all_max);                 // one thread per atom
+    const int GA = atom_blocks_l(n_all_max, a.lanes);    // lanes threads per atom
+    int rc;
+    hipLaunchKernelGGL(k_propose, dim3(1), dim3(kBlock), 0, st, a, move);
+    if ((rc = sort_in(s, n_all_max, st))) return rc;
+    hipLaunchKernelGGL(k_energy, dim3(GA), dim3(kBlock), 0, st, a, 0, -1, 0.0, 0);
+    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kBlock), 0, st, a, 0, GA);
+    int b = 0;
+    const bool final_rebuild = nf % M != 0;   // the end energy needs a list without fast atoms
+    for (int k = 0; k <= nf; ++k) {
+        if (k > 0 && k % M == 0)
+            if ((rc = rebuild_mid(s, b, n_all_max, st))) return rc;
+        const int bin = !a.G.use_cells ? 0 : ((k + 1) % M == 0 && k + 1 <= nf ? 1 : (k == nf && final_rebuild ? 1 : 0));
+        hipEvent_t e0 = timing ? s->ev[2 * k] : nullptr, e1 = timing ? s->ev[2 * k + 1] : nullptr;
+        if (s->p.precision == H4D_PREC_FP32) launch_step<1>(s, st, GA + 1, e0, e1, k, b, bin);
+        else launch_step<0>(s, st, GA + 1, e0, e1, k, b, bin);
+        b ^= 1;
+    }
+    if (final_rebuild && (rc = rebuild_mid(s, b, n_all_max, st))) return rc;
+    s->last_buf = b;
+    hipLaunchKernelGGL(k_energy, dim3(GA), dim3(kBlock), 0, st, a, 1, -1, 0.0, b);
+    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kBlock), 0, st, a, 1, GA);
+    hipLaunchKernelGGL(k_metropolis, dim3(1), dim3(1), 0, st, a);
+    hipLaunchKernelGGL(k_commit, dim3(G), dim3(kBlock), 0, st, a, b);
+    hipLaunchKernelGGL(k_compact1, dim3(G), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL(k_compact2, dim3(G), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL(k_commit_ctl, dim3(1), dim3(1), 0, st, a);
+    HIPC(hipGetLastError());
     return H4D_OK;
 }
 
 int launch_trial(h4d_system *s, int move) {
     KArgs &a = s->a;
     hipStream_t st = s->stream;
-    const int G = blocks_for(s->n_host + 2);
+    const int nf = s->p.n_steps_max > 0 ? s->p.n_steps_max : s->p.n_steps;
+    const int M = std::max(1, s->trial_M);
     int rc;
-    hipLaunchKernelGGL(k_propose, dim3(1), dim3(kBlock), 0, st, a, move);
-    hipLaunchKernelGGL(k_mb, dim3(G), dim3(kBlock), 0, st, a);
-    if ((rc = rebuild(s, 0, 0, G))) return rc;
-    hipLaunchKernelGGL(k_energy, dim3(G), dim3(kBlock), 0, st, a, 0, -1, 0.0, 0);
-    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kBlock), 0, st, a, 0, G);
-    hipLaunchKernelGGL(k_snapshot, dim3(G), dim3(kBlock), 0, st, a);
-    const int nf_launch = s->p.n_steps_max > 0 ? s->p.n_steps_max : s->p.n_steps;
-    const int M = std::max(1, s->rebuild_every);
-    s->trial_rebuilds = 0;
-    if (s->timing && (int)s->ev.size() < 2 * (nf_launch + 1)) {
-        while ((int)s->ev.size() < 2 * (nf_launch + 1)) {
+    s->trial_rebuilds = nf / M + (nf % M != 0 ? 1 : 0);
+    if (s->timing && (int)s->ev.size() < 2 * (nf + 1)) {
+        s->drop_graphs();
+        while ((int)s->ev.size() < 2 * (nf + 1)) {
             hipEvent_t e;
             HIPC(hipEventCreate(&e));
             s->ev.push_back(e);
         }
     }
-    for (int k = 0; k <= nf_launch; ++k) {
-        if (k > 0 && k % M == 0) {
-            if ((rc = rebuild(s, k & 1, k, G))) return rc;
-            s->trial_rebuilds += 1;
+    bool launched = false;
+    const int tm = s->timing ? 1 : 0;
+    if (s->graphs_ok[tm]) {
+        if (!s->cap_stream) HIPC(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+        const int n_all_max = s->n_host + 2;
+        const auto key = std::make_tuple(blocks_for(n_all_max), atom_blocks_l(n_all_max, a.lanes), M, nf, move, tm,
+                                         a.lanes);
+        auto it = s->graphs.find(key);
+        if (it == s->graphs.end()) {
+            hipGraph_t graph = nullptr;
+            hipGraphExec_t exec = nullptr;
+            bool ok = hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+            int erc = ok ? enqueue_trial(s, move, s->cap_stream, nf, M, s->timing) : H4D_OK;
+            ok = hipStreamEndCapture(s->cap_stream, &graph) == hipSuccess && ok && erc == H4D_OK;
+            if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+            if (graph) (void)hipGraphDestroy(graph);
+            (void)hipGetLastError();
+            if (ok) it = s->graphs.emplace(key, exec).first;
+            else s->graphs_ok[tm] = false;   // capture unsupported: launch eagerly from now on
         }
-        hipEvent_t e0 = s->timing ? s->ev[2 * k] : nullptr, e1 = s->timing ? s->ev[2 * k + 1] : nullptr;
-        if (s->p.precision == H4D_PREC_FP32)
-            hipExtLaunchKernelGGL(k_step<1>, dim3(G + 1), dim3(kBlock), 0, st, e0, e1, 0, a, k, k & 1);
-        else
-            hipExtLaunchKernelGGL(k_step<0>, dim3(G + 1), dim3(kBlock), 0, st, e0, e1, 0, a, k, k & 1);
+        if (it != s->graphs.end()) {
+            HIPC(hipGraphLaunch(it->second, st));
+            launched = true;
+        }
     }
-    hipLaunchKernelGGL(k_energy, dim3(G), dim3(kBlock), 0, st, a, 1, -1, 0.0, -1);
-    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kBlock), 0, st, a, 1, G);
-    hipLaunchKernelGGL(k_metropolis, dim3(1), dim3(1), 0, st, a);
-    hipLaunchKernelGGL(k_commit, dim3(G), dim3(kBlock), 0, st, a);
-    hipLaunchKernelGGL(k_commit2, dim3(G), dim3(kBlock), 0, st, a);
-    hipLaunchKernelGGL(k_commit_ctl, dim3(1), dim3(1), 0, st, a);
-    HIPC(hipGetLastError());
+    if (!launched && (rc = enqueue_trial(s, move, st, nf, M, s->timing))) return rc;
     HIPC(hipMemcpyAsync(s->h_rec, a.rec, sizeof(TrialRec), hipMemcpyDeviceToHost, st));
     HIPC(hipMemcpyAsync(s->h_ctl, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
     HIPC(hipStreamSynchronize(st));
     if (s->timing) {
-        const int nf_dev = std::min(s->h_ctl->nf, nf_launch);
+        const int nf_dev = std::min(s->h_ctl->nf, nf);
         for (int k = 0; k <= nf_dev; ++k) {
             float ms = 0.f;
             HIPC(hipEventElapsedTime(&ms, s->ev[2 * k], s->ev[2 * k + 1]));
@@ -317,6 +453,7 @@ int launch_trial(h4d_system *s, int move) {
 
 int run_one(h4d_system *s, int move, h4d_trial *out) {
     bool retried = false;
+    s->trial_M = std::max(1, s->rebuild_every);
     for (int attempt = 0; attempt < 16; ++attempt) {
         int rc = launch_trial(s, move);
         if (rc) return rc;
@@ -325,12 +462,16 @@ int run_one(h4d_system *s, int move, h4d_trial *out) {
             const unsigned err = c->err;
             if (err & kErrCap) return fail(H4D_ECAPACITY, "atom capacity exhausted");
             if ((rc = grow_lists(s, err))) return rc;
-            if (err & kErrSkin) {
-                s->rebuild_every = std::max(1, (s->rebuild_every * 3) / 4);
+            // more fast atoms than the fast list holds: recompute this trial
+            // with a shorter rebuild interval, and shorten the base interval
+            if (err & (kErrSkin | kErrFast)) {
+                s->trial_M = std::max(1, s->trial_M / 2);
+                if (s->p.rebuild_every == 0) s->rebuild_every = std::max(1, (s->rebuild_every * 3) / 4);
                 s->clean_trials = 0;
             }
             if ((rc = clear_errors(s))) return rc;
             retried = true;
+            s->retries += 1;
             continue;
         }
         h4d_trial r;
@@ -343,12 +484,17 @@ int run_one(h4d_system *s, int move, h4d_trial *out) {
         s->n_trials += 1;
         if (r.move > 0) { s->n_ins += 1; s->n_ins_acc += r.accepted; }
         else { s->n_del += 1; s->n_del_acc += r.accepted; }
+        // automatic rebuild interval: lengthen it after a run of trials whose
+        // fast lists stayed short (a few percent of their capacity)
+        if (s->p.rebuild_every == 0 && !retried) {
+            if (c->max_fast <= kFastCap / 16) {
+                if (++s->clean_trials >= 20) { s->rebuild_every += 1; s->clean_trials = 0; }
+            } else {
+                s->clean_trials = 0;
+            }
+        }
         s->N_sum += (double)c->nsalt;
         s->N2_sum += (double)c->nsalt * (double)c->nsalt;
-        if (++s->clean_trials >= 100 && s->p.rebuild_every == 0) {
-            s->rebuild_every += 1;
-            s->clean_trials = 0;
-        }
         if (r.flags & H4D_FLAG_NONFINITE) {
             if (!(r.dH == r.dH)) return fail(H4D_ENONFINITE, "NaN energy; the trial was rolled back");
         }
@@ -392,6 +538,9 @@ int32_t h4d_init_system(const h4d_params *params, int32_t n_atoms, int32_t n_sal
 
     auto *s = new h4d_system();
     s->p = *params;
+    if (const char *e = std::getenv("H4D_NO_GRAPHS")) {
+        if (e[0] == '1') s->graphs_ok[0] = false;   // launch every kernel eagerly
+    }
     s->stream = static_cast<hipStream_t>(hip_stream);
     s->cap = params->capacity > 0 ? params->capacity : n_atoms + 4096;
     if (s->cap < n_atoms + 2) { delete s; return fail(H4D_EINVAL, "capacity below n_atoms + 2"); }
@@ -399,6 +548,16 @@ int32_t h4d_init_system(const h4d_params *params, int32_t n_atoms, int32_t n_sal
     s->nsalt_host = n_salt;
     s->n_mol = n_mol;
     setup_geo(s);
+    if (!s->a.G.use_cells && s->cap > 8192) {
+        delete s;
+        return fail(H4D_EINVAL, "a box with fewer than 3 list cells per edge is limited to 8192 atoms");
+    }
+    {
+        int L = params->lanes_per_atom;
+        if (L == 0) L = n_atoms <= 16384 ? 16 : (n_atoms <= 65536 ? 8 : 4);
+        s->a.lanes = L;
+        s->a.lanes_log2 = L == 4 ? 2 : (L == 8 ? 3 : 4);
+    }
     initial_capacities(s, n_atoms);
     KArgs &a = s->a;
     a.cap = s->cap;
@@ -409,16 +568,17 @@ int32_t h4d_init_system(const h4d_params *params, int32_t n_atoms, int32_t n_sal
     a.n_steps_max = params->n_steps_max;
     a.cation_type = params->cation_type;
     a.anion_type = params->anion_type;
-    s->partial_blocks = blocks_for(s->cap + 2) + 1;   // every grid of the trial fits
+    s->partial_blocks = atom_blocks_l(s->cap + 2, kMaxLanes) + 1;   // every energy grid fits
     const size_t C = (size_t)s->cap;
     PairCoef *coef_d = nullptr;
     double *mass_d = nullptr;
-    if ((rc = s->alloc(&a.pos[0], C)) || (rc = s->alloc(&a.pos[1], C)) || (rc = s->alloc(&a.fx[0], C)) ||
-        (rc = s->alloc(&a.fx[1], C)) || (rc = s->alloc(&a.vel, C)) || (rc = s->alloc(&a.pos0, C)) ||
-        (rc = s->alloc(&a.posb, C)) || (rc = s->alloc(&a.force, C)) || (rc = s->alloc(&a.tag, C)) ||
-        (rc = s->alloc(&a.type, C)) || (rc = s->alloc(&a.mol, C)) || (rc = s->alloc(&a.tpos, C)) ||
+    if ((rc = s->alloc(&a.cpos, C)) || (rc = s->alloc(&a.ctag, C)) || (rc = s->alloc(&a.ctype, C)) ||
+        (rc = s->alloc(&a.cmol, C)) || (rc = s->alloc(&a.pos[0], C)) || (rc = s->alloc(&a.pos[1], C)) ||
+        (rc = s->alloc(&a.fx[0], C)) || (rc = s->alloc(&a.fx[1], C)) || (rc = s->alloc(&a.vel[0], C)) ||
+        (rc = s->alloc(&a.vel[1], C)) || (rc = s->alloc(&a.perm, C)) || (rc = s->alloc(&a.wmol, C)) ||
+        (rc = s->alloc(&a.posb, C)) || (rc = s->alloc(&a.force, C)) || (rc = s->alloc(&a.tpos, C)) ||
         (rc = s->alloc(&a.ttag, C)) || (rc = s->alloc(&a.ttype, C)) || (rc = s->alloc(&a.tmol, C)) ||
-        (rc = s->alloc(&a.nnbr, C)) || (rc = s->alloc(&a.partial, (size_t)s->partial_blocks * 4)) ||
+        (rc = s->alloc(&a.nnbr, C)) || (rc = s->alloc(&a.partial, (size_t)s->partial_blocks * 5)) ||
         (rc = s->alloc(&a.ctl, 1)) || (rc = s->alloc(&a.rec, 1)) ||
         (rc = s->alloc(&coef_d, (size_t)kMaxTypes * kMaxTypes)) || (rc = s->alloc(&mass_d, kMaxTypes)) ||
         (rc = alloc_lists(s))) {
@@ -459,10 +619,10 @@ int32_t h4d_init_system(const h4d_params *params, int32_t n_atoms, int32_t n_sal
         return fail(H4D_EHIP, "upload failed");                                                       \
     }
     if (n_atoms > 0) {
-        UPLOAD(a.pos[0], hp.data(), sizeof(double4) * n_atoms);
-        UPLOAD(a.type, type, sizeof(int) * n_atoms);
-        UPLOAD(a.mol, hm.data(), sizeof(int) * n_atoms);
-        UPLOAD(a.tag, tag, sizeof(long long) * n_atoms);
+        UPLOAD(a.cpos, hp.data(), sizeof(double4) * n_atoms);
+        UPLOAD(a.ctype, type, sizeof(int) * n_atoms);
+        UPLOAD(a.cmol, hm.data(), sizeof(int) * n_atoms);
+        UPLOAD(a.ctag, tag, sizeof(long long) * n_atoms);
     }
     UPLOAD(a.ctl, &c, sizeof(Ctl));
     UPLOAD(coef_d, s->coef_h, sizeof(s->coef_h));
@@ -484,7 +644,7 @@ int32_t h4d_init_system(const h4d_params *params, int32_t n_atoms, int32_t n_sal
 int32_t h4d_build_neighbors(h4d_system *s) {
     if (!s) return fail(H4D_EINVAL, "null handle");
     for (int attempt = 0; attempt < 8; ++attempt) {
-        int rc = rebuild(s, 0, 0, blocks_for(s->n_host));
+        int rc = sort_in(s, s->n_host, s->stream);
         if (rc) return rc;
         if ((rc = read_ctl(s))) return rc;
         const unsigned err = s->h_ctl->err;
@@ -532,16 +692,23 @@ int32_t h4d_get_state(h4d_system *s, int32_t cap, int32_t *n, int32_t *n_salt, d
     if ((pos || vel || type || mol || tag) && cap < nn) return fail(H4D_EINVAL, "cap smaller than the atom count");
     std::vector<double4> buf(std::max(1, nn));
     if (pos && nn) {
-        HIPC(hipMemcpy(buf.data(), s->a.pos[0], sizeof(double4) * nn, hipMemcpyDeviceToHost));
+        HIPC(hipMemcpy(buf.data(), s->a.cpos, sizeof(double4) * nn, hipMemcpyDeviceToHost));
         for (int i = 0; i < nn; ++i) { pos[3 * i] = buf[i].x; pos[3 * i + 1] = buf[i].y; pos[3 * i + 2] = buf[i].z; }
     }
     if (vel && nn) {
-        HIPC(hipMemcpy(buf.data(), s->a.vel, sizeof(double4) * nn, hipMemcpyDeviceToHost));
-        for (int i = 0; i < nn; ++i) { vel[3 * i] = buf[i].x; vel[3 * i + 1] = buf[i].y; vel[3 * i + 2] = buf[i].z; }
+        // velocities are those of the last trajectory's end, in canonical order
+        std::vector<int> perm(nn);
+        HIPC(hipMemcpy(perm.data(), s->a.perm, sizeof(int) * nn, hipMemcpyDeviceToHost));
+        HIPC(hipMemcpy(buf.data(), s->a.vel[s->last_buf], sizeof(double4) * nn, hipMemcpyDeviceToHost));
+        for (int w = 0; w < nn; ++w) {
+            const int i = perm[w];
+            if (i < 0 || i >= nn) continue;
+            vel[3 * i] = buf[w].x; vel[3 * i + 1] = buf[w].y; vel[3 * i + 2] = buf[w].z;
+        }
     }
-    if (type && nn) HIPC(hipMemcpy(type, s->a.type, sizeof(int) * nn, hipMemcpyDeviceToHost));
-    if (mol && nn) HIPC(hipMemcpy(mol, s->a.mol, sizeof(int) * nn, hipMemcpyDeviceToHost));
-    if (tag && nn) HIPC(hipMemcpy(tag, s->a.tag, sizeof(long long) * nn, hipMemcpyDeviceToHost));
+    if (type && nn) HIPC(hipMemcpy(type, s->a.ctype, sizeof(int) * nn, hipMemcpyDeviceToHost));
+    if (mol && nn) HIPC(hipMemcpy(mol, s->a.cmol, sizeof(int) * nn, hipMemcpyDeviceToHost));
+    if (tag && nn) HIPC(hipMemcpy(tag, s->a.ctag, sizeof(long long) * nn, hipMemcpyDeviceToHost));
     return H4D_OK;
 }
 
@@ -549,26 +716,12 @@ int32_t h4d_get_state(h4d_system *s, int32_t cap, int32_t *n, int32_t *n_salt, d
 
 namespace {
 
-__global__ void k_set_fly(KArgs a, int i, int on) {
-    double4 p = a.pos[0][i];
-    int m = meta_of(p);
-    m = on ? (m | kFlyBit) : (m & ~kFlyBit);
-    a.pos[0][i] = with_meta(p.x, p.y, p.z, m);
-}
-
-__global__ __launch_bounds__(kBlock) void k_refresh_fx(KArgs a) {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= a.ctl->n_all) return;
-    const double4 p = a.pos[0][i];
-    a.fx[0][i] = make_uint4(to_fixed(p.x, a.G.fx_inv[0]), to_fixed(p.y, a.G.fx_inv[1]),
-                            to_fixed(p.z, a.G.fx_inv[2]), (unsigned)meta_of(p));
-}
-
+// FP64 energies of the working buffer-0 state (after sort_in).
 int energies(h4d_system *s, int mode, double w, double out[4]) {
     KArgs &a = s->a;
-    const int G = blocks_for(s->n_host);
-    hipLaunchKernelGGL(k_energy, dim3(G), dim3(kBlock), 0, s->stream, a, 2, mode, w, 0);
-    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kBlock), 0, s->stream, a, 2, G);
+    const int GA = atom_blocks_l(s->n_host, a.lanes);
+    hipLaunchKernelGGL(k_energy, dim3(GA), dim3(kBlock), 0, s->stream, a, 2, mode, w, 0);
+    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kBlock), 0, s->stream, a, 2, GA);
     HIPC(hipGetLastError());
     int rc = read_ctl(s);
     if (rc) return rc;
@@ -589,16 +742,12 @@ int32_t h4d_forces_at(h4d_system *s, const int32_t flying[2], double w, double *
     for (int q = 0; q < 2; ++q)
         if (flying[q] < -1 || flying[q] >= n) return fail(H4D_EINVAL, "flying index out of range");
     KArgs &a = s->a;
-    const int G = blocks_for(n);
     for (int q = 0; q < 2; ++q)
         if (flying[q] >= 0) hipLaunchKernelGGL(k_set_fly, dim3(1), dim3(1), 0, s->stream, a, flying[q], 1);
-    hipLaunchKernelGGL(k_refresh_fx, dim3(G), dim3(kBlock), 0, s->stream, a);
     int rc = h4d_build_neighbors(s);
     if (rc) return rc;
-    if (s->p.precision == H4D_PREC_FP32)
-        hipLaunchKernelGGL(k_forces<1>, dim3(G), dim3(kBlock), 0, s->stream, a, w);
-    else
-        hipLaunchKernelGGL(k_forces<0>, dim3(G), dim3(kBlock), 0, s->stream, a, w);
+    if (s->p.precision == H4D_PREC_FP32) launch_forces<1>(s, atom_blocks_l(n, a.lanes), w);
+    else launch_forces<0>(s, atom_blocks_l(n, a.lanes), w);
     HIPC(hipGetLastError());
     double e[4];
     if ((rc = energies(s, 0, w, e))) return rc;
@@ -622,7 +771,9 @@ int32_t h4d_forces_at(h4d_system *s, const int32_t flying[2], double w, double *
 int32_t h4d_sample_observables(h4d_system *s, h4d_observables *out) {
     if (!s || !out) return fail(H4D_EINVAL, "null argument");
     double e[4];
-    int rc = energies(s, 0, 0.0, e);
+    int rc = h4d_build_neighbors(s);
+    if (rc) return rc;
+    if ((rc = energies(s, 0, 0.0, e))) return rc;
     if (rc) return rc;
     std::memset(out, 0, sizeof(*out));
     const Ctl *c = s->h_ctl;
@@ -648,7 +799,9 @@ int32_t h4d_sample_observables(h4d_system *s, h4d_observables *out) {
 
 int32_t h4d_set_timing(h4d_system *s, int32_t on) {
     if (!s) return fail(H4D_EINVAL, "null handle");
+    if ((on != 0) != s->timing) s->drop_graphs();
     s->timing = on != 0;
+    s->retries = 0;
     s->step_launches = 0;
     s->step_ms = 0.0;
     return H4D_OK;
@@ -670,6 +823,51 @@ int32_t h4d_get_timing(h4d_system *s, h4d_timing *out) {
     out->mean_nbr = s->n_host > 0 ? (double)sum / (double)s->n_host : 0.0;
     out->rebuild_every = s->rebuild_every;
     out->nbr_cap = s->a.nbr_cap;
+    out->lanes = s->a.lanes;
+    out->cell_cap = s->a.cell_cap;
+    out->retries = s->retries;
+    return H4D_OK;
+}
+
+}  // extern "C"
+
+namespace {
+__global__ __launch_bounds__(kBlock) void k_stream_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                                        size_t n) {
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
+        dst[i] = src[i];
+}
+}  // namespace
+
+extern "C" {
+
+int32_t h4d_stream_copy(int64_t bytes, int32_t reps, double *ms) {
+    if (bytes <= 0 || bytes % 16 || reps < 1 || !ms) return fail(H4D_EINVAL, "bytes must be a positive multiple of 16");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(H4D_ENODEV, "no HIP device");
+    void *a = nullptr, *b = nullptr;
+    if (hipMalloc(&a, bytes) != hipSuccess) return fail(H4D_ENOMEM, "hipMalloc failed");
+    if (hipMalloc(&b, bytes) != hipSuccess) { (void)hipFree(a); return fail(H4D_ENOMEM, "hipMalloc failed"); }
+    const size_t n = (size_t)bytes / 16;
+    const int grid = (int)std::min<size_t>((n + kBlock - 1) / kBlock, 256 * 64);
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    (void)hipMemset(a, 1, bytes);
+    hipLaunchKernelGGL(k_stream_copy, dim3(grid), dim3(kBlock), 0, nullptr, (const uint4 *)a, (uint4 *)b, n);
+    (void)hipEventRecord(e0, nullptr);
+    for (int r = 0; r < reps; ++r)
+        hipLaunchKernelGGL(k_stream_copy, dim3(grid), dim3(kBlock), 0, nullptr, (const uint4 *)a, (uint4 *)b, n);
+    (void)hipEventRecord(e1, nullptr);
+    const hipError_t e = hipEventSynchronize(e1);
+    float t = 0.f;
+    (void)hipEventElapsedTime(&t, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(a);
+    (void)hipFree(b);
+    if (e != hipSuccess) return fail(H4D_EHIP, std::string("stream copy: ") + hipGetErrorString(e));
+    *ms = t / reps;
     return H4D_OK;
 }
 

@@ -31,7 +31,7 @@ class Params(C.Structure):
         ("n_types", C.c_int32), ("cation_type", C.c_int32), ("anion_type", C.c_int32),
         ("n_steps", C.c_int32), ("n_steps_min", C.c_int32), ("n_steps_max", C.c_int32),
         ("water", C.c_int32), ("precision", C.c_int32), ("capacity", C.c_int32),
-        ("rebuild_every", C.c_int32),
+        ("rebuild_every", C.c_int32), ("lanes_per_atom", C.c_int32), ("reserved0", C.c_int32),
         ("mass", C.c_double * MAX_TYPES), ("charge", C.c_double * MAX_TYPES),
         ("sigma", C.c_double * MAX_TYPES), ("eps", C.c_double * MAX_TYPES),
         ("box", C.c_double * 3),
@@ -72,8 +72,9 @@ class Observables(C.Structure):
 
 
 class Timing(C.Structure):
-    _fields_ = [("step_launches", C.c_int64), ("step_ms", C.c_double), ("mean_nbr", C.c_double),
-                ("rebuild_every", C.c_int32), ("nbr_cap", C.c_int32)]
+    _fields_ = [("step_launches", C.c_int64), ("retries", C.c_int64), ("step_ms", C.c_double),
+                ("mean_nbr", C.c_double), ("rebuild_every", C.c_int32), ("nbr_cap", C.c_int32),
+                ("lanes", C.c_int32), ("cell_cap", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -114,8 +115,9 @@ def lib() -> C.CDLL:
                                     C.POINTER(C.c_double)]
         L.h4d_destroy.argtypes = [vp]
         L.h4d_set_timing.argtypes = [vp, C.c_int32]
+        L.h4d_stream_copy.argtypes = [C.c_int64, C.c_int32, C.POINTER(C.c_double)]
         L.h4d_get_timing.argtypes = [vp, C.POINTER(Timing)]
-        for name in ("h4d_set_timing", "h4d_get_timing", "h4d_init_system", "h4d_build_neighbors", "h4d_run_nemd_trial", "h4d_run_trials",
+        for name in ("h4d_stream_copy", "h4d_set_timing", "h4d_get_timing", "h4d_init_system", "h4d_build_neighbors", "h4d_run_nemd_trial", "h4d_run_trials",
                      "h4d_sample_observables", "h4d_get_state", "h4d_set_trial_index", "h4d_forces_at",
                      "h4d_destroy"):
             getattr(L, name).restype = C.c_int32
@@ -139,6 +141,7 @@ def make_params(d: dict) -> Params:
     p.precision = PREC_FP32 if prec in ("fp32", PREC_FP32) else PREC_FP64
     p.capacity = d.get("capacity", 0)
     p.rebuild_every = d.get("rebuild_every", 0)
+    p.lanes_per_atom = d.get("lanes_per_atom", 0)
     for name in ("mass", "charge", "sigma", "eps"):
         arr = getattr(p, name)
         for i, v in enumerate(d[name]):
@@ -163,6 +166,13 @@ def current_stream():
     except Exception:
         pass
     return None
+
+
+def stream_copy(nbytes: int, reps: int = 20) -> float:
+    """Mean time (ms) of a plain device copy of nbytes (read + write)."""
+    ms = C.c_double()
+    _check(lib().h4d_stream_copy(nbytes, reps, C.byref(ms)))
+    return ms.value
 
 
 class System:

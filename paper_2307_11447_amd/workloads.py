@@ -57,7 +57,7 @@ def _base_lj_params(L: float) -> dict:
         rc_lj=2.5, rc_coul=4.0, alpha=0.3, coulomb_k=3.0,
         beta_mu=0.0, lambda_s=1.0, n_steps=100, n_steps_min=0, n_steps_max=0,
         water=0, d_oh=0.0, d_hh=0.0, accel=1.0,
-        seed=1000, stream=0, skin=0.3, precision="fp64",
+        seed=1000, stream=0, skin=0.5, precision="fp64",
     )
 
 
