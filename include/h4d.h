@@ -50,7 +50,7 @@ extern "C" {
 #define H4D_ENOMEM     -2   /* device allocation failed                        */
 #define H4D_EHIP       -3   /* a HIP runtime call failed                       */
 #define H4D_ECAPACITY  -4   /* atom capacity exhausted                         */
-#define H4D_ENONFINITE -5   /* NaN energy; the state was rolled back           */
+#define H4D_ENONFINITE -5   /* reserved: non-finite trials are rejected instead */
 #define H4D_ENODEV     -6   /* no usable gfx950 device                         */
 
 /* Trial moves. */
@@ -66,7 +66,8 @@ extern "C" {
 
 /* Trial flags. */
 #define H4D_FLAG_EMPTY     0x1u  /* deletion drawn with no pair present: rejected */
-#define H4D_FLAG_NONFINITE 0x2u  /* dH not finite: rejected                       */
+#define H4D_FLAG_NONFINITE 0x2u  /* dH not finite (a violent overlap blew up the
+                                    trajectory): rejected, state rolled back      */
 #define H4D_FLAG_RETRIED   0x4u  /* the trial was recomputed after a list resize   */
 
 /*

@@ -337,12 +337,13 @@ int or_constrain_positions(const or_params *p, or_state *s, const double *xref)
         int a[3], b[3];
         double d[3], corr[9] = {0};
         bond_list(p, m, a, b, d);
-        double xl[9];  /* local unwrapped copy, relative to the oxygen */
+        /* local unwrapped copy relative to the oxygen: O(1) magnitudes keep
+         * the rounding of |s|^2 far below the convergence tolerance */
+        double xl[9];
         const int o = 3 * m;
         for (int k = 0; k < 3; ++k)
             for (int c = 0; c < 3; ++c)
-                xl[3 * k + c] = s->x[3 * o + c] +
-                    (k ? minimg(s->x[3 * (o + k) + c] - s->x[3 * o + c], p->box[c]) : 0.0);
+                xl[3 * k + c] = k ? minimg(s->x[3 * (o + k) + c] - s->x[3 * o + c], p->box[c]) : 0.0;
         int it;
         for (it = 0; it < 1000; ++it) {
             int done = 1;
@@ -356,7 +357,7 @@ int or_constrain_positions(const or_params *p, or_state *s, const double *xref)
                     sr += sv[c] * rr[c];
                 }
                 const double diff = d[q] * d[q] - ss;
-                if (fabs(diff) > 1e-14 * d[q] * d[q]) done = 0;
+                if (fabs(diff) > 1e-13 * d[q] * d[q]) done = 0;
                 const double ima = 1.0 / p->mass[s->type[a[q]]], imb = 1.0 / p->mass[s->type[b[q]]];
                 const double gq = diff / (2.0 * sr * (ima + imb));
                 for (int c = 0; c < 3; ++c) {
@@ -622,6 +623,18 @@ int or_trial(const or_params *p, or_state *s, uint64_t trial, int force_move,
     memcpy(x0, s->x, 3 * (size_t)s->n * sizeof(double));
     double W = 0.0;
     int rc = or_nemd(p, s, move, nf, &W);
+    if (rc == -2) {
+        /* the rigid-water constraints could not be met (a violent overlap):
+         * the trial has no finite outcome and is rejected */
+        memcpy(s->x, x0, 3 * (size_t)n_orig * sizeof(double));
+        if (move > 0) s->n = n_orig;
+        else { s->flying[ic] = 0; s->flying[ia] = 0; }
+        rec->dH = NAN;
+        rec->flags |= OR_FLAG_NONFINITE;
+        rec->ln_ratio = NAN;
+        free(x0);
+        return 0;
+    }
     if (rc) { free(x0); return -6; }
 
     if (move > 0) or_compute(p, s, 0.0, OR_MODE_NEMD, NULL, &e);

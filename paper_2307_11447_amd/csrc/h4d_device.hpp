@@ -16,6 +16,7 @@ constexpr int kWave = 64;            // gfx950 wavefront
 constexpr int kTypeMask = 0xF;
 constexpr int kFlyBit = 0x10;
 constexpr int kFastBit = 0x20;       // moved beyond half the skin since the list build
+constexpr int kMolBit = 0x40;        // belongs to a rigid 3-site water
 constexpr int kFastCap = 256;        // capacity of the fast-atom list
 
 // error bits of the control block
@@ -76,6 +77,10 @@ struct Geo {
     int n_types;
     int water;
     double d_oh, d_hh;
+    // rigid water: masses and the canonical triangle about its centre of mass
+    // (O at (0, ra), H at (-rc_w, -rb) and (rc_w, -rb))
+    double m_o, m_h, ra, rb, rc_w;
+    int n_mol;
 };
 
 // per type-pair coefficients, indexed ti * kMaxTypes + tj

@@ -75,6 +75,8 @@ struct KArgs {
     int *nbr, *nnbr;
     int *cell_cnt[2], *cell_atoms[2], *cell_off;
     int *fast;                // 3 lists of kFastCap working indices
+    int *molw;                // water atom (canonical 3m + q) -> working index
+    double4 *fw;              // forces on water atoms (working order)
     double *partial;          // per-block FP64 partial sums, 4 per block
     Ctl *ctl;
     TrialRec *rec;
@@ -297,15 +299,18 @@ __global__ __launch_bounds__(kWave) void k_gather_in(KArgs a, int cb) {
     for (int s = threadIdx.x; s < cnt; s += kWave) {
         const int src = row[s];
         const int w = off + s;
-        const double4 p = a.cpos[src];
-        const int meta = meta_of(p);
+        const double4 p0 = a.cpos[src];
+        const int mol = a.cmol[src];
+        const int meta = meta_of(p0) | (mol >= 0 ? kMolBit : 0);
         const int ty = meta & kTypeMask;
+        const double4 p = with_meta(p0.x, p0.y, p0.z, meta);
         a.pos[0][w] = p;
+        if (mol >= 0) a.molw[src] = w;
         const uint4 q = fixed_of(a.G, p.x, p.y, p.z, meta);
         a.posb[w] = q;
         a.fx[0][w] = q;
         a.perm[w] = src;
-        a.wmol[w] = a.cmol[src];
+        a.wmol[w] = mol;
         const u64x4 r = philox(t, kPurposeMB, (uint64_t)a.ctag[src], 0, a.seed, a.stream);
         const double u0 = unit_open(r.v[0]), u1 = unit_open(r.v[1]);
         const double u2 = unit_open(r.v[2]), u3 = unit_open(r.v[3]);
@@ -539,6 +544,10 @@ __device__ __forceinline__ void group_force(const KArgs &a, const CoefLds &cf, i
     constexpr int A = kWave / L;
     const int ti = mi & kTypeMask;
     const bool own_fast = (mi & kFastBit) != 0;
+    // molecule of this atom for the exclusions on the fast paths (the Verlet
+    // list already leaves intramolecular pairs out)
+    const int own_mol = (mi & kMolBit) ? a.wmol[w] : -1;
+    auto same_mol = [&](int j) { return own_mol >= 0 && a.wmol[j] == own_mol; };
     const PairCoef *crow = cf.c + ti * kMaxTypes;
     const int nx = a.G.ncell[0], ny = a.G.ncell[1], nz = a.G.ncell[2];
     if (PREC == 1) {
@@ -585,19 +594,19 @@ __device__ __forceinline__ void group_force(const KArgs &a, const CoefLds &cf, i
                 for (int u = s; u < m; u += L) {
                     const int j = row[u];
                     const uint4 qj = F[j];
-                    pair(qj, j != w && !(qj.w & kFastBit));
+                    pair(qj, j != w && !(qj.w & kFastBit) && !same_mol(j));
                 }
             }
         } else {
             const int n_all = a.ctl->n_all;
             for (int j = s; j < n_all; j += L) {
                 const uint4 qj = F[j];
-                pair(qj, j != w && !(qj.w & kFastBit));
+                pair(qj, j != w && !(qj.w & kFastBit) && !same_mol(j));
             }
         }
         for (int q = s; q < nfast; q += L) {
             const int j = flist[q];
-            pair(F[j], j != w);
+            pair(F[j], j != w && !same_mol(j));
         }
 #pragma unroll
         for (int off = L / 2; off > 0; off >>= 1) {
@@ -643,19 +652,19 @@ __device__ __forceinline__ void group_force(const KArgs &a, const CoefLds &cf, i
                 for (int u = s; u < m; u += L) {
                     const int j = row[u];
                     const double4 pj = P[j];
-                    pair(pj, j != w && !(meta_of(pj) & kFastBit));
+                    pair(pj, j != w && !(meta_of(pj) & kFastBit) && !same_mol(j));
                 }
             }
         } else {
             const int n_all = a.ctl->n_all;
             for (int j = s; j < n_all; j += L) {
                 const double4 pj = P[j];
-                pair(pj, j != w && !(meta_of(pj) & kFastBit));
+                pair(pj, j != w && !(meta_of(pj) & kFastBit) && !same_mol(j));
             }
         }
         for (int q = s; q < nfast; q += L) {
             const int j = flist[q];
-            pair(P[j], j != w);
+            pair(P[j], j != w && !same_mol(j));
         }
 #pragma unroll
         for (int off = L / 2; off > 0; off >>= 1) {
@@ -790,6 +799,10 @@ __global__ __launch_bounds__(kBlock) void k_step(KArgs a, int k, int b, int bin,
     double fx = 0.0, fy = 0.0, fz = 0.0;
     if (act && !fly) group_force<PREC, L>(a, cf, b, cl, wc, s, pi, mi, wv, gscr, flist, nfast, fx, fy, fz);
     if (!act || s != 0) return;
+    if (mi & kMolBit) {   // rigid water: integrated by k_settle
+        a.fw[wc] = make_double4(fx, fy, fz, 0.0);
+        return;
+    }
     double4 v = a.vel[b][wc];
     double x = pi.x, y = pi.y, z = pi.z;
     int mo = mi;
@@ -1005,7 +1018,7 @@ __global__ __launch_bounds__(kBlock) void k_commit(KArgs a, int bf) {
     if (c->accepted) {
         if (i < c->n_all) {
             const double4 p = a.pos[bf][i];
-            a.cpos[a.perm[i]] = with_meta(p.x, p.y, p.z, meta_of(p) & ~kFlyBit);
+            a.cpos[a.perm[i]] = with_meta(p.x, p.y, p.z, meta_of(p) & kTypeMask);
         }
     } else if (move < 0 && i == 0) {
         double4 p = a.cpos[c->ic];
@@ -1069,6 +1082,164 @@ __global__ void k_set_fly(KArgs a, int i, int on) {
     int m = meta_of(p);
     m = on ? (m | kFlyBit) : (m & ~kFlyBit);
     a.cpos[i] = with_meta(p.x, p.y, p.z, m);
+}
+
+// ==========================================================================
+// Rigid water.  Velocity constraint (RATTLE): remove from the three atoms'
+// velocities the components that would change a bond length, by solving the
+// 3x3 system for the multipliers of the bonds O-H1, O-H2, H1-H2 (Cramer).
+// Positions (SETTLE): the constrained triangle is the rigid canonical one
+// with the centre of mass of the unconstrained positions, the same
+// components normal to the old plane (the corrections act along old bonds),
+// and no torque of the corrections about the old positions; those fix the
+// two tilts and the in-plane angle in closed form.
+// ==========================================================================
+struct d3 { double x, y, z; };
+__device__ __forceinline__ d3 mk(double x, double y, double z) { d3 r; r.x = x; r.y = y; r.z = z; return r; }
+__device__ __forceinline__ d3 operator+(d3 a, d3 b) { return mk(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ __forceinline__ d3 operator-(d3 a, d3 b) { return mk(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ d3 operator*(double s, d3 a) { return mk(s * a.x, s * a.y, s * a.z); }
+__device__ __forceinline__ double dot(d3 a, d3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ d3 cross(d3 a, d3 b) {
+    return mk(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ d3 unit(d3 a) { return (1.0 / sqrt(dot(a, a))) * a; }
+
+__device__ __forceinline__ void rattle_velocities(const Geo &G, const d3 &a, const d3 &b, const d3 &c,
+                                                  d3 &va, d3 &vb, d3 &vc) {
+    const double io = 1.0 / G.m_o, ih = 1.0 / G.m_h;
+    const d3 rab = a - b, rac = a - c, rbc = b - c;
+    const double M11 = (io + ih) * dot(rab, rab), M12 = io * dot(rac, rab), M13 = -ih * dot(rbc, rab);
+    const double M21 = io * dot(rab, rac), M22 = (io + ih) * dot(rac, rac), M23 = ih * dot(rbc, rac);
+    const double M31 = -ih * dot(rab, rbc), M32 = ih * dot(rac, rbc), M33 = 2.0 * ih * dot(rbc, rbc);
+    const double r1 = -dot(va - vb, rab), r2 = -dot(va - vc, rac), r3 = -dot(vb - vc, rbc);
+    const double det = M11 * (M22 * M33 - M23 * M32) - M12 * (M21 * M33 - M23 * M31) + M13 * (M21 * M32 - M22 * M31);
+    const double l1 = (r1 * (M22 * M33 - M23 * M32) - M12 * (r2 * M33 - M23 * r3) + M13 * (r2 * M32 - M22 * r3)) / det;
+    const double l2 = (M11 * (r2 * M33 - M23 * r3) - r1 * (M21 * M33 - M23 * M31) + M13 * (M21 * r3 - r2 * M31)) / det;
+    const double l3 = (M11 * (M22 * r3 - r2 * M32) - M12 * (M21 * r3 - r2 * M31) + r1 * (M21 * M32 - M22 * M31)) / det;
+    va = va + io * (l1 * rab + l2 * rac);
+    vb = vb + ih * (l3 * rbc - l1 * rab);
+    vc = vc - ih * (l2 * rac + l3 * rbc);
+}
+
+// old: a0, b0, c0 (constrained); in/out: a1, b1, c1 (unconstrained -> constrained)
+__device__ __forceinline__ void settle_positions(const Geo &G, const d3 &a0, const d3 &b0, const d3 &c0,
+                                                 d3 &a1, d3 &b1, d3 &c1) {
+    const double mo = G.m_o, mh = G.m_h, Mt = mo + 2.0 * mh;
+    // frame of the old molecule: x from H1 to H2, y towards O, z normal
+    const d3 ex = unit(c0 - b0);
+    d3 ey = a0 - 0.5 * (b0 + c0);
+    ey = unit(ey - dot(ey, ex) * ex);
+    const d3 ez = cross(ex, ey);
+    const d3 d0 = (1.0 / Mt) * (mo * a0 + mh * (b0 + c0));
+    const d3 d1 = (1.0 / Mt) * (mo * a1 + mh * (b1 + c1));
+    const d3 A0 = a0 - d0, B0 = b0 - d0, C0 = c0 - d0;
+    const d3 A1 = a1 - d1, B1 = b1 - d1, C1 = c1 - d1;
+    const double X0[3] = {dot(A0, ex), dot(B0, ex), dot(C0, ex)};
+    const double Y0[3] = {dot(A0, ey), dot(B0, ey), dot(C0, ey)};
+    const double X1[3] = {dot(A1, ex), dot(B1, ex), dot(C1, ex)};
+    const double Y1[3] = {dot(A1, ey), dot(B1, ey), dot(C1, ey)};
+    const double zA = dot(A1, ez), zB = dot(B1, ez), zC = dot(C1, ez);
+    const double ra = G.ra, rb = G.rb, rc = G.rc_w;
+    const double sphi = zA / ra, cphi = sqrt(fmax(0.0, 1.0 - sphi * sphi));
+    const double spsi = (zB - zC) / (2.0 * rc * cphi), cpsi = sqrt(fmax(0.0, 1.0 - spsi * spsi));
+    // canonical triangle tilted about y (psi) then x (phi)
+    const double Qx[3] = {0.0, -rc * cpsi, rc * cpsi};
+    const double Qy[3] = {ra * cphi, -rb * cphi - rc * spsi * sphi, -rb * cphi + rc * spsi * sphi};
+    const double Qz[3] = {ra * sphi, -rb * sphi + rc * spsi * cphi, -rb * sphi - rc * spsi * cphi};
+    const double m[3] = {mo, mh, mh};
+    double al = 0.0, be = 0.0, ga = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        al += m[i] * (X0[i] * Qx[i] + Y0[i] * Qy[i]);
+        be += m[i] * (X0[i] * Qy[i] - Y0[i] * Qx[i]);
+        ga += m[i] * (X0[i] * Y1[i] - Y0[i] * X1[i]);
+    }
+    const double n2 = al * al + be * be;
+    const double sd = sqrt(fmax(0.0, n2 - ga * ga));
+    const double sth = (al * ga - be * sd) / n2, cth = (be * ga + al * sd) / n2;
+    d3 out[3];
+    for (int i = 0; i < 3; ++i) {
+        const double px = Qx[i] * cth - Qy[i] * sth, py = Qx[i] * sth + Qy[i] * cth;
+        out[i] = d1 + px * ex + py * ey + Qz[i] * ez;
+    }
+    a1 = out[0]; b1 = out[1]; c1 = out[2];
+}
+
+__device__ __forceinline__ d3 unwrap_near(const Geo &G, const double4 &p, const d3 &ref) {
+    return mk(ref.x + min_image(p.x - ref.x, G.L[0]), ref.y + min_image(p.y - ref.y, G.L[1]),
+              ref.z + min_image(p.z - ref.z, G.L[2]));
+}
+
+// trial start: project the freshly drawn water velocities (working buffer 0)
+__global__ __launch_bounds__(kBlock) void k_rattle_mb(KArgs a) {
+    const int m = blockIdx.x * kBlock + threadIdx.x;
+    if (m >= a.G.n_mol) return;
+    const int w[3] = {a.molw[3 * m], a.molw[3 * m + 1], a.molw[3 * m + 2]};
+    const double4 pa = a.pos[0][w[0]];
+    const d3 ra_ = mk(pa.x, pa.y, pa.z);
+    const d3 x1 = unwrap_near(a.G, a.pos[0][w[1]], ra_), x2 = unwrap_near(a.G, a.pos[0][w[2]], ra_);
+    double4 v4[3] = {a.vel[0][w[0]], a.vel[0][w[1]], a.vel[0][w[2]]};
+    d3 v[3];
+    for (int i = 0; i < 3; ++i) v[i] = mk(v4[i].x, v4[i].y, v4[i].z);
+    rattle_velocities(a.G, ra_, x1, x2, v[0], v[1], v[2]);
+    for (int i = 0; i < 3; ++i) a.vel[0][w[i]] = make_double4(v[i].x, v[i].y, v[i].z, 0.0);
+}
+
+// One step k of the rigid waters (after k_step stored their forces F_k):
+// v_k = v + h F/m and the velocity constraint (k > 0); v += h F/m, drift and
+// position constraint with its velocity correction (k < nf).
+__global__ __launch_bounds__(kBlock) void k_settle(KArgs a, int k, int b, int bin, int cl) {
+    Ctl *c = a.ctl;
+    const int move = c->move, nf = c->nf;
+    if (move == 0 || k > nf) return;
+    const int m = blockIdx.x * kBlock + threadIdx.x;
+    if (m >= a.G.n_mol) return;
+    const Geo &G = a.G;
+    const int w[3] = {a.molw[3 * m], a.molw[3 * m + 1], a.molw[3 * m + 2]};
+    double4 p4[3], v4[3], f4[3];
+    for (int i = 0; i < 3; ++i) { p4[i] = a.pos[b][w[i]]; v4[i] = a.vel[b][w[i]]; f4[i] = a.fw[w[i]]; }
+    const d3 x0[3] = {mk(p4[0].x, p4[0].y, p4[0].z), unwrap_near(G, p4[1], mk(p4[0].x, p4[0].y, p4[0].z)),
+                      unwrap_near(G, p4[2], mk(p4[0].x, p4[0].y, p4[0].z))};
+    d3 v[3];
+    double hm[3];
+    for (int i = 0; i < 3; ++i) {
+        v[i] = mk(v4[i].x, v4[i].y, v4[i].z);
+        hm[i] = G.half_dt * G.accel / a.mass[meta_of(p4[i]) & kTypeMask];
+    }
+    if (k > 0) {
+        for (int i = 0; i < 3; ++i) v[i] = v[i] + hm[i] * mk(f4[i].x, f4[i].y, f4[i].z);
+        rattle_velocities(G, x0[0], x0[1], x0[2], v[0], v[1], v[2]);
+    }
+    d3 x[3] = {x0[0], x0[1], x0[2]};
+    if (k < nf) {
+        d3 xu[3];
+        for (int i = 0; i < 3; ++i) {
+            v[i] = v[i] + hm[i] * mk(f4[i].x, f4[i].y, f4[i].z);
+            xu[i] = x0[i] + G.dt * v[i];
+            x[i] = xu[i];
+        }
+        settle_positions(G, x0[0], x0[1], x0[2], x[0], x[1], x[2]);
+        for (int i = 0; i < 3; ++i) v[i] = v[i] + (1.0 / G.dt) * (x[i] - xu[i]);
+    }
+    const int lw = (k + 1) % 3;
+    for (int i = 0; i < 3; ++i) {
+        const double px = wrap_coord(x[i].x, G.L[0]), py = wrap_coord(x[i].y, G.L[1]), pz = wrap_coord(x[i].z, G.L[2]);
+        int mo = meta_of(p4[i]);
+        uint4 qn = fixed_of(G, px, py, pz, mo);
+        if ((mo & kFastBit) == 0 && moved_beyond_half_skin(a, qn, a.posb[w[i]])) mo |= kFastBit;
+        if (mo & kFastBit) {
+            const int slot = atomicAdd(&c->nfast[lw], 1);
+            if (slot < kFastCap) a.fast[lw * kFastCap + slot] = w[i];
+            else atomicOr(&c->err, kErrFast);
+            atomicMax(&c->max_fast, slot + 1);
+        }
+        qn.w = (unsigned)mo;
+        const double4 pn = with_meta(px, py, pz, mo);
+        a.pos[b ^ 1][w[i]] = pn;
+        a.fx[b ^ 1][w[i]] = qn;
+        a.vel[b ^ 1][w[i]] = make_double4(v[i].x, v[i].y, v[i].z, 0.0);
+        if (bin) bin_atom(a, cl ^ 1, w[i], pn);
+    }
 }
 
 }  // namespace h4d

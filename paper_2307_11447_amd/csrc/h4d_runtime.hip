@@ -129,7 +129,8 @@ int check_params(const h4d_params &p) {
     for (int d = 0; d < 3; ++d)
         if (!(p.box[d] >= 2.0 * rc))
             return fail(H4D_EINVAL, "every box edge must be at least twice the largest cutoff");
-    if (p.water) return fail(H4D_EINVAL, "rigid water is not supported by this build");
+    if (p.water && !(p.d_oh > 0.0 && p.d_hh > 0.0 && p.d_hh < 2.0 * p.d_oh))
+        return fail(H4D_EINVAL, "rigid water needs 0 < d_hh < 2 d_oh");
     return H4D_OK;
 }
 
@@ -295,6 +296,7 @@ int sort_in(h4d_system *s, int n_all_max, hipStream_t st) {
     hipLaunchKernelGGL(k_cell_sort, dim3(nc), dim3(kWave), a.cell_cap * sizeof(int), st, a, 0);
     hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, st, a, 0);
     hipLaunchKernelGGL(k_gather_in, dim3(nc), dim3(kWave), 0, st, a, 0);
+    if (a.G.water) hipLaunchKernelGGL(k_rattle_mb, dim3(blocks_for(a.G.n_mol)), dim3(kBlock), 0, st, a);
     launch_list(s, 0, 0, n_all_max, st);
     s->cl = 0;
     HIPC(hipGetLastError());
@@ -380,6 +382,8 @@ int enqueue_trial(h4d_system *s, int move, hipStream_t st, int nf, int M, bool t
         hipEvent_t e0 = timing ? s->ev[2 * k] : nullptr, e1 = timing ? s->ev[2 * k + 1] : nullptr;
         if (s->p.precision == H4D_PREC_FP32) launch_step<1>(s, st, GA + 1, e0, e1, k, b, bin);
         else launch_step<0>(s, st, GA + 1, e0, e1, k, b, bin);
+        if (a.G.water)
+            hipLaunchKernelGGL(k_settle, dim3(blocks_for(a.G.n_mol)), dim3(kBlock), 0, st, a, k, b, bin, s->cl);
         b ^= 1;
     }
     if (final_rebuild && (rc = rebuild_mid(s, b, n_all_max, st))) return rc;
@@ -495,9 +499,6 @@ int run_one(h4d_system *s, int move, h4d_trial *out) {
         }
         s->N_sum += (double)c->nsalt;
         s->N2_sum += (double)c->nsalt * (double)c->nsalt;
-        if (r.flags & H4D_FLAG_NONFINITE) {
-            if (!(r.dH == r.dH)) return fail(H4D_ENONFINITE, "NaN energy; the trial was rolled back");
-        }
         return H4D_OK;
     }
     return fail(H4D_EHIP, "trial could not be completed after resizing the lists");
@@ -535,6 +536,20 @@ int32_t h4d_init_system(const h4d_params *params, int32_t n_atoms, int32_t n_sal
                 return fail(H4D_EINVAL, "positions must lie in [0, L)");
     }
     if (ncat != n_salt || nan_ != n_salt) return fail(H4D_EINVAL, "n_salt must equal the cation and anion counts");
+    if (params->water) {
+        if (n_mol < 1 || 3 * n_mol > n_atoms || !mol) return fail(H4D_EINVAL, "water = 1 needs n_mol >= 1 waters first");
+        for (int m = 0; m < n_mol; ++m)
+            for (int q = 0; q < 3; ++q) {
+                const int i = 3 * m + q;
+                if (mol[i] != m || type[i] != type[q]) return fail(H4D_EINVAL, "waters must be atoms 3m, 3m+1, 3m+2 (O, H, H) of molecule m");
+            }
+        if (type[1] != type[2] || type[0] == type[1]) return fail(H4D_EINVAL, "water atoms must be O, H, H");
+        for (int i = 3 * n_mol; i < n_atoms; ++i)
+            if (mol[i] >= 0) return fail(H4D_EINVAL, "only the waters may carry molecule ids");
+    } else if (mol) {
+        for (int i = 0; i < n_atoms; ++i)
+            if (mol[i] >= 0) return fail(H4D_EINVAL, "molecule ids need water = 1");
+    }
 
     auto *s = new h4d_system();
     s->p = *params;
@@ -548,6 +563,16 @@ int32_t h4d_init_system(const h4d_params *params, int32_t n_atoms, int32_t n_sal
     s->nsalt_host = n_salt;
     s->n_mol = n_mol;
     setup_geo(s);
+    if (params->water) {
+        Geo &G = s->a.G;
+        G.n_mol = n_mol;
+        G.m_o = params->mass[type[0]];
+        G.m_h = params->mass[type[1]];
+        G.rc_w = 0.5 * params->d_hh;
+        const double h = std::sqrt(params->d_oh * params->d_oh - G.rc_w * G.rc_w);
+        G.ra = 2.0 * G.m_h * h / (G.m_o + 2.0 * G.m_h);
+        G.rb = h - G.ra;
+    }
     if (!s->a.G.use_cells && s->cap > 8192) {
         delete s;
         return fail(H4D_EINVAL, "a box with fewer than 3 list cells per edge is limited to 8192 atoms");
@@ -580,6 +605,7 @@ int32_t h4d_init_system(const h4d_params *params, int32_t n_atoms, int32_t n_sal
         (rc = s->alloc(&a.ttag, C)) || (rc = s->alloc(&a.ttype, C)) || (rc = s->alloc(&a.tmol, C)) ||
         (rc = s->alloc(&a.nnbr, C)) || (rc = s->alloc(&a.partial, (size_t)s->partial_blocks * 5)) ||
         (rc = s->alloc(&a.ctl, 1)) || (rc = s->alloc(&a.rec, 1)) ||
+        (rc = s->alloc(&a.molw, (size_t)std::max(1, 3 * n_mol))) || (rc = s->alloc(&a.fw, C)) ||
         (rc = s->alloc(&coef_d, (size_t)kMaxTypes * kMaxTypes)) || (rc = s->alloc(&mass_d, kMaxTypes)) ||
         (rc = alloc_lists(s))) {
         delete s;

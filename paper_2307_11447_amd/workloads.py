@@ -154,10 +154,13 @@ def _random_rotation(rng: np.random.Generator) -> np.ndarray:
 
 
 def water_nacl(n_water: int = 8000, n_pairs: int = 150, L: float = 62.0, m: int = 21,
-               seed: int = 1004, name: str = "nacl_water") -> Workload:
+               seed: int = 1004, name: str = "nacl_water", tries: int = 24) -> Workload:
     """Rigid SPC/E waters and Na+/Cl- on randomly chosen sites of an m^3
-    lattice, waters randomly oriented.  Atom layout: waters first
-    (O, H, H of molecule k at 3k..3k+2), then the ions; tags ascending."""
+    lattice.  Each water's orientation is the best of `tries` random
+    rotations: the one whose hydrogens stay farthest from the neighbouring
+    occupied sites (hydrogens carry no Lennard-Jones core, so a hydrogen
+    placed against a neighbour would collapse onto it).  Atom layout: waters
+    first (O, H, H of molecule k at 3k..3k+2), then the ions; tags ascending."""
     rng = np.random.default_rng(seed)
     p = _water_params(L)
     p["seed"] = seed
@@ -165,15 +168,28 @@ def water_nacl(n_water: int = 8000, n_pairs: int = 150, L: float = 62.0, m: int 
     if n_water + 2 * n_pairs > m ** 3:
         raise ValueError("lattice too small")
     sites = rng.choice(m ** 3, size=n_water + 2 * n_pairs, replace=False)
-    ijk = np.stack([sites % m, (sites // m) % m, sites // (m * m)], axis=1).astype(np.float64)
-    centers = (ijk + 0.5) * a
+    ijk = np.stack([sites % m, (sites // m) % m, sites // (m * m)], axis=1)
+    centers = (ijk.astype(np.float64) + 0.5) * a
+    occupied = np.full((m, m, m), -1, dtype=np.int64)
+    occupied[ijk[:, 0], ijk[:, 1], ijk[:, 2]] = np.arange(len(sites))
+    shell = np.array([(dx, dy, dz) for dx in (-1, 0, 1) for dy in (-1, 0, 1) for dz in (-1, 0, 1)
+                      if (dx, dy, dz) != (0, 0, 0)])
     half = 0.5 * p["d_hh"]
     h_off = math.sqrt(p["d_oh"] ** 2 - half ** 2)
     body = np.array([[0.0, 0.0, 0.0], [half, h_off, 0.0], [-half, h_off, 0.0]])
     xs, ts, ms = [], [], []
     for k in range(n_water):
-        R = _random_rotation(rng)
-        xs.append(centers[k] + body @ R.T)
+        nb = (ijk[k] + shell) % m
+        occ = occupied[nb[:, 0], nb[:, 1], nb[:, 2]] >= 0
+        rel = shell[occ].astype(np.float64) * a          # neighbouring sites relative to this one
+        best, best_d = None, -1.0
+        for _ in range(tries):
+            R = _random_rotation(rng)
+            hpos = body[1:] @ R.T
+            d = np.min(np.linalg.norm(hpos[:, None, :] - rel[None, :, :], axis=2)) if len(rel) else 9.9
+            if d > best_d:
+                best, best_d = R, d
+        xs.append(centers[k] + body @ best.T)
         ts += [0, 1, 1]
         ms += [k, k, k]
     ion_types = np.array([2] * n_pairs + [3] * n_pairs, dtype=np.int32)
