@@ -69,6 +69,7 @@ extern "C" {
 #define H4D_FLAG_NONFINITE 0x2u  /* dH not finite (a violent overlap blew up the
                                     trajectory): rejected, state rolled back      */
 #define H4D_FLAG_RETRIED   0x4u  /* the trial was recomputed after a list resize   */
+#define H4D_FLAG_IDLE      0x8u  /* internal: a box of a batch with no trial left */
 
 /*
  * Model and protocol.  Types index the per-type tables; pair parameters
@@ -95,7 +96,8 @@ typedef struct h4d_params {
     int32_t n_steps_max;
     int32_t water;
     int32_t precision;          /* H4D_PREC_*                                   */
-    int32_t capacity;           /* maximum atoms (0: n_atoms + 4096)            */
+    int32_t capacity;           /* maximum atoms per box (0: the box's
+                                   n_atoms + max(1024, n_atoms / 8))           */
     int32_t rebuild_every;      /* neighbour-list rebuild interval (0: auto)   */
     int32_t lanes_per_atom;     /* lanes per atom in list traversals: 4, 8, 16
                                    (0: chosen from the atom count)              */
@@ -110,7 +112,8 @@ typedef struct h4d_params {
     double skin;                /* Verlet-list skin                              */
     double d_oh, d_hh;          /* rigid-water geometry                          */
     double accel;               /* acceleration per force/mass                   */
-    uint64_t seed, stream;      /* Philox key                                    */
+    uint64_t seed, stream;      /* Philox key (box b of a batch: seed,
+                                   stream + b)                                  */
 } h4d_params;
 
 /* One trial (move +1 insertion, -1 deletion). */
@@ -155,6 +158,28 @@ int32_t h4d_init_system(const h4d_params *params, int32_t n_atoms, int32_t n_sal
                         const int32_t *mol, const int64_t *tag, void *hip_stream,
                         h4d_system **out);
 
+/*
+ * Create a batch of independent boxes (replicas of uneven size and density)
+ * that run their trials together.  Every box has its own Markov chain: box b
+ * draws its random numbers from Philox key (seed, stream + b), so box b of a
+ * batch reproduces, trial for trial, a single system created with
+ * box = box_edges[3b..3b+2] and stream + b.  Model parameters are shared;
+ * params->box is ignored.
+ *   box_edges[3*n_boxes]   orthorhombic edges of each box (each >= 2 max cutoff);
+ *   n_atoms[n_boxes], n_salt[n_boxes];
+ *   pos, type, tag: the boxes' configurations one after another (box 0's
+ *   n_atoms[0] atoms first), same conventions as h4d_init_system.
+ * Every box must have >= 3 list cells per edge, or every box fewer.  No
+ * rigid water (water = 0).
+ */
+int32_t h4d_init_batch(const h4d_params *params, int32_t n_boxes, const double *box_edges,
+                       const int32_t *n_atoms, const int32_t *n_salt, const double *pos,
+                       const int32_t *type, const int64_t *tag, void *hip_stream,
+                       h4d_system **out);
+
+/* Number of boxes of a handle (1 for h4d_init_system). */
+int32_t h4d_num_boxes(const h4d_system *sys);
+
 /* Rebuild the cell and Verlet lists of the current state (cells of edge
  * >= max cutoff + skin; all pairs when a box edge holds fewer than 3). */
 int32_t h4d_build_neighbors(h4d_system *sys);
@@ -169,20 +194,36 @@ int32_t h4d_build_neighbors(h4d_system *sys);
 int32_t h4d_run_nemd_trial(h4d_system *sys, int32_t move, h4d_trial *out);
 int32_t h4d_run_trials(h4d_system *sys, int32_t n, int32_t move, h4d_trial *out);
 
+/*
+ * Run trials_per_box more trials in every box of a batch.  All boxes run
+ * their current trial in one round of launches (one graph, each box with its
+ * own N_f and move); a box that must recompute a trial after a list resize
+ * does so in the next round while the others go on.  out (host, may be
+ * NULL) receives n_boxes * trials_per_box records, box-major:
+ * out[b * trials_per_box + t].  Also accepts a single-box handle.
+ */
+int32_t h4d_run_batch(h4d_system *sys, int32_t trials_per_box, int32_t move, h4d_trial *out);
+
 /* FP64 energies and virial of the current state, plus the running
- * particle-number statistics of the trials run so far. */
+ * particle-number statistics of the trials run so far (box 0, or box `box`
+ * of a batch). */
 int32_t h4d_sample_observables(h4d_system *sys, h4d_observables *out);
+int32_t h4d_box_observables(h4d_system *sys, int32_t box, h4d_observables *out);
 
 /* Copy the current state to host arrays of length >= cap (positions 3*cap).
  * Any pointer may be NULL.  *n receives the number of atoms. */
 int32_t h4d_get_state(h4d_system *sys, int32_t cap, int32_t *n, int32_t *n_salt,
                       double *pos, double *vel, int32_t *type, int32_t *mol, int64_t *tag);
+/* The same for box `box` of a batch. */
+int32_t h4d_get_box_state(h4d_system *sys, int32_t box, int32_t cap, int32_t *n,
+                          int32_t *n_salt, double *pos, double *vel, int32_t *type,
+                          int32_t *mol, int64_t *tag);
 
-/* Set the next trial index (default 0). */
+/* Set the next trial index of every box (default 0). */
 int32_t h4d_set_trial_index(h4d_system *sys, uint64_t trial);
 
 /*
- * Test hook: forces and FP64 energy of the current state with atoms
+ * Test hook (single-box handles): forces and FP64 energy of the current state with atoms
  * flying[0], flying[1] (-1: none) lifted to altitude w, as in the NEMD pass.
  * forces[3*n] (host) receives F on every non-flying atom (0 on flyers),
  * computed in the handle's precision; energy[3] receives U, U_lj, U_coul.
@@ -210,6 +251,15 @@ typedef struct h4d_timing {
 
 int32_t h4d_set_timing(h4d_system *sys, int32_t on);
 int32_t h4d_get_timing(h4d_system *sys, h4d_timing *out);
+
+/*
+ * Autotuner of the launch shape: runs `trials` trials (per box) with each
+ * lanes-per-atom choice (4, 8, 16) of the list traversals, keeps the one
+ * with the least wall time per atom-step and returns it in *lanes_out (and
+ * that time in *ns_per_atom_step).  The trials are ordinary trials of the
+ * handle's chains (they advance the trial counters and the statistics).
+ */
+int32_t h4d_autotune(h4d_system *sys, int32_t trials, int32_t *lanes_out, double *ns_per_atom_step);
 
 /*
  * Stream-copy probe (no handle needed): copies `bytes` bytes between two

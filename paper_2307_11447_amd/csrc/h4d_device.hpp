@@ -58,12 +58,9 @@ __device__ __forceinline__ double unit_open(uint64_t b) {
 }
 
 // --------------------------------------------------------------------------
-// Geometry and model constants, passed by value to every kernel.
+// Model constants shared by every box, passed by value to every kernel.
 // --------------------------------------------------------------------------
 struct Geo {
-    double L[3];
-    double fx_inv[3];        // 2^32 / L: FP64 coordinate -> 32-bit fixed point
-    float fx_scale[3];       // L / 2^32
     double rc_lj2, rc_c2, rc_max2, rlist2, half_skin2;
     float rc_lj2f, rc_c2f, rc_max2f;
     double alpha, alpha2, cex, Sc, erfc_rc_over_rc, rc_coul;   // damped shifted force
@@ -71,9 +68,7 @@ struct Geo {
     float nalpha2_log2e;     // -alpha^2 log2(e): exp(-alpha^2 s^2) = 2^(nalpha2_log2e s^2)
     float p_alpha;           // 0.3275911 alpha (argument scale of the erfc fit)
     double dt, half_dt, accel, kT, w_max, kappa;
-    double volume, lambda3, beta, beta_mu;
-    int ncell[3];
-    int use_cells;
+    double lambda3, beta, beta_mu;
     int n_types;
     int water;
     double d_oh, d_hh;
@@ -81,6 +76,24 @@ struct Geo {
     // (O at (0, ra), H at (-rc_w, -rb) and (rc_w, -rb))
     double m_o, m_h, ra, rb, rc_w;
     int n_mol;
+};
+
+// --------------------------------------------------------------------------
+// One periodic box of a batch: its geometry and where its atoms and cells
+// live in the shared arrays.  Atom slots [a0, a0 + cap) and cells
+// [c0, c0 + nc); a0 and cap are multiples of kBlock, so no block of an atom
+// kernel straddles two boxes.
+// --------------------------------------------------------------------------
+struct Box {
+    double L[3];
+    double fx_inv[3];        // 2^32 / L: FP64 coordinate -> 32-bit fixed point
+    float fx_scale[3];       // L / 2^32
+    int ncell[3];
+    int use_cells;           // 0: fewer than 3 list cells per edge, all pairs
+    int a0, cap;
+    int c0, nc;
+    double volume;
+    uint64_t stream;         // second word of this box's Philox key
 };
 
 // per type-pair coefficients, indexed ti * kMaxTypes + tj

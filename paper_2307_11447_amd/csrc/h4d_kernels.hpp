@@ -1,18 +1,27 @@
-// h4d_kernels.hpp -- HIP kernels of one H4D exchange trial on gfx950.
+// h4d_kernels.hpp -- HIP kernels of H4D exchange trials on gfx950.
 //
-// Two copies of the configuration live in HBM:
+// One launch serves every box of a batch (a single system is a batch of
+// one).  Box b owns atom slots [a0, a0 + cap) and cells [c0, c0 + nc) of the
+// shared arrays, its own control block ctl[b] and trial record rec[b]; a
+// block finds its box from the slot (or cell) it starts at.  All boxes run
+// their current trial in lockstep rounds, each with its own N_f: a box whose
+// trajectory has ended is frozen and its blocks return at once.
+//
+// Two copies of each box's configuration live in HBM:
 //   canonical  cpos/ctag/ctype/cmol in ascending tag order: the state
 //              between trials and the rollback snapshot during a trial;
 //   working    the trial's atoms sorted by cell (spatial order) at its start:
 //              pos[2] double4 (FP64 x, y, z + meta word), fx[2] uint4 (32-bit
 //              fixed-point x, y, z + meta word), vel[2] double4, perm (working
-//              -> canonical index), wmol.  pos/fx/vel ping-pong every step.
-// Verlet list: full list, blocked for wavefront-contiguous reads: atom w's
-//   entry q sits at nbr[((w / A) * KQ + q / L) * 64 + (w % A) * L + q % L],
-//   with L lanes per atom (4, 8 or 16, chosen per system), A = 64 / L atoms
-//   per wavefront, KQ = cap_nbr / L.
-// Every kernel reads the atom counts from the control block, so the launches
-// of a trial never wait on the host.
+//              -> canonical index), wmol.  pos/fx/vel ping-pong every step:
+//              step k reads buffer k & 1, so a box's final state is in
+//              buffer (N_f + 1) & 1.
+// Verlet list: full list, blocked for wavefront-contiguous reads: atom slot
+//   w's entry q sits at nbr[((w / A) * KQ + q / L) * 64 + (w % A) * L + q % L],
+//   with L lanes per atom (4, 8 or 16), A = 64 / L atoms per wavefront,
+//   KQ = cap_nbr / L.
+// Every kernel reads the atom counts from the control blocks, so the launches
+// of a round never wait on the host.
 #pragma once
 #include "h4d_device.hpp"
 
@@ -25,8 +34,8 @@ struct Ctl {
     int n_all;        // atoms including the two ghosts of an insertion
     int nsalt;
     int move;         // +1 insertion, -1 deletion, 0 nothing to do
-    int ic, ia;       // canonical indices of the flying cation / anion
-    int wic, wia;     // their working indices
+    int ic, ia;       // slots of the flying cation / anion (canonical arrays)
+    int wic, wia;     // their working slots
     int nf;           // NEMD steps of this trial
     int accepted;
     unsigned err;     // kErr* bits of this trial
@@ -34,8 +43,10 @@ struct Ctl {
     int max_nbr, max_cell;
     int nfast[3];     // fast-atom list lengths (list k % 3 is read by step k)
     int max_fast;     // largest fast list of the trial
+    int idle;         // 1: this box has run its quota of trials
     long long next_tag;
     long long trial;
+    long long trial_end;   // the box idles once trial reaches this
     double u[8];
     double U0, K0, U1, K1;
     double Ulj, Uc, vir;
@@ -52,8 +63,14 @@ struct TrialRec {
     double dH, dU, dK, W_prot, E_switch, dM, ln_ratio, ln_u, ln_proposal, H0, H1;
 };
 
+constexpr unsigned kFlagEmpty = 1u, kFlagNonfinite = 2u, kFlagIdle = 8u;
+
 struct KArgs {
     Geo G;
+    const Box *box;
+    const int *slot_box;      // box of atom slots [kBlock q, kBlock (q + 1))
+    const int *cell_box;      // box of each cell
+    int nbox;
     const PairCoef *coef;
     const double *mass;       // per type
     // canonical state
@@ -66,7 +83,7 @@ struct KArgs {
     double4 *vel[2];
     int *perm, *wmol;
     uint4 *posb;              // fixed-point positions at the last list build
-    double4 *force;           // test hook output
+    double4 *force;           // test hook output (canonical slots)
     // compaction scratch (canonical order)
     double4 *tpos;
     long long *ttag;
@@ -74,20 +91,34 @@ struct KArgs {
     // lists
     int *nbr, *nnbr;
     int *cell_cnt[2], *cell_atoms[2], *cell_off;
-    int *fast;                // 3 lists of kFastCap working indices
-    int *molw;                // water atom (canonical 3m + q) -> working index
+    int *fast;                // per box: 3 lists of kFastCap working slots
+    int *molw;                // water atom (canonical 3m + q) -> working slot
     double4 *fw;              // forces on water atoms (working order)
-    double *partial;          // per-block FP64 partial sums, 4 per block
-    Ctl *ctl;
-    TrialRec *rec;
-    int cap, nbr_cap, cell_cap, ncell_total;
+    double *partial;          // per-block FP64 partial sums, 5 per block
+    Ctl *ctl;                 // per box
+    TrialRec *rec;            // per box
+    int slots;                // atom slots of all boxes
+    int step_blocks;          // blocks of the lanes-per-atom grids (the step
+                              // grid adds one flyer block per box after them)
+    int nbr_cap, cell_cap, ncell_total;
     int lanes, lanes_log2;    // lanes per atom in list traversals (4, 8 or 16)
-    uint64_t seed, stream;
+    uint64_t seed;
     int n_steps, n_steps_min, n_steps_max;
     int cation_type, anion_type;
 };
 
-// slot of entry q of atom w in the blocked list (L = a.lanes, A = 64 / L)
+// box of an atom slot / of a cell
+__device__ __forceinline__ int box_of_slot(const KArgs &a, int slot) {
+    return a.nbox == 1 ? 0 : a.slot_box[slot / kBlock];
+}
+__device__ __forceinline__ int box_of_cell(const KArgs &a, int cc) {
+    return a.nbox == 1 ? 0 : a.cell_box[cc];
+}
+
+// working buffer of a kernel: b >= 0 as given, b < 0 the box's final buffer
+__device__ __forceinline__ int buf_of(int b, const Ctl *c) { return b >= 0 ? b : ((c->nf + 1) & 1); }
+
+// slot of entry q of atom slot w in the blocked list (L = a.lanes, A = 64 / L)
 __device__ __forceinline__ size_t nbr_slot(const KArgs &a, int w, int q) {
     const int ll = a.lanes_log2, la = 6 - ll;
     return ((size_t)(w >> la) * (size_t)(a.nbr_cap >> ll) + (size_t)(q >> ll)) * kWave +
@@ -103,8 +134,8 @@ __device__ __forceinline__ void load_coef(CoefLds &s, const PairCoef *g) {
     for (int q = threadIdx.x; q < kMaxTypes * kMaxTypes; q += blockDim.x) s.c[q] = g[q];
 }
 
-__device__ __forceinline__ uint4 fixed_of(const Geo &G, double x, double y, double z, int meta) {
-    return make_uint4(to_fixed(x, G.fx_inv[0]), to_fixed(y, G.fx_inv[1]), to_fixed(z, G.fx_inv[2]),
+__device__ __forceinline__ uint4 fixed_of(const Box &B, double x, double y, double z, int meta) {
+    return make_uint4(to_fixed(x, B.fx_inv[0]), to_fixed(y, B.fx_inv[1]), to_fixed(z, B.fx_inv[2]),
                       (unsigned)meta);
 }
 
@@ -113,45 +144,58 @@ __device__ __forceinline__ int cell_coord(double x, double L, int nc) {
     return k < 0 ? 0 : (k >= nc ? nc - 1 : k);
 }
 
-__device__ __forceinline__ int cell_of(const Geo &G, const double4 &p) {
-    const int cx = cell_coord(p.x, G.L[0], G.ncell[0]);
-    const int cy = cell_coord(p.y, G.L[1], G.ncell[1]);
-    const int cz = cell_coord(p.z, G.L[2], G.ncell[2]);
-    return (cz * G.ncell[1] + cy) * G.ncell[0] + cx;
+// cell of a position, local to its box
+__device__ __forceinline__ int cell_of(const Box &B, const double4 &p) {
+    const int cx = cell_coord(p.x, B.L[0], B.ncell[0]);
+    const int cy = cell_coord(p.y, B.L[1], B.ncell[1]);
+    const int cz = cell_coord(p.z, B.L[2], B.ncell[2]);
+    return (cz * B.ncell[1] + cy) * B.ncell[0] + cx;
 }
 
-__device__ __forceinline__ void bin_atom(const KArgs &a, int cb, int w, const double4 &p) {
-    const int cc = a.G.use_cells ? cell_of(a.G, p) : 0;
+// global index of the neighbour cell t (0..26, dz-major) of local cell (cx, cy, cz)
+__device__ __forceinline__ int stencil_cell(const Box &B, int cx, int cy, int cz, int t) {
+    const int nx = B.ncell[0], ny = B.ncell[1], nz = B.ncell[2];
+    return B.c0 + (((cz + t / 9 - 1 + nz) % nz) * ny + (cy + (t / 3) % 3 - 1 + ny) % ny) * nx +
+           (cx + t % 3 - 1 + nx) % nx;
+}
+
+__device__ __forceinline__ void bin_atom(const KArgs &a, const Box &B, Ctl *c, int cb, int w, const double4 &p) {
+    const int cc = B.c0 + (B.use_cells ? cell_of(B, p) : 0);
     const int slot = atomicAdd(&a.cell_cnt[cb][cc], 1);
     if (slot < a.cell_cap) a.cell_atoms[cb][(size_t)cc * a.cell_cap + slot] = w;
-    else { atomicOr(&a.ctl->err, kErrCell); atomicMax(&a.ctl->max_cell, slot + 1); }
+    else { atomicOr(&c->err, kErrCell); atomicMax(&c->max_cell, slot + 1); }
 }
 
 // ==========================================================================
-// Proposal on the canonical state: move choice, ghost pair of an insertion,
-// rank selection of a deletion (Eqs. 3-4; insertion or deletion with 1/2).
+// Proposal on the canonical state, one block per box: move choice, ghost
+// pair of an insertion, rank selection of a deletion (Eqs. 3-4; insertion
+// or deletion with probability 1/2).  A box that has run its quota idles.
 // ==========================================================================
 __global__ __launch_bounds__(kBlock) void k_propose(KArgs a, int force_move) {
-    Ctl *c = a.ctl;
+    const int bi = blockIdx.x;
+    const Box &B = a.box[bi];
+    Ctl *c = a.ctl + bi;
     __shared__ int s_cnt[2][kBlock];
     __shared__ int s_move, s_kc, s_ka, s_ic, s_ia, s_n;
     const int tid = threadIdx.x;
     if (tid == 0) {
         const uint64_t t = (uint64_t)c->trial;
-        const u64x4 r0 = philox(t, kPurposeSelect, 0, 0, a.seed, a.stream);
-        const u64x4 r1 = philox(t, kPurposeSelect, 1, 0, a.seed, a.stream);
+        const u64x4 r0 = philox(t, kPurposeSelect, 0, 0, a.seed, B.stream);
+        const u64x4 r1 = philox(t, kPurposeSelect, 1, 0, a.seed, B.stream);
         for (int q = 0; q < 4; ++q) { c->u[q] = unit_open(r0.v[q]); c->u[4 + q] = unit_open(r1.v[q]); }
         int nf = a.n_steps;
         if (a.n_steps_max > 0) {
-            const u64x4 rn = philox(t, kPurposeNsteps, 0, 0, a.seed, a.stream);
+            const u64x4 rn = philox(t, kPurposeNsteps, 0, 0, a.seed, B.stream);
             nf = a.n_steps_min + (int)floor(unit_open(rn.v[0]) * (double)(a.n_steps_max - a.n_steps_min + 1));
         }
         c->nf = nf;
+        c->idle = c->trial >= c->trial_end;
         int move = force_move ? force_move : (c->u[0] < 0.5 ? 1 : -1);
-        if (move < 0 && c->nsalt == 0) move = 0;
+        if ((move < 0 && c->nsalt == 0) || c->idle) move = 0;
         c->move = move;
         c->err = 0; c->retry = 0; c->accepted = 0;
         c->Wf[0] = c->Wf[1] = 0.0; c->Ufly0 = c->Ufly1 = 0.0;
+        c->U0 = c->K0 = c->U1 = c->K1 = 0.0;
         c->ic = c->ia = c->wic = c->wia = -1;
         c->nfast[0] = c->nfast[1] = c->nfast[2] = 0;
         c->max_fast = 0;
@@ -162,17 +206,17 @@ __global__ __launch_bounds__(kBlock) void k_propose(KArgs a, int force_move) {
         s_ic = s_ia = -1;
         if (move > 0) {
             const int n = c->n;
-            if (n + 2 > a.cap) {
+            if (n + 2 > B.cap) {
                 c->err |= kErrCap; c->retry = 1; c->move = 0; s_move = 0;
             } else {
-                const int ic = n, ia = n + 1;
+                const int ic = B.a0 + n, ia = B.a0 + n + 1;
                 const int tcat = a.cation_type, tan = a.anion_type;
-                a.cpos[ic] = with_meta(wrap_coord(a.G.L[0] * c->u[1], a.G.L[0]),
-                                       wrap_coord(a.G.L[1] * c->u[2], a.G.L[1]),
-                                       wrap_coord(a.G.L[2] * c->u[3], a.G.L[2]), tcat | kFlyBit);
-                a.cpos[ia] = with_meta(wrap_coord(a.G.L[0] * c->u[4], a.G.L[0]),
-                                       wrap_coord(a.G.L[1] * c->u[5], a.G.L[1]),
-                                       wrap_coord(a.G.L[2] * c->u[6], a.G.L[2]), tan | kFlyBit);
+                a.cpos[ic] = with_meta(wrap_coord(B.L[0] * c->u[1], B.L[0]),
+                                       wrap_coord(B.L[1] * c->u[2], B.L[1]),
+                                       wrap_coord(B.L[2] * c->u[3], B.L[2]), tcat | kFlyBit);
+                a.cpos[ia] = with_meta(wrap_coord(B.L[0] * c->u[4], B.L[0]),
+                                       wrap_coord(B.L[1] * c->u[5], B.L[1]),
+                                       wrap_coord(B.L[2] * c->u[6], B.L[2]), tan | kFlyBit);
                 a.ctag[ic] = c->next_tag; a.ctag[ia] = c->next_tag + 1;
                 a.ctype[ic] = tcat; a.ctype[ia] = tan;
                 a.cmol[ic] = -1; a.cmol[ia] = -1;
@@ -186,7 +230,7 @@ __global__ __launch_bounds__(kBlock) void k_propose(KArgs a, int force_move) {
     // canonical order is tag order, so count species members per chunk and scan
     const int n = s_n;
     const int chunk = (n + kBlock - 1) / kBlock;
-    const int lo = tid * chunk, hi = min(n, lo + chunk);
+    const int lo = B.a0 + tid * chunk, hi = B.a0 + min(n, tid * chunk + chunk);
     int nc = 0, na = 0;
     for (int i = lo; i < hi; ++i) {
         const int ty = a.ctype[i];
@@ -242,8 +286,21 @@ __global__ void k_cell_clear(KArgs a, int cb) {
 // bin the canonical atoms (trial start)
 __global__ __launch_bounds__(kBlock) void k_bin_canonical(KArgs a, int cb) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= a.ctl->n_all) return;
-    bin_atom(a, cb, i, a.cpos[i]);
+    const int bi = box_of_slot(a, i);
+    const Box &B = a.box[bi];
+    Ctl *c = a.ctl + bi;
+    if (i - B.a0 >= c->n_all) return;
+    bin_atom(a, B, c, cb, i, a.cpos[i]);
+}
+
+// bin the working atoms of every box with a trajectory, from its final buffer
+__global__ __launch_bounds__(kBlock) void k_bin_working(KArgs a, int cb) {
+    const int w = blockIdx.x * kBlock + threadIdx.x;
+    const int bi = box_of_slot(a, w);
+    const Box &B = a.box[bi];
+    Ctl *c = a.ctl + bi;
+    if (c->move == 0 || w - B.a0 >= c->n_all) return;
+    bin_atom(a, B, c, cb, w, a.pos[buf_of(-1, c)][w]);
 }
 
 __global__ __launch_bounds__(kWave) void k_cell_sort(KArgs a, int cb) {
@@ -261,12 +318,14 @@ __global__ __launch_bounds__(kWave) void k_cell_sort(KArgs a, int cb) {
     }
 }
 
-// exclusive scan of the cell counts (one block)
+// exclusive scan of each box's cell counts (one block per box); cell_off
+// holds the first working slot of every cell
 __global__ __launch_bounds__(1024) void k_cell_scan(KArgs a, int cb) {
     __shared__ int part[1024];
-    const int nc = a.ncell_total;
+    const Box &B = a.box[blockIdx.x];
+    const int nc = B.nc;
     const int per = (nc + 1023) / 1024;
-    const int lo = threadIdx.x * per, hi = min(nc, lo + per);
+    const int lo = B.c0 + threadIdx.x * per, hi = B.c0 + min(nc, (int)threadIdx.x * per + per);
     int s = 0;
     for (int q = lo; q < hi; ++q) s += min(a.cell_cnt[cb][q], a.cell_cap);
     part[threadIdx.x] = s;
@@ -277,20 +336,21 @@ __global__ __launch_bounds__(1024) void k_cell_scan(KArgs a, int cb) {
         part[threadIdx.x] += v;
         __syncthreads();
     }
-    int run = threadIdx.x ? part[threadIdx.x - 1] : 0;
+    int run = B.a0 + (threadIdx.x ? part[threadIdx.x - 1] : 0);
     for (int q = lo; q < hi; ++q) {
         a.cell_off[q] = run;
         run += min(a.cell_cnt[cb][q], a.cell_cap);
     }
-    if (threadIdx.x == 1023) a.cell_off[nc] = part[1023];
 }
 
 // Trial start: gather the canonical atoms into cell order (working buffer 0),
 // draw the Maxwell-Boltzmann momenta (keyed by tag, Box-Muller on Philox
-// uniforms), and rewrite the cell rows with working indices.
+// uniforms), and rewrite the cell rows with working slots.
 __global__ __launch_bounds__(kWave) void k_gather_in(KArgs a, int cb) {
-    Ctl *c = a.ctl;
     const int cc = blockIdx.x;
+    const int bi = box_of_cell(a, cc);
+    const Box &B = a.box[bi];
+    Ctl *c = a.ctl + bi;
     const int cnt = min(a.cell_cnt[cb][cc], a.cell_cap);
     const int off = a.cell_off[cc];
     int *row = a.cell_atoms[cb] + (size_t)cc * a.cell_cap;
@@ -306,12 +366,12 @@ __global__ __launch_bounds__(kWave) void k_gather_in(KArgs a, int cb) {
         const double4 p = with_meta(p0.x, p0.y, p0.z, meta);
         a.pos[0][w] = p;
         if (mol >= 0) a.molw[src] = w;
-        const uint4 q = fixed_of(a.G, p.x, p.y, p.z, meta);
+        const uint4 q = fixed_of(B, p.x, p.y, p.z, meta);
         a.posb[w] = q;
         a.fx[0][w] = q;
         a.perm[w] = src;
         a.wmol[w] = mol;
-        const u64x4 r = philox(t, kPurposeMB, (uint64_t)a.ctag[src], 0, a.seed, a.stream);
+        const u64x4 r = philox(t, kPurposeMB, (uint64_t)a.ctag[src], 0, a.seed, B.stream);
         const double u0 = unit_open(r.v[0]), u1 = unit_open(r.v[1]);
         const double u2 = unit_open(r.v[2]), u3 = unit_open(r.v[3]);
         const double r01 = sqrt(-2.0 * log(u0)), r23 = sqrt(-2.0 * log(u2));
@@ -334,8 +394,13 @@ __device__ __forceinline__ void unflag_fast(const KArgs &a, int b, int w, unsign
     }
 }
 
-__device__ __forceinline__ void reset_fast_lists(const KArgs &a) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->nfast[0] = a.ctl->nfast[1] = a.ctl->nfast[2] = 0;
+// Which boxes a list build serves.  k = -1: every box (trial start, test
+// hooks); k = -2: every box with a trajectory (end of trajectory); k >= 0:
+// the rebuild before step k, for the boxes still running at step k.
+__device__ __forceinline__ bool list_wanted(const Ctl *c, int k) {
+    if (k == -1) return true;
+    if (c->move == 0) return false;
+    return k < 0 || k <= c->nf;
 }
 
 // ==========================================================================
@@ -343,25 +408,33 @@ __device__ __forceinline__ void reset_fast_lists(const KArgs &a) {
 // boxes with fewer than 3 cells per edge: L lanes per atom test consecutive
 // candidates; a ballot keeps the sequential order.
 // ==========================================================================
-__device__ __forceinline__ bool list_accepts(const KArgs &a, const uint4 &qi, int mi, int wi, int j,
+__device__ __forceinline__ bool list_accepts(const KArgs &a, const Box &B, const uint4 &qi, int mi, int wi, int j,
                                              const uint4 &qj, int mj, float rl2) {
     if (j == wi) return false;
     if (mi >= 0 && mj == mi) return false;
-    const float dx = (float)(int)(qi.x - qj.x) * a.G.fx_scale[0];
-    const float dy = (float)(int)(qi.y - qj.y) * a.G.fx_scale[1];
-    const float dz = (float)(int)(qi.z - qj.z) * a.G.fx_scale[2];
+    const float dx = (float)(int)(qi.x - qj.x) * B.fx_scale[0];
+    const float dy = (float)(int)(qi.y - qj.y) * B.fx_scale[1];
+    const float dz = (float)(int)(qi.z - qj.z) * B.fx_scale[2];
     return dx * dx + dy * dy + dz * dz < rl2;
 }
 
-__global__ __launch_bounds__(kBlock) void k_list_allpairs(KArgs a, int b, int cb) {
-    const Ctl *c = a.ctl;
+__global__ __launch_bounds__(kBlock) void k_list_allpairs(KArgs a, int k, int b0, int cb) {
+    const int slot0 = blockIdx.x * (kBlock >> a.lanes_log2);
+    const int bi = box_of_slot(a, slot0);
+    const Box &B = a.box[bi];
+    Ctl *c = a.ctl + bi;
+    if (!list_wanted(c, k)) return;
+    const int b = buf_of(b0, c);
     const int n_all = c->n_all;
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.cell_cnt[cb ^ 1][0] = 0;
+    if (slot0 == B.a0 && threadIdx.x == 0) {
+        a.cell_cnt[cb ^ 1][B.c0] = 0;
+        c->nfast[0] = c->nfast[1] = c->nfast[2] = 0;
+    }
     const int L = a.lanes;
     const int lane = threadIdx.x % kWave;
     const int s = lane & (L - 1);
     const int w = (blockIdx.x * kBlock + threadIdx.x) >> a.lanes_log2;
-    if (w >= n_all) return;
+    if (w - B.a0 >= n_all) return;
     const uint4 qi = a.fx[b][w];
     const int mi = a.wmol[w];
     const float rl2 = (float)a.G.rlist2 * 1.00001f;     // superset margin for FP32 distances
@@ -370,9 +443,9 @@ __global__ __launch_bounds__(kBlock) void k_list_allpairs(KArgs a, int b, int cb
     const unsigned long long below = (1ull << s) - 1ull;
     int cnt = 0;
     for (int base = 0; base < n_all; base += L) {
-        const int j = base + s;
+        const int j = B.a0 + base + s;
         bool acc = false;
-        if (j < n_all) acc = list_accepts(a, qi, mi, w, j, a.fx[b][j], a.wmol[j], rl2);
+        if (base + s < n_all) acc = list_accepts(a, B, qi, mi, w, j, a.fx[b][j], a.wmol[j], rl2);
         const unsigned long long m = (__ballot(acc) >> gshift) & gmask;
         if (acc) {
             const int q = cnt + __popcll(m & below);
@@ -384,28 +457,31 @@ __global__ __launch_bounds__(kBlock) void k_list_allpairs(KArgs a, int b, int cb
         a.nnbr[w] = min(cnt, a.nbr_cap);
         a.posb[w] = qi;
         unflag_fast(a, b, w, qi.w);
-        if (cnt > a.nbr_cap) { atomicOr(&a.ctl->err, kErrNbr); atomicMax(&a.ctl->max_nbr, cnt); }
+        if (cnt > a.nbr_cap) { atomicOr(&c->err, kErrNbr); atomicMax(&c->max_nbr, cnt); }
     }
-    reset_fast_lists(a);
 }
 
 // Cell form: one block per centre cell.  The atoms of all 27 stencil cells
-// are staged in LDS (fixed-point coordinates + working index) in stencil
+// are staged in LDS (fixed-point coordinates + working slot) in stencil
 // order; each wavefront takes a share of the centre atoms and tests 64
 // candidates per ballot, appending in stencil order.  Dynamic LDS:
 // 27 * cell_cap * 16 bytes.  Also records the build positions and clears this
 // cell's count in the other buffer.
-__global__ __launch_bounds__(kBlock) void k_list_cells(KArgs a, int b, int cb) {
+__global__ __launch_bounds__(kBlock) void k_list_cells(KArgs a, int k, int b0, int cb) {
     extern __shared__ uint4 cand[];
     __shared__ int cidx[27], cnt27[27], off[28];
     const int cap = a.cell_cap;
     const int cc = blockIdx.x;
-    const int nx = a.G.ncell[0], ny = a.G.ncell[1], nz = a.G.ncell[2];
+    const int bi = box_of_cell(a, cc);
+    const Box &B = a.box[bi];
+    Ctl *c = a.ctl + bi;
+    if (!list_wanted(c, k)) return;
+    const int b = buf_of(b0, c);
     if (threadIdx.x < 27) {
         const int t = threadIdx.x;
-        const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-        const int cx = cc % nx, cy = (cc / nx) % ny, cz = cc / (nx * ny);
-        const int c2 = (((cz + dz + nz) % nz) * ny + (cy + dy + ny) % ny) * nx + (cx + dx + nx) % nx;
+        const int nx = B.ncell[0], ny = B.ncell[1];
+        const int lc = cc - B.c0;
+        const int c2 = stencil_cell(B, lc % nx, (lc / nx) % ny, lc / (nx * ny), t);
         cidx[t] = c2;
         cnt27[t] = min(a.cell_cnt[cb][c2], cap);
     }
@@ -414,6 +490,7 @@ __global__ __launch_bounds__(kBlock) void k_list_cells(KArgs a, int b, int cb) {
         int run = 0;
         for (int t = 0; t < 27; ++t) { off[t] = run; run += cnt27[t]; }
         off[27] = run;
+        if (cc == B.c0) c->nfast[0] = c->nfast[1] = c->nfast[2] = 0;
     }
     __syncthreads();
     const int total = off[27];
@@ -449,9 +526,9 @@ __global__ __launch_bounds__(kBlock) void k_list_cells(KArgs a, int b, int cb) {
                 const uint4 qj = cand[u];
                 j = (int)qj.w;
                 if (j != wi) {
-                    const float dx = (float)(int)(qi.x - qj.x) * a.G.fx_scale[0];
-                    const float dy = (float)(int)(qi.y - qj.y) * a.G.fx_scale[1];
-                    const float dz = (float)(int)(qi.z - qj.z) * a.G.fx_scale[2];
+                    const float dx = (float)(int)(qi.x - qj.x) * B.fx_scale[0];
+                    const float dy = (float)(int)(qi.y - qj.y) * B.fx_scale[1];
+                    const float dz = (float)(int)(qi.z - qj.z) * B.fx_scale[2];
                     acc = dx * dx + dy * dy + dz * dz < rl2;
                     if (acc && mi >= 0 && a.wmol[j] == mi) acc = false;
                 }
@@ -467,66 +544,70 @@ __global__ __launch_bounds__(kBlock) void k_list_cells(KArgs a, int b, int cb) {
             a.nnbr[wi] = min(cnt, a.nbr_cap);
             a.posb[wi] = qi;
             if (t < 1024) unflag_fast(a, b, wi, cmeta[t]);
-            if (cnt > a.nbr_cap) { atomicOr(&a.ctl->err, kErrNbr); atomicMax(&a.ctl->max_nbr, cnt); }
+            if (cnt > a.nbr_cap) { atomicOr(&c->err, kErrNbr); atomicMax(&c->max_nbr, cnt); }
         }
     }
     if (threadIdx.x == 0) a.cell_cnt[cb ^ 1][cc] = 0;
-    reset_fast_lists(a);
 }
 
 // Cell form for cells too large to stage in LDS: L lanes per atom walk the
 // 27 stencil cells directly from global memory.
-__global__ __launch_bounds__(kBlock) void k_list_lanes(KArgs a, int b, int cb) {
-    const Ctl *c = a.ctl;
+__global__ __launch_bounds__(kBlock) void k_list_lanes(KArgs a, int k, int b0, int cb) {
+    const int P = kBlock >> a.lanes_log2;               // atoms per block
+    const int slot0 = blockIdx.x * P;
+    const int bi = box_of_slot(a, slot0);
+    const Box &B = a.box[bi];
+    Ctl *c = a.ctl + bi;
+    if (!list_wanted(c, k)) return;
+    const int b = buf_of(b0, c);
     const int n_all = c->n_all;
-    for (int q = blockIdx.x * kBlock + threadIdx.x; q < a.ncell_total; q += gridDim.x * kBlock)
-        a.cell_cnt[cb ^ 1][q] = 0;
+    {   // this box's blocks clear its cells in the other buffer
+        const int nblk = B.cap / P, lb = (slot0 - B.a0) / P;
+        for (int q = lb * kBlock + threadIdx.x; q < B.nc; q += nblk * kBlock) a.cell_cnt[cb ^ 1][B.c0 + q] = 0;
+        if (lb == 0 && threadIdx.x == 0) c->nfast[0] = c->nfast[1] = c->nfast[2] = 0;
+    }
     const int L = a.lanes;
     const int lane = threadIdx.x % kWave;
     const int s = lane & (L - 1);
     const int w = (blockIdx.x * kBlock + threadIdx.x) >> a.lanes_log2;
-    if (w >= n_all) return;
+    if (w - B.a0 >= n_all) return;
     const uint4 qi = a.fx[b][w];
     const int mi = a.wmol[w];
     const float rl2 = (float)a.G.rlist2 * 1.00001f;
     const int gshift = lane - s;
     const unsigned long long gmask = (1ull << L) - 1ull;
     const unsigned long long below = (1ull << s) - 1ull;
-    const int nx = a.G.ncell[0], ny = a.G.ncell[1], nz = a.G.ncell[2];
     const double4 pi = a.pos[b][w];
-    const int cx = cell_coord(pi.x, a.G.L[0], nx);
-    const int cy = cell_coord(pi.y, a.G.L[1], ny);
-    const int cz = cell_coord(pi.z, a.G.L[2], nz);
+    const int cx = cell_coord(pi.x, B.L[0], B.ncell[0]);
+    const int cy = cell_coord(pi.y, B.L[1], B.ncell[1]);
+    const int cz = cell_coord(pi.z, B.L[2], B.ncell[2]);
     int cnt = 0;
-    for (int dz = -1; dz <= 1; ++dz)
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int c2 = (((cz + dz + nz) % nz) * ny + (cy + dy + ny) % ny) * nx + (cx + dx + nx) % nx;
-                const int m = min(a.cell_cnt[cb][c2], a.cell_cap);
-                const int *row = a.cell_atoms[cb] + (size_t)c2 * a.cell_cap;
-                for (int base = 0; base < m; base += L) {
-                    const int u = base + s;
-                    bool acc = false;
-                    int j = 0;
-                    if (u < m) {
-                        j = row[u];
-                        acc = list_accepts(a, qi, mi, w, j, a.fx[b][j], a.wmol[j], rl2);
-                    }
-                    const unsigned long long mm = (__ballot(acc) >> gshift) & gmask;
-                    if (acc) {
-                        const int q = cnt + __popcll(mm & below);
-                        if (q < a.nbr_cap) a.nbr[nbr_slot(a, w, q)] = j;
-                    }
-                    cnt += __popcll(mm);
-                }
+    for (int t = 0; t < 27; ++t) {
+        const int c2 = stencil_cell(B, cx, cy, cz, t);
+        const int m = min(a.cell_cnt[cb][c2], a.cell_cap);
+        const int *row = a.cell_atoms[cb] + (size_t)c2 * a.cell_cap;
+        for (int base = 0; base < m; base += L) {
+            const int u = base + s;
+            bool acc = false;
+            int j = 0;
+            if (u < m) {
+                j = row[u];
+                acc = list_accepts(a, B, qi, mi, w, j, a.fx[b][j], a.wmol[j], rl2);
             }
+            const unsigned long long mm = (__ballot(acc) >> gshift) & gmask;
+            if (acc) {
+                const int q = cnt + __popcll(mm & below);
+                if (q < a.nbr_cap) a.nbr[nbr_slot(a, w, q)] = j;
+            }
+            cnt += __popcll(mm);
+        }
+    }
     if (s == 0) {
         a.nnbr[w] = min(cnt, a.nbr_cap);
         a.posb[w] = qi;
         unflag_fast(a, b, w, qi.w);
-        if (cnt > a.nbr_cap) { atomicOr(&a.ctl->err, kErrNbr); atomicMax(&a.ctl->max_nbr, cnt); }
+        if (cnt > a.nbr_cap) { atomicOr(&c->err, kErrNbr); atomicMax(&c->max_nbr, cnt); }
     }
-    reset_fast_lists(a);
 }
 
 // ==========================================================================
@@ -538,9 +619,9 @@ __global__ __launch_bounds__(kBlock) void k_list_lanes(KArgs a, int b, int cb) {
 // skin covers every partner within r_c).  Every pair is counted once.
 // ==========================================================================
 template <int PREC, int L>
-__device__ __forceinline__ void group_force(const KArgs &a, const CoefLds &cf, int b, int cl, int w, int s,
-                                            const double4 &pi, int mi, double wv, double gscr, const int *flist,
-                                            int nfast, double &fx, double &fy, double &fz) {
+__device__ __forceinline__ void group_force(const KArgs &a, const Box &B, const Ctl *c, const CoefLds &cf, int b,
+                                            int cl, int w, int s, const double4 &pi, int mi, double wv, double gscr,
+                                            const int *flist, int nfast, double &fx, double &fy, double &fz) {
     constexpr int A = kWave / L;
     const int ti = mi & kTypeMask;
     const bool own_fast = (mi & kFastBit) != 0;
@@ -549,16 +630,16 @@ __device__ __forceinline__ void group_force(const KArgs &a, const CoefLds &cf, i
     const int own_mol = (mi & kMolBit) ? a.wmol[w] : -1;
     auto same_mol = [&](int j) { return own_mol >= 0 && a.wmol[j] == own_mol; };
     const PairCoef *crow = cf.c + ti * kMaxTypes;
-    const int nx = a.G.ncell[0], ny = a.G.ncell[1], nz = a.G.ncell[2];
     if (PREC == 1) {
         const uint4 *F = a.fx[b];
         const uint4 qi = F[w];
         const float w2 = (float)(wv * wv), g = (float)gscr;
+        const float sx = B.fx_scale[0], sy = B.fx_scale[1], sz = B.fx_scale[2];
         float ax = 0.f, ay = 0.f, az = 0.f;
         auto pair = [&](const uint4 &qj, bool valid) {
-            const float dx = (float)(int)(qi.x - qj.x) * a.G.fx_scale[0];
-            const float dy = (float)(int)(qi.y - qj.y) * a.G.fx_scale[1];
-            const float dz = (float)(int)(qi.z - qj.z) * a.G.fx_scale[2];
+            const float dx = (float)(int)(qi.x - qj.x) * sx;
+            const float dy = (float)(int)(qi.y - qj.y) * sy;
+            const float dz = (float)(int)(qi.z - qj.z) * sz;
             const int mj = (int)qj.w;
             const bool fj = (mj & kFlyBit) != 0;
             const float r2 = dx * dx + dy * dy + dz * dz;
@@ -582,13 +663,12 @@ __device__ __forceinline__ void group_force(const KArgs &a, const CoefLds &cf, i
 #pragma unroll
                 for (int u = 0; u < 4; ++u) pair(q[u], k + u < nq && !(q[u].w & kFastBit));
             }
-        } else if (a.G.use_cells) {
-            const int cx = cell_coord(pi.x, a.G.L[0], nx);
-            const int cy = cell_coord(pi.y, a.G.L[1], ny);
-            const int cz = cell_coord(pi.z, a.G.L[2], nz);
+        } else if (B.use_cells) {
+            const int cx = cell_coord(pi.x, B.L[0], B.ncell[0]);
+            const int cy = cell_coord(pi.y, B.L[1], B.ncell[1]);
+            const int cz = cell_coord(pi.z, B.L[2], B.ncell[2]);
             for (int t = 0; t < 27; ++t) {
-                const int c2 = (((cz + t / 9 - 1 + nz) % nz) * ny + (cy + (t / 3) % 3 - 1 + ny) % ny) * nx +
-                               (cx + t % 3 - 1 + nx) % nx;
+                const int c2 = stencil_cell(B, cx, cy, cz, t);
                 const int m = min(a.cell_cnt[cl][c2], a.cell_cap);
                 const int *row = a.cell_atoms[cl] + (size_t)c2 * a.cell_cap;
                 for (int u = s; u < m; u += L) {
@@ -598,8 +678,8 @@ __device__ __forceinline__ void group_force(const KArgs &a, const CoefLds &cf, i
                 }
             }
         } else {
-            const int n_all = a.ctl->n_all;
-            for (int j = s; j < n_all; j += L) {
+            const int j1 = B.a0 + c->n_all;
+            for (int j = B.a0 + s; j < j1; j += L) {
                 const uint4 qj = F[j];
                 pair(qj, j != w && !(qj.w & kFastBit) && !same_mol(j));
             }
@@ -621,9 +701,9 @@ __device__ __forceinline__ void group_force(const KArgs &a, const CoefLds &cf, i
         const double w2 = wv * wv;
         auto pair = [&](const double4 &pj, bool valid) {
             if (!valid) return;
-            const double dx = min_image(pi.x - pj.x, a.G.L[0]);
-            const double dy = min_image(pi.y - pj.y, a.G.L[1]);
-            const double dz = min_image(pi.z - pj.z, a.G.L[2]);
+            const double dx = min_image(pi.x - pj.x, B.L[0]);
+            const double dy = min_image(pi.y - pj.y, B.L[1]);
+            const double dz = min_image(pi.z - pj.z, B.L[2]);
             const int mj = meta_of(pj);
             const bool fj = (mj & kFlyBit) != 0;
             const double r2 = dx * dx + dy * dy + dz * dz;
@@ -640,13 +720,12 @@ __device__ __forceinline__ void group_force(const KArgs &a, const CoefLds &cf, i
                 const double4 pj = P[base[(size_t)k * kWave]];
                 pair(pj, !(meta_of(pj) & kFastBit));
             }
-        } else if (a.G.use_cells) {
-            const int cx = cell_coord(pi.x, a.G.L[0], nx);
-            const int cy = cell_coord(pi.y, a.G.L[1], ny);
-            const int cz = cell_coord(pi.z, a.G.L[2], nz);
+        } else if (B.use_cells) {
+            const int cx = cell_coord(pi.x, B.L[0], B.ncell[0]);
+            const int cy = cell_coord(pi.y, B.L[1], B.ncell[1]);
+            const int cz = cell_coord(pi.z, B.L[2], B.ncell[2]);
             for (int t = 0; t < 27; ++t) {
-                const int c2 = (((cz + t / 9 - 1 + nz) % nz) * ny + (cy + (t / 3) % 3 - 1 + ny) % ny) * nx +
-                               (cx + t % 3 - 1 + nx) % nx;
+                const int c2 = stencil_cell(B, cx, cy, cz, t);
                 const int m = min(a.cell_cnt[cl][c2], a.cell_cap);
                 const int *row = a.cell_atoms[cl] + (size_t)c2 * a.cell_cap;
                 for (int u = s; u < m; u += L) {
@@ -656,8 +735,8 @@ __device__ __forceinline__ void group_force(const KArgs &a, const CoefLds &cf, i
                 }
             }
         } else {
-            const int n_all = a.ctl->n_all;
-            for (int j = s; j < n_all; j += L) {
+            const int j1 = B.a0 + c->n_all;
+            for (int j = B.a0 + s; j < j1; j += L) {
                 const double4 pj = P[j];
                 pair(pj, j != w && !(meta_of(pj) & kFastBit) && !same_mol(j));
             }
@@ -678,10 +757,10 @@ __device__ __forceinline__ void group_force(const KArgs &a, const CoefLds &cf, i
 
 // Displacement since the last list build, from the fixed-point coordinates
 // (flagged slightly early: the threshold is lowered by 1e-5 relative).
-__device__ __forceinline__ bool moved_beyond_half_skin(const KArgs &a, const uint4 &q, const uint4 &qb) {
-    const float dx = (float)(int)(q.x - qb.x) * a.G.fx_scale[0];
-    const float dy = (float)(int)(q.y - qb.y) * a.G.fx_scale[1];
-    const float dz = (float)(int)(q.z - qb.z) * a.G.fx_scale[2];
+__device__ __forceinline__ bool moved_beyond_half_skin(const KArgs &a, const Box &B, const uint4 &q, const uint4 &qb) {
+    const float dx = (float)(int)(q.x - qb.x) * B.fx_scale[0];
+    const float dy = (float)(int)(q.y - qb.y) * B.fx_scale[1];
+    const float dz = (float)(int)(q.z - qb.z) * B.fx_scale[2];
     return dx * dx + dy * dy + dz * dz > (float)a.G.half_skin2 * 0.99999f;
 }
 
@@ -691,8 +770,8 @@ __device__ __forceinline__ bool moved_beyond_half_skin(const KArgs &a, const uin
 // accumulated in FP64 (pair energies in the precision of the pass).
 // --------------------------------------------------------------------------
 template <int PREC>
-__device__ void flyer_work(const KArgs &a, const CoefLds &cf, int b, int k, const int *flist, int nfast) {
-    Ctl *c = a.ctl;
+__device__ void flyer_work(const KArgs &a, const Box &B, Ctl *c, const CoefLds &cf, int b, int k, const int *flist,
+                           int nfast) {
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     if (wave > 1) return;
     const int move = c->move, nf = c->nf;
@@ -715,9 +794,9 @@ __device__ void flyer_work(const KArgs &a, const CoefLds &cf, int b, int k, cons
             if (j == other) continue;
             const uint4 qj = a.fx[b][j];
             if (q < nn && (qj.w & kFastBit)) continue;
-            const float dx = (float)(int)(qf.x - qj.x) * a.G.fx_scale[0];
-            const float dy = (float)(int)(qf.y - qj.y) * a.G.fx_scale[1];
-            const float dz = (float)(int)(qf.z - qj.z) * a.G.fx_scale[2];
+            const float dx = (float)(int)(qf.x - qj.x) * B.fx_scale[0];
+            const float dy = (float)(int)(qf.y - qj.y) * B.fx_scale[1];
+            const float dz = (float)(int)(qf.z - qj.z) * B.fx_scale[2];
             const float r2 = dx * dx + dy * dy + dz * dz;
             const PairCoef &cc = cf.c[tf * kMaxTypes + ((int)qj.w & kTypeMask)];
             const float ulo = (r2 + wl2 < a.G.rc_max2f) ? pair_u_f32(a.G, cc, r2 + wl2, glo) : 0.0f;
@@ -734,9 +813,9 @@ __device__ void flyer_work(const KArgs &a, const CoefLds &cf, int b, int k, cons
             if (j == other) continue;
             const double4 pj = P[j];
             if (q < nn && (meta_of(pj) & kFastBit)) continue;
-            const double dx = min_image(pf.x - pj.x, a.G.L[0]);
-            const double dy = min_image(pf.y - pj.y, a.G.L[1]);
-            const double dz = min_image(pf.z - pj.z, a.G.L[2]);
+            const double dx = min_image(pf.x - pj.x, B.L[0]);
+            const double dy = min_image(pf.y - pj.y, B.L[1]);
+            const double dz = min_image(pf.z - pj.z, B.L[2]);
             const double r2 = dx * dx + dy * dy + dz * dz;
             const PairCoef &cc = cf.c[tf * kMaxTypes + (meta_of(pj) & kTypeMask)];
             double ulj, uc, fs, ulo = 0.0, uhi = 0.0;
@@ -754,20 +833,28 @@ __device__ void flyer_work(const KArgs &a, const CoefLds &cf, int b, int k, cons
 // atom); the second half kick of step k-1 (k > 0); the first half kick and
 // drift of step k (k < nf) into the other buffer.  Flyers stay fixed in 3D.
 // bin != 0: also bin the new positions for the rebuild before step k+1.
-// The last block evaluates the flying work.
+// Blocks [0, step_blocks) cover the atom slots; block step_blocks + b
+// evaluates the flying work of box b.
 // ==========================================================================
 template <int PREC, int L>
 __global__ __launch_bounds__(kBlock) void k_step(KArgs a, int k, int b, int bin, int cl) {
+    const bool flyer_block = (int)blockIdx.x >= a.step_blocks;
+    const int slot0 = (int)blockIdx.x * (kBlock / L);
+    const int bi = flyer_block ? (int)blockIdx.x - a.step_blocks : box_of_slot(a, slot0);
+    const Box &B = a.box[bi];
+    Ctl *c = a.ctl + bi;
+    const int move = c->move, nf = c->nf, n_all = c->n_all;
+    if (move == 0 || k > nf) return;
+    if (!flyer_block && slot0 - B.a0 >= n_all) return;
     __shared__ CoefLds cf;
     load_coef(cf, a.coef);
-    __syncthreads();
-    Ctl *c = a.ctl;
     const int lr = k % 3, lw = (k + 1) % 3;       // fast list read / written by this step
     const int nfast = min(c->nfast[lr], kFastCap);
+    int *fast = a.fast + (size_t)bi * 3 * kFastCap;
     // the list was appended to in atomic order: sort it (fixed summation order)
     __shared__ int sfast_in[kFastCap], sfast[kFastCap];
     if (nfast > 0) {
-        for (int q = threadIdx.x; q < nfast; q += kBlock) sfast_in[q] = a.fast[lr * kFastCap + q];
+        for (int q = threadIdx.x; q < nfast; q += kBlock) sfast_in[q] = fast[lr * kFastCap + q];
         __syncthreads();
         for (int q = threadIdx.x; q < nfast; q += kBlock) {
             const int e = sfast_in[q];
@@ -775,21 +862,19 @@ __global__ __launch_bounds__(kBlock) void k_step(KArgs a, int k, int b, int bin,
             for (int p = 0; p < nfast; ++p) r += (sfast_in[p] < e);
             sfast[r] = e;
         }
-        __syncthreads();
     }
+    __syncthreads();
     const int *flist = sfast;
-    if (blockIdx.x == gridDim.x - 1) {
+    if (flyer_block) {
         if (threadIdx.x == 0) c->nfast[(k + 2) % 3] = 0;
-        flyer_work<PREC>(a, cf, b, k, flist, nfast);
+        flyer_work<PREC>(a, B, c, cf, b, k, flist, nfast);
         return;
     }
-    const int move = c->move, nf = c->nf, n_all = c->n_all;
-    if (move == 0 || k > nf) return;
     const int lane = threadIdx.x % kWave;
     const int s = lane % L;
-    const int w = (blockIdx.x * kBlock + threadIdx.x) / L;
-    const bool act = w < n_all;
-    const int wc = act ? w : 0;
+    const int w = slot0 + (int)threadIdx.x / L;
+    const bool act = w - B.a0 < n_all;
+    const int wc = act ? w : B.a0;
     const double4 pi = a.pos[b][wc];
     const int mi = meta_of(pi);
     const bool fly = (mi & kFlyBit) != 0;
@@ -797,7 +882,7 @@ __global__ __launch_bounds__(kBlock) void k_step(KArgs a, int k, int b, int bin,
     const double wv = altitude(a.G.w_max, move, k, nf);
     const double gscr = exp(-a.G.kappa * wv);
     double fx = 0.0, fy = 0.0, fz = 0.0;
-    if (act && !fly) group_force<PREC, L>(a, cf, b, cl, wc, s, pi, mi, wv, gscr, flist, nfast, fx, fy, fz);
+    if (act && !fly) group_force<PREC, L>(a, B, c, cf, b, cl, wc, s, pi, mi, wv, gscr, flist, nfast, fx, fy, fz);
     if (!act || s != 0) return;
     if (mi & kMolBit) {   // rigid water: integrated by k_settle
         a.fw[wc] = make_double4(fx, fy, fz, 0.0);
@@ -811,16 +896,16 @@ __global__ __launch_bounds__(kBlock) void k_step(KArgs a, int k, int b, int bin,
         if (k > 0) { v.x += hm * fx; v.y += hm * fy; v.z += hm * fz; }
         if (k < nf) {
             v.x += hm * fx; v.y += hm * fy; v.z += hm * fz;
-            x = wrap_coord(pi.x + a.G.dt * v.x, a.G.L[0]);
-            y = wrap_coord(pi.y + a.G.dt * v.y, a.G.L[1]);
-            z = wrap_coord(pi.z + a.G.dt * v.z, a.G.L[2]);
+            x = wrap_coord(pi.x + a.G.dt * v.x, B.L[0]);
+            y = wrap_coord(pi.y + a.G.dt * v.y, B.L[1]);
+            z = wrap_coord(pi.z + a.G.dt * v.z, B.L[2]);
         }
     }
-    uint4 qn = fixed_of(a.G, x, y, z, mi);
-    if (!fly && (mo & kFastBit) == 0 && moved_beyond_half_skin(a, qn, a.posb[wc])) mo |= kFastBit;
+    uint4 qn = fixed_of(B, x, y, z, mi);
+    if (!fly && (mo & kFastBit) == 0 && moved_beyond_half_skin(a, B, qn, a.posb[wc])) mo |= kFastBit;
     if (mo & kFastBit) {   // (re-)register in the list read by the next step
         const int slot = atomicAdd(&c->nfast[lw], 1);
-        if (slot < kFastCap) a.fast[lw * kFastCap + slot] = wc;
+        if (slot < kFastCap) fast[lw * kFastCap + slot] = wc;
         else atomicOr(&c->err, kErrFast);
         atomicMax(&c->max_fast, slot + 1);
     }
@@ -829,26 +914,30 @@ __global__ __launch_bounds__(kBlock) void k_step(KArgs a, int k, int b, int bin,
     a.pos[b ^ 1][wc] = pn;
     a.vel[b ^ 1][wc] = v;
     a.fx[b ^ 1][wc] = qn;
-    if (bin) bin_atom(a, cl ^ 1, wc, pn);
+    if (bin && k < nf) bin_atom(a, B, c, cl ^ 1, wc, pn);
 }
 
 // Test hook: forces of the working buffer-0 state with the flags it carries;
-// written in canonical order.
+// written at the canonical slots.
 template <int PREC, int L>
 __global__ __launch_bounds__(kBlock) void k_forces(KArgs a, double wv) {
+    const int slot0 = (int)blockIdx.x * (kBlock / L);
+    const int bi = box_of_slot(a, slot0);
+    const Box &B = a.box[bi];
+    const Ctl *c = a.ctl + bi;
     __shared__ CoefLds cf;
     load_coef(cf, a.coef);
     __syncthreads();
     const int lane = threadIdx.x % kWave;
     const int s = lane % L;
-    const int w = (blockIdx.x * kBlock + threadIdx.x) / L;
-    const bool act = w < a.ctl->n_all;
-    const int wc = act ? w : 0;
+    const int w = slot0 + (int)threadIdx.x / L;
+    const bool act = w - B.a0 < c->n_all;
+    const int wc = act ? w : B.a0;
     const double4 pi = a.pos[0][wc];
     const int mi = meta_of(pi);
     double fx = 0.0, fy = 0.0, fz = 0.0;
     if (act && !(mi & kFlyBit))
-        group_force<PREC, L>(a, cf, 0, 0, wc, s, pi, mi, wv, exp(-a.G.kappa * wv), a.fast, 0, fx, fy, fz);
+        group_force<PREC, L>(a, B, c, cf, 0, 0, wc, s, pi, mi, wv, exp(-a.G.kappa * wv), a.fast, 0, fx, fy, fz);
     if (act && s == 0) a.force[a.perm[wc]] = make_double4(fx, fy, fz, 0.0);
 }
 
@@ -857,21 +946,27 @@ __global__ __launch_bounds__(kBlock) void k_forces(KArgs a, double wv) {
 // with a flyer left out.  mode -1: chosen from the move (start: insertion
 // excludes its ghosts; end: deletion excludes the removed pair; else all
 // atoms at w = 0).  Each pair is counted half from each side.
-// which: 0 start of trial, 1 end, 2 observables / test hook.
+// which: 0 start of trial, 1 end, 2 observables / test hook (every box).
+// b < 0: each box's final buffer.
 // ==========================================================================
-__global__ __launch_bounds__(kBlock) void k_energy(KArgs a, int which, int mode, double wv, int b) {
+__global__ __launch_bounds__(kBlock) void k_energy(KArgs a, int which, int mode, double wv, int b0) {
     __shared__ CoefLds cf;
     __shared__ double red[5][kBlock / kWave];
+    const int slot0 = (int)blockIdx.x * (kBlock >> a.lanes_log2);
+    const int bi = box_of_slot(a, slot0);
+    const Box &B = a.box[bi];
+    const Ctl *c = a.ctl + bi;
     load_coef(cf, a.coef);
     __syncthreads();
-    const Ctl *c = a.ctl;
     const int move = c->move;
+    const bool skip = which < 2 && move == 0;
     if (mode < 0) mode = ((which == 0 && move > 0) || (which == 1 && move < 0)) ? 1 : 0;
+    const int b = buf_of(b0, c);
     const int lane = threadIdx.x % kWave;
     const int s = lane & (a.lanes - 1);
     const int w = (blockIdx.x * kBlock + threadIdx.x) >> a.lanes_log2;
     double ulj_s = 0.0, uc_s = 0.0, k_s = 0.0, vir_s = 0.0, fly_s = 0.0;
-    if (w < c->n_all) {
+    if (!skip && w - B.a0 < c->n_all) {
         const double4 *P = a.pos[b];
         const double4 pi = P[w];
         const int mi = meta_of(pi);
@@ -886,9 +981,9 @@ __global__ __launch_bounds__(kBlock) void k_energy(KArgs a, int which, int mode,
             const double4 pj = P[j];
             const int mj = meta_of(pj);
             const bool fj = (mj & kFlyBit) != 0;
-            const double dx = min_image(pi.x - pj.x, a.G.L[0]);
-            const double dy = min_image(pi.y - pj.y, a.G.L[1]);
-            const double dz = min_image(pi.z - pj.z, a.G.L[2]);
+            const double dx = min_image(pi.x - pj.x, B.L[0]);
+            const double dy = min_image(pi.y - pj.y, B.L[1]);
+            const double dz = min_image(pi.z - pj.z, B.L[2]);
             const double r2 = dx * dx + dy * dy + dz * dz;
             const PairCoef &cc = cf.c[ti * kMaxTypes + (mj & kTypeMask)];
             double ulj, uc, fs;
@@ -935,11 +1030,16 @@ __global__ __launch_bounds__(kBlock) void k_energy(KArgs a, int which, int mode,
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_energy_final(KArgs a, int which, int nblocks) {
+// one block per box: sum the box's k_energy blocks in a fixed order
+__global__ __launch_bounds__(kBlock) void k_energy_final(KArgs a, int which) {
     __shared__ double red[5][kBlock];
+    const Box &B = a.box[blockIdx.x];
+    Ctl *c = a.ctl + blockIdx.x;
+    const int P = kBlock >> a.lanes_log2;
+    const int lo = B.a0 / P, hi = (B.a0 + B.cap) / P;
     for (int comp = 0; comp < 5; ++comp) {
         double s = 0.0;
-        for (int q = threadIdx.x; q < nblocks; q += kBlock) s += a.partial[(size_t)q * 5 + comp];
+        for (int q = lo + threadIdx.x; q < hi; q += kBlock) s += a.partial[(size_t)q * 5 + comp];
         red[comp][threadIdx.x] = s;
     }
     __syncthreads();
@@ -949,7 +1049,6 @@ __global__ __launch_bounds__(kBlock) void k_energy_final(KArgs a, int which, int
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        Ctl *c = a.ctl;
         const double U = red[0][0] + red[1][0];
         if (which == 0) { c->U0 = U; c->K0 = red[2][0]; c->Ufly0 = red[4][0]; }
         else if (which == 1) { c->U1 = U; c->K1 = red[2][0]; c->Ufly1 = red[4][0]; }
@@ -958,12 +1057,16 @@ __global__ __launch_bounds__(kBlock) void k_energy_final(KArgs a, int which, int
 }
 
 // ==========================================================================
-// Metropolis test, Eqs. (6) and (8): ln R = -beta dH +- (beta mu + I),
-// I = 2 ln(V / (Lambda_s^3 (N + 1))), N the pair count of the smaller state.
+// Metropolis test, Eqs. (6) and (8), one thread per box:
+// ln R = -beta dH +- (beta mu + I), I = 2 ln(V / (Lambda_s^3 (N + 1))),
+// N the pair count of the smaller state.
 // ==========================================================================
 __global__ void k_metropolis(KArgs a) {
-    Ctl *c = a.ctl;
-    TrialRec *r = a.rec;
+    const int bi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (bi >= a.nbox) return;
+    const Box &B = a.box[bi];
+    Ctl *c = a.ctl + bi;
+    TrialRec *r = a.rec + bi;
     const int move = c->move;
     r->trial = c->trial;
     r->n_atoms = c->n;
@@ -978,7 +1081,7 @@ __global__ void k_metropolis(KArgs a) {
     if (c->err & (kErrNbr | kErrCell | kErrSkin | kErrCap | kErrFast)) c->retry = 1;
     if (move == 0) {
         r->move = -1;
-        r->flags = c->retry ? 0u : 1u;   // H4D_FLAG_EMPTY
+        r->flags = c->idle ? kFlagIdle : (c->retry ? 0u : kFlagEmpty);
         r->tag_c = r->tag_a = -1;
         r->dH = r->dU = r->dK = r->W_prot = r->E_switch = r->dM = 0.0;
         r->ln_ratio = -INFINITY;
@@ -991,7 +1094,7 @@ __global__ void k_metropolis(KArgs a) {
     const double H0 = c->U0 + c->K0, H1 = c->U1 + c->K1;
     const double dH = H1 - H0;
     const int n_small = move > 0 ? c->nsalt : c->nsalt - 1;
-    const double I = 2.0 * log(a.G.volume / (a.G.lambda3 * (double)(n_small + 1)));
+    const double I = 2.0 * log(B.volume / (a.G.lambda3 * (double)(n_small + 1)));
     const double lnR = move > 0 ? -a.G.beta * dH + a.G.beta_mu + I : -a.G.beta * dH - a.G.beta_mu - I;
     r->dH = dH; r->dU = c->U1 - c->U0; r->dK = c->K1 - c->K0;
     r->H0 = H0; r->H1 = H1;
@@ -1000,7 +1103,7 @@ __global__ void k_metropolis(KArgs a) {
     r->dM = move > 0 ? dH - I / a.G.beta : -dH - I / a.G.beta;
     r->ln_ratio = lnR;
     int acc = 0;
-    if (!isfinite(dH)) r->flags |= 2u;   // H4D_FLAG_NONFINITE
+    if (!isfinite(dH)) r->flags |= kFlagNonfinite;
     else acc = r->ln_u < lnR;
     if (c->retry) acc = 0;
     r->accepted = acc;
@@ -1010,17 +1113,19 @@ __global__ void k_metropolis(KArgs a) {
 // Commit (accepted: the working positions go back to canonical order, ghosts
 // become physical, a deleted pair is compacted out) or roll back (the
 // canonical arrays are the snapshot; only a deletion's flags are cleared).
-__global__ __launch_bounds__(kBlock) void k_commit(KArgs a, int bf) {
-    const Ctl *c = a.ctl;
+__global__ __launch_bounds__(kBlock) void k_commit(KArgs a) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const int bi = box_of_slot(a, i);
+    const Box &B = a.box[bi];
+    const Ctl *c = a.ctl + bi;
     const int move = c->move;
     if (move == 0) return;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
     if (c->accepted) {
-        if (i < c->n_all) {
-            const double4 p = a.pos[bf][i];
+        if (i - B.a0 < c->n_all) {
+            const double4 p = a.pos[buf_of(-1, c)][i];
             a.cpos[a.perm[i]] = with_meta(p.x, p.y, p.z, meta_of(p) & kTypeMask);
         }
-    } else if (move < 0 && i == 0) {
+    } else if (move < 0 && i == B.a0) {
         double4 p = a.cpos[c->ic];
         a.cpos[c->ic] = with_meta(p.x, p.y, p.z, meta_of(p) & ~kFlyBit);
         p = a.cpos[c->ia];
@@ -1030,11 +1135,13 @@ __global__ __launch_bounds__(kBlock) void k_commit(KArgs a, int bf) {
 
 // accepted deletion: stable compaction of the canonical arrays without the pair
 __global__ __launch_bounds__(kBlock) void k_compact1(KArgs a) {
-    const Ctl *c = a.ctl;
-    if (!(c->accepted && c->move < 0)) return;
     const int i = blockIdx.x * kBlock + threadIdx.x;
+    const int bi = box_of_slot(a, i);
+    const Box &B = a.box[bi];
+    const Ctl *c = a.ctl + bi;
+    if (!(c->accepted && c->move < 0)) return;
     const int ic = c->ic, ia = c->ia;
-    if (i < c->n_all && i != ic && i != ia) {
+    if (i - B.a0 < c->n_all && i != ic && i != ia) {
         const int d = i - (i > ic) - (i > ia);
         a.tpos[d] = a.cpos[i];
         a.ttag[d] = a.ctag[i];
@@ -1044,10 +1151,12 @@ __global__ __launch_bounds__(kBlock) void k_compact1(KArgs a) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_compact2(KArgs a) {
-    const Ctl *c = a.ctl;
-    if (!(c->accepted && c->move < 0)) return;
     const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < c->n_all - 2) {
+    const int bi = box_of_slot(a, i);
+    const Box &B = a.box[bi];
+    const Ctl *c = a.ctl + bi;
+    if (!(c->accepted && c->move < 0)) return;
+    if (i - B.a0 < c->n_all - 2) {
         a.cpos[i] = a.tpos[i];
         a.ctag[i] = a.ttag[i];
         a.ctype[i] = a.ttype[i];
@@ -1056,27 +1165,39 @@ __global__ __launch_bounds__(kBlock) void k_compact2(KArgs a) {
 }
 
 __global__ void k_commit_ctl(KArgs a) {
-    Ctl *c = a.ctl;
-    TrialRec *r = a.rec;
+    const int bi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (bi >= a.nbox) return;
+    Ctl *c = a.ctl + bi;
+    TrialRec *r = a.rec + bi;
     if (c->accepted) {
         if (c->move > 0) { c->n += 2; c->nsalt += 1; c->next_tag += 2; }
         else { c->n -= 2; c->nsalt -= 1; }
     }
     c->n_all = c->n;
     r->n_salt_after = c->nsalt;
-    if (!c->retry) c->trial += 1;
+    if (!c->retry && !c->idle) c->trial += 1;
 }
 
-// Sum of list lengths of the current state (for the roofline byte count).
+// Every box runs `count` more trials and then idles (count < 0: no limit).
+__global__ void k_set_quota(KArgs a, long long count) {
+    const int bi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (bi >= a.nbox) return;
+    Ctl *c = a.ctl + bi;
+    c->trial_end = count < 0 ? 0x7fffffffffffffffLL : c->trial + count;
+}
+
+// Sum of list lengths of the current states (for the roofline byte count).
 __global__ __launch_bounds__(kBlock) void k_sum_nbr(KArgs a, unsigned long long *out) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
-    unsigned long long v = (i < a.ctl->n_all) ? (unsigned long long)a.nnbr[i] : 0ull;
+    const int bi = box_of_slot(a, i);
+    const Box &B = a.box[bi];
+    unsigned long long v = (i - B.a0 < a.ctl[bi].n_all) ? (unsigned long long)a.nnbr[i] : 0ull;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
     if ((threadIdx.x % kWave) == 0) atomicAdd(out, v);
 }
 
-// Test hooks on the canonical state: flag an atom as flying or not.
+// Test hooks on the canonical state: flag an atom slot as flying or not.
 __global__ void k_set_fly(KArgs a, int i, int on) {
     double4 p = a.cpos[i];
     int m = meta_of(p);
@@ -1165,19 +1286,21 @@ __device__ __forceinline__ void settle_positions(const Geo &G, const d3 &a0, con
     a1 = out[0]; b1 = out[1]; c1 = out[2];
 }
 
-__device__ __forceinline__ d3 unwrap_near(const Geo &G, const double4 &p, const d3 &ref) {
-    return mk(ref.x + min_image(p.x - ref.x, G.L[0]), ref.y + min_image(p.y - ref.y, G.L[1]),
-              ref.z + min_image(p.z - ref.z, G.L[2]));
+__device__ __forceinline__ d3 unwrap_near(const Box &B, const double4 &p, const d3 &ref) {
+    return mk(ref.x + min_image(p.x - ref.x, B.L[0]), ref.y + min_image(p.y - ref.y, B.L[1]),
+              ref.z + min_image(p.z - ref.z, B.L[2]));
 }
 
+// Rigid waters belong to a single-box system (box 0, slots from 0).
 // trial start: project the freshly drawn water velocities (working buffer 0)
 __global__ __launch_bounds__(kBlock) void k_rattle_mb(KArgs a) {
     const int m = blockIdx.x * kBlock + threadIdx.x;
     if (m >= a.G.n_mol) return;
+    const Box &B = a.box[0];
     const int w[3] = {a.molw[3 * m], a.molw[3 * m + 1], a.molw[3 * m + 2]};
     const double4 pa = a.pos[0][w[0]];
     const d3 ra_ = mk(pa.x, pa.y, pa.z);
-    const d3 x1 = unwrap_near(a.G, a.pos[0][w[1]], ra_), x2 = unwrap_near(a.G, a.pos[0][w[2]], ra_);
+    const d3 x1 = unwrap_near(B, a.pos[0][w[1]], ra_), x2 = unwrap_near(B, a.pos[0][w[2]], ra_);
     double4 v4[3] = {a.vel[0][w[0]], a.vel[0][w[1]], a.vel[0][w[2]]};
     d3 v[3];
     for (int i = 0; i < 3; ++i) v[i] = mk(v4[i].x, v4[i].y, v4[i].z);
@@ -1189,6 +1312,7 @@ __global__ __launch_bounds__(kBlock) void k_rattle_mb(KArgs a) {
 // v_k = v + h F/m and the velocity constraint (k > 0); v += h F/m, drift and
 // position constraint with its velocity correction (k < nf).
 __global__ __launch_bounds__(kBlock) void k_settle(KArgs a, int k, int b, int bin, int cl) {
+    const Box &B = a.box[0];
     Ctl *c = a.ctl;
     const int move = c->move, nf = c->nf;
     if (move == 0 || k > nf) return;
@@ -1198,8 +1322,8 @@ __global__ __launch_bounds__(kBlock) void k_settle(KArgs a, int k, int b, int bi
     const int w[3] = {a.molw[3 * m], a.molw[3 * m + 1], a.molw[3 * m + 2]};
     double4 p4[3], v4[3], f4[3];
     for (int i = 0; i < 3; ++i) { p4[i] = a.pos[b][w[i]]; v4[i] = a.vel[b][w[i]]; f4[i] = a.fw[w[i]]; }
-    const d3 x0[3] = {mk(p4[0].x, p4[0].y, p4[0].z), unwrap_near(G, p4[1], mk(p4[0].x, p4[0].y, p4[0].z)),
-                      unwrap_near(G, p4[2], mk(p4[0].x, p4[0].y, p4[0].z))};
+    const d3 x0[3] = {mk(p4[0].x, p4[0].y, p4[0].z), unwrap_near(B, p4[1], mk(p4[0].x, p4[0].y, p4[0].z)),
+                      unwrap_near(B, p4[2], mk(p4[0].x, p4[0].y, p4[0].z))};
     d3 v[3];
     double hm[3];
     for (int i = 0; i < 3; ++i) {
@@ -1223,10 +1347,10 @@ __global__ __launch_bounds__(kBlock) void k_settle(KArgs a, int k, int b, int bi
     }
     const int lw = (k + 1) % 3;
     for (int i = 0; i < 3; ++i) {
-        const double px = wrap_coord(x[i].x, G.L[0]), py = wrap_coord(x[i].y, G.L[1]), pz = wrap_coord(x[i].z, G.L[2]);
+        const double px = wrap_coord(x[i].x, B.L[0]), py = wrap_coord(x[i].y, B.L[1]), pz = wrap_coord(x[i].z, B.L[2]);
         int mo = meta_of(p4[i]);
-        uint4 qn = fixed_of(G, px, py, pz, mo);
-        if ((mo & kFastBit) == 0 && moved_beyond_half_skin(a, qn, a.posb[w[i]])) mo |= kFastBit;
+        uint4 qn = fixed_of(B, px, py, pz, mo);
+        if ((mo & kFastBit) == 0 && moved_beyond_half_skin(a, B, qn, a.posb[w[i]])) mo |= kFastBit;
         if (mo & kFastBit) {
             const int slot = atomicAdd(&c->nfast[lw], 1);
             if (slot < kFastCap) a.fast[lw * kFastCap + slot] = w[i];
@@ -1238,7 +1362,7 @@ __global__ __launch_bounds__(kBlock) void k_settle(KArgs a, int k, int b, int bi
         a.pos[b ^ 1][w[i]] = pn;
         a.fx[b ^ 1][w[i]] = qn;
         a.vel[b ^ 1][w[i]] = make_double4(v[i].x, v[i].y, v[i].z, 0.0);
-        if (bin) bin_atom(a, cl ^ 1, w[i], pn);
+        if (bin && k < nf) bin_atom(a, B, c, cl ^ 1, w[i], pn);
     }
 }
 

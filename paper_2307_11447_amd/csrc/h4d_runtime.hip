@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <map>
 #include <tuple>
 #include <cmath>
@@ -47,13 +48,16 @@ struct h4d_system {
     hipStream_t stream = nullptr;
     KArgs a{};
     PairCoef coef_h[kMaxTypes * kMaxTypes]{};
-    int cap = 0;
-    int n_host = 0, nsalt_host = 0, n_mol = 0;
+    int nbox = 1;
+    bool cells = true;          // every box has >= 3 list cells per edge
+    std::vector<Box> box_h;
+    std::vector<int> n_host, nsalt_host;   // per box, after the last round
+    int n_mol = 0;
     int rebuild_every = 1;
     int clean_trials = 0;
     int partial_blocks = 0;
-    TrialRec *h_rec = nullptr;
-    Ctl *h_ctl = nullptr;
+    TrialRec *h_rec = nullptr;  // per box (pinned)
+    Ctl *h_ctl = nullptr;       // per box (pinned)
     // step-kernel timing
     bool timing = false;
     std::vector<hipEvent_t> ev;
@@ -61,17 +65,19 @@ struct h4d_system {
     double step_ms = 0.0;
     int trial_rebuilds = 0;
     int64_t retries = 0;
-    int trial_M = 1;            // rebuild interval of the trial being run
+    int trial_M = 1;            // rebuild interval of the round being run
     int cl = 0;                 // cell buffer of the current list (the next binning uses cl ^ 1)
-    // captured trial graphs, keyed by launch shape; dropped when buffers move
+    // captured round graphs, keyed by launch shape; dropped when buffers move
     hipStream_t cap_stream = nullptr;
-    std::map<std::tuple<int, int, int, int, int, int, int>, hipGraphExec_t> graphs;
-    bool graphs_ok[2] = {true, false};  // timed trials launch eagerly (events per step kernel)
-    int last_buf = 0;           // working buffer that holds the last trajectory's end
+    std::map<std::tuple<int, int, int, int, int>, hipGraphExec_t> graphs;
+    bool graphs_ok[2] = {true, false};  // timed rounds launch eagerly (events per step kernel)
     std::vector<void *> allocs;
-    // running statistics (Eq. 1)
-    int64_t n_trials = 0, n_ins = 0, n_ins_acc = 0, n_del = 0, n_del_acc = 0;
-    double N_sum = 0.0, N2_sum = 0.0;
+    // running statistics per box (Eq. 1)
+    struct Stats {
+        int64_t n_trials = 0, n_ins = 0, n_ins_acc = 0, n_del = 0, n_del_acc = 0;
+        double N_sum = 0.0, N2_sum = 0.0;
+    };
+    std::vector<Stats> stats;
 
     template <class T>
     int alloc(T **ptr, size_t count) {
@@ -125,26 +131,18 @@ int check_params(const h4d_params &p) {
     if (!(p.rc_lj > 0.0) || !(p.rc_coul > 0.0) || !(p.skin >= 0.0) || !(p.w_max >= 0.0) ||
         !(p.dsf_alpha >= 0.0))
         return fail(H4D_EINVAL, "cutoffs must be positive, skin, w_max and dsf_alpha non-negative");
-    const double rc = std::max(p.rc_lj, p.rc_coul);
-    for (int d = 0; d < 3; ++d)
-        if (!(p.box[d] >= 2.0 * rc))
-            return fail(H4D_EINVAL, "every box edge must be at least twice the largest cutoff");
     if (p.water && !(p.d_oh > 0.0 && p.d_hh > 0.0 && p.d_hh < 2.0 * p.d_oh))
         return fail(H4D_EINVAL, "rigid water needs 0 < d_hh < 2 d_oh");
     return H4D_OK;
 }
 
+double rlist_of(const h4d_params &p) { return std::max(p.rc_lj, p.rc_coul) + p.skin; }
+
 void setup_geo(h4d_system *s) {
     const h4d_params &p = s->p;
     Geo &G = s->a.G;
-    const double two32 = 4294967296.0;
-    for (int d = 0; d < 3; ++d) {
-        G.L[d] = p.box[d];
-        G.fx_inv[d] = two32 / p.box[d];
-        G.fx_scale[d] = (float)(p.box[d] / two32);
-    }
     const double rc = std::max(p.rc_lj, p.rc_coul);
-    const double rlist = rc + p.skin;
+    const double rlist = rlist_of(p);
     G.rc_lj2 = p.rc_lj * p.rc_lj;
     G.rc_c2 = p.rc_coul * p.rc_coul;
     G.rc_max2 = rc * rc;
@@ -175,16 +173,9 @@ void setup_geo(h4d_system *s) {
     G.kT = p.kT;
     G.w_max = p.w_max;
     G.kappa = p.kappa_sr;
-    G.volume = p.box[0] * p.box[1] * p.box[2];
     G.lambda3 = p.lambda_s * p.lambda_s * p.lambda_s;
     G.beta = 1.0 / p.kT;
     G.beta_mu = p.beta_mu;
-    G.use_cells = 1;
-    for (int d = 0; d < 3; ++d) {
-        G.ncell[d] = (int)std::floor(p.box[d] / rlist);
-        if (G.ncell[d] < 3) G.use_cells = 0;
-    }
-    if (!G.use_cells) G.ncell[0] = G.ncell[1] = G.ncell[2] = 1;
     G.n_types = p.n_types;
     G.water = p.water;
     G.d_oh = p.d_oh;
@@ -209,28 +200,72 @@ void setup_geo(h4d_system *s) {
         }
 }
 
-// Neighbour and cell capacities from the density (grown on overflow).
-void initial_capacities(h4d_system *s, int n) {
+int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+// Geometry and placement of every box: slots [a0, a0 + cap), cells [c0, c0 + nc).
+int setup_boxes(h4d_system *s, const double *edges, const int32_t *n_atoms) {
     const h4d_params &p = s->p;
-    const double V = p.box[0] * p.box[1] * p.box[2];
-    const double rho = std::max(1.0, (double)n) / V;
-    const double rlist = std::max(p.rc_lj, p.rc_coul) + p.skin;
-    const double nb = 4.18879020478639 * rlist * rlist * rlist * rho;
-    int cap = (int)(1.5 * nb) + 32;
-    cap = std::min(cap, s->cap + kMaxLanes);
-    s->a.nbr_cap = (cap + kMaxLanes - 1) / kMaxLanes * kMaxLanes;
-    const Geo &G = s->a.G;
-    const double cell_vol = V / ((double)G.ncell[0] * G.ncell[1] * G.ncell[2]);
-    int cc = (int)(1.6 * rho * cell_vol) + 16;
-    s->a.cell_cap = G.use_cells ? std::min(cc, std::max(32, s->cap)) : s->cap;
-    s->a.ncell_total = G.ncell[0] * G.ncell[1] * G.ncell[2];
+    const double rlist = rlist_of(p);
+    const double rc = std::max(p.rc_lj, p.rc_coul);
+    const double two32 = 4294967296.0;
+    s->box_h.assign(s->nbox, Box{});
+    int a0 = 0, c0 = 0, n_cells = 0, n_pairs = 0;
+    for (int b = 0; b < s->nbox; ++b) {
+        Box &B = s->box_h[b];
+        const int n = n_atoms[b];
+        for (int d = 0; d < 3; ++d) {
+            const double L = edges[3 * b + d];
+            if (!(L >= 2.0 * rc)) return fail(H4D_EINVAL, "every box edge must be at least twice the largest cutoff");
+            B.L[d] = L;
+            B.fx_inv[d] = two32 / L;
+            B.fx_scale[d] = (float)(L / two32);
+            B.ncell[d] = (int)std::floor(L / rlist);
+        }
+        B.use_cells = B.ncell[0] >= 3 && B.ncell[1] >= 3 && B.ncell[2] >= 3;
+        if (!B.use_cells) B.ncell[0] = B.ncell[1] = B.ncell[2] = 1;
+        (B.use_cells ? n_cells : n_pairs) += 1;
+        int cap = p.capacity > 0 ? p.capacity : n + std::max(1024, n / 8);
+        if (cap < n + 2) return fail(H4D_EINVAL, "capacity below n_atoms + 2");
+        cap = round_up(cap, kBlock);
+        if (!B.use_cells && cap > 8192)
+            return fail(H4D_EINVAL, "a box with fewer than 3 list cells per edge is limited to 8192 atoms");
+        B.a0 = a0;
+        B.cap = cap;
+        B.c0 = c0;
+        B.nc = B.ncell[0] * B.ncell[1] * B.ncell[2];
+        B.volume = B.L[0] * B.L[1] * B.L[2];
+        B.stream = p.stream + (uint64_t)b;
+        a0 += cap;
+        c0 += B.nc;
+        if (a0 > (1 << 30)) return fail(H4D_EINVAL, "too many atom slots");
+    }
+    if (n_cells && n_pairs)
+        return fail(H4D_EINVAL, "the boxes of a batch must all have >= 3 list cells per edge, or all fewer");
+    s->cells = n_cells > 0;
+    s->a.slots = a0;
+    s->a.ncell_total = c0;
+    s->a.nbox = s->nbox;
+    return H4D_OK;
 }
 
-size_t nbr_elems(const h4d_system *s) {
-    const int A = kWave / s->a.lanes;
-    const size_t groups = (size_t)(s->cap + A - 1) / A;
-    return groups * (size_t)(s->a.nbr_cap / s->a.lanes) * kWave;
+// Neighbour and cell capacities from the densest box (grown on overflow).
+void initial_capacities(h4d_system *s, const int32_t *n_atoms) {
+    const h4d_params &p = s->p;
+    const double rlist = rlist_of(p);
+    int nbr = 32, cc = 32, capmax = 0;
+    for (int b = 0; b < s->nbox; ++b) {
+        const Box &B = s->box_h[b];
+        const double rho = std::max(1.0, (double)n_atoms[b]) / B.volume;
+        const double nb = 4.18879020478639 * rlist * rlist * rlist * rho;
+        nbr = std::max(nbr, std::min((int)(1.5 * nb) + 32, B.cap + kMaxLanes));
+        cc = std::max(cc, (int)(1.6 * rho * B.volume / B.nc) + 16);
+        capmax = std::max(capmax, B.cap);
+    }
+    s->a.nbr_cap = round_up(nbr, kMaxLanes);
+    s->a.cell_cap = s->cells ? std::min(cc, std::max(32, capmax)) : capmax;
 }
+
+size_t nbr_elems(const h4d_system *s) { return (size_t)s->a.slots * (size_t)s->a.nbr_cap; }
 
 int alloc_lists(h4d_system *s) {
     int rc;
@@ -240,114 +275,146 @@ int alloc_lists(h4d_system *s) {
         if ((rc = s->alloc(&s->a.cell_atoms[q], (size_t)s->a.ncell_total * s->a.cell_cap))) return rc;
         HIPC(hipMemset(s->a.cell_cnt[q], 0, sizeof(int) * s->a.ncell_total));
     }
-    if ((rc = s->alloc(&s->a.cell_off, (size_t)s->a.ncell_total + 1))) return rc;
-    if ((rc = s->alloc(&s->a.fast, (size_t)3 * kFastCap))) return rc;
+    if ((rc = s->alloc(&s->a.cell_off, (size_t)s->a.ncell_total))) return rc;
+    if ((rc = s->alloc(&s->a.fast, (size_t)s->nbox * 3 * kFastCap))) return rc;
     return H4D_OK;
 }
 
-int atom_blocks_l(int n, int lanes) { return std::max(1, (n * lanes + kBlock - 1) / kBlock); }
+void set_lanes(h4d_system *s, int L) {
+    s->a.lanes = L;
+    s->a.lanes_log2 = L == 4 ? 2 : (L == 8 ? 3 : 4);
+    s->a.step_blocks = s->a.slots / (kBlock / L);
+}
+
+int slot_blocks(const h4d_system *s) { return s->a.slots / kBlock; }
 
 size_t list_cells_lds(const h4d_system *s) { return (size_t)s->a.cell_cap * 27 * sizeof(uint4); }
 
-void launch_list(h4d_system *s, int b, int cb, int n_all_max, hipStream_t st) {
+// list build; k and b as in list_wanted / buf_of
+void launch_list(h4d_system *s, int k, int b, int cb, hipStream_t st) {
     KArgs &a = s->a;
-    if (a.G.use_cells && list_cells_lds(s) <= 56 * 1024)
-        hipLaunchKernelGGL(k_list_cells, dim3(a.ncell_total), dim3(kBlock), list_cells_lds(s), st, a, b, cb);
-    else if (a.G.use_cells)
-        hipLaunchKernelGGL(k_list_lanes, dim3(atom_blocks_l(n_all_max, a.lanes)), dim3(kBlock), 0, st, a, b, cb);
+    if (s->cells && list_cells_lds(s) <= 56 * 1024)
+        hipLaunchKernelGGL(k_list_cells, dim3(a.ncell_total), dim3(kBlock), list_cells_lds(s), st, a, k, b, cb);
+    else if (s->cells)
+        hipLaunchKernelGGL(k_list_lanes, dim3(a.step_blocks), dim3(kBlock), 0, st, a, k, b, cb);
     else
-        hipLaunchKernelGGL(k_list_allpairs, dim3(atom_blocks_l(n_all_max, a.lanes)), dim3(kBlock), 0, st, a, b, cb);
+        hipLaunchKernelGGL(k_list_allpairs, dim3(a.step_blocks), dim3(kBlock), 0, st, a, k, b, cb);
 }
 
 template <int PREC, int L>
-void launch_step_l(h4d_system *s, hipStream_t st, int G, hipEvent_t e0, hipEvent_t e1, int k, int b, int bin) {
+void launch_step_l(h4d_system *s, hipStream_t st, hipEvent_t e0, hipEvent_t e1, int k, int b, int bin) {
     KArgs &a = s->a;
-    if (e0) hipExtLaunchKernelGGL(k_step<PREC, L>, dim3(G), dim3(kBlock), 0, st, e0, e1, 0, a, k, b, bin, s->cl);
-    else hipLaunchKernelGGL((k_step<PREC, L>), dim3(G), dim3(kBlock), 0, st, a, k, b, bin, s->cl);
+    const dim3 grid(a.step_blocks + s->nbox);
+    if (e0) hipExtLaunchKernelGGL(k_step<PREC, L>, grid, dim3(kBlock), 0, st, e0, e1, 0, a, k, b, bin, s->cl);
+    else hipLaunchKernelGGL((k_step<PREC, L>), grid, dim3(kBlock), 0, st, a, k, b, bin, s->cl);
 }
 
 template <int PREC>
-void launch_step(h4d_system *s, hipStream_t st, int G, hipEvent_t e0, hipEvent_t e1, int k, int b, int bin) {
+void launch_step(h4d_system *s, hipStream_t st, hipEvent_t e0, hipEvent_t e1, int k, int b, int bin) {
     switch (s->a.lanes) {
-        case 4: launch_step_l<PREC, 4>(s, st, G, e0, e1, k, b, bin); break;
-        case 8: launch_step_l<PREC, 8>(s, st, G, e0, e1, k, b, bin); break;
-        default: launch_step_l<PREC, 16>(s, st, G, e0, e1, k, b, bin); break;
+        case 4: launch_step_l<PREC, 4>(s, st, e0, e1, k, b, bin); break;
+        case 8: launch_step_l<PREC, 8>(s, st, e0, e1, k, b, bin); break;
+        default: launch_step_l<PREC, 16>(s, st, e0, e1, k, b, bin); break;
     }
 }
 
 template <int PREC>
-void launch_forces(h4d_system *s, int G, double w) {
+void launch_forces(h4d_system *s, double w) {
     KArgs &a = s->a;
+    const dim3 grid(a.step_blocks);
     switch (a.lanes) {
-        case 4: hipLaunchKernelGGL((k_forces<PREC, 4>), dim3(G), dim3(kBlock), 0, s->stream, a, w); break;
-        case 8: hipLaunchKernelGGL((k_forces<PREC, 8>), dim3(G), dim3(kBlock), 0, s->stream, a, w); break;
-        default: hipLaunchKernelGGL((k_forces<PREC, 16>), dim3(G), dim3(kBlock), 0, s->stream, a, w); break;
+        case 4: hipLaunchKernelGGL((k_forces<PREC, 4>), grid, dim3(kBlock), 0, s->stream, a, w); break;
+        case 8: hipLaunchKernelGGL((k_forces<PREC, 8>), grid, dim3(kBlock), 0, s->stream, a, w); break;
+        default: hipLaunchKernelGGL((k_forces<PREC, 16>), grid, dim3(kBlock), 0, s->stream, a, w); break;
     }
 }
 
 // Sort the canonical atoms into cell order (working buffer 0), draw the
-// momenta of the current trial index, and build the list (cell buffer 0).
-int sort_in(h4d_system *s, int n_all_max, hipStream_t st) {
+// momenta of each box's current trial index, and build the lists (cell
+// buffer 0).
+int sort_in(h4d_system *s, hipStream_t st) {
     KArgs &a = s->a;
-    const int G1 = blocks_for(n_all_max);
     const int nc = a.ncell_total;
     hipLaunchKernelGGL(k_cell_clear, dim3(blocks_for(nc)), dim3(kBlock), 0, st, a, 0);
-    hipLaunchKernelGGL(k_bin_canonical, dim3(G1), dim3(kBlock), 0, st, a, 0);
+    hipLaunchKernelGGL(k_bin_canonical, dim3(slot_blocks(s)), dim3(kBlock), 0, st, a, 0);
     hipLaunchKernelGGL(k_cell_sort, dim3(nc), dim3(kWave), a.cell_cap * sizeof(int), st, a, 0);
-    hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, st, a, 0);
+    hipLaunchKernelGGL(k_cell_scan, dim3(s->nbox), dim3(1024), 0, st, a, 0);
     hipLaunchKernelGGL(k_gather_in, dim3(nc), dim3(kWave), 0, st, a, 0);
     if (a.G.water) hipLaunchKernelGGL(k_rattle_mb, dim3(blocks_for(a.G.n_mol)), dim3(kBlock), 0, st, a);
-    launch_list(s, 0, 0, n_all_max, st);
+    launch_list(s, -1, 0, 0, st);
     s->cl = 0;
     HIPC(hipGetLastError());
     return H4D_OK;
 }
 
-// Mid-trajectory rebuild: the preceding step binned the atoms into cell
-// buffer cl ^ 1.
-int rebuild_mid(h4d_system *s, int b, int n_all_max, hipStream_t st) {
+// Rebuild before step k: the preceding step binned the atoms of every box
+// still running into cell buffer cl ^ 1.
+int rebuild_mid(h4d_system *s, int k, int b, hipStream_t st) {
     KArgs &a = s->a;
     const int cb = s->cl ^ 1;
-    if (a.G.use_cells)
+    if (s->cells)
         hipLaunchKernelGGL(k_cell_sort, dim3(a.ncell_total), dim3(kWave), a.cell_cap * sizeof(int), st, a, cb);
-    launch_list(s, b, cb, n_all_max, st);
+    launch_list(s, k, b, cb, st);
+    s->cl = cb;
+    HIPC(hipGetLastError());
+    return H4D_OK;
+}
+
+// End of the trajectories: lists of every box with a trajectory at its final
+// state (no fast atoms), for the end energy.
+int rebuild_final(h4d_system *s, hipStream_t st) {
+    KArgs &a = s->a;
+    const int cb = s->cl ^ 1;
+    if (s->cells) {
+        hipLaunchKernelGGL(k_cell_clear, dim3(blocks_for(a.ncell_total)), dim3(kBlock), 0, st, a, cb);
+        hipLaunchKernelGGL(k_bin_working, dim3(slot_blocks(s)), dim3(kBlock), 0, st, a, cb);
+        hipLaunchKernelGGL(k_cell_sort, dim3(a.ncell_total), dim3(kWave), a.cell_cap * sizeof(int), st, a, cb);
+    }
+    launch_list(s, -2, -1, cb, st);
     s->cl = cb;
     HIPC(hipGetLastError());
     return H4D_OK;
 }
 
 int read_ctl(h4d_system *s) {
-    HIPC(hipMemcpyAsync(s->h_ctl, s->a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s->stream));
+    HIPC(hipMemcpyAsync(s->h_ctl, s->a.ctl, sizeof(Ctl) * s->nbox, hipMemcpyDeviceToHost, s->stream));
+    HIPC(hipStreamSynchronize(s->stream));
+    return H4D_OK;
+}
+
+int write_ctl(h4d_system *s) {
+    HIPC(hipMemcpyAsync(s->a.ctl, s->h_ctl, sizeof(Ctl) * s->nbox, hipMemcpyHostToDevice, s->stream));
     HIPC(hipStreamSynchronize(s->stream));
     return H4D_OK;
 }
 
 int clear_errors(h4d_system *s) {
-    Ctl *c = s->h_ctl;
-    c->err = 0;
-    c->retry = 0;
-    c->max_nbr = 0;
-    c->max_cell = 0;
-    HIPC(hipMemcpyAsync(s->a.ctl, c, sizeof(Ctl), hipMemcpyHostToDevice, s->stream));
-    HIPC(hipStreamSynchronize(s->stream));
-    return H4D_OK;
+    int rc = read_ctl(s);
+    if (rc) return rc;
+    for (int b = 0; b < s->nbox; ++b) {
+        Ctl *c = s->h_ctl + b;
+        c->err = 0;
+        c->retry = 0;
+        c->max_nbr = 0;
+        c->max_cell = 0;
+    }
+    return write_ctl(s);
 }
 
-// Grow the list storage after an overflow.
-int grow_lists(h4d_system *s, unsigned err) {
+// Grow the list storage after an overflow in any box.
+int grow_lists(h4d_system *s, unsigned err, int max_nbr, int max_cell) {
     KArgs &a = s->a;
-    const Ctl *c = s->h_ctl;
     if (err & kErrNbr) {
-        int need = std::max(c->max_nbr, a.nbr_cap + kMaxLanes);
+        int need = std::max(max_nbr, a.nbr_cap + kMaxLanes);
         need = (int)(need * 1.25) + kMaxLanes;
-        need = (need + kMaxLanes - 1) / kMaxLanes * kMaxLanes;
+        need = round_up(need, kMaxLanes);
         s->release(a.nbr);
         a.nbr_cap = need;
         int rc = s->alloc(&a.nbr, nbr_elems(s));
         if (rc) return rc;
     }
     if (err & kErrCell) {
-        int need = std::max(c->max_cell, a.cell_cap + 8);
+        int need = std::max(max_cell, a.cell_cap + 8);
         need = (int)(need * 1.25) + 8;
         s->release(a.cell_atoms[0]);
         s->release(a.cell_atoms[1]);
@@ -359,53 +426,49 @@ int grow_lists(h4d_system *s, unsigned err) {
     return H4D_OK;
 }
 
-// Enqueue every kernel of one trial on st (the trial's shape is fixed by the
-// host-side atom bound, the rebuild interval and N_f; the kernels read
-// everything else from the control block).  With timing, HIP events bracket
-// each step kernel.
-int enqueue_trial(h4d_system *s, int move, hipStream_t st, int nf, int M, bool timing) {
+// Enqueue every kernel of one round (each box's current trial) on st.  The
+// round's shape is fixed by the rebuild interval and the largest N_f; the
+// kernels read everything else from the control blocks.  With timing, HIP
+// events bracket each step kernel.
+int enqueue_round(h4d_system *s, int move, hipStream_t st, int nf, int M, bool timing) {
     KArgs &a = s->a;
-    const int n_all_max = s->n_host + 2;
-    const int G = blocks_for(n_all_max);                 // one thread per atom
-    const int GA = atom_blocks_l(n_all_max, a.lanes);    // lanes threads per atom
+    const int G1 = slot_blocks(s);
     int rc;
-    hipLaunchKernelGGL(k_propose, dim3(1), dim3(kBlock), 0, st, a, move);
-    if ((rc = sort_in(s, n_all_max, st))) return rc;
-    hipLaunchKernelGGL(k_energy, dim3(GA), dim3(kBlock), 0, st, a, 0, -1, 0.0, 0);
-    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kBlock), 0, st, a, 0, GA);
+    hipLaunchKernelGGL(k_propose, dim3(s->nbox), dim3(kBlock), 0, st, a, move);
+    if ((rc = sort_in(s, st))) return rc;
+    hipLaunchKernelGGL(k_energy, dim3(a.step_blocks), dim3(kBlock), 0, st, a, 0, -1, 0.0, 0);
+    hipLaunchKernelGGL(k_energy_final, dim3(s->nbox), dim3(kBlock), 0, st, a, 0);
     int b = 0;
-    const bool final_rebuild = nf % M != 0;   // the end energy needs a list without fast atoms
     for (int k = 0; k <= nf; ++k) {
         if (k > 0 && k % M == 0)
-            if ((rc = rebuild_mid(s, b, n_all_max, st))) return rc;
-        const int bin = !a.G.use_cells ? 0 : ((k + 1) % M == 0 && k + 1 <= nf ? 1 : (k == nf && final_rebuild ? 1 : 0));
+            if ((rc = rebuild_mid(s, k, b, st))) return rc;
+        const int bin = s->cells && (k + 1) % M == 0 && k + 1 <= nf;
         hipEvent_t e0 = timing ? s->ev[2 * k] : nullptr, e1 = timing ? s->ev[2 * k + 1] : nullptr;
-        if (s->p.precision == H4D_PREC_FP32) launch_step<1>(s, st, GA + 1, e0, e1, k, b, bin);
-        else launch_step<0>(s, st, GA + 1, e0, e1, k, b, bin);
+        if (s->p.precision == H4D_PREC_FP32) launch_step<1>(s, st, e0, e1, k, b, bin);
+        else launch_step<0>(s, st, e0, e1, k, b, bin);
         if (a.G.water)
             hipLaunchKernelGGL(k_settle, dim3(blocks_for(a.G.n_mol)), dim3(kBlock), 0, st, a, k, b, bin, s->cl);
         b ^= 1;
     }
-    if (final_rebuild && (rc = rebuild_mid(s, b, n_all_max, st))) return rc;
-    s->last_buf = b;
-    hipLaunchKernelGGL(k_energy, dim3(GA), dim3(kBlock), 0, st, a, 1, -1, 0.0, b);
-    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kBlock), 0, st, a, 1, GA);
-    hipLaunchKernelGGL(k_metropolis, dim3(1), dim3(1), 0, st, a);
-    hipLaunchKernelGGL(k_commit, dim3(G), dim3(kBlock), 0, st, a, b);
-    hipLaunchKernelGGL(k_compact1, dim3(G), dim3(kBlock), 0, st, a);
-    hipLaunchKernelGGL(k_compact2, dim3(G), dim3(kBlock), 0, st, a);
-    hipLaunchKernelGGL(k_commit_ctl, dim3(1), dim3(1), 0, st, a);
+    if ((rc = rebuild_final(s, st))) return rc;
+    hipLaunchKernelGGL(k_energy, dim3(a.step_blocks), dim3(kBlock), 0, st, a, 1, -1, 0.0, -1);
+    hipLaunchKernelGGL(k_energy_final, dim3(s->nbox), dim3(kBlock), 0, st, a, 1);
+    hipLaunchKernelGGL(k_metropolis, dim3(blocks_for(s->nbox)), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL(k_commit, dim3(G1), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL(k_compact1, dim3(G1), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL(k_compact2, dim3(G1), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL(k_commit_ctl, dim3(blocks_for(s->nbox)), dim3(kBlock), 0, st, a);
     HIPC(hipGetLastError());
     return H4D_OK;
 }
 
-int launch_trial(h4d_system *s, int move) {
+int launch_round(h4d_system *s, int move) {
     KArgs &a = s->a;
     hipStream_t st = s->stream;
     const int nf = s->p.n_steps_max > 0 ? s->p.n_steps_max : s->p.n_steps;
     const int M = std::max(1, s->trial_M);
     int rc;
-    s->trial_rebuilds = nf / M + (nf % M != 0 ? 1 : 0);
+    s->trial_rebuilds = nf / M + 1;
     if (s->timing && (int)s->ev.size() < 2 * (nf + 1)) {
         s->drop_graphs();
         while ((int)s->ev.size() < 2 * (nf + 1)) {
@@ -418,15 +481,13 @@ int launch_trial(h4d_system *s, int move) {
     const int tm = s->timing ? 1 : 0;
     if (s->graphs_ok[tm]) {
         if (!s->cap_stream) HIPC(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
-        const int n_all_max = s->n_host + 2;
-        const auto key = std::make_tuple(blocks_for(n_all_max), atom_blocks_l(n_all_max, a.lanes), M, nf, move, tm,
-                                         a.lanes);
+        const auto key = std::make_tuple(M, nf, move, tm, a.lanes);
         auto it = s->graphs.find(key);
         if (it == s->graphs.end()) {
             hipGraph_t graph = nullptr;
             hipGraphExec_t exec = nullptr;
             bool ok = hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
-            int erc = ok ? enqueue_trial(s, move, s->cap_stream, nf, M, s->timing) : H4D_OK;
+            int erc = ok ? enqueue_round(s, move, s->cap_stream, nf, M, s->timing) : H4D_OK;
             ok = hipStreamEndCapture(s->cap_stream, &graph) == hipSuccess && ok && erc == H4D_OK;
             if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
             if (graph) (void)hipGraphDestroy(graph);
@@ -439,12 +500,14 @@ int launch_trial(h4d_system *s, int move) {
             launched = true;
         }
     }
-    if (!launched && (rc = enqueue_trial(s, move, st, nf, M, s->timing))) return rc;
-    HIPC(hipMemcpyAsync(s->h_rec, a.rec, sizeof(TrialRec), hipMemcpyDeviceToHost, st));
-    HIPC(hipMemcpyAsync(s->h_ctl, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    if (!launched && (rc = enqueue_round(s, move, st, nf, M, s->timing))) return rc;
+    HIPC(hipMemcpyAsync(s->h_rec, a.rec, sizeof(TrialRec) * s->nbox, hipMemcpyDeviceToHost, st));
+    HIPC(hipMemcpyAsync(s->h_ctl, a.ctl, sizeof(Ctl) * s->nbox, hipMemcpyDeviceToHost, st));
     HIPC(hipStreamSynchronize(st));
     if (s->timing) {
-        const int nf_dev = std::min(s->h_ctl->nf, nf);
+        int nf_dev = 0;
+        for (int b = 0; b < s->nbox; ++b) nf_dev = std::max(nf_dev, s->h_ctl[b].nf);
+        nf_dev = std::min(nf_dev, nf);
         for (int k = 0; k <= nf_dev; ++k) {
             float ms = 0.f;
             HIPC(hipEventElapsedTime(&ms, s->ev[2 * k], s->ev[2 * k + 1]));
@@ -455,27 +518,71 @@ int launch_trial(h4d_system *s, int move) {
     return H4D_OK;
 }
 
+// After a round: boxes that must recompute their trial (list overflow, fast
+// list full, atom capacity) get larger buffers or a shorter rebuild interval.
+// Returns the number of boxes to recompute.
+int handle_retries(h4d_system *s, int &rc) {
+    rc = H4D_OK;
+    unsigned err = 0;
+    int max_nbr = 0, max_cell = 0, n = 0;
+    for (int b = 0; b < s->nbox; ++b) {
+        const Ctl *c = s->h_ctl + b;
+        if (!c->retry) continue;
+        ++n;
+        err |= c->err;
+        max_nbr = std::max(max_nbr, c->max_nbr);
+        max_cell = std::max(max_cell, c->max_cell);
+    }
+    if (!n) return 0;
+    if (err & kErrCap) { rc = fail(H4D_ECAPACITY, "atom capacity exhausted"); return n; }
+    if ((rc = grow_lists(s, err, max_nbr, max_cell))) return n;
+    // more fast atoms than the fast list holds: recompute with a shorter
+    // rebuild interval, and shorten the base interval
+    if (err & (kErrSkin | kErrFast)) {
+        s->trial_M = std::max(1, s->trial_M / 2);
+        if (s->p.rebuild_every == 0) s->rebuild_every = std::max(1, (s->rebuild_every * 3) / 4);
+        s->clean_trials = 0;
+    }
+    rc = clear_errors(s);
+    s->retries += n;
+    return n;
+}
+
+// Book-keeping of a finished trial of box b.
+void account(h4d_system *s, int b, const h4d_trial &r) {
+    const Ctl *c = s->h_ctl + b;
+    h4d_system::Stats &st = s->stats[b];
+    s->n_host[b] = c->n;
+    s->nsalt_host[b] = c->nsalt;
+    st.n_trials += 1;
+    if (r.move > 0) { st.n_ins += 1; st.n_ins_acc += r.accepted; }
+    else { st.n_del += 1; st.n_del_acc += r.accepted; }
+    st.N_sum += (double)c->nsalt;
+    st.N2_sum += (double)c->nsalt * (double)c->nsalt;
+}
+
+// automatic rebuild interval: lengthen it after a run of rounds whose fast
+// lists stayed short (a few percent of their capacity)
+void adapt_interval(h4d_system *s) {
+    if (s->p.rebuild_every != 0) return;
+    int mf = 0;
+    for (int b = 0; b < s->nbox; ++b) mf = std::max(mf, s->h_ctl[b].max_fast);
+    if (mf <= kFastCap / 16) {
+        if (++s->clean_trials >= 20) { s->rebuild_every += 1; s->clean_trials = 0; }
+    } else {
+        s->clean_trials = 0;
+    }
+}
+
 int run_one(h4d_system *s, int move, h4d_trial *out) {
     bool retried = false;
     s->trial_M = std::max(1, s->rebuild_every);
     for (int attempt = 0; attempt < 16; ++attempt) {
-        int rc = launch_trial(s, move);
+        int rc = launch_round(s, move);
         if (rc) return rc;
-        const Ctl *c = s->h_ctl;
-        if (c->retry) {
-            const unsigned err = c->err;
-            if (err & kErrCap) return fail(H4D_ECAPACITY, "atom capacity exhausted");
-            if ((rc = grow_lists(s, err))) return rc;
-            // more fast atoms than the fast list holds: recompute this trial
-            // with a shorter rebuild interval, and shorten the base interval
-            if (err & (kErrSkin | kErrFast)) {
-                s->trial_M = std::max(1, s->trial_M / 2);
-                if (s->p.rebuild_every == 0) s->rebuild_every = std::max(1, (s->rebuild_every * 3) / 4);
-                s->clean_trials = 0;
-            }
-            if ((rc = clear_errors(s))) return rc;
+        if (handle_retries(s, rc)) {
+            if (rc) return rc;
             retried = true;
-            s->retries += 1;
             continue;
         }
         h4d_trial r;
@@ -483,86 +590,136 @@ int run_one(h4d_system *s, int move, h4d_trial *out) {
         if (retried) r.flags |= H4D_FLAG_RETRIED;
         r.n_rebuilds = s->trial_rebuilds;
         if (out) *out = r;
-        s->n_host = c->n;
-        s->nsalt_host = c->nsalt;
-        s->n_trials += 1;
-        if (r.move > 0) { s->n_ins += 1; s->n_ins_acc += r.accepted; }
-        else { s->n_del += 1; s->n_del_acc += r.accepted; }
-        // automatic rebuild interval: lengthen it after a run of trials whose
-        // fast lists stayed short (a few percent of their capacity)
-        if (s->p.rebuild_every == 0 && !retried) {
-            if (c->max_fast <= kFastCap / 16) {
-                if (++s->clean_trials >= 20) { s->rebuild_every += 1; s->clean_trials = 0; }
-            } else {
-                s->clean_trials = 0;
-            }
-        }
-        s->N_sum += (double)c->nsalt;
-        s->N2_sum += (double)c->nsalt * (double)c->nsalt;
+        account(s, 0, r);
+        if (!retried) adapt_interval(s);
         return H4D_OK;
     }
     return fail(H4D_EHIP, "trial could not be completed after resizing the lists");
 }
 
-}  // namespace
+int set_quota(h4d_system *s, long long count) {
+    hipLaunchKernelGGL(k_set_quota, dim3(blocks_for(s->nbox)), dim3(kBlock), 0, s->stream, s->a, count);
+    HIPC(hipGetLastError());
+    return read_ctl(s);
+}
 
-extern "C" {
+int run_batch(h4d_system *s, int T, int move, h4d_trial *out) {
+    int rc = set_quota(s, T);
+    if (rc) return rc;
+    std::vector<long long> first(s->nbox);
+    std::vector<char> retried(s->nbox, 0);
+    for (int b = 0; b < s->nbox; ++b) first[b] = s->h_ctl[b].trial;
+    const int max_rounds = T + 64;
+    int rounds = 0;
+    bool any_retry = false;
+    for (;;) {
+        bool busy = false;
+        for (int b = 0; b < s->nbox; ++b) busy |= s->h_ctl[b].trial < s->h_ctl[b].trial_end;
+        if (!busy) break;
+        if (++rounds > max_rounds) {
+            (void)set_quota(s, -1);
+            return fail(H4D_EHIP, "batch could not be completed after resizing the lists");
+        }
+        // the base interval, unless the last round had to recompute a trial
+        // (then the interval handle_retries shortened stays for this round)
+        if (!any_retry) s->trial_M = std::max(1, s->rebuild_every);
+        if ((rc = launch_round(s, move))) return rc;
+        any_retry = false;
+        for (int b = 0; b < s->nbox; ++b) {
+            const Ctl *c = s->h_ctl + b;
+            const TrialRec &tr = s->h_rec[b];
+            if (tr.flags & kFlagIdle) continue;
+            if (c->retry) { retried[b] = 1; any_retry = true; continue; }
+            h4d_trial r;
+            std::memcpy(&r, &tr, sizeof(r));
+            if (retried[b]) r.flags |= H4D_FLAG_RETRIED;
+            retried[b] = 0;
+            r.n_rebuilds = s->trial_rebuilds;
+            const long long q = r.trial - first[b];
+            if (out && q >= 0 && q < T) out[(size_t)b * T + q] = r;
+            account(s, b, r);
+        }
+        if (any_retry) {
+            handle_retries(s, rc);
+            if (rc) { (void)set_quota(s, -1); return rc; }
+            if ((rc = read_ctl(s))) return rc;
+        } else {
+            adapt_interval(s);
+        }
+    }
+    return set_quota(s, -1);
+}
 
-const char *h4d_last_error(void) { return g_err.c_str(); }
-
-int32_t h4d_init_system(const h4d_params *params, int32_t n_atoms, int32_t n_salt, int32_t n_mol,
-                        const double *pos, const int32_t *type, const int32_t *mol, const int64_t *tag,
-                        void *hip_stream, h4d_system **out) {
+int create(const h4d_params *params, int nbox, const double *edges, const int32_t *n_atoms, const int32_t *n_salt,
+           int32_t n_mol, const double *pos, const int32_t *type, const int32_t *mol, const int64_t *tag,
+           void *hip_stream, h4d_system **out) {
     g_err.clear();
-    if (!params || !out || n_atoms < 0 || n_salt < 0 || (n_atoms > 0 && (!pos || !type || !tag)))
-        return fail(H4D_EINVAL, "null argument or negative size");
+    if (!params || !out || nbox < 1 || !edges || !n_atoms || !n_salt) return fail(H4D_EINVAL, "null argument");
     *out = nullptr;
     int rc = check_params(*params);
     if (rc) return rc;
+    long long total = 0;
+    for (int b = 0; b < nbox; ++b) {
+        if (n_atoms[b] < 0 || n_salt[b] < 0) return fail(H4D_EINVAL, "negative size");
+        total += n_atoms[b];
+    }
+    if (total > 0 && (!pos || !type || !tag)) return fail(H4D_EINVAL, "null configuration array");
+    if (params->water && nbox != 1) return fail(H4D_EINVAL, "rigid water needs a single box");
+    const double rc_max = std::max(params->rc_lj, params->rc_coul);
+    for (int q = 0; q < 3 * nbox; ++q)
+        if (!(edges[q] >= 2.0 * rc_max)) return fail(H4D_EINVAL, "every box edge must be at least twice the largest cutoff");
     int ndev = 0;
     const hipError_t de = hipGetDeviceCount(&ndev);
     if (de != hipSuccess || ndev < 1)
         return fail(H4D_ENODEV, std::string("no HIP device (hipGetDeviceCount: ") + hipGetErrorString(de) +
                                     ", count " + std::to_string(ndev) + ")");
-    // validate the configuration
-    int ncat = 0, nan_ = 0;
-    for (int i = 0; i < n_atoms; ++i) {
-        if (type[i] < 0 || type[i] >= params->n_types) return fail(H4D_EINVAL, "atom type out of range");
-        ncat += type[i] == params->cation_type;
-        nan_ += type[i] == params->anion_type;
-        if (i > 0 && tag[i] <= tag[i - 1]) return fail(H4D_EINVAL, "tags must ascend in array order");
-        for (int d = 0; d < 3; ++d)
-            if (!(pos[3 * i + d] >= 0.0 && pos[3 * i + d] < params->box[d]))
-                return fail(H4D_EINVAL, "positions must lie in [0, L)");
+    // validate the configuration, box by box
+    long long off = 0;
+    for (int b = 0; b < nbox; ++b) {
+        int ncat = 0, nan_ = 0;
+        for (int q = 0; q < n_atoms[b]; ++q) {
+            const long long i = off + q;
+            if (type[i] < 0 || type[i] >= params->n_types) return fail(H4D_EINVAL, "atom type out of range");
+            ncat += type[i] == params->cation_type;
+            nan_ += type[i] == params->anion_type;
+            if (q > 0 && tag[i] <= tag[i - 1]) return fail(H4D_EINVAL, "tags must ascend in array order within a box");
+            for (int d = 0; d < 3; ++d)
+                if (!(pos[3 * i + d] >= 0.0 && pos[3 * i + d] < edges[3 * b + d]))
+                    return fail(H4D_EINVAL, "positions must lie in [0, L)");
+        }
+        if (ncat != n_salt[b] || nan_ != n_salt[b])
+            return fail(H4D_EINVAL, "n_salt must equal the cation and anion counts of each box");
+        off += n_atoms[b];
     }
-    if (ncat != n_salt || nan_ != n_salt) return fail(H4D_EINVAL, "n_salt must equal the cation and anion counts");
+    const int n0 = n_atoms[0];
     if (params->water) {
-        if (n_mol < 1 || 3 * n_mol > n_atoms || !mol) return fail(H4D_EINVAL, "water = 1 needs n_mol >= 1 waters first");
+        if (n_mol < 1 || 3 * n_mol > n0 || !mol) return fail(H4D_EINVAL, "water = 1 needs n_mol >= 1 waters first");
         for (int m = 0; m < n_mol; ++m)
             for (int q = 0; q < 3; ++q) {
                 const int i = 3 * m + q;
                 if (mol[i] != m || type[i] != type[q]) return fail(H4D_EINVAL, "waters must be atoms 3m, 3m+1, 3m+2 (O, H, H) of molecule m");
             }
         if (type[1] != type[2] || type[0] == type[1]) return fail(H4D_EINVAL, "water atoms must be O, H, H");
-        for (int i = 3 * n_mol; i < n_atoms; ++i)
+        for (int i = 3 * n_mol; i < n0; ++i)
             if (mol[i] >= 0) return fail(H4D_EINVAL, "only the waters may carry molecule ids");
     } else if (mol) {
-        for (int i = 0; i < n_atoms; ++i)
+        for (long long i = 0; i < total; ++i)
             if (mol[i] >= 0) return fail(H4D_EINVAL, "molecule ids need water = 1");
     }
 
     auto *s = new h4d_system();
     s->p = *params;
+    s->nbox = nbox;
     if (const char *e = std::getenv("H4D_NO_GRAPHS")) {
         if (e[0] == '1') s->graphs_ok[0] = false;   // launch every kernel eagerly
     }
     s->stream = static_cast<hipStream_t>(hip_stream);
-    s->cap = params->capacity > 0 ? params->capacity : n_atoms + 4096;
-    if (s->cap < n_atoms + 2) { delete s; return fail(H4D_EINVAL, "capacity below n_atoms + 2"); }
-    s->n_host = n_atoms;
-    s->nsalt_host = n_salt;
     s->n_mol = n_mol;
+    s->n_host.assign(n_atoms, n_atoms + nbox);
+    s->nsalt_host.assign(n_salt, n_salt + nbox);
+    s->stats.assign(nbox, h4d_system::Stats{});
     setup_geo(s);
+    if ((rc = setup_boxes(s, edges, n_atoms))) { delete s; return rc; }
     if (params->water) {
         Geo &G = s->a.G;
         G.n_mol = n_mol;
@@ -573,30 +730,27 @@ int32_t h4d_init_system(const h4d_params *params, int32_t n_atoms, int32_t n_sal
         G.ra = 2.0 * G.m_h * h / (G.m_o + 2.0 * G.m_h);
         G.rb = h - G.ra;
     }
-    if (!s->a.G.use_cells && s->cap > 8192) {
-        delete s;
-        return fail(H4D_EINVAL, "a box with fewer than 3 list cells per edge is limited to 8192 atoms");
-    }
     {
         int L = params->lanes_per_atom;
-        if (L == 0) L = n_atoms <= 16384 ? 16 : (n_atoms <= 65536 ? 8 : 4);
-        s->a.lanes = L;
-        s->a.lanes_log2 = L == 4 ? 2 : (L == 8 ? 3 : 4);
+        int nmax = 0;
+        for (int b = 0; b < nbox; ++b) nmax = std::max(nmax, n_atoms[b]);
+        if (L == 0) L = (long long)total <= 16384 ? 16 : (total <= 65536 && nmax <= 65536 ? 8 : 4);
+        set_lanes(s, L);
     }
     initial_capacities(s, n_atoms);
     KArgs &a = s->a;
-    a.cap = s->cap;
     a.seed = params->seed;
-    a.stream = params->stream;
     a.n_steps = params->n_steps;
     a.n_steps_min = params->n_steps_min;
     a.n_steps_max = params->n_steps_max;
     a.cation_type = params->cation_type;
     a.anion_type = params->anion_type;
-    s->partial_blocks = atom_blocks_l(s->cap + 2, kMaxLanes) + 1;   // every energy grid fits
-    const size_t C = (size_t)s->cap;
+    s->partial_blocks = a.slots / (kBlock / kMaxLanes);   // every energy grid fits
+    const size_t C = (size_t)a.slots;
     PairCoef *coef_d = nullptr;
     double *mass_d = nullptr;
+    Box *box_d = nullptr;
+    int *slot_box_d = nullptr, *cell_box_d = nullptr;
     if ((rc = s->alloc(&a.cpos, C)) || (rc = s->alloc(&a.ctag, C)) || (rc = s->alloc(&a.ctype, C)) ||
         (rc = s->alloc(&a.cmol, C)) || (rc = s->alloc(&a.pos[0], C)) || (rc = s->alloc(&a.pos[1], C)) ||
         (rc = s->alloc(&a.fx[0], C)) || (rc = s->alloc(&a.fx[1], C)) || (rc = s->alloc(&a.vel[0], C)) ||
@@ -604,39 +758,56 @@ int32_t h4d_init_system(const h4d_params *params, int32_t n_atoms, int32_t n_sal
         (rc = s->alloc(&a.posb, C)) || (rc = s->alloc(&a.force, C)) || (rc = s->alloc(&a.tpos, C)) ||
         (rc = s->alloc(&a.ttag, C)) || (rc = s->alloc(&a.ttype, C)) || (rc = s->alloc(&a.tmol, C)) ||
         (rc = s->alloc(&a.nnbr, C)) || (rc = s->alloc(&a.partial, (size_t)s->partial_blocks * 5)) ||
-        (rc = s->alloc(&a.ctl, 1)) || (rc = s->alloc(&a.rec, 1)) ||
+        (rc = s->alloc(&a.ctl, (size_t)nbox)) || (rc = s->alloc(&a.rec, (size_t)nbox)) ||
         (rc = s->alloc(&a.molw, (size_t)std::max(1, 3 * n_mol))) || (rc = s->alloc(&a.fw, C)) ||
         (rc = s->alloc(&coef_d, (size_t)kMaxTypes * kMaxTypes)) || (rc = s->alloc(&mass_d, kMaxTypes)) ||
-        (rc = alloc_lists(s))) {
+        (rc = s->alloc(&box_d, (size_t)nbox)) || (rc = s->alloc(&slot_box_d, C / kBlock)) ||
+        (rc = s->alloc(&cell_box_d, (size_t)a.ncell_total)) || (rc = alloc_lists(s))) {
         delete s;
         return rc;
     }
     a.coef = coef_d;
     a.mass = mass_d;
-    if (hipHostMalloc((void **)&s->h_rec, sizeof(TrialRec)) != hipSuccess ||
-        hipHostMalloc((void **)&s->h_ctl, sizeof(Ctl)) != hipSuccess) {
+    a.box = box_d;
+    a.slot_box = slot_box_d;
+    a.cell_box = cell_box_d;
+    if (hipHostMalloc((void **)&s->h_rec, sizeof(TrialRec) * nbox) != hipSuccess ||
+        hipHostMalloc((void **)&s->h_ctl, sizeof(Ctl) * nbox) != hipSuccess) {
         delete s;
         return fail(H4D_ENOMEM, "pinned host allocation failed");
     }
-    // upload
-    std::vector<double4> hp(std::max(1, n_atoms));
-    std::vector<int> hm(std::max(1, n_atoms), -1);
-    for (int i = 0; i < n_atoms; ++i) {
-        long long meta = type[i];
-        double wbits;
-        std::memcpy(&wbits, &meta, sizeof(wbits));
-        hp[i] = make_double4(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], wbits);
-        if (mol) hm[i] = mol[i];
+    // upload: each box's atoms at its slots, rest of the slots zero
+    std::vector<double4> hp(C, make_double4(0.0, 0.0, 0.0, 0.0));
+    std::vector<int> ht(C, 0), hm(C, -1);
+    std::vector<long long> hg(C, 0);
+    std::vector<int> sb(C / kBlock), cbx(a.ncell_total);
+    std::memset(s->h_ctl, 0, sizeof(Ctl) * nbox);
+    off = 0;
+    for (int b = 0; b < nbox; ++b) {
+        const Box &B = s->box_h[b];
+        for (int q = 0; q < n_atoms[b]; ++q) {
+            const long long i = off + q;
+            const int w = B.a0 + q;
+            long long meta = type[i];
+            double wbits;
+            std::memcpy(&wbits, &meta, sizeof(wbits));
+            hp[w] = make_double4(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], wbits);
+            ht[w] = type[i];
+            hg[w] = tag[i];
+            if (mol) hm[w] = mol[i];
+        }
+        for (int q = B.a0 / kBlock; q < (B.a0 + B.cap) / kBlock; ++q) sb[q] = b;
+        for (int q = B.c0; q < B.c0 + B.nc; ++q) cbx[q] = b;
+        Ctl &c = s->h_ctl[b];
+        c.n = n_atoms[b];
+        c.n_all = n_atoms[b];
+        c.nsalt = n_salt[b];
+        c.next_tag = n_atoms[b] ? tag[off + n_atoms[b] - 1] + 1 : 0;
+        c.trial = 0;
+        c.trial_end = 0x7fffffffffffffffLL;
+        c.ic = c.ia = -1;
+        off += n_atoms[b];
     }
-    std::memset(s->h_ctl, 0, sizeof(Ctl));
-    Ctl &c = *s->h_ctl;
-    c.n = n_atoms;
-    c.n_all = n_atoms;
-    c.nsalt = n_salt;
-    c.next_tag = n_atoms ? tag[n_atoms - 1] + 1 : 0;
-    c.trial = 0;
-    c.nf = 0;
-    c.ic = c.ia = -1;
     double mass_h[kMaxTypes] = {0};
     for (int t = 0; t < params->n_types; ++t) mass_h[t] = params->mass[t];
 #define UPLOAD(dst, src, bytes)                                                                        \
@@ -644,15 +815,16 @@ int32_t h4d_init_system(const h4d_params *params, int32_t n_atoms, int32_t n_sal
         delete s;                                                                                      \
         return fail(H4D_EHIP, "upload failed");                                                       \
     }
-    if (n_atoms > 0) {
-        UPLOAD(a.cpos, hp.data(), sizeof(double4) * n_atoms);
-        UPLOAD(a.ctype, type, sizeof(int) * n_atoms);
-        UPLOAD(a.cmol, hm.data(), sizeof(int) * n_atoms);
-        UPLOAD(a.ctag, tag, sizeof(long long) * n_atoms);
-    }
-    UPLOAD(a.ctl, &c, sizeof(Ctl));
+    UPLOAD(a.cpos, hp.data(), sizeof(double4) * C);
+    UPLOAD(a.ctype, ht.data(), sizeof(int) * C);
+    UPLOAD(a.cmol, hm.data(), sizeof(int) * C);
+    UPLOAD(a.ctag, hg.data(), sizeof(long long) * C);
+    UPLOAD(a.ctl, s->h_ctl, sizeof(Ctl) * nbox);
     UPLOAD(coef_d, s->coef_h, sizeof(s->coef_h));
     UPLOAD(mass_d, mass_h, sizeof(mass_h));
+    UPLOAD(box_d, s->box_h.data(), sizeof(Box) * nbox);
+    UPLOAD(slot_box_d, sb.data(), sizeof(int) * sb.size());
+    UPLOAD(cell_box_d, cbx.data(), sizeof(int) * cbx.size());
 #undef UPLOAD
     // rebuild interval: the fastest atoms (5 standard deviations) cover half
     // the skin; adapted on overflow
@@ -667,15 +839,116 @@ int32_t h4d_init_system(const h4d_params *params, int32_t n_atoms, int32_t n_sal
     return H4D_OK;
 }
 
+// FP64 energies of every box's working buffer-0 state (after sort_in); the
+// results of box b are left in h_ctl[b].
+int energies(h4d_system *s) {
+    KArgs &a = s->a;
+    hipLaunchKernelGGL(k_energy, dim3(a.step_blocks), dim3(kBlock), 0, s->stream, a, 2, 0, 0.0, 0);
+    hipLaunchKernelGGL(k_energy_final, dim3(s->nbox), dim3(kBlock), 0, s->stream, a, 2);
+    HIPC(hipGetLastError());
+    return read_ctl(s);
+}
+
+int box_state(h4d_system *s, int box, int32_t cap, int32_t *n, int32_t *n_salt, double *pos, double *vel,
+              int32_t *type, int32_t *mol, int64_t *tag) {
+    if (!s) return fail(H4D_EINVAL, "null handle");
+    if (box < 0 || box >= s->nbox) return fail(H4D_EINVAL, "box index out of range");
+    int rc = read_ctl(s);
+    if (rc) return rc;
+    const Ctl &c = s->h_ctl[box];
+    const Box &B = s->box_h[box];
+    const int nn = c.n;
+    if (n) *n = nn;
+    if (n_salt) *n_salt = c.nsalt;
+    if ((pos || vel || type || mol || tag) && cap < nn) return fail(H4D_EINVAL, "cap smaller than the atom count");
+    std::vector<double4> buf(std::max(1, nn));
+    if (pos && nn) {
+        HIPC(hipMemcpy(buf.data(), s->a.cpos + B.a0, sizeof(double4) * nn, hipMemcpyDeviceToHost));
+        for (int i = 0; i < nn; ++i) { pos[3 * i] = buf[i].x; pos[3 * i + 1] = buf[i].y; pos[3 * i + 2] = buf[i].z; }
+    }
+    if (vel && nn) {
+        // velocities are those of the last trajectory's end, in canonical order
+        std::vector<int> perm(nn);
+        HIPC(hipMemcpy(perm.data(), s->a.perm + B.a0, sizeof(int) * nn, hipMemcpyDeviceToHost));
+        HIPC(hipMemcpy(buf.data(), s->a.vel[(c.nf + 1) & 1] + B.a0, sizeof(double4) * nn, hipMemcpyDeviceToHost));
+        for (int w = 0; w < nn; ++w) {
+            const int i = perm[w] - B.a0;
+            if (i < 0 || i >= nn) continue;
+            vel[3 * i] = buf[w].x; vel[3 * i + 1] = buf[w].y; vel[3 * i + 2] = buf[w].z;
+        }
+    }
+    if (type && nn) HIPC(hipMemcpy(type, s->a.ctype + B.a0, sizeof(int) * nn, hipMemcpyDeviceToHost));
+    if (mol && nn) HIPC(hipMemcpy(mol, s->a.cmol + B.a0, sizeof(int) * nn, hipMemcpyDeviceToHost));
+    if (tag && nn) HIPC(hipMemcpy(tag, s->a.ctag + B.a0, sizeof(long long) * nn, hipMemcpyDeviceToHost));
+    return H4D_OK;
+}
+
+int box_observables(h4d_system *s, int box, h4d_observables *out) {
+    if (!s || !out) return fail(H4D_EINVAL, "null argument");
+    if (box < 0 || box >= s->nbox) return fail(H4D_EINVAL, "box index out of range");
+    int rc = h4d_build_neighbors(s);
+    if (rc) return rc;
+    if ((rc = energies(s))) return rc;
+    std::memset(out, 0, sizeof(*out));
+    const Ctl *c = s->h_ctl + box;
+    const h4d_system::Stats &st = s->stats[box];
+    out->n_atoms = c->n;
+    out->n_salt = c->nsalt;
+    out->n_trials = st.n_trials;
+    out->n_ins = st.n_ins;
+    out->n_ins_acc = st.n_ins_acc;
+    out->n_del = st.n_del;
+    out->n_del_acc = st.n_del_acc;
+    out->U = c->Ulj + c->Uc;
+    out->U_lj = c->Ulj;
+    out->U_coul = c->Uc;
+    out->virial = c->vir;
+    out->pressure_virial = ((double)c->n * s->p.kT + c->vir / 3.0) / s->box_h[box].volume;
+    if (st.n_trials > 0) {
+        out->N_mean = st.N_sum / (double)st.n_trials;
+        out->N2_mean = st.N2_sum / (double)st.n_trials;
+        out->chi = out->N_mean > 0.0 ? (out->N2_mean - out->N_mean * out->N_mean) / out->N_mean : 0.0;
+    }
+    return H4D_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *h4d_last_error(void) { return g_err.c_str(); }
+
+int32_t h4d_init_system(const h4d_params *params, int32_t n_atoms, int32_t n_salt, int32_t n_mol,
+                        const double *pos, const int32_t *type, const int32_t *mol, const int64_t *tag,
+                        void *hip_stream, h4d_system **out) {
+    if (!params) return fail(H4D_EINVAL, "null argument");
+    return create(params, 1, params->box, &n_atoms, &n_salt, n_mol, pos, type, mol, tag, hip_stream, out);
+}
+
+int32_t h4d_init_batch(const h4d_params *params, int32_t n_boxes, const double *box_edges,
+                       const int32_t *n_atoms, const int32_t *n_salt, const double *pos, const int32_t *type,
+                       const int64_t *tag, void *hip_stream, h4d_system **out) {
+    if (n_boxes < 1) return fail(H4D_EINVAL, "n_boxes must be >= 1");
+    return create(params, n_boxes, box_edges, n_atoms, n_salt, 0, pos, type, nullptr, tag, hip_stream, out);
+}
+
+int32_t h4d_num_boxes(const h4d_system *s) { return s ? s->nbox : 0; }
+
 int32_t h4d_build_neighbors(h4d_system *s) {
     if (!s) return fail(H4D_EINVAL, "null handle");
     for (int attempt = 0; attempt < 8; ++attempt) {
-        int rc = sort_in(s, s->n_host, s->stream);
+        int rc = sort_in(s, s->stream);
         if (rc) return rc;
         if ((rc = read_ctl(s))) return rc;
-        const unsigned err = s->h_ctl->err;
+        unsigned err = 0;
+        int max_nbr = 0, max_cell = 0;
+        for (int b = 0; b < s->nbox; ++b) {
+            err |= s->h_ctl[b].err;
+            max_nbr = std::max(max_nbr, s->h_ctl[b].max_nbr);
+            max_cell = std::max(max_cell, s->h_ctl[b].max_cell);
+        }
         if (!(err & (kErrNbr | kErrCell))) return H4D_OK;
-        if ((rc = grow_lists(s, err))) return rc;
+        if ((rc = grow_lists(s, err, max_nbr, max_cell))) return rc;
         if ((rc = clear_errors(s))) return rc;
     }
     return fail(H4D_ECAPACITY, "neighbour lists could not be sized");
@@ -683,12 +956,14 @@ int32_t h4d_build_neighbors(h4d_system *s) {
 
 int32_t h4d_run_nemd_trial(h4d_system *s, int32_t move, h4d_trial *out) {
     if (!s) return fail(H4D_EINVAL, "null handle");
+    if (s->nbox != 1) return fail(H4D_EINVAL, "a batch of boxes runs with h4d_run_batch");
     if (move < -1 || move > 1) return fail(H4D_EINVAL, "move must be -1, 0 or +1");
     return run_one(s, move, out);
 }
 
 int32_t h4d_run_trials(h4d_system *s, int32_t n, int32_t move, h4d_trial *out) {
     if (!s || n < 0) return fail(H4D_EINVAL, "null handle or negative count");
+    if (s->nbox != 1) return fail(H4D_EINVAL, "a batch of boxes runs with h4d_run_batch");
     if (move < -1 || move > 1) return fail(H4D_EINVAL, "move must be -1, 0 or +1");
     for (int q = 0; q < n; ++q) {
         int rc = run_one(s, move, out ? out + q : nullptr);
@@ -697,74 +972,35 @@ int32_t h4d_run_trials(h4d_system *s, int32_t n, int32_t move, h4d_trial *out) {
     return H4D_OK;
 }
 
+int32_t h4d_run_batch(h4d_system *s, int32_t trials_per_box, int32_t move, h4d_trial *out) {
+    if (!s || trials_per_box < 0) return fail(H4D_EINVAL, "null handle or negative count");
+    if (move < -1 || move > 1) return fail(H4D_EINVAL, "move must be -1, 0 or +1");
+    if (trials_per_box == 0) return H4D_OK;
+    return run_batch(s, trials_per_box, move, out);
+}
+
 int32_t h4d_set_trial_index(h4d_system *s, uint64_t trial) {
     if (!s) return fail(H4D_EINVAL, "null handle");
     int rc = read_ctl(s);
     if (rc) return rc;
-    s->h_ctl->trial = (long long)trial;
-    HIPC(hipMemcpyAsync(s->a.ctl, s->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, s->stream));
-    HIPC(hipStreamSynchronize(s->stream));
-    return H4D_OK;
+    for (int b = 0; b < s->nbox; ++b) s->h_ctl[b].trial = (long long)trial;
+    return write_ctl(s);
 }
 
 int32_t h4d_get_state(h4d_system *s, int32_t cap, int32_t *n, int32_t *n_salt, double *pos, double *vel,
                       int32_t *type, int32_t *mol, int64_t *tag) {
-    if (!s) return fail(H4D_EINVAL, "null handle");
-    int rc = read_ctl(s);
-    if (rc) return rc;
-    const int nn = s->h_ctl->n;
-    if (n) *n = nn;
-    if (n_salt) *n_salt = s->h_ctl->nsalt;
-    if ((pos || vel || type || mol || tag) && cap < nn) return fail(H4D_EINVAL, "cap smaller than the atom count");
-    std::vector<double4> buf(std::max(1, nn));
-    if (pos && nn) {
-        HIPC(hipMemcpy(buf.data(), s->a.cpos, sizeof(double4) * nn, hipMemcpyDeviceToHost));
-        for (int i = 0; i < nn; ++i) { pos[3 * i] = buf[i].x; pos[3 * i + 1] = buf[i].y; pos[3 * i + 2] = buf[i].z; }
-    }
-    if (vel && nn) {
-        // velocities are those of the last trajectory's end, in canonical order
-        std::vector<int> perm(nn);
-        HIPC(hipMemcpy(perm.data(), s->a.perm, sizeof(int) * nn, hipMemcpyDeviceToHost));
-        HIPC(hipMemcpy(buf.data(), s->a.vel[s->last_buf], sizeof(double4) * nn, hipMemcpyDeviceToHost));
-        for (int w = 0; w < nn; ++w) {
-            const int i = perm[w];
-            if (i < 0 || i >= nn) continue;
-            vel[3 * i] = buf[w].x; vel[3 * i + 1] = buf[w].y; vel[3 * i + 2] = buf[w].z;
-        }
-    }
-    if (type && nn) HIPC(hipMemcpy(type, s->a.ctype, sizeof(int) * nn, hipMemcpyDeviceToHost));
-    if (mol && nn) HIPC(hipMemcpy(mol, s->a.cmol, sizeof(int) * nn, hipMemcpyDeviceToHost));
-    if (tag && nn) HIPC(hipMemcpy(tag, s->a.ctag, sizeof(long long) * nn, hipMemcpyDeviceToHost));
-    return H4D_OK;
+    return box_state(s, 0, cap, n, n_salt, pos, vel, type, mol, tag);
 }
 
-}  // extern "C"
-
-namespace {
-
-// FP64 energies of the working buffer-0 state (after sort_in).
-int energies(h4d_system *s, int mode, double w, double out[4]) {
-    KArgs &a = s->a;
-    const int GA = atom_blocks_l(s->n_host, a.lanes);
-    hipLaunchKernelGGL(k_energy, dim3(GA), dim3(kBlock), 0, s->stream, a, 2, mode, w, 0);
-    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kBlock), 0, s->stream, a, 2, GA);
-    HIPC(hipGetLastError());
-    int rc = read_ctl(s);
-    if (rc) return rc;
-    out[0] = s->h_ctl->Ulj + s->h_ctl->Uc;
-    out[1] = s->h_ctl->Ulj;
-    out[2] = s->h_ctl->Uc;
-    out[3] = s->h_ctl->vir;
-    return H4D_OK;
+int32_t h4d_get_box_state(h4d_system *s, int32_t box, int32_t cap, int32_t *n, int32_t *n_salt, double *pos,
+                          double *vel, int32_t *type, int32_t *mol, int64_t *tag) {
+    return box_state(s, box, cap, n, n_salt, pos, vel, type, mol, tag);
 }
-
-}  // namespace
-
-extern "C" {
 
 int32_t h4d_forces_at(h4d_system *s, const int32_t flying[2], double w, double *forces, double *energy) {
     if (!s || !flying) return fail(H4D_EINVAL, "null argument");
-    const int n = s->n_host;
+    if (s->nbox != 1) return fail(H4D_EINVAL, "the force hook serves single-box systems");
+    const int n = s->n_host[0];
     for (int q = 0; q < 2; ++q)
         if (flying[q] < -1 || flying[q] >= n) return fail(H4D_EINVAL, "flying index out of range");
     KArgs &a = s->a;
@@ -772,11 +1008,13 @@ int32_t h4d_forces_at(h4d_system *s, const int32_t flying[2], double w, double *
         if (flying[q] >= 0) hipLaunchKernelGGL(k_set_fly, dim3(1), dim3(1), 0, s->stream, a, flying[q], 1);
     int rc = h4d_build_neighbors(s);
     if (rc) return rc;
-    if (s->p.precision == H4D_PREC_FP32) launch_forces<1>(s, atom_blocks_l(n, a.lanes), w);
-    else launch_forces<0>(s, atom_blocks_l(n, a.lanes), w);
+    if (s->p.precision == H4D_PREC_FP32) launch_forces<1>(s, w);
+    else launch_forces<0>(s, w);
     HIPC(hipGetLastError());
-    double e[4];
-    if ((rc = energies(s, 0, w, e))) return rc;
+    hipLaunchKernelGGL(k_energy, dim3(a.step_blocks), dim3(kBlock), 0, s->stream, a, 2, 0, w, 0);
+    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kBlock), 0, s->stream, a, 2);
+    HIPC(hipGetLastError());
+    if ((rc = read_ctl(s))) return rc;
     if (forces && n) {
         std::vector<double4> buf(n);
         HIPC(hipMemcpy(buf.data(), a.force, sizeof(double4) * n, hipMemcpyDeviceToHost));
@@ -786,7 +1024,11 @@ int32_t h4d_forces_at(h4d_system *s, const int32_t flying[2], double w, double *
             forces[3 * i + 2] = buf[i].z;
         }
     }
-    if (energy) { energy[0] = e[0]; energy[1] = e[1]; energy[2] = e[2]; }
+    if (energy) {
+        energy[0] = s->h_ctl[0].Ulj + s->h_ctl[0].Uc;
+        energy[1] = s->h_ctl[0].Ulj;
+        energy[2] = s->h_ctl[0].Uc;
+    }
     for (int q = 0; q < 2; ++q)
         if (flying[q] >= 0) hipLaunchKernelGGL(k_set_fly, dim3(1), dim3(1), 0, s->stream, a, flying[q], 0);
     HIPC(hipGetLastError());
@@ -794,33 +1036,10 @@ int32_t h4d_forces_at(h4d_system *s, const int32_t flying[2], double w, double *
     return H4D_OK;
 }
 
-int32_t h4d_sample_observables(h4d_system *s, h4d_observables *out) {
-    if (!s || !out) return fail(H4D_EINVAL, "null argument");
-    double e[4];
-    int rc = h4d_build_neighbors(s);
-    if (rc) return rc;
-    if ((rc = energies(s, 0, 0.0, e))) return rc;
-    if (rc) return rc;
-    std::memset(out, 0, sizeof(*out));
-    const Ctl *c = s->h_ctl;
-    out->n_atoms = c->n;
-    out->n_salt = c->nsalt;
-    out->n_trials = s->n_trials;
-    out->n_ins = s->n_ins;
-    out->n_ins_acc = s->n_ins_acc;
-    out->n_del = s->n_del;
-    out->n_del_acc = s->n_del_acc;
-    out->U = e[0];
-    out->U_lj = e[1];
-    out->U_coul = e[2];
-    out->virial = e[3];
-    out->pressure_virial = ((double)c->n * s->p.kT + e[3] / 3.0) / s->a.G.volume;
-    if (s->n_trials > 0) {
-        out->N_mean = s->N_sum / (double)s->n_trials;
-        out->N2_mean = s->N2_sum / (double)s->n_trials;
-        out->chi = out->N_mean > 0.0 ? (out->N2_mean - out->N_mean * out->N_mean) / out->N_mean : 0.0;
-    }
-    return H4D_OK;
+int32_t h4d_sample_observables(h4d_system *s, h4d_observables *out) { return box_observables(s, 0, out); }
+
+int32_t h4d_box_observables(h4d_system *s, int32_t box, h4d_observables *out) {
+    return box_observables(s, box, out);
 }
 
 int32_t h4d_set_timing(h4d_system *s, int32_t on) {
@@ -839,19 +1058,57 @@ int32_t h4d_get_timing(h4d_system *s, h4d_timing *out) {
     int rc = s->alloc(&d, 1);
     if (rc) return rc;
     HIPC(hipMemsetAsync(d, 0, sizeof(*d), s->stream));
-    hipLaunchKernelGGL(k_sum_nbr, dim3(blocks_for(s->n_host)), dim3(kBlock), 0, s->stream, s->a, d);
+    hipLaunchKernelGGL(k_sum_nbr, dim3(slot_blocks(s)), dim3(kBlock), 0, s->stream, s->a, d);
     unsigned long long sum = 0;
     HIPC(hipMemcpyAsync(&sum, d, sizeof(sum), hipMemcpyDeviceToHost, s->stream));
     HIPC(hipStreamSynchronize(s->stream));
     s->release(d);
+    long long atoms = 0;
+    for (int b = 0; b < s->nbox; ++b) atoms += s->n_host[b];
     out->step_launches = s->step_launches;
     out->step_ms = s->step_ms;
-    out->mean_nbr = s->n_host > 0 ? (double)sum / (double)s->n_host : 0.0;
+    out->mean_nbr = atoms > 0 ? (double)sum / (double)atoms : 0.0;
     out->rebuild_every = s->rebuild_every;
     out->nbr_cap = s->a.nbr_cap;
     out->lanes = s->a.lanes;
     out->cell_cap = s->a.cell_cap;
     out->retries = s->retries;
+    return H4D_OK;
+}
+
+int32_t h4d_autotune(h4d_system *s, int32_t trials, int32_t *lanes_out, double *ns_per_atom_step) {
+    if (!s || trials < 1) return fail(H4D_EINVAL, "null handle or trials < 1");
+    const int cand[3] = {4, 8, 16};
+    int best = s->a.lanes;
+    double best_t = 0.0;
+    std::vector<h4d_trial> recs((size_t)trials * s->nbox);
+    for (int q = 0; q < 3; ++q) {
+        set_lanes(s, cand[q]);
+        s->drop_graphs();
+        int rc;
+        // one untimed round captures the graph of this shape
+        if ((rc = s->nbox == 1 ? run_one(s, 0, recs.data()) : run_batch(s, 1, 0, recs.data()))) return rc;
+        HIPC(hipStreamSynchronize(s->stream));
+        const auto t0 = std::chrono::steady_clock::now();
+        if (s->nbox == 1) {
+            for (int t = 0; t < trials && !rc; ++t) rc = run_one(s, 0, recs.data() + t);
+        } else {
+            rc = run_batch(s, trials, 0, recs.data());
+        }
+        if (rc) return rc;
+        HIPC(hipStreamSynchronize(s->stream));
+        const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        double atom_steps = 0.0;
+        for (const h4d_trial &r : recs) atom_steps += (double)r.n_atoms * (double)r.n_steps;
+        const double t = atom_steps > 0.0 ? sec / atom_steps : sec;
+        if (q == 0 || t < best_t) { best_t = t; best = cand[q]; }
+    }
+    set_lanes(s, best);
+    s->drop_graphs();
+    int rc = h4d_build_neighbors(s);
+    if (rc) return rc;
+    if (lanes_out) *lanes_out = best;
+    if (ns_per_atom_step) *ns_per_atom_step = best_t * 1e9;
     return H4D_OK;
 }
 

@@ -17,7 +17,7 @@ MAX_TYPES = 8
 H4D_OK, H4D_EINVAL, H4D_ENOMEM, H4D_EHIP, H4D_ECAPACITY, H4D_ENONFINITE, H4D_ENODEV = 0, -1, -2, -3, -4, -5, -6
 MOVE_AUTO, MOVE_INSERT, MOVE_DELETE = 0, 1, -1
 PREC_FP64, PREC_FP32 = 0, 1
-FLAG_EMPTY, FLAG_NONFINITE, FLAG_RETRIED = 0x1, 0x2, 0x4
+FLAG_EMPTY, FLAG_NONFINITE, FLAG_RETRIED, FLAG_IDLE = 0x1, 0x2, 0x4, 0x8
 
 
 class H4DError(RuntimeError):
@@ -117,9 +117,20 @@ def lib() -> C.CDLL:
         L.h4d_set_timing.argtypes = [vp, C.c_int32]
         L.h4d_stream_copy.argtypes = [C.c_int64, C.c_int32, C.POINTER(C.c_double)]
         L.h4d_get_timing.argtypes = [vp, C.POINTER(Timing)]
-        for name in ("h4d_stream_copy", "h4d_set_timing", "h4d_get_timing", "h4d_init_system", "h4d_build_neighbors", "h4d_run_nemd_trial", "h4d_run_trials",
-                     "h4d_sample_observables", "h4d_get_state", "h4d_set_trial_index", "h4d_forces_at",
-                     "h4d_destroy"):
+        L.h4d_init_batch.argtypes = [C.POINTER(Params), C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_int64), vp, C.POINTER(vp)]
+        L.h4d_num_boxes.argtypes = [vp]
+        L.h4d_run_batch.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(Trial)]
+        L.h4d_get_box_state.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                        C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int32),
+                                        C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
+        L.h4d_box_observables.argtypes = [vp, C.c_int32, C.POINTER(Observables)]
+        L.h4d_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double)]
+        for name in ("h4d_stream_copy", "h4d_set_timing", "h4d_get_timing", "h4d_init_system", "h4d_build_neighbors",
+                     "h4d_run_nemd_trial", "h4d_run_trials", "h4d_sample_observables", "h4d_get_state",
+                     "h4d_set_trial_index", "h4d_forces_at", "h4d_destroy", "h4d_init_batch", "h4d_num_boxes",
+                     "h4d_run_batch", "h4d_get_box_state", "h4d_box_observables", "h4d_autotune"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -175,7 +186,115 @@ def stream_copy(nbytes: int, reps: int = 20) -> float:
     return ms.value
 
 
-class System:
+def _state_of(h, box: int) -> dict:
+    n = C.c_int32()
+    ns = C.c_int32()
+    _check(lib().h4d_get_box_state(h, box, 0, C.byref(n), C.byref(ns), None, None, None, None, None))
+    cap = max(n.value, 1)
+    x = np.zeros((cap, 3)); v = np.zeros((cap, 3))
+    t = np.zeros(cap, np.int32); m = np.zeros(cap, np.int32)
+    g = np.zeros(cap, np.int64)
+    _check(lib().h4d_get_box_state(h, box, cap, C.byref(n), C.byref(ns),
+                                   x.ctypes.data_as(C.POINTER(C.c_double)),
+                                   v.ctypes.data_as(C.POINTER(C.c_double)),
+                                   t.ctypes.data_as(C.POINTER(C.c_int32)),
+                                   m.ctypes.data_as(C.POINTER(C.c_int32)),
+                                   g.ctypes.data_as(C.POINTER(C.c_int64))))
+    k = n.value
+    return dict(n=k, nsalt=ns.value, x=x[:k], v=v[:k], type=t[:k], mol=m[:k], tag=g[:k])
+
+
+class _Handle:
+    """Common part of single-box systems and batches."""
+
+    _h = None
+
+    def close(self):
+        if self._h is not None:
+            lib().h4d_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def build_neighbors(self):
+        _check(lib().h4d_build_neighbors(self._h))
+
+    def set_trial_index(self, t: int):
+        _check(lib().h4d_set_trial_index(self._h, t))
+
+    def set_timing(self, on: bool = True):
+        _check(lib().h4d_set_timing(self._h, 1 if on else 0))
+
+    def timing(self) -> dict:
+        t = Timing()
+        _check(lib().h4d_get_timing(self._h, C.byref(t)))
+        return t.as_dict()
+
+    def autotune(self, trials: int = 2):
+        lanes = C.c_int32()
+        ns = C.c_double()
+        _check(lib().h4d_autotune(self._h, trials, C.byref(lanes), C.byref(ns)))
+        return lanes.value, ns.value
+
+    def box_state(self, box: int) -> dict:
+        return _state_of(self._h, box)
+
+    def box_observables(self, box: int) -> dict:
+        o = Observables()
+        _check(lib().h4d_box_observables(self._h, box, C.byref(o)))
+        return o.as_dict()
+
+    @property
+    def n_boxes(self) -> int:
+        return lib().h4d_num_boxes(self._h)
+
+
+class Batch(_Handle):
+    """Independent boxes run together: box b has edges boxes[b] and its own
+    Philox stream (params["stream"] + b)."""
+
+    def __init__(self, params: dict, boxes, xs, types, tags, nsalts, stream=None):
+        self._h = None
+        self.params = dict(params)
+        nb = len(boxes)
+        edges = np.ascontiguousarray(np.asarray(boxes, dtype=np.float64).reshape(nb, 3))
+        n_atoms = np.array([len(t) for t in types], np.int32)
+        ns = np.ascontiguousarray(nsalts, dtype=np.int32)
+        x = np.ascontiguousarray(np.concatenate([np.asarray(v, np.float64).reshape(-1, 3) for v in xs]))
+        t = np.ascontiguousarray(np.concatenate(types).astype(np.int32))
+        g = np.ascontiguousarray(np.concatenate(tags).astype(np.int64))
+        h = C.c_void_p()
+        p = make_params(params)
+        _check(lib().h4d_init_batch(
+            C.byref(p), nb, edges.ctypes.data_as(C.POINTER(C.c_double)),
+            n_atoms.ctypes.data_as(C.POINTER(C.c_int32)), ns.ctypes.data_as(C.POINTER(C.c_int32)),
+            x.ctypes.data_as(C.POINTER(C.c_double)), t.ctypes.data_as(C.POINTER(C.c_int32)),
+            g.ctypes.data_as(C.POINTER(C.c_int64)),
+            stream if stream is not None else current_stream(), C.byref(h)))
+        self._h = h
+        self.nb = nb
+
+    @classmethod
+    def from_workloads(cls, ws, **overrides):
+        params = dict(ws[0].params)
+        params.update(overrides)
+        return cls(params, [w.params["box"] for w in ws], [w.x for w in ws], [w.type for w in ws],
+                   [w.tag for w in ws], [w.nsalt for w in ws])
+
+    def run(self, trials_per_box: int, move: int = MOVE_AUTO, as_array: bool = False):
+        """trials_per_box more trials in every box; records box-major."""
+        recs = (Trial * max(self.nb * trials_per_box, 1))()
+        _check(lib().h4d_run_batch(self._h, trials_per_box, move, recs))
+        if as_array:
+            return recs
+        return [[recs[b * trials_per_box + q].as_dict() for q in range(trials_per_box)] for b in range(self.nb)]
+
+
+class System(_Handle):
     """One simulation box on the GPU."""
 
     def __init__(self, params: dict, x, type_, mol, tag, nsalt: int, n_mol: int = 0, stream=None):
@@ -200,20 +319,6 @@ class System:
         params.update(overrides)
         return cls(params, w.x, w.type, w.mol, w.tag, w.nsalt, w.n_mol)
 
-    def close(self):
-        if self._h is not None:
-            lib().h4d_destroy(self._h)
-            self._h = None
-
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
-
-    def build_neighbors(self):
-        _check(lib().h4d_build_neighbors(self._h))
-
     def trial(self, move: int = MOVE_AUTO) -> dict:
         r = Trial()
         _check(lib().h4d_run_nemd_trial(self._h, move, C.byref(r)))
@@ -226,25 +331,8 @@ class System:
             return recs
         return [recs[q].as_dict() for q in range(n)]
 
-    def set_trial_index(self, t: int):
-        _check(lib().h4d_set_trial_index(self._h, t))
-
     def state(self) -> dict:
-        n = C.c_int32()
-        ns = C.c_int32()
-        _check(lib().h4d_get_state(self._h, 0, C.byref(n), C.byref(ns), None, None, None, None, None))
-        cap = n.value
-        x = np.zeros((max(cap, 1), 3)); v = np.zeros((max(cap, 1), 3))
-        t = np.zeros(max(cap, 1), np.int32); m = np.zeros(max(cap, 1), np.int32)
-        g = np.zeros(max(cap, 1), np.int64)
-        _check(lib().h4d_get_state(self._h, max(cap, 1), C.byref(n), C.byref(ns),
-                                   x.ctypes.data_as(C.POINTER(C.c_double)),
-                                   v.ctypes.data_as(C.POINTER(C.c_double)),
-                                   t.ctypes.data_as(C.POINTER(C.c_int32)),
-                                   m.ctypes.data_as(C.POINTER(C.c_int32)),
-                                   g.ctypes.data_as(C.POINTER(C.c_int64))))
-        k = n.value
-        return dict(n=k, nsalt=ns.value, x=x[:k], v=v[:k], type=t[:k], mol=m[:k], tag=g[:k])
+        return _state_of(self._h, 0)
 
     def forces_at(self, flying=(-1, -1), w: float = 0.0):
         st = self.state()
@@ -254,14 +342,6 @@ class System:
         _check(lib().h4d_forces_at(self._h, fl, w, F.ctypes.data_as(C.POINTER(C.c_double)),
                                    e.ctypes.data_as(C.POINTER(C.c_double))))
         return F[: st["n"]], dict(U=e[0], U_lj=e[1], U_c=e[2])
-
-    def set_timing(self, on: bool = True):
-        _check(lib().h4d_set_timing(self._h, 1 if on else 0))
-
-    def timing(self) -> dict:
-        t = Timing()
-        _check(lib().h4d_get_timing(self._h, C.byref(t)))
-        return t.as_dict()
 
     def observables(self) -> dict:
         o = Observables()
