@@ -461,15 +461,16 @@ __global__ __launch_bounds__(kBlock) void k_list_allpairs(KArgs a, int k, int b0
     }
 }
 
-// Cell form: one block per centre cell.  The atoms of all 27 stencil cells
-// are staged in LDS (fixed-point coordinates + working slot) in stencil
-// order; each wavefront takes a share of the centre atoms and tests 64
-// candidates per ballot, appending in stencil order.  Dynamic LDS:
-// 27 * cell_cap * 16 bytes.  Also records the build positions and clears this
-// cell's count in the other buffer.
-__global__ __launch_bounds__(kBlock) void k_list_cells(KArgs a, int k, int b0, int cb) {
+// Cell form: one block per centre cell, one thread per centre atom.  The
+// 27 stencil cells are staged in LDS one z-layer (9 cells) at a time
+// (fixed-point coordinates + working slot, in stencil order); every thread
+// scans the staged candidates (LDS broadcast) and appends its partners in
+// stencil order.  Dynamic LDS: 9 * cell_cap * 16 bytes; block size: cell_cap
+// rounded up to whole wavefronts.  Also records the build positions, clears
+// this cell's count in the other buffer and the box's fast lists.
+__global__ __launch_bounds__(1024) void k_list_cells(KArgs a, int k, int b0, int cb) {
     extern __shared__ uint4 cand[];
-    __shared__ int cidx[27], cnt27[27], off[28];
+    __shared__ int cidx[27], cnt27[27], off[10];
     const int cap = a.cell_cap;
     const int cc = blockIdx.x;
     const int bi = box_of_cell(a, cc);
@@ -485,67 +486,69 @@ __global__ __launch_bounds__(kBlock) void k_list_cells(KArgs a, int k, int b0, i
         cidx[t] = c2;
         cnt27[t] = min(a.cell_cnt[cb][c2], cap);
     }
+    if (threadIdx.x == 0 && cc == B.c0) c->nfast[0] = c->nfast[1] = c->nfast[2] = 0;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int run = 0;
-        for (int t = 0; t < 27; ++t) { off[t] = run; run += cnt27[t]; }
-        off[27] = run;
-        if (cc == B.c0) c->nfast[0] = c->nfast[1] = c->nfast[2] = 0;
-    }
-    __syncthreads();
-    const int total = off[27];
-    // one pass of loads over all stencil candidates
-    for (int u = threadIdx.x; u < total; u += kBlock) {
-        int t = 0;
-        while (off[t + 1] <= u) ++t;
-        const int j = a.cell_atoms[cb][(size_t)cidx[t] * cap + (u - off[t])];
-        const uint4 q = a.fx[b][j];
-        cand[u] = make_uint4(q.x, q.y, q.z, (unsigned)j);
-    }
-    __syncthreads();
-    // the centre atoms' meta words (fast flags are cleared below)
-    __shared__ unsigned cmeta[1024];
-    for (int u = threadIdx.x; u < off[14] - off[13] && u < 1024; u += kBlock)
-        cmeta[u] = a.fx[b][cand[off[13] + u].w].w;
-    __syncthreads();
-    const int c0 = off[13], mc = off[14] - off[13];      // the centre cell itself
-    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    // this thread's centre atom (the centre cell is stencil entry 13)
+    const int mc = cnt27[13];
+    const int i = threadIdx.x;
+    const bool own = i < mc;
+    const int wi = own ? a.cell_atoms[cb][(size_t)cidx[13] * cap + i] : 0;
+    const uint4 qi = own ? a.fx[b][wi] : make_uint4(0, 0, 0, 0);
+    const int mi = (own && a.G.water) ? a.wmol[wi] : -1;
     const float rl2 = (float)a.G.rlist2 * 1.00001f;
-    const unsigned long long below = (1ull << lane) - 1ull;
-    const bool molecules = a.G.water != 0;
-    for (int t = wave; t < mc; t += kBlock / kWave) {
-        const uint4 qi = cand[c0 + t];
-        const int wi = (int)qi.w;
-        const int mi = molecules ? a.wmol[wi] : -1;
-        int cnt = 0;
-        for (int base = 0; base < total; base += kWave) {
-            const int u = base + lane;
-            bool acc = false;
-            int j = 0;
-            if (u < total) {
-                const uint4 qj = cand[u];
-                j = (int)qj.w;
-                if (j != wi) {
-                    const float dx = (float)(int)(qi.x - qj.x) * B.fx_scale[0];
-                    const float dy = (float)(int)(qi.y - qj.y) * B.fx_scale[1];
-                    const float dz = (float)(int)(qi.z - qj.z) * B.fx_scale[2];
-                    acc = dx * dx + dy * dy + dz * dz < rl2;
-                    if (acc && mi >= 0 && a.wmol[j] == mi) acc = false;
+    const float sx = B.fx_scale[0], sy = B.fx_scale[1], sz = B.fx_scale[2];
+    const int L = a.lanes, ll = a.lanes_log2, la = 6 - ll;
+    // blocked list row of this atom: entry q at row + (q / L) * 64 + q % L
+    int *row = a.nbr + (size_t)(wi >> la) * (size_t)(a.nbr_cap >> ll) * kWave + (size_t)((wi & ((1 << la) - 1)) << ll);
+    int cnt = 0;
+    for (int layer = 0; layer < 3; ++layer) {
+        if (threadIdx.x == 0) {
+            int run = 0;
+            for (int t = 0; t < 9; ++t) { off[t] = run; run += cnt27[9 * layer + t]; }
+            off[9] = run;
+        }
+        __syncthreads();
+        const int total = off[9];
+        for (int t = 0; t < 9; ++t) {
+            const int m = cnt27[9 * layer + t];
+            const int *src = a.cell_atoms[cb] + (size_t)cidx[9 * layer + t] * cap;
+            for (int u = threadIdx.x; u < m; u += blockDim.x) {
+                const int j = src[u];
+                const uint4 q = a.fx[b][j];
+                cand[off[t] + u] = make_uint4(q.x, q.y, q.z, (unsigned)j);
+            }
+        }
+        __syncthreads();
+        if (own) {
+            auto test = [&](const uint4 &qj) {
+                const int j = (int)qj.w;
+                const float dx = (float)(int)(qi.x - qj.x) * sx;
+                const float dy = (float)(int)(qi.y - qj.y) * sy;
+                const float dz = (float)(int)(qi.z - qj.z) * sz;
+                bool acc = dx * dx + dy * dy + dz * dz < rl2 && j != wi;
+                if (acc && mi >= 0 && a.wmol[j] == mi) acc = false;
+                if (acc) {
+                    if (cnt < a.nbr_cap) row[(size_t)(cnt >> ll) * kWave + (cnt & (L - 1))] = j;
+                    ++cnt;
                 }
+            };
+            int u = 0;
+            for (; u + 8 <= total; u += 8) {   // eight LDS reads in flight
+                uint4 q[8];
+#pragma unroll
+                for (int v = 0; v < 8; ++v) q[v] = cand[u + v];
+#pragma unroll
+                for (int v = 0; v < 8; ++v) test(q[v]);
             }
-            const unsigned long long m = __ballot(acc);
-            if (acc) {
-                const int q = cnt + __popcll(m & below);
-                if (q < a.nbr_cap) a.nbr[nbr_slot(a, wi, q)] = j;
-            }
-            cnt += __popcll(m);
+            for (; u < total; ++u) test(cand[u]);
         }
-        if (lane == 0) {
-            a.nnbr[wi] = min(cnt, a.nbr_cap);
-            a.posb[wi] = qi;
-            if (t < 1024) unflag_fast(a, b, wi, cmeta[t]);
-            if (cnt > a.nbr_cap) { atomicOr(&c->err, kErrNbr); atomicMax(&c->max_nbr, cnt); }
-        }
+        __syncthreads();
+    }
+    if (own) {
+        a.nnbr[wi] = min(cnt, a.nbr_cap);
+        a.posb[wi] = qi;
+        unflag_fast(a, b, wi, qi.w);
+        if (cnt > a.nbr_cap) { atomicOr(&c->err, kErrNbr); atomicMax(&c->max_nbr, cnt); }
     }
     if (threadIdx.x == 0) a.cell_cnt[cb ^ 1][cc] = 0;
 }
