@@ -55,6 +55,10 @@ double or_u01(uint64_t bits)
     return ((double)(bits >> 12) + 0.5) * 0x1p-52;
 }
 
+static int trial_begin(const or_params *p, or_state *s, uint64_t trial, int force_move,
+                       const or_proposal *prop, or_trial_rec *rec, int *ic_out, int *ia_out, int *nf_out,
+                       double *feat_out);
+
 static void draw4(const or_params *p, uint64_t a, uint64_t b, uint64_t c, double u[4])
 {
     uint64_t ctr[4] = {a, b, c, 0}, key[2] = {p->seed, p->stream}, o[4];
@@ -62,8 +66,9 @@ static void draw4(const or_params *p, uint64_t a, uint64_t b, uint64_t c, double
     for (int i = 0; i < 4; ++i) u[i] = or_u01(o[i]);
 }
 
-/* Counter purposes. */
-enum { PURPOSE_SELECT = 1, PURPOSE_MB = 2, PURPOSE_NSTEPS = 3 };
+/* Counter purposes: move and plain sites, Maxwell-Boltzmann momenta, N_f,
+ * candidate sites of the learned proposal, its categorical choice. */
+enum { PURPOSE_SELECT = 1, PURPOSE_MB = 2, PURPOSE_NSTEPS = 3, PURPOSE_CAND = 4, PURPOSE_PICK = 5 };
 
 /* ------------------------------------------------------------------ */
 /* Geometry                                                            */
@@ -536,8 +541,134 @@ static void remove_atom(or_state *s, int i)
  * return the flyers are marked (an insertion has appended its ghost pair).
  * Returns 0 if the trial ends here (deletion from an empty box), 1 if the
  * trajectory follows, negative on error. */
+/* ------------------------------------------------------------------ */
+/* Features of a candidate pair site for the learned proposal.         */
+/* ------------------------------------------------------------------ */
+#define FEAT_CLIP 1.0e6
+
+static double clipd(double v)
+{
+    return v > FEAT_CLIP ? FEAT_CLIP : (v < -FEAT_CLIP ? -FEAT_CLIP : v);
+}
+
+/* The 31 descriptors of one ion of type T at r, from every non-flying
+ * atom (minimum image, all pairs):
+ *   [0, 24)  0.1 x Gaussian shell counts of atom types 0..3 in six shells
+ *            of width rc/6 up to rc = max cutoff (centres (m + 1/2) rc/6,
+ *            standard deviation rc/12);
+ *   24       asinh(beta U_C) of the ion at w = 0;
+ *   25       asinh(beta |F_C|), the Coulomb force on it at w = 0;
+ *   26, 27   asinh(beta U_LJ) at w = 0 and at w = w_max;
+ *   28       asinh(beta exp(-kappa_sr w_max) U_C) at w = w_max (Eq. 11);
+ *   29, 30   distance to the nearest atom and to the nearest counter-ion,
+ *            over rc, capped at 1.
+ * Every pair term is scaled by beta and clipped to +-1e6 before it is
+ * summed. */
+static void ion_features(const or_params *p, const or_state *s, int T, int counter, const double r[3],
+                         double out[31])
+{
+    const double beta = 1.0 / p->kT;
+    const double rc = p->rc_lj > p->rc_coul ? p->rc_lj : p->rc_coul;
+    const double delta = rc / 6.0, sd = delta / 2.0;
+    const double gmax = exp(-p->kappa_sr * p->w_max);
+    double shell[24] = {0};
+    double uc0 = 0.0, ulj0 = 0.0, uljw = 0.0, ucw = 0.0, F[3] = {0.0, 0.0, 0.0};
+    double dmin = INFINITY, dct = INFINITY;
+    for (int j = 0; j < s->n; ++j) {
+        if (s->flying[j]) continue;
+        double d[3], r2 = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            d[c] = minimg(r[c] - s->x[3 * j + c], p->box[c]);
+            r2 += d[c] * d[c];
+        }
+        const double rr = sqrt(r2);
+        const int tj = s->type[j];
+        if (rr < dmin) dmin = rr;
+        if (tj == counter && rr < dct) dct = rr;
+        if (rr < rc && tj < 4)
+            for (int m = 0; m < 6; ++m) {
+                const double z = (rr - (m + 0.5) * delta) / sd;
+                shell[6 * tj + m] += exp(-0.5 * z * z);
+            }
+        double ulj, uc, dlj, dc;
+        or_pair(p, T, tj, r2, 1.0, &ulj, &uc, &dlj, &dc);
+        ulj0 += clipd(beta * ulj);
+        uc0 += clipd(beta * uc);
+        const double fr = clipd(-beta * dc);          /* radial Coulomb force */
+        for (int c = 0; c < 3; ++c) F[c] += fr * d[c] / rr;
+        or_pair(p, T, tj, r2 + p->w_max * p->w_max, gmax, &ulj, &uc, &dlj, &dc);
+        uljw += clipd(beta * ulj);
+        ucw += clipd(beta * uc);
+    }
+    for (int q = 0; q < 24; ++q) out[q] = 0.1 * shell[q];
+    out[24] = asinh(uc0);
+    out[25] = asinh(sqrt(F[0] * F[0] + F[1] * F[1] + F[2] * F[2]));
+    out[26] = asinh(ulj0);
+    out[27] = asinh(uljw);
+    out[28] = asinh(ucw);
+    out[29] = (dmin < rc ? dmin : rc) / rc;
+    out[30] = (dct < rc ? dct : rc) / rc;
+}
+
+/* Features (64) of the candidate pair site: cation at site[0..2], anion
+ * at site[3..5], on the physical state without the flying atoms: 31 for
+ * the cation, 31 for the anion, then the pair's separation over rc (capped
+ * at 1) and asinh(beta u) of the pair's own energy (3D, unscreened). */
+int or_site_features(const or_params *p, const or_state *s, const double site[6], double out[64])
+{
+    const double beta = 1.0 / p->kT;
+    const double rc = p->rc_lj > p->rc_coul ? p->rc_lj : p->rc_coul;
+    ion_features(p, s, p->cation_type, p->anion_type, site, out);
+    ion_features(p, s, p->anion_type, p->cation_type, site + 3, out + 31);
+    double r2 = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        const double d = minimg(site[c] - site[3 + c], p->box[c]);
+        r2 += d * d;
+    }
+    const double rr = sqrt(r2);
+    double ulj, uc, dlj, dc;
+    or_pair(p, p->cation_type, p->anion_type, r2, 1.0, &ulj, &uc, &dlj, &dc);
+    out[62] = (rr < rc ? rr : rc) / rc;
+    out[63] = asinh(clipd(beta * (ulj + uc)));
+    return 0;
+}
+
+/* Candidate j of trial t: cation and anion uniform in the box, from the
+ * counters (t, 4, j, 0) and (t, 4, j, 1). */
+static void candidate_site(const or_params *p, uint64_t trial, int j, double site[6])
+{
+    double a[4], b[4];
+    draw4(p, trial, PURPOSE_CAND, (uint64_t)j, a);
+    uint64_t c[4] = {trial, PURPOSE_CAND, (uint64_t)j, 1}, k[2] = {p->seed, p->stream}, o[4];
+    or_philox4x64(c, k, o);
+    for (int q = 0; q < 3; ++q) b[q] = or_u01(o[q]);
+    for (int d = 0; d < 3; ++d) {
+        site[d] = wrap1(p->box[d] * a[d], p->box[d]);
+        site[3 + d] = wrap1(p->box[d] * b[d], p->box[d]);
+    }
+}
+
+/* log weights of n sites: the proposal's network, or 0 without one */
+static int score_sites(const or_params *p, const or_state *s, const or_proposal *prop, int n,
+                       const double *sites, double *feat, double *logw)
+{
+    for (int j = 0; j < n; ++j) or_site_features(p, s, sites + 6 * j, feat + 64 * j);
+    if (!prop->fn) {
+        for (int j = 0; j < n; ++j) logw[j] = 0.0;
+        return 0;
+    }
+    return prop->fn(prop->ctx, n, feat, logw);
+}
+
 int or_trial_begin(const or_params *p, or_state *s, uint64_t trial, int force_move,
                    or_trial_rec *rec, int *ic_out, int *ia_out, int *nf_out)
+{
+    return trial_begin(p, s, trial, force_move, NULL, rec, ic_out, ia_out, nf_out, NULL);
+}
+
+static int trial_begin(const or_params *p, or_state *s, uint64_t trial, int force_move,
+                       const or_proposal *prop, or_trial_rec *rec, int *ic_out, int *ia_out, int *nf_out,
+                       double *feat_out)
 {
     memset(rec, 0, sizeof(*rec));
     rec->trial = (int64_t)trial;
@@ -566,12 +697,41 @@ int or_trial_begin(const or_params *p, or_state *s, uint64_t trial, int force_mo
     }
     int ic, ia;
     if (move > 0) {
-        /* Eq. (4): both flying ions placed uniformly in the box (1/V each). */
+        /* Eq. (4): both flying ions placed uniformly in the box (1/V each);
+         * with a learned proposal, one of k uniform candidates chosen with
+         * probability proportional to its weight (multiple-try form). */
         if (s->n + 2 > s->cap) return -3;
+        double site[6];
+        for (int d = 0; d < 3; ++d) { site[d] = p->box[d] * u[1 + d]; site[3 + d] = p->box[d] * u[4 + d]; }
+        if (prop && prop->k >= 1) {
+            const int k = prop->k;
+            double *sites = malloc(sizeof(double) * 6 * (size_t)k);
+            double *feat = malloc(sizeof(double) * 64 * (size_t)k);
+            double *logw = malloc(sizeof(double) * (size_t)k);
+            if (!sites || !feat || !logw) { free(sites); free(feat); free(logw); return -1; }
+            for (int j = 0; j < k; ++j) candidate_site(p, trial, j, sites + 6 * j);
+            if (score_sites(p, s, prop, k, sites, feat, logw)) { free(sites); free(feat); free(logw); return -8; }
+            /* categorical choice: the first candidate whose running weight
+             * exceeds u W (weights relative to the largest) */
+            double mx = logw[0], W = 0.0, run = 0.0, us[4];
+            for (int j = 1; j < k; ++j) if (logw[j] > mx) mx = logw[j];
+            for (int j = 0; j < k; ++j) W += exp(logw[j] - mx);
+            draw4(p, trial, PURPOSE_PICK, 0, us);
+            const double target = us[0] * W;
+            int sel = k - 1;
+            for (int j = 0; j < k; ++j) {
+                run += exp(logw[j] - mx);
+                if (run > target) { sel = j; break; }
+            }
+            or_mtm_log_factor(+1, k, logw, sel, &rec->ln_proposal);
+            for (int q = 0; q < 6; ++q) site[q] = sites[6 * sel + q];
+            if (feat_out) memcpy(feat_out, feat + 64 * sel, 64 * sizeof(double));
+            free(sites); free(feat); free(logw);
+        }
         ic = s->n; ia = s->n + 1;
         for (int d = 0; d < 3; ++d) {
-            s->x[3 * ic + d] = wrap1(p->box[d] * u[1 + d], p->box[d]);
-            s->x[3 * ia + d] = wrap1(p->box[d] * u[4 + d], p->box[d]);
+            s->x[3 * ic + d] = wrap1(site[d], p->box[d]);
+            s->x[3 * ia + d] = wrap1(site[3 + d], p->box[d]);
         }
         s->type[ic] = p->cation_type; s->type[ia] = p->anion_type;
         s->mol[ic] = -1; s->mol[ia] = -1;
@@ -605,12 +765,19 @@ int or_trial_begin(const or_params *p, or_state *s, uint64_t trial, int force_mo
 int or_trial(const or_params *p, or_state *s, uint64_t trial, int force_move,
              or_trial_rec *rec)
 {
+    return or_trial_learned(p, s, trial, force_move, NULL, rec, NULL);
+}
+
+int or_trial_learned(const or_params *p, or_state *s, uint64_t trial, int force_move,
+                     const or_proposal *prop, or_trial_rec *rec, double *feat_out)
+{
     const double beta = 1.0 / p->kT;
     const double V = p->box[0] * p->box[1] * p->box[2];
     const int Ns = s->nsalt;
     const int n_orig = s->n;
     int ic, ia, nf;
-    const int st = or_trial_begin(p, s, trial, force_move, rec, &ic, &ia, &nf);
+    if (prop && prop->k < 1) prop = NULL;
+    const int st = trial_begin(p, s, trial, force_move, prop, rec, &ic, &ia, &nf, feat_out);
     if (st <= 0) return st;
     const int move = rec->move;
     const int n_small = (move > 0) ? Ns : Ns - 1;
@@ -641,6 +808,21 @@ int or_trial(const or_params *p, or_state *s, uint64_t trial, int force_move,
     else or_compute(p, s, 0.0, OR_MODE_EXCL, NULL, &e);
     const double U1 = e.U, K1 = or_kinetic(p, s);
     if (move < 0) E_switch = -u_fly(p, s, p->w_max);
+    if (move < 0 && prop) {
+        /* reverse multiple-try weights on the post-trajectory N-state:
+         * the removed pair's site first, then k - 1 fresh candidates */
+        const int k = prop->k;
+        double *sites = malloc(sizeof(double) * 6 * (size_t)k);
+        double *feat = malloc(sizeof(double) * 64 * (size_t)k);
+        double *logw = malloc(sizeof(double) * (size_t)k);
+        if (!sites || !feat || !logw) { free(sites); free(feat); free(logw); free(x0); return -1; }
+        for (int d = 0; d < 3; ++d) { sites[d] = s->x[3 * ic + d]; sites[3 + d] = s->x[3 * ia + d]; }
+        for (int j = 0; j + 1 < k; ++j) candidate_site(p, trial, j, sites + 6 * (j + 1));
+        if (score_sites(p, s, prop, k, sites, feat, logw)) { free(sites); free(feat); free(logw); free(x0); return -8; }
+        or_mtm_log_factor(-1, k, logw, 0, &rec->ln_proposal);
+        if (feat_out) memcpy(feat_out, feat, 64 * sizeof(double));
+        free(sites); free(feat); free(logw);
+    }
 
     const double dH = (U1 + K1) - H0;
     /* Eqs. (6) and (8) with Lambda_s: ln of (V / (Lambda^3 (N+1)))^2. */
@@ -649,6 +831,7 @@ int or_trial(const or_params *p, or_state *s, uint64_t trial, int force_move,
     double lnR;
     if (move > 0) lnR = -beta * dH + p->beta_mu + I;
     else lnR = -beta * dH - p->beta_mu - I;
+    lnR += rec->ln_proposal;
     rec->dU = U1 - rec->dU;
     rec->dK = K1 - rec->dK;
     rec->dH = dH;

@@ -112,8 +112,35 @@ int or_trial_begin(const or_params *p, or_state *s, uint64_t trial, int force_mo
 int or_trial(const or_params *p, or_state *s, uint64_t trial, int force_move,
              or_trial_rec *rec);
 
-/* Multiple-try (learned-proposal) trial: the caller supplies the log
- * weights of the candidate sets (see or_trial_mtm in the source). */
+/*
+ * Learned proposal (multiple-try form of the uniform pair insertion of
+ * Eq. 4).  An insertion draws k uniform candidate pair sites (counters
+ * (t, 4, j, 0/1)), weighs them by exp(logit) on the state before the
+ * trajectory and picks one with probability proportional to its weight
+ * (uniform (t, 5, 0, 0)); the ratio gains ln(W/k) - logit(chosen).  A
+ * deletion weighs the removed pair's site and k - 1 fresh candidates on the
+ * state after the trajectory (pair removed); the ratio gains
+ * logit(removed) - ln(W/k).  Exact for any weights; k = 1 or equal weights
+ * give the uniform proposal.
+ */
+typedef int (*or_logit_fn)(void *ctx, int n, const double *features /* n x 64 */, double *logits /* n */);
+typedef struct {
+    int32_t k;          /* candidates per move (>= 1)                     */
+    or_logit_fn fn;     /* network; NULL: every logit 0                   */
+    void *ctx;
+} or_proposal;
+
+/* The 64 features of a candidate pair site (cation site[0..2], anion
+ * site[3..5]) on the physical state without the flying atoms. */
+int or_site_features(const or_params *p, const or_state *s, const double site[6], double out[64]);
+
+/* A trial with the learned proposal (prop NULL: uniform).  feat_out (may
+ * be NULL) receives the features of the inserted or removed pair's site. */
+int or_trial_learned(const or_params *p, or_state *s, uint64_t trial, int force_move,
+                     const or_proposal *prop, or_trial_rec *rec, double *feat_out);
+
+/* ln of the multiple-try factor for log weights logw[0..k-1] (insertion:
+ * sel is the chosen candidate; deletion: logw[0] is the removed pair). */
 int or_mtm_log_factor(int move, int k, const double *logw, int sel, double *out);
 
 #endif

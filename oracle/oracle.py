@@ -60,6 +60,13 @@ class TrialRec(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+LOGIT_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double))
+
+
+class Proposal(C.Structure):
+    _fields_ = [("k", C.c_int32), ("fn", LOGIT_FN), ("ctx", C.c_void_p)]
+
+
 class Energy(C.Structure):
     _fields_ = [("U", C.c_double), ("U_lj", C.c_double), ("U_c", C.c_double),
                 ("virial", C.c_double), ("dUdw", C.c_double)]
@@ -94,6 +101,9 @@ def lib():
                                      C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.or_mtm_log_factor.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_double), C.c_int,
                                         C.POINTER(C.c_double)]
+        L.or_site_features.argtypes = [P, S, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.or_trial_learned.argtypes = [P, S, C.c_uint64, C.c_int, C.POINTER(Proposal), C.POINTER(TrialRec),
+                                       C.POINTER(C.c_double)]
         _lib = L
     return _lib
 
@@ -182,6 +192,44 @@ class OracleSystem:
         if rc:
             raise RuntimeError(f"or_trial failed: {rc}")
         return rec.as_dict()
+
+    def site_features(self, site) -> np.ndarray:
+        """Features (64) of the pair site (cation xyz, anion xyz) on the
+        current state without its flying atoms."""
+        st = np.ascontiguousarray(site, dtype=np.float64).reshape(6)
+        out = np.zeros(64)
+        rc = lib().or_site_features(C.byref(self.p), C.byref(self.s), _dp(st), _dp(out))
+        if rc:
+            raise RuntimeError(f"or_site_features failed: {rc}")
+        return out
+
+    def trial_learned(self, t: int, k: int, logits=None, force_move: int = 0):
+        """Trial with the learned proposal.  logits(features n x 64) -> n
+        logits, or None for equal weights.  Returns (record, features of the
+        inserted / removed site)."""
+        prop = Proposal()
+        prop.k = k
+        keep = None
+        if logits is not None:
+            def cb(ctx, n, feat, out):
+                try:
+                    X = np.ctypeslib.as_array(feat, shape=(n, 64)).copy()
+                    s = np.asarray(logits(X), dtype=np.float64).reshape(n)
+                    for j in range(n):
+                        out[j] = float(s[j])
+                    return 0
+                except Exception:
+                    return -1
+            keep = LOGIT_FN(cb)
+            prop.fn = keep
+        rec = TrialRec()
+        feat = np.zeros(64)
+        rc = lib().or_trial_learned(C.byref(self.p), C.byref(self.s), t, force_move, C.byref(prop),
+                                    C.byref(rec), _dp(feat))
+        if rc:
+            raise RuntimeError(f"or_trial_learned failed: {rc}")
+        del keep
+        return rec.as_dict(), feat
 
     def trial_begin(self, t: int, force_move: int = 0) -> dict:
         """Proposal, momenta, H_start and (insertion) switch-on energy of
