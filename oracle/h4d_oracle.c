@@ -555,7 +555,8 @@ static double clipd(double v)
  * atom (minimum image, all pairs):
  *   [0, 24)  0.1 x Gaussian shell counts of atom types 0..3 in six shells
  *            of width rc/6 up to rc = max cutoff (centres (m + 1/2) rc/6,
- *            standard deviation rc/12);
+ *            standard deviation rc/12), each term tapered by (1 - r^2/rc^2)^2
+ *            so that every feature is continuous in the positions;
  *   24       asinh(beta U_C) of the ion at w = 0;
  *   25       asinh(beta |F_C|), the Coulomb force on it at w = 0;
  *   26, 27   asinh(beta U_LJ) at w = 0 and at w = w_max;
@@ -585,11 +586,13 @@ static void ion_features(const or_params *p, const or_state *s, int T, int count
         const int tj = s->type[j];
         if (rr < dmin) dmin = rr;
         if (tj == counter && rr < dct) dct = rr;
-        if (rr < rc && tj < 4)
+        if (rr < rc && tj < 4) {
+            const double x = 1.0 - r2 / (rc * rc), taper = x * x;
             for (int m = 0; m < 6; ++m) {
                 const double z = (rr - (m + 0.5) * delta) / sd;
-                shell[6 * tj + m] += exp(-0.5 * z * z);
+                shell[6 * tj + m] += exp(-0.5 * z * z) * taper;
             }
+        }
         double ulj, uc, dlj, dc;
         or_pair(p, T, tj, r2, 1.0, &ulj, &uc, &dlj, &dc);
         ulj0 += clipd(beta * ulj);

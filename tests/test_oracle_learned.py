@@ -57,7 +57,8 @@ def test_features_translation_and_permutation_invariant():
 
 def test_lone_atom_gives_one_gaussian_shell():
     # one anion at distance (m + 1/2) rc / 6 from the cation site: that shell
-    # holds exactly 1, its neighbours exp(-2), the next exp(-8)
+    # holds exactly the taper (1 - r^2/rc^2)^2, its neighbours exp(-2) times
+    # it, the next exp(-8) times it
     w = W.small_lj(2, 0.3, 3)
     L = 40.0
     p = dict(w.params, box=[L, L, L])
@@ -68,10 +69,11 @@ def test_lone_atom_gives_one_gaussian_shell():
     s = O.OracleSystem(p, x, np.array([1], np.int32), np.array([-1], np.int32), np.array([0], np.int64), 0)
     f = s.site_features([10.0, 10.0, 10.0, 30.0, 30.0, 30.0])
     shells = f[:24].reshape(4, 6)
-    assert shells[1, m] == pytest.approx(0.1, rel=1e-14)
-    assert shells[1, m - 1] == pytest.approx(0.1 * math.exp(-2.0), rel=1e-12)
-    assert shells[1, m + 1] == pytest.approx(0.1 * math.exp(-2.0), rel=1e-12)
-    assert shells[1, m - 2] == pytest.approx(0.1 * math.exp(-8.0), rel=1e-12)
+    taper = (1.0 - (r / rc) ** 2) ** 2
+    assert shells[1, m] == pytest.approx(0.1 * taper, rel=1e-14)
+    assert shells[1, m - 1] == pytest.approx(0.1 * taper * math.exp(-2.0), rel=1e-12)
+    assert shells[1, m + 1] == pytest.approx(0.1 * taper * math.exp(-2.0), rel=1e-12)
+    assert shells[1, m - 2] == pytest.approx(0.1 * taper * math.exp(-8.0), rel=1e-12)
     assert np.all(shells[0] == 0.0) and np.all(shells[2:] == 0.0)
     assert f[29] == pytest.approx(r / rc, rel=1e-14)      # nearest atom
     assert f[30] == pytest.approx(r / rc, rel=1e-14)      # nearest counter-ion (an anion)
