@@ -130,24 +130,77 @@ def summarize(recs, wall, timing, timing_recs, traffic_bytes):
     }
 
 
+def expected_acceptance(recs):
+    """Mean Metropolis acceptance probability min(1, exp(ln R)) of the
+    records: an estimator of the acceptance rate with far less variance
+    than the count of accepted trials when acceptance is rare."""
+    vals = []
+    for r in recs:
+        lr = r.ln_ratio
+        vals.append(0.0 if (r.flags & 0x3) or not math.isfinite(lr) else math.exp(min(0.0, lr)))
+    return sum(vals) / max(1, len(vals))
+
+
+def jarzynski_beta_mu(dH, beta, volume, n_pairs):
+    """Operating chemical potential of the current state: the beta mu at
+    which the mean insertion ratio of Eq. (6), exp(-beta dH + beta mu + I),
+    is 1 over the pilot insertions (I = 2 ln(V / (N + 1)), Lambda = 1)."""
+    x = [-beta * d for d in dH if math.isfinite(d)]
+    m = max(x)
+    lme = m + math.log(sum(math.exp(v - m) for v in x) / len(x))
+    return -2.0 * math.log(volume / (n_pairs + 1)) - lme
+
+
+def timed_trials(sys_, torch, n):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    arr = sys_.trials(n, as_array=True)
+    torch.cuda.synchronize()
+    return [arr[q] for q in range(n)], time.perf_counter() - t0
+
+
 def bench_single(args, h4d, W, torch):
     w = W.config_lj_32k()
-    w.params.update(beta_mu=args.beta_mu, rebuild_every=args.rebuild_every, lanes_per_atom=args.lanes,
-                    capacity=w.n + 1024)
+    w.params.update(rebuild_every=args.rebuild_every, lanes_per_atom=args.lanes, capacity=w.n + 1024)
     if args.skin > 0:
         w.params.update(skin=args.skin)
     sys_ = h4d.System.from_workload(w)
     if args.warmup:
         sys_.trials(args.warmup)
-    # timed region: every trial launched as one captured HIP graph
-    torch.cuda.synchronize()
+    # pilot: forced uniform insertions that are never accepted (beta mu far
+    # below equilibrium), recording each site's features and dH
+    sys_.set_beta_mu(-1.0e3)
+    sys_.set_proposal(None, 1)
+    feats, dH = [], []
+    for _ in range(args.pilot):
+        r = sys_.trial(h4d.MOVE_INSERT)
+        feats.append(sys_.last_site_features())
+        dH.append(r["dH"])
+    st = sys_.state()
+    beta = 1.0 / w.params["kT"]
+    L = w.params["box"][0]
+    bmu_eq = jarzynski_beta_mu(dH, beta, L ** 3, st["nsalt"])
+    beta_mu = args.beta_mu if args.beta_mu is not None else bmu_eq
+    # the network learns clip(-beta dH, -20, 10) of the pilot sites (GPU, FP32)
+    import numpy as np
+    X = np.array(feats, dtype=np.float32)
+    y = np.clip(-beta * np.array(dH), -20.0, 10.0).astype(np.float32)
+    net = h4d.Mlp(seed=1)
     t0 = time.perf_counter()
-    arr = sys_.trials(args.steps, as_array=True)
+    steps = args.train_steps or max(50, (args.train_epochs * len(X)) // 128)
+    losses = net.train(X, y, steps=steps, batch=128, lr=1e-3, seed=2, weight_decay=1e-2)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    recs = [arr[q] for q in range(args.steps)]
-    # step-kernel duration: the same trials continue with HIP events around
-    # every launch of the fused step kernel (on the library's stream)
+    train_s = time.perf_counter() - t0
+    # timed region, uniform proposal: every trial launched as one HIP graph
+    sys_.set_beta_mu(beta_mu)
+    sys_.set_proposal(None, 0)
+    recs, wall = timed_trials(sys_, torch, args.steps)
+    # the learned proposal from the state the uniform run reached
+    sys_.set_proposal(net, args.candidates)
+    lrecs, lwall = timed_trials(sys_, torch, args.learned_steps)
+    sys_.set_proposal(None, 0)
+    # step-kernel duration: further trials with HIP events around every
+    # launch of the fused step kernel (on the library's stream)
     sys_.set_timing(True)
     tarr = sys_.trials(args.timing_trials, as_array=True)
     timing = sys_.timing()
@@ -155,12 +208,32 @@ def bench_single(args, h4d, W, torch):
     sys_.close()
     out = summarize(recs, wall, timing, [tarr[q] for q in range(args.timing_trials)],
                     counted_traffic(TRAFFIC_FILE))
+    out["expected_acceptance"] = expected_acceptance(recs)
+    out["expected_exchanges_per_s"] = out["expected_acceptance"] * out["trials_per_s"]
+    l_acc = sum(r.accepted for r in lrecs)
+    lo, hi = wilson(l_acc, len(lrecs))
+    l_exp = expected_acceptance(lrecs)
+    out["learned"] = {
+        "proposal": f"multiple-try, k = {args.candidates} candidates weighted by the trained network "
+                    "(BF16 matrix-core inference)",
+        "value": sum(r.n_atoms * r.n_steps for r in lrecs) / lwall, "unit": "atom-steps/s",
+        "trials": len(lrecs), "trials_per_s": len(lrecs) / lwall,
+        "accepted": l_acc, "accepted_exchanges_per_s": l_acc / lwall,
+        "p_acc": l_acc / max(1, len(lrecs)), "p_acc_wilson95": [lo, hi],
+        "expected_acceptance": l_exp, "expected_exchanges_per_s": l_exp * len(lrecs) / lwall,
+        "gain_expected_exchanges_per_s": (l_exp * len(lrecs) / lwall) / max(1e-300, out["expected_exchanges_per_s"]),
+        "pilot_insertions": args.pilot, "train_steps": steps, "train_s": train_s,
+        "train_loss_first": float(losses[:10].mean()), "train_loss_last": float(losses[-50:].mean()),
+    }
     config = {
         "workload": "lj32k: 32,000 LJ ions, density 0.3, 200-step NEMD pair insert/delete, "
-                    "FP32 pair arithmetic / FP64 state, energies and work, uniform proposal",
+                    "FP32 pair arithmetic / FP64 state, energies and work; value: uniform proposal, "
+                    "'learned': the trained multiple-try proposal from the same state",
         "n_atoms": w.n, "density": 0.3, "n_steps_per_trial": 200, "dt": 0.005, "w_max": 2.5,
-        "beta_mu": args.beta_mu, "skin": w.params["skin"], "proposal": "uniform",
-        "parallelism": "single box, one GPU",
+        "beta_mu": beta_mu, "beta_mu_source": "given" if args.beta_mu is not None else
+        "Jarzynski estimate from the pilot insertions (equilibrium operating point)",
+        "beta_mu_jarzynski": bmu_eq,
+        "skin": w.params["skin"], "proposal": "uniform", "parallelism": "single box, one GPU",
     }
     base = None if args.no_cpu_baseline else cpu_baseline(w, args.cpu_steps, "the 32,000-ion state")
     return out, config, base
@@ -211,7 +284,13 @@ def main():
     ap.add_argument("--steps", type=int, default=None,
                     help="timed exchange trials (lj32k, default 2000) or trials per box (batched, default 20)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed trials first (default 20 / 2)")
-    ap.add_argument("--beta-mu", type=float, default=-4.0)
+    ap.add_argument("--beta-mu", type=float, default=None,
+                    help="beta mu (default: lj32k, the Jarzynski estimate from the pilot; batched, -4)")
+    ap.add_argument("--pilot", type=int, default=1200, help="lj32k: pilot insertions for the network")
+    ap.add_argument("--train-steps", type=int, default=0, help="lj32k: Adam steps (0: --train-epochs)")
+    ap.add_argument("--train-epochs", type=int, default=30, help="lj32k: passes over the pilot data")
+    ap.add_argument("--candidates", type=int, default=64, help="lj32k: candidates of the learned proposal")
+    ap.add_argument("--learned-steps", type=int, default=None, help="lj32k: timed learned trials (default steps/2)")
     ap.add_argument("--timing-trials", type=int, default=None,
                     help="trials run after the timed region with HIP events on the step kernel (20 / 2)")
     ap.add_argument("--cpu-steps", type=int, default=12, help="oracle sample length (NEMD steps)")
@@ -236,6 +315,10 @@ def main():
         args.warmup = 2 if batched else 20
     if args.timing_trials is None:
         args.timing_trials = 2 if batched else 20
+    if args.learned_steps is None:
+        args.learned_steps = max(1, args.steps // 2)
+    if batched and args.beta_mu is None:
+        args.beta_mu = -4.0
 
     import torch
     from paper_2307_11447_amd import h4d

@@ -219,6 +219,9 @@ int32_t h4d_get_box_state(h4d_system *sys, int32_t box, int32_t cap, int32_t *n,
                           int32_t *n_salt, double *pos, double *vel, int32_t *type,
                           int32_t *mol, int64_t *tag);
 
+/* Chemical potential beta * mu_salt of the following trials (Eqs. 6, 8). */
+int32_t h4d_set_beta_mu(h4d_system *sys, double beta_mu);
+
 /* Set the next trial index of every box (default 0). */
 int32_t h4d_set_trial_index(h4d_system *sys, uint64_t trial);
 
@@ -270,6 +273,85 @@ int32_t h4d_autotune(h4d_system *sys, int32_t trials, int32_t *lanes_out, double
  * Allocates and frees its buffers; bytes must be a positive multiple of 16.
  */
 int32_t h4d_stream_copy(int64_t bytes, int32_t reps, double *ms);
+
+/*
+ * Learned insertion proposal (single-box handles).  A multiple-try form of
+ * the uniform pair insertion of Eq. (4), exact for any network: an
+ * insertion draws k uniform candidate pair sites (Philox counters
+ * (trial, 4, j, 0 / 1)), weighs each by exp(s), s the network's logit of the
+ * site's 64 features on the state before the trajectory (log weight
+ * min(s, logit_cap)), and flies the pair
+ * in at one chosen with probability proportional to its weight (uniform
+ * (trial, 5, 0, 0)); ln R of Eqs. (6) gains ln(W/k) - s(chosen).  A deletion
+ * weighs the removed pair's site and k - 1 fresh candidates on the state
+ * after its trajectory (pair removed) and ln R of Eq. (8) gains
+ * s(removed) - ln(W/k).  The factor is reported in h4d_trial.ln_proposal.
+ *
+ * Features of a site (31 per ion, then 2 for the pair), from the non-flying
+ * atoms within rc = max cutoff, each pair term scaled by beta, clipped to
+ * +-1e6 and summed in 64-bit fixed point (independent of atom order):
+ *   0.1 x Gaussian shell counts of atom types 0..3 (six shells of width
+ *   rc/6, centres (m + 1/2) rc/6, standard deviation rc/12, each term
+ *   tapered by (1 - r^2/rc^2)^2 so the features are continuous); asinh of beta
+ *   U_C, of beta |F_C|, of beta U_LJ at w = 0, of beta U_LJ and of beta
+ *   exp(-kappa_sr w_max) U_C at w = w_max (Eq. 11); nearest-atom and
+ *   nearest-counter-ion distances over rc (capped at 1); the pair's
+ *   separation over rc (capped at 1) and asinh(beta u) of its own energy.
+ *
+ * The network: 64 -> 128 -> 128 -> 128 -> 1, GELU (tanh form) on the
+ * hidden layers.  Parameters theta[41473] in the order W1[64][128], b1,
+ * W2[128][128], b2, W3[128][128], b3, w4[128], b4 (W[i][o] maps input i to
+ * output o).  Inference in the trial loop runs in BF16 on the matrix cores
+ * with FP32 accumulation; training runs in FP32.  A network handle owns its
+ * device memory; a system holding it (h4d_set_proposal) reads its
+ * parameters at every trial, so it must outlive that use.
+ */
+typedef struct h4d_mlp h4d_mlp;
+
+/* Network with Glorot-uniform weights from `seed`, zero biases. */
+int32_t h4d_mlp_create(uint64_t seed, void *hip_stream, h4d_mlp **out);
+int32_t h4d_mlp_destroy(h4d_mlp *net);
+/* theta: 41473 host floats (the optimiser state is reset). */
+int32_t h4d_mlp_set_weights(h4d_mlp *net, const float *theta);
+int32_t h4d_mlp_get_weights(h4d_mlp *net, float *theta);
+/* Logits of rows x 64 host features: bf16 = 1 the matrix-core inference
+ * path, 0 the FP32 training forward. */
+int32_t h4d_mlp_forward(h4d_mlp *net, int32_t rows, const float *features, int32_t bf16,
+                        float *logits);
+/* Mean-squared loss of the FP32 logits against targets and its gradient
+ * (grad[41473], host; may be NULL). */
+int32_t h4d_mlp_loss_grad(h4d_mlp *net, int32_t rows, const float *features,
+                          const float *targets, float *grad, float *loss);
+/* `steps` Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr,
+ * decoupled weight decay: theta -= lr * weight_decay * theta each step)
+ * on minibatches of `batch` rows drawn from seeded shuffles of the data;
+ * losses[steps] (host, may be NULL) receives each step's minibatch loss.
+ * Training runs on standardized features (per-column mean and standard
+ * deviation of the data); the affine map is folded into W1 and b1 before
+ * return, so the network still reads raw features.  Each call starts a
+ * fresh optimiser state.  Suggested target of a pilot insertion:
+ * clip(-beta dH, -20, 10). */
+int32_t h4d_mlp_train(h4d_mlp *net, int32_t rows, const float *features, const float *targets,
+                      int32_t steps, int32_t batch, float lr, float weight_decay, uint64_t seed,
+                      float *losses);
+
+/* Proposal of the following trials: k <= 0 the uniform proposal of Eq. (4);
+ * k >= 1 the multiple-try proposal with k candidates, weighted by
+ * exp(min(s, logit_cap)) with s the logit of `net` (NULL: equal weights,
+ * which with k = 1 is the uniform proposal again and records the features
+ * of every inserted or removed site).  The cap bounds how far a network's
+ * extrapolation errors can steer the choice; any cap keeps the method
+ * exact. */
+int32_t h4d_set_proposal(h4d_system *sys, const h4d_mlp *net, int32_t k, double logit_cap);
+/* Features of the last trial's inserted or removed pair site (64 floats). */
+int32_t h4d_last_site_features(h4d_system *sys, float *out);
+/* The last learned move's candidates: sites[6k], features[64k], logits[k]
+ * (host, any may be NULL); returns k (>= 0) or an error. */
+int32_t h4d_last_candidates(h4d_system *sys, int32_t cap, double *sites, float *features,
+                            float *logits);
+/* Test hook: features of n given sites (sites[6n]: cation xyz, anion xyz)
+ * on the current state (no flying atoms). */
+int32_t h4d_site_features(h4d_system *sys, int32_t n, const double *sites, float *features);
 
 /* Release every resource of the handle. */
 int32_t h4d_destroy(h4d_system *sys);

@@ -660,7 +660,9 @@ static int score_sites(const or_params *p, const or_state *s, const or_proposal 
         for (int j = 0; j < n; ++j) logw[j] = 0.0;
         return 0;
     }
-    return prop->fn(prop->ctx, n, feat, logw);
+    const int rc = prop->fn(prop->ctx, n, feat, logw);
+    for (int j = 0; j < n; ++j) logw[j] = fmin(logw[j], prop->cap);
+    return rc;
 }
 
 int or_trial_begin(const or_params *p, or_state *s, uint64_t trial, int force_move,

@@ -80,14 +80,15 @@ def loss_and_grad(theta, X, t):
     return loss, g
 
 
-def adam_step(theta, m, v, g, step, lr, b1=0.9, b2=0.999, eps=1e-8):
-    """One Adam update (Kingma & Ba 2015) with bias correction; step counts
-    from 1.  Returns the new (theta, m, v)."""
+def adam_step(theta, m, v, g, step, lr, b1=0.9, b2=0.999, eps=1e-8, wd=0.0):
+    """One Adam update (Kingma & Ba 2015) with bias correction and decoupled
+    weight decay wd (Loshchilov & Hutter 2019); step counts from 1.  Returns
+    the new (theta, m, v)."""
     m = b1 * m + (1.0 - b1) * g
     v = b2 * v + (1.0 - b2) * g * g
     mh = m / (1.0 - b1 ** step)
     vh = v / (1.0 - b2 ** step)
-    return theta - lr * mh / (np.sqrt(vh) + eps), m, v
+    return theta - lr * (mh / (np.sqrt(vh) + eps) + wd * theta), m, v
 
 
 def target_of(dH, kT):
@@ -105,3 +106,34 @@ def random_theta(seed: int, scale: float = 1.0):
         parts.append(rng.uniform(-a, a, size=i * o))
         parts.append(np.zeros(o))
     return np.concatenate(parts)
+
+
+def standardization(X):
+    """Per-column mean and standard deviation of the data (columns with
+    deviation below 1e-6 keep a scale of 1)."""
+    X = np.asarray(X, dtype=np.float64)
+    mean = X.mean(axis=0)
+    sd = X.std(axis=0)
+    sd[~(sd > 1e-6)] = 1.0
+    return mean, sd
+
+
+def to_standard(theta, mean, sd):
+    """The same network in standardized input coordinates x' = (x - mean) / sd:
+    W1' = sd W1 (row-wise), b1' = b1 + mean W1."""
+    th = np.array(theta, dtype=np.float64)
+    W1 = th[:64 * 128].reshape(64, 128)
+    b1 = th[64 * 128:64 * 128 + 128]
+    b1 += mean @ W1
+    W1 *= sd[:, None]
+    return th
+
+
+def from_standard(theta, mean, sd):
+    """Inverse of to_standard: W1 = W1' / sd, b1 = b1' - (mean / sd) W1'."""
+    th = np.array(theta, dtype=np.float64)
+    W1 = th[:64 * 128].reshape(64, 128)
+    b1 = th[64 * 128:64 * 128 + 128]
+    b1 -= (mean / sd) @ W1
+    W1 /= sd[:, None]
+    return th

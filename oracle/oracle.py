@@ -64,7 +64,7 @@ LOGIT_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.POINTER(C.c_double), C.PO
 
 
 class Proposal(C.Structure):
-    _fields_ = [("k", C.c_int32), ("fn", LOGIT_FN), ("ctx", C.c_void_p)]
+    _fields_ = [("k", C.c_int32), ("fn", LOGIT_FN), ("ctx", C.c_void_p), ("cap", C.c_double)]
 
 
 class Energy(C.Structure):
@@ -203,12 +203,13 @@ class OracleSystem:
             raise RuntimeError(f"or_site_features failed: {rc}")
         return out
 
-    def trial_learned(self, t: int, k: int, logits=None, force_move: int = 0):
+    def trial_learned(self, t: int, k: int, logits=None, force_move: int = 0, cap: float = 10.0):
         """Trial with the learned proposal.  logits(features n x 64) -> n
-        logits, or None for equal weights.  Returns (record, features of the
-        inserted / removed site)."""
+        logits, or None for equal weights; log weights are min(logit, cap).
+        Returns (record, features of the inserted / removed site)."""
         prop = Proposal()
         prop.k = k
+        prop.cap = cap
         keep = None
         if logits is not None:
             def cb(ctx, n, feat, out):

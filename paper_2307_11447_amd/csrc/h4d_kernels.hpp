@@ -52,6 +52,7 @@ struct Ctl {
     double Ulj, Uc, vir;
     double Wf[2];
     double Ufly0, Ufly1;   // U_fly(w_max) at the start / end state (FP64)
+    double lnq;            // ln of the learned proposal's multiple-try factor (0: uniform)
 };
 
 // Trial record, same layout as h4d_trial of the C ABI.
@@ -196,6 +197,7 @@ __global__ __launch_bounds__(kBlock) void k_propose(KArgs a, int force_move) {
         c->err = 0; c->retry = 0; c->accepted = 0;
         c->Wf[0] = c->Wf[1] = 0.0; c->Ufly0 = c->Ufly1 = 0.0;
         c->U0 = c->K0 = c->U1 = c->K1 = 0.0;
+        c->lnq = 0.0;
         c->ic = c->ia = c->wic = c->wia = -1;
         c->nfast[0] = c->nfast[1] = c->nfast[2] = 0;
         c->max_fast = 0;
@@ -1077,7 +1079,7 @@ __global__ void k_metropolis(KArgs a) {
     r->n_salt_after = c->nsalt;
     r->n_steps = c->nf;
     r->ln_u = log(c->u[7]);
-    r->ln_proposal = 0.0;
+    r->ln_proposal = c->lnq;
     r->flags = 0;
     r->accepted = 0;
     c->accepted = 0;
@@ -1098,7 +1100,7 @@ __global__ void k_metropolis(KArgs a) {
     const double dH = H1 - H0;
     const int n_small = move > 0 ? c->nsalt : c->nsalt - 1;
     const double I = 2.0 * log(B.volume / (a.G.lambda3 * (double)(n_small + 1)));
-    const double lnR = move > 0 ? -a.G.beta * dH + a.G.beta_mu + I : -a.G.beta * dH - a.G.beta_mu - I;
+    const double lnR = (move > 0 ? -a.G.beta * dH + a.G.beta_mu + I : -a.G.beta * dH - a.G.beta_mu - I) + c->lnq;
     r->dH = dH; r->dU = c->U1 - c->U0; r->dK = c->K1 - c->K0;
     r->H0 = H0; r->H1 = H1;
     r->W_prot = c->Wf[0] + c->Wf[1];

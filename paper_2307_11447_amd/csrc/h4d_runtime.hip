@@ -18,7 +18,8 @@
 #include <vector>
 
 #include "h4d.h"
-#include "h4d_kernels.hpp"
+#include "h4d_learned.hpp"
+#include <random>
 
 using namespace h4d;
 
@@ -78,6 +79,8 @@ struct h4d_system {
         double N_sum = 0.0, N2_sum = 0.0;
     };
     std::vector<Stats> stats;
+    // learned proposal (single box): k candidates per move, 0 = uniform
+    LearnArgs la{};
 
     template <class T>
     int alloc(T **ptr, size_t count) {
@@ -428,6 +431,21 @@ int grow_lists(h4d_system *s, unsigned err, int max_nbr, int max_cell) {
     return H4D_OK;
 }
 
+// Candidates, features, logits and the multiple-try step of the learned
+// proposal: phase 0 before an insertion's trajectory (working buffer 0, cell
+// buffer 0), phase 1 after a deletion's (final buffer, last cell buffer).
+void enqueue_learned(h4d_system *s, hipStream_t st, int phase, int b, int cb) {
+    KArgs &a = s->a;
+    const LearnArgs &l = s->la;
+    const int k = l.k;
+    hipLaunchKernelGGL(k_cand_sites, dim3(blocks_for(k)), dim3(kBlock), 0, st, a, l, phase);
+    hipLaunchKernelGGL(k_site_features, dim3((2 * k * kWave + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a, l, phase,
+                       b, cb);
+    if (l.use_net) hipLaunchKernelGGL(k_mlp_infer_move, dim3((k + 63) / 64), dim3(256), 0, st, a, l, phase);
+    else hipLaunchKernelGGL(k_zero_logits, dim3(blocks_for(k)), dim3(kBlock), 0, st, a, l, phase);
+    hipLaunchKernelGGL(k_mtm_select, dim3(1), dim3(1), 0, st, a, l, phase);
+}
+
 // Enqueue every kernel of one round (each box's current trial) on st.  The
 // round's shape is fixed by the rebuild interval and the largest N_f; the
 // kernels read everything else from the control blocks.  With timing, HIP
@@ -438,6 +456,10 @@ int enqueue_round(h4d_system *s, int move, hipStream_t st, int nf, int M, bool t
     int rc;
     hipLaunchKernelGGL(k_propose, dim3(s->nbox), dim3(kBlock), 0, st, a, move);
     if ((rc = sort_in(s, st))) return rc;
+    if (s->la.k > 0) {   // learned insertion: score k candidates, move the ghosts, sort again
+        enqueue_learned(s, st, 0, 0, 0);
+        if ((rc = sort_in(s, st))) return rc;
+    }
     hipLaunchKernelGGL(k_energy, dim3(a.step_blocks), dim3(kBlock), 0, st, a, 0, -1, 0.0, 0);
     hipLaunchKernelGGL(k_energy_final, dim3(s->nbox), dim3(kBlock), 0, st, a, 0);
     int b = 0;
@@ -455,6 +477,7 @@ int enqueue_round(h4d_system *s, int move, hipStream_t st, int nf, int M, bool t
     if ((rc = rebuild_final(s, st))) return rc;
     hipLaunchKernelGGL(k_energy, dim3(a.step_blocks), dim3(kBlock), 0, st, a, 1, -1, 0.0, -1);
     hipLaunchKernelGGL(k_energy_final, dim3(s->nbox), dim3(kBlock), 0, st, a, 1);
+    if (s->la.k > 0) enqueue_learned(s, st, 1, -1, s->cl);   // learned deletion: reverse weights
     hipLaunchKernelGGL(k_metropolis, dim3(blocks_for(s->nbox)), dim3(kBlock), 0, st, a);
     hipLaunchKernelGGL(k_commit, dim3(G1), dim3(kBlock), 0, st, a);
     hipLaunchKernelGGL(k_compact1, dim3(G1), dim3(kBlock), 0, st, a);
@@ -483,7 +506,7 @@ int launch_round(h4d_system *s, int move) {
     const int tm = s->timing ? 1 : 0;
     if (s->graphs_ok[tm]) {
         if (!s->cap_stream) HIPC(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
-        const auto key = std::make_tuple(M, nf, move, tm, a.lanes);
+        const auto key = std::make_tuple(M, nf, move, tm, a.lanes * 65536 + s->la.k);
         auto it = s->graphs.find(key);
         if (it == s->graphs.end()) {
             hipGraph_t graph = nullptr;
@@ -981,6 +1004,15 @@ int32_t h4d_run_batch(h4d_system *s, int32_t trials_per_box, int32_t move, h4d_t
     return run_batch(s, trials_per_box, move, out);
 }
 
+int32_t h4d_set_beta_mu(h4d_system *s, double beta_mu) {
+    if (!s) return fail(H4D_EINVAL, "null handle");
+    if (!std::isfinite(beta_mu)) return fail(H4D_EINVAL, "beta_mu must be finite");
+    s->p.beta_mu = beta_mu;
+    s->a.G.beta_mu = beta_mu;
+    s->drop_graphs();       // the captured launches hold the old value
+    return H4D_OK;
+}
+
 int32_t h4d_set_trial_index(h4d_system *s, uint64_t trial) {
     if (!s) return fail(H4D_EINVAL, "null handle");
     int rc = read_ctl(s);
@@ -1111,6 +1143,388 @@ int32_t h4d_autotune(h4d_system *s, int32_t trials, int32_t *lanes_out, double *
     if (rc) return rc;
     if (lanes_out) *lanes_out = best;
     if (ns_per_atom_step) *ns_per_atom_step = best_t * 1e9;
+    return H4D_OK;
+}
+
+}  // extern "C"
+
+// ==========================================================================
+// Learned proposal: the network handle and its training.
+// ==========================================================================
+struct h4d_mlp {
+    hipStream_t stream = nullptr;
+    float *theta = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
+    bf16x4 *wfrag = nullptr;
+    long long adam_t = 0;
+    int rows = 0;                          // capacity of the activation buffers
+    float *X = nullptr, *T = nullptr, *Z1 = nullptr, *A1 = nullptr, *Z2 = nullptr, *A2 = nullptr, *Z3 = nullptr,
+          *A3 = nullptr, *Sz = nullptr, *S = nullptr, *dS = nullptr, *dZ3 = nullptr, *dZ2 = nullptr,
+          *dZ1 = nullptr, *loss = nullptr;
+    std::vector<void *> act;
+    ~h4d_mlp() {
+        for (void *q : act) (void)hipFree(q);
+        for (void *q : {(void *)theta, (void *)m, (void *)v, (void *)g, (void *)wfrag}) if (q) (void)hipFree(q);
+    }
+};
+
+namespace {
+
+int mlp_rows(h4d_mlp *n, int rows) {
+    if (rows <= n->rows) return H4D_OK;
+    for (void *q : n->act) (void)hipFree(q);
+    n->act.clear();
+    auto get = [&](float **p, size_t cnt) -> int {
+        void *q = nullptr;
+        if (hipMalloc(&q, std::max<size_t>(cnt, 1) * sizeof(float)) != hipSuccess)
+            return fail(H4D_ENOMEM, "hipMalloc of network activations failed");
+        n->act.push_back(q);
+        *p = static_cast<float *>(q);
+        return H4D_OK;
+    };
+    const size_t R = (size_t)rows;
+    int rc;
+    if ((rc = get(&n->X, R * kFeat)) || (rc = get(&n->T, R)) || (rc = get(&n->Z1, R * kHid)) ||
+        (rc = get(&n->A1, R * kHid)) || (rc = get(&n->Z2, R * kHid)) || (rc = get(&n->A2, R * kHid)) ||
+        (rc = get(&n->Z3, R * kHid)) || (rc = get(&n->A3, R * kHid)) || (rc = get(&n->Sz, R)) ||
+        (rc = get(&n->S, R)) || (rc = get(&n->dS, R)) || (rc = get(&n->dZ3, R * kHid)) ||
+        (rc = get(&n->dZ2, R * kHid)) || (rc = get(&n->dZ1, R * kHid)) || (rc = get(&n->loss, 1)))
+        return rc;
+    n->rows = rows;
+    return H4D_OK;
+}
+
+int mlp_pack(h4d_mlp *n) {
+    const int nf = kFragL1 + 2 * kFragL2;
+    hipLaunchKernelGGL(k_mlp_pack, dim3(blocks_for(nf)), dim3(kBlock), 0, n->stream, n->theta, n->wfrag);
+    HIPC(hipGetLastError());
+    return H4D_OK;
+}
+
+// FP32 forward of rows X[0..rows) (logits in S)
+void mlp_fwd32(h4d_mlp *n, int rows) {
+    const hipStream_t st = n->stream;
+    const float *th = n->theta;
+    hipLaunchKernelGGL(k_dense_fwd, dim3(blocks_for(rows * kHid)), dim3(kBlock), 0, st, n->X, th + kOffW1,
+                       th + kOffB1, n->Z1, n->A1, rows, kFeat, kHid, 1);
+    hipLaunchKernelGGL(k_dense_fwd, dim3(blocks_for(rows * kHid)), dim3(kBlock), 0, st, n->A1, th + kOffW2,
+                       th + kOffB2, n->Z2, n->A2, rows, kHid, kHid, 1);
+    hipLaunchKernelGGL(k_dense_fwd, dim3(blocks_for(rows * kHid)), dim3(kBlock), 0, st, n->A2, th + kOffW3,
+                       th + kOffB3, n->Z3, n->A3, rows, kHid, kHid, 1);
+    hipLaunchKernelGGL(k_dense_fwd, dim3(blocks_for(rows)), dim3(kBlock), 0, st, n->A3, th + kOffW4, th + kOffB4,
+                       n->Sz, n->S, rows, kHid, 1, 0);
+}
+
+// loss of S against T and the gradient of the mean loss into g
+void mlp_bwd32(h4d_mlp *n, int rows) {
+    const hipStream_t st = n->stream;
+    const float *th = n->theta;
+    float *g = n->g;
+    hipLaunchKernelGGL(k_mse, dim3(1), dim3(256), 0, st, n->S, n->T, rows, n->dS, n->loss);
+    hipLaunchKernelGGL(k_wgrad, dim3(blocks_for((kHid + 1) * 1)), dim3(kBlock), 0, st, n->A3, n->dS, rows, kHid, 1,
+                       g + kOffW4, g + kOffB4);
+    hipLaunchKernelGGL(k_dgrad, dim3(blocks_for(rows * kHid)), dim3(kBlock), 0, st, n->dS, th + kOffW4, n->Z3, rows,
+                       kHid, 1, n->dZ3);
+    hipLaunchKernelGGL(k_wgrad, dim3(blocks_for((kHid + 1) * kHid)), dim3(kBlock), 0, st, n->A2, n->dZ3, rows, kHid,
+                       kHid, g + kOffW3, g + kOffB3);
+    hipLaunchKernelGGL(k_dgrad, dim3(blocks_for(rows * kHid)), dim3(kBlock), 0, st, n->dZ3, th + kOffW3, n->Z2, rows,
+                       kHid, kHid, n->dZ2);
+    hipLaunchKernelGGL(k_wgrad, dim3(blocks_for((kHid + 1) * kHid)), dim3(kBlock), 0, st, n->A1, n->dZ2, rows, kHid,
+                       kHid, g + kOffW2, g + kOffB2);
+    hipLaunchKernelGGL(k_dgrad, dim3(blocks_for(rows * kHid)), dim3(kBlock), 0, st, n->dZ2, th + kOffW2, n->Z1, rows,
+                       kHid, kHid, n->dZ1);
+    hipLaunchKernelGGL(k_wgrad, dim3(blocks_for((kFeat + 1) * kHid)), dim3(kBlock), 0, st, n->X, n->dZ1, rows, kFeat,
+                       kHid, g + kOffW1, g + kOffB1);
+}
+
+uint64_t splitmix64(uint64_t &x) {
+    uint64_t z = (x += 0x9E3779B97F4A7C15ULL);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t h4d_mlp_create(uint64_t seed, void *hip_stream, h4d_mlp **out) {
+    g_err.clear();
+    if (!out) return fail(H4D_EINVAL, "null argument");
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(H4D_ENODEV, "no HIP device");
+    auto *n = new h4d_mlp();
+    n->stream = static_cast<hipStream_t>(hip_stream);
+    const size_t P = kParams;
+    if (hipMalloc((void **)&n->theta, P * 4) != hipSuccess || hipMalloc((void **)&n->m, P * 4) != hipSuccess ||
+        hipMalloc((void **)&n->v, P * 4) != hipSuccess || hipMalloc((void **)&n->g, P * 4) != hipSuccess ||
+        hipMalloc((void **)&n->wfrag, sizeof(bf16x4) * (kFragL1 + 2 * kFragL2)) != hipSuccess) {
+        delete n;
+        return fail(H4D_ENOMEM, "hipMalloc of network parameters failed");
+    }
+    // Glorot-uniform weights, zero biases, from a seeded splitmix64 stream
+    std::vector<float> th(P, 0.0f);
+    uint64_t x = seed;
+    const int fan[4][3] = {{kOffW1, kFeat, kHid}, {kOffW2, kHid, kHid}, {kOffW3, kHid, kHid}, {kOffW4, kHid, 1}};
+    for (const auto &f : fan) {
+        const double lim = std::sqrt(6.0 / (f[1] + f[2]));
+        for (int q = 0; q < f[1] * f[2]; ++q) {
+            const double u = ((double)(splitmix64(x) >> 11) + 0.5) * 0x1p-53;
+            th[f[0] + q] = (float)(lim * (2.0 * u - 1.0));
+        }
+    }
+    if (hipMemcpy(n->theta, th.data(), P * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(n->m, 0, P * 4) != hipSuccess || hipMemset(n->v, 0, P * 4) != hipSuccess) {
+        delete n;
+        return fail(H4D_EHIP, "network upload failed");
+    }
+    int rc = mlp_pack(n);
+    if (rc) { delete n; return rc; }
+    *out = n;
+    return H4D_OK;
+}
+
+int32_t h4d_mlp_destroy(h4d_mlp *n) {
+    if (!n) return H4D_OK;
+    if (n->stream) (void)hipStreamSynchronize(n->stream);
+    else (void)hipDeviceSynchronize();
+    delete n;
+    return H4D_OK;
+}
+
+int32_t h4d_mlp_set_weights(h4d_mlp *n, const float *theta) {
+    if (!n || !theta) return fail(H4D_EINVAL, "null argument");
+    HIPC(hipMemcpyAsync(n->theta, theta, sizeof(float) * kParams, hipMemcpyHostToDevice, n->stream));
+    HIPC(hipMemsetAsync(n->m, 0, sizeof(float) * kParams, n->stream));
+    HIPC(hipMemsetAsync(n->v, 0, sizeof(float) * kParams, n->stream));
+    n->adam_t = 0;
+    int rc = mlp_pack(n);
+    if (rc) return rc;
+    HIPC(hipStreamSynchronize(n->stream));
+    return H4D_OK;
+}
+
+int32_t h4d_mlp_get_weights(h4d_mlp *n, float *theta) {
+    if (!n || !theta) return fail(H4D_EINVAL, "null argument");
+    HIPC(hipMemcpyAsync(theta, n->theta, sizeof(float) * kParams, hipMemcpyDeviceToHost, n->stream));
+    HIPC(hipStreamSynchronize(n->stream));
+    return H4D_OK;
+}
+
+int32_t h4d_mlp_forward(h4d_mlp *n, int32_t rows, const float *features, int32_t bf16, float *logits) {
+    if (!n || rows < 0 || (rows && (!features || !logits))) return fail(H4D_EINVAL, "null argument or negative size");
+    if (!rows) return H4D_OK;
+    int rc = mlp_rows(n, rows);
+    if (rc) return rc;
+    HIPC(hipMemcpyAsync(n->X, features, sizeof(float) * rows * kFeat, hipMemcpyHostToDevice, n->stream));
+    if (bf16) hipLaunchKernelGGL(k_mlp_infer, dim3((rows + 63) / 64), dim3(256), 0, n->stream, n->X, rows, n->theta,
+                                 n->wfrag, n->S);
+    else mlp_fwd32(n, rows);
+    HIPC(hipGetLastError());
+    HIPC(hipMemcpyAsync(logits, n->S, sizeof(float) * rows, hipMemcpyDeviceToHost, n->stream));
+    HIPC(hipStreamSynchronize(n->stream));
+    return H4D_OK;
+}
+
+int32_t h4d_mlp_loss_grad(h4d_mlp *n, int32_t rows, const float *features, const float *targets, float *grad,
+                          float *loss) {
+    if (!n || rows < 1 || !features || !targets) return fail(H4D_EINVAL, "null argument or rows < 1");
+    int rc = mlp_rows(n, rows);
+    if (rc) return rc;
+    HIPC(hipMemcpyAsync(n->X, features, sizeof(float) * rows * kFeat, hipMemcpyHostToDevice, n->stream));
+    HIPC(hipMemcpyAsync(n->T, targets, sizeof(float) * rows, hipMemcpyHostToDevice, n->stream));
+    mlp_fwd32(n, rows);
+    mlp_bwd32(n, rows);
+    HIPC(hipGetLastError());
+    if (grad) HIPC(hipMemcpyAsync(grad, n->g, sizeof(float) * kParams, hipMemcpyDeviceToHost, n->stream));
+    if (loss) HIPC(hipMemcpyAsync(loss, n->loss, sizeof(float), hipMemcpyDeviceToHost, n->stream));
+    HIPC(hipStreamSynchronize(n->stream));
+    return H4D_OK;
+}
+
+int32_t h4d_mlp_train(h4d_mlp *n, int32_t rows, const float *features, const float *targets, int32_t steps,
+                      int32_t batch, float lr, float weight_decay, uint64_t seed, float *losses) {
+    if (!n || rows < 1 || !features || !targets || steps < 0 || batch < 1 || !(lr > 0.0f) || !(weight_decay >= 0.0f))
+        return fail(H4D_EINVAL, "bad training arguments");
+    batch = std::min(batch, rows);
+    int rc = mlp_rows(n, batch);
+    if (rc) return rc;
+    float *data = nullptr, *tg = nullptr, *lossv = nullptr;
+    int *idx = nullptr;
+    auto cleanup = [&]() {
+        if (data) (void)hipFree(data);
+        if (tg) (void)hipFree(tg);
+        if (lossv) (void)hipFree(lossv);
+        if (idx) (void)hipFree(idx);
+    };
+    if (hipMalloc((void **)&data, sizeof(float) * rows * kFeat) != hipSuccess ||
+        hipMalloc((void **)&tg, sizeof(float) * rows) != hipSuccess ||
+        hipMalloc((void **)&lossv, sizeof(float) * std::max(1, steps)) != hipSuccess ||
+        hipMalloc((void **)&idx, sizeof(int) * (size_t)std::max(1, steps) * batch) != hipSuccess) {
+        cleanup();
+        return fail(H4D_ENOMEM, "hipMalloc of training data failed");
+    }
+    // the network trains on standardized features (mean 0, variance 1 per
+    // column over the data); the affine map is folded into the first layer
+    // afterwards, so the stored network reads raw features
+    std::vector<double> mean(kFeat, 0.0), sdev(kFeat, 0.0);
+    for (int r = 0; r < rows; ++r)
+        for (int q = 0; q < kFeat; ++q) mean[q] += features[(size_t)r * kFeat + q];
+    for (int q = 0; q < kFeat; ++q) mean[q] /= rows;
+    for (int r = 0; r < rows; ++r)
+        for (int q = 0; q < kFeat; ++q) {
+            const double d = features[(size_t)r * kFeat + q] - mean[q];
+            sdev[q] += d * d;
+        }
+    for (int q = 0; q < kFeat; ++q) {
+        sdev[q] = std::sqrt(sdev[q] / rows);
+        if (!(sdev[q] > 1e-6)) sdev[q] = 1.0;
+    }
+    std::vector<float> stdX((size_t)rows * kFeat);
+    for (int r = 0; r < rows; ++r)
+        for (int q = 0; q < kFeat; ++q)
+            stdX[(size_t)r * kFeat + q] = (float)((features[(size_t)r * kFeat + q] - mean[q]) / sdev[q]);
+    std::vector<float> th(kParams);
+    if (hipMemcpy(th.data(), n->theta, sizeof(float) * kParams, hipMemcpyDeviceToHost) != hipSuccess) {
+        cleanup();
+        return fail(H4D_EHIP, "network download failed");
+    }
+    // the current network in standardized coordinates: W1' = sd W1, b1' = b1 + mean W1
+    for (int o = 0; o < kHid; ++o) {
+        double b = th[kOffB1 + o];
+        for (int q = 0; q < kFeat; ++q) b += mean[q] * th[kOffW1 + q * kHid + o];
+        th[kOffB1 + o] = (float)b;
+    }
+    for (int q = 0; q < kFeat; ++q)
+        for (int o = 0; o < kHid; ++o) th[kOffW1 + q * kHid + o] = (float)(th[kOffW1 + q * kHid + o] * sdev[q]);
+    if (hipMemcpy(n->theta, th.data(), sizeof(float) * kParams, hipMemcpyHostToDevice) != hipSuccess) {
+        cleanup();
+        return fail(H4D_EHIP, "network upload failed");
+    }
+    features = stdX.data();
+    // minibatches: consecutive slices of seeded shuffles of the rows
+    std::vector<int> order(rows), all((size_t)std::max(1, steps) * batch);
+    for (int r = 0; r < rows; ++r) order[r] = r;
+    std::mt19937_64 gen(seed);
+    int pos = rows;
+    for (int q = 0; q < steps; ++q)
+        for (int b = 0; b < batch; ++b) {
+            if (pos == rows) { std::shuffle(order.begin(), order.end(), gen); pos = 0; }
+            all[(size_t)q * batch + b] = order[pos++];
+        }
+    const hipStream_t st = n->stream;
+    bool ok = hipMemcpyAsync(data, features, sizeof(float) * rows * kFeat, hipMemcpyHostToDevice, st) == hipSuccess &&
+              hipMemcpyAsync(tg, targets, sizeof(float) * rows, hipMemcpyHostToDevice, st) == hipSuccess &&
+              hipMemcpyAsync(idx, all.data(), sizeof(int) * all.size(), hipMemcpyHostToDevice, st) == hipSuccess;
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    for (int q = 0; ok && q < steps; ++q) {
+        hipLaunchKernelGGL(k_gather_rows, dim3(blocks_for(batch * kFeat)), dim3(kBlock), 0, st, data, tg,
+                           idx + (size_t)q * batch, batch, n->X, n->T);
+        mlp_fwd32(n, batch);
+        mlp_bwd32(n, batch);
+        ok = hipMemcpyAsync(lossv + q, n->loss, sizeof(float), hipMemcpyDeviceToDevice, st) == hipSuccess;
+        n->adam_t += 1;
+        const float c1 = (float)(1.0 / (1.0 - std::pow(0.9, (double)n->adam_t)));
+        const float c2 = (float)(1.0 / (1.0 - std::pow(0.999, (double)n->adam_t)));
+        hipLaunchKernelGGL(k_adam, dim3(blocks_for(kParams)), dim3(kBlock), 0, st, n->theta, n->m, n->v, n->g,
+                           kParams, lr, b1, b2, eps, c1, c2, weight_decay);
+    }
+    ok = ok && hipGetLastError() == hipSuccess;
+    if (ok && losses && steps)
+        ok = hipMemcpyAsync(losses, lossv, sizeof(float) * steps, hipMemcpyDeviceToHost, st) == hipSuccess;
+    ok = ok && hipStreamSynchronize(st) == hipSuccess;
+    cleanup();
+    if (!ok) return fail(H4D_EHIP, "network training failed");
+    // back to raw features: W1 = W1' / sd, b1 = b1' - (mean / sd) W1'
+    if (hipMemcpy(th.data(), n->theta, sizeof(float) * kParams, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(H4D_EHIP, "network download failed");
+    for (int o = 0; o < kHid; ++o) {
+        double b = th[kOffB1 + o];
+        for (int q = 0; q < kFeat; ++q) b -= mean[q] / sdev[q] * th[kOffW1 + q * kHid + o];
+        th[kOffB1 + o] = (float)b;
+    }
+    for (int q = 0; q < kFeat; ++q)
+        for (int o = 0; o < kHid; ++o) th[kOffW1 + q * kHid + o] = (float)(th[kOffW1 + q * kHid + o] / sdev[q]);
+    if (hipMemcpy(n->theta, th.data(), sizeof(float) * kParams, hipMemcpyHostToDevice) != hipSuccess)
+        return fail(H4D_EHIP, "network upload failed");
+    // Adam's moments belong to the standardized coordinates: start afresh
+    if (hipMemset(n->m, 0, sizeof(float) * kParams) != hipSuccess ||
+        hipMemset(n->v, 0, sizeof(float) * kParams) != hipSuccess)
+        return fail(H4D_EHIP, "optimiser reset failed");
+    n->adam_t = 0;
+    return mlp_pack(n);
+}
+
+int32_t h4d_set_proposal(h4d_system *s, const h4d_mlp *net, int32_t k, double logit_cap) {
+    if (!s) return fail(H4D_EINVAL, "null handle");
+    if (!(logit_cap == logit_cap)) return fail(H4D_EINVAL, "logit_cap is NaN");
+    if (k > 65536) return fail(H4D_EINVAL, "at most 65536 candidates");
+    if (k > 0 && s->nbox != 1) return fail(H4D_EINVAL, "the learned proposal serves single-box systems");
+    s->drop_graphs();
+    LearnArgs &l = s->la;
+    for (void *q : {(void *)l.sites, (void *)l.feat, (void *)l.logit}) if (q) s->release(q);
+    l.sites = nullptr; l.feat = nullptr; l.logit = nullptr;
+    l.k = 0;
+    l.use_net = 0;
+    if (k <= 0) return H4D_OK;
+    int rc;
+    if ((rc = s->alloc(&l.sites, (size_t)6 * k)) || (rc = s->alloc(&l.feat, (size_t)kFeat * k)) ||
+        (rc = s->alloc(&l.logit, (size_t)k)))
+        return rc;
+    if (!l.last_feat) {
+        if ((rc = s->alloc(&l.last_feat, kFeat))) return rc;
+        HIPC(hipMemset(l.last_feat, 0, sizeof(float) * kFeat));
+    }
+    l.k = k;
+    l.cap = logit_cap;
+    l.use_net = net != nullptr;
+    l.theta = net ? net->theta : nullptr;
+    l.wfrag = net ? net->wfrag : nullptr;
+    return H4D_OK;
+}
+
+int32_t h4d_last_site_features(h4d_system *s, float *out) {
+    if (!s || !out) return fail(H4D_EINVAL, "null argument");
+    if (!s->la.last_feat) return fail(H4D_EINVAL, "no learned-proposal trial has run");
+    HIPC(hipMemcpyAsync(out, s->la.last_feat, sizeof(float) * kFeat, hipMemcpyDeviceToHost, s->stream));
+    HIPC(hipStreamSynchronize(s->stream));
+    return H4D_OK;
+}
+
+int32_t h4d_last_candidates(h4d_system *s, int32_t cap, double *sites, float *features, float *logits) {
+    if (!s) return fail(H4D_EINVAL, "null handle");
+    const int k = s->la.k;
+    if (k <= 0) return fail(H4D_EINVAL, "the uniform proposal has no candidates");
+    if (cap < k) return fail(H4D_EINVAL, "cap smaller than the number of candidates");
+    if (sites) HIPC(hipMemcpyAsync(sites, s->la.sites, sizeof(double) * 6 * k, hipMemcpyDeviceToHost, s->stream));
+    if (features) HIPC(hipMemcpyAsync(features, s->la.feat, sizeof(float) * kFeat * k, hipMemcpyDeviceToHost, s->stream));
+    if (logits) HIPC(hipMemcpyAsync(logits, s->la.logit, sizeof(float) * k, hipMemcpyDeviceToHost, s->stream));
+    HIPC(hipStreamSynchronize(s->stream));
+    return k;
+}
+
+int32_t h4d_site_features(h4d_system *s, int32_t n, const double *sites, float *features) {
+    if (!s || n < 1 || !sites || !features) return fail(H4D_EINVAL, "null argument or n < 1");
+    if (s->nbox != 1) return fail(H4D_EINVAL, "site features serve single-box systems");
+    int rc = h4d_build_neighbors(s);
+    if (rc) return rc;
+    LearnArgs l = s->la;
+    double *sd = nullptr;
+    float *fd = nullptr;
+    if ((rc = s->alloc(&sd, (size_t)6 * n)) || (rc = s->alloc(&fd, (size_t)kFeat * n))) return rc;
+    l.k = n;
+    l.sites = sd;
+    l.feat = fd;
+    HIPC(hipMemcpyAsync(sd, sites, sizeof(double) * 6 * n, hipMemcpyHostToDevice, s->stream));
+    // the current state is an N-state for this hook: evaluate as the
+    // insertion phase does (a forced move flag makes the kernel run)
+    hipLaunchKernelGGL(k_site_features_hook, dim3((2 * n * kWave + kBlock - 1) / kBlock), dim3(kBlock), 0, s->stream,
+                       s->a, l);
+    HIPC(hipGetLastError());
+    HIPC(hipMemcpyAsync(features, fd, sizeof(float) * kFeat * n, hipMemcpyDeviceToHost, s->stream));
+    HIPC(hipStreamSynchronize(s->stream));
+    s->release(sd);
+    s->release(fd);
     return H4D_OK;
 }
 

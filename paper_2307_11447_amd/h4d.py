@@ -127,10 +127,27 @@ def lib() -> C.CDLL:
                                         C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
         L.h4d_box_observables.argtypes = [vp, C.c_int32, C.POINTER(Observables)]
         L.h4d_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double)]
+        fp, dp = C.POINTER(C.c_float), C.POINTER(C.c_double)
+        L.h4d_mlp_create.argtypes = [C.c_uint64, vp, C.POINTER(vp)]
+        L.h4d_mlp_destroy.argtypes = [vp]
+        L.h4d_mlp_set_weights.argtypes = [vp, fp]
+        L.h4d_mlp_get_weights.argtypes = [vp, fp]
+        L.h4d_mlp_forward.argtypes = [vp, C.c_int32, fp, C.c_int32, fp]
+        L.h4d_mlp_loss_grad.argtypes = [vp, C.c_int32, fp, fp, fp, fp]
+        L.h4d_mlp_train.argtypes = [vp, C.c_int32, fp, fp, C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_uint64,
+                                    fp]
+        L.h4d_set_proposal.argtypes = [vp, vp, C.c_int32, C.c_double]
+        L.h4d_last_site_features.argtypes = [vp, fp]
+        L.h4d_last_candidates.argtypes = [vp, C.c_int32, dp, fp, fp]
+        L.h4d_site_features.argtypes = [vp, C.c_int32, dp, fp]
+        L.h4d_set_beta_mu.argtypes = [vp, C.c_double]
         for name in ("h4d_stream_copy", "h4d_set_timing", "h4d_get_timing", "h4d_init_system", "h4d_build_neighbors",
                      "h4d_run_nemd_trial", "h4d_run_trials", "h4d_sample_observables", "h4d_get_state",
                      "h4d_set_trial_index", "h4d_forces_at", "h4d_destroy", "h4d_init_batch", "h4d_num_boxes",
-                     "h4d_run_batch", "h4d_get_box_state", "h4d_box_observables", "h4d_autotune"):
+                     "h4d_run_batch", "h4d_get_box_state", "h4d_box_observables", "h4d_autotune",
+                     "h4d_mlp_create", "h4d_mlp_destroy", "h4d_mlp_set_weights", "h4d_mlp_get_weights",
+                     "h4d_mlp_forward", "h4d_mlp_loss_grad", "h4d_mlp_train", "h4d_set_proposal",
+                     "h4d_last_site_features", "h4d_last_candidates", "h4d_site_features", "h4d_set_beta_mu"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -186,6 +203,66 @@ def stream_copy(nbytes: int, reps: int = 20) -> float:
     return ms.value
 
 
+N_PARAMS = 41473
+
+
+def _fp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+class Mlp:
+    """The learned proposal's network on the GPU (64 -> 3 x 128 GELU -> 1)."""
+
+    def __init__(self, seed: int = 0, stream=None):
+        self._h = None
+        h = C.c_void_p()
+        _check(lib().h4d_mlp_create(seed, stream if stream is not None else current_stream(), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if self._h is not None:
+            lib().h4d_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_weights(self, theta):
+        t = np.ascontiguousarray(theta, dtype=np.float32).reshape(N_PARAMS)
+        _check(lib().h4d_mlp_set_weights(self._h, _fp(t)))
+
+    def weights(self) -> np.ndarray:
+        t = np.zeros(N_PARAMS, np.float32)
+        _check(lib().h4d_mlp_get_weights(self._h, _fp(t)))
+        return t
+
+    def forward(self, X, bf16: bool = True) -> np.ndarray:
+        X = np.ascontiguousarray(X, dtype=np.float32).reshape(-1, 64)
+        out = np.zeros(max(len(X), 1), np.float32)
+        _check(lib().h4d_mlp_forward(self._h, len(X), _fp(X), 1 if bf16 else 0, _fp(out)))
+        return out[: len(X)]
+
+    def loss_grad(self, X, t):
+        X = np.ascontiguousarray(X, dtype=np.float32).reshape(-1, 64)
+        t = np.ascontiguousarray(t, dtype=np.float32).reshape(len(X))
+        g = np.zeros(N_PARAMS, np.float32)
+        loss = np.zeros(1, np.float32)
+        _check(lib().h4d_mlp_loss_grad(self._h, len(X), _fp(X), _fp(t), _fp(g), _fp(loss)))
+        return float(loss[0]), g
+
+    def train(self, X, t, steps: int, batch: int = 256, lr: float = 1e-3, seed: int = 0,
+              weight_decay: float = 0.0) -> np.ndarray:
+        X = np.ascontiguousarray(X, dtype=np.float32).reshape(-1, 64)
+        t = np.ascontiguousarray(t, dtype=np.float32).reshape(len(X))
+        losses = np.zeros(max(steps, 1), np.float32)
+        _check(lib().h4d_mlp_train(self._h, len(X), _fp(X), _fp(t), steps, batch, lr, weight_decay, seed,
+                                   _fp(losses)))
+        return losses[:steps]
+
+
 def _state_of(h, box: int) -> dict:
     n = C.c_int32()
     ns = C.c_int32()
@@ -225,6 +302,9 @@ class _Handle:
 
     def set_trial_index(self, t: int):
         _check(lib().h4d_set_trial_index(self._h, t))
+
+    def set_beta_mu(self, beta_mu: float):
+        _check(lib().h4d_set_beta_mu(self._h, beta_mu))
 
     def set_timing(self, on: bool = True):
         _check(lib().h4d_set_timing(self._h, 1 if on else 0))
@@ -342,6 +422,33 @@ class System(_Handle):
         _check(lib().h4d_forces_at(self._h, fl, w, F.ctypes.data_as(C.POINTER(C.c_double)),
                                    e.ctypes.data_as(C.POINTER(C.c_double))))
         return F[: st["n"]], dict(U=e[0], U_lj=e[1], U_c=e[2])
+
+    def set_proposal(self, net=None, k: int = 0, cap: float = 10.0):
+        """k <= 0: uniform proposal; k >= 1: multiple-try with k candidates
+        weighted by exp(min(logit, cap)) of net (None: equal weights)."""
+        _check(lib().h4d_set_proposal(self._h, net._h if net is not None else None, k, cap))
+        self._net = net     # the network must outlive its use
+
+    def last_site_features(self) -> np.ndarray:
+        f = np.zeros(64, np.float32)
+        _check(lib().h4d_last_site_features(self._h, _fp(f)))
+        return f
+
+    def last_candidates(self, k: int):
+        sites = np.zeros((k, 6))
+        feat = np.zeros((k, 64), np.float32)
+        logit = np.zeros(k, np.float32)
+        rc = lib().h4d_last_candidates(self._h, k, sites.ctypes.data_as(C.POINTER(C.c_double)), _fp(feat),
+                                       _fp(logit))
+        if rc < 0:
+            _check(rc)
+        return sites, feat, logit
+
+    def site_features(self, sites) -> np.ndarray:
+        st = np.ascontiguousarray(sites, dtype=np.float64).reshape(-1, 6)
+        out = np.zeros((len(st), 64), np.float32)
+        _check(lib().h4d_site_features(self._h, len(st), st.ctypes.data_as(C.POINTER(C.c_double)), _fp(out)))
+        return out
 
     def observables(self) -> dict:
         o = Observables()

@@ -15,7 +15,8 @@ The multiple-try factor is pinned by the ideal-gas laws (of N, and of the
 uniform placement of the ions) under a strongly biased proposal, and by its
 reduction to the uniform proposal.  The
 network is pinned by finite differences, the exact (erf) GELU, closed forms
-at zero weights and Adam's first step.
+at zero weights, Adam's first step, and the invariance of its function
+under the change to standardized input coordinates.
 """
 import math
 
@@ -226,3 +227,13 @@ def test_zero_network_closed_forms_and_first_adam_step():
     # first bias-corrected step: -lr * g / (|g| + eps)
     assert th1[-1] - theta[-1] == pytest.approx(-1e-3 * np.sign(g[-1]), rel=1e-6)
     assert mlp.N_PARAMS == 41473
+
+
+def test_standardized_coordinates_leave_the_network_unchanged():
+    rng = np.random.default_rng(9)
+    theta = mlp.random_theta(11)
+    X = rng.normal(size=(40, 64)) * rng.uniform(0.1, 30.0, size=64) + rng.normal(size=64) * 5
+    mean, sd = mlp.standardization(X)
+    ts = mlp.to_standard(theta, mean, sd)
+    assert np.allclose(mlp.forward(ts, (X - mean) / sd), mlp.forward(theta, X), rtol=1e-10, atol=1e-10)
+    assert np.allclose(mlp.from_standard(ts, mean, sd), theta, rtol=1e-12, atol=1e-12)
