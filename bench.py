@@ -165,6 +165,8 @@ def bench_single(args, h4d, W, torch):
     if args.skin > 0:
         w.params.update(skin=args.skin)
     sys_ = h4d.System.from_workload(w)
+    if args.autotune:
+        sys_.autotune(2)
     if args.warmup:
         sys_.trials(args.warmup)
     # pilot: forced uniform insertions that are never accepted (beta mu far
@@ -185,12 +187,17 @@ def bench_single(args, h4d, W, torch):
     import numpy as np
     X = np.array(feats, dtype=np.float32)
     y = np.clip(-beta * np.array(dH), -20.0, 10.0).astype(np.float32)
+    # a held-out fifth of the pilot measures what the network predicts
+    n_fit = max(1, (4 * len(X)) // 5)
     net = h4d.Mlp(seed=1)
     t0 = time.perf_counter()
-    steps = args.train_steps or max(50, (args.train_epochs * len(X)) // 128)
-    losses = net.train(X, y, steps=steps, batch=128, lr=1e-3, seed=2, weight_decay=1e-2)
+    steps = args.train_steps or max(50, (args.train_epochs * n_fit) // 128)
+    losses = net.train(X[:n_fit], y[:n_fit], steps=steps, batch=128, lr=1e-3, seed=2, weight_decay=1e-2)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
+    held = net.forward(X[n_fit:]) if n_fit < len(X) else None
+    holdout_corr = (float(np.corrcoef(held, y[n_fit:])[0, 1])
+                    if held is not None and len(held) > 2 and np.std(held) > 0 else None)
     # timed region, uniform proposal: every trial launched as one HIP graph
     sys_.set_beta_mu(beta_mu)
     sys_.set_proposal(None, 0)
@@ -224,6 +231,7 @@ def bench_single(args, h4d, W, torch):
         "gain_expected_exchanges_per_s": (l_exp * len(lrecs) / lwall) / max(1e-300, out["expected_exchanges_per_s"]),
         "pilot_insertions": args.pilot, "train_steps": steps, "train_s": train_s,
         "train_loss_first": float(losses[:10].mean()), "train_loss_last": float(losses[-50:].mean()),
+        "holdout_corr_logit_vs_target": holdout_corr,
     }
     config = {
         "workload": "lj32k: 32,000 LJ ions, density 0.3, 200-step NEMD pair insert/delete, "
@@ -297,7 +305,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rebuild-every", type=int, default=0, help="list rebuild interval (0: library default)")
     ap.add_argument("--lanes", type=int, default=0, help="lanes per atom (0: library default)")
-    ap.add_argument("--autotune", action="store_true", help="batched: pick lanes per atom by timing first")
+    ap.add_argument("--autotune", action="store_true", help="pick lanes per atom by timing trials first")
     ap.add_argument("--skin", type=float, default=0.0, help="Verlet skin (0: workload default)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run the stream-copy probe on MIB mebibytes and print its bandwidth")

@@ -463,17 +463,23 @@ __global__ __launch_bounds__(kBlock) void k_list_allpairs(KArgs a, int k, int b0
     }
 }
 
-// Cell form: one block per centre cell, one thread per centre atom.  The
-// 27 stencil cells are staged in LDS one z-layer (9 cells) at a time
-// (fixed-point coordinates + working slot, in stencil order); every thread
-// scans the staged candidates (LDS broadcast) and appends its partners in
-// stencil order.  Dynamic LDS: 9 * cell_cap * 16 bytes; block size: cell_cap
-// rounded up to whole wavefronts.  Also records the build positions, clears
-// this cell's count in the other buffer and the box's fast lists.
-__global__ __launch_bounds__(1024) void k_list_cells(KArgs a, int k, int b0, int cb) {
-    extern __shared__ uint4 cand[];
+// Cell form: one block of kListWaves wavefronts per centre cell.  The 27
+// stencil cells are staged in LDS one z-layer (9 cells) at a time
+// (fixed-point coordinates + working slot, in stencil order); each
+// wavefront takes a share of the centre atoms and tests 64 candidates per
+// ballot, appending partners in stencil order (a centre atom's running count
+// stays in LDS across the layers).  Dynamic LDS: (9 + 1) * cell_cap * 16 +
+// cell_cap * 4 bytes.  Also records the build positions, clears this cell's
+// count in the other buffer and the box's fast lists.
+constexpr int kListWaves = 8;
+
+__global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int k, int b0, int cb) {
+    extern __shared__ uint4 lds[];
     __shared__ int cidx[27], cnt27[27], off[10];
     const int cap = a.cell_cap;
+    uint4 *cand = lds;                           // 9 * cap staged candidates
+    uint4 *ctr = lds + 9 * (size_t)cap;          // cap centre atoms
+    int *ccount = reinterpret_cast<int *>(ctr + cap);
     const int cc = blockIdx.x;
     const int bi = box_of_cell(a, cc);
     const Box &B = a.box[bi];
@@ -490,19 +496,18 @@ __global__ __launch_bounds__(1024) void k_list_cells(KArgs a, int k, int b0, int
     }
     if (threadIdx.x == 0 && cc == B.c0) c->nfast[0] = c->nfast[1] = c->nfast[2] = 0;
     __syncthreads();
-    // this thread's centre atom (the centre cell is stencil entry 13)
-    const int mc = cnt27[13];
-    const int i = threadIdx.x;
-    const bool own = i < mc;
-    const int wi = own ? a.cell_atoms[cb][(size_t)cidx[13] * cap + i] : 0;
-    const uint4 qi = own ? a.fx[b][wi] : make_uint4(0, 0, 0, 0);
-    const int mi = (own && a.G.water) ? a.wmol[wi] : -1;
+    const int mc = cnt27[13];                    // the centre cell is stencil entry 13
+    for (int u = threadIdx.x; u < mc; u += blockDim.x) {
+        const int j = a.cell_atoms[cb][(size_t)cidx[13] * cap + u];
+        const uint4 q = a.fx[b][j];
+        ctr[u] = make_uint4(q.x, q.y, q.z, (unsigned)j);
+        ccount[u] = 0;
+    }
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const float rl2 = (float)a.G.rlist2 * 1.00001f;
     const float sx = B.fx_scale[0], sy = B.fx_scale[1], sz = B.fx_scale[2];
-    const int L = a.lanes, ll = a.lanes_log2, la = 6 - ll;
-    // blocked list row of this atom: entry q at row + (q / L) * 64 + q % L
-    int *row = a.nbr + (size_t)(wi >> la) * (size_t)(a.nbr_cap >> ll) * kWave + (size_t)((wi & ((1 << la) - 1)) << ll);
-    int cnt = 0;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const bool molecules = a.G.water != 0;
     for (int layer = 0; layer < 3; ++layer) {
         if (threadIdx.x == 0) {
             int run = 0;
@@ -521,35 +526,42 @@ __global__ __launch_bounds__(1024) void k_list_cells(KArgs a, int k, int b0, int
             }
         }
         __syncthreads();
-        if (own) {
-            auto test = [&](const uint4 &qj) {
-                const int j = (int)qj.w;
-                const float dx = (float)(int)(qi.x - qj.x) * sx;
-                const float dy = (float)(int)(qi.y - qj.y) * sy;
-                const float dz = (float)(int)(qi.z - qj.z) * sz;
-                bool acc = dx * dx + dy * dy + dz * dz < rl2 && j != wi;
-                if (acc && mi >= 0 && a.wmol[j] == mi) acc = false;
-                if (acc) {
-                    if (cnt < a.nbr_cap) row[(size_t)(cnt >> ll) * kWave + (cnt & (L - 1))] = j;
-                    ++cnt;
+        for (int t = wave; t < mc; t += kListWaves) {
+            const uint4 qi = ctr[t];
+            const int wi = (int)qi.w;
+            const int mi = molecules ? a.wmol[wi] : -1;
+            int cnt = ccount[t];
+            for (int base = 0; base < total; base += kWave) {
+                const int u = base + lane;
+                bool acc = false;
+                int j = 0;
+                if (u < total) {
+                    const uint4 qj = cand[u];
+                    j = (int)qj.w;
+                    const float dx = (float)(int)(qi.x - qj.x) * sx;
+                    const float dy = (float)(int)(qi.y - qj.y) * sy;
+                    const float dz = (float)(int)(qi.z - qj.z) * sz;
+                    acc = dx * dx + dy * dy + dz * dz < rl2 && j != wi;
+                    if (acc && mi >= 0 && a.wmol[j] == mi) acc = false;
                 }
-            };
-            int u = 0;
-            for (; u + 8 <= total; u += 8) {   // eight LDS reads in flight
-                uint4 q[8];
-#pragma unroll
-                for (int v = 0; v < 8; ++v) q[v] = cand[u + v];
-#pragma unroll
-                for (int v = 0; v < 8; ++v) test(q[v]);
+                const unsigned long long msk = __ballot(acc);
+                if (acc) {
+                    const int q = cnt + __popcll(msk & below);
+                    if (q < a.nbr_cap) a.nbr[nbr_slot(a, wi, q)] = j;
+                }
+                cnt += __popcll(msk);
             }
-            for (; u < total; ++u) test(cand[u]);
+            if (lane == 0) ccount[t] = cnt;
         }
         __syncthreads();
     }
-    if (own) {
+    for (int t = threadIdx.x; t < mc; t += blockDim.x) {
+        const uint4 qi = ctr[t];
+        const int wi = (int)qi.w;
+        const int cnt = ccount[t];
         a.nnbr[wi] = min(cnt, a.nbr_cap);
-        a.posb[wi] = qi;
-        unflag_fast(a, b, wi, qi.w);
+        a.posb[wi] = make_uint4(qi.x, qi.y, qi.z, a.fx[b][wi].w);
+        unflag_fast(a, b, wi, a.fx[b][wi].w);
         if (cnt > a.nbr_cap) { atomicOr(&c->err, kErrNbr); atomicMax(&c->max_nbr, cnt); }
     }
     if (threadIdx.x == 0) a.cell_cnt[cb ^ 1][cc] = 0;
@@ -655,18 +667,26 @@ __device__ __forceinline__ void group_force(const KArgs &a, const Box &B, const 
             ax += f * dx; ay += f * dy; az += f * dz;
         };
         if (!own_fast) {
+            // batches of NB neighbours: the list indices of the next batch
+            // load while this batch's records are gathered
+            constexpr int NB = 8;
             const int nn = a.nnbr[w];
             const int *base = a.nbr + ((size_t)(w / A) * (size_t)(a.nbr_cap / L)) * kWave + (size_t)(w % A) * L + s;
             const int nq = nn > s ? (nn - s + L - 1) / L : 0;
-            for (int k = 0; k < nq; k += 4) {
-                int j[4];
-                uint4 q[4];
+            int jn[NB];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) j[u] = (k + u < nq) ? base[(size_t)(k + u) * kWave] : w;
+            for (int u = 0; u < NB; ++u) jn[u] = (u < nq) ? base[(size_t)u * kWave] : w;
+            for (int k = 0; k < nq; k += NB) {
+                int j[NB];
+                uint4 q[NB];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) q[u] = F[j[u]];
+                for (int u = 0; u < NB; ++u) j[u] = jn[u];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) pair(q[u], k + u < nq && !(q[u].w & kFastBit));
+                for (int u = 0; u < NB; ++u) q[u] = F[j[u]];
+#pragma unroll
+                for (int u = 0; u < NB; ++u) jn[u] = (k + NB + u < nq) ? base[(size_t)(k + NB + u) * kWave] : w;
+#pragma unroll
+                for (int u = 0; u < NB; ++u) pair(q[u], k + u < nq && !(q[u].w & kFastBit));
             }
         } else if (B.use_cells) {
             const int cx = cell_coord(pi.x, B.L[0], B.ncell[0]);

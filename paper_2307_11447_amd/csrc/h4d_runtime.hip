@@ -291,14 +291,15 @@ void set_lanes(h4d_system *s, int L) {
 
 int slot_blocks(const h4d_system *s) { return s->a.slots / kBlock; }
 
-size_t list_cells_lds(const h4d_system *s) { return (size_t)s->a.cell_cap * 9 * sizeof(uint4); }
-int list_cells_threads(const h4d_system *s) { return round_up(s->a.cell_cap, kWave); }
+size_t list_cells_lds(const h4d_system *s) {
+    return (size_t)s->a.cell_cap * (10 * sizeof(uint4) + sizeof(int));
+}
 
 // list build; k and b as in list_wanted / buf_of
 void launch_list(h4d_system *s, int k, int b, int cb, hipStream_t st) {
     KArgs &a = s->a;
-    if (s->cells && list_cells_lds(s) <= 56 * 1024 && list_cells_threads(s) <= 1024)
-        hipLaunchKernelGGL(k_list_cells, dim3(a.ncell_total), dim3(list_cells_threads(s)), list_cells_lds(s), st, a,
+    if (s->cells && list_cells_lds(s) <= 56 * 1024)
+        hipLaunchKernelGGL(k_list_cells, dim3(a.ncell_total), dim3(kListWaves * kWave), list_cells_lds(s), st, a,
                            k, b, cb);
     else if (s->cells)
         hipLaunchKernelGGL(k_list_lanes, dim3(a.step_blocks), dim3(kBlock), 0, st, a, k, b, cb);
