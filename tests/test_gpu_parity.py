@@ -3,7 +3,10 @@ seeded inputs, through the C ABI.
 
 Tolerances:
 * forces from identical states: FP64 mode 1e-12 relative; FP32 mode
-  ||dF||_2 / ||F||_2 <= 1e-5 and |dF_i| <= 1e-5 max(|F_i|, F_rms) per atom;
+  ||dF||_2 / ||F||_2 <= 1e-5 and |dF_i| <= 1e-5 max(|F_i|, F_rms) per atom,
+  where an atom with a pair within 1e-6 of the Lennard-Jones cutoff (the
+  force jumps there, and the FP32 distance decides whether the pair counts)
+  may match the oracle with or without that pair;
 * FP64 energies: 1e-12 relative;
 * FP64 trials: identical accept/reject sequence, dH, W_prot and E_switch
   within 1e-6 relative (floor 1 kT);
@@ -43,7 +46,43 @@ def oracle_forces(w, flyers, wv, use_cells=True):
     return e, F
 
 
-def compare_forces(Fg, Fr, mask, tol_rel, per_atom):
+def cutoff_edge_terms(w, flyers, wv, eps=1e-6):
+    """Pairs whose (4D) distance lies within eps of the Lennard-Jones cutoff,
+    where the truncated-shifted potential's force jumps: whether such a pair
+    counts is decided by the precision of the distance (FP32 on the GPU,
+    FP64 in the oracle), and both outcomes are valid.  Returns, per atom, the
+    force those pairs contribute (FP64, from the oracle's pair function)."""
+    from scipy.spatial import cKDTree
+    p = w.params
+    L = p["box"][0]
+    rc = p["rc_lj"]
+    fly = np.zeros(w.n, bool)
+    for f in flyers:
+        if f >= 0:
+            fly[f] = True
+    tree = cKDTree(np.mod(w.x, L), boxsize=L)
+    pairs = tree.query_pairs(rc + 1e-3, output_type="ndarray")
+    extra = np.zeros((w.n, 3))
+    for i, j in pairs:
+        d = w.x[i] - w.x[j]
+        d -= L * np.round(d / L)
+        r2 = float(d @ d)
+        s2 = r2 + (wv * wv if fly[i] != fly[j] else 0.0)
+        if abs(math.sqrt(s2) - rc) > eps:
+            continue
+        ulj, uc, dlj, dc = O.pair(p, int(w.type[i]), int(w.type[j]), math.sqrt(s2) * (1 - 1e-12))
+        f = -dlj / math.sqrt(s2) * d          # force on i from the LJ term
+        extra[i] += f
+        extra[j] -= f
+    return extra
+
+
+def compare_forces(Fg, Fr, mask, tol_rel, per_atom, edge=None):
+    if edge is not None:
+        # atoms with a pair at the cutoff: either outcome of the inclusion test is valid
+        alt = Fr - edge
+        use_alt = np.linalg.norm(Fg - alt, axis=1) < np.linalg.norm(Fg - Fr, axis=1)
+        Fr = np.where(use_alt[:, None], alt, Fr)
     d = (Fg - Fr)[mask]
     ref = Fr[mask]
     rel = np.linalg.norm(d) / np.linalg.norm(ref)
@@ -73,7 +112,7 @@ def test_forces_match_oracle(n, prec, kappa):
     if prec == "fp64":
         compare_forces(Fg, Fr, mask, 1e-12, 1e-11)
     else:
-        compare_forces(Fg, Fr, mask, 1e-5, 1e-5)
+        compare_forces(Fg, Fr, mask, 1e-5, 1e-5, cutoff_edge_terms(w, flyers, wv))
     # FP64 energies in both modes
     assert eg["U"] == pytest.approx(er.U, rel=1e-12)
     assert eg["U_lj"] == pytest.approx(er.U_lj, rel=1e-12)
@@ -92,7 +131,9 @@ def test_forces_full_size_32k_fp32():
     er, Fr = oracle_forces(w, flyers, 0.8)
     mask = np.ones(w.n, bool)
     mask[list(flyers)] = False
-    compare_forces(Fg, Fr, mask, 1e-5, 1e-5)
+    edge = cutoff_edge_terms(w, flyers, 0.8)
+    say(f"   {int((np.linalg.norm(edge, axis=1) > 0).sum())} atoms with a pair within 1e-6 of the LJ cutoff")
+    compare_forces(Fg, Fr, mask, 1e-5, 1e-5, edge)
     assert eg["U"] == pytest.approx(er.U, rel=1e-12)
     sys_.close()
 
