@@ -151,6 +151,42 @@ def jarzynski_beta_mu(dH, beta, volume, n_pairs):
     return -2.0 * math.log(volume / (n_pairs + 1)) - lme
 
 
+def choose_proposal(logits, bdH, c, k_max, draws=4000, seed=7):
+    """(k, weight scale) of the learned proposal with the highest insertion
+    acceptance, estimated from held-out pilot insertions (network logit s_i,
+    beta dH_i, drawn uniformly): each simulated move draws k pilot sites,
+    picks one with probability proportional to exp(scale min(s, 10)) and
+    takes min(1, exp(c - beta dH + ln(W/k) - log weight)), c = beta mu + I.
+    Scale 0 is the uniform proposal."""
+    import numpy as np
+    if logits is None or len(logits) < 8:
+        return 1, 0.0, {}
+    rng = np.random.default_rng(seed)
+    s = np.minimum(np.asarray(logits, dtype=np.float64), 10.0)
+    bdH = np.asarray(bdH, dtype=np.float64)
+    bdH = np.where(np.isfinite(bdH), bdH, np.inf)     # an overlap is never accepted
+    m = len(s)
+    est = {"uniform": float(np.mean(np.exp(np.minimum(0.0, c - bdH))))}
+    best = (1, 0.0, est["uniform"])
+    for k in sorted({8, 16, k_max}):
+        idx = rng.integers(0, m, size=(draws, k))
+        for scale in (0.25, 0.5, 1.0):
+            lw = scale * s[idx]
+            mx = lw.max(axis=1, keepdims=True)
+            p = np.exp(lw - mx)
+            lnWk = (mx[:, 0] + np.log(p.sum(axis=1))) - math.log(k)
+            cum = np.cumsum(p, axis=1)
+            u = rng.random(draws) * cum[:, -1]
+            sel = np.minimum((cum < u[:, None]).sum(axis=1), k - 1)
+            j = idx[np.arange(draws), sel]
+            lnR = c - bdH[j] + lnWk - lw[np.arange(draws), sel]
+            a = float(np.mean(np.exp(np.minimum(0.0, lnR))))
+            est[f"k{k}_scale{scale}"] = a
+            if a > best[2]:
+                best = (k, scale, a)
+    return best[0], best[1], est
+
+
 def timed_trials(sys_, torch, n):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -198,12 +234,20 @@ def bench_single(args, h4d, W, torch):
     held = net.forward(X[n_fit:]) if n_fit < len(X) else None
     holdout_corr = (float(np.corrcoef(held, y[n_fit:])[0, 1])
                     if held is not None and len(held) > 2 and np.std(held) > 0 else None)
+    # candidates k and weight scale: the pair with the highest insertion
+    # acceptance estimated by resampling the held-out pilot sites (scale 0 is
+    # the uniform proposal, always among the choices)
+    k_sel, scale_sel, est = choose_proposal(held, beta * np.array(dH[n_fit:]) if held is not None else None,
+                                            beta_mu + 2.0 * math.log(L ** 3 / (st["nsalt"] + 1)),
+                                            args.candidates)
     # timed region, uniform proposal: every trial launched as one HIP graph
     sys_.set_beta_mu(beta_mu)
     sys_.set_proposal(None, 0)
     recs, wall = timed_trials(sys_, torch, args.steps)
-    # the learned proposal from the state the uniform run reached
-    sys_.set_proposal(net, args.candidates)
+    # the learned proposal from the state the uniform run reached (the plain
+    # uniform proposal when the held-out sites favour no weighting)
+    if scale_sel > 0.0:
+        sys_.set_proposal(net, k_sel, 10.0, scale_sel)
     lrecs, lwall = timed_trials(sys_, torch, args.learned_steps)
     sys_.set_proposal(None, 0)
     # step-kernel duration: further trials with HIP events around every
@@ -221,8 +265,11 @@ def bench_single(args, h4d, W, torch):
     lo, hi = wilson(l_acc, len(lrecs))
     l_exp = expected_acceptance(lrecs)
     out["learned"] = {
-        "proposal": f"multiple-try, k = {args.candidates} candidates weighted by the trained network "
-                    "(BF16 matrix-core inference)",
+        "proposal": (f"multiple-try, k = {k_sel} candidates weighted by exp({scale_sel} min(s, 10)), s the "
+                     "trained network's logit (BF16 matrix-core inference)" if scale_sel > 0.0 else
+                     "uniform: on the held-out pilot sites no (k, scale) beat it"),
+        "candidates": k_sel, "weight_scale": scale_sel,
+        "choice_estimates": est,
         "value": sum(r.n_atoms * r.n_steps for r in lrecs) / lwall, "unit": "atom-steps/s",
         "trials": len(lrecs), "trials_per_s": len(lrecs) / lwall,
         "accepted": l_acc, "accepted_exchanges_per_s": l_acc / lwall,

@@ -280,7 +280,7 @@ int32_t h4d_stream_copy(int64_t bytes, int32_t reps, double *ms);
  * insertion draws k uniform candidate pair sites (Philox counters
  * (trial, 4, j, 0 / 1)), weighs each by exp(s), s the network's logit of the
  * site's 64 features on the state before the trajectory (log weight
- * min(s, logit_cap)), and flies the pair
+ * weight_scale * min(s, logit_cap)), and flies the pair
  * in at one chosen with probability proportional to its weight (uniform
  * (trial, 5, 0, 0)); ln R of Eqs. (6) gains ln(W/k) - s(chosen).  A deletion
  * weighs the removed pair's site and k - 1 fresh candidates on the state
@@ -337,12 +337,14 @@ int32_t h4d_mlp_train(h4d_mlp *net, int32_t rows, const float *features, const f
 
 /* Proposal of the following trials: k <= 0 the uniform proposal of Eq. (4);
  * k >= 1 the multiple-try proposal with k candidates, weighted by
- * exp(min(s, logit_cap)) with s the logit of `net` (NULL: equal weights,
- * which with k = 1 is the uniform proposal again and records the features
- * of every inserted or removed site).  The cap bounds how far a network's
- * extrapolation errors can steer the choice; any cap keeps the method
- * exact. */
-int32_t h4d_set_proposal(h4d_system *sys, const h4d_mlp *net, int32_t k, double logit_cap);
+ * exp(weight_scale * min(s, logit_cap)) with s the logit of `net` (NULL:
+ * equal weights, which with k = 1 is the uniform proposal again and records
+ * the features of every inserted or removed site).  The cap bounds how far
+ * a network's extrapolation errors can steer the choice; weight_scale
+ * (>= 0) tempers a network whose predictions are weak (0: the uniform
+ * proposal).  Any cap and scale keep the method exact. */
+int32_t h4d_set_proposal(h4d_system *sys, const h4d_mlp *net, int32_t k, double logit_cap,
+                         double weight_scale);
 /* Features of the last trial's inserted or removed pair site (64 floats). */
 int32_t h4d_last_site_features(h4d_system *sys, float *out);
 /* The last learned move's candidates: sites[6k], features[64k], logits[k]

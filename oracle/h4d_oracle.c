@@ -661,7 +661,7 @@ static int score_sites(const or_params *p, const or_state *s, const or_proposal 
         return 0;
     }
     const int rc = prop->fn(prop->ctx, n, feat, logw);
-    for (int j = 0; j < n; ++j) logw[j] = fmin(logw[j], prop->cap);
+    for (int j = 0; j < n; ++j) logw[j] = prop->scale * fmin(logw[j], prop->cap);
     return rc;
 }
 

@@ -115,7 +115,7 @@ int or_trial(const or_params *p, or_state *s, uint64_t trial, int force_move,
 /*
  * Learned proposal (multiple-try form of the uniform pair insertion of
  * Eq. 4).  An insertion draws k uniform candidate pair sites (counters
- * (t, 4, j, 0/1)), weighs them by exp(min(logit, cap)) on the state before the
+ * (t, 4, j, 0/1)), weighs them by exp(scale min(logit, cap)) on the state before the
  * trajectory and picks one with probability proportional to its weight
  * (uniform (t, 5, 0, 0)); the ratio gains ln(W/k) - logit(chosen).  A
  * deletion weighs the removed pair's site and k - 1 fresh candidates on the
@@ -128,7 +128,8 @@ typedef struct {
     int32_t k;          /* candidates per move (>= 1)                     */
     or_logit_fn fn;     /* network; NULL: every logit 0                   */
     void *ctx;
-    double cap;         /* log weight = min(logit, cap)                   */
+    double cap;         /* log weight = scale * min(logit, cap)           */
+    double scale;
 } or_proposal;
 
 /* The 64 features of a candidate pair site (cation site[0..2], anion

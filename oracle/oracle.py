@@ -64,7 +64,8 @@ LOGIT_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.POINTER(C.c_double), C.PO
 
 
 class Proposal(C.Structure):
-    _fields_ = [("k", C.c_int32), ("fn", LOGIT_FN), ("ctx", C.c_void_p), ("cap", C.c_double)]
+    _fields_ = [("k", C.c_int32), ("fn", LOGIT_FN), ("ctx", C.c_void_p), ("cap", C.c_double),
+                ("scale", C.c_double)]
 
 
 class Energy(C.Structure):
@@ -203,13 +204,16 @@ class OracleSystem:
             raise RuntimeError(f"or_site_features failed: {rc}")
         return out
 
-    def trial_learned(self, t: int, k: int, logits=None, force_move: int = 0, cap: float = 10.0):
+    def trial_learned(self, t: int, k: int, logits=None, force_move: int = 0, cap: float = 10.0,
+                      scale: float = 1.0):
         """Trial with the learned proposal.  logits(features n x 64) -> n
-        logits, or None for equal weights; log weights are min(logit, cap).
-        Returns (record, features of the inserted / removed site)."""
+        logits, or None for equal weights; log weights are
+        scale * min(logit, cap).  Returns (record, features of the inserted /
+        removed site)."""
         prop = Proposal()
         prop.k = k
         prop.cap = cap
+        prop.scale = scale
         keep = None
         if logits is not None:
             def cb(ctx, n, feat, out):

@@ -1,7 +1,7 @@
 // h4d_learned.hpp -- learned insertion proposal on gfx950.
 //
 // Multiple-try form of the uniform pair insertion of Eq. (4): an insertion
-// draws k uniform candidate pair sites, weighs each by exp(min(s, cap)) with s the
+// draws k uniform candidate pair sites, weighs each by exp(scale min(s, cap)) with s the
 // network's logit of the site's 64 features on the state before the
 // trajectory, and flies the pair in at one chosen with probability
 // proportional to its weight; the Metropolis ratio gains ln(W/k) - s(chosen).
@@ -38,7 +38,8 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 struct LearnArgs {
     int k;                  // candidates per move
     int use_net;            // 0: every logit is 0 (equal weights)
-    double cap;             // log weight = min(logit, cap)
+    double cap;             // log weight = scale * min(logit, cap)
+    double scale;
     double *sites;          // k x 6: cation xyz, anion xyz
     float *feat;            // k x 64
     float *logit;           // k
@@ -352,7 +353,7 @@ __global__ void k_mtm_select(KArgs a, LearnArgs l, int phase) {
     const int move = c->move;
     if (phase == 0 ? move <= 0 : move >= 0) return;
     const int k = l.k;
-    auto lw = [&](int j) { return fmin((double)l.logit[j], l.cap); };
+    auto lw = [&](int j) { return l.scale * fmin((double)l.logit[j], l.cap); };
     double mx = lw(0);
     for (int j = 1; j < k; ++j) mx = fmax(mx, lw(j));
     double acc = 0.0;

@@ -1456,9 +1456,10 @@ int32_t h4d_mlp_train(h4d_mlp *n, int32_t rows, const float *features, const flo
     return mlp_pack(n);
 }
 
-int32_t h4d_set_proposal(h4d_system *s, const h4d_mlp *net, int32_t k, double logit_cap) {
+int32_t h4d_set_proposal(h4d_system *s, const h4d_mlp *net, int32_t k, double logit_cap, double weight_scale) {
     if (!s) return fail(H4D_EINVAL, "null handle");
-    if (!(logit_cap == logit_cap)) return fail(H4D_EINVAL, "logit_cap is NaN");
+    if (!(logit_cap == logit_cap) || !std::isfinite(weight_scale) || weight_scale < 0.0)
+        return fail(H4D_EINVAL, "logit_cap must not be NaN and weight_scale must be finite and >= 0");
     if (k > 65536) return fail(H4D_EINVAL, "at most 65536 candidates");
     if (k > 0 && s->nbox != 1) return fail(H4D_EINVAL, "the learned proposal serves single-box systems");
     s->drop_graphs();
@@ -1478,6 +1479,7 @@ int32_t h4d_set_proposal(h4d_system *s, const h4d_mlp *net, int32_t k, double lo
     }
     l.k = k;
     l.cap = logit_cap;
+    l.scale = weight_scale;
     l.use_net = net != nullptr;
     l.theta = net ? net->theta : nullptr;
     l.wfrag = net ? net->wfrag : nullptr;

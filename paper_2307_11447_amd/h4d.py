@@ -136,7 +136,7 @@ def lib() -> C.CDLL:
         L.h4d_mlp_loss_grad.argtypes = [vp, C.c_int32, fp, fp, fp, fp]
         L.h4d_mlp_train.argtypes = [vp, C.c_int32, fp, fp, C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_uint64,
                                     fp]
-        L.h4d_set_proposal.argtypes = [vp, vp, C.c_int32, C.c_double]
+        L.h4d_set_proposal.argtypes = [vp, vp, C.c_int32, C.c_double, C.c_double]
         L.h4d_last_site_features.argtypes = [vp, fp]
         L.h4d_last_candidates.argtypes = [vp, C.c_int32, dp, fp, fp]
         L.h4d_site_features.argtypes = [vp, C.c_int32, dp, fp]
@@ -423,10 +423,10 @@ class System(_Handle):
                                    e.ctypes.data_as(C.POINTER(C.c_double))))
         return F[: st["n"]], dict(U=e[0], U_lj=e[1], U_c=e[2])
 
-    def set_proposal(self, net=None, k: int = 0, cap: float = 10.0):
+    def set_proposal(self, net=None, k: int = 0, cap: float = 10.0, scale: float = 1.0):
         """k <= 0: uniform proposal; k >= 1: multiple-try with k candidates
-        weighted by exp(min(logit, cap)) of net (None: equal weights)."""
-        _check(lib().h4d_set_proposal(self._h, net._h if net is not None else None, k, cap))
+        weighted by exp(scale * min(logit, cap)) of net (None: equal weights)."""
+        _check(lib().h4d_set_proposal(self._h, net._h if net is not None else None, k, cap, scale))
         self._net = net     # the network must outlive its use
 
     def last_site_features(self) -> np.ndarray:

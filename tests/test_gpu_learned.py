@@ -116,8 +116,9 @@ def test_mlp_gradient_and_adam_match_fp64():
     net.close()
 
 
-def test_learned_trials_replay_oracle_decisions():
-    say("case learned trials fp64 lj500, k = 32, replayed through the oracle")
+@pytest.mark.parametrize("scale", [1.0, 0.5])
+def test_learned_trials_replay_oracle_decisions(scale):
+    say(f"case learned trials fp64 lj500, k = 32, weight scale {scale}, replayed through the oracle")
     w = W.config_lj_500()
     w.params.update(beta_mu=6.0, n_steps=60)
     k = 32
@@ -125,7 +126,7 @@ def test_learned_trials_replay_oracle_decisions():
     net = h4d.Mlp(seed=3)
     net.set_weights(theta)
     g = h4d.System.from_workload(w)
-    g.set_proposal(net, k)
+    g.set_proposal(net, k, 10.0, scale)
     o = O.OracleSystem.from_workload(w, cap=w.n + 200)
     worst_feat = 0.0
     n_acc = 0
@@ -138,7 +139,7 @@ def test_learned_trials_replay_oracle_decisions():
             seen["X"] = X
             return lg.astype(np.float64)
 
-        ro, _ = o.trial_learned(t, k, replay)
+        ro, _ = o.trial_learned(t, k, replay, scale=scale)
         assert rg["move"] == ro["move"] and rg["flags"] & 3 == ro["flags"]
         if ro["flags"] & 1:
             continue

@@ -147,6 +147,27 @@ def test_equal_weights_and_single_candidate_reduce_to_the_uniform_proposal():
         assert ra["ln_proposal"] == 0.0 and rb["ln_proposal"] == 0.0
 
 
+def test_zero_weight_scale_is_the_equal_weight_proposal():
+    # log weights scale * min(s, cap): scale 0 makes every candidate's weight
+    # 1 whatever the network says, so the trials repeat the equal-weight run
+    # record for record; a positive scale moves ln q away from 0
+    w = lj_state(n=200, rho=0.25, n_steps=20)
+    theta = mlp.random_theta(5, scale=3.0)
+    net = lambda X: mlp.forward(theta, X)
+    a = O.OracleSystem.from_workload(w, cap=w.n + 40)
+    b = O.OracleSystem.from_workload(w, cap=w.n + 40)
+    c = O.OracleSystem.from_workload(w, cap=w.n + 40)
+    lnq = []
+    for t in range(6):
+        ra, fa = a.trial_learned(t, 8, None)
+        rb, fb = b.trial_learned(t, 8, net, scale=0.0)
+        assert ra == rb and np.array_equal(fa, fb)
+        rc, _ = c.trial_learned(t, 8, net, scale=0.5)
+        lnq.append(rc["ln_proposal"])
+    assert np.array_equal(a.positions(), b.positions())
+    assert max(abs(q) for q in lnq) > 1e-3
+
+
 def test_ideal_gas_laws_hold_under_a_biased_proposal():
     # a proposal that strongly prefers sites next to existing ions (any
     # weights keep the chain exact): N still follows y^(2N) / (N!)^2 and the
