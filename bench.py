@@ -12,6 +12,15 @@ positions, velocities, energies, work and Metropolis ratio; uniform
 Prints one JSON line.  value = NEMD atom-steps/s (sum over trials of
 atoms x N_f, divided by the wall time of the timed trials).
 
+Both single-box workloads also measure the learned proposal: pilot
+insertions give each uniform site's 64 features and dH, the network is
+trained on them on the GPU, and the same number of timed trials run with
+the multiple-try proposal it weights (reported under "learned", next to the
+uniform run's accepted and expected exchanges per second).
+
+--workload water: 8,000 rigid SPC/E waters + 150 NaCl pairs in a 62 A box,
+NaCl-pair trials of 500 steps of 1 fs.
+
 --workload batched: 256 independent boxes of 1,000-16,000 ions at
 densities 0.1-0.4, N_f ~ U{100..400} per trial, all boxes running their
 trials together; one "step" is one trial in every box.
@@ -49,6 +58,11 @@ def counted_traffic(path):
         return float(kv["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def note(msg):
+    """Progress of the run on stderr (stdout carries only the JSON line)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
 def wilson(k, n, z=1.96):
@@ -151,15 +165,19 @@ def jarzynski_beta_mu(dH, beta, volume, n_pairs):
     return -2.0 * math.log(volume / (n_pairs + 1)) - lme
 
 
-def choose_proposal(logits, bdH, c, k_max, draws=4000, seed=7):
+def choose_proposal(logits, bdH, c, ks=(4, 8, 16, 32, 64), scales=(0.25, 0.5, 1.0), margin=1.25,
+                    draws=20000, seed=7):
     """(k, weight scale) of the learned proposal with the highest insertion
-    acceptance, estimated from held-out pilot insertions (network logit s_i,
-    beta dH_i, drawn uniformly): each simulated move draws k pilot sites,
-    picks one with probability proportional to exp(scale min(s, 10)) and
-    takes min(1, exp(c - beta dH + ln(W/k) - log weight)), c = beta mu + I.
-    Scale 0 is the uniform proposal."""
+    acceptance, estimated from pilot insertions (out-of-fold network logit
+    s_i and beta dH_i of sites drawn uniformly): each simulated move draws k
+    pilot sites, picks one with probability proportional to
+    exp(scale min(s, 10)) and takes min(1, exp(c - beta dH + ln(W/k) - log
+    weight)), c = beta mu + I.  k stays at most an eighth of the pilot so
+    that the resampled candidate sets do not repeat the same few sites.  The
+    uniform proposal (scale 0) is kept unless the best pair beats it by the
+    margin: rare acceptances make these estimates noisy."""
     import numpy as np
-    if logits is None or len(logits) < 8:
+    if logits is None or len(logits) < 32:
         return 1, 0.0, {}
     rng = np.random.default_rng(seed)
     s = np.minimum(np.asarray(logits, dtype=np.float64), 10.0)
@@ -167,10 +185,12 @@ def choose_proposal(logits, bdH, c, k_max, draws=4000, seed=7):
     bdH = np.where(np.isfinite(bdH), bdH, np.inf)     # an overlap is never accepted
     m = len(s)
     est = {"uniform": float(np.mean(np.exp(np.minimum(0.0, c - bdH))))}
-    best = (1, 0.0, est["uniform"])
-    for k in sorted({8, 16, k_max}):
+    best = (1, 0.0, est["uniform"] * margin)
+    for k in ks:
+        if 8 * k > m:
+            continue
         idx = rng.integers(0, m, size=(draws, k))
-        for scale in (0.25, 0.5, 1.0):
+        for scale in scales:
             lw = scale * s[idx]
             mx = lw.max(axis=1, keepdims=True)
             p = np.exp(lw - mx)
@@ -187,6 +207,72 @@ def choose_proposal(logits, bdH, c, k_max, draws=4000, seed=7):
     return best[0], best[1], est
 
 
+def train_network(h4d, X, y, epochs, seed=1):
+    """The proposal network trained on the GPU (FP32 forward, backward and
+    Adam with decoupled weight decay; batch 128, lr 1e-3)."""
+    net = h4d.Mlp(seed=seed)
+    steps = max(50, (epochs * len(X)) // 128)
+    losses = net.train(X, y, steps=steps, batch=128, lr=1e-3, seed=seed + 1, weight_decay=1e-2)
+    return net, steps, losses
+
+
+def out_of_fold(h4d, X, y, epochs, folds=5):
+    """Logits of every pilot site from a network trained without it
+    (folds-fold cross validation)."""
+    import numpy as np
+    oof = np.zeros(len(X))
+    fold = np.arange(len(X)) % folds
+    for f in range(folds):
+        tr, te = fold != f, fold == f
+        net, _, _ = train_network(h4d, X[tr], y[tr], epochs, seed=10 + f)
+        oof[te] = net.forward(X[te])
+        net.close()
+    return oof
+
+
+def proposal_ab(sys_, torch, h4d, arms, beta_mu, n_each, block=50):
+    """Insertion and deletion acceptance of several proposals on one fixed
+    state: forced moves at beta mu = -1000 (insertions) and +1000
+    (deletions), which are never accepted, so the state does not change;
+    each record's ln R is moved to the operating beta mu and the mean of
+    min(1, R) taken.  The arms alternate in blocks so that they share the
+    same state and device conditions.  arms: name -> (net, k, scale)."""
+    out = {name: {"ins": [], "del": [], "s": 0.0, "n": 0} for name in arms}
+    done = 0
+    while done < n_each:
+        nb = min(block, n_each - done)
+        for name, (net, k, scale) in arms.items():
+            if k > 0:
+                sys_.set_proposal(net, k, 10.0, scale)
+            else:
+                sys_.set_proposal(None, 0)
+            for move, bm, key in ((h4d.MOVE_INSERT, -1.0e3, "ins"), (h4d.MOVE_DELETE, 1.0e3, "del")):
+                sys_.set_beta_mu(bm)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                arr = sys_.trials(nb, move, as_array=True)
+                torch.cuda.synchronize()
+                out[name]["s"] += time.perf_counter() - t0
+                out[name]["n"] += nb
+                shift = (beta_mu - bm) * (1.0 if move > 0 else -1.0)
+                for q in range(nb):
+                    r = arr[q]
+                    ok = not (r.flags & 0x3) and math.isfinite(r.ln_ratio)
+                    out[name][key].append(math.exp(min(0.0, r.ln_ratio + shift)) if ok else 0.0)
+        done += nb
+    sys_.set_proposal(None, 0)
+    sys_.set_beta_mu(beta_mu)
+    res = {}
+    for name, o in out.items():
+        p_ins = sum(o["ins"]) / max(1, len(o["ins"]))
+        p_del = sum(o["del"]) / max(1, len(o["del"]))
+        rate = o["n"] / max(1e-300, o["s"])
+        res[name] = {"p_insert": p_ins, "p_delete": p_del, "trials_per_s": rate,
+                     "expected_exchanges_per_s": 0.5 * (p_ins + p_del) * rate,
+                     "insertions": len(o["ins"]), "deletions": len(o["del"])}
+    return res
+
+
 def timed_trials(sys_, torch, n):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -195,9 +281,29 @@ def timed_trials(sys_, torch, n):
     return [arr[q] for q in range(n)], time.perf_counter() - t0
 
 
+SINGLE = {
+    "lj32k": ("config_lj_32k",
+              "lj32k: 32,000 LJ ions, density 0.3, 200-step NEMD pair insert/delete, FP32 pair arithmetic / "
+              "FP64 state, energies and work", "the 32,000-ion state",
+              dict(n_atoms=32000, density=0.3, n_steps_per_trial=200, dt=0.005, w_max=2.5)),
+    "water": ("config_water_nacl",
+              "water: 8,000 rigid SPC/E waters + 150 NaCl pairs in a 62 A box, 298 K, 500-step NEMD NaCl-pair "
+              "insert/delete (dt 1 fs, w_max 3 A, kappa_sr 1/A), FP32 pair arithmetic / FP64 state, energies "
+              "and work", "the aqueous NaCl state",
+              dict(n_atoms=24300, n_waters=8000, n_pairs=150, box_A=62.0, n_steps_per_trial=500, dt_fs=1.0,
+                   w_max_A=3.0)),
+}
+
+
 def bench_single(args, h4d, W, torch):
-    w = W.config_lj_32k()
-    w.params.update(rebuild_every=args.rebuild_every, lanes_per_atom=args.lanes, capacity=w.n + 1024)
+    import numpy as np
+    maker, desc, label, shape = SINGLE[args.workload]
+    w = getattr(W, maker)()
+    w.params.update(capacity=w.n + 1024)
+    if args.rebuild_every:
+        w.params.update(rebuild_every=args.rebuild_every)
+    if args.lanes:
+        w.params.update(lanes_per_atom=args.lanes)
     if args.skin > 0:
         w.params.update(skin=args.skin)
     sys_ = h4d.System.from_workload(w)
@@ -210,46 +316,55 @@ def bench_single(args, h4d, W, torch):
     sys_.set_beta_mu(-1.0e3)
     sys_.set_proposal(None, 1)
     feats, dH = [], []
+    t0 = time.perf_counter()
     for _ in range(args.pilot):
         r = sys_.trial(h4d.MOVE_INSERT)
         feats.append(sys_.last_site_features())
         dH.append(r["dH"])
+    pilot_s = time.perf_counter() - t0
+    note(f"pilot: {args.pilot} insertions in {pilot_s:.1f} s")
     st = sys_.state()
     beta = 1.0 / w.params["kT"]
     L = w.params["box"][0]
     bmu_eq = jarzynski_beta_mu(dH, beta, L ** 3, st["nsalt"])
     beta_mu = args.beta_mu if args.beta_mu is not None else bmu_eq
-    # the network learns clip(-beta dH, -20, 10) of the pilot sites (GPU, FP32)
-    import numpy as np
+    c = beta_mu + 2.0 * math.log(L ** 3 / (st["nsalt"] + 1))
+    # the network learns the clipped log insertion ratio c - beta dH of the
+    # pilot sites (GPU, FP32); out-of-fold logits choose k and the scale
     X = np.array(feats, dtype=np.float32)
-    y = np.clip(-beta * np.array(dH), -20.0, 10.0).astype(np.float32)
-    # a held-out fifth of the pilot measures what the network predicts
-    n_fit = max(1, (4 * len(X)) // 5)
-    net = h4d.Mlp(seed=1)
+    bdH = beta * np.array(dH)
+    ok = np.isfinite(bdH)
+    X, bdH = X[ok], bdH[ok]
+    y = np.clip(c - bdH, -100.0, 10.0).astype(np.float32)
     t0 = time.perf_counter()
-    steps = args.train_steps or max(50, (args.train_epochs * n_fit) // 128)
-    losses = net.train(X[:n_fit], y[:n_fit], steps=steps, batch=128, lr=1e-3, seed=2, weight_decay=1e-2)
+    oof = out_of_fold(h4d, X, y, args.train_epochs)
+    k_sel, scale_sel, est = choose_proposal(oof, bdH, c, ks=tuple(k for k in (4, 8, 16, 32, 64)
+                                                                   if k <= args.candidates))
+    net, steps, losses = train_network(h4d, X, y, args.train_epochs)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
-    held = net.forward(X[n_fit:]) if n_fit < len(X) else None
-    holdout_corr = (float(np.corrcoef(held, y[n_fit:])[0, 1])
-                    if held is not None and len(held) > 2 and np.std(held) > 0 else None)
-    # candidates k and weight scale: the pair with the highest insertion
-    # acceptance estimated by resampling the held-out pilot sites (scale 0 is
-    # the uniform proposal, always among the choices)
-    k_sel, scale_sel, est = choose_proposal(held, beta * np.array(dH[n_fit:]) if held is not None else None,
-                                            beta_mu + 2.0 * math.log(L ** 3 / (st["nsalt"] + 1)),
-                                            args.candidates)
+    oof_corr = float(np.corrcoef(oof, y)[0, 1]) if np.std(oof) > 0 else None
+    note(f"network: out-of-fold correlation {oof_corr}, chose k = {k_sel}, scale = {scale_sel}")
     # timed region, uniform proposal: every trial launched as one HIP graph
     sys_.set_beta_mu(beta_mu)
     sys_.set_proposal(None, 0)
     recs, wall = timed_trials(sys_, torch, args.steps)
+    note(f"uniform: {args.steps} trials in {wall:.1f} s")
     # the learned proposal from the state the uniform run reached (the plain
-    # uniform proposal when the held-out sites favour no weighting)
+    # uniform proposal when the pilot favours no weighting)
     if scale_sel > 0.0:
         sys_.set_proposal(net, k_sel, 10.0, scale_sel)
     lrecs, lwall = timed_trials(sys_, torch, args.learned_steps)
+    note(f"learned: {args.learned_steps} trials in {lwall:.1f} s")
     sys_.set_proposal(None, 0)
+    # both proposals on the state the chains reached, alternating, with
+    # forced moves that leave it unchanged
+    arms = {"uniform": (None, 0, 0.0)}
+    if scale_sel > 0.0:
+        arms["learned"] = (net, k_sel, scale_sel)
+    ab = proposal_ab(sys_, torch, h4d, arms, beta_mu, args.ab_trials) if args.ab_trials > 0 else None
+    if ab is not None:
+        note(f"fixed-state comparison: {args.ab_trials} insertions and deletions per proposal")
     # step-kernel duration: further trials with HIP events around every
     # launch of the fused step kernel (on the library's stream)
     sys_.set_timing(True)
@@ -257,8 +372,9 @@ def bench_single(args, h4d, W, torch):
     timing = sys_.timing()
     sys_.set_timing(False)
     sys_.close()
-    out = summarize(recs, wall, timing, [tarr[q] for q in range(args.timing_trials)],
-                    counted_traffic(TRAFFIC_FILE))
+    net.close()
+    traffic = counted_traffic(TRAFFIC_FILE) if args.workload == "lj32k" else None
+    out = summarize(recs, wall, timing, [tarr[q] for q in range(args.timing_trials)], traffic)
     out["expected_acceptance"] = expected_acceptance(recs)
     out["expected_exchanges_per_s"] = out["expected_acceptance"] * out["trials_per_s"]
     l_acc = sum(r.accepted for r in lrecs)
@@ -267,7 +383,7 @@ def bench_single(args, h4d, W, torch):
     out["learned"] = {
         "proposal": (f"multiple-try, k = {k_sel} candidates weighted by exp({scale_sel} min(s, 10)), s the "
                      "trained network's logit (BF16 matrix-core inference)" if scale_sel > 0.0 else
-                     "uniform: on the held-out pilot sites no (k, scale) beat it"),
+                     "uniform: on the pilot's out-of-fold logits no (k, scale) beat it by the margin"),
         "candidates": k_sel, "weight_scale": scale_sel,
         "choice_estimates": est,
         "value": sum(r.n_atoms * r.n_steps for r in lrecs) / lwall, "unit": "atom-steps/s",
@@ -276,21 +392,24 @@ def bench_single(args, h4d, W, torch):
         "p_acc": l_acc / max(1, len(lrecs)), "p_acc_wilson95": [lo, hi],
         "expected_acceptance": l_exp, "expected_exchanges_per_s": l_exp * len(lrecs) / lwall,
         "gain_expected_exchanges_per_s": (l_exp * len(lrecs) / lwall) / max(1e-300, out["expected_exchanges_per_s"]),
-        "pilot_insertions": args.pilot, "train_steps": steps, "train_s": train_s,
+        "pilot_insertions": args.pilot, "pilot_s": pilot_s, "train_steps": steps, "train_s": train_s,
         "train_loss_first": float(losses[:10].mean()), "train_loss_last": float(losses[-50:].mean()),
-        "holdout_corr_logit_vs_target": holdout_corr,
+        "target": "clip(beta mu + I - beta dH, -100, 10)",
+        "fixed_state_comparison": ab,
+        "fixed_state_gain": (ab["learned"]["expected_exchanges_per_s"] /
+                             max(1e-300, ab["uniform"]["expected_exchanges_per_s"])
+                             if ab is not None and "learned" in ab else 1.0),
+        "out_of_fold_corr_logit_vs_target": oof_corr,
     }
-    config = {
-        "workload": "lj32k: 32,000 LJ ions, density 0.3, 200-step NEMD pair insert/delete, "
-                    "FP32 pair arithmetic / FP64 state, energies and work; value: uniform proposal, "
-                    "'learned': the trained multiple-try proposal from the same state",
-        "n_atoms": w.n, "density": 0.3, "n_steps_per_trial": 200, "dt": 0.005, "w_max": 2.5,
+    config = dict({"workload": desc + "; value: uniform proposal, 'learned': the trained multiple-try "
+                   "proposal from the same state"}, **shape)
+    config.update({
         "beta_mu": beta_mu, "beta_mu_source": "given" if args.beta_mu is not None else
         "Jarzynski estimate from the pilot insertions (equilibrium operating point)",
         "beta_mu_jarzynski": bmu_eq,
         "skin": w.params["skin"], "proposal": "uniform", "parallelism": "single box, one GPU",
-    }
-    base = None if args.no_cpu_baseline else cpu_baseline(w, args.cpu_steps, "the 32,000-ion state")
+    })
+    base = None if args.no_cpu_baseline else cpu_baseline(w, args.cpu_steps, label)
     return out, config, base
 
 
@@ -335,17 +454,22 @@ def bench_batched(args, h4d, W, torch):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=("lj32k", "batched"), default="lj32k")
+    ap.add_argument("--workload", choices=("lj32k", "water", "batched"), default="lj32k")
     ap.add_argument("--steps", type=int, default=None,
                     help="timed exchange trials (lj32k, default 2000) or trials per box (batched, default 20)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed trials first (default 20 / 2)")
     ap.add_argument("--beta-mu", type=float, default=None,
                     help="beta mu (default: lj32k, the Jarzynski estimate from the pilot; batched, -4)")
-    ap.add_argument("--pilot", type=int, default=1200, help="lj32k: pilot insertions for the network")
-    ap.add_argument("--train-steps", type=int, default=0, help="lj32k: Adam steps (0: --train-epochs)")
-    ap.add_argument("--train-epochs", type=int, default=30, help="lj32k: passes over the pilot data")
-    ap.add_argument("--candidates", type=int, default=64, help="lj32k: candidates of the learned proposal")
-    ap.add_argument("--learned-steps", type=int, default=None, help="lj32k: timed learned trials (default steps/2)")
+    ap.add_argument("--pilot", type=int, default=None,
+                    help="single box: pilot insertions for the network (default 1200 / water 1000)")
+    ap.add_argument("--train-epochs", type=int, default=30, help="single box: passes over the pilot data")
+    ap.add_argument("--candidates", type=int, default=64,
+                    help="single box: largest candidate count the learned proposal may choose")
+    ap.add_argument("--learned-steps", type=int, default=None,
+                    help="single box: timed learned trials (default: as many as --steps)")
+    ap.add_argument("--ab-trials", type=int, default=None,
+                    help="single box: forced insertions and deletions per proposal on the final state "
+                         "(default 400 / water 150)")
     ap.add_argument("--timing-trials", type=int, default=None,
                     help="trials run after the timed region with HIP events on the step kernel (20 / 2)")
     ap.add_argument("--cpu-steps", type=int, default=12, help="oracle sample length (NEMD steps)")
@@ -364,14 +488,19 @@ def main():
               "but no multi-GPU path is built", file=sys.stderr)
         sys.exit(2)
     batched = args.workload == "batched"
+    water = args.workload == "water"
     if args.steps is None:
-        args.steps = 20 if batched else 2000
+        args.steps = 20 if batched else (400 if water else 2000)
     if args.warmup is None:
-        args.warmup = 2 if batched else 20
+        args.warmup = 2 if batched else (5 if water else 20)
     if args.timing_trials is None:
-        args.timing_trials = 2 if batched else 20
+        args.timing_trials = 2 if batched else (4 if water else 20)
     if args.learned_steps is None:
-        args.learned_steps = max(1, args.steps // 2)
+        args.learned_steps = args.steps
+    if args.pilot is None:
+        args.pilot = 1000 if water else 1200
+    if args.ab_trials is None:
+        args.ab_trials = 150 if water else 400
     if batched and args.beta_mu is None:
         args.beta_mu = -4.0
 

@@ -73,7 +73,7 @@ extern "C" {
 
 /*
  * Model and protocol.  Types index the per-type tables; pair parameters
- * follow Lorentz-Berthelot mixing (Sec. II E 2).
+ * follow Lorentz-Berthelot mixing (Sec. II D 2).
  *   Lennard-Jones, Eq. (19): truncated and shifted at rc_lj, force not
  *     shifted.
  *   Coulomb: damped shifted force (erfc-screened, real space only; the
@@ -81,7 +81,7 @@ extern "C" {
  *     rc_coul; between a flying and a non-flying atom it is multiplied by
  *     exp(-kappa_sr w) (Eq. 11).
  *   A pair that involves exactly one flying atom uses the 4D distance
- *     sqrt(r^2 + w^2) (Sec. I, Sec. II D); both cutoffs apply to it.
+ *     sqrt(r^2 + w^2) (Sec. I, Sec. II C); both cutoffs apply to it.
  *   w follows Eq. (2): w_max -> 0 for an insertion, 0 -> w_max for a
  *     deletion, in n_steps steps of dt; the flying ions stay fixed in 3D
  *     (trick (i) of Sec. II B).
@@ -276,16 +276,19 @@ int32_t h4d_stream_copy(int64_t bytes, int32_t reps, double *ms);
 
 /*
  * Learned insertion proposal (single-box handles).  A multiple-try form of
- * the uniform pair insertion of Eq. (4), exact for any network: an
- * insertion draws k uniform candidate pair sites (Philox counters
- * (trial, 4, j, 0 / 1)), weighs each by exp(s), s the network's logit of the
- * site's 64 features on the state before the trajectory (log weight
- * weight_scale * min(s, logit_cap)), and flies the pair
- * in at one chosen with probability proportional to its weight (uniform
- * (trial, 5, 0, 0)); ln R of Eqs. (6) gains ln(W/k) - s(chosen).  A deletion
- * weighs the removed pair's site and k - 1 fresh candidates on the state
- * after its trajectory (pair removed) and ln R of Eq. (8) gains
- * s(removed) - ln(W/k).  The factor is reported in h4d_trial.ln_proposal.
+ * the uniform pair insertion of Eq. (4), exact for any network: a bias on
+ * the initial flying-ion positions (the paper notes one would help and
+ * leaves it out, Sec. II B 1) with the ratio corrected in the Rosenbluth
+ * form of its distance bias (Sec. II B 4, Eqs. 15-16).  An insertion draws
+ * k uniform candidate pair sites (Philox counters (trial, 4, j, 0 / 1)),
+ * gives each the log weight lw = weight_scale * min(s, logit_cap), s the
+ * network's logit of the site's 64 features on the state before the
+ * trajectory, and flies the pair in at one chosen with probability
+ * proportional to exp(lw) (uniform (trial, 5, 0, 0)); ln R of Eq. (6)
+ * gains ln(W/k) - lw(chosen), W the sum of the weights.  A deletion weighs
+ * the removed pair's site and k - 1 fresh candidates on the state after
+ * its trajectory (pair removed) and ln R of Eq. (8) gains
+ * lw(removed) - ln(W/k).  The factor is reported in h4d_trial.ln_proposal.
  *
  * Features of a site (31 per ion, then 2 for the pair), from the non-flying
  * atoms within rc = max cutoff, each pair term scaled by beta, clipped to

@@ -9,9 +9,9 @@
  *
  * Physics (one pair i<j, minimum image r_ij):
  *   s^2 = |r_ij|^2 + (w_i - w_j)^2, w = altitude of a flyer, 0 otherwise
- *     (the 4D distance of Sec. I and Sec. II D);
+ *     (the 4D distance of Sec. I and Sec. II C);
  *   truncated and shifted Lennard-Jones, Eq. (19), force not shifted,
- *     Lorentz-Berthelot mixing (Sec. II E 2);
+ *     Lorentz-Berthelot mixing (Sec. II D 2);
  *   damped shifted force Coulomb (Fennell & Gezelter 2006), the
  *     Wolf-family real-space-only electrostatics mentioned in Sec. II B 2,
  *     multiplied by g = exp(-kappa_sr * w) when exactly one of i, j is

@@ -114,14 +114,16 @@ int or_trial(const or_params *p, or_state *s, uint64_t trial, int force_move,
 
 /*
  * Learned proposal (multiple-try form of the uniform pair insertion of
- * Eq. 4).  An insertion draws k uniform candidate pair sites (counters
- * (t, 4, j, 0/1)), weighs them by exp(scale min(logit, cap)) on the state before the
- * trajectory and picks one with probability proportional to its weight
- * (uniform (t, 5, 0, 0)); the ratio gains ln(W/k) - logit(chosen).  A
+ * Eq. 4; a bias on the initial flying-ion positions corrected in the
+ * Rosenbluth form of Sec. II B 4, Eqs. 15-16).  Log weights are
+ * lw = scale min(logit, cap).  An insertion draws k uniform candidate pair
+ * sites (counters (t, 4, j, 0/1)), weighs them by exp(lw) on the state
+ * before the trajectory and picks one with probability proportional to its
+ * weight (uniform (t, 5, 0, 0)); the ratio gains ln(W/k) - lw(chosen).  A
  * deletion weighs the removed pair's site and k - 1 fresh candidates on the
  * state after the trajectory (pair removed); the ratio gains
- * logit(removed) - ln(W/k).  Exact for any weights; k = 1 or equal weights
- * give the uniform proposal.
+ * lw(removed) - ln(W/k).  Exact for any weights; k = 1, scale 0 or equal
+ * weights give the uniform proposal.
  */
 typedef int (*or_logit_fn)(void *ctx, int n, const double *features /* n x 64 */, double *logits /* n */);
 typedef struct {

@@ -1,13 +1,18 @@
 // h4d_learned.hpp -- learned insertion proposal on gfx950.
 //
 // Multiple-try form of the uniform pair insertion of Eq. (4): an insertion
-// draws k uniform candidate pair sites, weighs each by exp(scale min(s, cap)) with s the
-// network's logit of the site's 64 features on the state before the
-// trajectory, and flies the pair in at one chosen with probability
-// proportional to its weight; the Metropolis ratio gains ln(W/k) - s(chosen).
-// A deletion weighs the removed pair's site and k - 1 fresh candidates on the
-// state after its trajectory (pair removed) and gains s(removed) - ln(W/k).
-// Exact for any weights; k = 1 or equal weights is the uniform proposal.
+// draws k uniform candidate pair sites, gives each the log weight
+// scale min(s, cap), s the network's logit of the site's 64 features on the
+// state before the trajectory, and flies the pair in at one chosen with
+// probability proportional to its weight; the Metropolis ratio gains
+// ln(W/k) - (log weight of the chosen site), W the sum of the weights.  A
+// deletion weighs the removed pair's site and k - 1 fresh candidates on the
+// state after its trajectory (pair removed) and gains (log weight of the
+// removed site) - ln(W/k).  This is a bias on the initial positions of the
+// flying ions, the kind the paper leaves unimplemented (Sec. II B 1), with
+// the ratio correction in the Rosenbluth form of its distance bias
+// (Sec. II B 4, Eqs. 15-16).  Exact for any weights; k = 1, scale 0 or
+// equal weights is the uniform proposal.
 //
 // Features are summed in 64-bit fixed point (each FP32 term rounded to a
 // fixed grid), so a site's features -- and its weight -- do not depend on
@@ -343,10 +348,11 @@ __global__ __launch_bounds__(256) void k_mlp_infer_move(KArgs a, LearnArgs l, in
 }
 
 // --------------------------------------------------------------------------
-// The multiple-try step, one thread, FP64, in a fixed order.  Insertion: the
-// first candidate whose running weight exceeds u W (uniform (t, 5, 0, 0));
-// the ghosts move to it; ln q = ln(W/k) - s(chosen).  Deletion:
-// ln q = s(removed) - ln(W/k).  Weights are taken relative to the largest.
+// The multiple-try step, one thread, FP64, in a fixed order, with log
+// weights lw = scale min(s, cap).  Insertion: the first candidate whose
+// running weight exceeds u W (uniform (t, 5, 0, 0)); the ghosts move to it;
+// ln q = ln(W/k) - lw(chosen).  Deletion: ln q = lw(removed) - ln(W/k).
+// Weights are taken relative to the largest.
 // --------------------------------------------------------------------------
 __global__ void k_mtm_select(KArgs a, LearnArgs l, int phase) {
     Ctl *c = a.ctl;

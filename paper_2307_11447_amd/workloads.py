@@ -8,14 +8,14 @@ acceptance rule: only positions, types, tags and parameter values.
 
 Workloads (all cubic periodic boxes):
 
-* ``lj_electrolyte``: the paper's Lennard-Jones ions (Sec. II E 1):
+* ``lj_electrolyte``: the paper's Lennard-Jones ions (Sec. II D 1):
   sigma = epsilon = m = 1, charges +-1, LJ truncated and shifted at
   2.5 sigma, reduced Coulomb with a Bjerrum length of 3 sigma
   (coulomb_k = 3 at kT = 1), damped shifted force with alpha = 0.3 and a
   4 sigma cutoff.  Start: a jittered simple-cubic lattice (nearest
   distance >= 0.9 sigma) with random site occupation and random charges.
 * ``water_nacl``: SPC/E water plus Joung-Cheatham-like Na+/Cl- with
-  Lorentz-Berthelot mixing (Sec. II E 2), real units (kcal/mol, A, fs,
+  Lorentz-Berthelot mixing (Sec. II D 2), real units (kcal/mol, A, fs,
   amu, e), 298 K, rigid waters.
 """
 from __future__ import annotations
