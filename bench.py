@@ -307,8 +307,9 @@ def bench_single(args, h4d, W, torch):
     if args.skin > 0:
         w.params.update(skin=args.skin)
     sys_ = h4d.System.from_workload(w)
-    if args.autotune:
-        sys_.autotune(2)
+    tuned = sys_.autotune(4 if args.workload == "lj32k" else 2) if args.autotune else None
+    if tuned:
+        note(f"autotune: {tuned[0]} lanes per atom, rebuild every {tuned[1]} steps")
     if args.warmup:
         sys_.trials(args.warmup)
     # pilot: forced uniform insertions that are never accepted (beta mu far
@@ -420,8 +421,9 @@ def bench_batched(args, h4d, W, torch):
         if args.skin > 0:
             w.params.update(skin=args.skin)
     bat = h4d.Batch.from_workloads(ws)
-    if args.autotune:
-        bat.autotune(1)
+    tuned = bat.autotune(1) if args.autotune else None
+    if tuned:
+        note(f"autotune: {tuned[0]} lanes per atom, rebuild every {tuned[1]} steps")
     if args.warmup:
         bat.run(args.warmup)
     torch.cuda.synchronize()
@@ -476,7 +478,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rebuild-every", type=int, default=0, help="list rebuild interval (0: library default)")
     ap.add_argument("--lanes", type=int, default=0, help="lanes per atom (0: library default)")
-    ap.add_argument("--autotune", action="store_true", help="pick lanes per atom by timing trials first")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="keep the library's lanes per atom and automatic rebuild interval instead of timing "
+                         "the choices first")
     ap.add_argument("--skin", type=float, default=0.0, help="Verlet skin (0: workload default)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run the stream-copy probe on MIB mebibytes and print its bandwidth")

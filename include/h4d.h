@@ -257,12 +257,19 @@ int32_t h4d_get_timing(h4d_system *sys, h4d_timing *out);
 
 /*
  * Autotuner of the launch shape: runs `trials` trials (per box) with each
- * lanes-per-atom choice (4, 8, 16) of the list traversals, keeps the one
- * with the least wall time per atom-step and returns it in *lanes_out (and
- * that time in *ns_per_atom_step).  The trials are ordinary trials of the
- * handle's chains (they advance the trial counters and the statistics).
+ * lanes-per-atom choice (4, 8, 16) of the list traversals and keeps the one
+ * with the least wall time per atom-step; then, unless the parameters fix
+ * the rebuild interval, times base intervals of 1/4 to 2 times the
+ * automatic one and keeps the best for the handle's life (a trial whose
+ * fast-atom list overflows is still recomputed with a shorter one).
+ * Returns the choices in *lanes_out and *rebuild_out and the best time in
+ * *ns_per_atom_step (each may be NULL).  The trials are ordinary trials of
+ * the handle's chains (they advance the trial counters and the
+ * statistics).  Trajectories depend on the interval only through the
+ * summation order, so a tuned handle is reproducible given its choices.
  */
-int32_t h4d_autotune(h4d_system *sys, int32_t trials, int32_t *lanes_out, double *ns_per_atom_step);
+int32_t h4d_autotune(h4d_system *sys, int32_t trials, int32_t *lanes_out, int32_t *rebuild_out,
+                     double *ns_per_atom_step);
 
 /*
  * Stream-copy probe (no handle needed): copies `bytes` bytes between two

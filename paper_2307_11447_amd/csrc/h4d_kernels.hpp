@@ -463,24 +463,26 @@ __global__ __launch_bounds__(kBlock) void k_list_allpairs(KArgs a, int k, int b0
     }
 }
 
-// Cell form: one block of kListWaves wavefronts per centre cell.  The 27
+// Cell form: `split` blocks of kListWaves wavefronts per centre cell (block
+// s of the cell takes the centre atoms t with (t / kListWaves) % split == s,
+// so that cells with many atoms still give the chip enough blocks).  The 27
 // stencil cells are staged in LDS one z-layer (9 cells) at a time
 // (fixed-point coordinates + working slot, in stencil order); each
-// wavefront takes a share of the centre atoms and tests 64 candidates per
+// wavefront takes its centre atoms in turn and tests 64 candidates per
 // ballot, appending partners in stencil order (a centre atom's running count
 // stays in LDS across the layers).  Dynamic LDS: (9 + 1) * cell_cap * 16 +
 // cell_cap * 4 bytes.  Also records the build positions, clears this cell's
 // count in the other buffer and the box's fast lists.
 constexpr int kListWaves = 8;
 
-__global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int k, int b0, int cb) {
+__global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int k, int b0, int cb, int split) {
     extern __shared__ uint4 lds[];
     __shared__ int cidx[27], cnt27[27], off[10];
     const int cap = a.cell_cap;
     uint4 *cand = lds;                           // 9 * cap staged candidates
     uint4 *ctr = lds + 9 * (size_t)cap;          // cap centre atoms
     int *ccount = reinterpret_cast<int *>(ctr + cap);
-    const int cc = blockIdx.x;
+    const int cc = (int)blockIdx.x / split, part = (int)blockIdx.x % split;
     const int bi = box_of_cell(a, cc);
     const Box &B = a.box[bi];
     Ctl *c = a.ctl + bi;
@@ -494,9 +496,13 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int 
         cidx[t] = c2;
         cnt27[t] = min(a.cell_cnt[cb][c2], cap);
     }
-    if (threadIdx.x == 0 && cc == B.c0) c->nfast[0] = c->nfast[1] = c->nfast[2] = 0;
+    if (threadIdx.x == 0 && cc == B.c0 && part == 0) c->nfast[0] = c->nfast[1] = c->nfast[2] = 0;
     __syncthreads();
     const int mc = cnt27[13];                    // the centre cell is stencil entry 13
+    if (part * kListWaves >= mc) {               // no centre atoms for this block
+        if (part == 0 && threadIdx.x == 0) a.cell_cnt[cb ^ 1][cc] = 0;
+        return;
+    }
     for (int u = threadIdx.x; u < mc; u += blockDim.x) {
         const int j = a.cell_atoms[cb][(size_t)cidx[13] * cap + u];
         const uint4 q = a.fx[b][j];
@@ -526,7 +532,7 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int 
             }
         }
         __syncthreads();
-        for (int t = wave; t < mc; t += kListWaves) {
+        for (int t = part * kListWaves + wave; t < mc; t += split * kListWaves) {
             const uint4 qi = ctr[t];
             const int wi = (int)qi.w;
             const int mi = molecules ? a.wmol[wi] : -1;
@@ -556,6 +562,7 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int 
         __syncthreads();
     }
     for (int t = threadIdx.x; t < mc; t += blockDim.x) {
+        if ((t / kListWaves) % split != part) continue;
         const uint4 qi = ctr[t];
         const int wi = (int)qi.w;
         const int cnt = ccount[t];
@@ -564,7 +571,7 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int 
         unflag_fast(a, b, wi, a.fx[b][wi].w);
         if (cnt > a.nbr_cap) { atomicOr(&c->err, kErrNbr); atomicMax(&c->max_nbr, cnt); }
     }
-    if (threadIdx.x == 0) a.cell_cnt[cb ^ 1][cc] = 0;
+    if (threadIdx.x == 0 && part == 0) a.cell_cnt[cb ^ 1][cc] = 0;
 }
 
 // Cell form for cells too large to stage in LDS: L lanes per atom walk the
@@ -688,27 +695,15 @@ __device__ __forceinline__ void group_force(const KArgs &a, const Box &B, const 
 #pragma unroll
                 for (int u = 0; u < NB; ++u) pair(q[u], k + u < nq && !(q[u].w & kFastBit));
             }
-        } else if (B.use_cells) {
-            const int cx = cell_coord(pi.x, B.L[0], B.ncell[0]);
-            const int cy = cell_coord(pi.y, B.L[1], B.ncell[1]);
-            const int cz = cell_coord(pi.z, B.L[2], B.ncell[2]);
-            for (int t = 0; t < 27; ++t) {
-                const int c2 = stencil_cell(B, cx, cy, cz, t);
-                const int m = min(a.cell_cnt[cl][c2], a.cell_cap);
-                const int *row = a.cell_atoms[cl] + (size_t)c2 * a.cell_cap;
-                for (int u = s; u < m; u += L) {
-                    const int j = row[u];
-                    const uint4 qj = F[j];
-                    pair(qj, j != w && !(qj.w & kFastBit) && !same_mol(j));
-                }
-            }
-        } else {
+        } else if (!B.use_cells) {
             const int j1 = B.a0 + c->n_all;
             for (int j = B.a0 + s; j < j1; j += L) {
                 const uint4 qj = F[j];
                 pair(qj, j != w && !(qj.w & kFastBit) && !same_mol(j));
             }
         }
+        // (cell form: a fast atom's pairs with the cells are summed by its
+        // whole wavefront, fast_atoms_wave)
         for (int q = s; q < nfast; q += L) {
             const int j = flist[q];
             pair(F[j], j != w && !same_mol(j));
@@ -777,6 +772,65 @@ __device__ __forceinline__ void group_force(const KArgs &a, const Box &B, const 
             az += __shfl_xor(az, off, kWave);
         }
         fx = ax; fy = ay; fz = az;
+    }
+}
+
+// FP32 forces on the fast atoms of one wavefront from the 27 cells of the
+// last build (cell form): each fast atom in turn, lowest lane first, with
+// all 64 lanes sharing its candidates (an atom's own L lanes would take
+// 64 / L times as long and hold up the kernel).  Pairs with other fast atoms
+// come from the fast list in group_force.  Every lane of the wavefront
+// calls this; mine marks lane s = 0 of a fast, non-flying, active atom, and
+// that lane's force gains the sum (fixed butterfly order).
+__device__ __forceinline__ void fast_atoms_wave(const KArgs &a, const Box &B, const CoefLds &cf, int b, int cl,
+                                                bool mine, int w, int lane, double wv, double gscr, double &fx,
+                                                double &fy, double &fz) {
+    unsigned long long fm = __ballot(mine);
+    if (fm == 0ull || !B.use_cells) return;
+    const uint4 *F = a.fx[b];
+    const float w2 = (float)(wv * wv), g = (float)gscr;
+    const float sx = B.fx_scale[0], sy = B.fx_scale[1], sz = B.fx_scale[2];
+    while (fm != 0ull) {
+        const int src = __ffsll((long long)fm) - 1;
+        fm &= fm - 1ull;
+        const int wf = __shfl(w, src, kWave);
+        const uint4 qi = F[wf];
+        const double4 pf = a.pos[b][wf];
+        const int mi = (int)qi.w;
+        const PairCoef *crow = cf.c + (mi & kTypeMask) * kMaxTypes;
+        const int own_mol = (mi & kMolBit) ? a.wmol[wf] : -1;
+        const int cx = cell_coord(pf.x, B.L[0], B.ncell[0]);
+        const int cy = cell_coord(pf.y, B.L[1], B.ncell[1]);
+        const int cz = cell_coord(pf.z, B.L[2], B.ncell[2]);
+        float ax = 0.f, ay = 0.f, az = 0.f;
+        for (int t = 0; t < 27; ++t) {
+            const int c2 = stencil_cell(B, cx, cy, cz, t);
+            const int m = min(a.cell_cnt[cl][c2], a.cell_cap);
+            const int *row = a.cell_atoms[cl] + (size_t)c2 * a.cell_cap;
+            for (int u = lane; u < m; u += kWave) {
+                const int j = row[u];
+                const uint4 qj = F[j];
+                const bool valid = j != wf && !(qj.w & kFastBit) && !(own_mol >= 0 && a.wmol[j] == own_mol);
+                const float dx = (float)(int)(qi.x - qj.x) * sx;
+                const float dy = (float)(int)(qi.y - qj.y) * sy;
+                const float dz = (float)(int)(qi.z - qj.z) * sz;
+                const int mj = (int)qj.w;
+                const bool fj = (mj & kFlyBit) != 0;
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                const float s2 = fj ? r2 + w2 : r2;
+                const bool ok = valid && s2 < a.G.rc_max2f;
+                const float fs = pair_fs_f32(a.G, crow[mj & kTypeMask], ok ? s2 : a.G.rc_max2f, fj ? g : 1.0f);
+                const float f = ok ? fs : 0.0f;
+                ax += f * dx; ay += f * dy; az += f * dz;
+            }
+        }
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+            ax += __shfl_xor(ax, off, kWave);
+            ay += __shfl_xor(ay, off, kWave);
+            az += __shfl_xor(az, off, kWave);
+        }
+        if (lane == src) { fx += ax; fy += ay; fz += az; }
     }
 }
 
@@ -908,6 +962,8 @@ __global__ __launch_bounds__(kBlock) void k_step(KArgs a, int k, int b, int bin,
     const double gscr = exp(-a.G.kappa * wv);
     double fx = 0.0, fy = 0.0, fz = 0.0;
     if (act && !fly) group_force<PREC, L>(a, B, c, cf, b, cl, wc, s, pi, mi, wv, gscr, flist, nfast, fx, fy, fz);
+    if (PREC == 1) fast_atoms_wave(a, B, cf, b, cl, act && !fly && s == 0 && (mi & kFastBit), wc, lane, wv, gscr,
+                                   fx, fy, fz);
     if (!act || s != 0) return;
     if (mi & kMolBit) {   // rigid water: integrated by k_settle
         a.fw[wc] = make_double4(fx, fy, fz, 0.0);
@@ -963,6 +1019,8 @@ __global__ __launch_bounds__(kBlock) void k_forces(KArgs a, double wv) {
     double fx = 0.0, fy = 0.0, fz = 0.0;
     if (act && !(mi & kFlyBit))
         group_force<PREC, L>(a, B, c, cf, 0, 0, wc, s, pi, mi, wv, exp(-a.G.kappa * wv), a.fast, 0, fx, fy, fz);
+    if (PREC == 1) fast_atoms_wave(a, B, cf, 0, 0, act && !(mi & kFlyBit) && s == 0 && (mi & kFastBit), wc, lane, wv,
+                                   exp(-a.G.kappa * wv), fx, fy, fz);
     if (act && s == 0) a.force[a.perm[wc]] = make_double4(fx, fy, fz, 0.0);
 }
 

@@ -56,6 +56,7 @@ struct h4d_system {
     int n_mol = 0;
     int rebuild_every = 1;
     int clean_trials = 0;
+    bool interval_tuned = false;   // the autotuner fixed the base interval
     int partial_blocks = 0;
     TrialRec *h_rec = nullptr;  // per box (pinned)
     Ctl *h_ctl = nullptr;       // per box (pinned)
@@ -295,12 +296,23 @@ size_t list_cells_lds(const h4d_system *s) {
     return (size_t)s->a.cell_cap * (10 * sizeof(uint4) + sizeof(int));
 }
 
+// blocks per centre cell of the cell-form list build: enough blocks for
+// every CU (about 2048 in all), with at least two centre atoms of a full
+// cell per wavefront
+int list_split(const h4d_system *s) {
+    const int want = (2048 + s->a.ncell_total - 1) / s->a.ncell_total;
+    const int most = std::max(1, s->a.cell_cap / (2 * kListWaves));
+    return std::max(1, std::min({want, most, 16}));
+}
+
 // list build; k and b as in list_wanted / buf_of
 void launch_list(h4d_system *s, int k, int b, int cb, hipStream_t st) {
     KArgs &a = s->a;
-    if (s->cells && list_cells_lds(s) <= 56 * 1024)
-        hipLaunchKernelGGL(k_list_cells, dim3(a.ncell_total), dim3(kListWaves * kWave), list_cells_lds(s), st, a,
-                           k, b, cb);
+    if (s->cells && list_cells_lds(s) <= 56 * 1024) {
+        const int split = list_split(s);
+        hipLaunchKernelGGL(k_list_cells, dim3(a.ncell_total * split), dim3(kListWaves * kWave), list_cells_lds(s),
+                           st, a, k, b, cb, split);
+    }
     else if (s->cells)
         hipLaunchKernelGGL(k_list_lanes, dim3(a.step_blocks), dim3(kBlock), 0, st, a, k, b, cb);
     else
@@ -590,7 +602,7 @@ void account(h4d_system *s, int b, const h4d_trial &r) {
 // automatic rebuild interval: lengthen it after a run of rounds whose fast
 // lists stayed short (a few percent of their capacity)
 void adapt_interval(h4d_system *s) {
-    if (s->p.rebuild_every != 0) return;
+    if (s->p.rebuild_every != 0 || s->interval_tuned) return;
     int mf = 0;
     for (int b = 0; b < s->nbox; ++b) mf = std::max(mf, s->h_ctl[b].max_fast);
     if (mf <= kFastCap / 16) {
@@ -1111,38 +1123,76 @@ int32_t h4d_get_timing(h4d_system *s, h4d_timing *out) {
     return H4D_OK;
 }
 
-int32_t h4d_autotune(h4d_system *s, int32_t trials, int32_t *lanes_out, double *ns_per_atom_step) {
+}  // extern "C"
+
+namespace {
+
+// Wall time per atom-step of `trials` trials (per box) with the current
+// launch shape, after one untimed round that captures its graph.
+int time_shape(h4d_system *s, int trials, std::vector<h4d_trial> &recs, double *sec_per_atom_step) {
+    int rc;
+    if ((rc = s->nbox == 1 ? run_one(s, 0, recs.data()) : run_batch(s, 1, 0, recs.data()))) return rc;
+    HIPC(hipStreamSynchronize(s->stream));
+    const auto t0 = std::chrono::steady_clock::now();
+    if (s->nbox == 1) {
+        for (int t = 0; t < trials && !rc; ++t) rc = run_one(s, 0, recs.data() + t);
+    } else {
+        rc = run_batch(s, trials, 0, recs.data());
+    }
+    if (rc) return rc;
+    HIPC(hipStreamSynchronize(s->stream));
+    const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    double atom_steps = 0.0;
+    for (const h4d_trial &r : recs) atom_steps += (double)r.n_atoms * (double)r.n_steps;
+    *sec_per_atom_step = atom_steps > 0.0 ? sec / atom_steps : sec;
+    return H4D_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t h4d_autotune(h4d_system *s, int32_t trials, int32_t *lanes_out, int32_t *rebuild_out,
+                     double *ns_per_atom_step) {
     if (!s || trials < 1) return fail(H4D_EINVAL, "null handle or trials < 1");
     const int cand[3] = {4, 8, 16};
     int best = s->a.lanes;
     double best_t = 0.0;
     std::vector<h4d_trial> recs((size_t)trials * s->nbox);
+    int rc;
     for (int q = 0; q < 3; ++q) {
         set_lanes(s, cand[q]);
         s->drop_graphs();
-        int rc;
-        // one untimed round captures the graph of this shape
-        if ((rc = s->nbox == 1 ? run_one(s, 0, recs.data()) : run_batch(s, 1, 0, recs.data()))) return rc;
-        HIPC(hipStreamSynchronize(s->stream));
-        const auto t0 = std::chrono::steady_clock::now();
-        if (s->nbox == 1) {
-            for (int t = 0; t < trials && !rc; ++t) rc = run_one(s, 0, recs.data() + t);
-        } else {
-            rc = run_batch(s, trials, 0, recs.data());
-        }
-        if (rc) return rc;
-        HIPC(hipStreamSynchronize(s->stream));
-        const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        double atom_steps = 0.0;
-        for (const h4d_trial &r : recs) atom_steps += (double)r.n_atoms * (double)r.n_steps;
-        const double t = atom_steps > 0.0 ? sec / atom_steps : sec;
+        double t = 0.0;
+        if ((rc = time_shape(s, trials, recs, &t))) return rc;
         if (q == 0 || t < best_t) { best_t = t; best = cand[q]; }
     }
     set_lanes(s, best);
     s->drop_graphs();
-    int rc = h4d_build_neighbors(s);
-    if (rc) return rc;
+    // the base rebuild interval (unless the parameters fix it): multiples of
+    // the automatic one, each timed; the best is kept for the handle's life
+    if (s->p.rebuild_every == 0) {
+        const int m0 = std::max(1, s->rebuild_every);
+        std::vector<int> ms;
+        for (int num : {1, 2, 3, 4, 6, 8})
+            for (int m : {std::max(1, (m0 * num) / 4)})
+                if (std::find(ms.begin(), ms.end(), m) == ms.end()) ms.push_back(m);
+        int best_m = m0;
+        double best_mt = 0.0;
+        s->interval_tuned = true;
+        for (size_t q = 0; q < ms.size(); ++q) {
+            s->rebuild_every = ms[q];
+            double t = 0.0;
+            if ((rc = time_shape(s, trials, recs, &t))) return rc;
+            if (q == 0 || t < best_mt) { best_mt = t; best_m = ms[q]; }
+        }
+        s->rebuild_every = best_m;
+        best_t = best_mt;
+    }
+    s->drop_graphs();
+    if ((rc = h4d_build_neighbors(s))) return rc;
     if (lanes_out) *lanes_out = best;
+    if (rebuild_out) *rebuild_out = s->rebuild_every;
     if (ns_per_atom_step) *ns_per_atom_step = best_t * 1e9;
     return H4D_OK;
 }

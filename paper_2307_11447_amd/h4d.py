@@ -126,7 +126,7 @@ def lib() -> C.CDLL:
                                         C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int32),
                                         C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
         L.h4d_box_observables.argtypes = [vp, C.c_int32, C.POINTER(Observables)]
-        L.h4d_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double)]
+        L.h4d_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double)]
         fp, dp = C.POINTER(C.c_float), C.POINTER(C.c_double)
         L.h4d_mlp_create.argtypes = [C.c_uint64, vp, C.POINTER(vp)]
         L.h4d_mlp_destroy.argtypes = [vp]
@@ -315,10 +315,13 @@ class _Handle:
         return t.as_dict()
 
     def autotune(self, trials: int = 2):
+        """Lanes per atom and base rebuild interval chosen by timing
+        trials; returns (lanes, rebuild_every, ns per atom-step)."""
         lanes = C.c_int32()
+        every = C.c_int32()
         ns = C.c_double()
-        _check(lib().h4d_autotune(self._h, trials, C.byref(lanes), C.byref(ns)))
-        return lanes.value, ns.value
+        _check(lib().h4d_autotune(self._h, trials, C.byref(lanes), C.byref(every), C.byref(ns)))
+        return lanes.value, every.value, ns.value
 
     def box_state(self, box: int) -> dict:
         return _state_of(self._h, box)

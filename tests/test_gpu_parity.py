@@ -188,6 +188,33 @@ def test_fp64_trials_match_oracle_sequence():
     g.close()
 
 
+def test_autotuned_handle_matches_oracle():
+    """The autotuner picks lanes per atom and the base rebuild interval by
+    timing ordinary trials; the trials after it still follow the oracle
+    (FP64, the same tolerances as the untuned sequence)."""
+    say("case autotune lj500 fp64, then 12 trials against the oracle")
+    w = W.config_lj_500()
+    w.params.update(beta_mu=6.0)
+    g = h4d.System.from_workload(w)
+    lanes, every, ns = g.autotune(1)
+    say(f"   autotune: {lanes} lanes per atom, rebuild every {every} steps, {ns:.3f} ns per atom-step")
+    assert lanes in (4, 8, 16) and every >= 1 and ns > 0.0
+    st = g.state()
+    o = O.OracleSystem(w.params, st["x"], st["type"], st["mol"], st["tag"], st["nsalt"], cap=st["n"] + 200)
+    rg = g.trial()
+    t0 = rg["trial"]
+    assert t0 >= 8                   # 3 lane choices and at least 1 interval, 2 trials each
+    for t in range(t0, t0 + 12):
+        ro = o.trial(t)
+        assert rg["trial"] == t and rg["move"] == ro["move"] and rg["flags"] & 0x3 == ro["flags"]
+        if not ro["flags"]:
+            for key in ("dH", "W_prot", "E_switch", "H0"):
+                assert rel_close(rg[key], ro[key], 1e-6), (t, key, rg[key], ro[key])
+        assert rg["accepted"] == ro["accepted"], (t, rg, ro)
+        rg = g.trial()
+    g.close()
+
+
 def sync_oracle_from_gpu(o, st):
     n = st["n"]
     o.x[:n] = st["x"]; o.type[:n] = st["type"]; o.mol[:n] = st["mol"]; o.tag[:n] = st["tag"]
