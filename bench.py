@@ -270,7 +270,32 @@ def proposal_ab(sys_, torch, h4d, arms, beta_mu, n_each, block=50):
         res[name] = {"p_insert": p_ins, "p_delete": p_del, "trials_per_s": rate,
                      "expected_exchanges_per_s": 0.5 * (p_ins + p_del) * rate,
                      "insertions": len(o["ins"]), "deletions": len(o["del"])}
+    if "uniform" in out and "learned" in out:
+        res["gain"], res["gain_bootstrap90"] = ab_gain(out["uniform"], out["learned"])
     return res
+
+
+def ab_gain(u, l, reps=2000, seed=11):
+    """Ratio of expected exchanges per second (learned over uniform) and its
+    90 % bootstrap interval (moves resampled within each arm and kind)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    rate_u, rate_l = u["n"] / u["s"], l["n"] / l["s"]
+
+    def ex(o, rate, pick):
+        return 0.5 * (np.mean(pick(o["ins"])) + np.mean(pick(o["del"]))) * rate
+
+    ident = np.asarray
+    g = ex(l, rate_l, ident) / max(1e-300, ex(u, rate_u, ident))
+    boot = []
+    for _ in range(reps):
+        def res(x):
+            x = np.asarray(x)
+            return x[rng.integers(0, len(x), len(x))]
+        den = ex(u, rate_u, res)
+        boot.append(ex(l, rate_l, res) / den if den > 0 else float("inf"))
+    lo, hi = np.percentile(boot, [5, 95])
+    return float(g), [float(lo), float(hi)]
 
 
 def timed_trials(sys_, torch, n):
@@ -338,13 +363,14 @@ def bench_single(args, h4d, W, torch):
     X, bdH = X[ok], bdH[ok]
     y = np.clip(c - bdH, -100.0, 10.0).astype(np.float32)
     t0 = time.perf_counter()
-    oof = out_of_fold(h4d, X, y, args.train_epochs)
+    # (too small a pilot for cross validation keeps the uniform proposal)
+    oof = out_of_fold(h4d, X, y, args.train_epochs) if len(X) >= 40 else None
     k_sel, scale_sel, est = choose_proposal(oof, bdH, c, ks=tuple(k for k in (4, 8, 16, 32, 64)
                                                                    if k <= args.candidates))
     net, steps, losses = train_network(h4d, X, y, args.train_epochs)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
-    oof_corr = float(np.corrcoef(oof, y)[0, 1]) if np.std(oof) > 0 else None
+    oof_corr = float(np.corrcoef(oof, y)[0, 1]) if oof is not None and np.std(oof) > 0 else None
     note(f"network: out-of-fold correlation {oof_corr}, chose k = {k_sel}, scale = {scale_sel}")
     # timed region, uniform proposal: every trial launched as one HIP graph
     sys_.set_beta_mu(beta_mu)
@@ -397,9 +423,8 @@ def bench_single(args, h4d, W, torch):
         "train_loss_first": float(losses[:10].mean()), "train_loss_last": float(losses[-50:].mean()),
         "target": "clip(beta mu + I - beta dH, -100, 10)",
         "fixed_state_comparison": ab,
-        "fixed_state_gain": (ab["learned"]["expected_exchanges_per_s"] /
-                             max(1e-300, ab["uniform"]["expected_exchanges_per_s"])
-                             if ab is not None and "learned" in ab else 1.0),
+        "fixed_state_gain": ab.get("gain", 1.0) if ab is not None else None,
+        "fixed_state_gain_bootstrap90": ab.get("gain_bootstrap90") if ab is not None else None,
         "out_of_fold_corr_logit_vs_target": oof_corr,
     }
     config = dict({"workload": desc + "; value: uniform proposal, 'learned': the trained multiple-try "
@@ -471,7 +496,7 @@ def main():
                     help="single box: timed learned trials (default: as many as --steps)")
     ap.add_argument("--ab-trials", type=int, default=None,
                     help="single box: forced insertions and deletions per proposal on the final state "
-                         "(default 400 / water 150)")
+                         "(default 400 / water 600)")
     ap.add_argument("--timing-trials", type=int, default=None,
                     help="trials run after the timed region with HIP events on the step kernel (20 / 2)")
     ap.add_argument("--cpu-steps", type=int, default=12, help="oracle sample length (NEMD steps)")
@@ -504,7 +529,7 @@ def main():
     if args.pilot is None:
         args.pilot = 1000 if water else 1200
     if args.ab_trials is None:
-        args.ab_trials = 150 if water else 400
+        args.ab_trials = 600 if water else 400
     if batched and args.beta_mu is None:
         args.beta_mu = -4.0
 

@@ -258,7 +258,8 @@ int32_t h4d_get_timing(h4d_system *sys, h4d_timing *out);
 /*
  * Autotuner of the launch shape: runs `trials` trials (per box) with each
  * lanes-per-atom choice (4, 8, 16) of the list traversals and keeps the one
- * with the least wall time per atom-step; then, unless the parameters fix
+ * with the least wall time per atom-step; then the number of blocks that
+ * share a cell in the list build (1 to 16); then, unless the parameters fix
  * the rebuild interval, times base intervals of 1/4 to 2 times the
  * automatic one and keeps the best for the handle's life (a trial whose
  * fast-atom list overflows is still recomputed with a shorter one).

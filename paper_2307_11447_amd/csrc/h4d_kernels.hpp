@@ -469,18 +469,21 @@ __global__ __launch_bounds__(kBlock) void k_list_allpairs(KArgs a, int k, int b0
 // stencil cells are staged in LDS one z-layer (9 cells) at a time
 // (fixed-point coordinates + working slot, in stencil order); each
 // wavefront takes its centre atoms in turn and tests 64 candidates per
-// ballot, appending partners in stencil order (a centre atom's running count
-// stays in LDS across the layers).  Dynamic LDS: (9 + 1) * cell_cap * 16 +
+// ballot (a layer is padded to whole wavefronts with entries that never
+// match), appending partners in stencil order (a centre atom's running count
+// stays in LDS across the layers).  MOL: rigid molecules present (pairs
+// within a molecule are left out).  Dynamic LDS: (10 * cell_cap + 64) * 16 +
 // cell_cap * 4 bytes.  Also records the build positions, clears this cell's
 // count in the other buffer and the box's fast lists.
 constexpr int kListWaves = 8;
 
+template <bool MOL>
 __global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int k, int b0, int cb, int split) {
     extern __shared__ uint4 lds[];
     __shared__ int cidx[27], cnt27[27], off[10];
     const int cap = a.cell_cap;
-    uint4 *cand = lds;                           // 9 * cap staged candidates
-    uint4 *ctr = lds + 9 * (size_t)cap;          // cap centre atoms
+    uint4 *cand = lds;                           // 9 * cap + 64 staged candidates
+    uint4 *ctr = lds + 9 * (size_t)cap + kWave;  // cap centre atoms
     int *ccount = reinterpret_cast<int *>(ctr + cap);
     const int cc = (int)blockIdx.x / split, part = (int)blockIdx.x % split;
     const int bi = box_of_cell(a, cc);
@@ -513,7 +516,7 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int 
     const float rl2 = (float)a.G.rlist2 * 1.00001f;
     const float sx = B.fx_scale[0], sy = B.fx_scale[1], sz = B.fx_scale[2];
     const unsigned long long below = (1ull << lane) - 1ull;
-    const bool molecules = a.G.water != 0;
+    const int ll = a.lanes_log2, lmask = (1 << ll) - 1;
     for (int layer = 0; layer < 3; ++layer) {
         if (threadIdx.x == 0) {
             int run = 0;
@@ -531,30 +534,27 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int 
                 cand[off[t] + u] = make_uint4(q.x, q.y, q.z, (unsigned)j);
             }
         }
+        // pad to whole wavefronts with entries that never match (slot -1)
+        if (threadIdx.x < kWave) cand[off[9] + threadIdx.x] = make_uint4(0u, 0u, 0u, 0xffffffffu);
         __syncthreads();
         for (int t = part * kListWaves + wave; t < mc; t += split * kListWaves) {
             const uint4 qi = ctr[t];
             const int wi = (int)qi.w;
-            const int mi = molecules ? a.wmol[wi] : -1;
+            const int mi = MOL ? a.wmol[wi] : -1;
             int cnt = ccount[t];
+            int *dst = a.nbr + nbr_slot(a, wi, 0);
+#pragma unroll 2
             for (int base = 0; base < total; base += kWave) {
-                const int u = base + lane;
-                bool acc = false;
-                int j = 0;
-                if (u < total) {
-                    const uint4 qj = cand[u];
-                    j = (int)qj.w;
-                    const float dx = (float)(int)(qi.x - qj.x) * sx;
-                    const float dy = (float)(int)(qi.y - qj.y) * sy;
-                    const float dz = (float)(int)(qi.z - qj.z) * sz;
-                    acc = dx * dx + dy * dy + dz * dz < rl2 && j != wi;
-                    if (acc && mi >= 0 && a.wmol[j] == mi) acc = false;
-                }
+                const uint4 qj = cand[base + lane];
+                const int j = (int)qj.w;
+                const float dx = (float)(int)(qi.x - qj.x) * sx;
+                const float dy = (float)(int)(qi.y - qj.y) * sy;
+                const float dz = (float)(int)(qi.z - qj.z) * sz;
+                bool acc = dx * dx + dy * dy + dz * dz < rl2 && j != wi && j >= 0;
+                if (MOL && acc && mi >= 0 && a.wmol[j] == mi) acc = false;   // ions carry no molecule (-1)
                 const unsigned long long msk = __ballot(acc);
-                if (acc) {
-                    const int q = cnt + __popcll(msk & below);
-                    if (q < a.nbr_cap) a.nbr[nbr_slot(a, wi, q)] = j;
-                }
+                const int q = cnt + __popcll(msk & below);
+                if (acc && q < a.nbr_cap) dst[((q >> ll) << 6) + (q & lmask)] = j;
                 cnt += __popcll(msk);
             }
             if (lane == 0) ccount[t] = cnt;
@@ -676,7 +676,7 @@ __device__ __forceinline__ void group_force(const KArgs &a, const Box &B, const 
         if (!own_fast) {
             // batches of NB neighbours: the list indices of the next batch
             // load while this batch's records are gathered
-            constexpr int NB = 8;
+            constexpr int NB = 4;
             const int nn = a.nnbr[w];
             const int *base = a.nbr + ((size_t)(w / A) * (size_t)(a.nbr_cap / L)) * kWave + (size_t)(w % A) * L + s;
             const int nq = nn > s ? (nn - s + L - 1) / L : 0;

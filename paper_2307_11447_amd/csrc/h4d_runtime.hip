@@ -57,6 +57,7 @@ struct h4d_system {
     int rebuild_every = 1;
     int clean_trials = 0;
     bool interval_tuned = false;   // the autotuner fixed the base interval
+    int list_split = 0;            // list-build blocks per cell (0: automatic)
     int partial_blocks = 0;
     TrialRec *h_rec = nullptr;  // per box (pinned)
     Ctl *h_ctl = nullptr;       // per box (pinned)
@@ -293,16 +294,17 @@ void set_lanes(h4d_system *s, int L) {
 int slot_blocks(const h4d_system *s) { return s->a.slots / kBlock; }
 
 size_t list_cells_lds(const h4d_system *s) {
-    return (size_t)s->a.cell_cap * (10 * sizeof(uint4) + sizeof(int));
+    return (size_t)s->a.cell_cap * (10 * sizeof(uint4) + sizeof(int)) + kWave * sizeof(uint4);
 }
 
-// blocks per centre cell of the cell-form list build: enough blocks for
-// every CU (about 2048 in all), with at least two centre atoms of a full
-// cell per wavefront
+// blocks per centre cell of the cell-form list build: the autotuner's
+// choice, else enough blocks for two per CU (about 512 in all); at most 16
+// and at least two centre atoms of a full cell per wavefront
 int list_split(const h4d_system *s) {
-    const int want = (2048 + s->a.ncell_total - 1) / s->a.ncell_total;
-    const int most = std::max(1, s->a.cell_cap / (2 * kListWaves));
-    return std::max(1, std::min({want, most, 16}));
+    const int most = std::max(1, std::min(16, s->a.cell_cap / (2 * kListWaves)));
+    if (s->list_split > 0) return std::min(s->list_split, most);
+    const int want = (512 + s->a.ncell_total - 1) / s->a.ncell_total;
+    return std::max(1, std::min(want, most));
 }
 
 // list build; k and b as in list_wanted / buf_of
@@ -310,8 +312,12 @@ void launch_list(h4d_system *s, int k, int b, int cb, hipStream_t st) {
     KArgs &a = s->a;
     if (s->cells && list_cells_lds(s) <= 56 * 1024) {
         const int split = list_split(s);
-        hipLaunchKernelGGL(k_list_cells, dim3(a.ncell_total * split), dim3(kListWaves * kWave), list_cells_lds(s),
-                           st, a, k, b, cb, split);
+        if (a.G.water)
+            hipLaunchKernelGGL(k_list_cells<true>, dim3(a.ncell_total * split), dim3(kListWaves * kWave),
+                               list_cells_lds(s), st, a, k, b, cb, split);
+        else
+            hipLaunchKernelGGL(k_list_cells<false>, dim3(a.ncell_total * split), dim3(kListWaves * kWave),
+                               list_cells_lds(s), st, a, k, b, cb, split);
     }
     else if (s->cells)
         hipLaunchKernelGGL(k_list_lanes, dim3(a.step_blocks), dim3(kBlock), 0, st, a, k, b, cb);
@@ -1169,6 +1175,24 @@ int32_t h4d_autotune(h4d_system *s, int32_t trials, int32_t *lanes_out, int32_t 
     }
     set_lanes(s, best);
     s->drop_graphs();
+    // blocks per cell of the list build (cell form only)
+    if (s->cells && list_cells_lds(s) <= 56 * 1024) {
+        const int most = std::max(1, std::min(16, s->a.cell_cap / (2 * kListWaves)));
+        int best_split = list_split(s);
+        double best_st = 0.0;
+        bool first = true;
+        for (int sp : {1, 2, 4, 8, 16}) {
+            if (sp > most) break;
+            s->list_split = sp;
+            s->drop_graphs();
+            double t = 0.0;
+            if ((rc = time_shape(s, trials, recs, &t))) return rc;
+            if (first || t < best_st) { best_st = t; best_split = sp; first = false; }
+        }
+        s->list_split = best_split;
+        s->drop_graphs();
+        if (!first) best_t = best_st;
+    }
     // the base rebuild interval (unless the parameters fix it): multiples of
     // the automatic one, each timed; the best is kept for the handle's life
     if (s->p.rebuild_every == 0) {
