@@ -102,10 +102,11 @@ def step_bytes_per_atom(mean_nbr):
     return 4.0 * mean_nbr + 184.0
 
 
-def summarize(recs, wall, timing, timing_recs, traffic_bytes):
+def summarize(recs, wall, timing, timing_recs, traffic_bytes, atom_launches=None):
     """Throughput, acceptance and the step kernel's roofline from trial
     records (recs: the timed trials; timing_recs: the trials run with HIP
-    events around every step launch)."""
+    events around every step launch, or atom_launches: the atoms those
+    launches integrated, summed over launches)."""
     n = len(recs)
     atom_steps = sum(r.n_atoms * r.n_steps for r in recs)
     acc = sum(r.accepted for r in recs)
@@ -116,7 +117,8 @@ def summarize(recs, wall, timing, timing_recs, traffic_bytes):
     mean_nbr = timing["mean_nbr"]
     bpa = step_bytes_per_atom(mean_nbr)
     # every step launch k = 0..N_f of a trial touches each of its atoms once
-    atom_launches = sum(r.n_atoms * (r.n_steps + 1) for r in timing_recs)
+    if atom_launches is None:
+        atom_launches = sum(r.n_atoms * (r.n_steps + 1) for r in timing_recs)
     step_s = timing["step_ms"] * 1e-3
     launches = max(1, timing["step_launches"])
     achieved = bpa * atom_launches / step_s / 1e9
@@ -320,6 +322,45 @@ SINGLE = {
 }
 
 
+def uniform_leg_speculative(args, h4d, torch, w, beta_mu):
+    """The uniform chain run speculatively on args.replicas copies of its
+    state (the records equal a one-by-one run of the same trials): timed
+    trials, then timing trials with HIP events on the step kernel.  Returns
+    (records, wall, timing, atom launches of the timing trials, info)."""
+    spec = h4d.Speculative.from_workload(w, args.replicas, beta_mu=beta_mu)
+    tuned = spec.autotune(2) if args.autotune else None
+    if tuned:
+        note(f"speculative autotune: {tuned[0]} lanes per atom, rebuild every {tuned[1]} steps")
+    if args.warmup:
+        spec.trials(args.warmup)
+    r0 = spec.rounds
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    arr = spec.trials(args.steps, as_array=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    rounds = spec.rounds - r0
+    recs = [arr[q] for q in range(args.steps)]
+    note(f"uniform, speculative: {args.steps} trials in {rounds} rounds of {args.replicas} replicas, {wall:.1f} s")
+    spec.set_timing(True)
+    r1 = spec.rounds
+    tarr = spec.trials(args.timing_trials, as_array=True)
+    timing = spec.timing()
+    spec.set_timing(False)
+    t_rounds = spec.rounds - r1
+    spec.close()
+    # every replica integrates its trial in every round
+    n_mean = sum(tarr[q].n_atoms for q in range(args.timing_trials)) / max(1, args.timing_trials)
+    nf = max(tarr[q].n_steps for q in range(args.timing_trials)) if args.timing_trials else 0
+    atom_launches = t_rounds * args.replicas * n_mean * (nf + 1)
+    info = {"mode": "speculative", "replicas": args.replicas, "rounds": rounds,
+            "trials_per_round": args.steps / max(1, rounds),
+            "note": "replicas of the state run the next trials side by side; the chain keeps them up to the "
+                    "first accepted one (the records equal a one-by-one run); value counts the chain's "
+                    "trials only"}
+    return recs, wall, timing, atom_launches, info
+
+
 def bench_single(args, h4d, W, torch):
     import numpy as np
     maker, desc, label, shape = SINGLE[args.workload]
@@ -331,6 +372,7 @@ def bench_single(args, h4d, W, torch):
         w.params.update(lanes_per_atom=args.lanes)
     if args.skin > 0:
         w.params.update(skin=args.skin)
+    speculative = args.replicas > 1 and args.workload != "water"
     sys_ = h4d.System.from_workload(w)
     tuned = sys_.autotune(4 if args.workload == "lj32k" else 2) if args.autotune else None
     if tuned:
@@ -352,31 +394,39 @@ def bench_single(args, h4d, W, torch):
     st = sys_.state()
     beta = 1.0 / w.params["kT"]
     L = w.params["box"][0]
-    bmu_eq = jarzynski_beta_mu(dH, beta, L ** 3, st["nsalt"])
+    bmu_eq = jarzynski_beta_mu(dH, beta, L ** 3, st["nsalt"]) if dH else None
+    if args.beta_mu is None and bmu_eq is None:
+        raise SystemExit("bench.py: --pilot 0 needs --beta-mu")
     beta_mu = args.beta_mu if args.beta_mu is not None else bmu_eq
     c = beta_mu + 2.0 * math.log(L ** 3 / (st["nsalt"] + 1))
     # the network learns the clipped log insertion ratio c - beta dH of the
     # pilot sites (GPU, FP32); out-of-fold logits choose k and the scale
-    X = np.array(feats, dtype=np.float32)
-    bdH = beta * np.array(dH)
-    ok = np.isfinite(bdH)
-    X, bdH = X[ok], bdH[ok]
-    y = np.clip(c - bdH, -100.0, 10.0).astype(np.float32)
-    t0 = time.perf_counter()
-    # (too small a pilot for cross validation keeps the uniform proposal)
-    oof = out_of_fold(h4d, X, y, args.train_epochs) if len(X) >= 40 else None
-    k_sel, scale_sel, est = choose_proposal(oof, bdH, c, ks=tuple(k for k in (4, 8, 16, 32, 64)
-                                                                   if k <= args.candidates))
-    net, steps, losses = train_network(h4d, X, y, args.train_epochs)
-    torch.cuda.synchronize()
-    train_s = time.perf_counter() - t0
-    oof_corr = float(np.corrcoef(oof, y)[0, 1]) if oof is not None and np.std(oof) > 0 else None
-    note(f"network: out-of-fold correlation {oof_corr}, chose k = {k_sel}, scale = {scale_sel}")
-    # timed region, uniform proposal: every trial launched as one HIP graph
+    # (no pilot, or one too small for cross validation, keeps the uniform
+    # proposal)
+    net = None
+    k_sel, scale_sel, est, oof_corr, steps, train_s, losses = 1, 0.0, {}, None, 0, 0.0, np.zeros(1)
+    if len(feats) > 0:
+        X = np.array(feats, dtype=np.float32)
+        bdH = beta * np.array(dH)
+        ok = np.isfinite(bdH)
+        X, bdH = X[ok], bdH[ok]
+        y = np.clip(c - bdH, -100.0, 10.0).astype(np.float32)
+        t0 = time.perf_counter()
+        oof = out_of_fold(h4d, X, y, args.train_epochs) if len(X) >= 40 else None
+        k_sel, scale_sel, est = choose_proposal(oof, bdH, c, ks=tuple(k for k in (4, 8, 16, 32, 64)
+                                                                       if k <= args.candidates))
+        net, steps, losses = train_network(h4d, X, y, args.train_epochs)
+        torch.cuda.synchronize()
+        train_s = time.perf_counter() - t0
+        oof_corr = float(np.corrcoef(oof, y)[0, 1]) if oof is not None and np.std(oof) > 0 else None
+        note(f"network: out-of-fold correlation {oof_corr}, chose k = {k_sel}, scale = {scale_sel}")
+    # uniform proposal, one trial after another on the single box (the
+    # reference of the speculative leg; the timed leg itself when it is off)
     sys_.set_beta_mu(beta_mu)
     sys_.set_proposal(None, 0)
-    recs, wall = timed_trials(sys_, torch, args.steps)
-    note(f"uniform: {args.steps} trials in {wall:.1f} s")
+    seq_n = min(args.seq_steps, args.steps) if speculative else args.steps
+    seq_recs, seq_wall = timed_trials(sys_, torch, seq_n)
+    note(f"uniform, one by one: {seq_n} trials in {seq_wall:.1f} s")
     # the learned proposal from the state the uniform run reached (the plain
     # uniform proposal when the pilot favours no weighting)
     if scale_sel > 0.0:
@@ -394,31 +444,53 @@ def bench_single(args, h4d, W, torch):
         note(f"fixed-state comparison: {args.ab_trials} insertions and deletions per proposal")
     # step-kernel duration: further trials with HIP events around every
     # launch of the fused step kernel (on the library's stream)
+    n_seq_timing = args.timing_trials if seq_n > 0 else 0
     sys_.set_timing(True)
-    tarr = sys_.trials(args.timing_trials, as_array=True)
-    timing = sys_.timing()
+    tarr = sys_.trials(n_seq_timing, as_array=True)
+    seq_timing = sys_.timing()
     sys_.set_timing(False)
     sys_.close()
-    net.close()
+    if net is not None:
+        net.close()
     traffic = counted_traffic(TRAFFIC_FILE) if args.workload == "lj32k" else None
-    out = summarize(recs, wall, timing, [tarr[q] for q in range(args.timing_trials)], traffic)
+    seq_timing_recs = [tarr[q] for q in range(n_seq_timing)]
+    if speculative:
+        recs, wall, timing, atom_launches, execution = uniform_leg_speculative(args, h4d, torch, w, beta_mu)
+        out = summarize(recs, wall, timing, None, traffic, atom_launches=atom_launches)
+        if seq_n > 0:
+            seq = summarize(seq_recs, seq_wall, seq_timing, seq_timing_recs, None)
+            out["sequential"] = {k: seq[k] for k in ("value", "trials_per_s", "accepted",
+                                                     "accepted_exchanges_per_s", "p_acc", "rebuild_every",
+                                                     "lanes_per_atom")}
+            out["sequential"]["trials"] = seq_n
+            out["sequential"]["expected_exchanges_per_s"] = expected_acceptance(seq_recs) * seq["trials_per_s"]
+            out["sequential"]["roofline"] = {k: seq["roofline"][k] for k in ("achieved", "frac", "avg_kernel_us",
+                                                                              "mean_list_entries")}
+    else:
+        recs, wall = seq_recs, seq_wall
+        execution = {"mode": "one trial after another"}
+        out = summarize(recs, wall, seq_timing, seq_timing_recs, traffic)
+    out["execution"] = execution
     out["expected_acceptance"] = expected_acceptance(recs)
     out["expected_exchanges_per_s"] = out["expected_acceptance"] * out["trials_per_s"]
     l_acc = sum(r.accepted for r in lrecs)
     lo, hi = wilson(l_acc, len(lrecs))
     l_exp = expected_acceptance(lrecs)
+    l_rate = len(lrecs) / max(lwall, 1e-300)
+    seq_exp = expected_acceptance(seq_recs) * len(seq_recs) / max(seq_wall, 1e-300) if seq_recs else 0.0
     out["learned"] = {
         "proposal": (f"multiple-try, k = {k_sel} candidates weighted by exp({scale_sel} min(s, 10)), s the "
                      "trained network's logit (BF16 matrix-core inference)" if scale_sel > 0.0 else
                      "uniform: on the pilot's out-of-fold logits no (k, scale) beat it by the margin"),
+        "execution": "one trial after another (single box)",
         "candidates": k_sel, "weight_scale": scale_sel,
         "choice_estimates": est,
-        "value": sum(r.n_atoms * r.n_steps for r in lrecs) / lwall, "unit": "atom-steps/s",
-        "trials": len(lrecs), "trials_per_s": len(lrecs) / lwall,
-        "accepted": l_acc, "accepted_exchanges_per_s": l_acc / lwall,
+        "value": sum(r.n_atoms * r.n_steps for r in lrecs) / max(lwall, 1e-300), "unit": "atom-steps/s",
+        "trials": len(lrecs), "trials_per_s": l_rate,
+        "accepted": l_acc, "accepted_exchanges_per_s": l_acc * l_rate / max(1, len(lrecs)),
         "p_acc": l_acc / max(1, len(lrecs)), "p_acc_wilson95": [lo, hi],
-        "expected_acceptance": l_exp, "expected_exchanges_per_s": l_exp * len(lrecs) / lwall,
-        "gain_expected_exchanges_per_s": (l_exp * len(lrecs) / lwall) / max(1e-300, out["expected_exchanges_per_s"]),
+        "expected_acceptance": l_exp, "expected_exchanges_per_s": l_exp * l_rate,
+        "gain_expected_exchanges_per_s_vs_one_by_one_uniform": l_exp * l_rate / max(1e-300, seq_exp),
         "pilot_insertions": args.pilot, "pilot_s": pilot_s, "train_steps": steps, "train_s": train_s,
         "train_loss_first": float(losses[:10].mean()), "train_loss_last": float(losses[-50:].mean()),
         "target": "clip(beta mu + I - beta dH, -100, 10)",
@@ -427,13 +499,14 @@ def bench_single(args, h4d, W, torch):
         "fixed_state_gain_bootstrap90": ab.get("gain_bootstrap90") if ab is not None else None,
         "out_of_fold_corr_logit_vs_target": oof_corr,
     }
-    config = dict({"workload": desc + "; value: uniform proposal, 'learned': the trained multiple-try "
-                   "proposal from the same state"}, **shape)
+    config = dict({"workload": desc + "; value: uniform proposal" +
+                   (f", {args.replicas} speculative replicas of the one chain" if speculative else "") +
+                   "; 'learned': the trained multiple-try proposal from the same state"}, **shape)
     config.update({
         "beta_mu": beta_mu, "beta_mu_source": "given" if args.beta_mu is not None else
         "Jarzynski estimate from the pilot insertions (equilibrium operating point)",
         "beta_mu_jarzynski": bmu_eq,
-        "skin": w.params["skin"], "proposal": "uniform", "parallelism": "single box, one GPU",
+        "skin": w.params["skin"], "proposal": "uniform", "parallelism": "single chain, one GPU",
     })
     base = None if args.no_cpu_baseline else cpu_baseline(w, args.cpu_steps, label)
     return out, config, base
@@ -494,6 +567,11 @@ def main():
                     help="single box: largest candidate count the learned proposal may choose")
     ap.add_argument("--learned-steps", type=int, default=None,
                     help="single box: timed learned trials (default: as many as --steps)")
+    ap.add_argument("--replicas", type=int, default=8,
+                    help="lj32k: speculative replicas of the chain for the timed uniform trials (<= 1: one "
+                         "trial after another)")
+    ap.add_argument("--seq-steps", type=int, default=300,
+                    help="lj32k with replicas: one-by-one uniform trials timed for reference")
     ap.add_argument("--ab-trials", type=int, default=None,
                     help="single box: forced insertions and deletions per proposal on the final state "
                          "(default 400 / water 600)")

@@ -204,6 +204,35 @@ int32_t h4d_run_trials(h4d_system *sys, int32_t n, int32_t move, h4d_trial *out)
  */
 int32_t h4d_run_batch(h4d_system *sys, int32_t trials_per_box, int32_t move, h4d_trial *out);
 
+/*
+ * Speculative trials of ONE chain (the trial sequence of Sec. II A, Fig. 1,
+ * unchanged).  A trial's outcome depends only on the state it starts from
+ * and on its index (every random number is keyed by the index), and a
+ * rejected trial leaves the state unchanged.  So `replicas` copies of the
+ * state can run trials t, t+1, ..., t+replicas-1 side by side: the results up
+ * to and including the first accepted trial are the chain's, exactly as if
+ * run one after another; the later ones are discarded and every copy takes
+ * the accepted trial's state.  With acceptance probability p, a round yields
+ * about (1 - (1-p)^replicas) / p trials.
+ *
+ * h4d_init_speculative: the handle, from one configuration as for
+ * h4d_init_system (water = 0; 1 <= replicas <= 64; every replica uses
+ * Philox key (seed, stream)).  It is a batch of `replicas` boxes: the
+ * observables, state, timing and autotuning calls work on it (every box
+ * holds the chain's state between calls; h4d_run_batch runs the same trial
+ * in every replica, which keeps them equal, and leaves the chain's
+ * statistics out).
+ *
+ * h4d_run_speculative: n_trials more trials of the chain; out[n_trials]
+ * (host) receives their records (field `trial` runs on from the chain's
+ * counter) and *rounds (may be NULL) the number of rounds used.  move forces
+ * every trial's direction (H4D_MOVE_*).
+ */
+int32_t h4d_init_speculative(const h4d_params *params, int32_t replicas, int32_t n_atoms, int32_t n_salt,
+                             const double *pos, const int32_t *type, const int64_t *tag, void *hip_stream,
+                             h4d_system **out);
+int32_t h4d_run_speculative(h4d_system *sys, int32_t n_trials, int32_t move, h4d_trial *out, int32_t *rounds);
+
 /* FP64 energies and virial of the current state, plus the running
  * particle-number statistics of the trials run so far (box 0, or box `box`
  * of a batch). */

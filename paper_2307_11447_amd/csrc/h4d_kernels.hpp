@@ -1269,6 +1269,32 @@ __global__ void k_set_quota(KArgs a, long long count) {
     c->trial_end = count < 0 ? 0x7fffffffffffffffLL : c->trial + count;
 }
 
+// Speculative trials: every box of the batch takes box src's state between
+// trials (canonical arrays, atom and pair counts, next tag).  The boxes are
+// replicas of one chain with equal capacities.
+__global__ __launch_bounds__(kBlock) void k_broadcast_box(KArgs a, int src) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= a.slots) return;
+    const int bi = box_of_slot(a, i);
+    if (bi == src) return;
+    const Ctl *cs = a.ctl + src;
+    const int o = i - a.box[bi].a0;
+    if (o < cs->n) {
+        const int j = a.box[src].a0 + o;
+        a.cpos[i] = a.cpos[j];
+        a.ctag[i] = a.ctag[j];
+        a.ctype[i] = a.ctype[j];
+        a.cmol[i] = a.cmol[j];
+    }
+    if (o == 0) {
+        Ctl *c = a.ctl + bi;
+        c->n = cs->n;
+        c->n_all = cs->n_all;
+        c->nsalt = cs->nsalt;
+        c->next_tag = cs->next_tag;
+    }
+}
+
 // Sum of list lengths of the current states (for the roofline byte count).
 __global__ __launch_bounds__(kBlock) void k_sum_nbr(KArgs a, unsigned long long *out) {
     const int i = blockIdx.x * kBlock + threadIdx.x;

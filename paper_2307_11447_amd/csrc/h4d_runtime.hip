@@ -57,6 +57,7 @@ struct h4d_system {
     int rebuild_every = 1;
     int clean_trials = 0;
     bool interval_tuned = false;   // the autotuner fixed the base interval
+    bool speculative = false;      // the boxes are replicas of one chain (one Philox key)
     int list_split = 0;            // list-build blocks per cell (0: automatic)
     int partial_blocks = 0;
     TrialRec *h_rec = nullptr;  // per box (pinned)
@@ -81,6 +82,7 @@ struct h4d_system {
         double N_sum = 0.0, N2_sum = 0.0;
     };
     std::vector<Stats> stats;
+    Stats chain;                   // speculative handles: the chain's statistics
     // learned proposal (single box): k candidates per move, 0 = uniform
     LearnArgs la{};
 
@@ -239,7 +241,7 @@ int setup_boxes(h4d_system *s, const double *edges, const int32_t *n_atoms) {
         B.c0 = c0;
         B.nc = B.ncell[0] * B.ncell[1] * B.ncell[2];
         B.volume = B.L[0] * B.L[1] * B.L[2];
-        B.stream = p.stream + (uint64_t)b;
+        B.stream = p.stream + (s->speculative ? 0u : (uint64_t)b);
         a0 += cap;
         c0 += B.nc;
         if (a0 > (1 << 30)) return fail(H4D_EINVAL, "too many atom slots");
@@ -696,7 +698,7 @@ int run_batch(h4d_system *s, int T, int move, h4d_trial *out) {
 
 int create(const h4d_params *params, int nbox, const double *edges, const int32_t *n_atoms, const int32_t *n_salt,
            int32_t n_mol, const double *pos, const int32_t *type, const int32_t *mol, const int64_t *tag,
-           void *hip_stream, h4d_system **out) {
+           void *hip_stream, h4d_system **out, bool speculative = false) {
     g_err.clear();
     if (!params || !out || nbox < 1 || !edges || !n_atoms || !n_salt) return fail(H4D_EINVAL, "null argument");
     *out = nullptr;
@@ -758,6 +760,7 @@ int create(const h4d_params *params, int nbox, const double *edges, const int32_
         if (e[0] == '1') s->graphs_ok[0] = false;   // launch every kernel eagerly
     }
     s->stream = static_cast<hipStream_t>(hip_stream);
+    s->speculative = speculative;
     s->n_mol = n_mol;
     s->n_host.assign(n_atoms, n_atoms + nbox);
     s->nsalt_host.assign(n_salt, n_salt + nbox);
@@ -977,6 +980,76 @@ int32_t h4d_init_batch(const h4d_params *params, int32_t n_boxes, const double *
 }
 
 int32_t h4d_num_boxes(const h4d_system *s) { return s ? s->nbox : 0; }
+
+int32_t h4d_init_speculative(const h4d_params *params, int32_t replicas, int32_t n_atoms, int32_t n_salt,
+                             const double *pos, const int32_t *type, const int64_t *tag, void *hip_stream,
+                             h4d_system **out) {
+    if (!params || !out) return fail(H4D_EINVAL, "null argument");
+    if (replicas < 1 || replicas > 64) return fail(H4D_EINVAL, "replicas must be in 1..64");
+    if (params->water) return fail(H4D_EINVAL, "speculative trials need water = 0");
+    if (n_atoms < 0 || (n_atoms > 0 && (!pos || !type || !tag))) return fail(H4D_EINVAL, "null configuration array");
+    const size_t n = (size_t)n_atoms, K = (size_t)replicas;
+    std::vector<double> edges(3 * K), p(3 * n * K);
+    std::vector<int32_t> na(K, n_atoms), ns(K, n_salt), ty(n * K);
+    std::vector<int64_t> tg(n * K);
+    for (size_t r = 0; r < K; ++r) {
+        for (int d = 0; d < 3; ++d) edges[3 * r + d] = params->box[d];
+        std::copy(pos, pos + 3 * n, p.begin() + 3 * n * r);
+        std::copy(type, type + n, ty.begin() + n * r);
+        std::copy(tag, tag + n, tg.begin() + n * r);
+    }
+    return create(params, replicas, edges.data(), na.data(), ns.data(), 0, p.data(), ty.data(), nullptr, tg.data(),
+                  hip_stream, out, true);
+}
+
+int32_t h4d_run_speculative(h4d_system *s, int32_t n_trials, int32_t move, h4d_trial *out, int32_t *rounds_out) {
+    if (!s || n_trials < 0 || (n_trials > 0 && !out)) return fail(H4D_EINVAL, "null handle or output");
+    if (!s->speculative) return fail(H4D_EINVAL, "not a speculative handle (h4d_init_speculative)");
+    if (move < -1 || move > 1) return fail(H4D_EINVAL, "move must be -1, 0 or +1");
+    const int K = s->nbox;
+    std::vector<h4d_trial> recs(K);
+    int rc = read_ctl(s);
+    if (rc) return rc;
+    long long t0 = s->h_ctl[0].trial;
+    int done = 0, rounds = 0;
+    while (done < n_trials) {
+        // replica b runs trial t0 + b of the chain from the chain's state
+        for (int b = 0; b < K; ++b) s->h_ctl[b].trial = t0 + b;
+        if ((rc = write_ctl(s))) return rc;
+        if ((rc = run_batch(s, 1, move, recs.data()))) return rc;
+        ++rounds;
+        // the chain's trials: up to and including the first accepted one
+        bool any = false;
+        for (int b = 0; b < K; ++b) any |= recs[b].accepted != 0;
+        int m = 0;
+        while (m < K && done + m < n_trials) {
+            const h4d_trial &r = recs[m];
+            out[done + m] = r;
+            h4d_system::Stats &st = s->chain;
+            st.n_trials += 1;
+            if (r.move > 0) { st.n_ins += 1; st.n_ins_acc += r.accepted; }
+            else { st.n_del += 1; st.n_del_acc += r.accepted; }
+            st.N_sum += (double)r.n_salt_after;
+            st.N2_sum += (double)r.n_salt_after * (double)r.n_salt_after;
+            ++m;
+            if (r.accepted) break;
+        }
+        if (any) {   // every replica takes the state after the chain's last trial
+            const int src = m - 1;
+            hipLaunchKernelGGL(k_broadcast_box, dim3(slot_blocks(s)), dim3(kBlock), 0, s->stream, s->a, src);
+            HIPC(hipGetLastError());
+            if ((rc = read_ctl(s))) return rc;
+            for (int b = 0; b < K; ++b) { s->n_host[b] = s->n_host[src]; s->nsalt_host[b] = s->nsalt_host[src]; }
+        }
+        done += m;
+        t0 += m;
+    }
+    if ((rc = read_ctl(s))) return rc;
+    for (int b = 0; b < K; ++b) { s->h_ctl[b].trial = t0; s->stats[b] = s->chain; }
+    if ((rc = write_ctl(s))) return rc;
+    if (rounds_out) *rounds_out = rounds;
+    return H4D_OK;
+}
 
 int32_t h4d_build_neighbors(h4d_system *s) {
     if (!s) return fail(H4D_EINVAL, "null handle");

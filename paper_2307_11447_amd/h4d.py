@@ -121,6 +121,9 @@ def lib() -> C.CDLL:
                                      C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(C.c_int32),
                                      C.POINTER(C.c_int64), vp, C.POINTER(vp)]
         L.h4d_num_boxes.argtypes = [vp]
+        L.h4d_init_speculative.argtypes = [C.POINTER(Params), C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double),
+                                           C.POINTER(C.c_int32), C.POINTER(C.c_int64), vp, C.POINTER(vp)]
+        L.h4d_run_speculative.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(Trial), C.POINTER(C.c_int32)]
         L.h4d_run_batch.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(Trial)]
         L.h4d_get_box_state.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                         C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int32),
@@ -147,7 +150,8 @@ def lib() -> C.CDLL:
                      "h4d_run_batch", "h4d_get_box_state", "h4d_box_observables", "h4d_autotune",
                      "h4d_mlp_create", "h4d_mlp_destroy", "h4d_mlp_set_weights", "h4d_mlp_get_weights",
                      "h4d_mlp_forward", "h4d_mlp_loss_grad", "h4d_mlp_train", "h4d_set_proposal",
-                     "h4d_last_site_features", "h4d_last_candidates", "h4d_site_features", "h4d_set_beta_mu"):
+                     "h4d_last_site_features", "h4d_last_candidates", "h4d_site_features", "h4d_set_beta_mu",
+                     "h4d_init_speculative", "h4d_run_speculative"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -375,6 +379,46 @@ class Batch(_Handle):
         if as_array:
             return recs
         return [[recs[b * trials_per_box + q].as_dict() for q in range(trials_per_box)] for b in range(self.nb)]
+
+
+class Speculative(_Handle):
+    """One chain run speculatively on `replicas` copies of its state: a
+    round runs the next `replicas` trials side by side and keeps them up to
+    the first accepted one (the records equal a one-by-one run)."""
+
+    def __init__(self, params: dict, replicas: int, x, type_, tag, nsalt: int, stream=None):
+        self._h = None
+        self.params = dict(params)
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 3)
+        t = np.ascontiguousarray(type_, dtype=np.int32)
+        g = np.ascontiguousarray(tag, dtype=np.int64)
+        h = C.c_void_p()
+        p = make_params(params)
+        _check(lib().h4d_init_speculative(
+            C.byref(p), replicas, len(t), nsalt, x.ctypes.data_as(C.POINTER(C.c_double)),
+            t.ctypes.data_as(C.POINTER(C.c_int32)), g.ctypes.data_as(C.POINTER(C.c_int64)),
+            stream if stream is not None else current_stream(), C.byref(h)))
+        self._h = h
+        self.replicas = replicas
+        self.rounds = 0
+
+    @classmethod
+    def from_workload(cls, w, replicas: int, **overrides):
+        params = dict(w.params)
+        params.update(overrides)
+        return cls(params, replicas, w.x, w.type, w.tag, w.nsalt)
+
+    def trials(self, n: int, move: int = MOVE_AUTO, as_array: bool = False):
+        recs = (Trial * max(n, 1))()
+        rounds = C.c_int32()
+        _check(lib().h4d_run_speculative(self._h, n, move, recs, C.byref(rounds)))
+        self.rounds += rounds.value
+        if as_array:
+            return recs
+        return [recs[q].as_dict() for q in range(n)]
+
+    def state(self) -> dict:
+        return _state_of(self._h, 0)
 
 
 class System(_Handle):

@@ -1,0 +1,54 @@
+"""Speculative trials of one chain: replicas of the state run the next
+trials side by side and keep them up to the first accepted one.  Every
+random number is keyed by the trial index and a rejected trial leaves the
+state unchanged, so the chain must equal a one-by-one run of the same
+trials: here bitwise (FP32 pair pass, the same lanes per atom and rebuild
+interval in both runs), record for record and in the final state."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2307_11447_amd import h4d
+from paper_2307_11447_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("replicas,beta_mu", [(6, -5.0), (3, 2.0)])
+def test_speculative_chain_equals_sequential_run(replicas, beta_mu):
+    say(f"case speculative lj1000 fp32, {replicas} replicas, beta mu {beta_mu}, 40 trials")
+    w = W.lj_electrolyte(1000, 0.3, 4242, n_steps=40, precision="fp32")
+    w.params.update(beta_mu=beta_mu, rebuild_every=10, lanes_per_atom=8, capacity=w.n + 256)
+    T = 40
+    seq = h4d.System.from_workload(w)
+    rs = seq.trials(T)
+    spec = h4d.Speculative.from_workload(w, replicas)
+    rp = spec.trials(T)
+    n_acc = sum(r["accepted"] for r in rs)
+    say(f"   accepted {n_acc} of {T}; {spec.rounds} rounds of {replicas} replicas")
+    assert 0 < n_acc < T and spec.rounds < T
+    for t in range(T):
+        assert rp[t]["trial"] == t
+        assert rp[t] == dict(rs[t], n_rebuilds=rp[t]["n_rebuilds"]), t
+    a, b = seq.state(), spec.state()
+    assert a["n"] == b["n"] and a["nsalt"] == b["nsalt"]
+    assert np.array_equal(a["tag"], b["tag"]) and np.array_equal(a["x"], b["x"])
+    for box in range(replicas):   # every replica holds the chain's state
+        assert np.array_equal(spec.box_state(box)["x"], a["x"])
+    oa, ob = seq.observables(), spec.box_observables(0)
+    for key in ("n_trials", "n_ins", "n_ins_acc", "n_del", "n_del_acc", "N_mean", "N2_mean"):
+        assert oa[key] == ob[key], key
+    # and it goes on from there: the next trials continue the same chain
+    r2 = spec.trials(5)
+    s2 = seq.trials(5)
+    assert [r["trial"] for r in r2] == list(range(T, T + 5))
+    for x, y in zip(r2, s2):
+        assert x == dict(y, n_rebuilds=x["n_rebuilds"])
+    seq.close()
+    spec.close()
