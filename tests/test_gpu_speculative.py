@@ -52,3 +52,26 @@ def test_speculative_chain_equals_sequential_run(replicas, beta_mu):
         assert x == dict(y, n_rebuilds=x["n_rebuilds"])
     seq.close()
     spec.close()
+
+
+def test_speculative_fp64_chain_follows_the_oracle():
+    say("case speculative lj500 fp64, 5 replicas, 16 trials against the oracle")
+    from oracle import oracle as O
+    w = W.config_lj_500()
+    w.params.update(beta_mu=6.0, n_steps=60)
+    spec = h4d.Speculative.from_workload(w, 5)
+    o = O.OracleSystem.from_workload(w, cap=w.n + 64)
+    recs = spec.trials(16)
+    n_acc = 0
+    for t, rg in enumerate(recs):
+        ro = o.trial(t)
+        assert rg["trial"] == t and rg["move"] == ro["move"] and rg["flags"] & 3 == ro["flags"]
+        if not ro["flags"]:
+            for key in ("dH", "W_prot", "E_switch", "H0"):
+                assert abs(rg[key] - ro[key]) <= 1e-6 * max(1.0, abs(ro[key])), (t, key)
+        assert rg["accepted"] == ro["accepted"], (t, rg, ro)
+        n_acc += rg["accepted"]
+    say(f"   accepted {n_acc} of 16 in {spec.rounds} rounds")
+    st = spec.state()
+    assert st["n"] == o.n and np.array_equal(st["tag"], o.tag[: o.n])
+    spec.close()
