@@ -372,7 +372,7 @@ def bench_single(args, h4d, W, torch):
         w.params.update(lanes_per_atom=args.lanes)
     if args.skin > 0:
         w.params.update(skin=args.skin)
-    speculative = args.replicas > 1 and args.workload != "water"
+    speculative = args.replicas > 1
     sys_ = h4d.System.from_workload(w)
     tuned = sys_.autotune(4 if args.workload == "lj32k" else 2) if args.autotune else None
     if tuned:
@@ -568,10 +568,11 @@ def main():
     ap.add_argument("--learned-steps", type=int, default=None,
                     help="single box: timed learned trials (default: as many as --steps)")
     ap.add_argument("--replicas", type=int, default=8,
-                    help="lj32k: speculative replicas of the chain for the timed uniform trials (<= 1: one "
-                         "trial after another)")
-    ap.add_argument("--seq-steps", type=int, default=300,
-                    help="lj32k with replicas: one-by-one uniform trials timed for reference")
+                    help="single box: speculative replicas of the chain for the timed uniform trials (<= 1: "
+                         "one trial after another)")
+    ap.add_argument("--seq-steps", type=int, default=None,
+                    help="single box with replicas: one-by-one uniform trials timed for reference "
+                         "(default 300 / water 60)")
     ap.add_argument("--ab-trials", type=int, default=None,
                     help="single box: forced insertions and deletions per proposal on the final state "
                          "(default 400 / water 600)")
@@ -608,6 +609,8 @@ def main():
         args.pilot = 1000 if water else 1200
     if args.ab_trials is None:
         args.ab_trials = 600 if water else 400
+    if args.seq_steps is None:
+        args.seq_steps = 60 if water else 300
     if batched and args.beta_mu is None:
         args.beta_mu = -4.0
 

@@ -215,9 +215,9 @@ int32_t h4d_run_batch(h4d_system *sys, int32_t trials_per_box, int32_t move, h4d
  * the accepted trial's state.  With acceptance probability p, a round yields
  * about (1 - (1-p)^replicas) / p trials.
  *
- * h4d_init_speculative: the handle, from one configuration as for
- * h4d_init_system (water = 0; 1 <= replicas <= 64; every replica uses
- * Philox key (seed, stream)).  It is a batch of `replicas` boxes: the
+ * h4d_init_speculative: the handle, from one configuration with the same
+ * arguments and conventions as h4d_init_system (rigid water included;
+ * 1 <= replicas <= 64; every replica uses Philox key (seed, stream)).  It is a batch of `replicas` boxes: the
  * observables, state, timing and autotuning calls work on it (every box
  * holds the chain's state between calls; h4d_run_batch runs the same trial
  * in every replica, which keeps them equal, and leaves the chain's
@@ -229,8 +229,8 @@ int32_t h4d_run_batch(h4d_system *sys, int32_t trials_per_box, int32_t move, h4d
  * every trial's direction (H4D_MOVE_*).
  */
 int32_t h4d_init_speculative(const h4d_params *params, int32_t replicas, int32_t n_atoms, int32_t n_salt,
-                             const double *pos, const int32_t *type, const int64_t *tag, void *hip_stream,
-                             h4d_system **out);
+                             int32_t n_mol, const double *pos, const int32_t *type, const int32_t *mol,
+                             const int64_t *tag, void *hip_stream, h4d_system **out);
 int32_t h4d_run_speculative(h4d_system *sys, int32_t n_trials, int32_t move, h4d_trial *out, int32_t *rounds);
 
 /* FP64 energies and virial of the current state, plus the running

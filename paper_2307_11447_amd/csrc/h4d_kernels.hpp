@@ -1400,13 +1400,21 @@ __device__ __forceinline__ d3 unwrap_near(const Box &B, const double4 &p, const 
               ref.z + min_image(p.z - ref.z, B.L[2]));
 }
 
-// Rigid waters belong to a single-box system (box 0, slots from 0).
+// Rigid waters: every box holds n_mol of them as its first atoms (canonical
+// slots a0 + 3m + q, q = O, H, H); one thread per molecule of every box.
+__device__ __forceinline__ int water_slots(const KArgs &a, int gm, int w[3]) {
+    const int bi = gm / a.G.n_mol, m = gm - bi * a.G.n_mol;
+    const int c0 = a.box[bi].a0 + 3 * m;
+    w[0] = a.molw[c0]; w[1] = a.molw[c0 + 1]; w[2] = a.molw[c0 + 2];
+    return bi;
+}
+
 // trial start: project the freshly drawn water velocities (working buffer 0)
 __global__ __launch_bounds__(kBlock) void k_rattle_mb(KArgs a) {
-    const int m = blockIdx.x * kBlock + threadIdx.x;
-    if (m >= a.G.n_mol) return;
-    const Box &B = a.box[0];
-    const int w[3] = {a.molw[3 * m], a.molw[3 * m + 1], a.molw[3 * m + 2]};
+    const int gm = blockIdx.x * kBlock + threadIdx.x;
+    if (gm >= a.G.n_mol * a.nbox) return;
+    int w[3];
+    const Box &B = a.box[water_slots(a, gm, w)];
     const double4 pa = a.pos[0][w[0]];
     const d3 ra_ = mk(pa.x, pa.y, pa.z);
     const d3 x1 = unwrap_near(B, a.pos[0][w[1]], ra_), x2 = unwrap_near(B, a.pos[0][w[2]], ra_);
@@ -1420,15 +1428,18 @@ __global__ __launch_bounds__(kBlock) void k_rattle_mb(KArgs a) {
 // One step k of the rigid waters (after k_step stored their forces F_k):
 // v_k = v + h F/m and the velocity constraint (k > 0); v += h F/m, drift and
 // position constraint with its velocity correction (k < nf).
-__global__ __launch_bounds__(kBlock) void k_settle(KArgs a, int k, int b, int bin, int cl) {
-    const Box &B = a.box[0];
-    Ctl *c = a.ctl;
+__global__ __launch_bounds__(kBlock) void k_settle(KArgs a, int k, int b0, int bin, int cl) {
+    const int gm = blockIdx.x * kBlock + threadIdx.x;
+    if (gm >= a.G.n_mol * a.nbox) return;
+    int w[3];
+    const int bi = water_slots(a, gm, w);
+    const Box &B = a.box[bi];
+    Ctl *c = a.ctl + bi;
     const int move = c->move, nf = c->nf;
     if (move == 0 || k > nf) return;
-    const int m = blockIdx.x * kBlock + threadIdx.x;
-    if (m >= a.G.n_mol) return;
+    const int b = buf_of(b0, c);
+    int *fast = a.fast + (size_t)bi * 3 * kFastCap;
     const Geo &G = a.G;
-    const int w[3] = {a.molw[3 * m], a.molw[3 * m + 1], a.molw[3 * m + 2]};
     double4 p4[3], v4[3], f4[3];
     for (int i = 0; i < 3; ++i) { p4[i] = a.pos[b][w[i]]; v4[i] = a.vel[b][w[i]]; f4[i] = a.fw[w[i]]; }
     const d3 x0[3] = {mk(p4[0].x, p4[0].y, p4[0].z), unwrap_near(B, p4[1], mk(p4[0].x, p4[0].y, p4[0].z)),
@@ -1462,7 +1473,7 @@ __global__ __launch_bounds__(kBlock) void k_settle(KArgs a, int k, int b, int bi
         if ((mo & kFastBit) == 0 && moved_beyond_half_skin(a, B, qn, a.posb[w[i]])) mo |= kFastBit;
         if (mo & kFastBit) {
             const int slot = atomicAdd(&c->nfast[lw], 1);
-            if (slot < kFastCap) a.fast[lw * kFastCap + slot] = w[i];
+            if (slot < kFastCap) fast[lw * kFastCap + slot] = w[i];
             else atomicOr(&c->err, kErrFast);
             atomicMax(&c->max_fast, slot + 1);
         }

@@ -366,7 +366,7 @@ int sort_in(h4d_system *s, hipStream_t st) {
     hipLaunchKernelGGL(k_cell_sort, dim3(nc), dim3(kWave), a.cell_cap * sizeof(int), st, a, 0);
     hipLaunchKernelGGL(k_cell_scan, dim3(s->nbox), dim3(1024), 0, st, a, 0);
     hipLaunchKernelGGL(k_gather_in, dim3(nc), dim3(kWave), 0, st, a, 0);
-    if (a.G.water) hipLaunchKernelGGL(k_rattle_mb, dim3(blocks_for(a.G.n_mol)), dim3(kBlock), 0, st, a);
+    if (a.G.water) hipLaunchKernelGGL(k_rattle_mb, dim3(blocks_for(a.G.n_mol * s->nbox)), dim3(kBlock), 0, st, a);
     launch_list(s, -1, 0, 0, st);
     s->cl = 0;
     HIPC(hipGetLastError());
@@ -492,7 +492,8 @@ int enqueue_round(h4d_system *s, int move, hipStream_t st, int nf, int M, bool t
         if (s->p.precision == H4D_PREC_FP32) launch_step<1>(s, st, e0, e1, k, b, bin);
         else launch_step<0>(s, st, e0, e1, k, b, bin);
         if (a.G.water)
-            hipLaunchKernelGGL(k_settle, dim3(blocks_for(a.G.n_mol)), dim3(kBlock), 0, st, a, k, b, bin, s->cl);
+            hipLaunchKernelGGL(k_settle, dim3(blocks_for(a.G.n_mol * s->nbox)), dim3(kBlock), 0, st, a, k, b, bin,
+                               s->cl);
         b ^= 1;
     }
     if ((rc = rebuild_final(s, st))) return rc;
@@ -710,7 +711,8 @@ int create(const h4d_params *params, int nbox, const double *edges, const int32_
         total += n_atoms[b];
     }
     if (total > 0 && (!pos || !type || !tag)) return fail(H4D_EINVAL, "null configuration array");
-    if (params->water && nbox != 1) return fail(H4D_EINVAL, "rigid water needs a single box");
+    if (params->water && nbox != 1 && !speculative)
+        return fail(H4D_EINVAL, "rigid water needs a single box (or speculative replicas)");
     const double rc_max = std::max(params->rc_lj, params->rc_coul);
     for (int q = 0; q < 3 * nbox; ++q)
         if (!(edges[q] >= 2.0 * rc_max)) return fail(H4D_EINVAL, "every box edge must be at least twice the largest cutoff");
@@ -806,7 +808,7 @@ int create(const h4d_params *params, int nbox, const double *edges, const int32_
         (rc = s->alloc(&a.ttag, C)) || (rc = s->alloc(&a.ttype, C)) || (rc = s->alloc(&a.tmol, C)) ||
         (rc = s->alloc(&a.nnbr, C)) || (rc = s->alloc(&a.partial, (size_t)s->partial_blocks * 5)) ||
         (rc = s->alloc(&a.ctl, (size_t)nbox)) || (rc = s->alloc(&a.rec, (size_t)nbox)) ||
-        (rc = s->alloc(&a.molw, (size_t)std::max(1, 3 * n_mol))) || (rc = s->alloc(&a.fw, C)) ||
+        (rc = s->alloc(&a.molw, n_mol > 0 ? C : 1)) || (rc = s->alloc(&a.fw, C)) ||
         (rc = s->alloc(&coef_d, (size_t)kMaxTypes * kMaxTypes)) || (rc = s->alloc(&mass_d, kMaxTypes)) ||
         (rc = s->alloc(&box_d, (size_t)nbox)) || (rc = s->alloc(&slot_box_d, C / kBlock)) ||
         (rc = s->alloc(&cell_box_d, (size_t)a.ncell_total)) || (rc = alloc_lists(s))) {
@@ -982,24 +984,24 @@ int32_t h4d_init_batch(const h4d_params *params, int32_t n_boxes, const double *
 int32_t h4d_num_boxes(const h4d_system *s) { return s ? s->nbox : 0; }
 
 int32_t h4d_init_speculative(const h4d_params *params, int32_t replicas, int32_t n_atoms, int32_t n_salt,
-                             const double *pos, const int32_t *type, const int64_t *tag, void *hip_stream,
-                             h4d_system **out) {
+                             int32_t n_mol, const double *pos, const int32_t *type, const int32_t *mol,
+                             const int64_t *tag, void *hip_stream, h4d_system **out) {
     if (!params || !out) return fail(H4D_EINVAL, "null argument");
     if (replicas < 1 || replicas > 64) return fail(H4D_EINVAL, "replicas must be in 1..64");
-    if (params->water) return fail(H4D_EINVAL, "speculative trials need water = 0");
     if (n_atoms < 0 || (n_atoms > 0 && (!pos || !type || !tag))) return fail(H4D_EINVAL, "null configuration array");
     const size_t n = (size_t)n_atoms, K = (size_t)replicas;
     std::vector<double> edges(3 * K), p(3 * n * K);
-    std::vector<int32_t> na(K, n_atoms), ns(K, n_salt), ty(n * K);
+    std::vector<int32_t> na(K, n_atoms), ns(K, n_salt), ty(n * K), mo(mol ? n * K : 0);
     std::vector<int64_t> tg(n * K);
     for (size_t r = 0; r < K; ++r) {
         for (int d = 0; d < 3; ++d) edges[3 * r + d] = params->box[d];
         std::copy(pos, pos + 3 * n, p.begin() + 3 * n * r);
         std::copy(type, type + n, ty.begin() + n * r);
         std::copy(tag, tag + n, tg.begin() + n * r);
+        if (mol) std::copy(mol, mol + n, mo.begin() + n * r);
     }
-    return create(params, replicas, edges.data(), na.data(), ns.data(), 0, p.data(), ty.data(), nullptr, tg.data(),
-                  hip_stream, out, true);
+    return create(params, replicas, edges.data(), na.data(), ns.data(), n_mol, p.data(), ty.data(),
+                  mol ? mo.data() : nullptr, tg.data(), hip_stream, out, true);
 }
 
 int32_t h4d_run_speculative(h4d_system *s, int32_t n_trials, int32_t move, h4d_trial *out, int32_t *rounds_out) {

@@ -121,8 +121,9 @@ def lib() -> C.CDLL:
                                      C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(C.c_int32),
                                      C.POINTER(C.c_int64), vp, C.POINTER(vp)]
         L.h4d_num_boxes.argtypes = [vp]
-        L.h4d_init_speculative.argtypes = [C.POINTER(Params), C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double),
-                                           C.POINTER(C.c_int32), C.POINTER(C.c_int64), vp, C.POINTER(vp)]
+        L.h4d_init_speculative.argtypes = [C.POINTER(Params), C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                           C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                           C.POINTER(C.c_int64), vp, C.POINTER(vp)]
         L.h4d_run_speculative.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(Trial), C.POINTER(C.c_int32)]
         L.h4d_run_batch.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(Trial)]
         L.h4d_get_box_state.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -386,18 +387,19 @@ class Speculative(_Handle):
     round runs the next `replicas` trials side by side and keeps them up to
     the first accepted one (the records equal a one-by-one run)."""
 
-    def __init__(self, params: dict, replicas: int, x, type_, tag, nsalt: int, stream=None):
+    def __init__(self, params: dict, replicas: int, x, type_, mol, tag, nsalt: int, n_mol: int = 0, stream=None):
         self._h = None
         self.params = dict(params)
         x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 3)
         t = np.ascontiguousarray(type_, dtype=np.int32)
+        m = np.ascontiguousarray(mol, dtype=np.int32)
         g = np.ascontiguousarray(tag, dtype=np.int64)
         h = C.c_void_p()
         p = make_params(params)
         _check(lib().h4d_init_speculative(
-            C.byref(p), replicas, len(t), nsalt, x.ctypes.data_as(C.POINTER(C.c_double)),
-            t.ctypes.data_as(C.POINTER(C.c_int32)), g.ctypes.data_as(C.POINTER(C.c_int64)),
-            stream if stream is not None else current_stream(), C.byref(h)))
+            C.byref(p), replicas, len(t), nsalt, n_mol, x.ctypes.data_as(C.POINTER(C.c_double)),
+            t.ctypes.data_as(C.POINTER(C.c_int32)), m.ctypes.data_as(C.POINTER(C.c_int32)),
+            g.ctypes.data_as(C.POINTER(C.c_int64)), stream if stream is not None else current_stream(), C.byref(h)))
         self._h = h
         self.replicas = replicas
         self.rounds = 0
@@ -406,7 +408,7 @@ class Speculative(_Handle):
     def from_workload(cls, w, replicas: int, **overrides):
         params = dict(w.params)
         params.update(overrides)
-        return cls(params, replicas, w.x, w.type, w.tag, w.nsalt)
+        return cls(params, replicas, w.x, w.type, w.mol, w.tag, w.nsalt, n_mol=w.n_mol)
 
     def trials(self, n: int, move: int = MOVE_AUTO, as_array: bool = False):
         recs = (Trial * max(n, 1))()

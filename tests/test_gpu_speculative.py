@@ -58,7 +58,7 @@ def test_speculative_fp64_chain_follows_the_oracle():
     say("case speculative lj500 fp64, 5 replicas, 16 trials against the oracle")
     from oracle import oracle as O
     w = W.config_lj_500()
-    w.params.update(beta_mu=6.0, n_steps=60)
+    w.params.update(beta_mu=6.0)
     spec = h4d.Speculative.from_workload(w, 5)
     o = O.OracleSystem.from_workload(w, cap=w.n + 64)
     recs = spec.trials(16)
@@ -74,4 +74,30 @@ def test_speculative_fp64_chain_follows_the_oracle():
     say(f"   accepted {n_acc} of 16 in {spec.rounds} rounds")
     st = spec.state()
     assert st["n"] == o.n and np.array_equal(st["tag"], o.tag[: o.n])
+    spec.close()
+
+
+def test_speculative_water_chain_equals_sequential_run():
+    """Rigid SPC/E water with NaCl (1,300 waters, 34.2 A box): at beta mu =
+    400 insertions are accepted and deletions are not, so rounds end early
+    and the replicas take new states with their waters."""
+    say("case speculative water fp32, 4 replicas, 12 trials")
+    w = W.water_nacl(n_water=1300, n_pairs=20, L=34.2, m=12, seed=81)
+    w.params.update(precision="fp32", n_steps=120, beta_mu=400.0, rebuild_every=6, lanes_per_atom=8,
+                    capacity=w.n + 256)
+    T = 12
+    seq = h4d.System.from_workload(w)
+    rs = seq.trials(T)
+    spec = h4d.Speculative.from_workload(w, 4)
+    rp = spec.trials(T)
+    n_acc = sum(r["accepted"] for r in rs)
+    say(f"   accepted {n_acc} of {T}; {spec.rounds} rounds")
+    for t in range(T):
+        assert rp[t] == dict(rs[t], n_rebuilds=rp[t]["n_rebuilds"]), t
+    assert 0 < n_acc < T, [(r["move"], r["flags"], r["dH"], r["ln_ratio"]) for r in rs]
+    a, b = seq.state(), spec.state()
+    assert a["n"] == b["n"] and np.array_equal(a["tag"], b["tag"]) and np.array_equal(a["x"], b["x"])
+    for box in range(4):
+        assert np.array_equal(spec.box_state(box)["x"], a["x"])
+    seq.close()
     spec.close()
