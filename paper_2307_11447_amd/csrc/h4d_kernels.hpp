@@ -160,7 +160,14 @@ __device__ __forceinline__ int stencil_cell(const Box &B, int cx, int cy, int cz
            (cx + t % 3 - 1 + nx) % nx;
 }
 
+// A non-finite position (a trajectory that blew up) is left out of the cells
+// and marks the trial non-finite: it is rejected, never recomputed, and the
+// cells cannot fill up with such atoms.
 __device__ __forceinline__ void bin_atom(const KArgs &a, const Box &B, Ctl *c, int cb, int w, const double4 &p) {
+    if (!(isfinite(p.x) && isfinite(p.y) && isfinite(p.z))) {
+        atomicOr(&c->err, kErrNonfinite);
+        return;
+    }
     const int cc = B.c0 + (B.use_cells ? cell_of(B, p) : 0);
     const int slot = atomicAdd(&a.cell_cnt[cb][cc], 1);
     if (slot < a.cell_cap) a.cell_atoms[cb][(size_t)cc * a.cell_cap + slot] = w;
@@ -1161,7 +1168,7 @@ __global__ void k_metropolis(KArgs a) {
     r->flags = 0;
     r->accepted = 0;
     c->accepted = 0;
-    if (c->err & (kErrNbr | kErrCell | kErrSkin | kErrCap | kErrFast)) c->retry = 1;
+    if ((c->err & (kErrNbr | kErrCell | kErrSkin | kErrCap | kErrFast)) && !(c->err & kErrNonfinite)) c->retry = 1;
     if (move == 0) {
         r->move = -1;
         r->flags = c->idle ? kFlagIdle : (c->retry ? 0u : kFlagEmpty);
@@ -1186,7 +1193,7 @@ __global__ void k_metropolis(KArgs a) {
     r->dM = move > 0 ? dH - I / a.G.beta : -dH - I / a.G.beta;
     r->ln_ratio = lnR;
     int acc = 0;
-    if (!isfinite(dH)) r->flags |= kFlagNonfinite;
+    if (!isfinite(dH) || (c->err & kErrNonfinite)) r->flags |= kFlagNonfinite;
     else acc = r->ln_u < lnR;
     if (c->retry) acc = 0;
     r->accepted = acc;
