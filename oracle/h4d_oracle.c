@@ -68,7 +68,8 @@ static void draw4(const or_params *p, uint64_t a, uint64_t b, uint64_t c, double
 
 /* Counter purposes: move and plain sites, Maxwell-Boltzmann momenta, N_f,
  * candidate sites of the learned proposal, its categorical choice. */
-enum { PURPOSE_SELECT = 1, PURPOSE_MB = 2, PURPOSE_NSTEPS = 3, PURPOSE_CAND = 4, PURPOSE_PICK = 5 };
+enum { PURPOSE_SELECT = 1, PURPOSE_MB = 2, PURPOSE_NSTEPS = 3, PURPOSE_CAND = 4, PURPOSE_PICK = 5,
+       PURPOSE_BIAS = 6 };
 
 /* ------------------------------------------------------------------ */
 /* Geometry                                                            */
@@ -507,6 +508,77 @@ int or_nemd(const or_params *p, or_state *s, int move, int nf, double *W)
 /* ------------------------------------------------------------------ */
 /* One grand-canonical trial                                           */
 /* ------------------------------------------------------------------ */
+/* ------------------------------------------------------------------ */
+/* Bimodal bias of the flying anion's position given the cation's       */
+/* (Sec. II B 4, Eqs. 12-16).                                           */
+/* ------------------------------------------------------------------ */
+double or_bias_b(double x, double L, double xb, double alpha)
+{
+    /* Eq. (14): two Gaussians at +-x_b, normalised on [-L/2, L/2] */
+    const double sa = sqrt(alpha);
+    const double num = exp(-alpha * (x - xb) * (x - xb)) + exp(-alpha * (x + xb) * (x + xb));
+    const double den = erf(sa * (xb + 0.5 * L)) - erf(sa * (xb - 0.5 * L));
+    return sqrt(alpha / M_PI) * num / den;
+}
+
+double or_bias_B(const or_params *p, const double xa[3], const double xc[3])
+{
+    /* Eq. (12): V times the product of the three one-dimensional densities */
+    double B = p->box[0] * p->box[1] * p->box[2];
+    for (int d = 0; d < 3; ++d) {
+        const double L = p->box[d];
+        double x = xa[d] - xc[d];
+        x -= L * round(x / L);
+        B *= or_bias_b(x, L, p->bias_xb, p->bias_alpha);
+    }
+    return B;
+}
+
+double or_bias_offset(const or_params *p, uint64_t trial, int d)
+{
+    /* one uniform picks the Gaussian at -x_b or +x_b (equal masses on the
+     * symmetric edge), Box-Muller draws from it, and a draw outside
+     * [-L/2, L/2] is replaced by the next attempt's: a draw from Eq. (14) */
+    const double L = p->box[d];
+    for (int attempt = 0; attempt < 64; ++attempt) {
+        double u[4];
+        draw4(p, trial, PURPOSE_BIAS, (uint64_t)(4 * attempt + d), u);
+        const double mu = u[0] < 0.5 ? -p->bias_xb : p->bias_xb;
+        const double z = sqrt(-2.0 * log(u[1])) * cos(6.283185307179586476925286766559 * u[2]);
+        const double x = mu + z / sqrt(2.0 * p->bias_alpha);
+        if (fabs(x) <= 0.5 * L) return x;
+    }
+    return NAN;
+}
+
+/* anion indices in ascending tag order */
+static int anions_by_tag(const or_params *p, const or_state *s, int *idx)
+{
+    int m = 0;
+    for (int i = 0; i < s->n; ++i)
+        if (s->type[i] == p->anion_type) idx[m++] = i;
+    for (int a = 1; a < m; ++a) {            /* insertion sort on tags */
+        const int v = idx[a];
+        int b = a - 1;
+        while (b >= 0 && s->tag[idx[b]] > s->tag[v]) { idx[b + 1] = idx[b]; --b; }
+        idx[b + 1] = v;
+    }
+    return m;
+}
+
+/* sum over the anions of B_ins(r_a, r_c) for the cation at slot ic, in
+ * ascending tag order */
+static double bias_sum(const or_params *p, const or_state *s, int ic)
+{
+    int *idx = malloc(sizeof(int) * (size_t)(s->n > 0 ? s->n : 1));
+    if (!idx) return NAN;
+    const int m = anions_by_tag(p, s, idx);
+    double W = 0.0;
+    for (int q = 0; q < m; ++q) W += or_bias_B(p, s->x + 3 * idx[q], s->x + 3 * ic);
+    free(idx);
+    return W;
+}
+
 static int pick_rank(const or_state *s, int type, int rank)
 {
     /* the atom of the given type whose tag has the given rank (ascending) */
@@ -708,6 +780,15 @@ static int trial_begin(const or_params *p, or_state *s, uint64_t trial, int forc
         if (s->n + 2 > s->cap) return -3;
         double site[6];
         for (int d = 0; d < 3; ++d) { site[d] = p->box[d] * u[1 + d]; site[3 + d] = p->box[d] * u[4 + d]; }
+        if (p->bias_alpha > 0.0 && !(prop && prop->k >= 1)) {
+            /* Sec. II B 4: the anion at the cation plus an offset drawn from
+             * Eq. (14) along each edge */
+            for (int d = 0; d < 3; ++d) {
+                const double x = or_bias_offset(p, trial, d);
+                if (!isfinite(x)) return -9;
+                site[3 + d] = site[d] + x;
+            }
+        }
         if (prop && prop->k >= 1) {
             const int k = prop->k;
             double *sites = malloc(sizeof(double) * 6 * (size_t)k);
@@ -746,8 +827,30 @@ static int trial_begin(const or_params *p, or_state *s, uint64_t trial, int forc
     } else {
         /* Eq. (3): one of the N+1 cations and one of the N+1 anions. */
         ic = pick_rank(s, p->cation_type, (int)floor(u[1] * Ns));
-        ia = pick_rank(s, p->anion_type, (int)floor(u[2] * Ns));
-        if (ic < 0 || ia < 0) return -4;
+        if (ic < 0) return -4;
+        if (p->bias_alpha > 0.0 && !(prop && prop->k >= 1)) {
+            /* Eq. (13): the anion with probability B_ins(r_a, r_c) / sum_n
+             * B_ins(r_a,n, r_c), the first in ascending tag order whose
+             * running sum exceeds u W */
+            int *idx = malloc(sizeof(int) * (size_t)s->n);
+            if (!idx) return -1;
+            const int m = anions_by_tag(p, s, idx);
+            double W = 0.0;
+            for (int q = 0; q < m; ++q) W += or_bias_B(p, s->x + 3 * idx[q], s->x + 3 * ic);
+            const double target = u[2] * W;
+            double run = 0.0;
+            ia = m > 0 ? idx[m - 1] : -1;
+            for (int q = 0; q < m; ++q) {
+                run += or_bias_B(p, s->x + 3 * idx[q], s->x + 3 * ic);
+                if (run > target) { ia = idx[q]; break; }
+            }
+            free(idx);
+            /* Eq. (16): B_ins / B_del = W / (N + 1) */
+            rec->ln_proposal = log(W) - log((double)Ns);
+        } else {
+            ia = pick_rank(s, p->anion_type, (int)floor(u[2] * Ns));
+        }
+        if (ia < 0) return -4;
         s->flying[ic] = 1; s->flying[ia] = 1;
     }
     rec->tag_c = s->tag[ic];
@@ -829,6 +932,11 @@ int or_trial_learned(const or_params *p, or_state *s, uint64_t trial, int force_
         free(sites); free(feat); free(logw);
     }
 
+    if (move > 0 && p->bias_alpha > 0.0 && !prop) {
+        /* Eq. (15): B_del / B_ins = (N + 1) / sum_n B_ins(r_a,n, r_c) over
+         * the anions of the (N+1)-state the trajectory reached */
+        rec->ln_proposal = log((double)(Ns + 1)) - log(bias_sum(p, s, ic));
+    }
     const double dH = (U1 + K1) - H0;
     /* Eqs. (6) and (8) with Lambda_s: ln of (V / (Lambda^3 (N+1)))^2. */
     const double lam3 = p->lambda_s * p->lambda_s * p->lambda_s;

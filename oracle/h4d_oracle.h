@@ -36,6 +36,8 @@ typedef struct {
     double d_oh, d_hh;      /* rigid-water geometry                              */
     double accel;           /* acceleration per (force/mass); 1 in reduced units  */
     uint64_t seed, stream;  /* Philox key                                        */
+    double bias_xb;         /* bimodal bias of the flyers' separation (Sec.      */
+    double bias_alpha;      /* II B 4, Eq. 14): x_b and alpha_b; alpha_b = 0: off */
 } or_params;
 
 /* Configuration.  Arrays are owned by the caller and sized to cap. */
@@ -137,6 +139,14 @@ typedef struct {
 /* The 64 features of a candidate pair site (cation site[0..2], anion
  * site[3..5]) on the physical state without the flying atoms. */
 int or_site_features(const or_params *p, const or_state *s, const double site[6], double out[64]);
+
+/* Bimodal bias (Sec. II B 4): b_ins of Eq. (14) for the anion's offset x
+ * (minimum image, |x| <= L/2) along an edge of length L, and B_ins of
+ * Eq. (12) for an anion at xa and a cation at xc. */
+double or_bias_b(double x, double L, double xb, double alpha);
+double or_bias_B(const or_params *p, const double xa[3], const double xc[3]);
+/* The anion offset of an insertion along edge d (a draw from Eq. 14). */
+double or_bias_offset(const or_params *p, uint64_t trial, int d);
 
 /* A trial with the learned proposal (prop NULL: uniform).  feat_out (may
  * be NULL) receives the features of the inserted or removed pair's site. */

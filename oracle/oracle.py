@@ -33,6 +33,7 @@ class Params(C.Structure):
         ("beta_mu", C.c_double), ("lambda_s", C.c_double),
         ("d_oh", C.c_double), ("d_hh", C.c_double), ("accel", C.c_double),
         ("seed", C.c_uint64), ("stream", C.c_uint64),
+        ("bias_xb", C.c_double), ("bias_alpha", C.c_double),
     ]
 
 
@@ -103,6 +104,12 @@ def lib():
         L.or_mtm_log_factor.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_double), C.c_int,
                                         C.POINTER(C.c_double)]
         L.or_site_features.argtypes = [P, S, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.or_bias_b.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double]
+        L.or_bias_b.restype = C.c_double
+        L.or_bias_B.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.or_bias_B.restype = C.c_double
+        L.or_bias_offset.argtypes = [P, C.c_uint64, C.c_int]
+        L.or_bias_offset.restype = C.c_double
         L.or_trial_learned.argtypes = [P, S, C.c_uint64, C.c_int, C.POINTER(Proposal), C.POINTER(TrialRec),
                                        C.POINTER(C.c_double)]
         _lib = L
@@ -129,6 +136,7 @@ def make_params(d: dict, use_cells: bool = True) -> Params:
     p.ke = d["coulomb_k"]
     p.accel = d.get("accel", 1.0)
     p.seed, p.stream = d["seed"], d.get("stream", 0)
+    p.bias_xb, p.bias_alpha = d.get("bias_xb", 0.0), d.get("bias_alpha", 0.0)
     return p
 
 
@@ -294,3 +302,22 @@ def mtm_log_factor(move: int, logw, sel: int) -> float:
     if rc:
         raise ValueError("bad arguments")
     return out.value
+
+
+def bias_b(x: float, L: float, xb: float, alpha: float) -> float:
+    """b_ins of Eq. (14) (bimodal bias of the anion offset along one edge)."""
+    return lib().or_bias_b(x, L, xb, alpha)
+
+
+def bias_B(params: dict, xa, xc) -> float:
+    """B_ins of Eq. (12) for an anion at xa and a cation at xc."""
+    p = make_params(params)
+    a = np.ascontiguousarray(xa, dtype=np.float64)
+    c = np.ascontiguousarray(xc, dtype=np.float64)
+    return lib().or_bias_B(C.byref(p), _dp(a), _dp(c))
+
+
+def bias_offset(params: dict, trial: int, d: int) -> float:
+    """The anion offset of an insertion along edge d (a draw from Eq. 14)."""
+    p = make_params(params)
+    return lib().or_bias_offset(C.byref(p), trial, d)
