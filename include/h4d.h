@@ -114,6 +114,9 @@ typedef struct h4d_params {
     double accel;               /* acceleration per force/mass                   */
     uint64_t seed, stream;      /* Philox key (box b of a batch: seed,
                                    stream + b)                                  */
+    double bias_xb, bias_alpha; /* bimodal bias of the flying pair (Sec. II B 4,
+                                   Eqs. 12-16), see h4d_set_bias; bias_alpha = 0:
+                                   the uniform placement of Eq. (4)             */
 } h4d_params;
 
 /* One trial (move +1 insertion, -1 deletion). */
@@ -253,6 +256,24 @@ int32_t h4d_set_beta_mu(h4d_system *sys, double beta_mu);
 
 /* Set the next trial index of every box (default 0). */
 int32_t h4d_set_trial_index(h4d_system *sys, uint64_t trial);
+
+/*
+ * Bimodal bias of the flying pair's separation (Sec. II B 4, Eqs. 12-16),
+ * for the following trials (alpha_b = 0: off).  An insertion places the
+ * cation uniformly and the anion at an offset drawn along each edge from
+ * Eq. (14): Gaussians of exponent alpha_b at +-x_b, normalised on the edge,
+ * the offset taken as the minimum image (Philox counters (trial, 6,
+ * 4 attempt + edge, 0): a uniform picks the sign, Box-Muller the normal, a
+ * draw beyond half an edge is redrawn).  A deletion picks the cation by
+ * rank as before and the anion with probability B_ins(r_a, r_c) / W in tag
+ * order (Eq. 13), W the sum over the anions of B_ins = V prod b (Eq. 12).
+ * ln R gains ln((N+1) / W) for an insertion (W over the anions of the state
+ * its trajectory reached) and ln(W / (N+1)) for a deletion (W over those of
+ * its start state), Eqs. (15)-(16); the factor is reported in
+ * h4d_trial.ln_proposal.  Requires x_b + 6 / sqrt(2 alpha_b) <= half of
+ * every box edge; exclusive with the learned proposal.
+ */
+int32_t h4d_set_bias(h4d_system *sys, double x_b, double alpha_b);
 
 /*
  * Test hook (single-box handles): forces and FP64 energy of the current state with atoms

@@ -28,7 +28,7 @@ constexpr unsigned kErrFast = 0x10u;  // fast-atom list full
 constexpr unsigned kErrNonfinite = 0x20u;  // a position became non-finite (the trajectory blew up)
 
 // purposes of the counter-based generator
-constexpr uint64_t kPurposeSelect = 1, kPurposeMB = 2, kPurposeNsteps = 3;
+constexpr uint64_t kPurposeSelect = 1, kPurposeMB = 2, kPurposeNsteps = 3, kPurposeBias = 6;
 
 // --------------------------------------------------------------------------
 // Philox4x64-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of two
@@ -77,6 +77,9 @@ struct Geo {
     // (O at (0, ra), H at (-rc_w, -rb) and (rc_w, -rb))
     double m_o, m_h, ra, rb, rc_w;
     int n_mol;
+    // bimodal bias of the flying anion's offset from the cation (Sec. II B 4,
+    // Eq. 14); bias_alpha = 0: the uniform placement of Eq. (4)
+    double bias_xb, bias_alpha;
 };
 
 // --------------------------------------------------------------------------
@@ -95,6 +98,7 @@ struct Box {
     int c0, nc;
     double volume;
     uint64_t stream;         // second word of this box's Philox key
+    double bias_c[3];        // Eq. (14) normalisation per edge: sqrt(alpha / pi) / (erf - erf)
 };
 
 // per type-pair coefficients, indexed ti * kMaxTypes + tj

@@ -179,6 +179,38 @@ __device__ __forceinline__ void bin_atom(const KArgs &a, const Box &B, Ctl *c, i
 // pair of an insertion, rank selection of a deletion (Eqs. 3-4; insertion
 // or deletion with probability 1/2).  A box that has run its quota idles.
 // ==========================================================================
+// Bimodal bias (Sec. II B 4).  B_ins of Eq. (12) for an anion at pa and a
+// cation at pc: V times the Eq. (14) density of the minimum-image offset
+// along each edge.
+__device__ __forceinline__ double bias_B(const KArgs &a, const Box &B, const double4 &pa, const double4 &pc) {
+    const double al = a.G.bias_alpha, xb = a.G.bias_xb;
+    const double d[3] = {min_image(pa.x - pc.x, B.L[0]), min_image(pa.y - pc.y, B.L[1]),
+                         min_image(pa.z - pc.z, B.L[2])};
+    double v = B.volume;
+    for (int q = 0; q < 3; ++q)
+        v *= B.bias_c[q] * (exp(-al * (d[q] - xb) * (d[q] - xb)) + exp(-al * (d[q] + xb) * (d[q] + xb)));
+    return v;
+}
+
+// The insertion's anion offset along edge d: the Gaussian at -x_b or +x_b
+// by one uniform, Box-Muller from it, redrawn (next attempt's counters)
+// until it lies within half an edge -- a draw from Eq. (14).  The bias
+// parameters are checked so that a redraw is all but never needed.
+__device__ __forceinline__ double bias_offset(const KArgs &a, const Box &B, uint64_t t, int d) {
+    const double half = 0.5 * B.L[d];
+    const double sd = 1.0 / sqrt(2.0 * a.G.bias_alpha);
+    double mu = a.G.bias_xb;
+    for (int attempt = 0; attempt < 64; ++attempt) {
+        const u64x4 r = philox(t, kPurposeBias, (uint64_t)(4 * attempt + d), 0, a.seed, B.stream);
+        mu = unit_open(r.v[0]) < 0.5 ? -a.G.bias_xb : a.G.bias_xb;
+        const double z = sqrt(-2.0 * log(unit_open(r.v[1]))) *
+                         cos(6.283185307179586476925286766559 * unit_open(r.v[2]));
+        const double x = mu + z * sd;
+        if (fabs(x) <= half) return x;
+    }
+    return mu;
+}
+
 __global__ __launch_bounds__(kBlock) void k_propose(KArgs a, int force_move) {
     const int bi = blockIdx.x;
     const Box &B = a.box[bi];
@@ -223,9 +255,17 @@ __global__ __launch_bounds__(kBlock) void k_propose(KArgs a, int force_move) {
                 a.cpos[ic] = with_meta(wrap_coord(B.L[0] * c->u[1], B.L[0]),
                                        wrap_coord(B.L[1] * c->u[2], B.L[1]),
                                        wrap_coord(B.L[2] * c->u[3], B.L[2]), tcat | kFlyBit);
-                a.cpos[ia] = with_meta(wrap_coord(B.L[0] * c->u[4], B.L[0]),
-                                       wrap_coord(B.L[1] * c->u[5], B.L[1]),
-                                       wrap_coord(B.L[2] * c->u[6], B.L[2]), tan | kFlyBit);
+                if (a.G.bias_alpha > 0.0) {   // Sec. II B 4: offset from the cation drawn from Eq. (14)
+                    const uint64_t t = (uint64_t)c->trial;
+                    a.cpos[ia] = with_meta(wrap_coord(B.L[0] * c->u[1] + bias_offset(a, B, t, 0), B.L[0]),
+                                           wrap_coord(B.L[1] * c->u[2] + bias_offset(a, B, t, 1), B.L[1]),
+                                           wrap_coord(B.L[2] * c->u[3] + bias_offset(a, B, t, 2), B.L[2]),
+                                           tan | kFlyBit);
+                } else {
+                    a.cpos[ia] = with_meta(wrap_coord(B.L[0] * c->u[4], B.L[0]),
+                                           wrap_coord(B.L[1] * c->u[5], B.L[1]),
+                                           wrap_coord(B.L[2] * c->u[6], B.L[2]), tan | kFlyBit);
+                }
                 a.ctag[ic] = c->next_tag; a.ctag[ia] = c->next_tag + 1;
                 a.ctype[ic] = tcat; a.ctype[ia] = tan;
                 a.cmol[ic] = -1; a.cmol[ia] = -1;
@@ -263,10 +303,45 @@ __global__ __launch_bounds__(kBlock) void k_propose(KArgs a, int force_move) {
         for (int i = lo; i < hi; ++i)
             if (a.ctype[i] == a.cation_type) { if (r == s_kc) { s_ic = i; break; } ++r; }
     }
-    if (s_ka >= pa && s_ka < pa + na) {
+    if (a.G.bias_alpha <= 0.0 && s_ka >= pa && s_ka < pa + na) {
         int r = pa;
         for (int i = lo; i < hi; ++i)
             if (a.ctype[i] == a.anion_type) { if (r == s_ka) { s_ia = i; break; } ++r; }
+    }
+    __syncthreads();
+    if (a.G.bias_alpha > 0.0 && s_ic >= 0) {
+        // Eq. (13): the anion with probability B_ins(r_a, r_c) / W, the first
+        // in tag (canonical) order whose running sum exceeds u W; ln of
+        // B_ins / B_del = W / (N + 1) for Eq. (16)
+        __shared__ double s_w[kBlock];
+        __shared__ double s_target;
+        const double4 pc = a.cpos[s_ic];
+        double part = 0.0;
+        for (int i = lo; i < hi; ++i)
+            if (a.ctype[i] == a.anion_type) part += bias_B(a, B, a.cpos[i], pc);
+        s_w[tid] = part;
+        __syncthreads();
+        if (tid == 0) {
+            double run = 0.0;
+            for (int q = 0; q < kBlock; ++q) { const double v = s_w[q]; s_w[q] = run; run += v; }
+            s_target = c->u[2] * run;
+            c->lnq = log(run) - log((double)c->nsalt);
+        }
+        __syncthreads();
+        const double start = s_w[tid], tg = s_target;
+        if (tg >= start && tg < start + part) {
+            double run = start;
+            for (int i = lo; i < hi; ++i)
+                if (a.ctype[i] == a.anion_type) {
+                    run += bias_B(a, B, a.cpos[i], pc);
+                    if (run > tg) { s_ia = i; break; }
+                }
+        }
+        __syncthreads();
+        if (tid == 0 && s_ia < 0) {   // rounding at the top end: the last anion
+            for (int i = B.a0 + n - 1; i >= B.a0; --i)
+                if (a.ctype[i] == a.anion_type) { s_ia = i; break; }
+        }
     }
     __syncthreads();
     if (tid == 0) {
@@ -1198,6 +1273,35 @@ __global__ void k_metropolis(KArgs a) {
     if (c->retry) acc = 0;
     r->accepted = acc;
     c->accepted = acc;
+}
+
+// Bimodal bias, insertion (Eq. 15): ln of B_del / B_ins = (N + 1) / W, W the
+// sum of B_ins(r_a, r_c) over the anions of the (N+1)-state the trajectory
+// reached (final working buffer, the cation fixed in 3D); one block per box,
+// chunk sums combined in a fixed order.
+__global__ __launch_bounds__(kBlock) void k_bias_end(KArgs a) {
+    const int bi = blockIdx.x, tid = threadIdx.x;
+    const Box &B = a.box[bi];
+    Ctl *c = a.ctl + bi;
+    if (c->move <= 0 || a.G.bias_alpha <= 0.0) return;
+    __shared__ double s_w[kBlock];
+    const int b = buf_of(-1, c);
+    const double4 pc = a.pos[b][c->wic];
+    const int n = c->n_all;
+    const int chunk = (n + kBlock - 1) / kBlock;
+    const int lo = B.a0 + tid * chunk, hi = B.a0 + min(n, tid * chunk + chunk);
+    double part = 0.0;
+    for (int i = lo; i < hi; ++i) {
+        const double4 p = a.pos[b][i];
+        if ((meta_of(p) & kTypeMask) == a.anion_type) part += bias_B(a, B, p, pc);
+    }
+    s_w[tid] = part;
+    __syncthreads();
+    if (tid == 0) {
+        double W = 0.0;
+        for (int q = 0; q < kBlock; ++q) W += s_w[q];
+        c->lnq = log((double)(c->nsalt + 1)) - log(W);
+    }
 }
 
 // Commit (accepted: the working positions go back to canonical order, ghosts

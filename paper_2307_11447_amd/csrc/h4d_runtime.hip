@@ -209,6 +209,32 @@ void setup_geo(h4d_system *s) {
 
 int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
+// Bimodal bias (Sec. II B 4): parameters into Geo and the Eq. (14)
+// normalisation of every box edge; the Gaussians (6 standard deviations out
+// from +-x_b) must fit within half an edge, so that a drawn offset all but
+// never has to be redrawn.
+int setup_bias(h4d_system *s, double xb, double alpha) {
+    if (!(std::isfinite(xb) && std::isfinite(alpha)) || xb < 0.0 || alpha < 0.0)
+        return fail(H4D_EINVAL, "bias_xb and bias_alpha must be finite and >= 0");
+    if (alpha > 0.0) {
+        const double reach = xb + 6.0 / std::sqrt(2.0 * alpha);
+        for (const Box &B : s->box_h)
+            for (int d = 0; d < 3; ++d)
+                if (reach > 0.5 * B.L[d])
+                    return fail(H4D_EINVAL, "bias: x_b + 6 / sqrt(2 alpha_b) must not exceed half a box edge");
+    }
+    s->a.G.bias_xb = alpha > 0.0 ? xb : 0.0;
+    s->a.G.bias_alpha = alpha;
+    for (Box &B : s->box_h)
+        for (int d = 0; d < 3; ++d) {
+            const double sa = std::sqrt(alpha);
+            B.bias_c[d] = alpha > 0.0 ? std::sqrt(alpha / 3.14159265358979323846) /
+                                            (std::erf(sa * (xb + 0.5 * B.L[d])) - std::erf(sa * (xb - 0.5 * B.L[d])))
+                                      : 0.0;
+        }
+    return H4D_OK;
+}
+
 // Geometry and placement of every box: slots [a0, a0 + cap), cells [c0, c0 + nc).
 int setup_boxes(h4d_system *s, const double *edges, const int32_t *n_atoms) {
     const h4d_params &p = s->p;
@@ -500,6 +526,7 @@ int enqueue_round(h4d_system *s, int move, hipStream_t st, int nf, int M, bool t
     hipLaunchKernelGGL(k_energy, dim3(a.step_blocks), dim3(kBlock), 0, st, a, 1, -1, 0.0, -1);
     hipLaunchKernelGGL(k_energy_final, dim3(s->nbox), dim3(kBlock), 0, st, a, 1);
     if (s->la.k > 0) enqueue_learned(s, st, 1, -1, s->cl);   // learned deletion: reverse weights
+    if (a.G.bias_alpha > 0.0) hipLaunchKernelGGL(k_bias_end, dim3(s->nbox), dim3(kBlock), 0, st, a);
     hipLaunchKernelGGL(k_metropolis, dim3(blocks_for(s->nbox)), dim3(kBlock), 0, st, a);
     hipLaunchKernelGGL(k_commit, dim3(G1), dim3(kBlock), 0, st, a);
     hipLaunchKernelGGL(k_compact1, dim3(G1), dim3(kBlock), 0, st, a);
@@ -769,6 +796,7 @@ int create(const h4d_params *params, int nbox, const double *edges, const int32_
     s->stats.assign(nbox, h4d_system::Stats{});
     setup_geo(s);
     if ((rc = setup_boxes(s, edges, n_atoms))) { delete s; return rc; }
+    if ((rc = setup_bias(s, params->bias_xb, params->bias_alpha))) { delete s; return rc; }
     if (params->water) {
         Geo &G = s->a.G;
         G.n_mol = n_mol;
@@ -1104,6 +1132,19 @@ int32_t h4d_set_beta_mu(h4d_system *s, double beta_mu) {
     s->p.beta_mu = beta_mu;
     s->a.G.beta_mu = beta_mu;
     s->drop_graphs();       // the captured launches hold the old value
+    return H4D_OK;
+}
+
+int32_t h4d_set_bias(h4d_system *s, double x_b, double alpha_b) {
+    if (!s) return fail(H4D_EINVAL, "null handle");
+    if (alpha_b > 0.0 && s->la.k > 0)
+        return fail(H4D_EINVAL, "the bimodal bias and the learned proposal are exclusive");
+    int rc = setup_bias(s, x_b, alpha_b);
+    if (rc) return rc;
+    s->p.bias_xb = x_b;
+    s->p.bias_alpha = alpha_b;
+    HIPC(hipMemcpy(const_cast<Box *>(s->a.box), s->box_h.data(), sizeof(Box) * s->nbox, hipMemcpyHostToDevice));
+    s->drop_graphs();       // the captured launches hold the old parameters
     return H4D_OK;
 }
 
@@ -1611,6 +1652,8 @@ int32_t h4d_set_proposal(h4d_system *s, const h4d_mlp *net, int32_t k, double lo
         return fail(H4D_EINVAL, "logit_cap must not be NaN and weight_scale must be finite and >= 0");
     if (k > 65536) return fail(H4D_EINVAL, "at most 65536 candidates");
     if (k > 0 && s->nbox != 1) return fail(H4D_EINVAL, "the learned proposal serves single-box systems");
+    if (k > 0 && s->a.G.bias_alpha > 0.0)
+        return fail(H4D_EINVAL, "the bimodal bias and the learned proposal are exclusive");
     s->drop_graphs();
     LearnArgs &l = s->la;
     for (void *q : {(void *)l.sites, (void *)l.feat, (void *)l.logit}) if (q) s->release(q);

@@ -40,6 +40,7 @@ class Params(C.Structure):
         ("coulomb_k", C.c_double), ("beta_mu", C.c_double), ("lambda_s", C.c_double),
         ("skin", C.c_double), ("d_oh", C.c_double), ("d_hh", C.c_double), ("accel", C.c_double),
         ("seed", C.c_uint64), ("stream", C.c_uint64),
+        ("bias_xb", C.c_double), ("bias_alpha", C.c_double),
     ]
 
 
@@ -145,6 +146,7 @@ def lib() -> C.CDLL:
         L.h4d_last_candidates.argtypes = [vp, C.c_int32, dp, fp, fp]
         L.h4d_site_features.argtypes = [vp, C.c_int32, dp, fp]
         L.h4d_set_beta_mu.argtypes = [vp, C.c_double]
+        L.h4d_set_bias.argtypes = [vp, C.c_double, C.c_double]
         for name in ("h4d_stream_copy", "h4d_set_timing", "h4d_get_timing", "h4d_init_system", "h4d_build_neighbors",
                      "h4d_run_nemd_trial", "h4d_run_trials", "h4d_sample_observables", "h4d_get_state",
                      "h4d_set_trial_index", "h4d_forces_at", "h4d_destroy", "h4d_init_batch", "h4d_num_boxes",
@@ -152,7 +154,7 @@ def lib() -> C.CDLL:
                      "h4d_mlp_create", "h4d_mlp_destroy", "h4d_mlp_set_weights", "h4d_mlp_get_weights",
                      "h4d_mlp_forward", "h4d_mlp_loss_grad", "h4d_mlp_train", "h4d_set_proposal",
                      "h4d_last_site_features", "h4d_last_candidates", "h4d_site_features", "h4d_set_beta_mu",
-                     "h4d_init_speculative", "h4d_run_speculative"):
+                     "h4d_init_speculative", "h4d_run_speculative", "h4d_set_bias"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -175,6 +177,7 @@ def make_params(d: dict) -> Params:
     p.capacity = d.get("capacity", 0)
     p.rebuild_every = d.get("rebuild_every", 0)
     p.lanes_per_atom = d.get("lanes_per_atom", 0)
+    p.bias_xb, p.bias_alpha = d.get("bias_xb", 0.0), d.get("bias_alpha", 0.0)
     for name in ("mass", "charge", "sigma", "eps"):
         arr = getattr(p, name)
         for i, v in enumerate(d[name]):
@@ -307,6 +310,10 @@ class _Handle:
 
     def set_trial_index(self, t: int):
         _check(lib().h4d_set_trial_index(self._h, t))
+
+    def set_bias(self, x_b: float, alpha_b: float):
+        """Bimodal bias of the flying pair's separation (alpha_b = 0: off)."""
+        _check(lib().h4d_set_bias(self._h, x_b, alpha_b))
 
     def set_beta_mu(self, beta_mu: float):
         _check(lib().h4d_set_beta_mu(self._h, beta_mu))
