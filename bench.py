@@ -243,11 +243,14 @@ def proposal_ab(sys_, torch, h4d, arms, beta_mu, n_each, block=50):
     done = 0
     while done < n_each:
         nb = min(block, n_each - done)
-        for name, (net, k, scale) in arms.items():
+        for name, (net, k, scale, bias) in arms.items():
+            sys_.set_bias(0.0, 0.0)
             if k > 0:
                 sys_.set_proposal(net, k, 10.0, scale)
             else:
                 sys_.set_proposal(None, 0)
+            if bias is not None:
+                sys_.set_bias(*bias)
             for move, bm, key in ((h4d.MOVE_INSERT, -1.0e3, "ins"), (h4d.MOVE_DELETE, 1.0e3, "del")):
                 sys_.set_beta_mu(bm)
                 torch.cuda.synchronize()
@@ -263,6 +266,7 @@ def proposal_ab(sys_, torch, h4d, arms, beta_mu, n_each, block=50):
                     out[name][key].append(math.exp(min(0.0, r.ln_ratio + shift)) if ok else 0.0)
         done += nb
     sys_.set_proposal(None, 0)
+    sys_.set_bias(0.0, 0.0)
     sys_.set_beta_mu(beta_mu)
     res = {}
     for name, o in out.items():
@@ -274,12 +278,16 @@ def proposal_ab(sys_, torch, h4d, arms, beta_mu, n_each, block=50):
                      "insertions": len(o["ins"]), "deletions": len(o["del"])}
     if "uniform" in out and "learned" in out:
         res["gain"], res["gain_bootstrap90"] = ab_gain(out["uniform"], out["learned"])
+    if "uniform" in out and "bimodal" in out:
+        res["bimodal_gain"], res["bimodal_gain_bootstrap90"] = ab_gain(out["uniform"], out["bimodal"])
     return res
 
 
 def ab_gain(u, l, reps=2000, seed=11):
-    """Ratio of expected exchanges per second (learned over uniform) and its
-    90 % bootstrap interval (moves resampled within each arm and kind)."""
+    """Ratio of expected exchanges per second (another proposal over the
+    uniform one) and its 90 % bootstrap interval (moves resampled within
+    each arm and kind); None when the uniform arm's expected acceptance is
+    below 1e-12 (the ratio is then meaningless)."""
     import numpy as np
     rng = np.random.default_rng(seed)
     rate_u, rate_l = u["n"] / u["s"], l["n"] / l["s"]
@@ -288,7 +296,9 @@ def ab_gain(u, l, reps=2000, seed=11):
         return 0.5 * (np.mean(pick(o["ins"])) + np.mean(pick(o["del"]))) * rate
 
     ident = np.asarray
-    g = ex(l, rate_l, ident) / max(1e-300, ex(u, rate_u, ident))
+    if ex(u, rate_u, ident) < 1e-12:       # the uniform arm's acceptance underflows: no ratio
+        return None, None
+    g = ex(l, rate_l, ident) / ex(u, rate_u, ident)
     boot = []
     for _ in range(reps):
         def res(x):
@@ -307,6 +317,11 @@ def timed_trials(sys_, torch, n):
     torch.cuda.synchronize()
     return [arr[q] for q in range(n)], time.perf_counter() - t0
 
+
+# bimodal bias of the flying pair (x_b, alpha_b; Sec. II B 4): the paper's
+# aqueous NaCl choice (4 A, 0.1 / A^2), and a contact-distance bias for the
+# LJ ions (sigma = 1)
+BIAS = {"lj32k": (1.0, 2.0), "water": (4.0, 0.1)}
 
 SINGLE = {
     "lj32k": ("config_lj_32k",
@@ -436,9 +451,10 @@ def bench_single(args, h4d, W, torch):
     sys_.set_proposal(None, 0)
     # both proposals on the state the chains reached, alternating, with
     # forced moves that leave it unchanged
-    arms = {"uniform": (None, 0, 0.0)}
+    arms = {"uniform": (None, 0, 0.0, None)}
     if scale_sel > 0.0:
-        arms["learned"] = (net, k_sel, scale_sel)
+        arms["learned"] = (net, k_sel, scale_sel, None)
+    arms["bimodal"] = (None, 0, 0.0, BIAS[args.workload])
     ab = proposal_ab(sys_, torch, h4d, arms, beta_mu, args.ab_trials) if args.ab_trials > 0 else None
     if ab is not None:
         note(f"fixed-state comparison: {args.ab_trials} insertions and deletions per proposal")
@@ -495,9 +511,15 @@ def bench_single(args, h4d, W, torch):
         "train_loss_first": float(losses[:10].mean()), "train_loss_last": float(losses[-50:].mean()),
         "target": "clip(beta mu + I - beta dH, -100, 10)",
         "fixed_state_comparison": ab,
-        "fixed_state_gain": ab.get("gain", 1.0) if ab is not None else None,
+        "fixed_state_gain": ab.get("gain", 1.0 if scale_sel == 0.0 else None) if ab is not None else None,
         "fixed_state_gain_bootstrap90": ab.get("gain_bootstrap90") if ab is not None else None,
         "out_of_fold_corr_logit_vs_target": oof_corr,
+    }
+    out["bimodal_bias"] = {
+        "x_b": BIAS[args.workload][0], "alpha_b": BIAS[args.workload][1],
+        "note": "the paper's bias of the flying pair's separation (Sec. II B 4), in the fixed-state comparison",
+        "fixed_state_gain": ab.get("bimodal_gain") if ab is not None else None,
+        "fixed_state_gain_bootstrap90": ab.get("bimodal_gain_bootstrap90") if ab is not None else None,
     }
     config = dict({"workload": desc + "; value: uniform proposal" +
                    (f", {args.replicas} speculative replicas of the one chain" if speculative else "") +
@@ -575,7 +597,7 @@ def main():
                          "(default 300 / water 60)")
     ap.add_argument("--ab-trials", type=int, default=None,
                     help="single box: forced insertions and deletions per proposal on the final state "
-                         "(default 400 / water 600)")
+                         "(default 400)")
     ap.add_argument("--timing-trials", type=int, default=None,
                     help="trials run after the timed region with HIP events on the step kernel (20 / 2)")
     ap.add_argument("--cpu-steps", type=int, default=12, help="oracle sample length (NEMD steps)")
@@ -608,7 +630,7 @@ def main():
     if args.pilot is None:
         args.pilot = 1000 if water else 1200
     if args.ab_trials is None:
-        args.ab_trials = 600 if water else 400
+        args.ab_trials = 400
     if args.seq_steps is None:
         args.seq_steps = 60 if water else 300
     if batched and args.beta_mu is None:
