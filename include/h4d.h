@@ -83,8 +83,9 @@ extern "C" {
  *   A pair that involves exactly one flying atom uses the 4D distance
  *     sqrt(r^2 + w^2) (Sec. I, Sec. II C); both cutoffs apply to it.
  *   w follows Eq. (2): w_max -> 0 for an insertion, 0 -> w_max for a
- *     deletion, in n_steps steps of dt; the flying ions stay fixed in 3D
- *     (trick (i) of Sec. II B).
+ *     deletion, in n_steps steps of dt (or one of the supplement's
+ *     variable-velocity schedules, field schedule); the flying ions stay
+ *     fixed in 3D (trick (i) of Sec. II B).
  *   water = 1: the first 3*n_mol atoms are rigid 3-site waters (O, H, H),
  *     bond lengths d_oh and d_hh, intramolecular pairs excluded.
  */
@@ -101,7 +102,10 @@ typedef struct h4d_params {
     int32_t rebuild_every;      /* neighbour-list rebuild interval (0: auto)   */
     int32_t lanes_per_atom;     /* lanes per atom in list traversals: 4, 8, 16
                                    (0: chosen from the atom count)              */
-    int32_t reserved0;
+    int32_t schedule;           /* altitude schedule: 0 constant vertical
+                                   velocity (Eq. 2); 1 w_max (1 - x^n); 2
+                                   w_max (1 - x)^n, x = k / n_steps for an
+                                   insertion, the time reversal for a deletion */
     double mass[H4D_MAX_TYPES], charge[H4D_MAX_TYPES];
     double sigma[H4D_MAX_TYPES], eps[H4D_MAX_TYPES];
     double box[3];              /* orthorhombic edges; each >= 2 max cutoff     */
@@ -117,6 +121,7 @@ typedef struct h4d_params {
     double bias_xb, bias_alpha; /* bimodal bias of the flying pair (Sec. II B 4,
                                    Eqs. 12-16), see h4d_set_bias; bias_alpha = 0:
                                    the uniform placement of Eq. (4)             */
+    double schedule_n;          /* exponent n >= 1 of schedules 1 and 2         */
 } h4d_params;
 
 /* One trial (move +1 insertion, -1 deletion). */

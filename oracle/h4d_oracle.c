@@ -445,7 +445,14 @@ int or_constrain_velocities(const or_params *p, or_state *s)
 double or_altitude(const or_params *p, int move, int k, int nf)
 {
     /* Eq. (2), constant vertical velocity: insertion from w_max down to 0,
-     * deletion from 0 up to w_max. */
+     * deletion from 0 up to w_max.  The supplement's variable-velocity
+     * schedules, with x the insertion's reduced time k / nf:
+     * w_max (1 - x^n) and w_max (1 - x)^n.  A deletion runs the insertion's
+     * schedule backwards in time (x = (nf - k) / nf), the reverse path that
+     * detailed balance pairs with it. */
+    const int j = move > 0 ? k : nf - k;
+    if (p->schedule == 1) return p->w_max * (1.0 - pow((double)j / (double)nf, p->schedule_n));
+    if (p->schedule == 2) return p->w_max * pow(1.0 - (double)j / (double)nf, p->schedule_n);
     if (move > 0) return p->w_max * (double)(nf - k) / (double)nf;
     return p->w_max * (double)k / (double)nf;
 }

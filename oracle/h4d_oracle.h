@@ -38,6 +38,8 @@ typedef struct {
     uint64_t seed, stream;  /* Philox key                                        */
     double bias_xb;         /* bimodal bias of the flyers' separation (Sec.      */
     double bias_alpha;      /* II B 4, Eq. 14): x_b and alpha_b; alpha_b = 0: off */
+    int32_t schedule;       /* altitude: 0 Eq. (2); 1 w_max (1 - x^n); 2         */
+    double schedule_n;      /* w_max (1 - x)^n (supplement), exponent n           */
 } or_params;
 
 /* Configuration.  Arrays are owned by the caller and sized to cap. */

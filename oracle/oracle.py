@@ -34,6 +34,7 @@ class Params(C.Structure):
         ("d_oh", C.c_double), ("d_hh", C.c_double), ("accel", C.c_double),
         ("seed", C.c_uint64), ("stream", C.c_uint64),
         ("bias_xb", C.c_double), ("bias_alpha", C.c_double),
+        ("schedule", C.c_int32), ("schedule_n", C.c_double),
     ]
 
 
@@ -137,6 +138,7 @@ def make_params(d: dict, use_cells: bool = True) -> Params:
     p.accel = d.get("accel", 1.0)
     p.seed, p.stream = d["seed"], d.get("stream", 0)
     p.bias_xb, p.bias_alpha = d.get("bias_xb", 0.0), d.get("bias_alpha", 0.0)
+    p.schedule, p.schedule_n = d.get("schedule", 0), d.get("schedule_n", 1.0)
     return p
 
 

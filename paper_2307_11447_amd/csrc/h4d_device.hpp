@@ -80,6 +80,9 @@ struct Geo {
     // bimodal bias of the flying anion's offset from the cation (Sec. II B 4,
     // Eq. 14); bias_alpha = 0: the uniform placement of Eq. (4)
     double bias_xb, bias_alpha;
+    // altitude schedule (see altitude())
+    int schedule;
+    double schedule_n;
 };
 
 // --------------------------------------------------------------------------
@@ -110,8 +113,17 @@ struct PairCoef {
 // --------------------------------------------------------------------------
 // Altitude schedule, Eq. (2): constant vertical velocity.
 // --------------------------------------------------------------------------
-__device__ __forceinline__ double altitude(double w_max, int move, int k, int nf) {
-    return move > 0 ? w_max * (double)(nf - k) / (double)nf : w_max * (double)k / (double)nf;
+// Altitude of the flyers before step k of nf.  An insertion runs the
+// schedule forwards from w_max to 0, a deletion backwards (j = nf - k), so
+// each is the time reversal of the other.  schedule 0: constant vertical
+// velocity (Eq. 2); 1: w_max (1 - x^n) and 2: w_max (1 - x)^n, x = j / nf
+// (the two variable-velocity schedules of the supplement; n = 1 gives
+// Eq. 2 again).
+__device__ __forceinline__ double altitude(const Geo &G, int move, int k, int nf) {
+    const int j = move > 0 ? k : nf - k;
+    if (G.schedule == 0) return G.w_max * (double)(nf - j) / (double)nf;
+    const double x = (double)j / (double)nf;
+    return G.w_max * (G.schedule == 1 ? 1.0 - pow(x, G.schedule_n) : pow(1.0 - x, G.schedule_n));
 }
 
 // Periodic wrap into [0, L) of a coordinate less than one box edge outside

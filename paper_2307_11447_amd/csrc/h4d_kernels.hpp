@@ -939,8 +939,8 @@ __device__ void flyer_work(const KArgs &a, const Box &B, Ctl *c, const CoefLds &
     if (move == 0 || k > nf) return;
     const int f = wave == 0 ? c->wic : c->wia;
     const int other = wave == 0 ? c->wia : c->wic;
-    const double wlo = altitude(a.G.w_max, move, k > 0 ? k - 1 : 0, nf);
-    const double whi = altitude(a.G.w_max, move, k < nf ? k + 1 : nf, nf);
+    const double wlo = altitude(a.G, move, k > 0 ? k - 1 : 0, nf);
+    const double whi = altitude(a.G, move, k < nf ? k + 1 : nf, nf);
     double dsum = 0.0;
     const int nn = a.nnbr[f];
     // the flyer's list (partners that are now fast are taken from the fast list)
@@ -1040,7 +1040,7 @@ __global__ __launch_bounds__(kBlock) void k_step(KArgs a, int k, int b, int bin,
     const int mi = meta_of(pi);
     const bool fly = (mi & kFlyBit) != 0;
     const int ti = mi & kTypeMask;
-    const double wv = altitude(a.G.w_max, move, k, nf);
+    const double wv = altitude(a.G, move, k, nf);
     const double gscr = exp(-a.G.kappa * wv);
     double fx = 0.0, fy = 0.0, fz = 0.0;
     if (act && !fly) group_force<PREC, L>(a, B, c, cf, b, cl, wc, s, pi, mi, wv, gscr, flist, nfast, fx, fy, fz);

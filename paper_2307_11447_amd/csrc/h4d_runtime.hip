@@ -138,6 +138,8 @@ int check_params(const h4d_params &p) {
     if (!(p.rc_lj > 0.0) || !(p.rc_coul > 0.0) || !(p.skin >= 0.0) || !(p.w_max >= 0.0) ||
         !(p.dsf_alpha >= 0.0))
         return fail(H4D_EINVAL, "cutoffs must be positive, skin, w_max and dsf_alpha non-negative");
+    if (p.schedule < 0 || p.schedule > 2 || (p.schedule != 0 && !(p.schedule_n >= 1.0 && std::isfinite(p.schedule_n))))
+        return fail(H4D_EINVAL, "schedule must be 0, 1 or 2, with schedule_n >= 1 for 1 and 2");
     if (p.water && !(p.d_oh > 0.0 && p.d_hh > 0.0 && p.d_hh < 2.0 * p.d_oh))
         return fail(H4D_EINVAL, "rigid water needs 0 < d_hh < 2 d_oh");
     return H4D_OK;
@@ -179,6 +181,8 @@ void setup_geo(h4d_system *s) {
     G.accel = p.accel;
     G.kT = p.kT;
     G.w_max = p.w_max;
+    G.schedule = p.schedule;
+    G.schedule_n = p.schedule_n;
     G.kappa = p.kappa_sr;
     G.lambda3 = p.lambda_s * p.lambda_s * p.lambda_s;
     G.beta = 1.0 / p.kT;

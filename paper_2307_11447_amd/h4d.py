@@ -31,7 +31,7 @@ class Params(C.Structure):
         ("n_types", C.c_int32), ("cation_type", C.c_int32), ("anion_type", C.c_int32),
         ("n_steps", C.c_int32), ("n_steps_min", C.c_int32), ("n_steps_max", C.c_int32),
         ("water", C.c_int32), ("precision", C.c_int32), ("capacity", C.c_int32),
-        ("rebuild_every", C.c_int32), ("lanes_per_atom", C.c_int32), ("reserved0", C.c_int32),
+        ("rebuild_every", C.c_int32), ("lanes_per_atom", C.c_int32), ("schedule", C.c_int32),
         ("mass", C.c_double * MAX_TYPES), ("charge", C.c_double * MAX_TYPES),
         ("sigma", C.c_double * MAX_TYPES), ("eps", C.c_double * MAX_TYPES),
         ("box", C.c_double * 3),
@@ -41,6 +41,7 @@ class Params(C.Structure):
         ("skin", C.c_double), ("d_oh", C.c_double), ("d_hh", C.c_double), ("accel", C.c_double),
         ("seed", C.c_uint64), ("stream", C.c_uint64),
         ("bias_xb", C.c_double), ("bias_alpha", C.c_double),
+        ("schedule_n", C.c_double),
     ]
 
 
@@ -178,6 +179,7 @@ def make_params(d: dict) -> Params:
     p.rebuild_every = d.get("rebuild_every", 0)
     p.lanes_per_atom = d.get("lanes_per_atom", 0)
     p.bias_xb, p.bias_alpha = d.get("bias_xb", 0.0), d.get("bias_alpha", 0.0)
+    p.schedule, p.schedule_n = d.get("schedule", 0), d.get("schedule_n", 1.0)
     for name in ("mass", "charge", "sigma", "eps"):
         arr = getattr(p, name)
         for i, v in enumerate(d[name]):

@@ -324,3 +324,20 @@ def test_full_size_trials_32k_fp32():
             assert np.array_equal(after["x"], st["x"]) and np.array_equal(after["tag"], st["tag"])
         assert after["n"] == 2 * after["nsalt"]
     g.close()
+
+
+@pytest.mark.parametrize("schedule,n", [(1, 2.0), (2, 3.0)])
+def test_variable_schedule_trials_match_oracle(schedule, n):
+    say(f"case trials lj500 fp64, altitude schedule {schedule} (n = {n}), 20 trials")
+    w = W.config_lj_500()
+    w.params.update(beta_mu=6.0, schedule=schedule, schedule_n=n)
+    g = h4d.System.from_workload(w)
+    o = O.OracleSystem.from_workload(w, cap=w.n + 200)
+    for t in range(20):
+        rg, ro = g.trial(), o.trial(t)
+        assert rg["move"] == ro["move"] and rg["flags"] & 0x3 == ro["flags"]
+        if not ro["flags"]:
+            for key in ("dH", "W_prot", "E_switch", "H0", "H1"):
+                assert rel_close(rg[key], ro[key], 1e-6), (t, key, rg[key], ro[key])
+        assert rg["accepted"] == ro["accepted"], (t, rg, ro)
+    g.close()

@@ -3,6 +3,7 @@ oracle itself: a published generator, closed forms of the potentials,
 calculus (finite differences), conservation laws, time reversibility and
 the exact stationary distribution of an ideal ion-pair reservoir."""
 import json
+import ctypes
 import math
 import os
 
@@ -363,3 +364,40 @@ def test_ideal_reservoir_stationary_distribution():
     assert 0.5 * np.abs(emp - exact).sum() < 0.02
     mean_exact = y * i1(2 * y) / i0(2 * y)
     assert ns.mean() == pytest.approx(mean_exact, abs=0.06)
+
+
+def _altitudes(schedule, n, move, nf=50, w_max=2.5):
+    p = O.make_params(dict(W.lj_electrolyte(24, 0.02, 3).params, schedule=schedule, schedule_n=n, w_max=w_max))
+    return np.array([O.lib().or_altitude(ctypes.byref(p), move, k, nf) for k in range(nf + 1)])
+
+
+@pytest.mark.parametrize("schedule", [1, 2])
+def test_variable_velocity_schedules(schedule):
+    # the supplement's w_v (1) and w_x (2): endpoints w_max and 0, n = 1 is
+    # Eq. (2), and the deletion runs the insertion's schedule backwards
+    ins = _altitudes(schedule, 3.0, +1)
+    dele = _altitudes(schedule, 3.0, -1)
+    assert ins[0] == pytest.approx(2.5, abs=1e-15) and ins[-1] == pytest.approx(0.0, abs=1e-15)
+    assert np.allclose(dele, ins[::-1], rtol=0, atol=1e-15)
+    assert np.allclose(_altitudes(schedule, 1.0, +1), _altitudes(0, 1.0, +1), rtol=0, atol=1e-14)
+    x = 0.5
+    mid = ins[25]
+    # w_v is slow near w_max first (concave), w_x fast first (convex)
+    assert mid == pytest.approx(2.5 * ((1 - x ** 3) if schedule == 1 else (1 - x) ** 3), rel=1e-14)
+    assert (mid > 2.5 * 0.5) == (schedule == 1)
+
+
+@pytest.mark.parametrize("schedule", [1, 2])
+def test_trajectory_is_time_reversible_with_a_variable_schedule(schedule):
+    # with the deletion the time reversal of the insertion's schedule, the
+    # reversed NEMD returns to the start (the deletion formulas as printed
+    # pair w_v's insertion with w_x's reversal and would not)
+    s = small_system(n=200, rho=0.3, kappa=0.6, schedule=schedule, schedule_n=2.5)
+    s.mb(1)
+    x0 = s.positions()
+    s.nemd(+1, 100)
+    s.v *= -1.0
+    s.nemd(-1, 100)
+    d = s.positions() - x0
+    d -= s.pd["box"][0] * np.round(d / s.pd["box"][0])
+    assert np.abs(d).max() < 1e-9
