@@ -239,7 +239,7 @@ def proposal_ab(sys_, torch, h4d, arms, beta_mu, n_each, block=50):
     each record's ln R is moved to the operating beta mu and the mean of
     min(1, R) taken.  The arms alternate in blocks so that they share the
     same state and device conditions.  arms: name -> (net, k, scale)."""
-    out = {name: {"ins": [], "del": [], "s": 0.0, "n": 0} for name in arms}
+    out = {name: {"ins": [], "del": [], "dM_ins": [], "dM_del": [], "s": 0.0, "n": 0} for name in arms}
     done = 0
     while done < n_each:
         nb = min(block, n_each - done)
@@ -264,6 +264,7 @@ def proposal_ab(sys_, torch, h4d, arms, beta_mu, n_each, block=50):
                     r = arr[q]
                     ok = not (r.flags & 0x3) and math.isfinite(r.ln_ratio)
                     out[name][key].append(math.exp(min(0.0, r.ln_ratio + shift)) if ok else 0.0)
+                    out[name]["dM_" + key].append(r.dM if ok else math.nan)
         done += nb
     sys_.set_proposal(None, 0)
     sys_.set_bias(0.0, 0.0)
@@ -273,7 +274,7 @@ def proposal_ab(sys_, torch, h4d, arms, beta_mu, n_each, block=50):
         p_ins = sum(o["ins"]) / max(1, len(o["ins"]))
         p_del = sum(o["del"]) / max(1, len(o["del"]))
         rate = o["n"] / max(1e-300, o["s"])
-        res[name] = {"p_insert": p_ins, "p_delete": p_del, "trials_per_s": rate,
+        res[name] = {"p_insert": p_ins, "p_delete": p_del, "trials_per_s": rate, "dM": (o["dM_ins"], o["dM_del"]),
                      "expected_exchanges_per_s": 0.5 * (p_ins + p_del) * rate,
                      "insertions": len(o["ins"]), "deletions": len(o["del"])}
     if "uniform" in out and "learned" in out:
@@ -456,8 +457,12 @@ def bench_single(args, h4d, W, torch):
         arms["learned"] = (net, k_sel, scale_sel, None)
     arms["bimodal"] = (None, 0, 0.0, BIAS[args.workload])
     ab = proposal_ab(sys_, torch, h4d, arms, beta_mu, args.ab_trials) if args.ab_trials > 0 else None
+    works = None
     if ab is not None:
         note(f"fixed-state comparison: {args.ab_trials} insertions and deletions per proposal")
+        works = ab["uniform"]["dM"]
+        for name in arms:
+            ab[name].pop("dM")
     # step-kernel duration: further trials with HIP events around every
     # launch of the fused step kernel (on the library's stream)
     n_seq_timing = args.timing_trials if seq_n > 0 else 0
@@ -521,6 +526,16 @@ def bench_single(args, h4d, W, torch):
         "fixed_state_gain": ab.get("bimodal_gain") if ab is not None else None,
         "fixed_state_gain_bootstrap90": ab.get("bimodal_gain_bootstrap90") if ab is not None else None,
     }
+    # the chemical potential and the predicted acceptance from the uniform
+    # arm's work distributions (Crooks' theorem solved by BAR, Eq. 21)
+    if works is not None:
+        from paper_2307_11447_amd import analysis
+        cal = analysis.work_summary(works[0], works[1], beta, beta_mu)
+        cal["note"] = ("uniform forced insertions and deletions on one fixed state (no move accepted): "
+                       "beta mu from BAR, P_acc predicted by Eq. (21) at the operating beta mu")
+        cal["beta_mu_operating"] = beta_mu
+        cal["observed_p_acc_uniform"] = (sum(r.accepted for r in recs) / len(recs)) if recs else None
+        out["mu_calibration"] = cal
     config = dict({"workload": desc + "; value: uniform proposal" +
                    (f", {args.replicas} speculative replicas of the one chain" if speculative else "") +
                    "; 'learned': the trained multiple-try proposal from the same state"}, **shape)
