@@ -69,7 +69,7 @@ static void draw4(const or_params *p, uint64_t a, uint64_t b, uint64_t c, double
 /* Counter purposes: move and plain sites, Maxwell-Boltzmann momenta, N_f,
  * candidate sites of the learned proposal, its categorical choice. */
 enum { PURPOSE_SELECT = 1, PURPOSE_MB = 2, PURPOSE_NSTEPS = 3, PURPOSE_CAND = 4, PURPOSE_PICK = 5,
-       PURPOSE_BIAS = 6 };
+       PURPOSE_BIAS = 6, PURPOSE_REVERSE = 7, PURPOSE_MD = 8, PURPOSE_REFRESH = 9, PURPOSE_INITV = 10 };
 
 /* ------------------------------------------------------------------ */
 /* Geometry                                                            */
@@ -293,23 +293,44 @@ int or_compute(const or_params *p, const or_state *s, double w, int mode,
 /* ------------------------------------------------------------------ */
 /* Momenta                                                             */
 /* ------------------------------------------------------------------ */
+/* A Maxwell-Boltzmann velocity of atom i: each 3D component ~ N(0, kT/m)
+ * (Sec. II A), normals from the Box-Muller transform of two uniforms of the
+ * stream (counter, purpose, tag). */
+static void mb_velocity(const or_params *p, const or_state *s, int i, uint64_t counter, uint64_t purpose,
+                        double out[3])
+{
+    double u[4];
+    draw4(p, counter, purpose, (uint64_t)s->tag[i], u);
+    const double r01 = sqrt(-2.0 * log(u[0]));
+    const double r23 = sqrt(-2.0 * log(u[2]));
+    const double sd = sqrt(p->accel * p->kT / p->mass[s->type[i]]);
+    out[0] = sd * r01 * cos(2.0 * M_PI * u[1]);
+    out[1] = sd * r01 * sin(2.0 * M_PI * u[1]);
+    out[2] = sd * r23 * cos(2.0 * M_PI * u[3]);
+}
+
 int or_mb_velocities(const or_params *p, or_state *s, uint64_t trial)
 {
-    /* Maxwell-Boltzmann: each 3D component ~ N(0, kT/m) (Sec. II A);
-     * normals from the Box-Muller transform of two uniforms. */
-    for (int i = 0; i < s->n; ++i) {
-        double u[4];
-        draw4(p, trial, PURPOSE_MB, (uint64_t)s->tag[i], u);
-        const double r01 = sqrt(-2.0 * log(u[0]));
-        const double r23 = sqrt(-2.0 * log(u[2]));
-        const double z[3] = {r01 * cos(2.0 * M_PI * u[1]),
-                             r01 * sin(2.0 * M_PI * u[1]),
-                             r23 * cos(2.0 * M_PI * u[3])};
-        const double sd = sqrt(p->accel * p->kT / p->mass[s->type[i]]);
-        for (int d = 0; d < 3; ++d) s->v[3 * i + d] = sd * z[d];
-    }
+    for (int i = 0; i < s->n; ++i) mb_velocity(p, s, i, trial, PURPOSE_MB, s->v + 3 * i);
     if (p->water) return or_constrain_velocities(p, s);
     return 0;
+}
+
+int or_init_velocities(const or_params *p, or_state *s)
+{
+    if (p->water) return -10;
+    for (int i = 0; i < s->n; ++i) mb_velocity(p, s, i, 0, PURPOSE_INITV, s->v + 3 * i);
+    return 0;
+}
+
+/* Signs of the symmetric two-end momentum reversal of a trial: each end
+ * reverses every momentum with probability 1/2. */
+static void reversal_signs(const or_params *p, uint64_t trial, double *s0, double *s1)
+{
+    double u[4];
+    draw4(p, trial, PURPOSE_REVERSE, 0, u);
+    *s0 = u[0] < 0.5 ? -1.0 : 1.0;
+    *s1 = u[1] < 0.5 ? -1.0 : 1.0;
 }
 
 double or_kinetic(const or_params *p, const or_state *s)
@@ -864,7 +885,16 @@ static int trial_begin(const or_params *p, or_state *s, uint64_t trial, int forc
     rec->tag_a = s->tag[ia];
     *ic_out = ic; *ia_out = ia;
 
-    if (or_mb_velocities(p, s, trial)) return -5;
+    if (p->momenta) {
+        /* carried momenta: the state's own, reversed with probability 1/2
+         * at the start of the trajectory; the flyers' drawn afresh */
+        double s0, s1;
+        reversal_signs(p, trial, &s0, &s1);
+        for (int i = 0; i < s->n; ++i) {
+            if (s->flying[i]) mb_velocity(p, s, i, trial, PURPOSE_MB, s->v + 3 * i);
+            else for (int d = 0; d < 3; ++d) s->v[3 * i + d] *= s0;
+        }
+    } else if (or_mb_velocities(p, s, trial)) return -5;
     or_energy e;
     /* H at the start: the N-state (ghosts left out) for an insertion, the
      * physical (N+1)-state for a deletion. */
@@ -892,8 +922,13 @@ int or_trial_learned(const or_params *p, or_state *s, uint64_t trial, int force_
     const int n_orig = s->n;
     int ic, ia, nf;
     if (prop && prop->k < 1) prop = NULL;
+    if (p->momenta && p->water) return -10;
+    /* the carried momenta before the trial (a rejection restores them) */
+    double *v0 = p->momenta ? malloc(3 * (size_t)(n_orig > 0 ? n_orig : 1) * sizeof(double)) : NULL;
+    if (p->momenta && !v0) return -1;
+    if (v0) memcpy(v0, s->v, 3 * (size_t)n_orig * sizeof(double));
     const int st = trial_begin(p, s, trial, force_move, prop, rec, &ic, &ia, &nf, feat_out);
-    if (st <= 0) return st;
+    if (st <= 0) { free(v0); return st; }
     const int move = rec->move;
     const int n_small = (move > 0) ? Ns : Ns - 1;
     const double H0 = rec->H0;
@@ -901,7 +936,7 @@ int or_trial_learned(const or_params *p, or_state *s, uint64_t trial, int force_
     or_energy e;
 
     double *x0 = malloc(3 * (size_t)s->n * sizeof(double));
-    if (!x0) return -1;
+    if (!x0) { free(v0); return -1; }
     memcpy(x0, s->x, 3 * (size_t)s->n * sizeof(double));
     double W = 0.0;
     int rc = or_nemd(p, s, move, nf, &W);
@@ -914,10 +949,10 @@ int or_trial_learned(const or_params *p, or_state *s, uint64_t trial, int force_
         rec->dH = NAN;
         rec->flags |= OR_FLAG_NONFINITE;
         rec->ln_ratio = NAN;
-        free(x0);
+        free(x0); free(v0);
         return 0;
     }
-    if (rc) { free(x0); return -6; }
+    if (rc) { free(x0); free(v0); return -6; }
 
     if (move > 0) or_compute(p, s, 0.0, OR_MODE_NEMD, NULL, &e);
     else or_compute(p, s, 0.0, OR_MODE_EXCL, NULL, &e);
@@ -930,10 +965,13 @@ int or_trial_learned(const or_params *p, or_state *s, uint64_t trial, int force_
         double *sites = malloc(sizeof(double) * 6 * (size_t)k);
         double *feat = malloc(sizeof(double) * 64 * (size_t)k);
         double *logw = malloc(sizeof(double) * (size_t)k);
-        if (!sites || !feat || !logw) { free(sites); free(feat); free(logw); free(x0); return -1; }
+        if (!sites || !feat || !logw) { free(sites); free(feat); free(logw); free(x0); free(v0); return -1; }
         for (int d = 0; d < 3; ++d) { sites[d] = s->x[3 * ic + d]; sites[3 + d] = s->x[3 * ia + d]; }
         for (int j = 0; j + 1 < k; ++j) candidate_site(p, trial, j, sites + 6 * (j + 1));
-        if (score_sites(p, s, prop, k, sites, feat, logw)) { free(sites); free(feat); free(logw); free(x0); return -8; }
+        if (score_sites(p, s, prop, k, sites, feat, logw)) {
+            free(sites); free(feat); free(logw); free(x0); free(v0);
+            return -8;
+        }
         or_mtm_log_factor(-1, k, logw, 0, &rec->ln_proposal);
         if (feat_out) memcpy(feat_out, feat, 64 * sizeof(double));
         free(sites); free(feat); free(logw);
@@ -980,8 +1018,88 @@ int or_trial_learned(const or_params *p, or_state *s, uint64_t trial, int force_
         if (move > 0) s->n = n_orig;
         else { s->flying[ic] = 0; s->flying[ia] = 0; }
     }
+    if (p->momenta) {
+        /* the end reversal: the state reached keeps its momenta (the new
+         * pair's are its fresh draws), or the rejected state its own, each
+         * reversed with probability 1/2 */
+        double s0, s1;
+        reversal_signs(p, trial, &s0, &s1);
+        if (acc) for (int q = 0; q < 3 * s->n; ++q) s->v[q] *= s1;
+        else for (int q = 0; q < 3 * n_orig; ++q) s->v[q] = s0 * s1 * v0[q];
+    }
     rec->n_salt_after = s->nsalt;
-    free(x0);
+    free(x0); free(v0);
+    return 0;
+}
+
+int or_md_phase(const or_params *p, or_state *s, uint64_t phase, int n_steps, or_trial_rec *rec)
+{
+    /* Equilibrium sampling between trials, as generalized hybrid Monte
+     * Carlo: the momenta are partly refreshed, v <- c v + sqrt(1 - c^2) xi
+     * with xi Maxwell-Boltzmann (c = 0: plain hybrid MC), the whole state
+     * runs n_steps velocity-Verlet steps in 3D, and the end state is taken
+     * with probability min(1, exp(-beta dH)); a rejection keeps the
+     * positions and reverses the refreshed momenta.  Each part leaves the
+     * canonical distribution of (x, p) invariant. */
+    if (p->water) return -10;
+    if (n_steps < 1) return -11;
+    const int n = s->n;
+    const double beta = 1.0 / p->kT;
+    memset(rec, 0, sizeof(*rec));
+    rec->move = 2;
+    rec->trial = (int64_t)phase;
+    rec->n_steps = n_steps;
+    rec->n_salt_before = rec->n_salt_after = s->nsalt;
+    rec->tag_c = rec->tag_a = -1;
+    const double c = p->md_refresh, sc = sqrt(1.0 - c * c);
+    for (int i = 0; i < n; ++i) {
+        double xi[3];
+        mb_velocity(p, s, i, phase, PURPOSE_REFRESH, xi);
+        for (int d = 0; d < 3; ++d) s->v[3 * i + d] = c * s->v[3 * i + d] + sc * xi[d];
+    }
+    double *x0 = malloc(3 * (size_t)(n > 0 ? n : 1) * sizeof(double));
+    double *v0 = malloc(3 * (size_t)(n > 0 ? n : 1) * sizeof(double));
+    double *F = malloc(3 * (size_t)(n > 0 ? n : 1) * sizeof(double));
+    if (!x0 || !v0 || !F) { free(x0); free(v0); free(F); return -1; }
+    memcpy(x0, s->x, 3 * (size_t)n * sizeof(double));
+    memcpy(v0, s->v, 3 * (size_t)n * sizeof(double));
+    or_energy e;
+    if (or_compute(p, s, 0.0, OR_MODE_NEMD, F, &e)) { free(x0); free(v0); free(F); return -7; }
+    const double U0 = e.U, K0 = or_kinetic(p, s);
+    const double h = 0.5 * p->dt;
+    for (int k = 0; k < n_steps; ++k) {
+        for (int i = 0; i < n; ++i) {
+            const double m = p->mass[s->type[i]];
+            for (int d = 0; d < 3; ++d) {
+                s->v[3 * i + d] += h * p->accel * F[3 * i + d] / m;
+                s->x[3 * i + d] = wrap1(s->x[3 * i + d] + p->dt * s->v[3 * i + d], p->box[d]);
+            }
+        }
+        if (or_compute(p, s, 0.0, OR_MODE_NEMD, F, &e)) { free(x0); free(v0); free(F); return -7; }
+        for (int i = 0; i < n; ++i) {
+            const double m = p->mass[s->type[i]];
+            for (int d = 0; d < 3; ++d) s->v[3 * i + d] += h * p->accel * F[3 * i + d] / m;
+        }
+    }
+    const double U1 = e.U, K1 = or_kinetic(p, s);
+    double u[4];
+    draw4(p, phase, PURPOSE_MD, 0, u);
+    rec->H0 = U0 + K0;
+    rec->H1 = U1 + K1;
+    rec->dH = rec->H1 - rec->H0;
+    rec->dU = U1 - U0;
+    rec->dK = K1 - K0;
+    rec->ln_ratio = -beta * rec->dH;
+    rec->ln_u = log(u[0]);
+    int acc = 0;
+    if (!isfinite(rec->dH)) rec->flags |= OR_FLAG_NONFINITE;
+    else acc = rec->ln_u < rec->ln_ratio;
+    rec->accepted = acc;
+    if (!acc) {
+        memcpy(s->x, x0, 3 * (size_t)n * sizeof(double));
+        for (int q = 0; q < 3 * n; ++q) s->v[q] = -v0[q];
+    }
+    free(x0); free(v0); free(F);
     return 0;
 }
 

@@ -40,6 +40,10 @@ typedef struct {
     double bias_alpha;      /* II B 4, Eq. 14): x_b and alpha_b; alpha_b = 0: off */
     int32_t schedule;       /* altitude: 0 Eq. (2); 1 w_max (1 - x^n); 2         */
     double schedule_n;      /* w_max (1 - x)^n (supplement), exponent n           */
+    int32_t momenta;        /* 0: fresh Maxwell-Boltzmann momenta every trial; 1: */
+                            /* the state's momenta carried into the trajectory    */
+                            /* with the symmetric two-end reversal (Sec. II A)    */
+    double md_refresh;      /* equilibrium phase: v <- c v + sqrt(1 - c^2) xi     */
 } or_params;
 
 /* Configuration.  Arrays are owned by the caller and sized to cap. */
@@ -157,6 +161,16 @@ int or_trial_learned(const or_params *p, or_state *s, uint64_t trial, int force_
 
 /* ln of the multiple-try factor for log weights logw[0..k-1] (insertion:
  * sel is the chosen candidate; deletion: logw[0] is the removed pair). */
+/* Momenta of a new state: every atom's velocity drawn from the
+ * Maxwell-Boltzmann distribution (counter 0 of its own stream). */
+int or_init_velocities(const or_params *p, or_state *s);
+
+/* Equilibrium phase between trials (generalized hybrid MC): partial
+ * momentum refresh, n_steps velocity-Verlet steps of the whole state in 3D,
+ * Metropolis test on exp(-beta dH); a rejected phase restores the positions
+ * and reverses the refreshed momenta.  rec->move = 2, rec->trial = phase. */
+int or_md_phase(const or_params *p, or_state *s, uint64_t phase, int n_steps, or_trial_rec *rec);
+
 int or_mtm_log_factor(int move, int k, const double *logw, int sel, double *out);
 
 #endif

@@ -35,6 +35,7 @@ class Params(C.Structure):
         ("seed", C.c_uint64), ("stream", C.c_uint64),
         ("bias_xb", C.c_double), ("bias_alpha", C.c_double),
         ("schedule", C.c_int32), ("schedule_n", C.c_double),
+        ("momenta", C.c_int32), ("md_refresh", C.c_double),
     ]
 
 
@@ -113,6 +114,8 @@ def lib():
         L.or_bias_offset.restype = C.c_double
         L.or_trial_learned.argtypes = [P, S, C.c_uint64, C.c_int, C.POINTER(Proposal), C.POINTER(TrialRec),
                                        C.POINTER(C.c_double)]
+        L.or_init_velocities.argtypes = [P, S]
+        L.or_md_phase.argtypes = [P, S, C.c_uint64, C.c_int, C.POINTER(TrialRec)]
         _lib = L
     return _lib
 
@@ -139,6 +142,7 @@ def make_params(d: dict, use_cells: bool = True) -> Params:
     p.seed, p.stream = d["seed"], d.get("stream", 0)
     p.bias_xb, p.bias_alpha = d.get("bias_xb", 0.0), d.get("bias_alpha", 0.0)
     p.schedule, p.schedule_n = d.get("schedule", 0), d.get("schedule_n", 1.0)
+    p.momenta, p.md_refresh = d.get("momenta", 0), d.get("md_refresh", 0.0)
     return p
 
 
@@ -175,6 +179,8 @@ class OracleSystem:
         self.s.x, self.s.v = _dp(self.x), _dp(self.v)
         self.s.type, self.s.mol = _ip(self.type), _ip(self.mol)
         self.s.tag, self.s.flying = _lp(self.tag), _ip(self.flying)
+        if not self.p.water:
+            lib().or_init_velocities(C.byref(self.p), C.byref(self.s))
 
     @classmethod
     def from_workload(cls, w, cap=None, use_cells=True):
@@ -203,6 +209,17 @@ class OracleSystem:
         if rc:
             raise RuntimeError(f"or_trial failed: {rc}")
         return rec.as_dict()
+
+    def md_phase(self, phase: int, n_steps: int) -> dict:
+        """Equilibrium phase `phase` (generalized hybrid MC, n_steps steps)."""
+        rec = TrialRec()
+        rc = lib().or_md_phase(C.byref(self.p), C.byref(self.s), phase, n_steps, C.byref(rec))
+        if rc:
+            raise RuntimeError(f"or_md_phase failed: {rc}")
+        return rec.as_dict()
+
+    def velocities(self):
+        return self.v[: self.n].copy()
 
     def site_features(self, site) -> np.ndarray:
         """Features (64) of the pair site (cation xyz, anion xyz) on the
