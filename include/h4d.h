@@ -57,6 +57,7 @@ extern "C" {
 #define H4D_MOVE_AUTO    0  /* insertion or deletion with probability 1/2    */
 #define H4D_MOVE_INSERT  1
 #define H4D_MOVE_DELETE -1
+#define H4D_MOVE_MD      2  /* record of an equilibrium phase (h4d_run_md)  */
 
 /* Arithmetic of the pair pass. */
 #define H4D_PREC_FP64 0     /* everything in FP64                               */
@@ -122,6 +123,13 @@ typedef struct h4d_params {
                                    Eqs. 12-16), see h4d_set_bias; bias_alpha = 0:
                                    the uniform placement of Eq. (4)             */
     double schedule_n;          /* exponent n >= 1 of schedules 1 and 2         */
+    int32_t momenta;            /* 0: every trial draws fresh Maxwell-Boltzmann
+                                   momenta; 1: trials carry the state's momenta
+                                   with the symmetric two-end reversal (Sec.
+                                   II A), to alternate with h4d_run_md (ions
+                                   only; not with speculative replicas)         */
+    double md_refresh;          /* c in [0, 1] of the equilibrium phase's
+                                   momentum refresh, see h4d_run_md             */
 } h4d_params;
 
 /* One trial (move +1 insertion, -1 deletion). */
@@ -203,6 +211,24 @@ int32_t h4d_run_nemd_trial(h4d_system *sys, int32_t move, h4d_trial *out);
 int32_t h4d_run_trials(h4d_system *sys, int32_t n, int32_t move, h4d_trial *out);
 
 /*
+ * Equilibrium phase between trials (Sec. II A, Fig. 1: equilibrium MD samples
+ * configurations between exchange trials), one in every box: the state's
+ * momenta are partly refreshed, v <- c v + sqrt(1 - c^2) xi with xi
+ * Maxwell-Boltzmann and c = md_refresh (c = 0: plain hybrid MC), the whole
+ * state runs n_steps velocity-Verlet steps in 3D (no flyers), and the end
+ * state is taken with probability min(1, exp(-beta dH)); a rejected phase
+ * keeps the positions and reverses the refreshed momenta (generalized
+ * hybrid MC, exact for the canonical distribution at any dt).  Phase p of a
+ * box draws from the generator with counter p (its own sequence, apart from
+ * the trials').  The momenta stay with the state: trials with momenta = 1
+ * start from them, and h4d_get_state returns them.  out (host, may be NULL)
+ * receives one record per box: move = H4D_MOVE_MD, trial = the phase index,
+ * dH, dU, dK, H0, H1, ln_ratio = -beta dH, ln_u, accepted.  Ion systems only
+ * (H4D_EINVAL with water); n_steps >= 1.
+ */
+int32_t h4d_run_md(h4d_system *sys, int32_t n_steps, h4d_trial *out);
+
+/*
  * Run trials_per_box more trials in every box of a batch.  All boxes run
  * their current trial in one round of launches (one graph, each box with its
  * own N_f and move); a box that must recompute a trial after a list resize
@@ -248,7 +274,10 @@ int32_t h4d_sample_observables(h4d_system *sys, h4d_observables *out);
 int32_t h4d_box_observables(h4d_system *sys, int32_t box, h4d_observables *out);
 
 /* Copy the current state to host arrays of length >= cap (positions 3*cap).
- * Any pointer may be NULL.  *n receives the number of atoms. */
+ * Any pointer may be NULL.  *n receives the number of atoms.  vel: the
+ * state's own momenta (with momenta = 1, after set-up and after an
+ * equilibrium phase); after a trial with fresh momenta, the momenta its
+ * trajectory ended with. */
 int32_t h4d_get_state(h4d_system *sys, int32_t cap, int32_t *n, int32_t *n_salt,
                       double *pos, double *vel, int32_t *type, int32_t *mol, int64_t *tag);
 /* The same for box `box` of a batch. */

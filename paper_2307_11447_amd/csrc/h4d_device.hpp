@@ -29,6 +29,10 @@ constexpr unsigned kErrNonfinite = 0x20u;  // a position became non-finite (the 
 
 // purposes of the counter-based generator
 constexpr uint64_t kPurposeSelect = 1, kPurposeMB = 2, kPurposeNsteps = 3, kPurposeBias = 6;
+constexpr uint64_t kPurposeReverse = 7, kPurposeMD = 8, kPurposeRefresh = 9, kPurposeInitV = 10;
+
+// move code of an equilibrium phase (the trials are +1 / -1, 0 idle)
+constexpr int kMoveMD = 2;
 
 // --------------------------------------------------------------------------
 // Philox4x64-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of two
@@ -83,6 +87,10 @@ struct Geo {
     // altitude schedule (see altitude())
     int schedule;
     double schedule_n;
+    // momenta: 0 a fresh Maxwell-Boltzmann draw for every trial; 1 the
+    // state's own, carried between trials with the two-end reversal
+    int momenta;
+    double md_refresh;       // equilibrium phase: v <- c v + sqrt(1 - c^2) xi
 };
 
 // --------------------------------------------------------------------------

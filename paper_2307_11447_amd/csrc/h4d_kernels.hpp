@@ -33,7 +33,7 @@ struct Ctl {
     int n;            // atoms of the physical state
     int n_all;        // atoms including the two ghosts of an insertion
     int nsalt;
-    int move;         // +1 insertion, -1 deletion, 0 nothing to do
+    int move;         // +1 insertion, -1 deletion, kMoveMD equilibrium phase, 0 nothing to do
     int ic, ia;       // slots of the flying cation / anion (canonical arrays)
     int wic, wia;     // their working slots
     int nf;           // NEMD steps of this trial
@@ -53,6 +53,8 @@ struct Ctl {
     double Wf[2];
     double Ufly0, Ufly1;   // U_fly(w_max) at the start / end state (FP64)
     double lnq;            // ln of the learned proposal's multiple-try factor (0: uniform)
+    long long md;          // equilibrium phases run (the phase's generator counter)
+    long long md_end;      // the box idles in a phase round once md reaches this
 };
 
 // Trial record, same layout as h4d_trial of the C ABI.
@@ -76,6 +78,7 @@ struct KArgs {
     const double *mass;       // per type
     // canonical state
     double4 *cpos;
+    double4 *cvel;            // the state's momenta (carried momenta, equilibrium phases)
     long long *ctag;
     int *ctype, *cmol;
     // working state
@@ -86,7 +89,7 @@ struct KArgs {
     uint4 *posb;              // fixed-point positions at the last list build
     double4 *force;           // test hook output (canonical slots)
     // compaction scratch (canonical order)
-    double4 *tpos;
+    double4 *tpos, *tvel;
     long long *ttag;
     int *ttype, *tmol;
     // lists
@@ -105,6 +108,7 @@ struct KArgs {
     int lanes, lanes_log2;    // lanes per atom in list traversals (4, 8 or 16)
     uint64_t seed;
     int n_steps, n_steps_min, n_steps_max;
+    int md_steps;             // steps of an equilibrium phase
     int cation_type, anion_type;
 };
 
@@ -211,6 +215,37 @@ __device__ __forceinline__ double bias_offset(const KArgs &a, const Box &B, uint
     return mu;
 }
 
+// A Maxwell-Boltzmann velocity (each component ~ N(0, kT/m), Sec. II A):
+// Box-Muller normals of the stream (counter, purpose, tag), sd = sqrt(kT/m).
+__device__ __forceinline__ double4 mb_velocity(const KArgs &a, const Box &B, uint64_t counter, uint64_t purpose,
+                                               long long tag, double sd) {
+    const double twopi = 6.283185307179586476925286766559;
+    const u64x4 r = philox(counter, purpose, (uint64_t)tag, 0, a.seed, B.stream);
+    const double u0 = unit_open(r.v[0]), u1 = unit_open(r.v[1]);
+    const double u2 = unit_open(r.v[2]), u3 = unit_open(r.v[3]);
+    const double r01 = sqrt(-2.0 * log(u0)), r23 = sqrt(-2.0 * log(u2));
+    return make_double4(sd * (r01 * cos(twopi * u1)), sd * (r01 * sin(twopi * u1)), sd * (r23 * cos(twopi * u3)),
+                        0.0);
+}
+
+// Sign of the symmetric two-end momentum reversal of a trial with carried
+// momenta: end 0 before the trajectory, end 1 after it, each -1 with
+// probability 1/2.
+__device__ __forceinline__ double reversal_sign(const KArgs &a, const Box &B, long long trial, int end) {
+    const u64x4 r = philox((uint64_t)trial, kPurposeReverse, 0, 0, a.seed, B.stream);
+    return unit_open(r.v[end]) < 0.5 ? -1.0 : 1.0;
+}
+
+// Equilibrium phase: the partly refreshed momenta of canonical atom i,
+// c v + sqrt(1 - c^2) xi (generalized hybrid MC; c = 0 a full refresh).
+__device__ __forceinline__ double4 refreshed_velocity(const KArgs &a, const Box &B, const Ctl *c, int i) {
+    const double sd = sqrt(a.G.accel * a.G.kT / a.mass[a.ctype[i]]);
+    const double4 xi = mb_velocity(a, B, (uint64_t)c->md, kPurposeRefresh, a.ctag[i], sd);
+    const double4 v = a.cvel[i];
+    const double cr = a.G.md_refresh, sr = sqrt(1.0 - cr * cr);
+    return make_double4(cr * v.x + sr * xi.x, cr * v.y + sr * xi.y, cr * v.z + sr * xi.z, 0.0);
+}
+
 __global__ __launch_bounds__(kBlock) void k_propose(KArgs a, int force_move) {
     const int bi = blockIdx.x;
     const Box &B = a.box[bi];
@@ -219,18 +254,26 @@ __global__ __launch_bounds__(kBlock) void k_propose(KArgs a, int force_move) {
     __shared__ int s_move, s_kc, s_ka, s_ic, s_ia, s_n;
     const int tid = threadIdx.x;
     if (tid == 0) {
-        const uint64_t t = (uint64_t)c->trial;
-        const u64x4 r0 = philox(t, kPurposeSelect, 0, 0, a.seed, B.stream);
-        const u64x4 r1 = philox(t, kPurposeSelect, 1, 0, a.seed, B.stream);
-        for (int q = 0; q < 4; ++q) { c->u[q] = unit_open(r0.v[q]); c->u[4 + q] = unit_open(r1.v[q]); }
+        const bool md = force_move == kMoveMD;
         int nf = a.n_steps;
-        if (a.n_steps_max > 0) {
-            const u64x4 rn = philox(t, kPurposeNsteps, 0, 0, a.seed, B.stream);
-            nf = a.n_steps_min + (int)floor(unit_open(rn.v[0]) * (double)(a.n_steps_max - a.n_steps_min + 1));
+        if (md) {   // equilibrium phase: the whole state in 3D, no flyers; u[7] its Metropolis uniform
+            const u64x4 r0 = philox((uint64_t)c->md, kPurposeMD, 0, 0, a.seed, B.stream);
+            for (int q = 0; q < 4; ++q) { c->u[q] = unit_open(r0.v[q]); c->u[4 + q] = 0.5; }
+            c->u[7] = c->u[0];
+            nf = a.md_steps;
+        } else {
+            const uint64_t t = (uint64_t)c->trial;
+            const u64x4 r0 = philox(t, kPurposeSelect, 0, 0, a.seed, B.stream);
+            const u64x4 r1 = philox(t, kPurposeSelect, 1, 0, a.seed, B.stream);
+            for (int q = 0; q < 4; ++q) { c->u[q] = unit_open(r0.v[q]); c->u[4 + q] = unit_open(r1.v[q]); }
+            if (a.n_steps_max > 0) {
+                const u64x4 rn = philox(t, kPurposeNsteps, 0, 0, a.seed, B.stream);
+                nf = a.n_steps_min + (int)floor(unit_open(rn.v[0]) * (double)(a.n_steps_max - a.n_steps_min + 1));
+            }
         }
         c->nf = nf;
-        c->idle = c->trial >= c->trial_end;
-        int move = force_move ? force_move : (c->u[0] < 0.5 ? 1 : -1);
+        c->idle = md ? c->md >= c->md_end : c->trial >= c->trial_end;
+        int move = md ? kMoveMD : (force_move ? force_move : (c->u[0] < 0.5 ? 1 : -1));
         if ((move < 0 && c->nsalt == 0) || c->idle) move = 0;
         c->move = move;
         c->err = 0; c->retry = 0; c->accepted = 0;
@@ -245,7 +288,7 @@ __global__ __launch_bounds__(kBlock) void k_propose(KArgs a, int force_move) {
         s_kc = (int)floor(c->u[1] * (double)c->nsalt);
         s_ka = (int)floor(c->u[2] * (double)c->nsalt);
         s_ic = s_ia = -1;
-        if (move > 0) {
+        if (move == 1) {
             const int n = c->n;
             if (n + 2 > B.cap) {
                 c->err |= kErrCap; c->retry = 1; c->move = 0; s_move = 0;
@@ -439,7 +482,6 @@ __global__ __launch_bounds__(kWave) void k_gather_in(KArgs a, int cb) {
     const int off = a.cell_off[cc];
     int *row = a.cell_atoms[cb] + (size_t)cc * a.cell_cap;
     const uint64_t t = (uint64_t)c->trial;
-    const double twopi = 6.283185307179586476925286766559;
     for (int s = threadIdx.x; s < cnt; s += kWave) {
         const int src = row[s];
         const int w = off + s;
@@ -455,13 +497,18 @@ __global__ __launch_bounds__(kWave) void k_gather_in(KArgs a, int cb) {
         a.fx[0][w] = q;
         a.perm[w] = src;
         a.wmol[w] = mol;
-        const u64x4 r = philox(t, kPurposeMB, (uint64_t)a.ctag[src], 0, a.seed, B.stream);
-        const double u0 = unit_open(r.v[0]), u1 = unit_open(r.v[1]);
-        const double u2 = unit_open(r.v[2]), u3 = unit_open(r.v[3]);
-        const double r01 = sqrt(-2.0 * log(u0)), r23 = sqrt(-2.0 * log(u2));
-        const double sd = sqrt(a.G.accel * a.G.kT / a.mass[ty]);
-        a.vel[0][w] = make_double4(sd * (r01 * cos(twopi * u1)), sd * (r01 * sin(twopi * u1)),
-                                   sd * (r23 * cos(twopi * u3)), 0.0);
+        // momenta: an equilibrium phase's partial refresh of the carried
+        // ones; with carried momenta a trial's start reversal of them (the
+        // flyers' drawn afresh); else the trial's Maxwell-Boltzmann draw
+        if (c->move == kMoveMD) {
+            a.vel[0][w] = refreshed_velocity(a, B, c, src);
+        } else if (a.G.momenta && !(meta & kFlyBit)) {
+            const double s0 = reversal_sign(a, B, c->trial, 0);
+            const double4 v = a.cvel[src];
+            a.vel[0][w] = make_double4(s0 * v.x, s0 * v.y, s0 * v.z, 0.0);
+        } else {
+            a.vel[0][w] = mb_velocity(a, B, t, kPurposeMB, a.ctag[src], sqrt(a.G.accel * a.G.kT / a.mass[ty]));
+        }
         if (src == c->ic) c->wic = w;
         if (src == c->ia) c->wia = w;
         row[s] = w;
@@ -936,7 +983,7 @@ __device__ void flyer_work(const KArgs &a, const Box &B, Ctl *c, const CoefLds &
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     if (wave > 1) return;
     const int move = c->move, nf = c->nf;
-    if (move == 0 || k > nf) return;
+    if (move == 0 || move == kMoveMD || k > nf) return;
     const int f = wave == 0 ? c->wic : c->wia;
     const int other = wave == 0 ? c->wia : c->wic;
     const double wlo = altitude(a.G, move, k > 0 ? k - 1 : 0, nf);
@@ -1125,7 +1172,7 @@ __global__ __launch_bounds__(kBlock) void k_energy(KArgs a, int which, int mode,
     __syncthreads();
     const int move = c->move;
     const bool skip = which < 2 && move == 0;
-    if (mode < 0) mode = ((which == 0 && move > 0) || (which == 1 && move < 0)) ? 1 : 0;
+    if (mode < 0) mode = ((which == 0 && move == 1) || (which == 1 && move == -1)) ? 1 : 0;
     const int b = buf_of(b0, c);
     const int lane = threadIdx.x % kWave;
     const int s = lane & (a.lanes - 1);
@@ -1253,6 +1300,24 @@ __global__ void k_metropolis(KArgs a) {
         r->H0 = r->H1 = 0.0;
         return;
     }
+    if (move == kMoveMD) {
+        // equilibrium phase (generalized hybrid MC): ln R = -beta dH
+        const double H0 = c->U0 + c->K0, H1 = c->U1 + c->K1, dH = H1 - H0;
+        r->trial = c->md;
+        r->move = kMoveMD;
+        r->tag_c = r->tag_a = -1;
+        r->dH = dH; r->dU = c->U1 - c->U0; r->dK = c->K1 - c->K0;
+        r->H0 = H0; r->H1 = H1;
+        r->W_prot = r->E_switch = r->dM = 0.0;
+        r->ln_ratio = -a.G.beta * dH;
+        int acc = 0;
+        if (!isfinite(dH) || (c->err & kErrNonfinite)) r->flags |= kFlagNonfinite;
+        else acc = r->ln_u < r->ln_ratio;
+        if (c->retry) acc = 0;
+        r->accepted = acc;
+        c->accepted = acc;
+        return;
+    }
     r->move = move;
     r->tag_c = a.ctag[c->ic];
     r->tag_a = a.ctag[c->ia];
@@ -1283,7 +1348,7 @@ __global__ __launch_bounds__(kBlock) void k_bias_end(KArgs a) {
     const int bi = blockIdx.x, tid = threadIdx.x;
     const Box &B = a.box[bi];
     Ctl *c = a.ctl + bi;
-    if (c->move <= 0 || a.G.bias_alpha <= 0.0) return;
+    if (c->move != 1 || a.G.bias_alpha <= 0.0) return;
     __shared__ double s_w[kBlock];
     const int b = buf_of(-1, c);
     const double4 pc = a.pos[b][c->wic];
@@ -1307,6 +1372,9 @@ __global__ __launch_bounds__(kBlock) void k_bias_end(KArgs a) {
 // Commit (accepted: the working positions go back to canonical order, ghosts
 // become physical, a deleted pair is compacted out) or roll back (the
 // canonical arrays are the snapshot; only a deletion's flags are cleared).
+// Carried momenta: an accepted trial's end momenta (times the end reversal
+// sign) become the state's, a rejected trial's keep both reversal signs; an
+// equilibrium phase keeps its end momenta, or reverses its refreshed ones.
 __global__ __launch_bounds__(kBlock) void k_commit(KArgs a) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     const int bi = box_of_slot(a, i);
@@ -1314,12 +1382,31 @@ __global__ __launch_bounds__(kBlock) void k_commit(KArgs a) {
     const Ctl *c = a.ctl + bi;
     const int move = c->move;
     if (move == 0) return;
+    const bool carry = a.G.momenta != 0 || move == kMoveMD;
     if (c->accepted) {
         if (i - B.a0 < c->n_all) {
-            const double4 p = a.pos[buf_of(-1, c)][i];
+            const int e = buf_of(-1, c);
+            const double4 p = a.pos[e][i];
             a.cpos[a.perm[i]] = with_meta(p.x, p.y, p.z, meta_of(p) & kTypeMask);
+            if (carry) {
+                const double s1 = move == kMoveMD ? 1.0 : reversal_sign(a, B, c->trial, 1);
+                const double4 v = a.vel[e][i];
+                a.cvel[a.perm[i]] = make_double4(s1 * v.x, s1 * v.y, s1 * v.z, 0.0);
+            }
         }
-    } else if (move < 0 && i == B.a0) {
+        return;
+    }
+    if (carry && !c->retry && i - B.a0 < c->n) {   // (a trial to recompute keeps its start state)
+        if (move == kMoveMD) {
+            const double4 v = refreshed_velocity(a, B, c, i);
+            a.cvel[i] = make_double4(-v.x, -v.y, -v.z, 0.0);
+        } else {
+            const double s = reversal_sign(a, B, c->trial, 0) * reversal_sign(a, B, c->trial, 1);
+            const double4 v = a.cvel[i];
+            a.cvel[i] = make_double4(s * v.x, s * v.y, s * v.z, 0.0);
+        }
+    }
+    if (move < 0 && i == B.a0) {
         double4 p = a.cpos[c->ic];
         a.cpos[c->ic] = with_meta(p.x, p.y, p.z, meta_of(p) & ~kFlyBit);
         p = a.cpos[c->ia];
@@ -1338,6 +1425,7 @@ __global__ __launch_bounds__(kBlock) void k_compact1(KArgs a) {
     if (i - B.a0 < c->n_all && i != ic && i != ia) {
         const int d = i - (i > ic) - (i > ia);
         a.tpos[d] = a.cpos[i];
+        a.tvel[d] = a.cvel[i];
         a.ttag[d] = a.ctag[i];
         a.ttype[d] = a.ctype[i];
         a.tmol[d] = a.cmol[i];
@@ -1352,6 +1440,7 @@ __global__ __launch_bounds__(kBlock) void k_compact2(KArgs a) {
     if (!(c->accepted && c->move < 0)) return;
     if (i - B.a0 < c->n_all - 2) {
         a.cpos[i] = a.tpos[i];
+        a.cvel[i] = a.tvel[i];
         a.ctag[i] = a.ttag[i];
         a.ctype[i] = a.ttype[i];
         a.cmol[i] = a.tmol[i];
@@ -1364,12 +1453,33 @@ __global__ void k_commit_ctl(KArgs a) {
     Ctl *c = a.ctl + bi;
     TrialRec *r = a.rec + bi;
     if (c->accepted) {
-        if (c->move > 0) { c->n += 2; c->nsalt += 1; c->next_tag += 2; }
-        else { c->n -= 2; c->nsalt -= 1; }
+        if (c->move == 1) { c->n += 2; c->nsalt += 1; c->next_tag += 2; }
+        else if (c->move == -1) { c->n -= 2; c->nsalt -= 1; }
     }
     c->n_all = c->n;
     r->n_salt_after = c->nsalt;
-    if (!c->retry && !c->idle) c->trial += 1;
+    if (c->move == kMoveMD) { if (!c->retry) c->md += 1; }
+    else if (!c->retry && !c->idle) c->trial += 1;
+}
+
+// Every box runs `count` more equilibrium phases in a phase round and then
+// idles.
+__global__ void k_set_md_quota(KArgs a, long long count) {
+    const int bi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (bi >= a.nbox) return;
+    Ctl *c = a.ctl + bi;
+    c->md_end = c->md + count;
+}
+
+// Momenta of the state at set-up: a Maxwell-Boltzmann draw for every atom
+// (counter 0 of its own stream).
+__global__ __launch_bounds__(kBlock) void k_init_velocities(KArgs a) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= a.slots) return;
+    const int bi = box_of_slot(a, i);
+    const Box &B = a.box[bi];
+    if (i - B.a0 >= a.ctl[bi].n) return;
+    a.cvel[i] = mb_velocity(a, B, 0, kPurposeInitV, a.ctag[i], sqrt(a.G.accel * a.G.kT / a.mass[a.ctype[i]]));
 }
 
 // Every box runs `count` more trials and then idles (count < 0: no limit).
@@ -1393,6 +1503,7 @@ __global__ __launch_bounds__(kBlock) void k_broadcast_box(KArgs a, int src) {
     if (o < cs->n) {
         const int j = a.box[src].a0 + o;
         a.cpos[i] = a.cpos[j];
+        a.cvel[i] = a.cvel[j];
         a.ctag[i] = a.ctag[j];
         a.ctype[i] = a.ctype[j];
         a.cmol[i] = a.cmol[j];
@@ -1403,6 +1514,7 @@ __global__ __launch_bounds__(kBlock) void k_broadcast_box(KArgs a, int src) {
         c->n_all = cs->n_all;
         c->nsalt = cs->nsalt;
         c->next_tag = cs->next_tag;
+        c->md = cs->md;
     }
 }
 

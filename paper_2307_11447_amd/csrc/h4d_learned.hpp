@@ -101,7 +101,7 @@ __device__ __forceinline__ void pair_parts_f32(const Geo &G, const PairCoef &c, 
 __global__ void k_cand_sites(KArgs a, LearnArgs l, int phase) {
     const Ctl *c = a.ctl;
     const int move = c->move;
-    if (phase == 0 ? move <= 0 : move >= 0) return;
+    if (phase == 0 ? move != 1 : move != -1) return;
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= l.k) return;
     const Box &B = a.box[0];
@@ -243,7 +243,7 @@ __device__ __forceinline__ void site_features(const KArgs &a, const LearnArgs &l
 
 __global__ __launch_bounds__(kBlock) void k_site_features(KArgs a, LearnArgs l, int phase, int b0, int cb) {
     const int move = a.ctl->move;
-    if (phase == 0 ? move <= 0 : move >= 0) return;
+    if (phase == 0 ? move != 1 : move != -1) return;
     site_features(a, l, b0, cb);
 }
 
@@ -335,7 +335,7 @@ __global__ void k_mlp_pack(const float *theta, bf16x4 *wfrag) {
 
 __global__ void k_zero_logits(KArgs a, LearnArgs l, int phase) {
     const int move = a.ctl->move;
-    if (phase == 0 ? move <= 0 : move >= 0) return;
+    if (phase == 0 ? move != 1 : move != -1) return;
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j < l.k) l.logit[j] = 0.0f;
 }
@@ -343,7 +343,7 @@ __global__ void k_zero_logits(KArgs a, LearnArgs l, int phase) {
 // logits of the move's candidates (after k_site_features)
 __global__ __launch_bounds__(256) void k_mlp_infer_move(KArgs a, LearnArgs l, int phase) {
     const int move = a.ctl->move;
-    if (phase == 0 ? move <= 0 : move >= 0) return;
+    if (phase == 0 ? move != 1 : move != -1) return;
     mlp_tile(l.feat, l.k, l.theta, l.wfrag, l.logit);
 }
 
@@ -357,7 +357,7 @@ __global__ __launch_bounds__(256) void k_mlp_infer_move(KArgs a, LearnArgs l, in
 __global__ void k_mtm_select(KArgs a, LearnArgs l, int phase) {
     Ctl *c = a.ctl;
     const int move = c->move;
-    if (phase == 0 ? move <= 0 : move >= 0) return;
+    if (phase == 0 ? move != 1 : move != -1) return;
     const int k = l.k;
     auto lw = [&](int j) { return l.scale * fmin((double)l.logit[j], l.cap); };
     double mx = lw(0);

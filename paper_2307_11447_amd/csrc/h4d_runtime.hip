@@ -24,6 +24,7 @@
 using namespace h4d;
 
 static_assert(sizeof(TrialRec) == sizeof(h4d_trial), "record layout");
+static_assert(kMoveMD == H4D_MOVE_MD, "move code of an equilibrium phase");
 
 namespace {
 
@@ -58,6 +59,7 @@ struct h4d_system {
     int clean_trials = 0;
     bool interval_tuned = false;   // the autotuner fixed the base interval
     bool speculative = false;      // the boxes are replicas of one chain (one Philox key)
+    bool vel_canonical = false;    // the state's momenta are the canonical ones (after a phase)
     int list_split = 0;            // list-build blocks per cell (0: automatic)
     int partial_blocks = 0;
     TrialRec *h_rec = nullptr;  // per box (pinned)
@@ -140,6 +142,9 @@ int check_params(const h4d_params &p) {
         return fail(H4D_EINVAL, "cutoffs must be positive, skin, w_max and dsf_alpha non-negative");
     if (p.schedule < 0 || p.schedule > 2 || (p.schedule != 0 && !(p.schedule_n >= 1.0 && std::isfinite(p.schedule_n))))
         return fail(H4D_EINVAL, "schedule must be 0, 1 or 2, with schedule_n >= 1 for 1 and 2");
+    if (p.momenta != 0 && p.momenta != 1) return fail(H4D_EINVAL, "momenta must be 0 or 1");
+    if (p.momenta && p.water) return fail(H4D_EINVAL, "carried momenta need an ion system (water = 0)");
+    if (!(p.md_refresh >= 0.0 && p.md_refresh <= 1.0)) return fail(H4D_EINVAL, "md_refresh must lie in [0, 1]");
     if (p.water && !(p.d_oh > 0.0 && p.d_hh > 0.0 && p.d_hh < 2.0 * p.d_oh))
         return fail(H4D_EINVAL, "rigid water needs 0 < d_hh < 2 d_oh");
     return H4D_OK;
@@ -183,6 +188,8 @@ void setup_geo(h4d_system *s) {
     G.w_max = p.w_max;
     G.schedule = p.schedule;
     G.schedule_n = p.schedule_n;
+    G.momenta = p.momenta;
+    G.md_refresh = p.md_refresh;
     G.kappa = p.kappa_sr;
     G.lambda3 = p.lambda_s * p.lambda_s * p.lambda_s;
     G.beta = 1.0 / p.kT;
@@ -507,7 +514,7 @@ int enqueue_round(h4d_system *s, int move, hipStream_t st, int nf, int M, bool t
     int rc;
     hipLaunchKernelGGL(k_propose, dim3(s->nbox), dim3(kBlock), 0, st, a, move);
     if ((rc = sort_in(s, st))) return rc;
-    if (s->la.k > 0) {   // learned insertion: score k candidates, move the ghosts, sort again
+    if (s->la.k > 0 && move != kMoveMD) {   // learned insertion: score k candidates, move the ghosts, sort again
         enqueue_learned(s, st, 0, 0, 0);
         if ((rc = sort_in(s, st))) return rc;
     }
@@ -529,7 +536,7 @@ int enqueue_round(h4d_system *s, int move, hipStream_t st, int nf, int M, bool t
     if ((rc = rebuild_final(s, st))) return rc;
     hipLaunchKernelGGL(k_energy, dim3(a.step_blocks), dim3(kBlock), 0, st, a, 1, -1, 0.0, -1);
     hipLaunchKernelGGL(k_energy_final, dim3(s->nbox), dim3(kBlock), 0, st, a, 1);
-    if (s->la.k > 0) enqueue_learned(s, st, 1, -1, s->cl);   // learned deletion: reverse weights
+    if (s->la.k > 0 && move != kMoveMD) enqueue_learned(s, st, 1, -1, s->cl);   // learned deletion: reverse weights
     if (a.G.bias_alpha > 0.0) hipLaunchKernelGGL(k_bias_end, dim3(s->nbox), dim3(kBlock), 0, st, a);
     hipLaunchKernelGGL(k_metropolis, dim3(blocks_for(s->nbox)), dim3(kBlock), 0, st, a);
     hipLaunchKernelGGL(k_commit, dim3(G1), dim3(kBlock), 0, st, a);
@@ -543,7 +550,8 @@ int enqueue_round(h4d_system *s, int move, hipStream_t st, int nf, int M, bool t
 int launch_round(h4d_system *s, int move) {
     KArgs &a = s->a;
     hipStream_t st = s->stream;
-    const int nf = s->p.n_steps_max > 0 ? s->p.n_steps_max : s->p.n_steps;
+    const int nf = move == kMoveMD ? a.md_steps : (s->p.n_steps_max > 0 ? s->p.n_steps_max : s->p.n_steps);
+    if (move != kMoveMD) s->vel_canonical = false;
     const int M = std::max(1, s->trial_M);
     int rc;
     s->trial_rebuilds = nf / M + 1;
@@ -728,6 +736,46 @@ int run_batch(h4d_system *s, int T, int move, h4d_trial *out) {
     return set_quota(s, -1);
 }
 
+// One equilibrium phase of every box (its records in out[b]); a box whose
+// phase overflowed a list repeats it after the resize while the others idle.
+int run_md(h4d_system *s, int n_steps, h4d_trial *out) {
+    KArgs &a = s->a;
+    if (a.md_steps != n_steps) {
+        a.md_steps = n_steps;
+        s->drop_graphs();     // the graphs captured the step count
+    }
+    hipLaunchKernelGGL(k_set_md_quota, dim3(blocks_for(s->nbox)), dim3(kBlock), 0, s->stream, a, 1LL);
+    HIPC(hipGetLastError());
+    int rc = read_ctl(s);
+    if (rc) return rc;
+    s->trial_M = std::max(1, s->rebuild_every);
+    for (int round = 0; round < 64; ++round) {
+        bool busy = false;
+        for (int b = 0; b < s->nbox; ++b) busy |= s->h_ctl[b].md < s->h_ctl[b].md_end;
+        if (!busy) {
+            s->vel_canonical = true;
+            return H4D_OK;
+        }
+        if ((rc = launch_round(s, kMoveMD))) return rc;
+        bool any_retry = false;
+        for (int b = 0; b < s->nbox; ++b) {
+            const TrialRec &tr = s->h_rec[b];
+            if (tr.flags & kFlagIdle) continue;
+            if (s->h_ctl[b].retry) { any_retry = true; continue; }
+            h4d_trial r;
+            std::memcpy(&r, &tr, sizeof(r));
+            r.n_rebuilds = s->trial_rebuilds;
+            if (out) out[b] = r;
+        }
+        if (any_retry) {
+            handle_retries(s, rc);
+            if (rc) return rc;
+            if ((rc = read_ctl(s))) return rc;
+        }
+    }
+    return fail(H4D_EHIP, "equilibrium phase could not be completed after resizing the lists");
+}
+
 int create(const h4d_params *params, int nbox, const double *edges, const int32_t *n_atoms, const int32_t *n_salt,
            int32_t n_mol, const double *pos, const int32_t *type, const int32_t *mol, const int64_t *tag,
            void *hip_stream, h4d_system **out, bool speculative = false) {
@@ -744,6 +792,8 @@ int create(const h4d_params *params, int nbox, const double *edges, const int32_
     if (total > 0 && (!pos || !type || !tag)) return fail(H4D_EINVAL, "null configuration array");
     if (params->water && nbox != 1 && !speculative)
         return fail(H4D_EINVAL, "rigid water needs a single box (or speculative replicas)");
+    if (params->momenta && speculative)
+        return fail(H4D_EINVAL, "carried momenta need trials one after another (no speculative replicas)");
     const double rc_max = std::max(params->rc_lj, params->rc_coul);
     for (int q = 0; q < 3 * nbox; ++q)
         if (!(edges[q] >= 2.0 * rc_max)) return fail(H4D_EINVAL, "every box edge must be at least twice the largest cutoff");
@@ -832,7 +882,8 @@ int create(const h4d_params *params, int nbox, const double *edges, const int32_
     double *mass_d = nullptr;
     Box *box_d = nullptr;
     int *slot_box_d = nullptr, *cell_box_d = nullptr;
-    if ((rc = s->alloc(&a.cpos, C)) || (rc = s->alloc(&a.ctag, C)) || (rc = s->alloc(&a.ctype, C)) ||
+    if ((rc = s->alloc(&a.cpos, C)) || (rc = s->alloc(&a.cvel, C)) || (rc = s->alloc(&a.tvel, C)) ||
+        (rc = s->alloc(&a.ctag, C)) || (rc = s->alloc(&a.ctype, C)) ||
         (rc = s->alloc(&a.cmol, C)) || (rc = s->alloc(&a.pos[0], C)) || (rc = s->alloc(&a.pos[1], C)) ||
         (rc = s->alloc(&a.fx[0], C)) || (rc = s->alloc(&a.fx[1], C)) || (rc = s->alloc(&a.vel[0], C)) ||
         (rc = s->alloc(&a.vel[1], C)) || (rc = s->alloc(&a.perm, C)) || (rc = s->alloc(&a.wmol, C)) ||
@@ -915,6 +966,11 @@ int create(const h4d_params *params, int nbox, const double *edges, const int32_
     s->rebuild_every = params->rebuild_every > 0
                            ? params->rebuild_every
                            : std::max(1, (int)std::floor(0.5 * params->skin / (vmax * params->dt)));
+    if (!params->water) {   // the state's own momenta (carried momenta, equilibrium phases)
+        hipLaunchKernelGGL(k_init_velocities, dim3(slot_blocks(s)), dim3(kBlock), 0, s->stream, s->a);
+        if (hipGetLastError() != hipSuccess) { delete s; return fail(H4D_EHIP, "velocity set-up failed"); }
+        s->vel_canonical = true;
+    }
     if ((rc = h4d_build_neighbors(s))) { delete s; return rc; }
     *out = s;
     return H4D_OK;
@@ -947,7 +1003,11 @@ int box_state(h4d_system *s, int box, int32_t cap, int32_t *n, int32_t *n_salt, 
         HIPC(hipMemcpy(buf.data(), s->a.cpos + B.a0, sizeof(double4) * nn, hipMemcpyDeviceToHost));
         for (int i = 0; i < nn; ++i) { pos[3 * i] = buf[i].x; pos[3 * i + 1] = buf[i].y; pos[3 * i + 2] = buf[i].z; }
     }
-    if (vel && nn) {
+    if (vel && nn && (s->p.momenta || s->vel_canonical)) {
+        // the state's own momenta (carried momenta, or after an equilibrium phase)
+        HIPC(hipMemcpy(buf.data(), s->a.cvel + B.a0, sizeof(double4) * nn, hipMemcpyDeviceToHost));
+        for (int i = 0; i < nn; ++i) { vel[3 * i] = buf[i].x; vel[3 * i + 1] = buf[i].y; vel[3 * i + 2] = buf[i].z; }
+    } else if (vel && nn) {
         // velocities are those of the last trajectory's end, in canonical order
         std::vector<int> perm(nn);
         HIPC(hipMemcpy(perm.data(), s->a.perm + B.a0, sizeof(int) * nn, hipMemcpyDeviceToHost));
@@ -1034,6 +1094,13 @@ int32_t h4d_init_speculative(const h4d_params *params, int32_t replicas, int32_t
     }
     return create(params, replicas, edges.data(), na.data(), ns.data(), n_mol, p.data(), ty.data(),
                   mol ? mo.data() : nullptr, tg.data(), hip_stream, out, true);
+}
+
+int32_t h4d_run_md(h4d_system *s, int32_t n_steps, h4d_trial *out) {
+    if (!s) return fail(H4D_EINVAL, "null handle");
+    if (n_steps < 1) return fail(H4D_EINVAL, "n_steps must be at least 1");
+    if (s->p.water) return fail(H4D_EINVAL, "the equilibrium phase needs an ion system (water = 0)");
+    return run_md(s, n_steps, out);
 }
 
 int32_t h4d_run_speculative(h4d_system *s, int32_t n_trials, int32_t move, h4d_trial *out, int32_t *rounds_out) {

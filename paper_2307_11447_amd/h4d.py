@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libh4d.so")
 MAX_TYPES = 8
 
 H4D_OK, H4D_EINVAL, H4D_ENOMEM, H4D_EHIP, H4D_ECAPACITY, H4D_ENONFINITE, H4D_ENODEV = 0, -1, -2, -3, -4, -5, -6
-MOVE_AUTO, MOVE_INSERT, MOVE_DELETE = 0, 1, -1
+MOVE_AUTO, MOVE_INSERT, MOVE_DELETE, MOVE_MD = 0, 1, -1, 2
 PREC_FP64, PREC_FP32 = 0, 1
 FLAG_EMPTY, FLAG_NONFINITE, FLAG_RETRIED, FLAG_IDLE = 0x1, 0x2, 0x4, 0x8
 
@@ -42,6 +42,7 @@ class Params(C.Structure):
         ("seed", C.c_uint64), ("stream", C.c_uint64),
         ("bias_xb", C.c_double), ("bias_alpha", C.c_double),
         ("schedule_n", C.c_double),
+        ("momenta", C.c_int32), ("md_refresh", C.c_double),
     ]
 
 
@@ -148,6 +149,7 @@ def lib() -> C.CDLL:
         L.h4d_site_features.argtypes = [vp, C.c_int32, dp, fp]
         L.h4d_set_beta_mu.argtypes = [vp, C.c_double]
         L.h4d_set_bias.argtypes = [vp, C.c_double, C.c_double]
+        L.h4d_run_md.argtypes = [vp, C.c_int32, C.POINTER(Trial)]
         for name in ("h4d_stream_copy", "h4d_set_timing", "h4d_get_timing", "h4d_init_system", "h4d_build_neighbors",
                      "h4d_run_nemd_trial", "h4d_run_trials", "h4d_sample_observables", "h4d_get_state",
                      "h4d_set_trial_index", "h4d_forces_at", "h4d_destroy", "h4d_init_batch", "h4d_num_boxes",
@@ -155,7 +157,7 @@ def lib() -> C.CDLL:
                      "h4d_mlp_create", "h4d_mlp_destroy", "h4d_mlp_set_weights", "h4d_mlp_get_weights",
                      "h4d_mlp_forward", "h4d_mlp_loss_grad", "h4d_mlp_train", "h4d_set_proposal",
                      "h4d_last_site_features", "h4d_last_candidates", "h4d_site_features", "h4d_set_beta_mu",
-                     "h4d_init_speculative", "h4d_run_speculative", "h4d_set_bias"):
+                     "h4d_init_speculative", "h4d_run_speculative", "h4d_set_bias", "h4d_run_md"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -180,6 +182,7 @@ def make_params(d: dict) -> Params:
     p.lanes_per_atom = d.get("lanes_per_atom", 0)
     p.bias_xb, p.bias_alpha = d.get("bias_xb", 0.0), d.get("bias_alpha", 0.0)
     p.schedule, p.schedule_n = d.get("schedule", 0), d.get("schedule_n", 1.0)
+    p.momenta, p.md_refresh = d.get("momenta", 0), d.get("md_refresh", 0.0)
     for name in ("mass", "charge", "sigma", "eps"):
         arr = getattr(p, name)
         for i, v in enumerate(d[name]):
@@ -339,6 +342,16 @@ class _Handle:
 
     def box_state(self, box: int) -> dict:
         return _state_of(self._h, box)
+
+    def md_phase(self, n_steps: int, as_array: bool = False):
+        """One equilibrium phase (generalized hybrid MC, n_steps steps) in
+        every box; one record per box."""
+        nb = self.n_boxes
+        recs = (Trial * nb)()
+        _check(lib().h4d_run_md(self._h, n_steps, recs))
+        if as_array:
+            return recs
+        return [recs[b].as_dict() for b in range(nb)]
 
     def box_observables(self, box: int) -> dict:
         o = Observables()

@@ -69,3 +69,15 @@ def test_invalid_parameters_are_rejected_before_any_device_work():
     with pytest.raises(h4d.H4DError) as e:
         h4d.System(small_box, w.x % 5.0, w.type, w.mol, w.tag, w.nsalt, stream=C.c_void_p())
     assert e.value.code == h4d.H4D_EINVAL
+
+
+def test_momentum_options_are_validated_before_any_device_work():
+    from paper_2307_11447_amd import workloads as W
+    w = W.small_lj(64, 0.3, 1)
+    for bad in (dict(w.params, momenta=2), dict(w.params, md_refresh=1.5), dict(w.params, md_refresh=-0.1)):
+        with pytest.raises(h4d.H4DError) as e:
+            h4d.System(bad, w.x, w.type, w.mol, w.tag, w.nsalt, stream=C.c_void_p())
+        assert e.value.code == h4d.H4D_EINVAL
+    with pytest.raises(h4d.H4DError) as e:   # replicas of one chain cannot carry momenta
+        h4d.Speculative(dict(w.params, momenta=1), 4, w.x, w.type, w.mol, w.tag, w.nsalt, stream=C.c_void_p())
+    assert e.value.code == h4d.H4D_EINVAL

@@ -1,0 +1,102 @@
+"""Equilibrium phases between trials and trials with carried momenta on
+the GPU against the FP64 oracle (records, positions and momenta after every
+step of a mixed sequence), in one box and in a batch."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2307_11447_amd import h4d
+from paper_2307_11447_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def close_state(g, o, atol=1e-7):
+    assert g["n"] == o.n and g["nsalt"] == o.nsalt
+    assert np.array_equal(g["tag"], o.tag[: o.n])
+    L = o.pd["box"][0]
+    d = g["x"] - o.positions()
+    d -= L * np.round(d / L)
+    assert np.abs(d).max() < atol
+    assert np.abs(g["v"] - o.velocities()).max() < atol
+
+
+def same_record(rg, ro, what):
+    assert rg["move"] == ro["move"] and rg["accepted"] == ro["accepted"], (what, rg, ro)
+    assert rg["trial"] == ro["trial"], what
+    if not ro["flags"]:
+        assert abs(rg["dH"] - ro["dH"]) < 1e-6 * max(1.0, abs(ro["dH"])), (what, rg["dH"], ro["dH"])
+        assert rg["ln_u"] == pytest.approx(ro["ln_u"], abs=1e-12), what
+
+
+@pytest.mark.parametrize("refresh,dt", [(0.0, 0.005), (0.6, 0.02)])
+def test_md_phases_match_the_oracle(refresh, dt):
+    say(f"case md phases lj300 fp64, refresh {refresh}, dt {dt}")
+    w = W.lj_electrolyte(300, 0.3, 77, n_steps=20, precision="fp64")
+    w.params.update(md_refresh=refresh, dt=dt)
+    g = h4d.System.from_workload(w)
+    o = O.OracleSystem.from_workload(w, cap=w.n + 64)
+    close_state(g.state(), o)             # the same initial momenta
+    acc = 0
+    for p in range(6):
+        rg = g.md_phase(15)[0]
+        ro = o.md_phase(p, 15)
+        same_record(rg, ro, f"phase {p}")
+        close_state(g.state(), o)
+        acc += ro["accepted"]
+    say(f"   accepted {acc} of 6")
+    g.close()
+
+
+def test_carried_momenta_sequence_matches_the_oracle():
+    say("case carried momenta lj300 fp64: phases and trials interleaved")
+    w = W.lj_electrolyte(300, 0.1, 78, n_steps=30, precision="fp64")
+    w.params.update(momenta=1, md_refresh=0.5, beta_mu=10.0, kappa_sr=0.4)
+    g = h4d.System.from_workload(w)
+    o = O.OracleSystem.from_workload(w, cap=w.n + 64)
+    n_acc = 0
+    for t in range(10):
+        rg = g.md_phase(10)[0]
+        ro = o.md_phase(t, 10)
+        same_record(rg, ro, f"phase {t}")
+        rg = g.trial()
+        ro = o.trial(t)
+        same_record(rg, ro, f"trial {t}")
+        n_acc += ro["accepted"]
+        close_state(g.state(), o, atol=1e-6)
+    say(f"   trials accepted {n_acc} of 10")
+    assert n_acc > 0
+    g.close()
+
+
+def test_batched_phases_match_the_oracle_per_box():
+    say("case md phases, batch of 3 lj boxes fp64")
+    ws = [W.lj_electrolyte(n, 0.1, 90 + n, n_steps=20, precision="fp64") for n in (340, 400, 460)]
+    for w in ws:
+        w.params.update(md_refresh=0.3, momenta=1, beta_mu=10.0)
+    bat = h4d.Batch.from_workloads(ws)
+    os_ = []
+    for b, w in enumerate(ws):
+        p = dict(ws[0].params, box=w.params["box"], stream=ws[0].params["stream"] + b)
+        os_.append(O.OracleSystem(p, w.x, w.type, w.mol, w.tag, w.nsalt, cap=w.n + 64))
+    n_acc = 0
+    for t in range(4):
+        rg = bat.md_phase(12)
+        for b in range(3):
+            same_record(rg[b], os_[b].md_phase(t, 12), f"box {b} phase {t}")
+        rt = bat.run(1)
+        for b in range(3):
+            ro = os_[b].trial(t)
+            same_record(rt[b][0], ro, f"box {b} trial {t}")
+            n_acc += ro["accepted"]
+    say(f"   trials accepted {n_acc} of 12")
+    for b in range(3):
+        close_state(bat.box_state(b), os_[b], atol=1e-6)
+    bat.close()
