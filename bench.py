@@ -377,6 +377,49 @@ def uniform_leg_speculative(args, h4d, torch, w, beta_mu):
     return recs, wall, timing, atom_launches, info
 
 
+def gcmd_leg(args, h4d, torch, w, beta_mu, tuned):
+    """The grand-canonical cycle of Fig. 1: an equilibrium phase of
+    args.n_eq steps (generalized hybrid MC with partial momentum refresh)
+    and one exchange trial that carries the state's momenta with the
+    symmetric two-end reversal, one cycle after another on one box."""
+    over = dict(beta_mu=beta_mu, momenta=1, md_refresh=args.md_refresh)
+    if tuned:
+        over.update(lanes_per_atom=tuned[0], rebuild_every=tuned[1])
+    g = h4d.System.from_workload(w, **over)
+    g.md_phase(args.n_eq)
+    g.trial()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    md_recs, tr_recs = [], []
+    t_md = 0.0
+    for _ in range(args.gcmd_cycles):
+        t1 = time.perf_counter()
+        md_recs.append(g.md_phase(args.n_eq)[0])
+        torch.cuda.synchronize()
+        t_md += time.perf_counter() - t1
+        tr_recs.append(g.trial())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    g.close()
+    n_md = sum(r["accepted"] for r in md_recs)
+    n_tr = sum(r["accepted"] for r in tr_recs)
+    steps = sum(r["n_atoms"] * (r["n_steps"] + 1) for r in md_recs + tr_recs)
+    note(f"gcmd: {args.gcmd_cycles} cycles of {args.n_eq} equilibrium steps and one trial in {wall:.1f} s")
+    p_tr = n_tr / max(1, len(tr_recs))
+    nf = tr_recs[0]["n_steps"] if tr_recs else 0
+    return {
+        "cycle": f"equilibrium phase of {args.n_eq} steps (partial momentum refresh c = {args.md_refresh}, "
+                 "Metropolis on dH) + one trial with carried momenta and the two-end reversal",
+        "cycles": args.gcmd_cycles, "wall_s": wall, "ms_per_cycle": 1e3 * wall / max(1, args.gcmd_cycles),
+        "equilibrium_share_of_wall": t_md / max(wall, 1e-300),
+        "atom_steps_per_s": steps / max(wall, 1e-300),
+        "equilibrium_acceptance": n_md / max(1, len(md_recs)),
+        "equilibrium_mean_abs_beta_dH": sum(abs(r["dH"]) for r in md_recs) / max(1, len(md_recs)) / w.params["kT"],
+        "trials_accepted": n_tr, "trial_acceptance": p_tr,
+        "efficiency_per_step": p_tr / max(1, nf + args.n_eq),
+    }
+
+
 def bench_single(args, h4d, W, torch):
     import numpy as np
     maker, desc, label, shape = SINGLE[args.workload]
@@ -473,6 +516,7 @@ def bench_single(args, h4d, W, torch):
     sys_.close()
     if net is not None:
         net.close()
+    gcmd = gcmd_leg(args, h4d, torch, w, beta_mu, tuned) if args.gcmd_cycles > 0 and not w.params["water"] else None
     traffic = counted_traffic(TRAFFIC_FILE) if args.workload == "lj32k" else None
     seq_timing_recs = [tarr[q] for q in range(n_seq_timing)]
     if speculative:
@@ -520,6 +564,8 @@ def bench_single(args, h4d, W, torch):
         "fixed_state_gain_bootstrap90": ab.get("gain_bootstrap90") if ab is not None else None,
         "out_of_fold_corr_logit_vs_target": oof_corr,
     }
+    if gcmd is not None:
+        out["gcmd"] = gcmd
     out["bimodal_bias"] = {
         "x_b": BIAS[args.workload][0], "alpha_b": BIAS[args.workload][1],
         "note": "the paper's bias of the flying pair's separation (Sec. II B 4), in the fixed-state comparison",
@@ -616,6 +662,10 @@ def main():
     ap.add_argument("--timing-trials", type=int, default=None,
                     help="trials run after the timed region with HIP events on the step kernel (20 / 2)")
     ap.add_argument("--cpu-steps", type=int, default=12, help="oracle sample length (NEMD steps)")
+    ap.add_argument("--gcmd-cycles", type=int, default=10,
+                    help="single ion box: grand-canonical cycles (equilibrium phase + one trial) timed after the rest")
+    ap.add_argument("--n-eq", type=int, default=1000, help="steps of an equilibrium phase (the paper's N_eq)")
+    ap.add_argument("--md-refresh", type=float, default=0.5, help="momentum persistence c of the equilibrium phase")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rebuild-every", type=int, default=0, help="list rebuild interval (0: library default)")
     ap.add_argument("--lanes", type=int, default=0, help="lanes per atom (0: library default)")
