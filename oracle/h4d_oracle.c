@@ -238,6 +238,13 @@ static int enumerate_fly_pairs(const or_params *p, const or_state *s, double rcu
 /* ------------------------------------------------------------------ */
 /* Energy and forces                                                   */
 /* ------------------------------------------------------------------ */
+/* Species-specific w_max (supplement): both flyers reach w = 0 together,
+ * the anion's altitude r_w times the cation's all along the schedule, so
+ * w is the cation's altitude and each flyer has its own factor. */
+static double w_ratio(const or_params *p) { return p->w_max_ratio > 0.0 ? p->w_max_ratio : 1.0; }
+
+static double flyer_factor(const or_params *p, int type) { return type == p->anion_type ? w_ratio(p) : 1.0; }
+
 int or_compute(const or_params *p, const or_state *s, double w, int mode,
                double *F, or_energy *e)
 {
@@ -251,7 +258,10 @@ int or_compute(const or_params *p, const or_state *s, double w, int mode,
     int rc = (mode == OR_MODE_FLY) ? enumerate_fly_pairs(p, s, rcut, &pl)
                                    : enumerate_pairs(p, s, rcut, &pl);
     if (rc) { pl_free(&pl); return -1; }
-    const double gscr = exp(-p->kappa_sr * w);
+    /* Eq. 11 screening at the flyers' mean altitude (Sec. II B 2: with
+     * several flyers at different altitudes, the average one) */
+    const double wbar = 0.5 * w * (1.0 + w_ratio(p));
+    const double gscr = exp(-p->kappa_sr * wbar);
     for (int64_t k = 0; k < pl.n; ++k) {
         const int i = pl.i[k], j = pl.j[k];
         const int fi = s->flying[i], fj = s->flying[j];
@@ -262,7 +272,8 @@ int or_compute(const or_params *p, const or_state *s, double w, int mode,
             r[d] = minimg(s->x[3 * i + d] - s->x[3 * j + d], p->box[d]);
             r2 += r[d] * r[d];
         }
-        const double wi = fi ? w : 0.0, wj = fj ? w : 0.0;
+        const double ri = fi ? flyer_factor(p, s->type[i]) : 0.0, rj = fj ? flyer_factor(p, s->type[j]) : 0.0;
+        const double wi = ri * w, wj = rj * w;
         const double dw = wi - wj;
         const double s2 = r2 + dw * dw;
         const int one_flying = (fi != fj);
@@ -283,8 +294,10 @@ int or_compute(const or_params *p, const or_state *s, double w, int mode,
                 F[3 * j + d] -= fs * r[d];
             }
         }
-        /* dU/dw: ds/dw = w/s for one flyer; dg/dw = -kappa_sr g. */
-        if (one_flying) e->dUdw += duds * (w / sd) - p->kappa_sr * uc;
+        /* dU/dw: ds/dw = dw (r_i - r_j) / s with the flyers' factors r;
+         * dg/dw = -kappa_sr (1 + r_w) / 2 g for a flyer-nonflyer pair. */
+        if (sd > 0.0) e->dUdw += duds * (dw * (ri - rj) / sd);
+        if (one_flying) e->dUdw -= p->kappa_sr * 0.5 * (1.0 + w_ratio(p)) * uc;
     }
     pl_free(&pl);
     return 0;

@@ -44,6 +44,9 @@ typedef struct {
                             /* the state's momenta carried into the trajectory    */
                             /* with the symmetric two-end reversal (Sec. II A)    */
     double md_refresh;      /* equilibrium phase: v <- c v + sqrt(1 - c^2) xi     */
+    double w_max_ratio;     /* species-specific w_max (supplement): the anion     */
+                            /* flies at w_max_ratio times the cation's altitude;  */
+                            /* 0 or 1: both at the same altitude                  */
 } or_params;
 
 /* Configuration.  Arrays are owned by the caller and sized to cap. */

@@ -36,6 +36,7 @@ class Params(C.Structure):
         ("bias_xb", C.c_double), ("bias_alpha", C.c_double),
         ("schedule", C.c_int32), ("schedule_n", C.c_double),
         ("momenta", C.c_int32), ("md_refresh", C.c_double),
+        ("w_max_ratio", C.c_double),
     ]
 
 
@@ -143,6 +144,7 @@ def make_params(d: dict, use_cells: bool = True) -> Params:
     p.bias_xb, p.bias_alpha = d.get("bias_xb", 0.0), d.get("bias_alpha", 0.0)
     p.schedule, p.schedule_n = d.get("schedule", 0), d.get("schedule_n", 1.0)
     p.momenta, p.md_refresh = d.get("momenta", 0), d.get("md_refresh", 0.0)
+    p.w_max_ratio = d.get("w_max_ratio", 0.0)
     return p
 
 
