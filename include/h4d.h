@@ -130,6 +130,15 @@ typedef struct h4d_params {
                                    only; not with speculative replicas)         */
     double md_refresh;          /* c in [0, 1] of the equilibrium phase's
                                    momentum refresh, see h4d_run_md             */
+    double w_max_ratio;         /* species-specific w_max (the supplement's
+                                   remedy for overlapping flyers): the anion
+                                   flies at r_w = w_max_ratio times the cation's
+                                   altitude all along the schedule (w_max is
+                                   the cation's), both reaching w = 0 together;
+                                   their own pair sits at (w_c - w_a)^2 and
+                                   Eq. 11 screening takes the flyers' mean
+                                   altitude (Sec. II B 2).  0 or 1: one
+                                   altitude for both                           */
 } h4d_params;
 
 /* One trial (move +1 insertion, -1 deletion). */
@@ -311,7 +320,8 @@ int32_t h4d_set_bias(h4d_system *sys, double x_b, double alpha_b);
 
 /*
  * Test hook (single-box handles): forces and FP64 energy of the current state with atoms
- * flying[0], flying[1] (-1: none) lifted to altitude w, as in the NEMD pass.
+ * flying[0], flying[1] (-1: none) lifted to altitude w, as in the NEMD pass
+ * (an anion among them to w_max_ratio * w when that is set).
  * forces[3*n] (host) receives F on every non-flying atom (0 on flyers),
  * computed in the handle's precision; energy[3] receives U, U_lj, U_coul.
  */

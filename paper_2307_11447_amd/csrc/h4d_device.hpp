@@ -91,6 +91,9 @@ struct Geo {
     // state's own, carried between trials with the two-end reversal
     int momenta;
     double md_refresh;       // equilibrium phase: v <- c v + sqrt(1 - c^2) xi
+    // species-specific w_max: the anion flies at w_ratio times the cation's
+    // altitude (1: both at the same altitude)
+    double w_ratio;
 };
 
 // --------------------------------------------------------------------------

@@ -764,14 +764,15 @@ __global__ __launch_bounds__(kBlock) void k_list_lanes(KArgs a, int k, int b0, i
 }
 
 // ==========================================================================
-// Force on one atom at altitude w (flyers at w), by the L lanes of its group,
+// Force on one atom at altitude w (flyers at w; with SP the anion flyer at
+// w_ratio w, species-specific w_max), by the L lanes of its group,
 // reduced over the group in a fixed order.  An atom that has moved beyond
 // half the skin since the list build is "fast": pairs with fast atoms come
 // from the fast list instead of the Verlet list, and a fast atom's own
 // partners come from the 27 cells of the last build (cell edge >= r_c +
 // skin covers every partner within r_c).  Every pair is counted once.
 // ==========================================================================
-template <int PREC, int L>
+template <int PREC, int L, bool SP>
 __device__ __forceinline__ void group_force(const KArgs &a, const Box &B, const Ctl *c, const CoefLds &cf, int b,
                                             int cl, int w, int s, const double4 &pi, int mi, double wv, double gscr,
                                             const int *flist, int nfast, double &fx, double &fy, double &fz) {
@@ -787,6 +788,7 @@ __device__ __forceinline__ void group_force(const KArgs &a, const Box &B, const 
         const uint4 *F = a.fx[b];
         const uint4 qi = F[w];
         const float w2 = (float)(wv * wv), g = (float)gscr;
+        const float w2a = SP ? (float)((wv * a.G.w_ratio) * (wv * a.G.w_ratio)) : w2;
         const float sx = B.fx_scale[0], sy = B.fx_scale[1], sz = B.fx_scale[2];
         float ax = 0.f, ay = 0.f, az = 0.f;
         auto pair = [&](const uint4 &qj, bool valid) {
@@ -796,7 +798,7 @@ __device__ __forceinline__ void group_force(const KArgs &a, const Box &B, const 
             const int mj = (int)qj.w;
             const bool fj = (mj & kFlyBit) != 0;
             const float r2 = dx * dx + dy * dy + dz * dz;
-            const float s2 = fj ? r2 + w2 : r2;
+            const float s2 = fj ? r2 + ((SP && (mj & kTypeMask) == a.anion_type) ? w2a : w2) : r2;
             const bool ok = valid && s2 < a.G.rc_max2f;
             const float fs = pair_fs_f32(a.G, crow[mj & kTypeMask], ok ? s2 : a.G.rc_max2f, fj ? g : 1.0f);
             const float f = ok ? fs : 0.0f;
@@ -848,6 +850,7 @@ __device__ __forceinline__ void group_force(const KArgs &a, const Box &B, const 
         const double4 *P = a.pos[b];
         double ax = 0.0, ay = 0.0, az = 0.0;
         const double w2 = wv * wv;
+        const double w2a = SP ? (wv * a.G.w_ratio) * (wv * a.G.w_ratio) : w2;
         auto pair = [&](const double4 &pj, bool valid) {
             if (!valid) return;
             const double dx = min_image(pi.x - pj.x, B.L[0]);
@@ -856,7 +859,7 @@ __device__ __forceinline__ void group_force(const KArgs &a, const Box &B, const 
             const int mj = meta_of(pj);
             const bool fj = (mj & kFlyBit) != 0;
             const double r2 = dx * dx + dy * dy + dz * dz;
-            const double s2 = fj ? r2 + w2 : r2;
+            const double s2 = fj ? r2 + ((SP && (mj & kTypeMask) == a.anion_type) ? w2a : w2) : r2;
             if (s2 < a.G.rc_max2) {
                 const double fs = pair_fs_f64(a.G, crow[mj & kTypeMask], s2, fj ? gscr : 1.0);
                 ax += fs * dx; ay += fs * dy; az += fs * dz;
@@ -911,6 +914,7 @@ __device__ __forceinline__ void group_force(const KArgs &a, const Box &B, const 
 // come from the fast list in group_force.  Every lane of the wavefront
 // calls this; mine marks lane s = 0 of a fast, non-flying, active atom, and
 // that lane's force gains the sum (fixed butterfly order).
+template <bool SP>
 __device__ __forceinline__ void fast_atoms_wave(const KArgs &a, const Box &B, const CoefLds &cf, int b, int cl,
                                                 bool mine, int w, int lane, double wv, double gscr, double &fx,
                                                 double &fy, double &fz) {
@@ -918,6 +922,7 @@ __device__ __forceinline__ void fast_atoms_wave(const KArgs &a, const Box &B, co
     if (fm == 0ull || !B.use_cells) return;
     const uint4 *F = a.fx[b];
     const float w2 = (float)(wv * wv), g = (float)gscr;
+    const float w2a = SP ? (float)((wv * a.G.w_ratio) * (wv * a.G.w_ratio)) : w2;
     const float sx = B.fx_scale[0], sy = B.fx_scale[1], sz = B.fx_scale[2];
     while (fm != 0ull) {
         const int src = __ffsll((long long)fm) - 1;
@@ -946,7 +951,7 @@ __device__ __forceinline__ void fast_atoms_wave(const KArgs &a, const Box &B, co
                 const int mj = (int)qj.w;
                 const bool fj = (mj & kFlyBit) != 0;
                 const float r2 = dx * dx + dy * dy + dz * dz;
-                const float s2 = fj ? r2 + w2 : r2;
+                const float s2 = fj ? r2 + ((SP && (mj & kTypeMask) == a.anion_type) ? w2a : w2) : r2;
                 const bool ok = valid && s2 < a.G.rc_max2f;
                 const float fs = pair_fs_f32(a.G, crow[mj & kTypeMask], ok ? s2 : a.G.rc_max2f, fj ? g : 1.0f);
                 const float f = ok ? fs : 0.0f;
@@ -975,9 +980,12 @@ __device__ __forceinline__ bool moved_beyond_half_skin(const KArgs &a, const Box
 // --------------------------------------------------------------------------
 // Flying work of one flyer at x_k (one wavefront per flyer): the trapezoid
 // share 1/2 [U_fly(x_k; w_{k+1}) - U_fly(x_k; w_{k-1})] (endpoints clamped),
-// accumulated in FP64 (pair energies in the precision of the pass).
+// accumulated in FP64 (pair energies in the precision of the pass).  With
+// SP (species-specific w_max) each flyer sits at its own altitude, the
+// screening follows the flyers' mean altitude, and the flyer-flyer pair,
+// whose altitude difference now changes, adds its share once (wave 0).
 // --------------------------------------------------------------------------
-template <int PREC>
+template <int PREC, bool SP>
 __device__ void flyer_work(const KArgs &a, const Box &B, Ctl *c, const CoefLds &cf, int b, int k, const int *flist,
                            int nfast) {
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -986,8 +994,14 @@ __device__ void flyer_work(const KArgs &a, const Box &B, Ctl *c, const CoefLds &
     if (move == 0 || move == kMoveMD || k > nf) return;
     const int f = wave == 0 ? c->wic : c->wia;
     const int other = wave == 0 ? c->wia : c->wic;
-    const double wlo = altitude(a.G, move, k > 0 ? k - 1 : 0, nf);
-    const double whi = altitude(a.G, move, k < nf ? k + 1 : nf, nf);
+    const double wlo0 = altitude(a.G, move, k > 0 ? k - 1 : 0, nf);
+    const double whi0 = altitude(a.G, move, k < nf ? k + 1 : nf, nf);
+    // this flyer's own altitudes (wave 1 is the anion) and the screening altitudes
+    const double rf = (SP && wave == 1) ? a.G.w_ratio : 1.0;
+    const double wlo = wlo0 * rf, whi = whi0 * rf;
+    const double slo = SP ? 0.5 * wlo0 * (1.0 + a.G.w_ratio) : wlo0;
+    const double shi = SP ? 0.5 * whi0 * (1.0 + a.G.w_ratio) : whi0;
+    const double dflo = SP ? wlo0 * (1.0 - a.G.w_ratio) : 0.0, dfhi = SP ? whi0 * (1.0 - a.G.w_ratio) : 0.0;
     double dsum = 0.0;
     const int nn = a.nnbr[f];
     // the flyer's list (partners that are now fast are taken from the fast list)
@@ -996,7 +1010,19 @@ __device__ void flyer_work(const KArgs &a, const Box &B, Ctl *c, const CoefLds &
         const uint4 qf = a.fx[b][f];
         const int tf = (int)qf.w & kTypeMask;
         const float wl2 = (float)(wlo * wlo), wh2 = (float)(whi * whi);
-        const float glo = (float)exp(-a.G.kappa * wlo), ghi = (float)exp(-a.G.kappa * whi);
+        const float glo = (float)exp(-a.G.kappa * slo), ghi = (float)exp(-a.G.kappa * shi);
+        if (SP && wave == 0 && lane == 0) {   // the flyer-flyer pair, unscreened
+            const uint4 qo = a.fx[b][other];
+            const float dx = (float)(int)(qf.x - qo.x) * B.fx_scale[0];
+            const float dy = (float)(int)(qf.y - qo.y) * B.fx_scale[1];
+            const float dz = (float)(int)(qf.z - qo.z) * B.fx_scale[2];
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            const PairCoef &cc = cf.c[tf * kMaxTypes + ((int)qo.w & kTypeMask)];
+            const float sl = r2 + (float)(dflo * dflo), sh = r2 + (float)(dfhi * dfhi);
+            const float ulo = sl < a.G.rc_max2f ? pair_u_f32(a.G, cc, sl, 1.0f) : 0.0f;
+            const float uhi = sh < a.G.rc_max2f ? pair_u_f32(a.G, cc, sh, 1.0f) : 0.0f;
+            dsum += (double)uhi - (double)ulo;
+        }
         for (int q = lane; q < ntot; q += kWave) {
             const int j = q < nn ? a.nbr[nbr_slot(a, f, q)] : flist[q - nn];
             if (j == other) continue;
@@ -1015,7 +1041,19 @@ __device__ void flyer_work(const KArgs &a, const Box &B, Ctl *c, const CoefLds &
         const double4 *P = a.pos[b];
         const double4 pf = P[f];
         const int tf = meta_of(pf) & kTypeMask;
-        const double glo = exp(-a.G.kappa * wlo), ghi = exp(-a.G.kappa * whi);
+        const double glo = exp(-a.G.kappa * slo), ghi = exp(-a.G.kappa * shi);
+        if (SP && wave == 0 && lane == 0) {   // the flyer-flyer pair, unscreened
+            const double4 po = P[other];
+            const double dx = min_image(pf.x - po.x, B.L[0]);
+            const double dy = min_image(pf.y - po.y, B.L[1]);
+            const double dz = min_image(pf.z - po.z, B.L[2]);
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            const PairCoef &cc = cf.c[tf * kMaxTypes + (meta_of(po) & kTypeMask)];
+            double ulj, uc, fs, ulo = 0.0, uhi = 0.0;
+            if (r2 + dflo * dflo < a.G.rc_max2) { pair_u_f64(a.G, cc, r2 + dflo * dflo, 1.0, ulj, uc, fs); ulo = ulj + uc; }
+            if (r2 + dfhi * dfhi < a.G.rc_max2) { pair_u_f64(a.G, cc, r2 + dfhi * dfhi, 1.0, ulj, uc, fs); uhi = ulj + uc; }
+            dsum += uhi - ulo;
+        }
         for (int q = lane; q < ntot; q += kWave) {
             const int j = q < nn ? a.nbr[nbr_slot(a, f, q)] : flist[q - nn];
             if (j == other) continue;
@@ -1044,7 +1082,7 @@ __device__ void flyer_work(const KArgs &a, const Box &B, Ctl *c, const CoefLds &
 // Blocks [0, step_blocks) cover the atom slots; block step_blocks + b
 // evaluates the flying work of box b.
 // ==========================================================================
-template <int PREC, int L>
+template <int PREC, int L, bool SP>
 __global__ __launch_bounds__(kBlock) void k_step(KArgs a, int k, int b, int bin, int cl) {
     const bool flyer_block = (int)blockIdx.x >= a.step_blocks;
     const int slot0 = (int)blockIdx.x * (kBlock / L);
@@ -1075,7 +1113,7 @@ __global__ __launch_bounds__(kBlock) void k_step(KArgs a, int k, int b, int bin,
     const int *flist = sfast;
     if (flyer_block) {
         if (threadIdx.x == 0) c->nfast[(k + 2) % 3] = 0;
-        flyer_work<PREC>(a, B, c, cf, b, k, flist, nfast);
+        flyer_work<PREC, SP>(a, B, c, cf, b, k, flist, nfast);
         return;
     }
     const int lane = threadIdx.x % kWave;
@@ -1088,10 +1126,11 @@ __global__ __launch_bounds__(kBlock) void k_step(KArgs a, int k, int b, int bin,
     const bool fly = (mi & kFlyBit) != 0;
     const int ti = mi & kTypeMask;
     const double wv = altitude(a.G, move, k, nf);
-    const double gscr = exp(-a.G.kappa * wv);
+    // Eq. 11 screening at the flyers' mean altitude
+    const double gscr = exp(-a.G.kappa * (SP ? 0.5 * wv * (1.0 + a.G.w_ratio) : wv));
     double fx = 0.0, fy = 0.0, fz = 0.0;
-    if (act && !fly) group_force<PREC, L>(a, B, c, cf, b, cl, wc, s, pi, mi, wv, gscr, flist, nfast, fx, fy, fz);
-    if (PREC == 1) fast_atoms_wave(a, B, cf, b, cl, act && !fly && s == 0 && (mi & kFastBit), wc, lane, wv, gscr,
+    if (act && !fly) group_force<PREC, L, SP>(a, B, c, cf, b, cl, wc, s, pi, mi, wv, gscr, flist, nfast, fx, fy, fz);
+    if (PREC == 1) fast_atoms_wave<SP>(a, B, cf, b, cl, act && !fly && s == 0 && (mi & kFastBit), wc, lane, wv, gscr,
                                    fx, fy, fz);
     if (!act || s != 0) return;
     if (mi & kMolBit) {   // rigid water: integrated by k_settle
@@ -1129,7 +1168,7 @@ __global__ __launch_bounds__(kBlock) void k_step(KArgs a, int k, int b, int bin,
 
 // Test hook: forces of the working buffer-0 state with the flags it carries;
 // written at the canonical slots.
-template <int PREC, int L>
+template <int PREC, int L, bool SP>
 __global__ __launch_bounds__(kBlock) void k_forces(KArgs a, double wv) {
     const int slot0 = (int)blockIdx.x * (kBlock / L);
     const int bi = box_of_slot(a, slot0);
@@ -1146,10 +1185,11 @@ __global__ __launch_bounds__(kBlock) void k_forces(KArgs a, double wv) {
     const double4 pi = a.pos[0][wc];
     const int mi = meta_of(pi);
     double fx = 0.0, fy = 0.0, fz = 0.0;
+    const double gscr = exp(-a.G.kappa * (SP ? 0.5 * wv * (1.0 + a.G.w_ratio) : wv));
     if (act && !(mi & kFlyBit))
-        group_force<PREC, L>(a, B, c, cf, 0, 0, wc, s, pi, mi, wv, exp(-a.G.kappa * wv), a.fast, 0, fx, fy, fz);
-    if (PREC == 1) fast_atoms_wave(a, B, cf, 0, 0, act && !(mi & kFlyBit) && s == 0 && (mi & kFastBit), wc, lane, wv,
-                                   exp(-a.G.kappa * wv), fx, fy, fz);
+        group_force<PREC, L, SP>(a, B, c, cf, 0, 0, wc, s, pi, mi, wv, gscr, a.fast, 0, fx, fy, fz);
+    if (PREC == 1) fast_atoms_wave<SP>(a, B, cf, 0, 0, act && !(mi & kFlyBit) && s == 0 && (mi & kFastBit), wc, lane,
+                                       wv, gscr, fx, fy, fz);
     if (act && s == 0) a.force[a.perm[wc]] = make_double4(fx, fy, fz, 0.0);
 }
 
@@ -1184,9 +1224,12 @@ __global__ __launch_bounds__(kBlock) void k_energy(KArgs a, int which, int mode,
         const int mi = meta_of(pi);
         const bool fi = (mi & kFlyBit) != 0;
         const int ti = mi & kTypeMask;
-        const double gs = exp(-a.G.kappa * wv);
-        const double gmax = exp(-a.G.kappa * a.G.w_max);
-        const double wmax2 = a.G.w_max * a.G.w_max;
+        // species-specific w_max: each flyer at its own factor times the
+        // cation's altitude, screening at the flyers' mean altitude
+        const double ri = (ti == a.anion_type) ? a.G.w_ratio : 1.0;
+        const double gs = exp(-a.G.kappa * (0.5 * wv * (1.0 + a.G.w_ratio)));
+        const double gmax = exp(-a.G.kappa * (0.5 * a.G.w_max * (1.0 + a.G.w_ratio)));
+        const double wmax_i = a.G.w_max * ri;
         const int nn = a.nnbr[w];
         for (int q = s; q < nn; q += a.lanes) {
             const int j = a.nbr[nbr_slot(a, w, q)];
@@ -1201,18 +1244,20 @@ __global__ __launch_bounds__(kBlock) void k_energy(KArgs a, int which, int mode,
             double ulj, uc, fs;
             // switch energy U_fly(w_max), counted from the flyer's side:
             // flyer-nonflyer at the 4D distance, flyer-flyer half from each
+            const double rj = ((mj & kTypeMask) == a.anion_type) ? a.G.w_ratio : 1.0;
             if (fi && which < 2) {
-                if (!fj && r2 + wmax2 < a.G.rc_max2) {
-                    pair_u_f64(a.G, cc, r2 + wmax2, gmax, ulj, uc, fs);
+                const double dmax = wmax_i - a.G.w_max * rj;
+                if (!fj && r2 + wmax_i * wmax_i < a.G.rc_max2) {
+                    pair_u_f64(a.G, cc, r2 + wmax_i * wmax_i, gmax, ulj, uc, fs);
                     fly_s += ulj + uc;
-                } else if (fj && r2 < a.G.rc_max2) {
-                    pair_u_f64(a.G, cc, r2, 1.0, ulj, uc, fs);
+                } else if (fj && r2 + dmax * dmax < a.G.rc_max2) {
+                    pair_u_f64(a.G, cc, r2 + dmax * dmax, 1.0, ulj, uc, fs);
                     fly_s += 0.5 * (ulj + uc);
                 }
             }
             if (mode == 1 && (fi || fj)) continue;
-            const double wi = (mode == 0 && fi) ? wv : 0.0;
-            const double wj = (mode == 0 && fj) ? wv : 0.0;
+            const double wi = (mode == 0 && fi) ? wv * ri : 0.0;
+            const double wj = (mode == 0 && fj) ? wv * rj : 0.0;
             const double dw = wi - wj;
             const double s2 = r2 + dw * dw;
             if (s2 >= a.G.rc_max2) continue;

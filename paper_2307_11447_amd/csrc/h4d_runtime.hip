@@ -145,6 +145,8 @@ int check_params(const h4d_params &p) {
     if (p.momenta != 0 && p.momenta != 1) return fail(H4D_EINVAL, "momenta must be 0 or 1");
     if (p.momenta && p.water) return fail(H4D_EINVAL, "carried momenta need an ion system (water = 0)");
     if (!(p.md_refresh >= 0.0 && p.md_refresh <= 1.0)) return fail(H4D_EINVAL, "md_refresh must lie in [0, 1]");
+    if (!(p.w_max_ratio >= 0.0 && std::isfinite(p.w_max_ratio)))
+        return fail(H4D_EINVAL, "w_max_ratio must be finite and >= 0 (0: the cation's w_max)");
     if (p.water && !(p.d_oh > 0.0 && p.d_hh > 0.0 && p.d_hh < 2.0 * p.d_oh))
         return fail(H4D_EINVAL, "rigid water needs 0 < d_hh < 2 d_oh");
     return H4D_OK;
@@ -190,6 +192,7 @@ void setup_geo(h4d_system *s) {
     G.schedule_n = p.schedule_n;
     G.momenta = p.momenta;
     G.md_refresh = p.md_refresh;
+    G.w_ratio = p.w_max_ratio > 0.0 ? p.w_max_ratio : 1.0;
     G.kappa = p.kappa_sr;
     G.lambda3 = p.lambda_s * p.lambda_s * p.lambda_s;
     G.beta = 1.0 / p.kT;
@@ -364,12 +367,19 @@ void launch_list(h4d_system *s, int k, int b, int cb, hipStream_t st) {
         hipLaunchKernelGGL(k_list_allpairs, dim3(a.step_blocks), dim3(kBlock), 0, st, a, k, b, cb);
 }
 
-template <int PREC, int L>
-void launch_step_l(h4d_system *s, hipStream_t st, hipEvent_t e0, hipEvent_t e1, int k, int b, int bin) {
+template <int PREC, int L, bool SP>
+void launch_step_sp(h4d_system *s, hipStream_t st, hipEvent_t e0, hipEvent_t e1, int k, int b, int bin) {
     KArgs &a = s->a;
     const dim3 grid(a.step_blocks + s->nbox);
-    if (e0) hipExtLaunchKernelGGL(k_step<PREC, L>, grid, dim3(kBlock), 0, st, e0, e1, 0, a, k, b, bin, s->cl);
-    else hipLaunchKernelGGL((k_step<PREC, L>), grid, dim3(kBlock), 0, st, a, k, b, bin, s->cl);
+    if (e0) hipExtLaunchKernelGGL(k_step<PREC, L, SP>, grid, dim3(kBlock), 0, st, e0, e1, 0, a, k, b, bin, s->cl);
+    else hipLaunchKernelGGL((k_step<PREC, L, SP>), grid, dim3(kBlock), 0, st, a, k, b, bin, s->cl);
+}
+
+// species-specific w_max takes the kernels that give each flyer its own altitude
+template <int PREC, int L>
+void launch_step_l(h4d_system *s, hipStream_t st, hipEvent_t e0, hipEvent_t e1, int k, int b, int bin) {
+    if (s->a.G.w_ratio != 1.0) launch_step_sp<PREC, L, true>(s, st, e0, e1, k, b, bin);
+    else launch_step_sp<PREC, L, false>(s, st, e0, e1, k, b, bin);
 }
 
 template <int PREC>
@@ -381,15 +391,21 @@ void launch_step(h4d_system *s, hipStream_t st, hipEvent_t e0, hipEvent_t e1, in
     }
 }
 
-template <int PREC>
-void launch_forces(h4d_system *s, double w) {
+template <int PREC, bool SP>
+void launch_forces_sp(h4d_system *s, double w) {
     KArgs &a = s->a;
     const dim3 grid(a.step_blocks);
     switch (a.lanes) {
-        case 4: hipLaunchKernelGGL((k_forces<PREC, 4>), grid, dim3(kBlock), 0, s->stream, a, w); break;
-        case 8: hipLaunchKernelGGL((k_forces<PREC, 8>), grid, dim3(kBlock), 0, s->stream, a, w); break;
-        default: hipLaunchKernelGGL((k_forces<PREC, 16>), grid, dim3(kBlock), 0, s->stream, a, w); break;
+        case 4: hipLaunchKernelGGL((k_forces<PREC, 4, SP>), grid, dim3(kBlock), 0, s->stream, a, w); break;
+        case 8: hipLaunchKernelGGL((k_forces<PREC, 8, SP>), grid, dim3(kBlock), 0, s->stream, a, w); break;
+        default: hipLaunchKernelGGL((k_forces<PREC, 16, SP>), grid, dim3(kBlock), 0, s->stream, a, w); break;
     }
+}
+
+template <int PREC>
+void launch_forces(h4d_system *s, double w) {
+    if (s->a.G.w_ratio != 1.0) launch_forces_sp<PREC, true>(s, w);
+    else launch_forces_sp<PREC, false>(s, w);
 }
 
 // Sort the canonical atoms into cell order (working buffer 0), draw the

@@ -43,6 +43,7 @@ class Params(C.Structure):
         ("bias_xb", C.c_double), ("bias_alpha", C.c_double),
         ("schedule_n", C.c_double),
         ("momenta", C.c_int32), ("md_refresh", C.c_double),
+        ("w_max_ratio", C.c_double),
     ]
 
 
@@ -183,6 +184,7 @@ def make_params(d: dict) -> Params:
     p.bias_xb, p.bias_alpha = d.get("bias_xb", 0.0), d.get("bias_alpha", 0.0)
     p.schedule, p.schedule_n = d.get("schedule", 0), d.get("schedule_n", 1.0)
     p.momenta, p.md_refresh = d.get("momenta", 0), d.get("md_refresh", 0.0)
+    p.w_max_ratio = d.get("w_max_ratio", 0.0)
     for name in ("mass", "charge", "sigma", "eps"):
         arr = getattr(p, name)
         for i, v in enumerate(d[name]):
