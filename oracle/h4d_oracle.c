@@ -484,6 +484,7 @@ double or_altitude(const or_params *p, int move, int k, int nf)
      * w_max (1 - x^n) and w_max (1 - x)^n.  A deletion runs the insertion's
      * schedule backwards in time (x = (nf - k) / nf), the reverse path that
      * detailed balance pairs with it. */
+    if (nf <= 0) return 0.0;   /* an instantaneous exchange switches at once */
     const int j = move > 0 ? k : nf - k;
     if (p->schedule == 1) return p->w_max * (1.0 - pow((double)j / (double)nf, p->schedule_n));
     if (p->schedule == 2) return p->w_max * pow(1.0 - (double)j / (double)nf, p->schedule_n);
@@ -897,6 +898,22 @@ static int trial_begin(const or_params *p, or_state *s, uint64_t trial, int forc
     rec->tag_c = s->tag[ic];
     rec->tag_a = s->tag[ia];
     *ic_out = ic; *ia_out = ia;
+    if (p->v_ex_edge > 0.0) {
+        /* early rejection (supplement): a pair whose anion lies in the cube
+         * V_ex centred on the cation is exchanged instantly, a conventional
+         * MC move with no trajectory, for insertions and deletions alike (the
+         * move type is a function of the pair, so each move and its reverse
+         * take the same type) */
+        int inside = 1;
+        for (int d = 0; d < 3; ++d)
+            inside &= fabs(minimg(s->x[3 * ia + d] - s->x[3 * ic + d], p->box[d])) < 0.5 * p->v_ex_edge;
+        if (inside) {
+            nf = 0;
+            *nf_out = 0;
+            rec->n_steps = 0;
+            rec->flags |= OR_FLAG_INSTANT;
+        }
+    }
 
     if (p->momenta) {
         /* carried momenta: the state's own, reversed with probability 1/2

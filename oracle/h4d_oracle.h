@@ -47,6 +47,10 @@ typedef struct {
     double w_max_ratio;     /* species-specific w_max (supplement): the anion     */
                             /* flies at w_max_ratio times the cation's altitude;  */
                             /* 0 or 1: both at the same altitude                  */
+    double v_ex_edge;       /* early rejection (supplement): edge of the cube V_ex */
+                            /* around the flying cation; a pair whose anion lies  */
+                            /* inside is exchanged instantly (no trajectory);     */
+                            /* 0: off                                             */
 } or_params;
 
 /* Configuration.  Arrays are owned by the caller and sized to cap. */
@@ -70,6 +74,7 @@ typedef struct {
 
 #define OR_FLAG_EMPTY     1u   /* deletion attempted with no salt pair present */
 #define OR_FLAG_NONFINITE 2u   /* dH not finite: rejected                       */
+#define OR_FLAG_INSTANT  16u   /* pair inside V_ex: instantaneous exchange      */
 
 /* Energy modes. */
 #define OR_MODE_NEMD   0   /* flyers at altitude w, 4D distance, screened Coulomb */

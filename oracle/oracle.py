@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 MAXT = 8
 
 MODE_NEMD, MODE_EXCL, MODE_FLY = 0, 1, 2
-FLAG_EMPTY, FLAG_NONFINITE = 1, 2
+FLAG_EMPTY, FLAG_NONFINITE, FLAG_INSTANT = 1, 2, 16
 
 
 class Params(C.Structure):
@@ -36,7 +36,7 @@ class Params(C.Structure):
         ("bias_xb", C.c_double), ("bias_alpha", C.c_double),
         ("schedule", C.c_int32), ("schedule_n", C.c_double),
         ("momenta", C.c_int32), ("md_refresh", C.c_double),
-        ("w_max_ratio", C.c_double),
+        ("w_max_ratio", C.c_double), ("v_ex_edge", C.c_double),
     ]
 
 
@@ -145,6 +145,7 @@ def make_params(d: dict, use_cells: bool = True) -> Params:
     p.schedule, p.schedule_n = d.get("schedule", 0), d.get("schedule_n", 1.0)
     p.momenta, p.md_refresh = d.get("momenta", 0), d.get("md_refresh", 0.0)
     p.w_max_ratio = d.get("w_max_ratio", 0.0)
+    p.v_ex_edge = d.get("v_ex_edge", 0.0)
     return p
 
 
