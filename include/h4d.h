@@ -71,6 +71,7 @@ extern "C" {
                                     trajectory): rejected, state rolled back      */
 #define H4D_FLAG_RETRIED   0x4u  /* the trial was recomputed after a list resize   */
 #define H4D_FLAG_IDLE      0x8u  /* internal: a box of a batch with no trial left */
+#define H4D_FLAG_INSTANT   0x10u /* the pair lay in V_ex: exchanged instantly     */
 
 /*
  * Model and protocol.  Types index the per-type tables; pair parameters
@@ -139,6 +140,15 @@ typedef struct h4d_params {
                                    Eq. 11 screening takes the flyers' mean
                                    altitude (Sec. II B 2).  0 or 1: one
                                    altitude for both                           */
+    double v_ex_edge;           /* early rejection (the supplement's
+                                   instantaneous exchange): edge of the cube
+                                   V_ex centred on the flying cation.  A pair
+                                   whose anion lies inside, on insertion or
+                                   deletion alike, is exchanged with no
+                                   trajectory (n_steps = 0, H4D_FLAG_INSTANT):
+                                   the Metropolis test of Eqs. 6 and 8 on the
+                                   potential-energy change alone.  0: off; not
+                                   with the learned proposal                    */
 } h4d_params;
 
 /* One trial (move +1 insertion, -1 deletion). */

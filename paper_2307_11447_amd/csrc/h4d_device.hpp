@@ -94,6 +94,9 @@ struct Geo {
     // species-specific w_max: the anion flies at w_ratio times the cation's
     // altitude (1: both at the same altitude)
     double w_ratio;
+    // early rejection: half the edge of the cube V_ex around the flying
+    // cation (0: off)
+    double v_ex_half;
 };
 
 // --------------------------------------------------------------------------
@@ -131,6 +134,7 @@ struct PairCoef {
 // (the two variable-velocity schedules of the supplement; n = 1 gives
 // Eq. 2 again).
 __device__ __forceinline__ double altitude(const Geo &G, int move, int k, int nf) {
+    if (nf <= 0) return 0.0;   // an instantaneous exchange switches at once
     const int j = move > 0 ? k : nf - k;
     if (G.schedule == 0) return G.w_max * (double)(nf - j) / (double)nf;
     const double x = (double)j / (double)nf;

@@ -53,6 +53,7 @@ struct Ctl {
     double Wf[2];
     double Ufly0, Ufly1;   // U_fly(w_max) at the start / end state (FP64)
     double lnq;            // ln of the learned proposal's multiple-try factor (0: uniform)
+    int instant;           // 1: the pair lies in V_ex, exchanged with no trajectory (nf = 0)
     long long md;          // equilibrium phases run (the phase's generator counter)
     long long md_end;      // the box idles in a phase round once md reaches this
 };
@@ -66,7 +67,7 @@ struct TrialRec {
     double dH, dU, dK, W_prot, E_switch, dM, ln_ratio, ln_u, ln_proposal, H0, H1;
 };
 
-constexpr unsigned kFlagEmpty = 1u, kFlagNonfinite = 2u, kFlagIdle = 8u;
+constexpr unsigned kFlagEmpty = 1u, kFlagNonfinite = 2u, kFlagIdle = 8u, kFlagInstant = 16u;
 
 struct KArgs {
     Geo G;
@@ -246,6 +247,14 @@ __device__ __forceinline__ double4 refreshed_velocity(const KArgs &a, const Box 
     return make_double4(cr * v.x + sr * xi.x, cr * v.y + sr * xi.y, cr * v.z + sr * xi.z, 0.0);
 }
 
+// Early rejection: does the anion lie inside the cube V_ex centred on the
+// flying cation?  Such a pair is exchanged instantly (a conventional MC move
+// with no trajectory), on insertion and deletion alike.
+__device__ __forceinline__ bool in_ex_cube(const KArgs &a, const Box &B, const double4 &pc, const double4 &pa) {
+    return fabs(min_image(pa.x - pc.x, B.L[0])) < a.G.v_ex_half && fabs(min_image(pa.y - pc.y, B.L[1])) < a.G.v_ex_half &&
+           fabs(min_image(pa.z - pc.z, B.L[2])) < a.G.v_ex_half;
+}
+
 __global__ __launch_bounds__(kBlock) void k_propose(KArgs a, int force_move) {
     const int bi = blockIdx.x;
     const Box &B = a.box[bi];
@@ -280,6 +289,7 @@ __global__ __launch_bounds__(kBlock) void k_propose(KArgs a, int force_move) {
         c->Wf[0] = c->Wf[1] = 0.0; c->Ufly0 = c->Ufly1 = 0.0;
         c->U0 = c->K0 = c->U1 = c->K1 = 0.0;
         c->lnq = 0.0;
+        c->instant = 0;
         c->ic = c->ia = c->wic = c->wia = -1;
         c->nfast[0] = c->nfast[1] = c->nfast[2] = 0;
         c->max_fast = 0;
@@ -313,6 +323,7 @@ __global__ __launch_bounds__(kBlock) void k_propose(KArgs a, int force_move) {
                 a.ctype[ic] = tcat; a.ctype[ia] = tan;
                 a.cmol[ic] = -1; a.cmol[ia] = -1;
                 c->ic = ic; c->ia = ia; c->n_all = n + 2;
+                if (a.G.v_ex_half > 0.0 && in_ex_cube(a, B, a.cpos[ic], a.cpos[ia])) { c->nf = 0; c->instant = 1; }
             }
         }
     }
@@ -394,6 +405,7 @@ __global__ __launch_bounds__(kBlock) void k_propose(KArgs a, int force_move) {
             return;
         }
         c->ic = ic; c->ia = ia;
+        if (a.G.v_ex_half > 0.0 && in_ex_cube(a, B, a.cpos[ic], a.cpos[ia])) { c->nf = 0; c->instant = 1; }
         double4 p = a.cpos[ic];
         a.cpos[ic] = with_meta(p.x, p.y, p.z, meta_of(p) | kFlyBit);
         p = a.cpos[ia];
@@ -1364,6 +1376,7 @@ __global__ void k_metropolis(KArgs a) {
         return;
     }
     r->move = move;
+    if (c->instant) r->flags |= kFlagInstant;
     r->tag_c = a.ctag[c->ic];
     r->tag_a = a.ctag[c->ia];
     const double H0 = c->U0 + c->K0, H1 = c->U1 + c->K1;

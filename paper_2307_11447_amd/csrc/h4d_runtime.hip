@@ -25,6 +25,7 @@ using namespace h4d;
 
 static_assert(sizeof(TrialRec) == sizeof(h4d_trial), "record layout");
 static_assert(kMoveMD == H4D_MOVE_MD, "move code of an equilibrium phase");
+static_assert(kFlagInstant == H4D_FLAG_INSTANT && kFlagIdle == H4D_FLAG_IDLE, "record flags");
 
 namespace {
 
@@ -147,6 +148,7 @@ int check_params(const h4d_params &p) {
     if (!(p.md_refresh >= 0.0 && p.md_refresh <= 1.0)) return fail(H4D_EINVAL, "md_refresh must lie in [0, 1]");
     if (!(p.w_max_ratio >= 0.0 && std::isfinite(p.w_max_ratio)))
         return fail(H4D_EINVAL, "w_max_ratio must be finite and >= 0 (0: the cation's w_max)");
+    if (!(p.v_ex_edge >= 0.0 && std::isfinite(p.v_ex_edge))) return fail(H4D_EINVAL, "v_ex_edge must be finite and >= 0");
     if (p.water && !(p.d_oh > 0.0 && p.d_hh > 0.0 && p.d_hh < 2.0 * p.d_oh))
         return fail(H4D_EINVAL, "rigid water needs 0 < d_hh < 2 d_oh");
     return H4D_OK;
@@ -193,6 +195,7 @@ void setup_geo(h4d_system *s) {
     G.momenta = p.momenta;
     G.md_refresh = p.md_refresh;
     G.w_ratio = p.w_max_ratio > 0.0 ? p.w_max_ratio : 1.0;
+    G.v_ex_half = 0.5 * p.v_ex_edge;
     G.kappa = p.kappa_sr;
     G.lambda3 = p.lambda_s * p.lambda_s * p.lambda_s;
     G.beta = 1.0 / p.kT;
@@ -1741,6 +1744,8 @@ int32_t h4d_set_proposal(h4d_system *s, const h4d_mlp *net, int32_t k, double lo
     if (k > 0 && s->nbox != 1) return fail(H4D_EINVAL, "the learned proposal serves single-box systems");
     if (k > 0 && s->a.G.bias_alpha > 0.0)
         return fail(H4D_EINVAL, "the bimodal bias and the learned proposal are exclusive");
+    if (k > 0 && s->a.G.v_ex_half > 0.0)
+        return fail(H4D_EINVAL, "early rejection and the learned proposal are exclusive");
     s->drop_graphs();
     LearnArgs &l = s->la;
     for (void *q : {(void *)l.sites, (void *)l.feat, (void *)l.logit}) if (q) s->release(q);

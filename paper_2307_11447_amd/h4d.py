@@ -17,7 +17,7 @@ MAX_TYPES = 8
 H4D_OK, H4D_EINVAL, H4D_ENOMEM, H4D_EHIP, H4D_ECAPACITY, H4D_ENONFINITE, H4D_ENODEV = 0, -1, -2, -3, -4, -5, -6
 MOVE_AUTO, MOVE_INSERT, MOVE_DELETE, MOVE_MD = 0, 1, -1, 2
 PREC_FP64, PREC_FP32 = 0, 1
-FLAG_EMPTY, FLAG_NONFINITE, FLAG_RETRIED, FLAG_IDLE = 0x1, 0x2, 0x4, 0x8
+FLAG_EMPTY, FLAG_NONFINITE, FLAG_RETRIED, FLAG_IDLE, FLAG_INSTANT = 0x1, 0x2, 0x4, 0x8, 0x10
 
 
 class H4DError(RuntimeError):
@@ -43,7 +43,7 @@ class Params(C.Structure):
         ("bias_xb", C.c_double), ("bias_alpha", C.c_double),
         ("schedule_n", C.c_double),
         ("momenta", C.c_int32), ("md_refresh", C.c_double),
-        ("w_max_ratio", C.c_double),
+        ("w_max_ratio", C.c_double), ("v_ex_edge", C.c_double),
     ]
 
 
@@ -185,6 +185,7 @@ def make_params(d: dict) -> Params:
     p.schedule, p.schedule_n = d.get("schedule", 0), d.get("schedule_n", 1.0)
     p.momenta, p.md_refresh = d.get("momenta", 0), d.get("md_refresh", 0.0)
     p.w_max_ratio = d.get("w_max_ratio", 0.0)
+    p.v_ex_edge = d.get("v_ex_edge", 0.0)
     for name in ("mass", "charge", "sigma", "eps"):
         arr = getattr(p, name)
         for i, v in enumerate(d[name]):
