@@ -238,19 +238,25 @@ def proposal_ab(sys_, torch, h4d, arms, beta_mu, n_each, block=50):
     (deletions), which are never accepted, so the state does not change;
     each record's ln R is moved to the operating beta mu and the mean of
     min(1, R) taken.  The arms alternate in blocks so that they share the
-    same state and device conditions.  arms: name -> (net, k, scale)."""
-    out = {name: {"ins": [], "del": [], "dM_ins": [], "dM_del": [], "s": 0.0, "n": 0} for name in arms}
+    same state and device conditions.  arms: name -> (net, k, scale, bias
+    (x_b, alpha_b) or None[, V_ex edge for early rejection])."""
+    out = {name: {"ins": [], "del": [], "dM_ins": [], "dM_del": [], "s": 0.0, "n": 0, "instant": 0} for name in arms}
     done = 0
     while done < n_each:
         nb = min(block, n_each - done)
-        for name, (net, k, scale, bias) in arms.items():
+        for name, arm in arms.items():
+            net, k, scale, bias = arm[:4]
+            v_ex = arm[4] if len(arm) > 4 else 0.0
             sys_.set_bias(0.0, 0.0)
+            sys_.set_early_rejection(0.0)
             if k > 0:
                 sys_.set_proposal(net, k, 10.0, scale)
             else:
                 sys_.set_proposal(None, 0)
             if bias is not None:
                 sys_.set_bias(*bias)
+            if v_ex > 0.0:
+                sys_.set_early_rejection(v_ex)
             for move, bm, key in ((h4d.MOVE_INSERT, -1.0e3, "ins"), (h4d.MOVE_DELETE, 1.0e3, "del")):
                 sys_.set_beta_mu(bm)
                 torch.cuda.synchronize()
@@ -265,9 +271,11 @@ def proposal_ab(sys_, torch, h4d, arms, beta_mu, n_each, block=50):
                     ok = not (r.flags & 0x3) and math.isfinite(r.ln_ratio)
                     out[name][key].append(math.exp(min(0.0, r.ln_ratio + shift)) if ok else 0.0)
                     out[name]["dM_" + key].append(r.dM if ok else math.nan)
+                    out[name]["instant"] += 1 if r.flags & 0x10 else 0
         done += nb
     sys_.set_proposal(None, 0)
     sys_.set_bias(0.0, 0.0)
+    sys_.set_early_rejection(0.0)
     sys_.set_beta_mu(beta_mu)
     res = {}
     for name, o in out.items():
@@ -276,11 +284,15 @@ def proposal_ab(sys_, torch, h4d, arms, beta_mu, n_each, block=50):
         rate = o["n"] / max(1e-300, o["s"])
         res[name] = {"p_insert": p_ins, "p_delete": p_del, "trials_per_s": rate, "dM": (o["dM_ins"], o["dM_del"]),
                      "expected_exchanges_per_s": 0.5 * (p_ins + p_del) * rate,
-                     "insertions": len(o["ins"]), "deletions": len(o["del"])}
+                     "insertions": len(o["ins"]), "deletions": len(o["del"]),
+                     "instant_share": o["instant"] / max(1, len(o["ins"]) + len(o["del"]))}
     if "uniform" in out and "learned" in out:
         res["gain"], res["gain_bootstrap90"] = ab_gain(out["uniform"], out["learned"])
     if "uniform" in out and "bimodal" in out:
         res["bimodal_gain"], res["bimodal_gain_bootstrap90"] = ab_gain(out["uniform"], out["bimodal"])
+    if "bimodal" in out and "bimodal_early" in out:
+        res["early_gain_over_bimodal"], res["early_gain_over_bimodal_bootstrap90"] = ab_gain(out["bimodal"],
+                                                                                             out["bimodal_early"])
     return res
 
 
@@ -323,6 +335,9 @@ def timed_trials(sys_, torch, n):
 # aqueous NaCl choice (4 A, 0.1 / A^2), and a contact-distance bias for the
 # LJ ions (sigma = 1)
 BIAS = {"lj32k": (1.0, 2.0), "water": (4.0, 0.1)}
+# early rejection: edge of V_ex around the flying cation (LJ units; the water
+# box leaves it out to keep its run short)
+EARLY = {"lj32k": 1.2}
 
 SINGLE = {
     "lj32k": ("config_lj_32k",
@@ -499,6 +514,8 @@ def bench_single(args, h4d, W, torch):
     if scale_sel > 0.0:
         arms["learned"] = (net, k_sel, scale_sel, None)
     arms["bimodal"] = (None, 0, 0.0, BIAS[args.workload])
+    if args.workload in EARLY:   # the bias with early rejection of pairs in contact
+        arms["bimodal_early"] = (None, 0, 0.0, BIAS[args.workload], EARLY[args.workload])
     ab = proposal_ab(sys_, torch, h4d, arms, beta_mu, args.ab_trials) if args.ab_trials > 0 else None
     works = None
     if ab is not None:
@@ -572,6 +589,15 @@ def bench_single(args, h4d, W, torch):
         "fixed_state_gain": ab.get("bimodal_gain") if ab is not None else None,
         "fixed_state_gain_bootstrap90": ab.get("bimodal_gain_bootstrap90") if ab is not None else None,
     }
+    if ab is not None and "bimodal_early" in ab:
+        out["early_rejection"] = {
+            "v_ex_edge": EARLY[args.workload],
+            "note": "the bias with early rejection (pairs whose anion lies in the cube V_ex around the cation are "
+                    "exchanged instantly, no trajectory), in the fixed-state comparison",
+            "instant_share": ab["bimodal_early"]["instant_share"],
+            "gain_over_bias_alone": ab.get("early_gain_over_bimodal"),
+            "gain_over_bias_alone_bootstrap90": ab.get("early_gain_over_bimodal_bootstrap90"),
+        }
     # the chemical potential and the predicted acceptance from the uniform
     # arm's work distributions (Crooks' theorem solved by BAR, Eq. 21)
     if works is not None:

@@ -329,6 +329,14 @@ int32_t h4d_set_trial_index(h4d_system *sys, uint64_t trial);
 int32_t h4d_set_bias(h4d_system *sys, double x_b, double alpha_b);
 
 /*
+ * Early rejection (the supplement's instantaneous exchange of a pair in
+ * contact) from the next trial on: v_ex_edge is the edge of the cube V_ex
+ * centred on the flying cation, as h4d_params.v_ex_edge (0: off).  H4D_EINVAL
+ * for a negative or non-finite edge, or with the learned proposal set.
+ */
+int32_t h4d_set_early_rejection(h4d_system *sys, double v_ex_edge);
+
+/*
  * Test hook (single-box handles): forces and FP64 energy of the current state with atoms
  * flying[0], flying[1] (-1: none) lifted to altitude w, as in the NEMD pass
  * (an anion among them to w_max_ratio * w when that is set).

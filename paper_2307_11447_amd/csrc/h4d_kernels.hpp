@@ -666,14 +666,15 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int 
         }
         __syncthreads();
         const int total = off[9];
-        for (int t = 0; t < 9; ++t) {
-            const int m = cnt27[9 * layer + t];
-            const int *src = a.cell_atoms[cb] + (size_t)cidx[9 * layer + t] * cap;
-            for (int u = threadIdx.x; u < m; u += blockDim.x) {
-                const int j = src[u];
-                const uint4 q = a.fx[b][j];
-                cand[off[t] + u] = make_uint4(q.x, q.y, q.z, (unsigned)j);
-            }
+        // one candidate per thread across the layer's 9 cells, so that all
+        // of the layer's gathers are in flight at once
+        for (int e = threadIdx.x; e < total; e += blockDim.x) {
+            int t = 0;
+#pragma unroll
+            for (int q = 1; q < 9; ++q) t += (e >= off[q]);
+            const int j = a.cell_atoms[cb][(size_t)cidx[9 * layer + t] * cap + (e - off[t])];
+            const uint4 q = a.fx[b][j];
+            cand[e] = make_uint4(q.x, q.y, q.z, (unsigned)j);
         }
         // pad to whole wavefronts with entries that never match (slot -1)
         if (threadIdx.x < kWave) cand[off[9] + threadIdx.x] = make_uint4(0u, 0u, 0u, 0xffffffffu);

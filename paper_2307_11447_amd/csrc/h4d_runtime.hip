@@ -1238,6 +1238,17 @@ int32_t h4d_set_bias(h4d_system *s, double x_b, double alpha_b) {
     return H4D_OK;
 }
 
+int32_t h4d_set_early_rejection(h4d_system *s, double v_ex_edge) {
+    if (!s) return fail(H4D_EINVAL, "null handle");
+    if (!(v_ex_edge >= 0.0 && std::isfinite(v_ex_edge))) return fail(H4D_EINVAL, "v_ex_edge must be finite and >= 0");
+    if (v_ex_edge > 0.0 && s->la.k > 0)
+        return fail(H4D_EINVAL, "early rejection and the learned proposal are exclusive");
+    s->p.v_ex_edge = v_ex_edge;
+    s->a.G.v_ex_half = 0.5 * v_ex_edge;
+    s->drop_graphs();       // the captured launches hold the old parameters
+    return H4D_OK;
+}
+
 int32_t h4d_set_trial_index(h4d_system *s, uint64_t trial) {
     if (!s) return fail(H4D_EINVAL, "null handle");
     int rc = read_ctl(s);

@@ -151,6 +151,7 @@ def lib() -> C.CDLL:
         L.h4d_set_beta_mu.argtypes = [vp, C.c_double]
         L.h4d_set_bias.argtypes = [vp, C.c_double, C.c_double]
         L.h4d_run_md.argtypes = [vp, C.c_int32, C.POINTER(Trial)]
+        L.h4d_set_early_rejection.argtypes = [vp, C.c_double]
         for name in ("h4d_stream_copy", "h4d_set_timing", "h4d_get_timing", "h4d_init_system", "h4d_build_neighbors",
                      "h4d_run_nemd_trial", "h4d_run_trials", "h4d_sample_observables", "h4d_get_state",
                      "h4d_set_trial_index", "h4d_forces_at", "h4d_destroy", "h4d_init_batch", "h4d_num_boxes",
@@ -158,7 +159,7 @@ def lib() -> C.CDLL:
                      "h4d_mlp_create", "h4d_mlp_destroy", "h4d_mlp_set_weights", "h4d_mlp_get_weights",
                      "h4d_mlp_forward", "h4d_mlp_loss_grad", "h4d_mlp_train", "h4d_set_proposal",
                      "h4d_last_site_features", "h4d_last_candidates", "h4d_site_features", "h4d_set_beta_mu",
-                     "h4d_init_speculative", "h4d_run_speculative", "h4d_set_bias", "h4d_run_md"):
+                     "h4d_init_speculative", "h4d_run_speculative", "h4d_set_bias", "h4d_run_md", "h4d_set_early_rejection"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -322,6 +323,10 @@ class _Handle:
     def set_bias(self, x_b: float, alpha_b: float):
         """Bimodal bias of the flying pair's separation (alpha_b = 0: off)."""
         _check(lib().h4d_set_bias(self._h, x_b, alpha_b))
+
+    def set_early_rejection(self, v_ex_edge: float):
+        """Edge of the cube V_ex around the flying cation (0: off)."""
+        _check(lib().h4d_set_early_rejection(self._h, v_ex_edge))
 
     def set_beta_mu(self, beta_mu: float):
         _check(lib().h4d_set_beta_mu(self._h, beta_mu))

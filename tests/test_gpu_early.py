@@ -17,14 +17,18 @@ def say(msg):
     sys.stdout.flush()
 
 
-@pytest.mark.parametrize("speculative", [False, True])
-def test_early_rejection_trials_match_oracle(speculative):
-    say(f"case early rejection lj300 fp64, V_ex edge 7, 40 trials, speculative {speculative}")
+@pytest.mark.parametrize("mode", ["params", "setter", "speculative"])
+def test_early_rejection_trials_match_oracle(mode):
+    say(f"case early rejection lj300 fp64, V_ex edge 7, 40 trials, {mode}")
     w = W.lj_electrolyte(300, 0.1, 79, n_steps=20, precision="fp64")
     w.params.update(v_ex_edge=7.0, beta_mu=10.0)
-    if speculative:
+    if mode == "speculative":
         g = h4d.Speculative.from_workload(w, 4)
         recs = g.trials(40)
+    elif mode == "setter":
+        g = h4d.System.from_workload(w, v_ex_edge=0.0)
+        g.set_early_rejection(7.0)
+        recs = [g.trial() for _ in range(40)]
     else:
         g = h4d.System.from_workload(w)
         recs = [g.trial() for _ in range(40)]
