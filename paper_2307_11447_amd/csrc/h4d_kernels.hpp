@@ -607,24 +607,27 @@ __global__ __launch_bounds__(kBlock) void k_list_allpairs(KArgs a, int k, int b0
 // Cell form: `split` blocks of kListWaves wavefronts per centre cell (block
 // s of the cell takes the centre atoms t with (t / kListWaves) % split == s,
 // so that cells with many atoms still give the chip enough blocks).  The 27
-// stencil cells are staged in LDS one z-layer (9 cells) at a time
+// stencil cells are staged in LDS one z-layer (9 cells) at a time, or all at
+// once (FULL, when they fit: one staging round instead of three)
 // (fixed-point coordinates + working slot, in stencil order); each
 // wavefront takes its centre atoms in turn and tests 64 candidates per
 // ballot (a layer is padded to whole wavefronts with entries that never
 // match), appending partners in stencil order (a centre atom's running count
 // stays in LDS across the layers).  MOL: rigid molecules present (pairs
-// within a molecule are left out).  Dynamic LDS: (10 * cell_cap + 64) * 16 +
-// cell_cap * 4 bytes.  Also records the build positions, clears this cell's
+// within a molecule are left out).  Dynamic LDS: ((9 or 27) * cell_cap +
+// cell_cap + 64) * 16 + cell_cap * 4 bytes.  Also records the build positions, clears this cell's
 // count in the other buffer and the box's fast lists.
 constexpr int kListWaves = 8;
 
-template <bool MOL>
+template <bool MOL, bool FULL>
 __global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int k, int b0, int cb, int split) {
+    constexpr int CPL = FULL ? 27 : 9;          // cells staged per round
+    constexpr int NL = 27 / CPL;                // staging rounds
     extern __shared__ uint4 lds[];
-    __shared__ int cidx[27], cnt27[27], off[10];
+    __shared__ int cidx[27], cnt27[27], off[CPL + 1];
     const int cap = a.cell_cap;
-    uint4 *cand = lds;                           // 9 * cap + 64 staged candidates
-    uint4 *ctr = lds + 9 * (size_t)cap + kWave;  // cap centre atoms
+    uint4 *cand = lds;                             // CPL * cap + 64 staged candidates
+    uint4 *ctr = lds + CPL * (size_t)cap + kWave;  // cap centre atoms
     int *ccount = reinterpret_cast<int *>(ctr + cap);
     const int cc = (int)blockIdx.x / split, part = (int)blockIdx.x % split;
     const int bi = box_of_cell(a, cc);
@@ -658,26 +661,26 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int 
     const float sx = B.fx_scale[0], sy = B.fx_scale[1], sz = B.fx_scale[2];
     const unsigned long long below = (1ull << lane) - 1ull;
     const int ll = a.lanes_log2, lmask = (1 << ll) - 1;
-    for (int layer = 0; layer < 3; ++layer) {
+    for (int layer = 0; layer < NL; ++layer) {
         if (threadIdx.x == 0) {
             int run = 0;
-            for (int t = 0; t < 9; ++t) { off[t] = run; run += cnt27[9 * layer + t]; }
-            off[9] = run;
+            for (int t = 0; t < CPL; ++t) { off[t] = run; run += cnt27[CPL * layer + t]; }
+            off[CPL] = run;
         }
         __syncthreads();
-        const int total = off[9];
-        // one candidate per thread across the layer's 9 cells, so that all
-        // of the layer's gathers are in flight at once
+        const int total = off[CPL];
+        // one candidate per thread across the round's cells, so that all of
+        // its gathers are in flight at once
         for (int e = threadIdx.x; e < total; e += blockDim.x) {
             int t = 0;
 #pragma unroll
-            for (int q = 1; q < 9; ++q) t += (e >= off[q]);
-            const int j = a.cell_atoms[cb][(size_t)cidx[9 * layer + t] * cap + (e - off[t])];
+            for (int q = 1; q < CPL; ++q) t += (e >= off[q]);
+            const int j = a.cell_atoms[cb][(size_t)cidx[CPL * layer + t] * cap + (e - off[t])];
             const uint4 q = a.fx[b][j];
             cand[e] = make_uint4(q.x, q.y, q.z, (unsigned)j);
         }
         // pad to whole wavefronts with entries that never match (slot -1)
-        if (threadIdx.x < kWave) cand[off[9] + threadIdx.x] = make_uint4(0u, 0u, 0u, 0xffffffffu);
+        if (threadIdx.x < kWave) cand[off[CPL] + threadIdx.x] = make_uint4(0u, 0u, 0u, 0xffffffffu);
         __syncthreads();
         for (int t = part * kListWaves + wave; t < mc; t += split * kListWaves) {
             const uint4 qi = ctr[t];

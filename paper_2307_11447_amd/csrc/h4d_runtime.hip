@@ -338,9 +338,14 @@ void set_lanes(h4d_system *s, int L) {
 
 int slot_blocks(const h4d_system *s) { return s->a.slots / kBlock; }
 
-size_t list_cells_lds(const h4d_system *s) {
-    return (size_t)s->a.cell_cap * (10 * sizeof(uint4) + sizeof(int)) + kWave * sizeof(uint4);
+// LDS of the cell-form list build: cells staged per round (9 or 27) + the
+// centre cell, the padding and the centre atoms' running counts
+size_t list_cells_lds(const h4d_system *s, int cells_per_round = 9) {
+    return (size_t)s->a.cell_cap * ((cells_per_round + 1) * sizeof(uint4) + sizeof(int)) + kWave * sizeof(uint4);
 }
+
+// all 27 cells in one staging round while that keeps four blocks per CU
+bool list_full(const h4d_system *s) { return list_cells_lds(s, 27) <= 40 * 1024; }
 
 // blocks per centre cell of the cell-form list build: the autotuner's
 // choice, else enough blocks for two per CU (about 512 in all); at most 16
@@ -357,12 +362,16 @@ void launch_list(h4d_system *s, int k, int b, int cb, hipStream_t st) {
     KArgs &a = s->a;
     if (s->cells && list_cells_lds(s) <= 56 * 1024) {
         const int split = list_split(s);
-        if (a.G.water)
-            hipLaunchKernelGGL(k_list_cells<true>, dim3(a.ncell_total * split), dim3(kListWaves * kWave),
-                               list_cells_lds(s), st, a, k, b, cb, split);
-        else
-            hipLaunchKernelGGL(k_list_cells<false>, dim3(a.ncell_total * split), dim3(kListWaves * kWave),
-                               list_cells_lds(s), st, a, k, b, cb, split);
+        const dim3 grid(a.ncell_total * split), block(kListWaves * kWave);
+        if (list_full(s)) {
+            const size_t lds = list_cells_lds(s, 27);
+            if (a.G.water) hipLaunchKernelGGL((k_list_cells<true, true>), grid, block, lds, st, a, k, b, cb, split);
+            else hipLaunchKernelGGL((k_list_cells<false, true>), grid, block, lds, st, a, k, b, cb, split);
+        } else {
+            const size_t lds = list_cells_lds(s);
+            if (a.G.water) hipLaunchKernelGGL((k_list_cells<true, false>), grid, block, lds, st, a, k, b, cb, split);
+            else hipLaunchKernelGGL((k_list_cells<false, false>), grid, block, lds, st, a, k, b, cb, split);
+        }
     }
     else if (s->cells)
         hipLaunchKernelGGL(k_list_lanes, dim3(a.step_blocks), dim3(kBlock), 0, st, a, k, b, cb);
