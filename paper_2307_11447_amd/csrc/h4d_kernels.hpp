@@ -607,27 +607,27 @@ __global__ __launch_bounds__(kBlock) void k_list_allpairs(KArgs a, int k, int b0
 // Cell form: `split` blocks of kListWaves wavefronts per centre cell (block
 // s of the cell takes the centre atoms t with (t / kListWaves) % split == s,
 // so that cells with many atoms still give the chip enough blocks).  The 27
-// stencil cells are staged in LDS one z-layer (9 cells) at a time, or all at
-// once (FULL, when they fit: one staging round instead of three)
+// stencil cells are staged in LDS all at once when their atoms fit in the
+// cand_cap staging entries, else one z-layer (9 cells) at a time (the
+// choice is the block's own; cand_cap >= 9 cell_cap)
 // (fixed-point coordinates + working slot, in stencil order); each
 // wavefront takes its centre atoms in turn and tests 64 candidates per
 // ballot (a layer is padded to whole wavefronts with entries that never
 // match), appending partners in stencil order (a centre atom's running count
 // stays in LDS across the layers).  MOL: rigid molecules present (pairs
-// within a molecule are left out).  Dynamic LDS: ((9 or 27) * cell_cap +
-// cell_cap + 64) * 16 + cell_cap * 4 bytes.  Also records the build positions, clears this cell's
+// within a molecule are left out).  Dynamic LDS: (cand_cap + cell_cap + 64)
+// * 16 + cell_cap * 4 bytes.  Also records the build positions, clears this cell's
 // count in the other buffer and the box's fast lists.
 constexpr int kListWaves = 8;
 
-template <bool MOL, bool FULL>
-__global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int k, int b0, int cb, int split) {
-    constexpr int CPL = FULL ? 27 : 9;          // cells staged per round
-    constexpr int NL = 27 / CPL;                // staging rounds
+template <bool MOL>
+__global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int k, int b0, int cb, int split,
+                                                                    int cand_cap) {
     extern __shared__ uint4 lds[];
-    __shared__ int cidx[27], cnt27[27], off[CPL + 1];
+    __shared__ int cidx[27], cnt27[27], off[28];
     const int cap = a.cell_cap;
-    uint4 *cand = lds;                             // CPL * cap + 64 staged candidates
-    uint4 *ctr = lds + CPL * (size_t)cap + kWave;  // cap centre atoms
+    uint4 *cand = lds;                             // cand_cap + 64 staged candidates
+    uint4 *ctr = lds + (size_t)cand_cap + kWave;   // cap centre atoms
     int *ccount = reinterpret_cast<int *>(ctr + cap);
     const int cc = (int)blockIdx.x / split, part = (int)blockIdx.x % split;
     const int bi = box_of_cell(a, cc);
@@ -661,26 +661,33 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int 
     const float sx = B.fx_scale[0], sy = B.fx_scale[1], sz = B.fx_scale[2];
     const unsigned long long below = (1ull << lane) - 1ull;
     const int ll = a.lanes_log2, lmask = (1 << ll) - 1;
-    for (int layer = 0; layer < NL; ++layer) {
+    int total27 = 0;
+    for (int t = 0; t < 27; ++t) total27 += cnt27[t];
+    const int cpl = total27 <= cand_cap ? 27 : 9;   // cells staged per round (uniform over the block)
+    for (int layer = 0; layer < 27 / cpl; ++layer) {
         if (threadIdx.x == 0) {
             int run = 0;
-            for (int t = 0; t < CPL; ++t) { off[t] = run; run += cnt27[CPL * layer + t]; }
-            off[CPL] = run;
+            for (int t = 0; t < cpl; ++t) { off[t] = run; run += cnt27[cpl * layer + t]; }
+            off[cpl] = run;
         }
         __syncthreads();
-        const int total = off[CPL];
+        const int total = off[cpl];
         // one candidate per thread across the round's cells, so that all of
-        // its gathers are in flight at once
+        // its gathers are in flight at once; its cell is the last one whose
+        // offset does not exceed it (empty cells share their offset)
         for (int e = threadIdx.x; e < total; e += blockDim.x) {
-            int t = 0;
-#pragma unroll
-            for (int q = 1; q < CPL; ++q) t += (e >= off[q]);
-            const int j = a.cell_atoms[cb][(size_t)cidx[CPL * layer + t] * cap + (e - off[t])];
+            int lo = 0, hi = cpl - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (off[mid] <= e) lo = mid;
+                else hi = mid - 1;
+            }
+            const int j = a.cell_atoms[cb][(size_t)cidx[cpl * layer + lo] * cap + (e - off[lo])];
             const uint4 q = a.fx[b][j];
             cand[e] = make_uint4(q.x, q.y, q.z, (unsigned)j);
         }
         // pad to whole wavefronts with entries that never match (slot -1)
-        if (threadIdx.x < kWave) cand[off[CPL] + threadIdx.x] = make_uint4(0u, 0u, 0u, 0xffffffffu);
+        if (threadIdx.x < kWave) cand[off[cpl] + threadIdx.x] = make_uint4(0u, 0u, 0u, 0xffffffffu);
         __syncthreads();
         for (int t = part * kListWaves + wave; t < mc; t += split * kListWaves) {
             const uint4 qi = ctr[t];

@@ -338,14 +338,20 @@ void set_lanes(h4d_system *s, int L) {
 
 int slot_blocks(const h4d_system *s) { return s->a.slots / kBlock; }
 
-// LDS of the cell-form list build: cells staged per round (9 or 27) + the
-// centre cell, the padding and the centre atoms' running counts
-size_t list_cells_lds(const h4d_system *s, int cells_per_round = 9) {
-    return (size_t)s->a.cell_cap * ((cells_per_round + 1) * sizeof(uint4) + sizeof(int)) + kWave * sizeof(uint4);
+// Staging entries of the cell-form list build: as many as 40 KB of LDS
+// holds (four blocks per CU), enough for all 27 cells of typical occupancy
+// in one round, and never fewer than one z-layer of full cells.
+int list_cand_cap(const h4d_system *s) {
+    const int cap = s->a.cell_cap;
+    const int fixed = (int)(kWave * sizeof(uint4) + (size_t)cap * (sizeof(uint4) + sizeof(int)));
+    return std::max(9 * cap, (40 * 1024 - fixed) / (int)sizeof(uint4));
 }
 
-// all 27 cells in one staging round while that keeps four blocks per CU
-bool list_full(const h4d_system *s) { return list_cells_lds(s, 27) <= 40 * 1024; }
+// LDS of the cell-form list build: the staged candidates and their padding,
+// the centre atoms and their running counts
+size_t list_cells_lds(const h4d_system *s) {
+    return (size_t)(list_cand_cap(s) + kWave) * sizeof(uint4) + (size_t)s->a.cell_cap * (sizeof(uint4) + sizeof(int));
+}
 
 // blocks per centre cell of the cell-form list build: the autotuner's
 // choice, else enough blocks for two per CU (about 512 in all); at most 16
@@ -361,17 +367,11 @@ int list_split(const h4d_system *s) {
 void launch_list(h4d_system *s, int k, int b, int cb, hipStream_t st) {
     KArgs &a = s->a;
     if (s->cells && list_cells_lds(s) <= 56 * 1024) {
-        const int split = list_split(s);
+        const int split = list_split(s), cand_cap = list_cand_cap(s);
         const dim3 grid(a.ncell_total * split), block(kListWaves * kWave);
-        if (list_full(s)) {
-            const size_t lds = list_cells_lds(s, 27);
-            if (a.G.water) hipLaunchKernelGGL((k_list_cells<true, true>), grid, block, lds, st, a, k, b, cb, split);
-            else hipLaunchKernelGGL((k_list_cells<false, true>), grid, block, lds, st, a, k, b, cb, split);
-        } else {
-            const size_t lds = list_cells_lds(s);
-            if (a.G.water) hipLaunchKernelGGL((k_list_cells<true, false>), grid, block, lds, st, a, k, b, cb, split);
-            else hipLaunchKernelGGL((k_list_cells<false, false>), grid, block, lds, st, a, k, b, cb, split);
-        }
+        const size_t lds = list_cells_lds(s);
+        if (a.G.water) hipLaunchKernelGGL(k_list_cells<true>, grid, block, lds, st, a, k, b, cb, split, cand_cap);
+        else hipLaunchKernelGGL(k_list_cells<false>, grid, block, lds, st, a, k, b, cb, split, cand_cap);
     }
     else if (s->cells)
         hipLaunchKernelGGL(k_list_lanes, dim3(a.step_blocks), dim3(kBlock), 0, st, a, k, b, cb);
