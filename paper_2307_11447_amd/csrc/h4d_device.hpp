@@ -184,11 +184,11 @@ __device__ __forceinline__ float erfc_as(float x, float ex) {
 // hardware reciprocal, reciprocal square root and exp2.  g screens the
 // Coulomb part.  s2 must be positive.
 __device__ __forceinline__ float pair_fs_f32(const Geo &G, const PairCoef &c, float s2, float g) {
-    const float inv = __builtin_amdgcn_rcpf(s2);
+    const float rs = __builtin_amdgcn_rsqf(s2);
+    const float inv = rs * rs;                   // 1 / s^2 without a second transcendental
     const float sr2 = c.sig2f * inv;
     const float sr6 = sr2 * sr2 * sr2;
     const float flj = c.eps24f * sr6 * (2.0f * sr6 - 1.0f) * inv;
-    const float rs = __builtin_amdgcn_rsqf(s2);
     const float s = s2 * rs;
     const float ex = __builtin_amdgcn_exp2f(G.nalpha2_log2e * s2);
     const float t = __builtin_amdgcn_rcpf(1.0f + G.p_alpha * s);
