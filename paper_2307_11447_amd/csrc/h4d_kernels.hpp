@@ -693,6 +693,13 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int 
             const uint4 qi = ctr[t];
             const int wi = (int)qi.w;
             const int mi = MOL ? a.wmol[wi] : -1;
+            // the working slots of this atom's molecule (its partners in it
+            // are left out), held in registers for the candidate loop
+            int sib0 = -1, sib1 = -1, sib2 = -1;
+            if (MOL && mi >= 0) {
+                const int c0 = B.a0 + 3 * mi;
+                sib0 = a.molw[c0]; sib1 = a.molw[c0 + 1]; sib2 = a.molw[c0 + 2];
+            }
             int cnt = ccount[t];
             int *dst = a.nbr + nbr_slot(a, wi, 0);
 #pragma unroll 2
@@ -703,7 +710,7 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int 
                 const float dy = (float)(int)(qi.y - qj.y) * sy;
                 const float dz = (float)(int)(qi.z - qj.z) * sz;
                 bool acc = dx * dx + dy * dy + dz * dz < rl2 && j != wi && j >= 0;
-                if (MOL && acc && mi >= 0 && a.wmol[j] == mi) acc = false;   // ions carry no molecule (-1)
+                if (MOL && (j == sib0 || j == sib1 || j == sib2)) acc = false;   // ions carry no molecule (-1)
                 const unsigned long long msk = __ballot(acc);
                 const int q = cnt + __popcll(msk & below);
                 if (acc && q < a.nbr_cap) dst[((q >> ll) << 6) + (q & lmask)] = j;
@@ -1720,8 +1727,12 @@ __global__ __launch_bounds__(kBlock) void k_rattle_mb(KArgs a) {
 // One step k of the rigid waters (after k_step stored their forces F_k):
 // v_k = v + h F/m and the velocity constraint (k > 0); v += h F/m, drift and
 // position constraint with its velocity correction (k < nf).
-__global__ __launch_bounds__(kBlock) void k_settle(KArgs a, int k, int b0, int bin, int cl) {
-    const int gm = blockIdx.x * kBlock + threadIdx.x;
+// (one thread per molecule in blocks of one wavefront, so that the few
+// thousand molecules of a box spread over many CUs)
+constexpr int kSettleBlock = 64;
+
+__global__ __launch_bounds__(kSettleBlock) void k_settle(KArgs a, int k, int b0, int bin, int cl) {
+    const int gm = blockIdx.x * kSettleBlock + threadIdx.x;
     if (gm >= a.G.n_mol * a.nbox) return;
     int w[3];
     const int bi = water_slots(a, gm, w);

@@ -557,7 +557,8 @@ int enqueue_round(h4d_system *s, int move, hipStream_t st, int nf, int M, bool t
         if (s->p.precision == H4D_PREC_FP32) launch_step<1>(s, st, e0, e1, k, b, bin);
         else launch_step<0>(s, st, e0, e1, k, b, bin);
         if (a.G.water)
-            hipLaunchKernelGGL(k_settle, dim3(blocks_for(a.G.n_mol * s->nbox)), dim3(kBlock), 0, st, a, k, b, bin,
+            hipLaunchKernelGGL(k_settle, dim3((a.G.n_mol * s->nbox + kSettleBlock - 1) / kSettleBlock),
+                               dim3(kSettleBlock), 0, st, a, k, b, bin,
                                s->cl);
         b ^= 1;
     }
