@@ -338,13 +338,15 @@ void set_lanes(h4d_system *s, int L) {
 
 int slot_blocks(const h4d_system *s) { return s->a.slots / kBlock; }
 
-// Staging entries of the cell-form list build: as many as 40 KB of LDS
-// holds (four blocks per CU), enough for all 27 cells of typical occupancy
-// in one round, and never fewer than one z-layer of full cells.
+// Staging entries of the cell-form list build: as many as a quarter of the
+// CU's 160 KB of LDS holds next to the kernel's static arrays (four blocks
+// per CU), enough for all 27 cells of typical occupancy in one round, and
+// never fewer than one z-layer of full cells.
 int list_cand_cap(const h4d_system *s) {
     const int cap = s->a.cell_cap;
     const int fixed = (int)(kWave * sizeof(uint4) + (size_t)cap * (sizeof(uint4) + sizeof(int)));
-    return std::max(9 * cap, (40 * 1024 - fixed) / (int)sizeof(uint4));
+    constexpr int kStaticLds = 512;   // cidx, cnt27, off (328 bytes) and slack
+    return std::max(9 * cap, (40 * 1024 - kStaticLds - fixed) / (int)sizeof(uint4));
 }
 
 // LDS of the cell-form list build: the staged candidates and their padding,
