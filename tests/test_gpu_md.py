@@ -100,3 +100,34 @@ def test_batched_phases_match_the_oracle_per_box():
     for b in range(3):
         close_state(bat.box_state(b), os_[b], atol=1e-6)
     bat.close()
+
+
+def test_phase_on_speculative_replicas_keeps_them_equal():
+    say("case md phase on 4 speculative replicas of lj300 fp64")
+    w = W.lj_electrolyte(300, 0.1, 81, n_steps=20, precision="fp64")
+    w.params.update(md_refresh=0.4, beta_mu=10.0)
+    sp = h4d.Speculative.from_workload(w, 4)
+    o = O.OracleSystem.from_workload(w, cap=w.n + 64)
+    recs = sp.md_phase(12)
+    ro = o.md_phase(0, 12)
+    for r in recs:   # every replica ran the same phase
+        same_record(r, ro, "phase 0")
+    s0 = sp.box_state(0)
+    close_state(s0, o)
+    for b in range(1, 4):
+        sb = sp.box_state(b)
+        assert np.array_equal(sb["x"], s0["x"]) and np.array_equal(sb["v"], s0["v"])
+    # the chain's trials go on from the phase's state
+    rt = sp.trials(6)
+    for t, rg in enumerate(rt):
+        same_record(rg, o.trial(t), f"trial {t}")
+    sp.close()
+
+
+def test_phase_refuses_rigid_water():
+    w = W.water_nacl(n_water=300, n_pairs=10, L=21.0, m=7, seed=78)
+    g = h4d.System.from_workload(w, precision="fp64")
+    with pytest.raises(h4d.H4DError) as e:
+        g.md_phase(5)
+    assert e.value.code == h4d.H4D_EINVAL
+    g.close()
