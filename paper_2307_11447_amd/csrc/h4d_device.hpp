@@ -179,22 +179,31 @@ __device__ __forceinline__ float erfc_as(float x, float ex) {
     return poly * ex;
 }
 
+// FP32 force coefficients of a non-flying atom of one type against a
+// partner of type tj (index tj | kFlyBit for a flying partner): the flyer's
+// squared altitude w2 and its Eq. 11 screening folded into qqk, so that the
+// pair loop needs no flyer test.  Built per block and step.
+struct ForceCoef {
+    float sig2, eps24, qqk, w2;
+};
+constexpr int kForceRow = 32;   // partner indices: meta & (kTypeMask | kFlyBit)
+
 // Radial force over distance, -(du/ds)/s, of one pair at squared 4D
 // distance s2 (FP32), without branches (both cutoffs by select), with the
-// hardware reciprocal, reciprocal square root and exp2.  g screens the
-// Coulomb part.  s2 must be positive.
-__device__ __forceinline__ float pair_fs_f32(const Geo &G, const PairCoef &c, float s2, float g) {
+// hardware reciprocal square root and exp2 and one reciprocal.  s2 must be
+// positive.
+__device__ __forceinline__ float pair_fs_f32(const Geo &G, const ForceCoef &c, float s2) {
     const float rs = __builtin_amdgcn_rsqf(s2);
     const float inv = rs * rs;                   // 1 / s^2 without a second transcendental
-    const float sr2 = c.sig2f * inv;
+    const float sr2 = c.sig2 * inv;
     const float sr6 = sr2 * sr2 * sr2;
-    const float flj = c.eps24f * sr6 * (2.0f * sr6 - 1.0f) * inv;
+    const float flj = c.eps24 * sr6 * (2.0f * sr6 - 1.0f) * inv;
     const float s = s2 * rs;
     const float ex = __builtin_amdgcn_exp2f(G.nalpha2_log2e * s2);
     const float t = __builtin_amdgcn_rcpf(1.0f + G.p_alpha * s);
     const float poly = t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f +
                        t * (-1.453152027f + t * 1.061405429f))));
-    const float fc = g * c.qqkf * ((poly * inv + G.cexf * rs) * ex - G.Scf) * rs;
+    const float fc = c.qqk * ((poly * inv + G.cexf * rs) * ex - G.Scf) * rs;
     return (s2 < G.rc_lj2f ? flj : 0.0f) + (s2 < G.rc_c2f ? fc : 0.0f);
 }
 

@@ -802,10 +802,33 @@ __global__ __launch_bounds__(kBlock) void k_list_lanes(KArgs a, int k, int b0, i
 // partners come from the 27 cells of the last build (cell edge >= r_c +
 // skin covers every partner within r_c).  Every pair is counted once.
 // ==========================================================================
+// The block's FP32 force table for altitude wv and screening gscr (one
+// entry per thread; call before a barrier): row ti, index tj | fly.  A flying
+// partner sits at its own altitude (the anion's scaled by w_ratio with SP).
+template <bool SP>
+__device__ __forceinline__ void build_force_coef(const KArgs &a, ForceCoef *fcf, double wv, double gscr) {
+    for (int q = threadIdx.x; q < kMaxTypes * kForceRow; q += blockDim.x) {
+        const int ti = q / kForceRow, v = q % kForceRow, tj = v & kTypeMask;
+        const bool fly = (v & kFlyBit) != 0;
+        ForceCoef f = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (tj < kMaxTypes) {
+            const PairCoef &pc = a.coef[ti * kMaxTypes + tj];
+            const float w2 = (float)(wv * wv);
+            const float w2a = SP ? (float)((wv * a.G.w_ratio) * (wv * a.G.w_ratio)) : w2;
+            f.sig2 = pc.sig2f;
+            f.eps24 = pc.eps24f;
+            f.qqk = fly ? (float)gscr * pc.qqkf : pc.qqkf;
+            f.w2 = fly ? ((SP && tj == a.anion_type) ? w2a : w2) : 0.0f;
+        }
+        fcf[q] = f;
+    }
+}
+
 template <int PREC, int L, bool SP>
-__device__ __forceinline__ void group_force(const KArgs &a, const Box &B, const Ctl *c, const CoefLds &cf, int b,
-                                            int cl, int w, int s, const double4 &pi, int mi, double wv, double gscr,
-                                            const int *flist, int nfast, double &fx, double &fy, double &fz) {
+__device__ __forceinline__ void group_force(const KArgs &a, const Box &B, const Ctl *c, const CoefLds &cf,
+                                            const ForceCoef *fcf, int b, int cl, int w, int s, const double4 &pi,
+                                            int mi, double wv, double gscr, const int *flist, int nfast, double &fx,
+                                            double &fy, double &fz) {
     constexpr int A = kWave / L;
     const int ti = mi & kTypeMask;
     const bool own_fast = (mi & kFastBit) != 0;
@@ -817,21 +840,19 @@ __device__ __forceinline__ void group_force(const KArgs &a, const Box &B, const 
     if (PREC == 1) {
         const uint4 *F = a.fx[b];
         const uint4 qi = F[w];
-        const float w2 = (float)(wv * wv), g = (float)gscr;
-        const float w2a = SP ? (float)((wv * a.G.w_ratio) * (wv * a.G.w_ratio)) : w2;
+        const ForceCoef *frow = fcf + ti * kForceRow;
         const float sx = B.fx_scale[0], sy = B.fx_scale[1], sz = B.fx_scale[2];
         float ax = 0.f, ay = 0.f, az = 0.f;
+        // (an invalid entry may give a non-finite fs, e.g. the padding's
+        // self pair at s2 = 0: the select drops it)
         auto pair = [&](const uint4 &qj, bool valid) {
             const float dx = (float)(int)(qi.x - qj.x) * sx;
             const float dy = (float)(int)(qi.y - qj.y) * sy;
             const float dz = (float)(int)(qi.z - qj.z) * sz;
-            const int mj = (int)qj.w;
-            const bool fj = (mj & kFlyBit) != 0;
+            const ForceCoef &fc = frow[(int)qj.w & (kTypeMask | kFlyBit)];
             const float r2 = dx * dx + dy * dy + dz * dz;
-            const float s2 = fj ? r2 + ((SP && (mj & kTypeMask) == a.anion_type) ? w2a : w2) : r2;
-            const bool ok = valid && s2 < a.G.rc_max2f;
-            const float fs = pair_fs_f32(a.G, crow[mj & kTypeMask], ok ? s2 : a.G.rc_max2f, fj ? g : 1.0f);
-            const float f = ok ? fs : 0.0f;
+            const float fs = pair_fs_f32(a.G, fc, r2 + fc.w2);
+            const float f = valid ? fs : 0.0f;
             ax += f * dx; ay += f * dy; az += f * dz;
         };
         if (!own_fast) {
@@ -945,14 +966,12 @@ __device__ __forceinline__ void group_force(const KArgs &a, const Box &B, const 
 // calls this; mine marks lane s = 0 of a fast, non-flying, active atom, and
 // that lane's force gains the sum (fixed butterfly order).
 template <bool SP>
-__device__ __forceinline__ void fast_atoms_wave(const KArgs &a, const Box &B, const CoefLds &cf, int b, int cl,
+__device__ __forceinline__ void fast_atoms_wave(const KArgs &a, const Box &B, const ForceCoef *fcf, int b, int cl,
                                                 bool mine, int w, int lane, double wv, double gscr, double &fx,
                                                 double &fy, double &fz) {
     unsigned long long fm = __ballot(mine);
     if (fm == 0ull || !B.use_cells) return;
     const uint4 *F = a.fx[b];
-    const float w2 = (float)(wv * wv), g = (float)gscr;
-    const float w2a = SP ? (float)((wv * a.G.w_ratio) * (wv * a.G.w_ratio)) : w2;
     const float sx = B.fx_scale[0], sy = B.fx_scale[1], sz = B.fx_scale[2];
     while (fm != 0ull) {
         const int src = __ffsll((long long)fm) - 1;
@@ -961,7 +980,7 @@ __device__ __forceinline__ void fast_atoms_wave(const KArgs &a, const Box &B, co
         const uint4 qi = F[wf];
         const double4 pf = a.pos[b][wf];
         const int mi = (int)qi.w;
-        const PairCoef *crow = cf.c + (mi & kTypeMask) * kMaxTypes;
+        const ForceCoef *frow = fcf + (mi & kTypeMask) * kForceRow;
         const int own_mol = (mi & kMolBit) ? a.wmol[wf] : -1;
         const int cx = cell_coord(pf.x, B.L[0], B.ncell[0]);
         const int cy = cell_coord(pf.y, B.L[1], B.ncell[1]);
@@ -978,13 +997,10 @@ __device__ __forceinline__ void fast_atoms_wave(const KArgs &a, const Box &B, co
                 const float dx = (float)(int)(qi.x - qj.x) * sx;
                 const float dy = (float)(int)(qi.y - qj.y) * sy;
                 const float dz = (float)(int)(qi.z - qj.z) * sz;
-                const int mj = (int)qj.w;
-                const bool fj = (mj & kFlyBit) != 0;
+                const ForceCoef &fc = frow[(int)qj.w & (kTypeMask | kFlyBit)];
                 const float r2 = dx * dx + dy * dy + dz * dz;
-                const float s2 = fj ? r2 + ((SP && (mj & kTypeMask) == a.anion_type) ? w2a : w2) : r2;
-                const bool ok = valid && s2 < a.G.rc_max2f;
-                const float fs = pair_fs_f32(a.G, crow[mj & kTypeMask], ok ? s2 : a.G.rc_max2f, fj ? g : 1.0f);
-                const float f = ok ? fs : 0.0f;
+                const float fs = pair_fs_f32(a.G, fc, r2 + fc.w2);
+                const float f = valid ? fs : 0.0f;
                 ax += f * dx; ay += f * dy; az += f * dz;
             }
         }
@@ -1124,6 +1140,11 @@ __global__ __launch_bounds__(kBlock) void k_step(KArgs a, int k, int b, int bin,
     if (!flyer_block && slot0 - B.a0 >= n_all) return;
     __shared__ CoefLds cf;
     load_coef(cf, a.coef);
+    const double wv = altitude(a.G, move, k, nf);
+    // Eq. 11 screening at the flyers' mean altitude
+    const double gscr = exp(-a.G.kappa * (SP ? 0.5 * wv * (1.0 + a.G.w_ratio) : wv));
+    __shared__ ForceCoef fcf[PREC == 1 ? kMaxTypes * kForceRow : 1];
+    if (PREC == 1) build_force_coef<SP>(a, fcf, wv, gscr);
     const int lr = k % 3, lw = (k + 1) % 3;       // fast list read / written by this step
     const int nfast = min(c->nfast[lr], kFastCap);
     int *fast = a.fast + (size_t)bi * 3 * kFastCap;
@@ -1155,13 +1176,11 @@ __global__ __launch_bounds__(kBlock) void k_step(KArgs a, int k, int b, int bin,
     const int mi = meta_of(pi);
     const bool fly = (mi & kFlyBit) != 0;
     const int ti = mi & kTypeMask;
-    const double wv = altitude(a.G, move, k, nf);
-    // Eq. 11 screening at the flyers' mean altitude
-    const double gscr = exp(-a.G.kappa * (SP ? 0.5 * wv * (1.0 + a.G.w_ratio) : wv));
     double fx = 0.0, fy = 0.0, fz = 0.0;
-    if (act && !fly) group_force<PREC, L, SP>(a, B, c, cf, b, cl, wc, s, pi, mi, wv, gscr, flist, nfast, fx, fy, fz);
-    if (PREC == 1) fast_atoms_wave<SP>(a, B, cf, b, cl, act && !fly && s == 0 && (mi & kFastBit), wc, lane, wv, gscr,
-                                   fx, fy, fz);
+    if (act && !fly)
+        group_force<PREC, L, SP>(a, B, c, cf, fcf, b, cl, wc, s, pi, mi, wv, gscr, flist, nfast, fx, fy, fz);
+    if (PREC == 1) fast_atoms_wave<SP>(a, B, fcf, b, cl, act && !fly && s == 0 && (mi & kFastBit), wc, lane, wv, gscr,
+                                       fx, fy, fz);
     if (!act || s != 0) return;
     if (mi & kMolBit) {   // rigid water: integrated by k_settle
         a.fw[wc] = make_double4(fx, fy, fz, 0.0);
@@ -1206,6 +1225,9 @@ __global__ __launch_bounds__(kBlock) void k_forces(KArgs a, double wv) {
     const Ctl *c = a.ctl + bi;
     __shared__ CoefLds cf;
     load_coef(cf, a.coef);
+    const double gscr = exp(-a.G.kappa * (SP ? 0.5 * wv * (1.0 + a.G.w_ratio) : wv));
+    __shared__ ForceCoef fcf[PREC == 1 ? kMaxTypes * kForceRow : 1];
+    if (PREC == 1) build_force_coef<SP>(a, fcf, wv, gscr);
     __syncthreads();
     const int lane = threadIdx.x % kWave;
     const int s = lane % L;
@@ -1215,11 +1237,10 @@ __global__ __launch_bounds__(kBlock) void k_forces(KArgs a, double wv) {
     const double4 pi = a.pos[0][wc];
     const int mi = meta_of(pi);
     double fx = 0.0, fy = 0.0, fz = 0.0;
-    const double gscr = exp(-a.G.kappa * (SP ? 0.5 * wv * (1.0 + a.G.w_ratio) : wv));
     if (act && !(mi & kFlyBit))
-        group_force<PREC, L, SP>(a, B, c, cf, 0, 0, wc, s, pi, mi, wv, gscr, a.fast, 0, fx, fy, fz);
-    if (PREC == 1) fast_atoms_wave<SP>(a, B, cf, 0, 0, act && !(mi & kFlyBit) && s == 0 && (mi & kFastBit), wc, lane,
-                                       wv, gscr, fx, fy, fz);
+        group_force<PREC, L, SP>(a, B, c, cf, fcf, 0, 0, wc, s, pi, mi, wv, gscr, a.fast, 0, fx, fy, fz);
+    if (PREC == 1) fast_atoms_wave<SP>(a, B, fcf, 0, 0, act && !(mi & kFlyBit) && s == 0 && (mi & kFastBit), wc,
+                                       lane, wv, gscr, fx, fy, fz);
     if (act && s == 0) a.force[a.perm[wc]] = make_double4(fx, fy, fz, 0.0);
 }
 
