@@ -184,7 +184,8 @@ __device__ __forceinline__ float erfc_as(float x, float ex) {
 // squared altitude w2 and its Eq. 11 screening folded into qqk, so that the
 // pair loop needs no flyer test.  Built per block and step.
 struct ForceCoef {
-    float sig2, eps24, qqk, w2;
+    float lj12, lj6;   // 48 eps sigma^12 and 24 eps sigma^6: f_LJ = (lj12 / s^6 - lj6) / s^8
+    float qqk, w2;
 };
 constexpr int kForceRow = 32;   // partner indices: meta & (kTypeMask | kFlyBit)
 
@@ -195,9 +196,8 @@ constexpr int kForceRow = 32;   // partner indices: meta & (kTypeMask | kFlyBit)
 __device__ __forceinline__ float pair_fs_f32(const Geo &G, const ForceCoef &c, float s2) {
     const float rs = __builtin_amdgcn_rsqf(s2);
     const float inv = rs * rs;                   // 1 / s^2 without a second transcendental
-    const float sr2 = c.sig2 * inv;
-    const float sr6 = sr2 * sr2 * sr2;
-    const float flj = c.eps24 * sr6 * (2.0f * sr6 - 1.0f) * inv;
+    const float inv3 = inv * inv * inv;
+    const float flj = inv3 * (c.lj12 * inv3 - c.lj6) * inv;
     const float s = s2 * rs;
     const float ex = __builtin_amdgcn_exp2f(G.nalpha2_log2e * s2);
     const float t = __builtin_amdgcn_rcpf(1.0f + G.p_alpha * s);

@@ -815,8 +815,9 @@ __device__ __forceinline__ void build_force_coef(const KArgs &a, ForceCoef *fcf,
             const PairCoef &pc = a.coef[ti * kMaxTypes + tj];
             const float w2 = (float)(wv * wv);
             const float w2a = SP ? (float)((wv * a.G.w_ratio) * (wv * a.G.w_ratio)) : w2;
-            f.sig2 = pc.sig2f;
-            f.eps24 = pc.eps24f;
+            const double sig6 = pc.sig2 * pc.sig2 * pc.sig2;
+            f.lj12 = (float)(48.0 * pc.eps * sig6 * sig6);
+            f.lj6 = (float)(24.0 * pc.eps * sig6);
             f.qqk = fly ? (float)gscr * pc.qqkf : pc.qqkf;
             f.w2 = fly ? ((SP && tj == a.anion_type) ? w2a : w2) : 0.0f;
         }
@@ -841,19 +842,22 @@ __device__ __forceinline__ void group_force(const KArgs &a, const Box &B, const 
         const uint4 *F = a.fx[b];
         const uint4 qi = F[w];
         const ForceCoef *frow = fcf + ti * kForceRow;
-        const float sx = B.fx_scale[0], sy = B.fx_scale[1], sz = B.fx_scale[2];
+        // displacements stay in fixed-point units (one scale per axis,
+        // squared into the distance and applied to the summed force)
+        const float sx2 = B.fx_scale[0] * B.fx_scale[0], sy2 = B.fx_scale[1] * B.fx_scale[1];
+        const float sz2 = B.fx_scale[2] * B.fx_scale[2];
         float ax = 0.f, ay = 0.f, az = 0.f;
         // (an invalid entry may give a non-finite fs, e.g. the padding's
         // self pair at s2 = 0: the select drops it)
         auto pair = [&](const uint4 &qj, bool valid) {
-            const float dx = (float)(int)(qi.x - qj.x) * sx;
-            const float dy = (float)(int)(qi.y - qj.y) * sy;
-            const float dz = (float)(int)(qi.z - qj.z) * sz;
+            const float ux = (float)(int)(qi.x - qj.x);
+            const float uy = (float)(int)(qi.y - qj.y);
+            const float uz = (float)(int)(qi.z - qj.z);
             const ForceCoef &fc = frow[(int)qj.w & (kTypeMask | kFlyBit)];
-            const float r2 = dx * dx + dy * dy + dz * dz;
-            const float fs = pair_fs_f32(a.G, fc, r2 + fc.w2);
+            const float s2 = fmaf(uz * sz2, uz, fmaf(uy * sy2, uy, fmaf(ux * sx2, ux, fc.w2)));
+            const float fs = pair_fs_f32(a.G, fc, s2);
             const float f = valid ? fs : 0.0f;
-            ax += f * dx; ay += f * dy; az += f * dz;
+            ax += f * ux; ay += f * uy; az += f * uz;
         };
         if (!own_fast) {
             // batches of NB neighbours: the list indices of the next batch
@@ -896,7 +900,7 @@ __device__ __forceinline__ void group_force(const KArgs &a, const Box &B, const 
             ay += __shfl_xor(ay, off, kWave);
             az += __shfl_xor(az, off, kWave);
         }
-        fx = ax; fy = ay; fz = az;
+        fx = ax * B.fx_scale[0]; fy = ay * B.fx_scale[1]; fz = az * B.fx_scale[2];
     } else {
         const double4 *P = a.pos[b];
         double ax = 0.0, ay = 0.0, az = 0.0;
