@@ -620,6 +620,11 @@ __global__ __launch_bounds__(kBlock) void k_list_allpairs(KArgs a, int k, int b0
 // count in the other buffer and the box's fast lists.
 constexpr int kListWaves = 8;
 
+template <bool C>
+struct BoolTag {
+    static constexpr bool value = C;
+};
+
 template <bool MOL>
 __global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int k, int b0, int cb, int split,
                                                                     int cand_cap) {
@@ -659,6 +664,8 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int 
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const float rl2 = (float)a.G.rlist2 * 1.00001f;
     const float sx = B.fx_scale[0], sy = B.fx_scale[1], sz = B.fx_scale[2];
+    const bool cubic = sx == sy && sy == sz;
+    const float rl2u = (float)(a.G.rlist2 / ((double)sx * (double)sx)) * 1.00001f;   // in fixed-point units
     const unsigned long long below = (1ull << lane) - 1ull;
     const int ll = a.lanes_log2, lmask = (1 << ll) - 1;
     int total27 = 0;
@@ -702,20 +709,35 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int 
             }
             int cnt = ccount[t];
             int *dst = a.nbr + nbr_slot(a, wi, 0);
-#pragma unroll 2
-            for (int base = 0; base < total; base += kWave) {
-                const uint4 qj = cand[base + lane];
-                const int j = (int)qj.w;
-                const float dx = (float)(int)(qi.x - qj.x) * sx;
-                const float dy = (float)(int)(qi.y - qj.y) * sy;
-                const float dz = (float)(int)(qi.z - qj.z) * sz;
-                bool acc = dx * dx + dy * dy + dz * dz < rl2 && j != wi && j >= 0;
-                if (MOL && (j == sib0 || j == sib1 || j == sib2)) acc = false;   // ions carry no molecule (-1)
-                const unsigned long long msk = __ballot(acc);
-                const int q = cnt + __popcll(msk & below);
-                if (acc && q < a.nbr_cap) dst[((q >> ll) << 6) + (q & lmask)] = j;
-                cnt += __popcll(msk);
-            }
+            // a cubic box compares squared distances in fixed-point units
+            // (three multiplies fewer per candidate)
+            auto scan = [&](auto cubic_tag) {
+                constexpr bool CUBIC = decltype(cubic_tag)::value;
+                for (int base = 0; base < total; base += kWave) {
+                    const uint4 qj = cand[base + lane];
+                    const int j = (int)qj.w;
+                    float d2;
+                    if constexpr (CUBIC) {
+                        const float ux = (float)(int)(qi.x - qj.x);
+                        const float uy = (float)(int)(qi.y - qj.y);
+                        const float uz = (float)(int)(qi.z - qj.z);
+                        d2 = ux * ux + uy * uy + uz * uz;
+                    } else {
+                        const float dx = (float)(int)(qi.x - qj.x) * sx;
+                        const float dy = (float)(int)(qi.y - qj.y) * sy;
+                        const float dz = (float)(int)(qi.z - qj.z) * sz;
+                        d2 = dx * dx + dy * dy + dz * dz;
+                    }
+                    bool acc = d2 < (CUBIC ? rl2u : rl2) && j != wi && j >= 0;
+                    if (MOL && (j == sib0 || j == sib1 || j == sib2)) acc = false;   // ions carry no molecule (-1)
+                    const unsigned long long msk = __ballot(acc);
+                    const int q = cnt + __popcll(msk & below);
+                    if (acc && q < a.nbr_cap) dst[((q >> ll) << 6) + (q & lmask)] = j;
+                    cnt += __popcll(msk);
+                }
+            };
+            if (cubic) scan(BoolTag<true>{});
+            else scan(BoolTag<false>{});
             if (lane == 0) ccount[t] = cnt;
         }
         __syncthreads();
