@@ -180,14 +180,18 @@ __device__ __forceinline__ float erfc_as(float x, float ex) {
 }
 
 // FP32 force coefficients of a non-flying atom of one type against a
-// partner of type tj (index tj | kFlyBit for a flying partner): the flyer's
-// squared altitude w2 and its Eq. 11 screening folded into qqk, so that the
-// pair loop needs no flyer test.  Built per block and step.
+// partner with meta bits tj | fly | fast: the flyer's squared altitude w2
+// and its Eq. 11 screening folded into qqk, so that the pair loop needs no
+// flyer test; a fast partner (its pairs come from the fast list) and the
+// null record that pads the lists get no force (zero coefficients at
+// w2 = 1e30, far beyond every cutoff), so the loop needs no validity test
+// either.  Built per block and step.
 struct ForceCoef {
     float lj12, lj6;   // 48 eps sigma^12 and 24 eps sigma^6: f_LJ = (lj12 / s^6 - lj6) / s^8
     float qqk, w2;
 };
-constexpr int kForceRow = 32;   // partner indices: meta & (kTypeMask | kFlyBit)
+constexpr int kForceRow = 64;   // partner indices: meta & (kTypeMask | kFlyBit | kFastBit)
+constexpr float kFarW2 = 1.0e30f;
 
 // Radial force over distance, -(du/ds)/s, of one pair at squared 4D
 // distance s2 (FP32), without branches (both cutoffs by select), with the

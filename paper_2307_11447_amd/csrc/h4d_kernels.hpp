@@ -832,8 +832,8 @@ __device__ __forceinline__ void build_force_coef(const KArgs &a, ForceCoef *fcf,
     for (int q = threadIdx.x; q < kMaxTypes * kForceRow; q += blockDim.x) {
         const int ti = q / kForceRow, v = q % kForceRow, tj = v & kTypeMask;
         const bool fly = (v & kFlyBit) != 0;
-        ForceCoef f = {0.0f, 0.0f, 0.0f, 0.0f};
-        if (tj < kMaxTypes) {
+        ForceCoef f = {0.0f, 0.0f, 0.0f, kFarW2};
+        if (tj < kMaxTypes && !(v & kFastBit)) {
             const PairCoef &pc = a.coef[ti * kMaxTypes + tj];
             const float w2 = (float)(wv * wv);
             const float w2a = SP ? (float)((wv * a.G.w_ratio) * (wv * a.G.w_ratio)) : w2;
@@ -869,8 +869,8 @@ __device__ __forceinline__ void group_force(const KArgs &a, const Box &B, const 
         const float sx2 = B.fx_scale[0] * B.fx_scale[0], sy2 = B.fx_scale[1] * B.fx_scale[1];
         const float sz2 = B.fx_scale[2] * B.fx_scale[2];
         float ax = 0.f, ay = 0.f, az = 0.f;
-        // (an invalid entry may give a non-finite fs, e.g. the padding's
-        // self pair at s2 = 0: the select drops it)
+        // (an invalid entry may give a non-finite fs, e.g. a self pair at
+        // s2 = 0: the select drops it)
         auto pair = [&](const uint4 &qj, bool valid) {
             const float ux = (float)(int)(qi.x - qj.x);
             const float uy = (float)(int)(qi.y - qj.y);
@@ -882,15 +882,19 @@ __device__ __forceinline__ void group_force(const KArgs &a, const Box &B, const 
             ax += f * ux; ay += f * uy; az += f * uz;
         };
         if (!own_fast) {
-            // batches of NB neighbours: the list indices of the next batch
-            // load while this batch's records are gathered
+            // The Verlet list, in batches of NB neighbours (the list indices
+            // of the next batch load while this batch's records are
+            // gathered).  A fast partner and the null record that pads the
+            // last batch index force-table entries that give exactly zero,
+            // so no entry needs a validity test.
             constexpr int NB = 4;
             const int nn = a.nnbr[w];
             const int *base = a.nbr + ((size_t)(w / A) * (size_t)(a.nbr_cap / L)) * kWave + (size_t)(w % A) * L + s;
             const int nq = nn > s ? (nn - s + L - 1) / L : 0;
+            const int null_slot = a.slots;
             int jn[NB];
 #pragma unroll
-            for (int u = 0; u < NB; ++u) jn[u] = (u < nq) ? base[(size_t)u * kWave] : w;
+            for (int u = 0; u < NB; ++u) jn[u] = (u < nq) ? base[(size_t)u * kWave] : null_slot;
             for (int k = 0; k < nq; k += NB) {
                 int j[NB];
                 uint4 q[NB];
@@ -899,9 +903,18 @@ __device__ __forceinline__ void group_force(const KArgs &a, const Box &B, const 
 #pragma unroll
                 for (int u = 0; u < NB; ++u) q[u] = F[j[u]];
 #pragma unroll
-                for (int u = 0; u < NB; ++u) jn[u] = (k + NB + u < nq) ? base[(size_t)(k + NB + u) * kWave] : w;
+                for (int u = 0; u < NB; ++u)
+                    jn[u] = (k + NB + u < nq) ? base[(size_t)(k + NB + u) * kWave] : null_slot;
 #pragma unroll
-                for (int u = 0; u < NB; ++u) pair(q[u], k + u < nq && !(q[u].w & kFastBit));
+                for (int u = 0; u < NB; ++u) {
+                    const float ux = (float)(int)(qi.x - q[u].x);
+                    const float uy = (float)(int)(qi.y - q[u].y);
+                    const float uz = (float)(int)(qi.z - q[u].z);
+                    const ForceCoef &fc = frow[(int)q[u].w & (kTypeMask | kFlyBit | kFastBit)];
+                    const float s2 = fmaf(uz * sz2, uz, fmaf(uy * sy2, uy, fmaf(ux * sx2, ux, fc.w2)));
+                    const float f = pair_fs_f32(a.G, fc, s2);
+                    ax += f * ux; ay += f * uy; az += f * uz;
+                }
             }
         } else if (!B.use_cells) {
             const int j1 = B.a0 + c->n_all;

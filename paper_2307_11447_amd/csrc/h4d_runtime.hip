@@ -916,7 +916,7 @@ int create(const h4d_params *params, int nbox, const double *edges, const int32_
     if ((rc = s->alloc(&a.cpos, C)) || (rc = s->alloc(&a.cvel, C)) || (rc = s->alloc(&a.tvel, C)) ||
         (rc = s->alloc(&a.ctag, C)) || (rc = s->alloc(&a.ctype, C)) ||
         (rc = s->alloc(&a.cmol, C)) || (rc = s->alloc(&a.pos[0], C)) || (rc = s->alloc(&a.pos[1], C)) ||
-        (rc = s->alloc(&a.fx[0], C)) || (rc = s->alloc(&a.fx[1], C)) || (rc = s->alloc(&a.vel[0], C)) ||
+        (rc = s->alloc(&a.fx[0], C + 1)) || (rc = s->alloc(&a.fx[1], C + 1)) || (rc = s->alloc(&a.vel[0], C)) ||
         (rc = s->alloc(&a.vel[1], C)) || (rc = s->alloc(&a.perm, C)) || (rc = s->alloc(&a.wmol, C)) ||
         (rc = s->alloc(&a.posb, C)) || (rc = s->alloc(&a.force, C)) || (rc = s->alloc(&a.tpos, C)) ||
         (rc = s->alloc(&a.ttag, C)) || (rc = s->alloc(&a.ttype, C)) || (rc = s->alloc(&a.tmol, C)) ||
@@ -988,6 +988,11 @@ int create(const h4d_params *params, int nbox, const double *edges, const int32_
     UPLOAD(box_d, s->box_h.data(), sizeof(Box) * nbox);
     UPLOAD(slot_box_d, sb.data(), sizeof(int) * sb.size());
     UPLOAD(cell_box_d, cbx.data(), sizeof(int) * cbx.size());
+    {   // the null record past the last slot: the pair pass pads the lists with it
+        const uint4 null_rec = make_uint4(0u, 0u, 0u, (unsigned)kFastBit);
+        UPLOAD(a.fx[0] + C, &null_rec, sizeof(uint4));
+        UPLOAD(a.fx[1] + C, &null_rec, sizeof(uint4));
+    }
 #undef UPLOAD
     // rebuild interval: the fastest atoms (5 standard deviations) cover half
     // the skin; adapted on overflow
