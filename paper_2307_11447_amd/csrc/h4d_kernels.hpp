@@ -665,7 +665,19 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int 
     const float rl2 = (float)a.G.rlist2 * 1.00001f;
     const float sx = B.fx_scale[0], sy = B.fx_scale[1], sz = B.fx_scale[2];
     const bool cubic = sx == sy && sy == sz;
+    const unsigned lim = __float_as_uint(rl2) - 1u;
+    uint4 far_pad;
+    {
+        const int nx = B.ncell[0], ny = B.ncell[1], nz = B.ncell[2];
+        const int lc = cc - B.c0;
+        const int cx = lc % nx, cy = (lc / nx) % ny, cz = lc / (nx * ny);
+        auto opposite = [](int c, int n) {   // fixed-point coordinate of the cell centre, plus half the box
+            return (unsigned)(((2.0 * c + 1.0) / (2.0 * n)) * 4294967296.0) + 0x80000000u;
+        };
+        far_pad = make_uint4(opposite(cx, nx), opposite(cy, ny), opposite(cz, nz), 0xffffffffu);
+    }
     const float rl2u = (float)(a.G.rlist2 / ((double)sx * (double)sx)) * 1.00001f;   // in fixed-point units
+    const unsigned lim_u = __float_as_uint(rl2u) - 1u;
     const unsigned long long below = (1ull << lane) - 1ull;
     const int ll = a.lanes_log2, lmask = (1 << ll) - 1;
     int total27 = 0;
@@ -693,8 +705,11 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int 
             const uint4 q = a.fx[b][j];
             cand[e] = make_uint4(q.x, q.y, q.z, (unsigned)j);
         }
-        // pad to whole wavefronts with entries that never match (slot -1)
-        if (threadIdx.x < kWave) cand[off[cpl] + threadIdx.x] = make_uint4(0u, 0u, 0u, 0xffffffffu);
+        // pad to whole wavefronts with entries that never match: slot -1 at
+        // the point opposite the centre cell's centre, at least L/2 - h/2 >= h
+        // >= r_list from every centre atom along each axis (3 or more cells
+        // per edge)
+        if (threadIdx.x < kWave) cand[off[cpl] + threadIdx.x] = far_pad;
         __syncthreads();
         for (int t = part * kListWaves + wave; t < mc; t += split * kListWaves) {
             const uint4 qi = ctr[t];
@@ -728,11 +743,15 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int 
                         const float dz = (float)(int)(qi.z - qj.z) * sz;
                         d2 = dx * dx + dy * dy + dz * dz;
                     }
-                    bool acc = d2 < (CUBIC ? rl2u : rl2) && j != wi && j >= 0;
-                    if (MOL && (j == sib0 || j == sib1 || j == sib2)) acc = false;   // ions carry no molecule (-1)
-                    const unsigned long long msk = __ballot(acc);
-                    const int q = cnt + __popcll(msk & below);
-                    if (acc && q < a.nbr_cap) dst[((q >> ll) << 6) + (q & lmask)] = j;
+                    // 0 < d2 < r_list^2 as one unsigned compare of the float bits
+                    // (monotonic for d2 >= 0); d2 = 0 is the atom itself
+                    bool acc = __float_as_uint(d2) - 1u < (CUBIC ? lim_u : lim);
+                    if (MOL) acc &= (j != sib0) & (j != sib1) & (j != sib2);   // ions carry no molecule (-1)
+                    const unsigned long long msk = __builtin_amdgcn_ballot_w64(acc);
+                    // accepted lanes below this one: the lane's slot after the running count
+                    const unsigned q = (unsigned)cnt + __builtin_amdgcn_mbcnt_hi(
+                                           (unsigned)(msk >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)msk, 0u));
+                    if (acc && q < (unsigned)a.nbr_cap) dst[((q >> ll) << 6) | (q & (unsigned)lmask)] = j;
                     cnt += __popcll(msk);
                 }
             };
