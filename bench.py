@@ -704,7 +704,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py: this build runs on one GPU (asked for {args.gpus} GPUs, WORLD_SIZE={world}); "
+        print(f"bench.py: the library runs on one GPU (asked for {args.gpus} GPUs, WORLD_SIZE={world}); "
               "boxes are independent Markov chains and would shard across GPUs without communication, "
               "but no multi-GPU path is built", file=sys.stderr)
         sys.exit(2)

@@ -81,3 +81,14 @@ def test_momentum_options_are_validated_before_any_device_work():
     with pytest.raises(h4d.H4DError) as e:   # replicas of one chain cannot carry momenta
         h4d.Speculative(dict(w.params, momenta=1), 4, w.x, w.type, w.mol, w.tag, w.nsalt, stream=C.c_void_p())
     assert e.value.code == h4d.H4D_EINVAL
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
