@@ -242,8 +242,10 @@ int32_t h4d_run_trials(h4d_system *sys, int32_t n, int32_t move, h4d_trial *out)
  * the trials').  The momenta stay with the state: trials with momenta = 1
  * start from them, and h4d_get_state returns them.  out (host, may be NULL)
  * receives one record per box: move = H4D_MOVE_MD, trial = the phase index,
- * dH, dU, dK, H0, H1, ln_ratio = -beta dH, ln_u, accepted.  Ion systems only
- * (H4D_EINVAL with water); n_steps >= 1.
+ * dH, dU, dK, H0, H1, ln_ratio = -beta dH, ln_u, accepted.  On a speculative
+ * handle the phase runs on the first replica and the others take its state
+ * (every record is that replica's).  Ion systems only (H4D_EINVAL with
+ * water); n_steps >= 1.
  */
 int32_t h4d_run_md(h4d_system *sys, int32_t n_steps, h4d_trial *out);
 

@@ -775,15 +775,33 @@ int run_md(h4d_system *s, int n_steps, h4d_trial *out) {
         a.md_steps = n_steps;
         s->drop_graphs();     // the graphs captured the step count
     }
-    hipLaunchKernelGGL(k_set_md_quota, dim3(blocks_for(s->nbox)), dim3(kBlock), 0, s->stream, a, 1LL);
-    HIPC(hipGetLastError());
-    int rc = read_ctl(s);
-    if (rc) return rc;
+    int rc;
+    if (s->speculative) {
+        // the replicas hold one chain: the phase runs on replica 0 alone and
+        // the others take its state afterwards
+        if ((rc = read_ctl(s))) return rc;
+        for (int b = 0; b < s->nbox; ++b) s->h_ctl[b].md_end = s->h_ctl[b].md + (b == 0 ? 1 : 0);
+        if ((rc = write_ctl(s))) return rc;
+    } else {
+        hipLaunchKernelGGL(k_set_md_quota, dim3(blocks_for(s->nbox)), dim3(kBlock), 0, s->stream, a, 1LL);
+        HIPC(hipGetLastError());
+        if ((rc = read_ctl(s))) return rc;
+    }
     s->trial_M = std::max(1, s->rebuild_every);
     for (int round = 0; round < 64; ++round) {
         bool busy = false;
         for (int b = 0; b < s->nbox; ++b) busy |= s->h_ctl[b].md < s->h_ctl[b].md_end;
         if (!busy) {
+            if (s->speculative && s->nbox > 1) {
+                hipLaunchKernelGGL(k_broadcast_box, dim3(slot_blocks(s)), dim3(kBlock), 0, s->stream, a, 0);
+                HIPC(hipGetLastError());
+                if ((rc = read_ctl(s))) return rc;
+                for (int b = 1; b < s->nbox; ++b) {
+                    s->n_host[b] = s->n_host[0];
+                    s->nsalt_host[b] = s->nsalt_host[0];
+                    if (out) out[b] = out[0];
+                }
+            }
             s->vel_canonical = true;
             return H4D_OK;
         }
