@@ -37,6 +37,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "accepted salt-pair exchanges/s + NEMD atom-steps/s (1 GPU), learned vs plain"
 HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # published vector FP32 rate (packed FP32 counted)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_lj32k_traffic.txt")
 TRAFFIC_FILE_BATCHED = os.path.join(ROOT, "profiles", "k_step_batched256_traffic.txt")
 
@@ -102,6 +103,18 @@ def step_bytes_per_atom(mean_nbr):
     return 4.0 * mean_nbr + 184.0
 
 
+def step_flop_per_atom(mean_nbr):
+    """Algorithmic floating-point operations of one fused step launch, per
+    atom (an FMA counts 2, a reciprocal, square root or exponential 1).
+    Per list entry, in FP32: the displacement and the squared 4D distance
+    with the altitude term (9), the LJ force factor with 1/s^2 (7), the DSF
+    Coulomb force factor with s, 1/s, the Gaussian and the erfc
+    approximation (23), their sum (1) and the accumulation of the factor
+    times the displacement (6): 46.  Per atom, in FP64: the two half kicks
+    and the drift of velocity Verlet (18)."""
+    return 46.0 * mean_nbr + 18.0
+
+
 def summarize(recs, wall, timing, timing_recs, traffic_bytes, atom_launches=None):
     """Throughput, acceptance and the step kernel's roofline from trial
     records (recs: the timed trials; timing_recs: the trials run with HIP
@@ -121,7 +134,9 @@ def summarize(recs, wall, timing, timing_recs, traffic_bytes, atom_launches=None
         atom_launches = sum(r.n_atoms * (r.n_steps + 1) for r in timing_recs)
     step_s = timing["step_ms"] * 1e-3
     launches = max(1, timing["step_launches"])
-    achieved = bpa * atom_launches / step_s / 1e9
+    fpa = step_flop_per_atom(mean_nbr)
+    achieved = fpa * atom_launches / step_s / 1e12
+    achieved_bytes = bpa * atom_launches / step_s / 1e9
     traffic = None if traffic_bytes is None else traffic_bytes * launches / step_s / 1e9
     return {
         "value": atom_steps / wall,
@@ -134,10 +149,12 @@ def summarize(recs, wall, timing, timing_recs, traffic_bytes, atom_launches=None
         "retried_trials": retried,
         "roofline": {
             "kernel": "k_step<1> (fused pair force + velocity Verlet)",
-            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "traffic_bytes_per_launch": traffic_bytes,
-            "bytes_per_atom_step": bpa, "mean_list_entries": mean_nbr,
+            "bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "flop_per_atom_step": fpa,
+            "traffic": traffic, "traffic_unit": "GB/s", "traffic_bytes_per_launch": traffic_bytes,
+            "hbm": {"achieved": achieved_bytes, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved_bytes / HBM_PEAK_GBS, "bytes_per_atom_step": bpa},
+            "mean_list_entries": mean_nbr,
             "avg_kernel_us": 1e3 * timing["step_ms"] / launches, "launches": timing["step_launches"],
             "timing": "HIP events around each step launch over the timing trials",
         },
