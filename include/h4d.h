@@ -306,6 +306,54 @@ int32_t h4d_get_box_state(h4d_system *sys, int32_t box, int32_t cap, int32_t *n,
                           int32_t *n_salt, double *pos, double *vel, int32_t *type,
                           int32_t *mol, int64_t *tag);
 
+/*
+ * Checkpoint and resume of a single-box chain.  The chain has no hidden
+ * generator state: every random number is a Philox draw keyed by (seed,
+ * stream) and counted by the trial index, the equilibrium-phase index and the
+ * ions' tags (the trial sequence of Sec. II A and the phase of Fig. 1).  So
+ * the atoms (h4d_get_state) and the fields below are all a new handle needs
+ * to continue where this one stands, with the same records: bitwise at the
+ * same launch shape, list capacities and rebuild interval, which the
+ * checkpoint carries.
+ *
+ * Resume: h4d_init_system(&ck.params, n, n_salt, n_mol, pos, type, mol, tag,
+ * stream, &sys) with the arrays of h4d_get_state, then
+ * h4d_restore_checkpoint(sys, &ck, n, vel).  A learned proposal is not part
+ * of the checkpoint: save its network with h4d_mlp_get_weights and apply it
+ * again with h4d_set_proposal.
+ */
+typedef struct h4d_checkpoint {
+    h4d_params params;        /* the parameters in force (setters included)  */
+    uint64_t trial;           /* index of the next trial                      */
+    uint64_t md_phases;       /* equilibrium phases run (their counter)       */
+    int64_t next_tag;         /* tag the next inserted cation takes           */
+    int32_t lanes_per_atom;   /* step-kernel launch shape in force: 4, 8, 16  */
+    int32_t rebuild_every;    /* list rebuild interval in force               */
+    int32_t clean_trials;     /* automatic interval: trials since the last
+                                 change                                       */
+    int32_t interval_tuned;   /* 1: h4d_autotune fixed the interval           */
+    int32_t nbr_cap, cell_cap;/* list capacities reached                      */
+    int32_t has_velocities;   /* 1: the state carries its own momenta (the vel
+                                 of h4d_get_state), required by the restore   */
+    int32_t reserved;
+    int64_t n_trials, n_ins, n_ins_acc, n_del, n_del_acc;
+    double N_sum, N2_sum;     /* running sums behind h4d_sample_observables   */
+} h4d_checkpoint;
+
+/* Fill *ck from a single-box handle (H4D_EINVAL for batches and speculative
+ * handles).  Synchronizes the handle's stream. */
+int32_t h4d_save_checkpoint(h4d_system *sys, h4d_checkpoint *ck);
+/* Apply *ck to a handle just created from the checkpoint's parameters and
+ * the state saved with it.  n_atoms: the state's atom count (checked); vel:
+ * host array n_atoms x 3 of the state's momenta (required when
+ * ck->has_velocities, else ignored; copied).  Errors: H4D_EINVAL for a
+ * handle whose seed, stream, precision, momenta mode, type count or water
+ * flag differ from the checkpoint's, an atom-count mismatch, next_tag not
+ * above every tag of the state, or invalid shape or capacities; the handle
+ * is then unchanged.  Rebuilds the lists. */
+int32_t h4d_restore_checkpoint(h4d_system *sys, const h4d_checkpoint *ck, int32_t n_atoms,
+                               const double *vel);
+
 /* Chemical potential beta * mu_salt of the following trials (Eqs. 6, 8). */
 int32_t h4d_set_beta_mu(h4d_system *sys, double beta_mu);
 

@@ -1292,6 +1292,103 @@ int32_t h4d_set_trial_index(h4d_system *s, uint64_t trial) {
     return write_ctl(s);
 }
 
+int32_t h4d_save_checkpoint(h4d_system *s, h4d_checkpoint *out) {
+    if (!s || !out) return fail(H4D_EINVAL, "null argument");
+    if (s->nbox != 1 || s->speculative) return fail(H4D_EINVAL, "checkpoints serve single-box systems");
+    int rc = read_ctl(s);
+    if (rc) return rc;
+    const Ctl &c = s->h_ctl[0];
+    const h4d_system::Stats &st = s->stats[0];
+    std::memset(out, 0, sizeof(*out));
+    out->params = s->p;
+    out->trial = (uint64_t)c.trial;
+    out->md_phases = (uint64_t)c.md;
+    out->next_tag = c.next_tag;
+    out->lanes_per_atom = s->a.lanes;
+    out->rebuild_every = s->rebuild_every;
+    out->clean_trials = s->clean_trials;
+    out->interval_tuned = s->interval_tuned ? 1 : 0;
+    out->nbr_cap = s->a.nbr_cap;
+    out->cell_cap = s->a.cell_cap;
+    out->has_velocities = (s->p.momenta || s->vel_canonical) ? 1 : 0;
+    out->n_trials = st.n_trials;
+    out->n_ins = st.n_ins;
+    out->n_ins_acc = st.n_ins_acc;
+    out->n_del = st.n_del;
+    out->n_del_acc = st.n_del_acc;
+    out->N_sum = st.N_sum;
+    out->N2_sum = st.N2_sum;
+    return H4D_OK;
+}
+
+int32_t h4d_restore_checkpoint(h4d_system *s, const h4d_checkpoint *ck, int32_t n_atoms, const double *vel) {
+    if (!s || !ck) return fail(H4D_EINVAL, "null argument");
+    if (s->nbox != 1 || s->speculative) return fail(H4D_EINVAL, "checkpoints serve single-box systems");
+    const h4d_params &q = ck->params;
+    if (q.seed != s->p.seed || q.stream != s->p.stream || q.precision != s->p.precision ||
+        q.momenta != s->p.momenta || q.n_types != s->p.n_types || q.water != s->p.water)
+        return fail(H4D_EINVAL, "the handle was not created with the checkpoint's parameters");
+    if (ck->lanes_per_atom != 4 && ck->lanes_per_atom != 8 && ck->lanes_per_atom != 16)
+        return fail(H4D_EINVAL, "lanes_per_atom must be 4, 8 or 16");
+    if (ck->rebuild_every < 1 || ck->clean_trials < 0 || ck->nbr_cap < 1 || ck->cell_cap < 1 ||
+        ck->nbr_cap % kMaxLanes != 0)
+        return fail(H4D_EINVAL, "invalid rebuild interval or list capacity");
+    if (ck->has_velocities && !vel) return fail(H4D_EINVAL, "the checkpoint carries momenta: vel is required");
+    int rc = read_ctl(s);
+    if (rc) return rc;
+    Ctl &c = s->h_ctl[0];
+    if (n_atoms != c.n) return fail(H4D_EINVAL, "n_atoms differs from the handle's state");
+    long long max_tag = -1;
+    if (c.n) {
+        std::vector<long long> tags(c.n);
+        HIPC(hipMemcpyAsync(tags.data(), s->a.ctag + s->box_h[0].a0, sizeof(long long) * c.n,
+                            hipMemcpyDeviceToHost, s->stream));
+        HIPC(hipStreamSynchronize(s->stream));
+        for (long long t : tags) max_tag = std::max(max_tag, t);
+    }
+    if (ck->next_tag <= max_tag) return fail(H4D_EINVAL, "next_tag must exceed every tag of the state");
+    KArgs &a = s->a;
+    // list capacities as the saved handle had them (the list layout follows them)
+    if (ck->nbr_cap != a.nbr_cap) {
+        s->release(a.nbr);
+        a.nbr_cap = ck->nbr_cap;
+        if ((rc = s->alloc(&a.nbr, nbr_elems(s)))) return rc;
+    }
+    if (ck->cell_cap != a.cell_cap) {
+        s->release(a.cell_atoms[0]);
+        s->release(a.cell_atoms[1]);
+        a.cell_cap = ck->cell_cap;
+        if ((rc = s->alloc(&a.cell_atoms[0], (size_t)a.ncell_total * a.cell_cap))) return rc;
+        if ((rc = s->alloc(&a.cell_atoms[1], (size_t)a.ncell_total * a.cell_cap))) return rc;
+    }
+    set_lanes(s, ck->lanes_per_atom);
+    s->drop_graphs();
+    s->rebuild_every = ck->rebuild_every;
+    s->clean_trials = ck->clean_trials;
+    s->interval_tuned = ck->interval_tuned != 0;
+    if (ck->has_velocities && c.n) {
+        std::vector<double4> buf(c.n);
+        for (int i = 0; i < c.n; ++i) buf[i] = make_double4(vel[3 * i], vel[3 * i + 1], vel[3 * i + 2], 0.0);
+        HIPC(hipMemcpyAsync(a.cvel + s->box_h[0].a0, buf.data(), sizeof(double4) * c.n, hipMemcpyHostToDevice,
+                            s->stream));
+        HIPC(hipStreamSynchronize(s->stream));
+    }
+    s->vel_canonical = ck->has_velocities != 0;
+    c.trial = (long long)ck->trial;
+    c.md = (long long)ck->md_phases;
+    c.next_tag = ck->next_tag;
+    if ((rc = write_ctl(s))) return rc;
+    h4d_system::Stats &st = s->stats[0];
+    st.n_trials = ck->n_trials;
+    st.n_ins = ck->n_ins;
+    st.n_ins_acc = ck->n_ins_acc;
+    st.n_del = ck->n_del;
+    st.n_del_acc = ck->n_del_acc;
+    st.N_sum = ck->N_sum;
+    st.N2_sum = ck->N2_sum;
+    return h4d_build_neighbors(s);
+}
+
 int32_t h4d_get_state(h4d_system *s, int32_t cap, int32_t *n, int32_t *n_salt, double *pos, double *vel,
                       int32_t *type, int32_t *mol, int64_t *tag) {
     return box_state(s, 0, cap, n, n_salt, pos, vel, type, mol, tag);

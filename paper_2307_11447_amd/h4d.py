@@ -47,6 +47,17 @@ class Params(C.Structure):
     ]
 
 
+class Checkpoint(C.Structure):
+    _fields_ = [
+        ("params", Params), ("trial", C.c_uint64), ("md_phases", C.c_uint64), ("next_tag", C.c_int64),
+        ("lanes_per_atom", C.c_int32), ("rebuild_every", C.c_int32), ("clean_trials", C.c_int32),
+        ("interval_tuned", C.c_int32), ("nbr_cap", C.c_int32), ("cell_cap", C.c_int32),
+        ("has_velocities", C.c_int32), ("reserved", C.c_int32),
+        ("n_trials", C.c_int64), ("n_ins", C.c_int64), ("n_ins_acc", C.c_int64), ("n_del", C.c_int64),
+        ("n_del_acc", C.c_int64), ("N_sum", C.c_double), ("N2_sum", C.c_double),
+    ]
+
+
 class Trial(C.Structure):
     _fields_ = [
         ("move", C.c_int32), ("accepted", C.c_int32), ("n_salt_before", C.c_int32),
@@ -152,6 +163,8 @@ def lib() -> C.CDLL:
         L.h4d_set_bias.argtypes = [vp, C.c_double, C.c_double]
         L.h4d_run_md.argtypes = [vp, C.c_int32, C.POINTER(Trial)]
         L.h4d_set_early_rejection.argtypes = [vp, C.c_double]
+        L.h4d_save_checkpoint.argtypes = [vp, C.POINTER(Checkpoint)]
+        L.h4d_restore_checkpoint.argtypes = [vp, C.POINTER(Checkpoint), C.c_int32, dp]
         for name in ("h4d_stream_copy", "h4d_set_timing", "h4d_get_timing", "h4d_init_system", "h4d_build_neighbors",
                      "h4d_run_nemd_trial", "h4d_run_trials", "h4d_sample_observables", "h4d_get_state",
                      "h4d_set_trial_index", "h4d_forces_at", "h4d_destroy", "h4d_init_batch", "h4d_num_boxes",
@@ -159,7 +172,8 @@ def lib() -> C.CDLL:
                      "h4d_mlp_create", "h4d_mlp_destroy", "h4d_mlp_set_weights", "h4d_mlp_get_weights",
                      "h4d_mlp_forward", "h4d_mlp_loss_grad", "h4d_mlp_train", "h4d_set_proposal",
                      "h4d_last_site_features", "h4d_last_candidates", "h4d_site_features", "h4d_set_beta_mu",
-                     "h4d_init_speculative", "h4d_run_speculative", "h4d_set_bias", "h4d_run_md", "h4d_set_early_rejection"):
+                     "h4d_init_speculative", "h4d_run_speculative", "h4d_set_bias", "h4d_run_md", "h4d_set_early_rejection",
+                     "h4d_save_checkpoint", "h4d_restore_checkpoint"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -456,15 +470,18 @@ class Speculative(_Handle):
 class System(_Handle):
     """One simulation box on the GPU."""
 
-    def __init__(self, params: dict, x, type_, mol, tag, nsalt: int, n_mol: int = 0, stream=None):
+    def __init__(self, params, x, type_, mol, tag, nsalt: int, n_mol: int = 0, stream=None):
+        """params: a dict for make_params, or a Params structure as it is."""
         self._h = None
-        self.params = dict(params)
+        raw = isinstance(params, Params)
+        self.params = {k: getattr(params, k) for k, _ in params._fields_} if raw else dict(params)
+        self.n_mol = n_mol
         x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 3)
         t = np.ascontiguousarray(type_, dtype=np.int32)
         m = np.ascontiguousarray(mol, dtype=np.int32)
         g = np.ascontiguousarray(tag, dtype=np.int64)
         h = C.c_void_p()
-        p = make_params(params)
+        p = params if raw else make_params(params)
         _check(lib().h4d_init_system(
             C.byref(p), len(t), nsalt, n_mol,
             x.ctypes.data_as(C.POINTER(C.c_double)), t.ctypes.data_as(C.POINTER(C.c_int32)),
@@ -482,6 +499,34 @@ class System(_Handle):
         r = Trial()
         _check(lib().h4d_run_nemd_trial(self._h, move, C.byref(r)))
         return r.as_dict()
+
+    def checkpoint(self) -> dict:
+        """The chain's atoms and counters as numpy arrays (np.savez stores
+        them without pickling); System.resume continues the chain from them."""
+        ck = Checkpoint()
+        _check(lib().h4d_save_checkpoint(self._h, C.byref(ck)))
+        st = self.state()
+        return {"checkpoint": np.frombuffer(bytes(ck), np.uint8).copy(), "x": st["x"], "v": st["v"],
+                "type": st["type"], "mol": st["mol"], "tag": st["tag"], "nsalt": np.int64(st["nsalt"]),
+                "n_mol": np.int64(self.n_mol)}
+
+    @classmethod
+    def resume(cls, ckpt, stream=None):
+        """A new handle that continues the chain saved by checkpoint()."""
+        raw = np.ascontiguousarray(ckpt["checkpoint"], dtype=np.uint8).tobytes()
+        if len(raw) != C.sizeof(Checkpoint):
+            raise ValueError("checkpoint record of the wrong size")
+        ck = Checkpoint.from_buffer_copy(raw)
+        sysm = cls(ck.params, ckpt["x"], ckpt["type"], ckpt["mol"], ckpt["tag"], int(ckpt["nsalt"]),
+                   int(ckpt["n_mol"]), stream=stream)
+        v = np.ascontiguousarray(ckpt["v"], dtype=np.float64).reshape(-1, 3)
+        try:
+            _check(lib().h4d_restore_checkpoint(sysm._h, C.byref(ck), len(v),
+                                                v.ctypes.data_as(C.POINTER(C.c_double))))
+        except H4DError:
+            sysm.close()
+            raise
+        return sysm
 
     def trials(self, n: int, move: int = MOVE_AUTO, as_array: bool = False):
         recs = (Trial * max(n, 1))()

@@ -41,9 +41,10 @@ def test_struct_layouts_match_header():
 #include <stddef.h>
 #include "h4d.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(h4d_params), sizeof(h4d_trial), sizeof(h4d_observables),
-         offsetof(h4d_params, seed), offsetof(h4d_trial, dH), offsetof(h4d_observables, U),
-         sizeof(h4d_timing), offsetof(h4d_trial, trial));
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(h4d_params), sizeof(h4d_trial),
+         sizeof(h4d_observables), offsetof(h4d_params, seed), offsetof(h4d_trial, dH), offsetof(h4d_observables, U),
+         sizeof(h4d_timing), offsetof(h4d_trial, trial), sizeof(h4d_checkpoint), offsetof(h4d_checkpoint, trial),
+         offsetof(h4d_checkpoint, n_trials));
   return 0;
 }
 '''
@@ -55,7 +56,8 @@ int main(void) {
         vals = [int(v) for v in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()]
     assert vals == [C.sizeof(h4d.Params), C.sizeof(h4d.Trial), C.sizeof(h4d.Observables),
                     h4d.Params.seed.offset, h4d.Trial.dH.offset, h4d.Observables.U.offset,
-                    C.sizeof(h4d.Timing), h4d.Trial.trial.offset]
+                    C.sizeof(h4d.Timing), h4d.Trial.trial.offset, C.sizeof(h4d.Checkpoint),
+                    h4d.Checkpoint.trial.offset, h4d.Checkpoint.n_trials.offset]
 
 
 def test_invalid_parameters_are_rejected_before_any_device_work():

@@ -1,0 +1,116 @@
+"""Checkpoint and resume: a handle created from a saved state and its
+counters continues the chain with the records, states and running sums of
+the uninterrupted run, bitwise (FP32 forces, carried momenta with
+equilibrium phases, rigid water)."""
+import os
+import sys
+import tempfile
+
+import numpy as np
+import pytest
+
+from paper_2307_11447_amd import h4d
+from paper_2307_11447_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def same(ra, rb, what):
+    assert ra.keys() == rb.keys()
+    for k in ra:
+        a, b = ra[k], rb[k]
+        assert a == b or (a != a and b != b), (what, k, a, b)
+
+
+def same_state(sa, sb):
+    assert sa["n"] == sb["n"] and sa["nsalt"] == sb["nsalt"]
+    for k in ("x", "v", "type", "mol", "tag"):
+        assert np.array_equal(sa[k], sb[k]), k
+
+
+def run(g, plan):
+    """plan: a sequence of "t" (one trial) and integers (a phase of that many
+    steps); the records in order."""
+    out = []
+    for step in plan:
+        out.append(g.trial() if step == "t" else g.md_phase(step)[0])
+    return out
+
+
+def through_file(ck):
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "ck.npz")
+        np.savez(path, **ck)
+        with np.load(path) as f:          # no pickled objects in the file
+            return {k: f[k] for k in f.files}
+
+
+@pytest.mark.parametrize("case", ["fp32", "momenta", "water"])
+def test_resumed_chain_equals_the_uninterrupted_run(case):
+    if case == "fp32":
+        w = W.lj_electrolyte(400, 0.1, 4301, n_steps=40, precision="fp32")
+        w.params.update(beta_mu=10.0)
+        before, after = ["t"] * 10, ["t"] * 10
+    elif case == "momenta":
+        w = W.lj_electrolyte(400, 0.1, 4302, n_steps=20, precision="fp64")
+        w.params.update(beta_mu=10.0, momenta=1, md_refresh=0.5)
+        before, after = [10, "t", 10, "t", "t"], [10, "t", "t", 10, "t"]
+    else:
+        w = W.water_nacl(n_water=300, n_pairs=10, L=21.0, m=7, seed=4303)
+        w.params.update(precision="fp32")
+        before, after = ["t"] * 4, ["t"] * 4
+    say(f"case checkpoint {case}: {w.n} atoms, {len(before)} steps before, {len(after)} after")
+    g = h4d.System.from_workload(w)
+    pre = run(g, before)
+    ck = through_file(g.checkpoint())
+    raw = h4d.Checkpoint.from_buffer_copy(ck["checkpoint"].tobytes())
+    ins = sum(1 for x in pre if x["move"] == 1 and x["accepted"])
+    assert raw.next_tag == int(w.tag.max()) + 1 + 2 * ins
+    assert raw.trial == sum(1 for x in before if x == "t")
+    assert raw.md_phases == sum(1 for x in before if x != "t")
+    ref = run(g, after)
+    ref_state, ref_obs = g.state(), g.observables()
+    g.close()
+    r = h4d.System.resume(ck)
+    got = run(r, after)
+    for q, (a, b) in enumerate(zip(ref, got)):
+        same(a, b, f"{case} step {q}")
+    same_state(ref_state, r.state())
+    same(ref_obs, r.observables(), f"{case} observables")
+    say(f"   {sum(x['accepted'] for x in pre)} of {len(pre)} accepted before the checkpoint, "
+        f"{sum(x['accepted'] for x in ref)} of {len(ref)} after")
+    r.close()
+
+
+def test_restore_rejects_a_mismatched_handle():
+    w = W.lj_electrolyte(300, 0.1, 4304, n_steps=10, precision="fp64")
+    g = h4d.System.from_workload(w)
+    g.trials(2)
+    ck = g.checkpoint()
+    g.close()
+    # another seed: the chain would not continue
+    ckb = dict(ck)
+    raw = h4d.Checkpoint.from_buffer_copy(ck["checkpoint"].tobytes())
+    other = h4d.System(dict(w.params, seed=w.params["seed"] + 1), ck["x"], ck["type"], ck["mol"], ck["tag"],
+                       int(ck["nsalt"]))
+    with pytest.raises(h4d.H4DError) as e:
+        h4d._check(h4d.lib().h4d_restore_checkpoint(other._h, raw, len(ck["x"]), None))
+    assert e.value.code == h4d.H4D_EINVAL
+    other.close()
+    # a next tag that an atom of the state already holds
+    raw.next_tag = int(ck["tag"].max())
+    ckb["checkpoint"] = np.frombuffer(bytes(raw), np.uint8).copy()
+    with pytest.raises(h4d.H4DError) as e:
+        h4d.System.resume(ckb)
+    assert e.value.code == h4d.H4D_EINVAL
+    # checkpoints serve single-box handles
+    sp = h4d.Speculative.from_workload(w, 2)
+    with pytest.raises(h4d.H4DError) as e:
+        h4d._check(h4d.lib().h4d_save_checkpoint(sp._h, h4d.Checkpoint()))
+    assert e.value.code == h4d.H4D_EINVAL
+    sp.close()
