@@ -224,7 +224,12 @@ int32_t h4d_build_neighbors(h4d_system *sys);
  * t+1, ...) draws its move, sites and momenta from the generator, runs the
  * NEMD trajectory and the Metropolis test (Eqs. 6 and 8 with Lambda_s),
  * and commits or rolls back.  out[n] receives the records (host memory).
- * move forces every trial's direction (H4D_MOVE_*).
+ * move forces every trial's direction (H4D_MOVE_*).  Lists that overflow
+ * during a trial grow and the trial is recomputed (H4D_FLAG_RETRIED), with
+ * the same result.  An insertion into a box at its atom capacity returns
+ * H4D_ECAPACITY before any device state changes: the state, the running sums
+ * and the trial counter stay as they were, so the next call runs the same
+ * trial index (a deletion fits).
  */
 int32_t h4d_run_nemd_trial(h4d_system *sys, int32_t move, h4d_trial *out);
 int32_t h4d_run_trials(h4d_system *sys, int32_t n, int32_t move, h4d_trial *out);
