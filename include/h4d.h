@@ -312,7 +312,8 @@ int32_t h4d_get_box_state(h4d_system *sys, int32_t box, int32_t cap, int32_t *n,
                           int32_t *mol, int64_t *tag);
 
 /*
- * Checkpoint and resume of a single-box chain.  The chain has no hidden
+ * Checkpoint and resume of one chain (a single-box or a speculative handle;
+ * not a batch).  The chain has no hidden
  * generator state: every random number is a Philox draw keyed by (seed,
  * stream) and counted by the trial index, the equilibrium-phase index and the
  * ions' tags (the trial sequence of Sec. II A and the phase of Fig. 1).  So
@@ -322,8 +323,11 @@ int32_t h4d_get_box_state(h4d_system *sys, int32_t box, int32_t cap, int32_t *n,
  * checkpoint carries.
  *
  * Resume: h4d_init_system(&ck.params, n, n_salt, n_mol, pos, type, mol, tag,
- * stream, &sys) with the arrays of h4d_get_state, then
- * h4d_restore_checkpoint(sys, &ck, n, vel).  A learned proposal is not part
+ * stream, &sys) with the arrays of h4d_get_state, or h4d_init_speculative
+ * with the same arrays, then h4d_restore_checkpoint(sys, &ck, n, vel).  A
+ * chain saved from one kind of handle resumes on the other; its records are
+ * then those of the uninterrupted run as the speculative trials guarantee
+ * (bitwise with a fixed rebuild interval).  A learned proposal is not part
  * of the checkpoint: save its network with h4d_mlp_get_weights and apply it
  * again with h4d_set_proposal.
  */
@@ -345,13 +349,13 @@ typedef struct h4d_checkpoint {
     double N_sum, N2_sum;     /* running sums behind h4d_sample_observables   */
 } h4d_checkpoint;
 
-/* Fill *ck from a single-box handle (H4D_EINVAL for batches and speculative
- * handles).  Synchronizes the handle's stream. */
+/* Fill *ck from a single-box or speculative handle (H4D_EINVAL for a
+ * batch).  Synchronizes the handle's stream. */
 int32_t h4d_save_checkpoint(h4d_system *sys, h4d_checkpoint *ck);
 /* Apply *ck to a handle just created from the checkpoint's parameters and
  * the state saved with it.  n_atoms: the state's atom count (checked); vel:
  * host array n_atoms x 3 of the state's momenta (required when
- * ck->has_velocities, else ignored; copied).  Errors: H4D_EINVAL for a
+ * ck->has_velocities, else ignored; copied to every replica).  Errors: H4D_EINVAL for a
  * handle whose seed, stream, precision, momenta mode, type count or water
  * flag differ from the checkpoint's, an atom-count mismatch, next_tag not
  * above every tag of the state, or invalid shape or capacities; the handle

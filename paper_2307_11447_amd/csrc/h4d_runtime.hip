@@ -1294,11 +1294,11 @@ int32_t h4d_set_trial_index(h4d_system *s, uint64_t trial) {
 
 int32_t h4d_save_checkpoint(h4d_system *s, h4d_checkpoint *out) {
     if (!s || !out) return fail(H4D_EINVAL, "null argument");
-    if (s->nbox != 1 || s->speculative) return fail(H4D_EINVAL, "checkpoints serve single-box systems");
+    if (s->nbox != 1 && !s->speculative) return fail(H4D_EINVAL, "checkpoints serve single chains, not batches");
     int rc = read_ctl(s);
     if (rc) return rc;
-    const Ctl &c = s->h_ctl[0];
-    const h4d_system::Stats &st = s->stats[0];
+    const Ctl &c = s->h_ctl[0];     // (replicas hold the chain's state between calls)
+    const h4d_system::Stats &st = s->speculative ? s->chain : s->stats[0];
     std::memset(out, 0, sizeof(*out));
     out->params = s->p;
     out->trial = (uint64_t)c.trial;
@@ -1323,7 +1323,7 @@ int32_t h4d_save_checkpoint(h4d_system *s, h4d_checkpoint *out) {
 
 int32_t h4d_restore_checkpoint(h4d_system *s, const h4d_checkpoint *ck, int32_t n_atoms, const double *vel) {
     if (!s || !ck) return fail(H4D_EINVAL, "null argument");
-    if (s->nbox != 1 || s->speculative) return fail(H4D_EINVAL, "checkpoints serve single-box systems");
+    if (s->nbox != 1 && !s->speculative) return fail(H4D_EINVAL, "checkpoints serve single chains, not batches");
     const h4d_params &q = ck->params;
     if (q.seed != s->p.seed || q.stream != s->p.stream || q.precision != s->p.precision ||
         q.momenta != s->p.momenta || q.n_types != s->p.n_types || q.water != s->p.water)
@@ -1337,7 +1337,8 @@ int32_t h4d_restore_checkpoint(h4d_system *s, const h4d_checkpoint *ck, int32_t 
     int rc = read_ctl(s);
     if (rc) return rc;
     Ctl &c = s->h_ctl[0];
-    if (n_atoms != c.n) return fail(H4D_EINVAL, "n_atoms differs from the handle's state");
+    for (int b = 0; b < s->nbox; ++b)
+        if (n_atoms != s->h_ctl[b].n) return fail(H4D_EINVAL, "n_atoms differs from the handle's state");
     long long max_tag = -1;
     if (c.n) {
         std::vector<long long> tags(c.n);
@@ -1369,16 +1370,13 @@ int32_t h4d_restore_checkpoint(h4d_system *s, const h4d_checkpoint *ck, int32_t 
     if (ck->has_velocities && c.n) {
         std::vector<double4> buf(c.n);
         for (int i = 0; i < c.n; ++i) buf[i] = make_double4(vel[3 * i], vel[3 * i + 1], vel[3 * i + 2], 0.0);
-        HIPC(hipMemcpyAsync(a.cvel + s->box_h[0].a0, buf.data(), sizeof(double4) * c.n, hipMemcpyHostToDevice,
-                            s->stream));
+        for (int b = 0; b < s->nbox; ++b)   // every replica of a speculative handle
+            HIPC(hipMemcpyAsync(a.cvel + s->box_h[b].a0, buf.data(), sizeof(double4) * c.n,
+                                hipMemcpyHostToDevice, s->stream));
         HIPC(hipStreamSynchronize(s->stream));
     }
     s->vel_canonical = ck->has_velocities != 0;
-    c.trial = (long long)ck->trial;
-    c.md = (long long)ck->md_phases;
-    c.next_tag = ck->next_tag;
-    if ((rc = write_ctl(s))) return rc;
-    h4d_system::Stats &st = s->stats[0];
+    h4d_system::Stats st;
     st.n_trials = ck->n_trials;
     st.n_ins = ck->n_ins;
     st.n_ins_acc = ck->n_ins_acc;
@@ -1386,6 +1384,15 @@ int32_t h4d_restore_checkpoint(h4d_system *s, const h4d_checkpoint *ck, int32_t 
     st.n_del_acc = ck->n_del_acc;
     st.N_sum = ck->N_sum;
     st.N2_sum = ck->N2_sum;
+    for (int b = 0; b < s->nbox; ++b) {
+        Ctl &cb = s->h_ctl[b];
+        cb.trial = (long long)ck->trial;
+        cb.md = (long long)ck->md_phases;
+        cb.next_tag = ck->next_tag;
+        s->stats[b] = st;
+    }
+    s->chain = st;
+    if ((rc = write_ctl(s))) return rc;
     return h4d_build_neighbors(s);
 }
 

@@ -426,20 +426,54 @@ class Batch(_Handle):
         return [[recs[b * trials_per_box + q].as_dict() for q in range(trials_per_box)] for b in range(self.nb)]
 
 
-class Speculative(_Handle):
+def _checkpoint_record(ckpt) -> Checkpoint:
+    raw = np.ascontiguousarray(ckpt["checkpoint"], dtype=np.uint8).tobytes()
+    if len(raw) != C.sizeof(Checkpoint):
+        raise ValueError("checkpoint record of the wrong size")
+    return Checkpoint.from_buffer_copy(raw)
+
+
+def _restore(handle, ck: Checkpoint, ckpt):
+    v = np.ascontiguousarray(ckpt["v"], dtype=np.float64).reshape(-1, 3)
+    try:
+        _check(lib().h4d_restore_checkpoint(handle._h, C.byref(ck), len(v), v.ctypes.data_as(C.POINTER(C.c_double))))
+    except H4DError:
+        handle.close()
+        raise
+    return handle
+
+
+class _Chain(_Handle):
+    """A single chain (one box, or speculative replicas of one box)."""
+
+    def checkpoint(self) -> dict:
+        """The chain's atoms and counters as numpy arrays (np.savez stores
+        them without pickling); resume() continues the chain from them."""
+        ck = Checkpoint()
+        _check(lib().h4d_save_checkpoint(self._h, C.byref(ck)))
+        st = self.state()
+        return {"checkpoint": np.frombuffer(bytes(ck), np.uint8).copy(), "x": st["x"], "v": st["v"],
+                "type": st["type"], "mol": st["mol"], "tag": st["tag"], "nsalt": np.int64(st["nsalt"]),
+                "n_mol": np.int64(self.n_mol)}
+
+
+class Speculative(_Chain):
     """One chain run speculatively on `replicas` copies of its state: a
     round runs the next `replicas` trials side by side and keeps them up to
     the first accepted one (the records equal a one-by-one run)."""
 
-    def __init__(self, params: dict, replicas: int, x, type_, mol, tag, nsalt: int, n_mol: int = 0, stream=None):
+    def __init__(self, params, replicas: int, x, type_, mol, tag, nsalt: int, n_mol: int = 0, stream=None):
+        """params: a dict for make_params, or a Params structure as it is."""
         self._h = None
-        self.params = dict(params)
+        raw = isinstance(params, Params)
+        self.params = {k: getattr(params, k) for k, _ in params._fields_} if raw else dict(params)
+        self.n_mol = n_mol
         x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 3)
         t = np.ascontiguousarray(type_, dtype=np.int32)
         m = np.ascontiguousarray(mol, dtype=np.int32)
         g = np.ascontiguousarray(tag, dtype=np.int64)
         h = C.c_void_p()
-        p = make_params(params)
+        p = params if raw else make_params(params)
         _check(lib().h4d_init_speculative(
             C.byref(p), replicas, len(t), nsalt, n_mol, x.ctypes.data_as(C.POINTER(C.c_double)),
             t.ctypes.data_as(C.POINTER(C.c_int32)), m.ctypes.data_as(C.POINTER(C.c_int32)),
@@ -447,6 +481,14 @@ class Speculative(_Handle):
         self._h = h
         self.replicas = replicas
         self.rounds = 0
+
+    @classmethod
+    def resume(cls, ckpt, replicas: int, stream=None):
+        """Speculative replicas that continue the chain saved by checkpoint()
+        (of a System or of a Speculative handle)."""
+        ck = _checkpoint_record(ckpt)
+        return _restore(cls(ck.params, replicas, ckpt["x"], ckpt["type"], ckpt["mol"], ckpt["tag"],
+                            int(ckpt["nsalt"]), int(ckpt["n_mol"]), stream=stream), ck, ckpt)
 
     @classmethod
     def from_workload(cls, w, replicas: int, **overrides):
@@ -467,7 +509,7 @@ class Speculative(_Handle):
         return _state_of(self._h, 0)
 
 
-class System(_Handle):
+class System(_Chain):
     """One simulation box on the GPU."""
 
     def __init__(self, params, x, type_, mol, tag, nsalt: int, n_mol: int = 0, stream=None):
@@ -495,38 +537,19 @@ class System(_Handle):
         params.update(overrides)
         return cls(params, w.x, w.type, w.mol, w.tag, w.nsalt, w.n_mol)
 
+    @classmethod
+    def resume(cls, ckpt, stream=None):
+        """A new handle that continues the chain saved by checkpoint() (of a
+        System or of a Speculative handle)."""
+        ck = _checkpoint_record(ckpt)
+        return _restore(cls(ck.params, ckpt["x"], ckpt["type"], ckpt["mol"], ckpt["tag"], int(ckpt["nsalt"]),
+                            int(ckpt["n_mol"]), stream=stream), ck, ckpt)
+
     def trial(self, move: int = MOVE_AUTO) -> dict:
         r = Trial()
         _check(lib().h4d_run_nemd_trial(self._h, move, C.byref(r)))
         return r.as_dict()
 
-    def checkpoint(self) -> dict:
-        """The chain's atoms and counters as numpy arrays (np.savez stores
-        them without pickling); System.resume continues the chain from them."""
-        ck = Checkpoint()
-        _check(lib().h4d_save_checkpoint(self._h, C.byref(ck)))
-        st = self.state()
-        return {"checkpoint": np.frombuffer(bytes(ck), np.uint8).copy(), "x": st["x"], "v": st["v"],
-                "type": st["type"], "mol": st["mol"], "tag": st["tag"], "nsalt": np.int64(st["nsalt"]),
-                "n_mol": np.int64(self.n_mol)}
-
-    @classmethod
-    def resume(cls, ckpt, stream=None):
-        """A new handle that continues the chain saved by checkpoint()."""
-        raw = np.ascontiguousarray(ckpt["checkpoint"], dtype=np.uint8).tobytes()
-        if len(raw) != C.sizeof(Checkpoint):
-            raise ValueError("checkpoint record of the wrong size")
-        ck = Checkpoint.from_buffer_copy(raw)
-        sysm = cls(ck.params, ckpt["x"], ckpt["type"], ckpt["mol"], ckpt["tag"], int(ckpt["nsalt"]),
-                   int(ckpt["n_mol"]), stream=stream)
-        v = np.ascontiguousarray(ckpt["v"], dtype=np.float64).reshape(-1, 3)
-        try:
-            _check(lib().h4d_restore_checkpoint(sysm._h, C.byref(ck), len(v),
-                                                v.ctypes.data_as(C.POINTER(C.c_double))))
-        except H4DError:
-            sysm.close()
-            raise
-        return sysm
 
     def trials(self, n: int, move: int = MOVE_AUTO, as_array: bool = False):
         recs = (Trial * max(n, 1))()

@@ -108,9 +108,39 @@ def test_restore_rejects_a_mismatched_handle():
     with pytest.raises(h4d.H4DError) as e:
         h4d.System.resume(ckb)
     assert e.value.code == h4d.H4D_EINVAL
-    # checkpoints serve single-box handles
-    sp = h4d.Speculative.from_workload(w, 2)
+    # checkpoints serve single chains, not batches
+    bat = h4d.Batch.from_workloads([w, W.lj_electrolyte(300, 0.1, 4305, n_steps=10, precision="fp64")])
     with pytest.raises(h4d.H4DError) as e:
-        h4d._check(h4d.lib().h4d_save_checkpoint(sp._h, h4d.Checkpoint()))
+        h4d._check(h4d.lib().h4d_save_checkpoint(bat._h, h4d.Checkpoint()))
     assert e.value.code == h4d.H4D_EINVAL
+    bat.close()
+
+
+def test_checkpoint_moves_between_one_by_one_and_speculative_runs():
+    say("case checkpoint across handle kinds: lj1000 fp32, 4 replicas, 3 x 12 trials")
+    w = W.lj_electrolyte(1000, 0.3, 4306, n_steps=40, precision="fp32")
+    w.params.update(beta_mu=-5.0, rebuild_every=10, lanes_per_atom=8, capacity=w.n + 256)
+    T = 12
+    seq = h4d.System.from_workload(w)
+    first = seq.trials(T)
+    ck = through_file(seq.checkpoint())
+    ref = seq.trials(2 * T)
+    ref_state = seq.state()
+    seq.close()
+    # one-by-one -> speculative
+    sp = h4d.Speculative.resume(ck, 4)
+    got = sp.trials(T)
+    for a, b in zip(ref[:T], got):
+        same(dict(a, n_rebuilds=0), dict(b, n_rebuilds=0), f"speculative trial {a['trial']}")
+    # speculative -> one-by-one
+    ck2 = through_file(sp.checkpoint())
     sp.close()
+    r = h4d.System.resume(ck2)
+    got2 = r.trials(T)
+    for a, b in zip(ref[T:], got2):
+        same(dict(a, n_rebuilds=0), dict(b, n_rebuilds=0), f"resumed trial {a['trial']}")
+    same_state(dict(ref_state, v=0), dict(r.state(), v=0))
+    acc = [sum(x["accepted"] for x in part) for part in (first, ref[:T], ref[T:])]
+    say(f"   accepted {acc[0]}, {acc[1]}, {acc[2]} of {T} in the three parts")
+    assert sum(acc[1:]) > 0
+    r.close()
