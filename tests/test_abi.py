@@ -7,6 +7,7 @@ import re
 import subprocess
 import tempfile
 
+import numpy as np
 import pytest
 
 from paper_2307_11447_amd import h4d
@@ -94,3 +95,10 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=300)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_checkpoint_record_of_the_wrong_size_is_refused():
+    good = np.zeros(C.sizeof(h4d.Checkpoint), np.uint8)
+    assert isinstance(h4d._checkpoint_record({"checkpoint": good}), h4d.Checkpoint)
+    with pytest.raises(ValueError):
+        h4d._checkpoint_record({"checkpoint": good[:-8]})
