@@ -128,7 +128,9 @@ typedef struct h4d_params {
                                    momenta; 1: trials carry the state's momenta
                                    with the symmetric two-end reversal (Sec.
                                    II A), to alternate with h4d_run_md (ions
-                                   only; not with speculative replicas)         */
+                                   only).  Speculative replicas start from
+                                   the chain's momenta times the reversal
+                                   signs of the trials before theirs         */
     double md_refresh;          /* c in [0, 1] of the equilibrium phase's
                                    momentum refresh, see h4d_run_md             */
     double w_max_ratio;         /* species-specific w_max (the supplement's

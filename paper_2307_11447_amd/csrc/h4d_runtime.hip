@@ -720,9 +720,13 @@ int set_quota(h4d_system *s, long long count) {
     return read_ctl(s);
 }
 
-int run_batch(h4d_system *s, int T, int move, h4d_trial *out) {
+int run_batch(h4d_system *s, int T, int move, h4d_trial *out, int active = -1) {
     int rc = set_quota(s, T);
     if (rc) return rc;
+    if (active >= 0 && active < s->nbox) {   // boxes from `active` on sit this batch out
+        for (int b = active; b < s->nbox; ++b) s->h_ctl[b].trial_end = s->h_ctl[b].trial;
+        if ((rc = write_ctl(s))) return rc;
+    }
     std::vector<long long> first(s->nbox);
     std::vector<char> retried(s->nbox, 0);
     for (int b = 0; b < s->nbox; ++b) first[b] = s->h_ctl[b].trial;
@@ -765,6 +769,23 @@ int run_batch(h4d_system *s, int T, int move, h4d_trial *out) {
         }
     }
     return set_quota(s, -1);
+}
+
+// Carried momenta on speculative replicas: replica b runs trial t0 + b, which
+// follows b rejected trials of the chain.  Each of those reversed the
+// momenta by the product of its two reversal signs (a trial with a pair to
+// delete, or any insertion, moves), so the replica starts from the chain's
+// momenta times those b products.
+__global__ __launch_bounds__(kBlock) void k_spec_momenta(KArgs a, long long t0) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= a.slots) return;
+    const int bi = box_of_slot(a, i);
+    const Box &B = a.box[bi];
+    if (bi == 0 || i - B.a0 >= a.ctl[bi].n) return;
+    double sgn = 1.0;
+    for (int j = 0; j < bi; ++j) sgn *= reversal_sign(a, B, t0 + j, 0) * reversal_sign(a, B, t0 + j, 1);
+    const double4 v = a.cvel[i];
+    a.cvel[i] = make_double4(sgn * v.x, sgn * v.y, sgn * v.z, v.w);
 }
 
 // One equilibrium phase of every box (its records in out[b]); a box whose
@@ -841,8 +862,6 @@ int create(const h4d_params *params, int nbox, const double *edges, const int32_
     if (total > 0 && (!pos || !type || !tag)) return fail(H4D_EINVAL, "null configuration array");
     if (params->water && nbox != 1 && !speculative)
         return fail(H4D_EINVAL, "rigid water needs a single box (or speculative replicas)");
-    if (params->momenta && speculative)
-        return fail(H4D_EINVAL, "carried momenta need trials one after another (no speculative replicas)");
     const double rc_max = std::max(params->rc_lj, params->rc_coul);
     for (int q = 0; q < 3 * nbox; ++q)
         if (!(edges[q] >= 2.0 * rc_max)) return fail(H4D_EINVAL, "every box edge must be at least twice the largest cutoff");
@@ -1167,17 +1186,26 @@ int32_t h4d_run_speculative(h4d_system *s, int32_t n_trials, int32_t move, h4d_t
     if (rc) return rc;
     long long t0 = s->h_ctl[0].trial;
     int done = 0, rounds = 0;
+    const bool carry = s->p.momenta != 0;
     while (done < n_trials) {
+        // With carried momenta and no salt, a drawn deletion makes no move
+        // and no reversal, so the replicas' start momenta are not known in
+        // advance: such a round runs the first replica alone.
+        const int Ka = (carry && s->nsalt_host[0] == 0) ? 1 : K;
         // replica b runs trial t0 + b of the chain from the chain's state
         for (int b = 0; b < K; ++b) s->h_ctl[b].trial = t0 + b;
         if ((rc = write_ctl(s))) return rc;
-        if ((rc = run_batch(s, 1, move, recs.data()))) return rc;
+        if (carry && Ka > 1) {
+            hipLaunchKernelGGL(k_spec_momenta, dim3(slot_blocks(s)), dim3(kBlock), 0, s->stream, s->a, t0);
+            HIPC(hipGetLastError());
+        }
+        if ((rc = run_batch(s, 1, move, recs.data(), Ka))) return rc;
         ++rounds;
         // the chain's trials: up to and including the first accepted one
         bool any = false;
-        for (int b = 0; b < K; ++b) any |= recs[b].accepted != 0;
+        for (int b = 0; b < Ka; ++b) any |= recs[b].accepted != 0;
         int m = 0;
-        while (m < K && done + m < n_trials) {
+        while (m < Ka && done + m < n_trials) {
             const h4d_trial &r = recs[m];
             out[done + m] = r;
             h4d_system::Stats &st = s->chain;
@@ -1189,7 +1217,9 @@ int32_t h4d_run_speculative(h4d_system *s, int32_t n_trials, int32_t move, h4d_t
             ++m;
             if (r.accepted) break;
         }
-        if (any) {   // every replica takes the state after the chain's last trial
+        if (any || (carry && K > 1)) {   // every replica takes the state after the chain's last trial
+            // (with carried momenta also after rejections: the momenta of
+            // the chain's last trial's replica carry all their reversals)
             const int src = m - 1;
             hipLaunchKernelGGL(k_broadcast_box, dim3(slot_blocks(s)), dim3(kBlock), 0, s->stream, s->a, src);
             HIPC(hipGetLastError());

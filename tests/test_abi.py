@@ -81,8 +81,8 @@ def test_momentum_options_are_validated_before_any_device_work():
         with pytest.raises(h4d.H4DError) as e:
             h4d.System(bad, w.x, w.type, w.mol, w.tag, w.nsalt, stream=C.c_void_p())
         assert e.value.code == h4d.H4D_EINVAL
-    with pytest.raises(h4d.H4DError) as e:   # replicas of one chain cannot carry momenta
-        h4d.Speculative(dict(w.params, momenta=1), 4, w.x, w.type, w.mol, w.tag, w.nsalt, stream=C.c_void_p())
+    with pytest.raises(h4d.H4DError) as e:   # carried momenta need an ion system
+        h4d.System(dict(w.params, momenta=1, water=1), w.x, w.type, w.mol, w.tag, w.nsalt, stream=C.c_void_p())
     assert e.value.code == h4d.H4D_EINVAL
 
 

@@ -131,3 +131,44 @@ def test_phase_refuses_rigid_water():
         g.md_phase(5)
     assert e.value.code == h4d.H4D_EINVAL
     g.close()
+
+
+def _run_plan(g, plan, speculative):
+    out = []
+    for step in plan:
+        if step == "md":
+            out.append(g.md_phase(10)[0])
+        else:
+            out.extend(g.trials(step))
+    return out
+
+
+@pytest.mark.parametrize("case", ["salt_bm10", "salt_bm2", "empty_ideal_gas"])
+def test_speculative_replicas_carry_momenta_like_one_by_one(case):
+    if case.startswith("salt"):
+        w = W.lj_electrolyte(400, 0.1, 4501, n_steps=20, precision="fp32")
+        w.params.update(beta_mu=10.0 if case == "salt_bm10" else 2.0, momenta=1, md_refresh=0.5,
+                        rebuild_every=10, lanes_per_atom=8, capacity=w.n + 256)
+        plan = ["md", 8, "md", 8, 8]
+    else:   # starts with no salt: rounds run one replica until an insertion is accepted
+        w = W.ideal_gas(L=6.0, beta_mu=0.0, n_steps=3)
+        w.params.update(momenta=1, md_refresh=0.5)
+        plan = [30, 10]
+    say(f"case carried momenta on 4 speculative replicas: {case}")
+    seq = h4d.System.from_workload(w)
+    sp = h4d.Speculative.from_workload(w, 4)
+    ra = _run_plan(seq, plan, False)
+    rb = _run_plan(sp, plan, True)
+    for q, (a, b) in enumerate(zip(ra, rb)):
+        assert a == dict(b, n_rebuilds=a["n_rebuilds"]), (q, a, b)
+    sa = seq.state()
+    for box in range(4):
+        sb = sp.box_state(box)
+        assert sa["n"] == sb["n"] and np.array_equal(sa["tag"], sb["tag"])
+        assert np.array_equal(sa["x"], sb["x"]) and np.array_equal(sa["v"], sb["v"]), box
+    acc = sum(r["accepted"] for r in ra if r["move"] != h4d.MOVE_MD)
+    n_tr = sum(1 for r in ra if r["move"] != h4d.MOVE_MD)
+    say(f"   {acc} of {n_tr} trials accepted; {sp.rounds} speculative rounds")
+    assert 0 < acc < n_tr
+    seq.close()
+    sp.close()
