@@ -270,12 +270,17 @@ int32_t h4d_run_batch(h4d_system *sys, int32_t trials_per_box, int32_t move, h4d
  * Speculative trials of ONE chain (the trial sequence of Sec. II A, Fig. 1,
  * unchanged).  A trial's outcome depends only on the state it starts from
  * and on its index (every random number is keyed by the index), and a
- * rejected trial leaves the state unchanged.  So `replicas` copies of the
+ * rejected trial leaves the positions unchanged.  So `replicas` copies of the
  * state can run trials t, t+1, ..., t+replicas-1 side by side: the results up
  * to and including the first accepted trial are the chain's, exactly as if
  * run one after another; the later ones are discarded and every copy takes
- * the accepted trial's state.  With acceptance probability p, a round yields
- * about (1 - (1-p)^replicas) / p trials.
+ * the state after the chain's last kept trial.  With carried momenta
+ * (h4d_params.momenta = 1) a rejected trial reverses the momenta by the
+ * product of its two reversal signs: copy b starts from the chain's momenta
+ * times the products of trials t .. t+b-1, and a round in a box with no salt
+ * (where a drawn deletion makes no move) runs the first copy alone.  With
+ * acceptance probability p, a round yields about (1 - (1-p)^replicas) / p
+ * trials.
  *
  * h4d_init_speculative: the handle, from one configuration with the same
  * arguments and conventions as h4d_init_system (rigid water included;
