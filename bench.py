@@ -437,6 +437,30 @@ def gcmd_leg(args, h4d, torch, w, beta_mu, tuned):
     n_tr = sum(r["accepted"] for r in tr_recs)
     steps = sum(r["n_atoms"] * (r["n_steps"] + 1) for r in md_recs + tr_recs)
     note(f"gcmd: {args.gcmd_cycles} cycles of {args.n_eq} equilibrium steps and one trial in {wall:.1f} s")
+    carried = None
+    if args.gcmd_trials > 0 and args.replicas > 1:
+        # runs of trials with carried momenta from the same state: one after
+        # another, and on speculative replicas (the same records when the
+        # launch shape and rebuild interval are fixed)
+        runs = {}
+        for kind in ("one_by_one", "speculative"):
+            h = (h4d.System.from_workload(w, **over) if kind == "one_by_one"
+                 else h4d.Speculative.from_workload(w, args.replicas, **over))
+            h.trials(4)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            recs = h.trials(args.gcmd_trials)
+            torch.cuda.synchronize()
+            runs[kind] = (recs, time.perf_counter() - t1, getattr(h, "rounds", None))
+            h.close()
+        (ra, wa, _), (rb, wb, rounds) = runs["one_by_one"], runs["speculative"]
+        same = all(a == dict(b, n_rebuilds=a["n_rebuilds"]) for a, b in zip(ra, rb)) if tuned else None
+        carried = {"trials": args.gcmd_trials, "replicas": args.replicas,
+                   "one_by_one_trials_per_s": len(ra) / wa, "speculative_trials_per_s": len(rb) / wb,
+                   "speedup": wa / max(wb, 1e-300), "accepted": sum(r["accepted"] for r in rb),
+                   "records_equal": same}
+        note(f"gcmd: {args.gcmd_trials} carried-momentum trials, one by one {wa:.1f} s, on {args.replicas} "
+             f"replicas {wb:.1f} s, records equal: {same}")
     p_tr = n_tr / max(1, len(tr_recs))
     nf = tr_recs[0]["n_steps"] if tr_recs else 0
     return {
@@ -449,6 +473,7 @@ def gcmd_leg(args, h4d, torch, w, beta_mu, tuned):
         "equilibrium_mean_abs_beta_dH": sum(abs(r["dH"]) for r in md_recs) / max(1, len(md_recs)) / w.params["kT"],
         "trials_accepted": n_tr, "trial_acceptance": p_tr,
         "efficiency_per_step": p_tr / max(1, nf + args.n_eq),
+        "carried_momentum_trials": carried,
     }
 
 
@@ -708,6 +733,8 @@ def main():
     ap.add_argument("--gcmd-cycles", type=int, default=10,
                     help="single ion box: grand-canonical cycles (equilibrium phase + one trial) timed after the rest")
     ap.add_argument("--n-eq", type=int, default=1000, help="steps of an equilibrium phase (the paper's N_eq)")
+    ap.add_argument("--gcmd-trials", type=int, default=200,
+                    help="trials with carried momenta timed one by one and on speculative replicas (0: none)")
     ap.add_argument("--md-refresh", type=float, default=0.5, help="momentum persistence c of the equilibrium phase")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rebuild-every", type=int, default=0, help="list rebuild interval (0: library default)")
