@@ -357,7 +357,7 @@ typedef struct h4d_checkpoint {
 } h4d_checkpoint;
 
 /* Fill *ck from a single-box or speculative handle (H4D_EINVAL for a
- * batch).  Synchronizes the handle's stream. */
+ * batch: see h4d_save_box_checkpoint).  Synchronizes the handle's stream. */
 int32_t h4d_save_checkpoint(h4d_system *sys, h4d_checkpoint *ck);
 /* Apply *ck to a handle just created from the checkpoint's parameters and
  * the state saved with it.  n_atoms: the state's atom count (checked); vel:
@@ -369,6 +369,15 @@ int32_t h4d_save_checkpoint(h4d_system *sys, h4d_checkpoint *ck);
  * is then unchanged.  Rebuilds the lists. */
 int32_t h4d_restore_checkpoint(h4d_system *sys, const h4d_checkpoint *ck, int32_t n_atoms,
                                const double *vel);
+/* The same for box `box` of a batch, each box a chain of its own (box 0 of a
+ * single-box or speculative handle).  The saved record carries the box's own
+ * edges (params.box) and Philox stream (params.stream = the batch's stream +
+ * box), so it also resumes as a single-box handle; a batch resumes from its
+ * boxes' records with h4d_init_batch(&ck[0].params, ...) and one restore per
+ * box.  The restore checks the box's edges and stream as well. */
+int32_t h4d_save_box_checkpoint(h4d_system *sys, int32_t box, h4d_checkpoint *ck);
+int32_t h4d_restore_box_checkpoint(h4d_system *sys, int32_t box, const h4d_checkpoint *ck,
+                                   int32_t n_atoms, const double *vel);
 
 /* Chemical potential beta * mu_salt of the following trials (Eqs. 6, 8). */
 int32_t h4d_set_beta_mu(h4d_system *sys, double beta_mu);

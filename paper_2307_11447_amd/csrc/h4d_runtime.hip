@@ -1322,15 +1322,19 @@ int32_t h4d_set_trial_index(h4d_system *s, uint64_t trial) {
     return write_ctl(s);
 }
 
-int32_t h4d_save_checkpoint(h4d_system *s, h4d_checkpoint *out) {
+static int save_box(h4d_system *s, int box, h4d_checkpoint *out) {
     if (!s || !out) return fail(H4D_EINVAL, "null argument");
-    if (s->nbox != 1 && !s->speculative) return fail(H4D_EINVAL, "checkpoints serve single chains, not batches");
+    if (box < 0 || box >= s->nbox || (s->speculative && box != 0))
+        return fail(H4D_EINVAL, "box index out of range (speculative handles: box 0)");
     int rc = read_ctl(s);
     if (rc) return rc;
-    const Ctl &c = s->h_ctl[0];     // (replicas hold the chain's state between calls)
-    const h4d_system::Stats &st = s->speculative ? s->chain : s->stats[0];
+    const Ctl &c = s->h_ctl[box];     // (replicas hold the chain's state between calls)
+    const h4d_system::Stats &st = s->speculative ? s->chain : s->stats[box];
+    const Box &B = s->box_h[box];
     std::memset(out, 0, sizeof(*out));
     out->params = s->p;
+    for (int d = 0; d < 3; ++d) out->params.box[d] = B.L[d];   // the box's own edges and stream
+    out->params.stream = B.stream;
     out->trial = (uint64_t)c.trial;
     out->md_phases = (uint64_t)c.md;
     out->next_tag = c.next_tag;
@@ -1351,11 +1355,15 @@ int32_t h4d_save_checkpoint(h4d_system *s, h4d_checkpoint *out) {
     return H4D_OK;
 }
 
-int32_t h4d_restore_checkpoint(h4d_system *s, const h4d_checkpoint *ck, int32_t n_atoms, const double *vel) {
+static int restore_box(h4d_system *s, int box, const h4d_checkpoint *ck, int32_t n_atoms, const double *vel) {
     if (!s || !ck) return fail(H4D_EINVAL, "null argument");
-    if (s->nbox != 1 && !s->speculative) return fail(H4D_EINVAL, "checkpoints serve single chains, not batches");
+    if (box < 0 || box >= s->nbox || (s->speculative && box != 0))
+        return fail(H4D_EINVAL, "box index out of range (speculative handles: box 0)");
     const h4d_params &q = ck->params;
-    if (q.seed != s->p.seed || q.stream != s->p.stream || q.precision != s->p.precision ||
+    const Box &B0 = s->box_h[box];
+    bool same_box = true;
+    for (int d = 0; d < 3; ++d) same_box &= q.box[d] == B0.L[d];
+    if (q.seed != s->p.seed || q.stream != B0.stream || !same_box || q.precision != s->p.precision ||
         q.momenta != s->p.momenta || q.n_types != s->p.n_types || q.water != s->p.water)
         return fail(H4D_EINVAL, "the handle was not created with the checkpoint's parameters");
     if (ck->lanes_per_atom != 4 && ck->lanes_per_atom != 8 && ck->lanes_per_atom != 16)
@@ -1366,13 +1374,16 @@ int32_t h4d_restore_checkpoint(h4d_system *s, const h4d_checkpoint *ck, int32_t 
     if (ck->has_velocities && !vel) return fail(H4D_EINVAL, "the checkpoint carries momenta: vel is required");
     int rc = read_ctl(s);
     if (rc) return rc;
-    Ctl &c = s->h_ctl[0];
-    for (int b = 0; b < s->nbox; ++b)
+    // the boxes this record applies to: every replica of a speculative
+    // handle, else the one box
+    const int b0 = s->speculative ? 0 : box, b1 = s->speculative ? s->nbox : box + 1;
+    Ctl &c = s->h_ctl[box];
+    for (int b = b0; b < b1; ++b)
         if (n_atoms != s->h_ctl[b].n) return fail(H4D_EINVAL, "n_atoms differs from the handle's state");
     long long max_tag = -1;
     if (c.n) {
         std::vector<long long> tags(c.n);
-        HIPC(hipMemcpyAsync(tags.data(), s->a.ctag + s->box_h[0].a0, sizeof(long long) * c.n,
+        HIPC(hipMemcpyAsync(tags.data(), s->a.ctag + s->box_h[box].a0, sizeof(long long) * c.n,
                             hipMemcpyDeviceToHost, s->stream));
         HIPC(hipStreamSynchronize(s->stream));
         for (long long t : tags) max_tag = std::max(max_tag, t);
@@ -1400,7 +1411,7 @@ int32_t h4d_restore_checkpoint(h4d_system *s, const h4d_checkpoint *ck, int32_t 
     if (ck->has_velocities && c.n) {
         std::vector<double4> buf(c.n);
         for (int i = 0; i < c.n; ++i) buf[i] = make_double4(vel[3 * i], vel[3 * i + 1], vel[3 * i + 2], 0.0);
-        for (int b = 0; b < s->nbox; ++b)   // every replica of a speculative handle
+        for (int b = b0; b < b1; ++b)
             HIPC(hipMemcpyAsync(a.cvel + s->box_h[b].a0, buf.data(), sizeof(double4) * c.n,
                                 hipMemcpyHostToDevice, s->stream));
         HIPC(hipStreamSynchronize(s->stream));
@@ -1414,16 +1425,35 @@ int32_t h4d_restore_checkpoint(h4d_system *s, const h4d_checkpoint *ck, int32_t 
     st.n_del_acc = ck->n_del_acc;
     st.N_sum = ck->N_sum;
     st.N2_sum = ck->N2_sum;
-    for (int b = 0; b < s->nbox; ++b) {
+    for (int b = b0; b < b1; ++b) {
         Ctl &cb = s->h_ctl[b];
         cb.trial = (long long)ck->trial;
         cb.md = (long long)ck->md_phases;
         cb.next_tag = ck->next_tag;
         s->stats[b] = st;
     }
-    s->chain = st;
+    if (s->speculative) s->chain = st;
     if ((rc = write_ctl(s))) return rc;
     return h4d_build_neighbors(s);
+}
+
+int32_t h4d_save_checkpoint(h4d_system *s, h4d_checkpoint *ck) {
+    if (s && s->nbox != 1 && !s->speculative)
+        return fail(H4D_EINVAL, "a batch holds one chain per box: h4d_save_box_checkpoint");
+    return save_box(s, 0, ck);
+}
+
+int32_t h4d_restore_checkpoint(h4d_system *s, const h4d_checkpoint *ck, int32_t n_atoms, const double *vel) {
+    if (s && s->nbox != 1 && !s->speculative)
+        return fail(H4D_EINVAL, "a batch holds one chain per box: h4d_restore_box_checkpoint");
+    return restore_box(s, 0, ck, n_atoms, vel);
+}
+
+int32_t h4d_save_box_checkpoint(h4d_system *s, int32_t box, h4d_checkpoint *ck) { return save_box(s, box, ck); }
+
+int32_t h4d_restore_box_checkpoint(h4d_system *s, int32_t box, const h4d_checkpoint *ck, int32_t n_atoms,
+                                   const double *vel) {
+    return restore_box(s, box, ck, n_atoms, vel);
 }
 
 int32_t h4d_get_state(h4d_system *s, int32_t cap, int32_t *n, int32_t *n_salt, double *pos, double *vel,

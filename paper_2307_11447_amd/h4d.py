@@ -165,6 +165,8 @@ def lib() -> C.CDLL:
         L.h4d_set_early_rejection.argtypes = [vp, C.c_double]
         L.h4d_save_checkpoint.argtypes = [vp, C.POINTER(Checkpoint)]
         L.h4d_restore_checkpoint.argtypes = [vp, C.POINTER(Checkpoint), C.c_int32, dp]
+        L.h4d_save_box_checkpoint.argtypes = [vp, C.c_int32, C.POINTER(Checkpoint)]
+        L.h4d_restore_box_checkpoint.argtypes = [vp, C.c_int32, C.POINTER(Checkpoint), C.c_int32, dp]
         for name in ("h4d_stream_copy", "h4d_set_timing", "h4d_get_timing", "h4d_init_system", "h4d_build_neighbors",
                      "h4d_run_nemd_trial", "h4d_run_trials", "h4d_sample_observables", "h4d_get_state",
                      "h4d_set_trial_index", "h4d_forces_at", "h4d_destroy", "h4d_init_batch", "h4d_num_boxes",
@@ -173,7 +175,8 @@ def lib() -> C.CDLL:
                      "h4d_mlp_forward", "h4d_mlp_loss_grad", "h4d_mlp_train", "h4d_set_proposal",
                      "h4d_last_site_features", "h4d_last_candidates", "h4d_site_features", "h4d_set_beta_mu",
                      "h4d_init_speculative", "h4d_run_speculative", "h4d_set_bias", "h4d_run_md", "h4d_set_early_rejection",
-                     "h4d_save_checkpoint", "h4d_restore_checkpoint"):
+                     "h4d_save_checkpoint", "h4d_restore_checkpoint", "h4d_save_box_checkpoint",
+                     "h4d_restore_box_checkpoint"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -389,9 +392,11 @@ class Batch(_Handle):
     """Independent boxes run together: box b has edges boxes[b] and its own
     Philox stream (params["stream"] + b)."""
 
-    def __init__(self, params: dict, boxes, xs, types, tags, nsalts, stream=None):
+    def __init__(self, params, boxes, xs, types, tags, nsalts, stream=None):
+        """params: a dict for make_params, or a Params structure as it is."""
         self._h = None
-        self.params = dict(params)
+        raw = isinstance(params, Params)
+        self.params = {k: getattr(params, k) for k, _ in params._fields_} if raw else dict(params)
         nb = len(boxes)
         edges = np.ascontiguousarray(np.asarray(boxes, dtype=np.float64).reshape(nb, 3))
         n_atoms = np.array([len(t) for t in types], np.int32)
@@ -400,7 +405,7 @@ class Batch(_Handle):
         t = np.ascontiguousarray(np.concatenate(types).astype(np.int32))
         g = np.ascontiguousarray(np.concatenate(tags).astype(np.int64))
         h = C.c_void_p()
-        p = make_params(params)
+        p = params if raw else make_params(params)
         _check(lib().h4d_init_batch(
             C.byref(p), nb, edges.ctypes.data_as(C.POINTER(C.c_double)),
             n_atoms.ctypes.data_as(C.POINTER(C.c_int32)), ns.ctypes.data_as(C.POINTER(C.c_int32)),
@@ -416,6 +421,36 @@ class Batch(_Handle):
         params.update(overrides)
         return cls(params, [w.params["box"] for w in ws], [w.x for w in ws], [w.type for w in ws],
                    [w.tag for w in ws], [w.nsalt for w in ws])
+
+    def checkpoint(self) -> list:
+        """One checkpoint per box (each box a chain of its own; box b's also
+        resumes as a System)."""
+        out = []
+        for b in range(self.nb):
+            ck = Checkpoint()
+            _check(lib().h4d_save_box_checkpoint(self._h, b, C.byref(ck)))
+            st = self.box_state(b)
+            out.append({"checkpoint": np.frombuffer(bytes(ck), np.uint8).copy(), "x": st["x"], "v": st["v"],
+                        "type": st["type"], "mol": st["mol"], "tag": st["tag"], "nsalt": np.int64(st["nsalt"]),
+                        "n_mol": np.int64(0)})
+        return out
+
+    @classmethod
+    def resume(cls, ckpts, stream=None):
+        """A batch that continues every box's chain from Batch.checkpoint()."""
+        cks = [_checkpoint_record(c) for c in ckpts]
+        bat = cls(cks[0].params, [list(ck.params.box) for ck in cks], [c["x"] for c in ckpts],
+                  [c["type"] for c in ckpts], [c["tag"] for c in ckpts], [int(c["nsalt"]) for c in ckpts],
+                  stream=stream)
+        try:
+            for b, (ck, c) in enumerate(zip(cks, ckpts)):
+                v = np.ascontiguousarray(c["v"], dtype=np.float64).reshape(-1, 3)
+                _check(lib().h4d_restore_box_checkpoint(bat._h, b, C.byref(ck), len(v),
+                                                        v.ctypes.data_as(C.POINTER(C.c_double))))
+        except H4DError:
+            bat.close()
+            raise
+        return bat
 
     def run(self, trials_per_box: int, move: int = MOVE_AUTO, as_array: bool = False):
         """trials_per_box more trials in every box; records box-major."""

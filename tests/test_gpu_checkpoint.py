@@ -144,3 +144,32 @@ def test_checkpoint_moves_between_one_by_one_and_speculative_runs():
     say(f"   accepted {acc[0]}, {acc[1]}, {acc[2]} of {T} in the three parts")
     assert sum(acc[1:]) > 0
     r.close()
+
+
+def test_batch_checkpoint_resumes_every_box_and_a_box_alone():
+    say("case batch checkpoint: 3 LJ boxes fp64 with carried momenta, 4 + 4 trials per box")
+    ws = [W.lj_electrolyte(n, 0.1, 4600 + n, n_steps=20, precision="fp64") for n in (340, 400, 460)]
+    for w in ws:
+        w.params.update(momenta=1, md_refresh=0.3, beta_mu=10.0, rebuild_every=5, lanes_per_atom=8)
+    bat = h4d.Batch.from_workloads(ws)
+    bat.run(4)
+    cks = [through_file(c) for c in bat.checkpoint()]
+    ref = bat.run(4)
+    ref_states = [bat.box_state(b) for b in range(3)]
+    bat.close()
+    r = h4d.Batch.resume(cks)
+    got = r.run(4)
+    for b in range(3):
+        for q in range(4):
+            same(dict(ref[b][q], n_rebuilds=0), dict(got[b][q], n_rebuilds=0), f"box {b} trial {q}")
+        same_state(ref_states[b], r.box_state(b))
+    r.close()
+    # box 1's record on its own: a single-box handle with the box's edges and stream
+    one = h4d.System.resume(cks[1])
+    alone = one.trials(4)
+    for q in range(4):
+        a, b = ref[1][q], alone[q]
+        assert (a["move"], a["accepted"], a["trial"]) == (b["move"], b["accepted"], b["trial"]), q
+        assert abs(a["dH"] - b["dH"]) < 1e-9 * max(1.0, abs(a["dH"])), q
+    say(f"   {sum(x['accepted'] for row in ref for x in row)} of 12 accepted after the checkpoint")
+    one.close()
