@@ -7,6 +7,14 @@
  * shares no code with the GPU path.  Slow on purpose: every energy or force
  * evaluation re-enumerates the pairs, all sums run left to right in FP64.
  *
+ * Timing build.  Compiled with -fopenmp (liboracle_omp.so, for the
+ * benchmark's CPU baseline only), the pair enumeration and the pair sum of
+ * every energy or force evaluation, and the candidate features of the
+ * learned proposal, spread over threads; the pair order is the serial one,
+ * but the energy and force sums are reduced per thread, so that build
+ * rounds differently.  The parity build has no -fopenmp: the pragmas are
+ * ignored and every sum runs in the order written.
+ *
  * Physics (one pair i<j, minimum image r_ij):
  *   s^2 = |r_ij|^2 + (w_i - w_j)^2, w = altitude of a flyer, 0 otherwise
  *     (the 4D distance of Sec. I and Sec. II C);
@@ -22,6 +30,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ------------------------------------------------------------------ */
 /* Philox4x64-10 from its published definition (Salmon, Moraes, Dror & */
@@ -163,6 +174,26 @@ static double r2_of(const or_params *p, const or_state *s, int i, int j)
     return r2;
 }
 
+/* The pairs (i, j > i) of atom i from the 27 cells around its own. */
+static int cell_pairs(const or_params *p, const or_state *s, int i, const int nc[3], const int *head,
+                      const int *next, const int *cid, double rc2, pairlist *pl)
+{
+    int c = cid[i];
+    int cx = c % nc[0], cy = (c / nc[0]) % nc[1], cz = c / (nc[0] * nc[1]);
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                int ax = (cx + dx + nc[0]) % nc[0];
+                int ay = (cy + dy + nc[1]) % nc[1];
+                int az = (cz + dz + nc[2]) % nc[2];
+                int cc = (az * nc[1] + ay) * nc[0] + ax;
+                for (int j = head[cc]; j >= 0; j = next[j])
+                    if (j > i && !excluded(s, i, j) && r2_of(p, s, i, j) < rc2)
+                        if (pl_push(pl, i, j)) return -1;
+            }
+    return 0;
+}
+
 static int enumerate_pairs(const or_params *p, const or_state *s, double rcut, pairlist *pl)
 {
     const int n = s->n;
@@ -200,23 +231,29 @@ static int enumerate_pairs(const or_params *p, const or_state *s, double rcut, p
         next[i] = head[c];
         head[c] = i;
     }
-    for (int i = 0; i < n; ++i) {
-        int c = cid[i];
-        int cx = c % nc[0], cy = (c / nc[0]) % nc[1], cz = c / (nc[0] * nc[1]);
-        for (int dz = -1; dz <= 1; ++dz)
-            for (int dy = -1; dy <= 1; ++dy)
-                for (int dx = -1; dx <= 1; ++dx) {
-                    int ax = (cx + dx + nc[0]) % nc[0];
-                    int ay = (cy + dy + nc[1]) % nc[1];
-                    int az = (cz + dz + nc[2]) % nc[2];
-                    int cc = (az * nc[1] + ay) * nc[0] + ax;
-                    for (int j = head[cc]; j >= 0; j = next[j])
-                        if (j > i && !excluded(s, i, j) && r2_of(p, s, i, j) < rc2)
-                            if (pl_push(pl, i, j)) { free(head); free(next); free(cid); return -1; }
-                }
+    int err = 0;
+#ifdef _OPENMP
+    /* timing build: each thread lists the pairs of a contiguous range of i,
+     * and the lists are joined in thread order, i.e. in the serial order */
+    int nt = omp_get_max_threads();
+    pairlist *part = calloc((size_t)nt, sizeof(pairlist));
+    if (!part) { free(head); free(next); free(cid); return -1; }
+#pragma omp parallel num_threads(nt) reduction(|:err)
+    {
+        const int t = omp_get_thread_num();
+        const int lo = (int)((int64_t)n * t / nt), hi = (int)((int64_t)n * (t + 1) / nt);
+        for (int i = lo; i < hi && !err; ++i) err |= cell_pairs(p, s, i, nc, head, next, cid, rc2, &part[t]);
     }
+    for (int t = 0; t < nt; ++t) {
+        for (int64_t q = 0; q < part[t].n && !err; ++q) err |= pl_push(pl, part[t].i[q], part[t].j[q]);
+        pl_free(&part[t]);
+    }
+    free(part);
+#else
+    for (int i = 0; i < n && !err; ++i) err |= cell_pairs(p, s, i, nc, head, next, cid, rc2, pl);
+#endif
     free(head); free(next); free(cid);
-    return 0;
+    return err ? -1 : 0;
 }
 
 /* Pairs that involve a flyer: flyer x every other atom, flyer-flyer once. */
@@ -262,6 +299,16 @@ int or_compute(const or_params *p, const or_state *s, double w, int mode,
      * several flyers at different altitudes, the average one) */
     const double wbar = 0.5 * w * (1.0 + w_ratio(p));
     const double gscr = exp(-p->kappa_sr * wbar);
+    double U = 0.0, U_lj = 0.0, U_c = 0.0, virial = 0.0, dUdw = 0.0;
+#ifdef _OPENMP
+    /* timing build: per-thread force copies, summed at the end */
+    const int nf3 = 3 * s->n;
+    double *Fsum = F ? F : calloc((size_t)nf3 + 1, sizeof(double));
+    if (!Fsum) { pl_free(&pl); return -1; }
+#pragma omp parallel for schedule(static) reduction(+:U, U_lj, U_c, virial, dUdw) reduction(+:Fsum[:nf3])
+#else
+    double *Fsum = F;
+#endif
     for (int64_t k = 0; k < pl.n; ++k) {
         const int i = pl.i[k], j = pl.j[k];
         const int fi = s->flying[i], fj = s->flying[j];
@@ -282,23 +329,27 @@ int or_compute(const or_params *p, const or_state *s, double w, int mode,
         or_pair(p, s->type[i], s->type[j], s2, g, &ulj, &uc, &dlj, &dc);
         const double sd = sqrt(s2);
         const double duds = dlj + dc;
-        e->U_lj += ulj;
-        e->U_c += uc;
-        e->U += ulj + uc;
+        U_lj += ulj;
+        U_c += uc;
+        U += ulj + uc;
         /* F_i = -du/ds * (r_i - r_j)/s, virial sum r_ij . F_ij (3D part). */
         const double fs = -duds / sd;
-        e->virial += fs * r2;
-        if (F) {
+        virial += fs * r2;
+        if (Fsum) {
             for (int d = 0; d < 3; ++d) {
-                F[3 * i + d] += fs * r[d];
-                F[3 * j + d] -= fs * r[d];
+                Fsum[3 * i + d] += fs * r[d];
+                Fsum[3 * j + d] -= fs * r[d];
             }
         }
         /* dU/dw: ds/dw = dw (r_i - r_j) / s with the flyers' factors r;
          * dg/dw = -kappa_sr (1 + r_w) / 2 g for a flyer-nonflyer pair. */
-        if (sd > 0.0) e->dUdw += duds * (dw * (ri - rj) / sd);
-        if (one_flying) e->dUdw -= p->kappa_sr * 0.5 * (1.0 + w_ratio(p)) * uc;
+        if (sd > 0.0) dUdw += duds * (dw * (ri - rj) / sd);
+        if (one_flying) dUdw -= p->kappa_sr * 0.5 * (1.0 + w_ratio(p)) * uc;
     }
+#ifdef _OPENMP
+    if (!F) free(Fsum);
+#endif
+    e->U = U; e->U_lj = U_lj; e->U_c = U_c; e->virial = virial; e->dUdw = dUdw;
     pl_free(&pl);
     return 0;
 }
@@ -769,6 +820,9 @@ static void candidate_site(const or_params *p, uint64_t trial, int j, double sit
 static int score_sites(const or_params *p, const or_state *s, const or_proposal *prop, int n,
                        const double *sites, double *feat, double *logw)
 {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 8)
+#endif
     for (int j = 0; j < n; ++j) or_site_features(p, s, sites + 6 * j, feat + 64 * j);
     if (!prop->fn) {
         for (int j = 0; j < n; ++j) logw[j] = 0.0;

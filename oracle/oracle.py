@@ -14,6 +14,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
+LIB_OMP_PATH = os.path.join(HERE, "liboracle_omp.so")
 MAXT = 8
 
 MODE_NEMD, MODE_EXCL, MODE_FLY = 0, 1, 2
@@ -80,13 +81,27 @@ class Energy(C.Structure):
 _lib = None
 
 
-def lib():
+def use_timing_build() -> str:
+    """Switch this process to the OpenMP build of the same source (thread
+    count from OMP_NUM_THREADS): for the benchmark's CPU-baseline timing
+    only; every parity check uses the single-threaded build.  Call before
+    anything else loads the oracle."""
+    global _lib
+    if _lib is not None and getattr(_lib, "_path", None) != LIB_OMP_PATH:
+        raise RuntimeError("the oracle is already loaded single-threaded")
+    _lib = None
+    return lib(LIB_OMP_PATH)._path
+
+
+def lib(path=None):
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
+        path = path or LIB_PATH
+        if not os.path.exists(path):
             from . import build as _b  # type: ignore
             _b.build()
-        L = C.CDLL(LIB_PATH)
+        L = C.CDLL(path)
+        L._path = path
         P, S = C.POINTER(Params), C.POINTER(State)
         L.or_philox4x64.argtypes = [C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
         L.or_u01.argtypes = [C.c_uint64]
