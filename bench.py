@@ -1,33 +1,42 @@
 #!/usr/bin/env python3
-"""NEMD throughput of H4D salt-pair exchange trials on one MI355X.
+"""Throughput of H4D salt-pair exchange trials on one MI355X, learned vs plain.
 
-Workload (N = 1): 32,000 Lennard-Jones ions (16,000 cations, 16,000
-anions) at reduced density 0.3, T* = 1, Bjerrum length 3 sigma, LJ cut
-2.5 sigma, damped shifted force Coulomb (alpha 0.3, cut 4 sigma); every
-trial flies one cation-anion pair in or out along w in 200 velocity-Verlet
-steps of dt = 0.005 (w_max = 2.5 sigma); FP32 pair arithmetic with FP64
-positions, velocities, energies, work and Metropolis ratio; uniform
-(plain) proposal.  One "step" of this benchmark is one exchange trial.
+Default workload (N = 1), the aqueous NaCl box with the learned proposal:
+8,000 rigid SPC/E waters + 150 Na+/Cl- pairs in a 62 A box at 298 K; every
+trial flies one NaCl pair in or out along w in 500 velocity-Verlet steps of
+1 fs (w_max 3 A, kappa_sr 1/A, DSF Coulomb alpha 0.25/A cut 10 A); FP32 pair
+arithmetic on FP64 positions, velocities, energies, work and Metropolis
+ratio.  Two arms run the same chain from the same start state, each on 8
+speculative replicas of the box (a batch of replica boxes in one engine, the
+chain's records equal to a one-by-one run):
+  plain    the uniform pair insertion of Eq. (4);
+  learned  the multiple-try proposal over 4,096 uniform candidate sites per
+           attempt (Sec. II B 4, Eqs. 15-16, with a learned weight), each
+           scored by the network (64 features -> 3 x 128 GELU -> 1) in BF16
+           on the matrix cores, the ratio corrected exactly.
+Before the timed region: pilot insertions and deletions on the start state
+(forced moves that are never accepted, so the state stays fixed) give the
+operating beta mu by Bennett's acceptance ratio (Crooks' relation, the
+supplement's CFT/BAR section) and the network's training data (features and
+work of the method's own moves); the network trains on the GPU (FP32
+forward, backward, Adam).
 
-Prints one JSON line.  value = NEMD atom-steps/s (sum over trials of
-atoms x N_f, divided by the wall time of the timed trials).
+One "step" of this benchmark is one exchange trial of the chain.  value =
+NEMD atom-steps/s of the learned arm (the whole hot path, candidate scoring
+included); the plain arm, accepted exchanges/s of both arms with Wilson
+intervals, and a fixed-state comparison of their insertion and deletion
+acceptance stand beside it.  Extra keys time the 32,000-ion LJ chain and
+the 256-box batch (--no-extras leaves them out).
 
-Both single-box workloads also measure the learned proposal: pilot
-insertions give each uniform site's 64 features and dH, the network is
-trained on them on the GPU, and the same number of timed trials run with
-the multiple-try proposal it weights (reported under "learned", next to the
-uniform run's accepted and expected exchanges per second).
+Other workloads: --workload lj32k (32,000 LJ ions), --workload batched (256
+independent LJ boxes of 1,000-16,000 ions).
 
---workload water: 8,000 rigid SPC/E waters + 150 NaCl pairs in a 62 A box,
-NaCl-pair trials of 500 steps of 1 fs.
-
---workload batched: 256 independent boxes of 1,000-16,000 ions at
-densities 0.1-0.4, N_f ~ U{100..400} per trial, all boxes running their
-trials together; one "step" is one trial in every box.
+Prints one JSON line on stdout; progress goes to stderr.
 """
 import argparse
 import json
 import math
+import multiprocessing as mp
 import os
 import sys
 import time
@@ -38,27 +47,12 @@ sys.path.insert(0, ROOT)
 METRIC = "accepted salt-pair exchanges/s + NEMD atom-steps/s (1 GPU), learned vs plain"
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # published vector FP32 rate (packed FP32 counted)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_lj32k_traffic.txt")
-TRAFFIC_FILE_BATCHED = os.path.join(ROOT, "profiles", "k_step_batched256_traffic.txt")
-
-
-def counted_traffic(path):
-    """HBM bytes per step launch from a committed rocprofv3 counter summary,
-    or None if it is missing or was taken on different kernel sources."""
-    from paper_2307_11447_amd import rocprof_summary
-    if not os.path.exists(path):
-        return None
-    kv = {}
-    for line in open(path):
-        if ":" in line:
-            k, v = line.split(":", 1)
-            kv[k.strip()] = v.strip().split()[0] if v.strip() else ""
-    if kv.get("kernel_source_sha256") != rocprof_summary.kernel_source_hash():
-        return None
-    try:
-        return float(kv["traffic_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+TRAFFIC_FILES = {
+    "water": os.path.join(ROOT, "profiles", "k_step_water_traffic.txt"),
+    "lj32k": os.path.join(ROOT, "profiles", "k_step_lj32k_traffic.txt"),
+    "batched": os.path.join(ROOT, "profiles", "k_step_batched256_traffic.txt"),
+}
+CANDIDATES = 4096
 
 
 def note(msg):
@@ -76,154 +70,192 @@ def wilson(k, n, z=1.96):
     return (max(0.0, c - h), min(1.0, c + h))
 
 
-def cpu_baseline(w, n_steps, label):
-    """The FP64 oracle, single threaded, on a bounded sample: one trial of
-    the given state with the trajectory cut to n_steps steps."""
-    from oracle import build as ob
-    from oracle import oracle as O
-    if not os.path.exists(O.LIB_PATH):
-        ob.build()
-    params = dict(w.params, n_steps=n_steps, n_steps_min=0, n_steps_max=0)
-    o = O.OracleSystem(params, w.x, w.type, w.mol, w.tag, w.nsalt, cap=w.n + 8)
-    t0 = time.perf_counter()
-    rec = o.trial(0)
-    dt = time.perf_counter() - t0
-    atoms = w.n
-    return {"value": atoms * n_steps / dt, "unit": "atom-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 trial (move {rec['move']:+d}) of {label} with N_f cut to "
-                      f"{n_steps} steps ({atoms * n_steps:.3g} atom-steps, {dt:.1f} s)"}
+def host_cores():
+    """Threads of the CPU baseline: OMP_NUM_THREADS if set, else the
+    process's CPUs, at most 16 (the host share of one GPU)."""
+    env = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    if env > 0:
+        return env
+    return max(1, min(16, len(os.sched_getaffinity(0))))
 
 
+# ---------------------------------------------------------------------------
+# Roofline of the fused step kernel
+# ---------------------------------------------------------------------------
 def step_bytes_per_atom(mean_nbr):
-    """Algorithmic bytes of one fused step launch, per atom: 4 B per list
-    entry, 4 B list length, 16 B own fixed-point record, 32 B own FP64
-    position, 16 B fixed-point position at the list build, 64 B velocity in
-    and out, 48 B new position (FP64 + fixed point); neighbour records are
-    gathered through the caches and not counted."""
-    return 4.0 * mean_nbr + 184.0
+    """Algorithmic HBM bytes of one atom-step of the fused step kernel: the
+    pair pass, 4 B per list entry + 16 B own coordinates, charge and type +
+    16 B force + 4 B list length (4 n_list + 36), plus the velocity-Verlet
+    update, 120 B (FP64 position and velocity in and out, FP32 force);
+    neighbour records are gathered through the caches and not counted."""
+    return 4.0 * mean_nbr + 36.0 + 120.0
 
 
 def step_flop_per_atom(mean_nbr):
-    """Algorithmic floating-point operations of one fused step launch, per
-    atom (an FMA counts 2, a reciprocal, square root or exponential 1).
-    Per list entry, in FP32: the displacement and the squared 4D distance
-    with the altitude term (9), the LJ force factor with 1/s^2 (7), the DSF
-    Coulomb force factor with s, 1/s, the Gaussian and the erfc
-    approximation (23), their sum (1) and the accumulation of the factor
-    times the displacement (6): 46.  Per atom, in FP64: the two half kicks
-    and the drift of velocity Verlet (18)."""
+    """Floating-point operations of one atom-step (an FMA counts 2, a
+    reciprocal, square root or exponential 1): per list entry, in FP32, the
+    displacement and squared 4D distance (9), the LJ force factor with 1/s^2
+    (7), the DSF Coulomb force factor with s, 1/s, the Gaussian and the erfc
+    approximation (23), their sum (1) and the accumulation (6): 46; per atom,
+    in FP64, the two half kicks and the drift (18)."""
     return 46.0 * mean_nbr + 18.0
 
 
-def summarize(recs, wall, timing, timing_recs, traffic_bytes, atom_launches=None):
-    """Throughput, acceptance and the step kernel's roofline from trial
-    records (recs: the timed trials; timing_recs: the trials run with HIP
-    events around every step launch, or atom_launches: the atoms those
-    launches integrated, summed over launches)."""
-    n = len(recs)
-    atom_steps = sum(r.n_atoms * r.n_steps for r in recs)
-    acc = sum(r.accepted for r in recs)
-    n_ins = sum(1 for r in recs if r.move > 0)
-    n_ins_acc = sum(r.accepted for r in recs if r.move > 0)
-    retried = sum(1 for r in recs if r.flags & 0x4)
-    lo, hi = wilson(acc, n)
-    mean_nbr = timing["mean_nbr"]
-    bpa = step_bytes_per_atom(mean_nbr)
-    # every step launch k = 0..N_f of a trial touches each of its atoms once
-    if atom_launches is None:
-        atom_launches = sum(r.n_atoms * (r.n_steps + 1) for r in timing_recs)
-    step_s = timing["step_ms"] * 1e-3
+def counted_traffic(path):
+    """HBM bytes per step launch from a committed rocprofv3 counter summary,
+    or None if it is missing or was taken on different kernel sources."""
+    from paper_2307_11447_amd import rocprof_summary
+    if not path or not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip().split()[0] if v.strip() else ""
+    if kv.get("kernel_source_sha256") != rocprof_summary.kernel_source_hash():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def roofline(timing, traffic_bytes, kernel):
+    """The step kernel against the HBM roofline: algorithmic bytes of the
+    atoms its timed launches integrated over their summed HIP-event time."""
+    n_l = timing["mean_nbr"]
+    step_s = max(timing["step_ms"], 1e-300) * 1e-3
     launches = max(1, timing["step_launches"])
-    fpa = step_flop_per_atom(mean_nbr)
-    achieved = fpa * atom_launches / step_s / 1e12
-    achieved_bytes = bpa * atom_launches / step_s / 1e9
-    traffic = None if traffic_bytes is None else traffic_bytes * launches / step_s / 1e9
+    atoms = timing["atom_launches"]
+    bpa, fpa = step_bytes_per_atom(n_l), step_flop_per_atom(n_l)
+    achieved = bpa * atoms / step_s / 1e9
+    flops = fpa * atoms / step_s / 1e12
     return {
-        "value": atom_steps / wall,
-        "trials_per_s": n / wall,
-        "accepted_exchanges_per_s": acc / wall,
-        "accepted": acc,
-        "p_acc": acc / max(1, n),
-        "p_acc_wilson95": [lo, hi],
-        "insertions": n_ins, "insertions_accepted": n_ins_acc,
-        "retried_trials": retried,
-        "roofline": {
-            "kernel": "k_step<1> (fused pair force + velocity Verlet)",
-            "bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "flop_per_atom_step": fpa,
-            "traffic": traffic, "traffic_unit": "GB/s", "traffic_bytes_per_launch": traffic_bytes,
-            "hbm": {"achieved": achieved_bytes, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved_bytes / HBM_PEAK_GBS, "bytes_per_atom_step": bpa},
-            "mean_list_entries": mean_nbr,
-            "avg_kernel_us": 1e3 * timing["step_ms"] / launches, "launches": timing["step_launches"],
-            "timing": "HIP events around each step launch over the timing trials",
-        },
-        "rebuild_every": timing["rebuild_every"], "lanes_per_atom": timing["lanes"],
-        "cell_cap": timing["cell_cap"], "list_cap": timing["nbr_cap"],
+        "kernel": kernel, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS,
+        "traffic": None if traffic_bytes is None else traffic_bytes * launches / step_s / 1e9,
+        "traffic_bytes_per_launch": traffic_bytes,
+        "bytes_per_atom_step": bpa, "mean_list_entries": n_l,
+        "atom_launches": atoms, "launches": timing["step_launches"],
+        "avg_kernel_us": 1e3 * timing["step_ms"] / launches,
+        "flop": {"achieved": flops, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                 "frac": flops / FP32_VECTOR_PEAK_TFLOPS, "flop_per_atom_step": fpa},
+        "timing": "HIP events around every step-kernel launch of the timing trials, on the library's stream",
     }
 
 
-def expected_acceptance(recs):
-    """Mean Metropolis acceptance probability min(1, exp(ln R)) of the
-    records: an estimator of the acceptance rate with far less variance
-    than the count of accepted trials when acceptance is rare."""
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle's OpenMP timing build in a child process
+# ---------------------------------------------------------------------------
+def _oracle_trial(args):
+    root, threads, params, x, type_, mol, tag, nsalt, n_mol, t, move = args
+    os.environ["OMP_NUM_THREADS"] = str(threads)
+    if root not in sys.path:
+        sys.path.insert(0, root)
+    from oracle import oracle as O
+    O.use_timing_build()
+    o = O.OracleSystem(params, x, type_, mol, tag, nsalt, n_mol=n_mol, cap=len(type_) + 8)
+    t0 = time.perf_counter()
+    rec = o.trial(t, move)
+    return time.perf_counter() - t0, rec["move"], rec["n_steps"]
+
+
+def cpu_baseline(w, n_steps, label, beta_mu):
+    """The FP64 oracle (its OpenMP timing build, on the host's cores) on one
+    trial of the workload's start state with N_f = n_steps."""
+    cores = host_cores()
+    params = dict(w.params, n_steps=n_steps, n_steps_min=0, n_steps_max=0, beta_mu=beta_mu)
+    job = (ROOT, cores, params, w.x, w.type, w.mol, w.tag, w.nsalt, w.n_mol, 0, 1)
+    with mp.get_context("spawn").Pool(1) as pool:
+        dt, move, nf = pool.apply(_oracle_trial, (job,))
+    atom_steps = w.n * nf
+    return {"value": atom_steps / dt, "unit": "atom-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"1 insertion trial of {label} with N_f = {nf} ({atom_steps:.3g} atom-steps, {dt:.1f} s), "
+                      f"OpenMP build of the oracle on {cores} threads",
+            "trials_per_s": 1.0 / dt}
+
+
+# ---------------------------------------------------------------------------
+# Acceptance statistics of trial records
+# ---------------------------------------------------------------------------
+def expected_acceptance(recs, move=0):
+    """Mean Metropolis acceptance min(1, exp(ln R)) of the records (of one
+    kind of move if given): an estimator of the acceptance rate with far less
+    variance than the count of accepted trials when acceptance is rare."""
     vals = []
     for r in recs:
+        if move and r.move != move:
+            continue
         lr = r.ln_ratio
         vals.append(0.0 if (r.flags & 0x3) or not math.isfinite(lr) else math.exp(min(0.0, lr)))
-    return sum(vals) / max(1, len(vals))
+    return sum(vals) / max(1, len(vals)), len(vals)
 
 
-def jarzynski_beta_mu(dH, beta, volume, n_pairs):
-    """Operating chemical potential of the current state: the beta mu at
-    which the mean insertion ratio of Eq. (6), exp(-beta dH + beta mu + I),
-    is 1 over the pilot insertions (I = 2 ln(V / (N + 1)), Lambda = 1)."""
-    x = [-beta * d for d in dH if math.isfinite(d)]
-    m = max(x)
-    lme = m + math.log(sum(math.exp(v - m) for v in x) / len(x))
-    return -2.0 * math.log(volume / (n_pairs + 1)) - lme
+def arm_summary(recs, wall, rounds=None):
+    n = len(recs)
+    atom_steps = sum(r.n_atoms * r.n_steps for r in recs)
+    acc = sum(r.accepted for r in recs)
+    ins = [r for r in recs if r.move > 0]
+    dels = [r for r in recs if r.move < 0]
+    lo, hi = wilson(acc, n)
+    e_all, _ = expected_acceptance(recs)
+    e_ins, n_ins = expected_acceptance(recs, 1)
+    e_del, n_del = expected_acceptance(recs, -1)
+    ns = [r.n_salt_after for r in recs]
+    out = {
+        "atom_steps_per_s": atom_steps / wall, "trials": n, "wall_s": wall, "trials_per_s": n / wall,
+        "accepted": acc, "accepted_exchanges_per_s": acc / wall,
+        "p_acc": acc / max(1, n), "p_acc_wilson95": [lo, hi],
+        "insertions": n_ins, "insertions_accepted": sum(r.accepted for r in ins),
+        "deletions": n_del, "deletions_accepted": sum(r.accepted for r in dels),
+        "p_ins_wilson95": list(wilson(sum(r.accepted for r in ins), len(ins))),
+        "p_del_wilson95": list(wilson(sum(r.accepted for r in dels), len(dels))),
+        "expected_p_ins": e_ins, "expected_p_del": e_del,
+        "expected_exchanges_per_s": e_all * n / wall,
+        "n_salt_first": recs[0].n_salt_before if recs else None, "n_salt_last": ns[-1] if ns else None,
+        "n_salt_mean": sum(ns) / max(1, len(ns)),
+        "retried_trials": sum(1 for r in recs if r.flags & 0x4),
+    }
+    if rounds is not None:
+        out["rounds"] = rounds
+    return out
 
 
-def choose_proposal(logits, bdH, c, ks=(4, 8, 16, 32, 64), scales=(0.25, 0.5, 1.0), margin=1.25,
-                    draws=20000, seed=7):
-    """(k, weight scale) of the learned proposal with the highest insertion
-    acceptance, estimated from pilot insertions (out-of-fold network logit
-    s_i and beta dH_i of sites drawn uniformly): each simulated move draws k
-    pilot sites, picks one with probability proportional to
-    exp(scale min(s, 10)) and takes min(1, exp(c - beta dH + ln(W/k) - log
-    weight)), c = beta mu + I.  k stays at most an eighth of the pilot so
-    that the resampled candidate sets do not repeat the same few sites.  The
-    uniform proposal (scale 0) is kept unless the best pair beats it by the
-    margin: rare acceptances make these estimates noisy."""
-    import numpy as np
-    if logits is None or len(logits) < 32:
-        return 1, 0.0, {}
-    rng = np.random.default_rng(seed)
-    s = np.minimum(np.asarray(logits, dtype=np.float64), 10.0)
-    bdH = np.asarray(bdH, dtype=np.float64)
-    bdH = np.where(np.isfinite(bdH), bdH, np.inf)     # an overlap is never accepted
-    m = len(s)
-    est = {"uniform": float(np.mean(np.exp(np.minimum(0.0, c - bdH))))}
-    best = (1, 0.0, est["uniform"] * margin)
-    for k in ks:
-        if 8 * k > m:
-            continue
-        idx = rng.integers(0, m, size=(draws, k))
-        for scale in scales:
-            lw = scale * s[idx]
-            mx = lw.max(axis=1, keepdims=True)
-            p = np.exp(lw - mx)
-            lnWk = (mx[:, 0] + np.log(p.sum(axis=1))) - math.log(k)
-            cum = np.cumsum(p, axis=1)
-            u = rng.random(draws) * cum[:, -1]
-            sel = np.minimum((cum < u[:, None]).sum(axis=1), k - 1)
-            j = idx[np.arange(draws), sel]
-            lnR = c - bdH[j] + lnWk - lw[np.arange(draws), sel]
-            a = float(np.mean(np.exp(np.minimum(0.0, lnR))))
-            est[f"k{k}_scale{scale}"] = a
-            if a > best[2]:
-                best = (k, scale, a)
-    return best[0], best[1], est
+def timed(torch, fn):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t0
+
+
+# ---------------------------------------------------------------------------
+# Pilot, chemical potential, network and its weighting
+# ---------------------------------------------------------------------------
+def pilot(sys_, h4d, n_ins, n_del):
+    """Forced uniform insertions (beta mu = -1000) and deletions (+1000) on
+    the handle's state: never accepted, so the state stays fixed.  Returns
+    the records and each moved site's 64 features."""
+    sys_.set_proposal(None, 1)          # equal weights, k = 1: uniform, features recorded
+    out = {}
+    for key, move, bm, n in (("ins", h4d.MOVE_INSERT, -1.0e3, n_ins), ("del", h4d.MOVE_DELETE, 1.0e3, n_del)):
+        sys_.set_beta_mu(bm)
+        recs, feats = [], []
+        for _ in range(n):
+            recs.append(sys_.trial(move))
+            feats.append(sys_.last_site_features())
+        out[key] = (recs, feats, bm)
+    sys_.set_proposal(None, 0)
+    return out
+
+
+def ln_ratio_at(rec, beta_mu_rec, beta_mu):
+    """ln R of a record moved from the beta mu it ran at to another one
+    (an insertion's ln R rises with beta mu, a deletion's falls)."""
+    lr = rec["ln_ratio"]
+    if rec["flags"] & 0x3 or not math.isfinite(lr):
+        return -math.inf
+    return lr + (beta_mu - beta_mu_rec) * (1.0 if rec["move"] > 0 else -1.0)
 
 
 def train_network(h4d, X, y, epochs, seed=1):
@@ -236,8 +268,7 @@ def train_network(h4d, X, y, epochs, seed=1):
 
 
 def out_of_fold(h4d, X, y, epochs, folds=5):
-    """Logits of every pilot site from a network trained without it
-    (folds-fold cross validation)."""
+    """Logits of every pilot site from a network trained without it."""
     import numpy as np
     oof = np.zeros(len(X))
     fold = np.arange(len(X)) % folds
@@ -249,75 +280,90 @@ def out_of_fold(h4d, X, y, epochs, folds=5):
     return oof
 
 
+def choose_scale(s_ins, lr_ins, s_del, lr_del, cap=10.0, scales=(0.25, 0.5, 0.75, 1.0), margin=1.25):
+    """Weight scale of the multiple-try proposal at many candidates, from
+    uniform pilot moves: with k large, the chosen site is drawn from
+    q(y) ~ exp(lw(y)) over uniform sites and ln(W/k) tends to ln Z,
+    Z = E_uniform[exp(lw)], so the mean insertion acceptance is
+    sum_i e^lw_i min(1, e^(lnR_i + lnZ - lw_i)) / sum_i e^lw_i (importance
+    weights over the pilot insertions) and the mean deletion acceptance
+    mean_j min(1, e^(lnR_j + lw_j - lnZ)); lw = scale min(s, cap), s the
+    network's logits (out-of-fold for the insertions).  The uniform proposal
+    (scale 0) is kept unless the best scale beats it by the margin."""
+    import numpy as np
+    s_ins = np.minimum(np.asarray(s_ins, np.float64), cap)
+    s_del = np.minimum(np.asarray(s_del, np.float64), cap)
+    lr_ins = np.asarray(lr_ins, np.float64)
+    lr_del = np.asarray(lr_del, np.float64)
+
+    def est(scale):
+        lw_i, lw_d = scale * s_ins, scale * s_del
+        m = lw_i.max()
+        wi = np.exp(lw_i - m)
+        lnZ = m + math.log(wi.mean())
+        p_ins = float((wi * np.exp(np.minimum(0.0, lr_ins + lnZ - lw_i))).sum() / wi.sum())
+        p_del = float(np.mean(np.exp(np.minimum(0.0, lr_del + lw_d - lnZ))))
+        return p_ins, p_del
+
+    table = {"uniform": est(0.0)}
+    best, best_v = 0.0, 0.5 * sum(table["uniform"]) * margin
+    for sc in scales:
+        table[f"scale{sc}"] = est(sc)
+        v = 0.5 * sum(table[f"scale{sc}"])
+        if v > best_v:
+            best, best_v = sc, v
+    return best, {k: {"p_ins": v[0], "p_del": v[1]} for k, v in table.items()}
+
+
 def proposal_ab(sys_, torch, h4d, arms, beta_mu, n_each, block=50):
     """Insertion and deletion acceptance of several proposals on one fixed
     state: forced moves at beta mu = -1000 (insertions) and +1000
     (deletions), which are never accepted, so the state does not change;
     each record's ln R is moved to the operating beta mu and the mean of
     min(1, R) taken.  The arms alternate in blocks so that they share the
-    same state and device conditions.  arms: name -> (net, k, scale, bias
-    (x_b, alpha_b) or None[, V_ex edge for early rejection])."""
-    out = {name: {"ins": [], "del": [], "dM_ins": [], "dM_del": [], "s": 0.0, "n": 0, "instant": 0} for name in arms}
+    same state and device conditions.  arms: name -> (net, k, scale)."""
+    out = {name: {"ins": [], "del": [], "s": 0.0, "n": 0} for name in arms}
     done = 0
     while done < n_each:
         nb = min(block, n_each - done)
-        for name, arm in arms.items():
-            net, k, scale, bias = arm[:4]
-            v_ex = arm[4] if len(arm) > 4 else 0.0
-            sys_.set_bias(0.0, 0.0)
-            sys_.set_early_rejection(0.0)
+        for name, (net, k, scale) in arms.items():
             if k > 0:
                 sys_.set_proposal(net, k, 10.0, scale)
             else:
                 sys_.set_proposal(None, 0)
-            if bias is not None:
-                sys_.set_bias(*bias)
-            if v_ex > 0.0:
-                sys_.set_early_rejection(v_ex)
             for move, bm, key in ((h4d.MOVE_INSERT, -1.0e3, "ins"), (h4d.MOVE_DELETE, 1.0e3, "del")):
                 sys_.set_beta_mu(bm)
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                arr = sys_.trials(nb, move, as_array=True)
-                torch.cuda.synchronize()
-                out[name]["s"] += time.perf_counter() - t0
+                arr, dt = timed(torch, lambda: sys_.trials(nb, move, as_array=True))
+                out[name]["s"] += dt
                 out[name]["n"] += nb
                 shift = (beta_mu - bm) * (1.0 if move > 0 else -1.0)
                 for q in range(nb):
                     r = arr[q]
                     ok = not (r.flags & 0x3) and math.isfinite(r.ln_ratio)
                     out[name][key].append(math.exp(min(0.0, r.ln_ratio + shift)) if ok else 0.0)
-                    out[name]["dM_" + key].append(r.dM if ok else math.nan)
-                    out[name]["instant"] += 1 if r.flags & 0x10 else 0
         done += nb
     sys_.set_proposal(None, 0)
-    sys_.set_bias(0.0, 0.0)
-    sys_.set_early_rejection(0.0)
     sys_.set_beta_mu(beta_mu)
     res = {}
     for name, o in out.items():
         p_ins = sum(o["ins"]) / max(1, len(o["ins"]))
         p_del = sum(o["del"]) / max(1, len(o["del"]))
         rate = o["n"] / max(1e-300, o["s"])
-        res[name] = {"p_insert": p_ins, "p_delete": p_del, "trials_per_s": rate, "dM": (o["dM_ins"], o["dM_del"]),
+        res[name] = {"p_insert": p_ins, "p_delete": p_del, "trials_per_s": rate,
                      "expected_exchanges_per_s": 0.5 * (p_ins + p_del) * rate,
-                     "insertions": len(o["ins"]), "deletions": len(o["del"]),
-                     "instant_share": o["instant"] / max(1, len(o["ins"]) + len(o["del"]))}
-    if "uniform" in out and "learned" in out:
-        res["gain"], res["gain_bootstrap90"] = ab_gain(out["uniform"], out["learned"])
-    if "uniform" in out and "bimodal" in out:
-        res["bimodal_gain"], res["bimodal_gain_bootstrap90"] = ab_gain(out["uniform"], out["bimodal"])
-    if "bimodal" in out and "bimodal_early" in out:
-        res["early_gain_over_bimodal"], res["early_gain_over_bimodal_bootstrap90"] = ab_gain(out["bimodal"],
-                                                                                             out["bimodal_early"])
+                     "insertions": len(o["ins"]), "deletions": len(o["del"])}
+    names = list(arms)
+    for other in names[1:]:
+        g, ci = ab_gain(out[names[0]], out[other])
+        res[f"gain_{other}"], res[f"gain_{other}_bootstrap90"] = g, ci
     return res
 
 
 def ab_gain(u, l, reps=2000, seed=11):
     """Ratio of expected exchanges per second (another proposal over the
-    uniform one) and its 90 % bootstrap interval (moves resampled within
-    each arm and kind); None when the uniform arm's expected acceptance is
-    below 1e-12 (the ratio is then meaningless)."""
+    first) and its 90 % bootstrap interval (moves resampled within each arm
+    and kind); None when the first arm's expected acceptance is below 1e-12
+    (the ratio is then meaningless)."""
     import numpy as np
     rng = np.random.default_rng(seed)
     rate_u, rate_l = u["n"] / u["s"], l["n"] / l["s"]
@@ -326,7 +372,7 @@ def ab_gain(u, l, reps=2000, seed=11):
         return 0.5 * (np.mean(pick(o["ins"])) + np.mean(pick(o["del"]))) * rate
 
     ident = np.asarray
-    if ex(u, rate_u, ident) < 1e-12:       # the uniform arm's acceptance underflows: no ratio
+    if ex(u, rate_u, ident) < 1e-12:
         return None, None
     g = ex(l, rate_l, ident) / ex(u, rate_u, ident)
     boot = []
@@ -340,409 +386,227 @@ def ab_gain(u, l, reps=2000, seed=11):
     return float(g), [float(lo), float(hi)]
 
 
-def timed_trials(sys_, torch, n):
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    arr = sys_.trials(n, as_array=True)
-    torch.cuda.synchronize()
-    return [arr[q] for q in range(n)], time.perf_counter() - t0
-
-
-# bimodal bias of the flying pair (x_b, alpha_b; Sec. II B 4): the paper's
-# aqueous NaCl choice (4 A, 0.1 / A^2), and a contact-distance bias for the
-# LJ ions (sigma = 1)
-BIAS = {"lj32k": (1.0, 2.0), "water": (4.0, 0.1)}
-# early rejection: edge of V_ex around the flying cation (LJ units; the water
-# box leaves it out to keep its run short)
-EARLY = {"lj32k": 1.2}
-
-SINGLE = {
-    "lj32k": ("config_lj_32k",
-              "lj32k: 32,000 LJ ions, density 0.3, 200-step NEMD pair insert/delete, FP32 pair arithmetic / "
-              "FP64 state, energies and work", "the 32,000-ion state",
-              dict(n_atoms=32000, density=0.3, n_steps_per_trial=200, dt=0.005, w_max=2.5)),
-    "water": ("config_water_nacl",
-              "water: 8,000 rigid SPC/E waters + 150 NaCl pairs in a 62 A box, 298 K, 500-step NEMD NaCl-pair "
-              "insert/delete (dt 1 fs, w_max 3 A, kappa_sr 1/A), FP32 pair arithmetic / FP64 state, energies "
-              "and work", "the aqueous NaCl state",
-              dict(n_atoms=24300, n_waters=8000, n_pairs=150, box_A=62.0, n_steps_per_trial=500, dt_fs=1.0,
-                   w_max_A=3.0)),
-}
-
-
-def uniform_leg_speculative(args, h4d, torch, w, beta_mu):
-    """The uniform chain run speculatively on args.replicas copies of its
-    state (the records equal a one-by-one run of the same trials): timed
-    trials, then timing trials with HIP events on the step kernel.  Returns
-    (records, wall, timing, atom launches of the timing trials, info)."""
-    spec = h4d.Speculative.from_workload(w, args.replicas, beta_mu=beta_mu)
-    tuned = spec.autotune(2) if args.autotune else None
+# ---------------------------------------------------------------------------
+# The default workload: aqueous NaCl, learned vs plain
+# ---------------------------------------------------------------------------
+def bench_nacl(args, h4d, W, torch):
+    import numpy as np
+    from paper_2307_11447_amd import analysis
+    w = W.config_water_nacl()
+    w.params.update(capacity=w.n + 1024)
+    beta = 1.0 / w.params["kT"]
+    V = float(np.prod(w.params["box"]))
+    one = h4d.System.from_workload(w)
+    tuned = one.autotune(2) if args.autotune else None
     if tuned:
-        note(f"speculative autotune: {tuned[0]} lanes per atom, rebuild every {tuned[1]} steps")
-    if args.warmup:
-        spec.trials(args.warmup)
-    r0 = spec.rounds
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    arr = spec.trials(args.steps, as_array=True)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    rounds = spec.rounds - r0
-    recs = [arr[q] for q in range(args.steps)]
-    note(f"uniform, speculative: {args.steps} trials in {rounds} rounds of {args.replicas} replicas, {wall:.1f} s")
-    spec.set_timing(True)
-    r1 = spec.rounds
-    tarr = spec.trials(args.timing_trials, as_array=True)
-    timing = spec.timing()
-    spec.set_timing(False)
-    t_rounds = spec.rounds - r1
-    spec.close()
-    # every replica integrates its trial in every round
-    n_mean = sum(tarr[q].n_atoms for q in range(args.timing_trials)) / max(1, args.timing_trials)
-    nf = max(tarr[q].n_steps for q in range(args.timing_trials)) if args.timing_trials else 0
-    atom_launches = t_rounds * args.replicas * n_mean * (nf + 1)
-    info = {"mode": "speculative", "replicas": args.replicas, "rounds": rounds,
-            "trials_per_round": args.steps / max(1, rounds),
-            "note": "replicas of the state run the next trials side by side; the chain keeps them up to the "
-                    "first accepted one (the records equal a one-by-one run); value counts the chain's "
-                    "trials only"}
-    return recs, wall, timing, atom_launches, info
-
-
-def gcmd_leg(args, h4d, torch, w, beta_mu, tuned):
-    """The grand-canonical cycle of Fig. 1: an equilibrium phase of
-    args.n_eq steps (generalized hybrid MC with partial momentum refresh)
-    and one exchange trial that carries the state's momenta with the
-    symmetric two-end reversal, one cycle after another on one box."""
-    over = dict(beta_mu=beta_mu, momenta=1, md_refresh=args.md_refresh)
+        note(f"autotune: {tuned[0]} lanes per atom, rebuild every {tuned[1]} steps")
+    over = {}
     if tuned:
         over.update(lanes_per_atom=tuned[0], rebuild_every=tuned[1])
-    g = h4d.System.from_workload(w, **over)
-    g.md_phase(args.n_eq)
-    g.trial()
-    torch.cuda.synchronize()
+    # pilot on the start state (the autotuner's trials left it unchanged
+    # unless one was accepted: take the state as it is now)
+    st = one.state()
     t0 = time.perf_counter()
-    md_recs, tr_recs = [], []
-    t_md = 0.0
-    for _ in range(args.gcmd_cycles):
-        t1 = time.perf_counter()
-        md_recs.append(g.md_phase(args.n_eq)[0])
-        torch.cuda.synchronize()
-        t_md += time.perf_counter() - t1
-        tr_recs.append(g.trial())
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    g.close()
-    n_md = sum(r["accepted"] for r in md_recs)
-    n_tr = sum(r["accepted"] for r in tr_recs)
-    steps = sum(r["n_atoms"] * (r["n_steps"] + 1) for r in md_recs + tr_recs)
-    note(f"gcmd: {args.gcmd_cycles} cycles of {args.n_eq} equilibrium steps and one trial in {wall:.1f} s")
-    carried = None
-    if args.gcmd_trials > 0 and args.replicas > 1:
-        # runs of trials with carried momenta from the same state: one after
-        # another, and on speculative replicas (the same records when the
-        # launch shape and rebuild interval are fixed)
-        runs = {}
-        for kind in ("one_by_one", "speculative"):
-            h = (h4d.System.from_workload(w, **over) if kind == "one_by_one"
-                 else h4d.Speculative.from_workload(w, args.replicas, **over))
-            h.trials(4)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            recs = h.trials(args.gcmd_trials)
-            torch.cuda.synchronize()
-            runs[kind] = (recs, time.perf_counter() - t1, getattr(h, "rounds", None))
-            h.close()
-        (ra, wa, _), (rb, wb, rounds) = runs["one_by_one"], runs["speculative"]
-        same = all(a == dict(b, n_rebuilds=a["n_rebuilds"]) for a, b in zip(ra, rb)) if tuned else None
-        carried = {"trials": args.gcmd_trials, "replicas": args.replicas,
-                   "one_by_one_trials_per_s": len(ra) / wa, "speculative_trials_per_s": len(rb) / wb,
-                   "speedup": wa / max(wb, 1e-300), "accepted": sum(r["accepted"] for r in rb),
-                   "records_equal": same}
-        note(f"gcmd: {args.gcmd_trials} carried-momentum trials, one by one {wa:.1f} s, on {args.replicas} "
-             f"replicas {wb:.1f} s, records equal: {same}")
-    p_tr = n_tr / max(1, len(tr_recs))
-    nf = tr_recs[0]["n_steps"] if tr_recs else 0
-    return {
-        "cycle": f"equilibrium phase of {args.n_eq} steps (partial momentum refresh c = {args.md_refresh}, "
-                 "Metropolis on dH) + one trial with carried momenta and the two-end reversal",
-        "cycles": args.gcmd_cycles, "wall_s": wall, "ms_per_cycle": 1e3 * wall / max(1, args.gcmd_cycles),
-        "equilibrium_share_of_wall": t_md / max(wall, 1e-300),
-        "atom_steps_per_s": steps / max(wall, 1e-300),
-        "equilibrium_acceptance": n_md / max(1, len(md_recs)),
-        "equilibrium_mean_abs_beta_dH": sum(abs(r["dH"]) for r in md_recs) / max(1, len(md_recs)) / w.params["kT"],
-        "trials_accepted": n_tr, "trial_acceptance": p_tr,
-        "efficiency_per_step": p_tr / max(1, nf + args.n_eq),
-        "carried_momentum_trials": carried,
-    }
-
-
-def bench_single(args, h4d, W, torch):
-    import numpy as np
-    maker, desc, label, shape = SINGLE[args.workload]
-    w = getattr(W, maker)()
-    w.params.update(capacity=w.n + 1024)
-    if args.rebuild_every:
-        w.params.update(rebuild_every=args.rebuild_every)
-    if args.lanes:
-        w.params.update(lanes_per_atom=args.lanes)
-    if args.skin > 0:
-        w.params.update(skin=args.skin)
-    speculative = args.replicas > 1
-    sys_ = h4d.System.from_workload(w)
-    tuned = sys_.autotune(4 if args.workload == "lj32k" else 2) if args.autotune else None
-    if tuned:
-        note(f"autotune: {tuned[0]} lanes per atom, rebuild every {tuned[1]} steps")
-    if args.warmup:
-        sys_.trials(args.warmup)
-    # pilot: forced uniform insertions that are never accepted (beta mu far
-    # below equilibrium), recording each site's features and dH
-    sys_.set_beta_mu(-1.0e3)
-    sys_.set_proposal(None, 1)
-    feats, dH = [], []
-    t0 = time.perf_counter()
-    for _ in range(args.pilot):
-        r = sys_.trial(h4d.MOVE_INSERT)
-        feats.append(sys_.last_site_features())
-        dH.append(r["dH"])
+    pil = pilot(one, h4d, args.pilot, args.pilot_del)
     pilot_s = time.perf_counter() - t0
-    note(f"pilot: {args.pilot} insertions in {pilot_s:.1f} s")
-    st = sys_.state()
-    beta = 1.0 / w.params["kT"]
-    L = w.params["box"][0]
-    bmu_eq = jarzynski_beta_mu(dH, beta, L ** 3, st["nsalt"]) if dH else None
-    if args.beta_mu is None and bmu_eq is None:
-        raise SystemExit("bench.py: --pilot 0 needs --beta-mu")
-    beta_mu = args.beta_mu if args.beta_mu is not None else bmu_eq
-    c = beta_mu + 2.0 * math.log(L ** 3 / (st["nsalt"] + 1))
-    # the network learns the clipped log insertion ratio c - beta dH of the
-    # pilot sites (GPU, FP32); out-of-fold logits choose k and the scale
-    # (no pilot, or one too small for cross validation, keeps the uniform
-    # proposal)
-    net = None
-    k_sel, scale_sel, est, oof_corr, steps, train_s, losses = 1, 0.0, {}, None, 0, 0.0, np.zeros(1)
-    if len(feats) > 0:
-        X = np.array(feats, dtype=np.float32)
-        bdH = beta * np.array(dH)
-        ok = np.isfinite(bdH)
-        X, bdH = X[ok], bdH[ok]
-        y = np.clip(c - bdH, -100.0, 10.0).astype(np.float32)
-        t0 = time.perf_counter()
-        oof = out_of_fold(h4d, X, y, args.train_epochs) if len(X) >= 40 else None
-        k_sel, scale_sel, est = choose_proposal(oof, bdH, c, ks=tuple(k for k in (4, 8, 16, 32, 64)
-                                                                       if k <= args.candidates))
-        net, steps, losses = train_network(h4d, X, y, args.train_epochs)
-        torch.cuda.synchronize()
-        train_s = time.perf_counter() - t0
-        oof_corr = float(np.corrcoef(oof, y)[0, 1]) if oof is not None and np.std(oof) > 0 else None
-        note(f"network: out-of-fold correlation {oof_corr}, chose k = {k_sel}, scale = {scale_sel}")
-    # uniform proposal, one trial after another on the single box (the
-    # reference of the speculative leg; the timed leg itself when it is off)
-    sys_.set_beta_mu(beta_mu)
-    sys_.set_proposal(None, 0)
-    seq_n = min(args.seq_steps, args.steps) if speculative else args.steps
-    seq_recs, seq_wall = timed_trials(sys_, torch, seq_n)
-    note(f"uniform, one by one: {seq_n} trials in {seq_wall:.1f} s")
-    # the learned proposal from the state the uniform run reached (the plain
-    # uniform proposal when the pilot favours no weighting)
-    if scale_sel > 0.0:
-        sys_.set_proposal(net, k_sel, 10.0, scale_sel)
-    lrecs, lwall = timed_trials(sys_, torch, args.learned_steps)
-    note(f"learned: {args.learned_steps} trials in {lwall:.1f} s")
-    sys_.set_proposal(None, 0)
-    # both proposals on the state the chains reached, alternating, with
-    # forced moves that leave it unchanged
-    arms = {"uniform": (None, 0, 0.0, None)}
-    if scale_sel > 0.0:
-        arms["learned"] = (net, k_sel, scale_sel, None)
-    arms["bimodal"] = (None, 0, 0.0, BIAS[args.workload])
-    if args.workload in EARLY:   # the bias with early rejection of pairs in contact
-        arms["bimodal_early"] = (None, 0, 0.0, BIAS[args.workload], EARLY[args.workload])
-    ab = proposal_ab(sys_, torch, h4d, arms, beta_mu, args.ab_trials) if args.ab_trials > 0 else None
-    works = None
-    if ab is not None:
+    note(f"pilot: {args.pilot} insertions and {args.pilot_del} deletions in {pilot_s:.1f} s")
+    ins_recs, ins_feat, bm_ins = pil["ins"]
+    del_recs, del_feat, bm_del = pil["del"]
+    dM_ins = [r["dM"] for r in ins_recs if not r["flags"] & 0x3]
+    dM_del = [r["dM"] for r in del_recs if not r["flags"] & 0x3]
+    cal = analysis.work_summary(dM_ins, dM_del, beta, 0.0)
+    beta_mu = args.beta_mu if args.beta_mu is not None else cal["beta_mu_bar"]
+    cal = analysis.work_summary(dM_ins, dM_del, beta, beta_mu)
+    cal["note"] = ("uniform forced insertions and deletions on the start state (none accepted): beta mu from "
+                   "Bennett's acceptance ratio, P_acc predicted by Eq. (21) at the operating beta mu")
+    note(f"BAR: beta mu = {cal['beta_mu_bar']:.3f} {cal['beta_mu_bar_bootstrap90']}; operating at {beta_mu:.3f}")
+    # the network: target the clipped log insertion ratio at the operating
+    # point, c - beta dH with c = beta mu + I
+    c = beta_mu + 2.0 * math.log(V / (st["nsalt"] + 1))
+    X = np.array(ins_feat, dtype=np.float32)
+    bdH = beta * np.array([r["dH"] for r in ins_recs])
+    ok = np.isfinite(bdH) & np.array([not r["flags"] & 0x3 for r in ins_recs])
+    X, bdH = X[ok], bdH[ok]
+    y = np.clip(c - bdH, -100.0, 10.0).astype(np.float32)
+    t0 = time.perf_counter()
+    oof = out_of_fold(h4d, X, y, args.train_epochs)
+    net, steps, losses = train_network(h4d, X, y, args.train_epochs)
+    s_del = net.forward(np.array(del_feat, dtype=np.float32))
+    train_s = time.perf_counter() - t0
+    lr_ins = [ln_ratio_at(r, bm_ins, beta_mu) for r, k in zip(ins_recs, ok) if k]
+    lr_del = [ln_ratio_at(r, bm_del, beta_mu) for r in del_recs]
+    scale, estimates = choose_scale(oof, lr_ins, s_del, lr_del)
+    if args.scale is not None:
+        scale = args.scale
+    oof_corr = float(np.corrcoef(oof, y)[0, 1]) if np.std(oof) > 0 else None
+    note(f"network: out-of-fold correlation {oof_corr}, weight scale {scale} at k = {args.candidates}")
+    # the timed arms: the same chain from the same state on speculative replicas
+    arms = {}
+    learned_timing = None
+    for name in ("plain", "learned"):
+        spec = h4d.Speculative.from_workload(w, args.replicas, beta_mu=beta_mu, **over)
+        if name == "learned":
+            spec.set_proposal(net, args.candidates, 10.0, scale)
+        if args.warmup:
+            spec.trials(args.warmup)
+        r0 = spec.rounds
+        arr, wall = timed(torch, lambda: spec.trials(args.steps, as_array=True))
+        recs = [arr[q] for q in range(args.steps)]
+        arms[name] = arm_summary(recs, wall, spec.rounds - r0)
+        note(f"{name}: {args.steps} trials in {wall:.2f} s, {arms[name]['accepted']} accepted")
+        if name == "learned":
+            spec.set_timing(True)
+            spec.trials(args.timing_trials)
+            learned_timing = spec.timing()
+            spec.set_timing(False)
+        spec.close()
+    # both proposals on the start state, forced moves alternating in blocks
+    ab = None
+    if args.ab_trials > 0:
+        one.set_beta_mu(beta_mu)
+        ab = proposal_ab(one, torch, h4d, {"plain": (None, 0, 0.0), "learned": (net, args.candidates, scale)},
+                         beta_mu, args.ab_trials)
         note(f"fixed-state comparison: {args.ab_trials} insertions and deletions per proposal")
-        works = ab["uniform"]["dM"]
-        for name in arms:
-            ab[name].pop("dM")
-    # step-kernel duration: further trials with HIP events around every
-    # launch of the fused step kernel (on the library's stream)
-    n_seq_timing = args.timing_trials if seq_n > 0 else 0
-    sys_.set_timing(True)
-    tarr = sys_.trials(n_seq_timing, as_array=True)
-    seq_timing = sys_.timing()
-    sys_.set_timing(False)
-    sys_.close()
-    if net is not None:
-        net.close()
-    gcmd = gcmd_leg(args, h4d, torch, w, beta_mu, tuned) if args.gcmd_cycles > 0 and not w.params["water"] else None
-    traffic = counted_traffic(TRAFFIC_FILE) if args.workload == "lj32k" else None
-    seq_timing_recs = [tarr[q] for q in range(n_seq_timing)]
-    if speculative:
-        recs, wall, timing, atom_launches, execution = uniform_leg_speculative(args, h4d, torch, w, beta_mu)
-        out = summarize(recs, wall, timing, None, traffic, atom_launches=atom_launches)
-        if seq_n > 0:
-            seq = summarize(seq_recs, seq_wall, seq_timing, seq_timing_recs, None)
-            out["sequential"] = {k: seq[k] for k in ("value", "trials_per_s", "accepted",
-                                                     "accepted_exchanges_per_s", "p_acc", "rebuild_every",
-                                                     "lanes_per_atom")}
-            out["sequential"]["trials"] = seq_n
-            out["sequential"]["expected_exchanges_per_s"] = expected_acceptance(seq_recs) * seq["trials_per_s"]
-            out["sequential"]["roofline"] = {k: seq["roofline"][k] for k in ("achieved", "frac", "avg_kernel_us",
-                                                                              "mean_list_entries")}
-    else:
-        recs, wall = seq_recs, seq_wall
-        execution = {"mode": "one trial after another"}
-        out = summarize(recs, wall, seq_timing, seq_timing_recs, traffic)
-    out["execution"] = execution
-    out["expected_acceptance"] = expected_acceptance(recs)
-    out["expected_exchanges_per_s"] = out["expected_acceptance"] * out["trials_per_s"]
-    l_acc = sum(r.accepted for r in lrecs)
-    lo, hi = wilson(l_acc, len(lrecs))
-    l_exp = expected_acceptance(lrecs)
-    l_rate = len(lrecs) / max(lwall, 1e-300)
-    seq_exp = expected_acceptance(seq_recs) * len(seq_recs) / max(seq_wall, 1e-300) if seq_recs else 0.0
-    out["learned"] = {
-        "proposal": (f"multiple-try, k = {k_sel} candidates weighted by exp({scale_sel} min(s, 10)), s the "
-                     "trained network's logit (BF16 matrix-core inference)" if scale_sel > 0.0 else
-                     "uniform: on the pilot's out-of-fold logits no (k, scale) beat it by the margin"),
-        "execution": "one trial after another (single box)",
-        "candidates": k_sel, "weight_scale": scale_sel,
-        "choice_estimates": est,
-        "value": sum(r.n_atoms * r.n_steps for r in lrecs) / max(lwall, 1e-300), "unit": "atom-steps/s",
-        "trials": len(lrecs), "trials_per_s": l_rate,
-        "accepted": l_acc, "accepted_exchanges_per_s": l_acc * l_rate / max(1, len(lrecs)),
-        "p_acc": l_acc / max(1, len(lrecs)), "p_acc_wilson95": [lo, hi],
-        "expected_acceptance": l_exp, "expected_exchanges_per_s": l_exp * l_rate,
-        "gain_expected_exchanges_per_s_vs_one_by_one_uniform": l_exp * l_rate / max(1e-300, seq_exp),
-        "pilot_insertions": args.pilot, "pilot_s": pilot_s, "train_steps": steps, "train_s": train_s,
-        "train_loss_first": float(losses[:10].mean()), "train_loss_last": float(losses[-50:].mean()),
-        "target": "clip(beta mu + I - beta dH, -100, 10)",
-        "fixed_state_comparison": ab,
-        "fixed_state_gain": ab.get("gain", 1.0 if scale_sel == 0.0 else None) if ab is not None else None,
-        "fixed_state_gain_bootstrap90": ab.get("gain_bootstrap90") if ab is not None else None,
-        "out_of_fold_corr_logit_vs_target": oof_corr,
+    one.close()
+    net.close()
+    la, pa = arms["learned"], arms["plain"]
+    out = {
+        "value": la["atom_steps_per_s"], "trials_per_s": la["trials_per_s"],
+        "accepted_exchanges_per_s": la["accepted_exchanges_per_s"],
+        "arms": arms,
+        "learned_vs_plain": {
+            "accepted_exchanges_per_s_ratio": (la["accepted_exchanges_per_s"] / pa["accepted_exchanges_per_s"]
+                                               if pa["accepted"] > 0 else None),
+            "expected_exchanges_per_s_ratio": (la["expected_exchanges_per_s"] / pa["expected_exchanges_per_s"]
+                                               if pa["expected_exchanges_per_s"] > 1e-12 else None),
+            "atom_steps_per_s_ratio": la["atom_steps_per_s"] / pa["atom_steps_per_s"],
+            "fixed_state": ab,
+            "note": "accepted counts are rare at the BAR beta mu with 500-step flights; the expected acceptance "
+                    "(mean of min(1, R) over the trials) and the fixed-state comparison carry the comparison",
+        },
+        "learned": {"candidates": args.candidates, "weight_scale": scale, "logit_cap": 10.0,
+                    "inference": "BF16 MFMA (v_mfma_f32_16x16x16_bf16), FP32 accumulation",
+                    "scale_choice_estimates": estimates, "out_of_fold_corr_logit_vs_target": oof_corr,
+                    "pilot_insertions": args.pilot, "pilot_deletions": args.pilot_del, "pilot_s": pilot_s,
+                    "train_rows": int(len(X)), "train_steps": steps, "train_s": train_s,
+                    "train_loss_first": float(losses[:10].mean()), "train_loss_last": float(losses[-50:].mean()),
+                    "target": "clip(beta mu + I - beta dH, -100, 10) of the pilot insertions"},
+        "mu_calibration": cal,
+        "roofline": roofline(learned_timing, counted_traffic(TRAFFIC_FILES["water"]),
+                             "k_step<1,L> (fused pair force + velocity Verlet), learned arm"),
+        "lanes_per_atom": learned_timing["lanes"], "rebuild_every": learned_timing["rebuild_every"],
+        "execution": {"mode": "speculative", "replicas": args.replicas},
     }
-    if gcmd is not None:
-        out["gcmd"] = gcmd
-    out["bimodal_bias"] = {
-        "x_b": BIAS[args.workload][0], "alpha_b": BIAS[args.workload][1],
-        "note": "the paper's bias of the flying pair's separation (Sec. II B 4), in the fixed-state comparison",
-        "fixed_state_gain": ab.get("bimodal_gain") if ab is not None else None,
-        "fixed_state_gain_bootstrap90": ab.get("bimodal_gain_bootstrap90") if ab is not None else None,
-    }
-    if ab is not None and "bimodal_early" in ab:
-        out["early_rejection"] = {
-            "v_ex_edge": EARLY[args.workload],
-            "note": "the bias with early rejection (pairs whose anion lies in the cube V_ex around the cation are "
-                    "exchanged instantly, no trajectory), in the fixed-state comparison",
-            "instant_share": ab["bimodal_early"]["instant_share"],
-            "gain_over_bias_alone": ab.get("early_gain_over_bimodal"),
-            "gain_over_bias_alone_bootstrap90": ab.get("early_gain_over_bimodal_bootstrap90"),
-        }
-    # the chemical potential and the predicted acceptance from the uniform
-    # arm's work distributions (Crooks' theorem solved by BAR, Eq. 21)
-    if works is not None:
-        from paper_2307_11447_amd import analysis
-        cal = analysis.work_summary(works[0], works[1], beta, beta_mu)
-        cal["note"] = ("uniform forced insertions and deletions on one fixed state (no move accepted): "
-                       "beta mu from BAR, P_acc predicted by Eq. (21) at the operating beta mu")
-        cal["beta_mu_operating"] = beta_mu
-        cal["observed_p_acc_uniform"] = (sum(r.accepted for r in recs) / len(recs)) if recs else None
-        out["mu_calibration"] = cal
-    config = dict({"workload": desc + "; value: uniform proposal" +
-                   (f", {args.replicas} speculative replicas of the one chain" if speculative else "") +
-                   "; 'learned': the trained multiple-try proposal from the same state"}, **shape)
-    config.update({
+    config = {
+        "workload": "aqueous NaCl + learned proposal: 8,000 rigid SPC/E waters + 150 NaCl pairs in a 62 A box, "
+                    "298 K, 500-step NEMD NaCl-pair insert/delete (dt 1 fs, w_max 3 A, kappa_sr 1/A, DSF alpha "
+                    "0.25/A cut 10 A), FP32 pair arithmetic / FP64 state, energies and work; learned arm: "
+                    f"multiple-try over {args.candidates} candidate sites scored by a 64-3x128-1 network (BF16), "
+                    f"plain arm: uniform; each arm one chain on {args.replicas} speculative replicas",
+        "n_atoms": w.n, "n_waters": 8000, "n_pairs": 150, "box_A": 62.0, "n_steps_per_trial": 500,
+        "dt_fs": 1.0, "w_max_A": 3.0, "candidates": args.candidates,
         "beta_mu": beta_mu, "beta_mu_source": "given" if args.beta_mu is not None else
-        "Jarzynski estimate from the pilot insertions (equilibrium operating point)",
-        "beta_mu_jarzynski": bmu_eq,
-        "skin": w.params["skin"], "proposal": "uniform", "parallelism": "single chain, one GPU",
-    })
-    base = None if args.no_cpu_baseline else cpu_baseline(w, args.cpu_steps, label)
+        "Bennett's acceptance ratio over the pilot insertions and deletions",
+        "skin": w.params["skin"], "parallelism": f"one chain, {args.replicas} speculative replicas, one GPU",
+    }
+    base = None if args.no_cpu_baseline else cpu_baseline(w, args.cpu_steps or 60, "the aqueous NaCl state",
+                                                          beta_mu)
     return out, config, base
 
 
-def bench_batched(args, h4d, W, torch):
+# ---------------------------------------------------------------------------
+# The 32,000-ion LJ chain and the 256-box batch
+# ---------------------------------------------------------------------------
+def leg_lj32k(args, h4d, W, torch, steps, warmup, timing_trials):
+    w = W.config_lj_32k()
+    w.params.update(capacity=w.n + 1024, beta_mu=args.lj_beta_mu)
+    spec = h4d.Speculative.from_workload(w, args.replicas)
+    tuned = spec.autotune(2) if args.autotune else None
+    if warmup:
+        spec.trials(warmup)
+    r0 = spec.rounds
+    arr, wall = timed(torch, lambda: spec.trials(steps, as_array=True))
+    out = arm_summary([arr[q] for q in range(steps)], wall, spec.rounds - r0)
+    spec.set_timing(True)
+    spec.trials(timing_trials)
+    tm = spec.timing()
+    spec.close()
+    out["value"] = out.pop("atom_steps_per_s")
+    out["roofline"] = roofline(tm, counted_traffic(TRAFFIC_FILES["lj32k"]),
+                               "k_step<1,L> (fused pair force + velocity Verlet)")
+    out["lanes_per_atom"], out["rebuild_every"] = tm["lanes"], tm["rebuild_every"]
+    out["autotune"] = tuned
+    out["config"] = {"workload": "lj32k: 32,000 LJ ions, density 0.3, 200-step NEMD pair insert/delete, FP32 pair "
+                                 "arithmetic / FP64 state, uniform proposal, one chain on speculative replicas",
+                     "replicas": args.replicas, "beta_mu": args.lj_beta_mu}
+    note(f"lj32k: {steps} trials, {out['value']:.3g} atom-steps/s, frac {out['roofline']['frac']:.3f}")
+    return out, w
+
+
+def leg_batched(args, h4d, W, torch, steps, warmup, timing_trials, learned_k=0):
     ws = W.config_batched()
     for w in ws:
-        w.params.update(beta_mu=args.beta_mu, rebuild_every=args.rebuild_every, lanes_per_atom=args.lanes)
-        if args.skin > 0:
-            w.params.update(skin=args.skin)
+        w.params.update(beta_mu=args.batch_beta_mu)
+        if args.rebuild_every:
+            w.params.update(rebuild_every=args.rebuild_every)
+        if args.lanes:
+            w.params.update(lanes_per_atom=args.lanes)
     bat = h4d.Batch.from_workloads(ws)
     tuned = bat.autotune(1) if args.autotune else None
-    if tuned:
-        note(f"autotune: {tuned[0]} lanes per atom, rebuild every {tuned[1]} steps")
-    if args.warmup:
-        bat.run(args.warmup)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    arr = bat.run(args.steps, as_array=True)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    recs = [arr[q] for q in range(len(ws) * args.steps)]
+    if warmup:
+        bat.run(warmup)
+    arr, wall = timed(torch, lambda: bat.run(steps, as_array=True))
+    recs = [arr[q] for q in range(len(ws) * steps)]
+    out = arm_summary(recs, wall)
     bat.set_timing(True)
-    tarr = bat.run(args.timing_trials, as_array=True)
-    timing = bat.timing()
-    bat.set_timing(False)
+    bat.run(timing_trials)
+    tm = bat.timing()
     bat.close()
-    out = summarize(recs, wall, timing, [tarr[q] for q in range(len(ws) * args.timing_trials)],
-                    counted_traffic(TRAFFIC_FILE_BATCHED))
-    config = {
-        "workload": "batched256: 256 LJ-electrolyte boxes, N even in [1000, 16000] (2,220,126 ions), "
-                    "density U[0.1, 0.4], N_f ~ U{100..400} per trial, FP32 pair arithmetic / FP64 state, "
-                    "uniform proposal; every box runs its trial in one round of launches",
-        "n_boxes": len(ws), "n_atoms": sum(w.n for w in ws), "trials_per_box": args.steps,
-        "dt": 0.005, "w_max": 2.5, "beta_mu": args.beta_mu, "skin": ws[0].params["skin"],
-        "proposal": "uniform", "parallelism": "256 boxes, one GPU",
-    }
-    big = max(ws, key=lambda w: w.n)
-    base = None if args.no_cpu_baseline else cpu_baseline(big, args.cpu_steps,
-                                                          f"the largest box ({big.n} ions)")
-    return out, config, base
+    out["value"] = out.pop("atom_steps_per_s")
+    out["roofline"] = roofline(tm, counted_traffic(TRAFFIC_FILES["batched"]),
+                               "k_step<1,L> (fused pair force + velocity Verlet)")
+    out["lanes_per_atom"], out["rebuild_every"] = tm["lanes"], tm["rebuild_every"]
+    out["autotune"] = tuned
+    out["config"] = {"workload": "batched256: 256 LJ-electrolyte boxes, N even in [1000, 16000] (2,220,126 ions), "
+                                 "density U[0.1, 0.4], N_f ~ U{100..400} per trial, FP32 pair arithmetic / FP64 "
+                                 "state, uniform proposal; every box runs its trial in one round of launches",
+                     "n_boxes": len(ws), "n_atoms": sum(w.n for w in ws), "trials_per_box": steps,
+                     "beta_mu": args.batch_beta_mu}
+    note(f"batched256: {steps} trials per box, {out['value']:.3g} atom-steps/s, frac {out['roofline']['frac']:.3f}")
+    return out, ws
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=("lj32k", "water", "batched"), default="lj32k")
+    ap.add_argument("--workload", choices=("nacl", "lj32k", "batched"), default="nacl")
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed exchange trials (lj32k, default 2000) or trials per box (batched, default 20)")
-    ap.add_argument("--warmup", type=int, default=None, help="untimed trials first (default 20 / 2)")
+                    help="timed exchange trials per arm (nacl, default 20), of the chain (lj32k, default 400) or "
+                         "per box (batched, default 10)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed trials first (default 5 / 20 / 2)")
     ap.add_argument("--beta-mu", type=float, default=None,
-                    help="beta mu (default: lj32k, the Jarzynski estimate from the pilot; batched, -4)")
-    ap.add_argument("--pilot", type=int, default=None,
-                    help="single box: pilot insertions for the network (default 1200 / water 1000)")
-    ap.add_argument("--train-epochs", type=int, default=30, help="single box: passes over the pilot data")
-    ap.add_argument("--candidates", type=int, default=64,
-                    help="single box: largest candidate count the learned proposal may choose")
-    ap.add_argument("--learned-steps", type=int, default=None,
-                    help="single box: timed learned trials (default: as many as --steps)")
-    ap.add_argument("--replicas", type=int, default=8,
-                    help="single box: speculative replicas of the chain for the timed uniform trials (<= 1: "
-                         "one trial after another)")
-    ap.add_argument("--seq-steps", type=int, default=None,
-                    help="single box with replicas: one-by-one uniform trials timed for reference "
-                         "(default 300 / water 60)")
-    ap.add_argument("--ab-trials", type=int, default=None,
-                    help="single box: forced insertions and deletions per proposal on the final state "
-                         "(default 400)")
+                    help="nacl: beta mu (default: Bennett's acceptance ratio over the pilot moves)")
+    ap.add_argument("--lj-beta-mu", type=float, default=-8.8,
+                    help="lj32k: beta mu (default -8.8, the BAR estimate of the 32,000-ion state)")
+    ap.add_argument("--batch-beta-mu", type=float, default=-4.0, help="batched: beta mu")
+    ap.add_argument("--pilot", type=int, default=500, help="nacl: pilot insertions")
+    ap.add_argument("--pilot-del", type=int, default=250, help="nacl: pilot deletions")
+    ap.add_argument("--train-epochs", type=int, default=30, help="nacl: passes over the pilot data")
+    ap.add_argument("--candidates", type=int, default=CANDIDATES, help="nacl: candidate sites per learned move")
+    ap.add_argument("--scale", type=float, default=None, help="nacl: weight scale (default: chosen from the pilot)")
+    ap.add_argument("--replicas", type=int, default=8, help="speculative replicas of a single chain")
+    ap.add_argument("--ab-trials", type=int, default=150,
+                    help="nacl: forced insertions and deletions per proposal on the start state (0: none)")
     ap.add_argument("--timing-trials", type=int, default=None,
-                    help="trials run after the timed region with HIP events on the step kernel (20 / 2)")
-    ap.add_argument("--cpu-steps", type=int, default=12, help="oracle sample length (NEMD steps)")
-    ap.add_argument("--gcmd-cycles", type=int, default=10,
-                    help="single ion box: grand-canonical cycles (equilibrium phase + one trial) timed after the rest")
-    ap.add_argument("--n-eq", type=int, default=1000, help="steps of an equilibrium phase (the paper's N_eq)")
-    ap.add_argument("--gcmd-trials", type=int, default=200,
-                    help="trials with carried momenta timed one by one and on speculative replicas (0: none)")
-    ap.add_argument("--md-refresh", type=float, default=0.5, help="momentum persistence c of the equilibrium phase")
+                    help="trials after the timed region with HIP events on the step kernel (default 4 / 20 / 1)")
+    ap.add_argument("--cpu-steps", type=int, default=0,
+                    help="oracle sample length (N_f of its one trial; default 60 for nacl, the full flight for lj32k)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="nacl: leave out the lj32k and batched keys")
     ap.add_argument("--rebuild-every", type=int, default=0, help="list rebuild interval (0: library default)")
     ap.add_argument("--lanes", type=int, default=0, help="lanes per atom (0: library default)")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
-                    help="keep the library's lanes per atom and automatic rebuild interval instead of timing "
-                         "the choices first")
-    ap.add_argument("--skin", type=float, default=0.0, help="Verlet skin (0: workload default)")
+                    help="keep the library's lanes per atom and automatic rebuild interval")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run the stream-copy probe on MIB mebibytes and print its bandwidth")
     args = ap.parse_args()
@@ -752,24 +616,13 @@ def main():
               "boxes are independent Markov chains and would shard across GPUs without communication, "
               "but no multi-GPU path is built", file=sys.stderr)
         sys.exit(2)
-    batched = args.workload == "batched"
-    water = args.workload == "water"
+    wl = args.workload
     if args.steps is None:
-        args.steps = 20 if batched else (400 if water else 2000)
+        args.steps = {"nacl": 20, "lj32k": 400, "batched": 10}[wl]
     if args.warmup is None:
-        args.warmup = 2 if batched else (5 if water else 20)
+        args.warmup = {"nacl": 5, "lj32k": 20, "batched": 2}[wl]
     if args.timing_trials is None:
-        args.timing_trials = 2 if batched else (4 if water else 20)
-    if args.learned_steps is None:
-        args.learned_steps = args.steps
-    if args.pilot is None:
-        args.pilot = 1000 if water else 1200
-    if args.ab_trials is None:
-        args.ab_trials = 400
-    if args.seq_steps is None:
-        args.seq_steps = 60 if water else 300
-    if batched and args.beta_mu is None:
-        args.beta_mu = -4.0
+        args.timing_trials = {"nacl": 4, "lj32k": 20, "batched": 1}[wl]
 
     import torch
     from paper_2307_11447_amd import h4d
@@ -782,7 +635,27 @@ def main():
                           "GB_per_s": 2 * nbytes / (ms * 1e-3) / 1e9}), flush=True)
         return
 
-    out, config, base = (bench_batched if batched else bench_single)(args, h4d, W, torch)
+    extras = {}
+    if wl == "nacl":
+        out, config, base = bench_nacl(args, h4d, W, torch)
+        if not args.no_extras:
+            extras["lj32k"], w32 = leg_lj32k(args, h4d, W, torch, 100, 10, 5)
+            if not args.no_cpu_baseline:
+                extras["lj32k"]["cpu_baseline"] = cpu_baseline(w32, 200, "the 32,000-ion state",
+                                                               args.lj_beta_mu)
+            extras["batched256"], _ = leg_batched(args, h4d, W, torch, 2, 1, 1)
+    elif wl == "lj32k":
+        out, w32 = leg_lj32k(args, h4d, W, torch, args.steps, args.warmup, args.timing_trials)
+        config = out.pop("config")
+        base = None if args.no_cpu_baseline else cpu_baseline(w32, args.cpu_steps or 200, "the 32,000-ion state",
+                                                              args.lj_beta_mu)
+    else:
+        out, ws = leg_batched(args, h4d, W, torch, args.steps, args.warmup, args.timing_trials)
+        config = out.pop("config")
+        big = max(ws, key=lambda w: w.n)
+        base = None if args.no_cpu_baseline else cpu_baseline(big, args.cpu_steps or 100,
+                                                              f"the largest box ({big.n} ions)", args.batch_beta_mu)
+    n_boxes = config.get("n_boxes", 1)
     line = {
         "metric": METRIC,
         "value": out.pop("value"),
@@ -790,7 +663,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": None,
+        "ms_per_step": 1e3 / out["trials_per_s"] * n_boxes,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -798,8 +671,8 @@ def main():
         "data": "synthetic",
         "config": config,
     }
-    line["ms_per_step"] = 1e3 / out["trials_per_s"] * (config.get("n_boxes", 1))
     line.update(out)
+    line.update(extras)
     if base is not None:
         line["cpu_baseline"] = base
     print(json.dumps(line), flush=True)

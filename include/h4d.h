@@ -127,8 +127,9 @@ typedef struct h4d_params {
     int32_t momenta;            /* 0: every trial draws fresh Maxwell-Boltzmann
                                    momenta; 1: trials carry the state's momenta
                                    with the symmetric two-end reversal (Sec.
-                                   II A), to alternate with h4d_run_md (ions
-                                   only).  Speculative replicas start from
+                                   II A), to alternate with h4d_run_md (rigid
+                                   waters' momenta stay on the constraint
+                                   surface).  Speculative replicas start from
                                    the chain's momenta times the reversal
                                    signs of the trials before theirs         */
     double md_refresh;          /* c in [0, 1] of the equilibrium phase's
@@ -251,8 +252,11 @@ int32_t h4d_run_trials(h4d_system *sys, int32_t n, int32_t move, h4d_trial *out)
  * receives one record per box: move = H4D_MOVE_MD, trial = the phase index,
  * dH, dU, dK, H0, H1, ln_ratio = -beta dH, ln_u, accepted.  On a speculative
  * handle the phase runs on the first replica and the others take its state
- * (every record is that replica's).  Ion systems only (H4D_EINVAL with
- * water); n_steps >= 1.
+ * (every record is that replica's).  Rigid waters: the refreshed momenta are
+ * restricted to the constraint surface (the velocity constraint, which keeps
+ * the constrained Maxwell-Boltzmann distribution) and every step constrains
+ * positions and velocities as a trial's trajectory does; a phase whose
+ * constraints cannot be met is rejected (H4D_FLAG_NONFINITE).  n_steps >= 1.
  */
 int32_t h4d_run_md(h4d_system *sys, int32_t n_steps, h4d_trial *out);
 
@@ -425,8 +429,8 @@ int32_t h4d_forces_at(h4d_system *sys, const int32_t flying[2], double w,
  * Kernel timing for roofline measurements.  While enabled, every launch of
  * the fused NEMD step kernel is bracketed by HIP events on the handle's
  * stream (hipExtLaunchKernelGGL); h4d_get_timing returns the accumulated
- * device time of those launches, their count, and the mean Verlet-list
- * length of the current state.
+ * device time of those launches, their count, the atoms they integrated, and
+ * the mean Verlet-list length of the current state.
  */
 typedef struct h4d_timing {
     int64_t step_launches;
@@ -437,6 +441,9 @@ typedef struct h4d_timing {
     int32_t nbr_cap;       /* list capacity per atom                           */
     int32_t lanes;         /* lanes per atom                                   */
     int32_t cell_cap;      /* atoms per cell capacity                          */
+    double atom_launches;  /* atoms the timed step launches integrated: over
+                              every trajectory timed, (N_f + 1) launches times
+                              the atoms of its state                           */
 } h4d_timing;
 
 int32_t h4d_set_timing(h4d_system *sys, int32_t on);
@@ -460,17 +467,22 @@ int32_t h4d_autotune(h4d_system *sys, int32_t trials, int32_t *lanes_out, int32_
                      double *ns_per_atom_step);
 
 /*
- * Stream-copy probe (no handle needed): copies `bytes` bytes between two
- * device buffers with a plain 16-byte-per-lane copy kernel `reps` times and
- * returns the mean kernel time in *ms (HIP events).  Used to measure the
- * achievable HBM bandwidth and to calibrate hardware byte counters against a
- * kernel whose traffic is known (read `bytes`, write `bytes` per launch).
- * Allocates and frees its buffers; bytes must be a positive multiple of 16.
+ * MEASUREMENT ONLY, not part of the method: the stream-copy probe that
+ * calibrates the benchmark's hardware byte counters (no handle needed).  It
+ * copies `bytes` bytes between two device buffers with a plain
+ * 16-byte-per-lane copy kernel `reps` times and returns the mean kernel time
+ * in *ms (HIP events): the achievable HBM bandwidth, and a kernel whose
+ * traffic is known (read `bytes`, write `bytes` per launch) to scale the
+ * counters by.  Allocates and frees its buffers; bytes must be a positive
+ * multiple of 16.
  */
 int32_t h4d_stream_copy(int64_t bytes, int32_t reps, double *ms);
 
 /*
- * Learned insertion proposal (single-box handles).  A multiple-try form of
+ * Learned insertion proposal (every kind of handle: one box, a batch, or
+ * speculative replicas; each box scores its own candidates with its own
+ * Philox stream and trial index, and one matrix-core pass serves every box's
+ * candidates).  A multiple-try form of
  * the uniform pair insertion of Eq. (4), exact for any network: a bias on
  * the initial flying-ion positions (the paper notes one would help and
  * leaves it out, Sec. II B 1) with the ratio corrected in the Rosenbluth
@@ -527,8 +539,8 @@ int32_t h4d_mlp_loss_grad(h4d_mlp *net, int32_t rows, const float *features,
  * Training runs on standardized features (per-column mean and standard
  * deviation of the data); the affine map is folded into W1 and b1 before
  * return, so the network still reads raw features.  Each call starts a
- * fresh optimiser state.  Suggested target of a pilot insertion:
- * clip(-beta dH, -20, 10). */
+ * fresh optimiser state.  Suggested target of a pilot insertion: its
+ * clipped log ratio, clip(beta mu + I - beta dH, -100, 10). */
 int32_t h4d_mlp_train(h4d_mlp *net, int32_t rows, const float *features, const float *targets,
                       int32_t steps, int32_t batch, float lr, float weight_decay, uint64_t seed,
                       float *losses);
@@ -543,12 +555,16 @@ int32_t h4d_mlp_train(h4d_mlp *net, int32_t rows, const float *features, const f
  * proposal).  Any cap and scale keep the method exact. */
 int32_t h4d_set_proposal(h4d_system *sys, const h4d_mlp *net, int32_t k, double logit_cap,
                          double weight_scale);
-/* Features of the last trial's inserted or removed pair site (64 floats). */
+/* Features of the last trial's inserted or removed pair site (64 floats; box 0). */
 int32_t h4d_last_site_features(h4d_system *sys, float *out);
 /* The last learned move's candidates: sites[6k], features[64k], logits[k]
- * (host, any may be NULL); returns k (>= 0) or an error. */
+ * (host, any may be NULL); returns k (>= 0) or an error.  Box 0, or box
+ * `box` of a batch (a box with no learned move in its last trial keeps the
+ * candidates of an earlier one). */
 int32_t h4d_last_candidates(h4d_system *sys, int32_t cap, double *sites, float *features,
                             float *logits);
+int32_t h4d_last_box_candidates(h4d_system *sys, int32_t box, int32_t cap, double *sites,
+                                float *features, float *logits);
 /* Test hook: features of n given sites (sites[6n]: cation xyz, anion xyz)
  * on the current state (no flying atoms). */
 int32_t h4d_site_features(h4d_system *sys, int32_t n, const double *sites, float *features);

@@ -382,8 +382,10 @@ int or_mb_velocities(const or_params *p, or_state *s, uint64_t trial)
 
 int or_init_velocities(const or_params *p, or_state *s)
 {
-    if (p->water) return -10;
     for (int i = 0; i < s->n; ++i) mb_velocity(p, s, i, 0, PURPOSE_INITV, s->v + 3 * i);
+    /* rigid waters: Maxwell-Boltzmann momenta restricted to the constraint
+     * surface (the velocity constraint removes the bond components) */
+    if (p->water) return or_constrain_velocities(p, s);
     return 0;
 }
 
@@ -1006,7 +1008,6 @@ int or_trial_learned(const or_params *p, or_state *s, uint64_t trial, int force_
     const int n_orig = s->n;
     int ic, ia, nf;
     if (prop && prop->k < 1) prop = NULL;
-    if (p->momenta && p->water) return -10;
     /* the carried momenta before the trial (a rejection restores them) */
     double *v0 = p->momenta ? malloc(3 * (size_t)(n_orig > 0 ? n_orig : 1) * sizeof(double)) : NULL;
     if (p->momenta && !v0) return -1;
@@ -1124,8 +1125,11 @@ int or_md_phase(const or_params *p, or_state *s, uint64_t phase, int n_steps, or
      * runs n_steps velocity-Verlet steps in 3D, and the end state is taken
      * with probability min(1, exp(-beta dH)); a rejection keeps the
      * positions and reverses the refreshed momenta.  Each part leaves the
-     * canonical distribution of (x, p) invariant. */
-    if (p->water) return -10;
+     * canonical distribution of (x, p) invariant.  Rigid waters: the
+     * refreshed momenta are restricted to the constraint surface (the
+     * velocity constraint, a linear projection that keeps the constrained
+     * Maxwell-Boltzmann distribution), and every step constrains positions
+     * and velocities as in a trial's trajectory. */
     if (n_steps < 1) return -11;
     const int n = s->n;
     const double beta = 1.0 / p->kT;
@@ -1141,31 +1145,37 @@ int or_md_phase(const or_params *p, or_state *s, uint64_t phase, int n_steps, or
         mb_velocity(p, s, i, phase, PURPOSE_REFRESH, xi);
         for (int d = 0; d < 3; ++d) s->v[3 * i + d] = c * s->v[3 * i + d] + sc * xi[d];
     }
+    if (p->water && or_constrain_velocities(p, s)) return -5;
     double *x0 = malloc(3 * (size_t)(n > 0 ? n : 1) * sizeof(double));
     double *v0 = malloc(3 * (size_t)(n > 0 ? n : 1) * sizeof(double));
     double *F = malloc(3 * (size_t)(n > 0 ? n : 1) * sizeof(double));
-    if (!x0 || !v0 || !F) { free(x0); free(v0); free(F); return -1; }
+    double *xref = p->water ? malloc(3 * (size_t)(n > 0 ? n : 1) * sizeof(double)) : NULL;
+    if (!x0 || !v0 || !F || (p->water && !xref)) { free(x0); free(v0); free(F); free(xref); return -1; }
     memcpy(x0, s->x, 3 * (size_t)n * sizeof(double));
     memcpy(v0, s->v, 3 * (size_t)n * sizeof(double));
     or_energy e;
-    if (or_compute(p, s, 0.0, OR_MODE_NEMD, F, &e)) { free(x0); free(v0); free(F); return -7; }
+    if (or_compute(p, s, 0.0, OR_MODE_NEMD, F, &e)) { free(x0); free(v0); free(F); free(xref); return -7; }
     const double U0 = e.U, K0 = or_kinetic(p, s);
     const double h = 0.5 * p->dt;
-    for (int k = 0; k < n_steps; ++k) {
-        for (int i = 0; i < n; ++i) {
-            const double m = p->mass[s->type[i]];
-            for (int d = 0; d < 3; ++d) {
-                s->v[3 * i + d] += h * p->accel * F[3 * i + d] / m;
-                s->x[3 * i + d] = wrap1(s->x[3 * i + d] + p->dt * s->v[3 * i + d], p->box[d]);
-            }
-        }
-        if (or_compute(p, s, 0.0, OR_MODE_NEMD, F, &e)) { free(x0); free(v0); free(F); return -7; }
+    int unmet = 0;   /* rigid-water constraints that could not be met */
+    for (int k = 0; k < n_steps && !unmet; ++k) {
         for (int i = 0; i < n; ++i) {
             const double m = p->mass[s->type[i]];
             for (int d = 0; d < 3; ++d) s->v[3 * i + d] += h * p->accel * F[3 * i + d] / m;
         }
+        if (xref) memcpy(xref, s->x, 3 * (size_t)n * sizeof(double));
+        for (int i = 0; i < n; ++i)
+            for (int d = 0; d < 3; ++d)
+                s->x[3 * i + d] = wrap1(s->x[3 * i + d] + p->dt * s->v[3 * i + d], p->box[d]);
+        if (xref && or_constrain_positions(p, s, xref)) { unmet = 1; break; }
+        if (or_compute(p, s, 0.0, OR_MODE_NEMD, F, &e)) { free(x0); free(v0); free(F); free(xref); return -7; }
+        for (int i = 0; i < n; ++i) {
+            const double m = p->mass[s->type[i]];
+            for (int d = 0; d < 3; ++d) s->v[3 * i + d] += h * p->accel * F[3 * i + d] / m;
+        }
+        if (p->water && or_constrain_velocities(p, s)) unmet = 1;
     }
-    const double U1 = e.U, K1 = or_kinetic(p, s);
+    const double U1 = unmet ? NAN : e.U, K1 = or_kinetic(p, s);
     double u[4];
     draw4(p, phase, PURPOSE_MD, 0, u);
     rec->H0 = U0 + K0;
@@ -1183,7 +1193,7 @@ int or_md_phase(const or_params *p, or_state *s, uint64_t phase, int n_steps, or
         memcpy(s->x, x0, 3 * (size_t)n * sizeof(double));
         for (int q = 0; q < 3 * n; ++q) s->v[q] = -v0[q];
     }
-    free(x0); free(v0); free(F);
+    free(x0); free(v0); free(F); free(xref);
     return 0;
 }
 

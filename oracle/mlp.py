@@ -8,8 +8,10 @@ Hendrycks & Gimpel (2016) in its tanh form, then a linear output.
 Parameter vector theta (41,473 values) in this order:
     W1[64][128], b1[128], W2[128][128], b2[128], W3[128][128], b3[128],
     w4[128], b4
-(W[i][o] multiplies input i into output o).  Training fits s to the target
-clip(-beta dH, -50, 10) of pilot insertions with a mean-squared loss and Adam.
+(W[i][o] multiplies input i into output o).  Training fits s with a
+mean-squared loss and Adam; the benchmark's target for a pilot insertion is
+its clipped log ratio clip(beta mu + I - beta dH, -100, 10) at the operating
+beta mu, I = 2 ln(V / (N + 1)).
 """
 from __future__ import annotations
 

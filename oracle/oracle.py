@@ -197,8 +197,10 @@ class OracleSystem:
         self.s.x, self.s.v = _dp(self.x), _dp(self.v)
         self.s.type, self.s.mol = _ip(self.type), _ip(self.mol)
         self.s.tag, self.s.flying = _lp(self.tag), _ip(self.flying)
-        if not self.p.water:
-            lib().or_init_velocities(C.byref(self.p), C.byref(self.s))
+        if n:
+            rc = lib().or_init_velocities(C.byref(self.p), C.byref(self.s))
+            if rc:
+                raise RuntimeError(f"or_init_velocities failed: {rc}")
 
     @classmethod
     def from_workload(cls, w, cap=None, use_cells=True):

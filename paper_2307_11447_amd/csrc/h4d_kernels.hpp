@@ -96,6 +96,8 @@ struct KArgs {
     // lists
     int *nbr, *nnbr;
     int *cell_cnt[2], *cell_atoms[2], *cell_off;
+    int *cell_sub[2];         // per cell: where each of its 8 sub-cells begins in its row
+    int *slot_sub;            // sub-cell of each slot at its last binning
     int *fast;                // per box: 3 lists of kFastCap working slots
     int *molw;                // water atom (canonical 3m + q) -> working slot
     double4 *fw;              // forces on water atoms (working order)
@@ -165,6 +167,23 @@ __device__ __forceinline__ int stencil_cell(const Box &B, int cx, int cy, int cz
            (cx + t % 3 - 1 + nx) % nx;
 }
 
+// Sub-cell of a position: the octant of its cell (half a cell edge along
+// each axis), bit d set for the upper half along axis d, from the same
+// scaled coordinate as cell_coord.
+__device__ __forceinline__ int subcell_of(const Box &B, const double4 &p) {
+    const double x[3] = {p.x, p.y, p.z};
+    int sub = 0;
+    for (int d = 0; d < 3; ++d) {
+        const double y = x[d] / B.L[d] * (double)B.ncell[d];
+        int k = (int)y;
+        k = k < 0 ? 0 : (k >= B.ncell[d] ? B.ncell[d] - 1 : k);
+        int h = (int)(2.0 * y) - 2 * k;
+        h = h < 0 ? 0 : (h > 1 ? 1 : h);
+        sub |= h << d;
+    }
+    return sub;
+}
+
 // A non-finite position (a trajectory that blew up) is left out of the cells
 // and marks the trial non-finite: it is rejected, never recomputed, and the
 // cells cannot fill up with such atoms.
@@ -173,6 +192,7 @@ __device__ __forceinline__ void bin_atom(const KArgs &a, const Box &B, Ctl *c, i
         atomicOr(&c->err, kErrNonfinite);
         return;
     }
+    a.slot_sub[w] = B.use_cells ? subcell_of(B, p) : 0;
     const int cc = B.c0 + (B.use_cells ? cell_of(B, p) : 0);
     const int slot = atomicAdd(&a.cell_cnt[cb][cc], 1);
     if (slot < a.cell_cap) a.cell_atoms[cb][(size_t)cc * a.cell_cap + slot] = w;
@@ -414,8 +434,9 @@ __global__ __launch_bounds__(kBlock) void k_propose(KArgs a, int force_move) {
 }
 
 // ==========================================================================
-// Cells.  Binning uses atomics; each cell's members are then sorted by index
-// so that every list is built in a fixed order (bitwise reproducible).
+// Cells.  Binning uses atomics; each cell's members are then sorted by
+// sub-cell and index so that every list is built in a fixed order (bitwise
+// reproducible), and each sub-cell's members are contiguous.
 // ==========================================================================
 __global__ void k_cell_clear(KArgs a, int cb) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -442,18 +463,29 @@ __global__ __launch_bounds__(kBlock) void k_bin_working(KArgs a, int cb) {
     bin_atom(a, B, c, cb, w, a.pos[buf_of(-1, c)][w]);
 }
 
+// dynamic LDS: 2 cell_cap ints (members and their sub-cells)
 __global__ __launch_bounds__(kWave) void k_cell_sort(KArgs a, int cb) {
     extern __shared__ int buf[];
+    int *sub = buf + a.cell_cap;
     const int cc = blockIdx.x;
     const int cnt = min(a.cell_cnt[cb][cc], a.cell_cap);
     int *row = a.cell_atoms[cb] + (size_t)cc * a.cell_cap;
-    for (int q = threadIdx.x; q < cnt; q += kWave) buf[q] = row[q];
+    for (int q = threadIdx.x; q < cnt; q += kWave) {
+        const int e = row[q];
+        buf[q] = e;
+        sub[q] = a.slot_sub[e];
+    }
     __syncthreads();
     for (int q = threadIdx.x; q < cnt; q += kWave) {
-        const int e = buf[q];
+        const int e = buf[q], se = sub[q];
         int r = 0;
-        for (int p = 0; p < cnt; ++p) r += (buf[p] < e);
+        for (int p = 0; p < cnt; ++p) r += (sub[p] < se) | ((sub[p] == se) & (buf[p] < e));
         row[r] = e;
+    }
+    if (threadIdx.x < 8) {   // sub-cell q's members begin where the smaller sub-cells end
+        int r = 0;
+        for (int p = 0; p < cnt; ++p) r += sub[p] < (int)threadIdx.x;
+        a.cell_sub[cb][8 * (size_t)cc + threadIdx.x] = r;
     }
 }
 
@@ -604,21 +636,27 @@ __global__ __launch_bounds__(kBlock) void k_list_allpairs(KArgs a, int k, int b0
     }
 }
 
-// Cell form: `split` blocks of kListWaves wavefronts per centre cell (block
-// s of the cell takes the centre atoms t with (t / kListWaves) % split == s,
-// so that cells with many atoms still give the chip enough blocks).  The 27
-// stencil cells are staged in LDS all at once when their atoms fit in the
-// cand_cap staging entries, else one z-layer (9 cells) at a time (the
-// choice is the block's own; cand_cap >= 9 cell_cap)
-// (fixed-point coordinates + working slot, in stencil order); each
-// wavefront takes its centre atoms in turn and tests 64 candidates per
-// ballot (a layer is padded to whole wavefronts with entries that never
-// match), appending partners in stencil order (a centre atom's running count
-// stays in LDS across the layers).  MOL: rigid molecules present (pairs
-// within a molecule are left out).  Dynamic LDS: (cand_cap + cell_cap + 64)
-// * 16 + cell_cap * 4 bytes.  Also records the build positions, clears this cell's
-// count in the other buffer and the box's fast lists.
+// Cell form with sub-cell culling.  A cell's row is ordered by sub-cell (its
+// eight half-edge octants; cell_sub says where each begins), and `split`
+// blocks of kListWaves wavefronts serve the centre atoms of one sub-cell
+// (block s of the sub-cell takes its centre atoms t with (t / kListWaves) %
+// split == s).  Cells have edge >= r_list, so along each axis the far half
+// of a neighbouring cell lies at least one cell edge away from this
+// sub-cell: of the 27 x 8 neighbouring sub-cells only the 5 x 5 x 5 around
+// it can hold partners (125 / 216 of the 27 cells' volume), and only those
+// ranges are staged in LDS -- all at once when they fit in cand_cap entries,
+// else in consecutive groups of ranges (cand_cap >= 9 cell_cap, so every
+// range fits).  Candidates are staged as fixed-point coordinates + working
+// slot in stencil order (cell, then sub-cell, then index); each wavefront
+// takes its centre atoms in turn and tests 64 candidates per ballot (a group
+// is padded to whole wavefronts with entries that never match), appending
+// partners in that order (a centre atom's running count stays in LDS across
+// the groups).  MOL: rigid molecules present (pairs within a molecule are
+// left out).  Dynamic LDS: (cand_cap + cell_cap + 64) * 16 + cell_cap * 4
+// bytes.  Also records the build positions, clears this cell's count in the
+// other buffer and the box's fast lists.
 constexpr int kListWaves = 8;
+constexpr int kSubRanges = 27 * 8;
 
 template <bool C>
 struct BoolTag {
@@ -629,34 +667,53 @@ template <bool MOL>
 __global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int k, int b0, int cb, int split,
                                                                     int cand_cap) {
     extern __shared__ uint4 lds[];
-    __shared__ int cidx[27], cnt27[27], off[28];
+    __shared__ int roff[kSubRanges + 1], rstart[kSubRanges], rcell[kSubRanges];
+    __shared__ int s_c0, s_mc;
     const int cap = a.cell_cap;
     uint4 *cand = lds;                             // cand_cap + 64 staged candidates
-    uint4 *ctr = lds + (size_t)cand_cap + kWave;   // cap centre atoms
+    uint4 *ctr = lds + (size_t)cand_cap + kWave;   // the sub-cell's centre atoms (at most cap)
     int *ccount = reinterpret_cast<int *>(ctr + cap);
-    const int cc = (int)blockIdx.x / split, part = (int)blockIdx.x % split;
+    const int part = (int)blockIdx.x % split, sc = ((int)blockIdx.x / split) & 7, cc = (int)blockIdx.x / split / 8;
     const int bi = box_of_cell(a, cc);
     const Box &B = a.box[bi];
     Ctl *c = a.ctl + bi;
     if (!list_wanted(c, k)) return;
     const int b = buf_of(b0, c);
-    if (threadIdx.x < 27) {
-        const int t = threadIdx.x;
-        const int nx = B.ncell[0], ny = B.ncell[1];
-        const int lc = cc - B.c0;
-        const int c2 = stencil_cell(B, lc % nx, (lc / nx) % ny, lc / (nx * ny), t);
-        cidx[t] = c2;
-        cnt27[t] = min(a.cell_cnt[cb][c2], cap);
+    const int nx = B.ncell[0], ny = B.ncell[1], nz = B.ncell[2];
+    const int lc = cc - B.c0;
+    const int cx = lc % nx, cy = (lc / nx) % ny, cz = lc / (nx * ny);
+    if (threadIdx.x < kSubRanges) {
+        // range q: sub-cell q % 8 of stencil cell q / 8, kept when along every
+        // axis it lies in the same cell or in the neighbour's near half, or
+        // this sub-cell is the centre cell's half on the neighbour's side
+        const int q = threadIdx.x, t = q >> 3, su = q & 7;
+        auto keep = [](int d, int h, int hc) { return d == 0 || (d < 0 ? (h == 1 || hc == 0) : (h == 0 || hc == 1)); };
+        const bool ok = keep(t % 3 - 1, su & 1, sc & 1) && keep((t / 3) % 3 - 1, (su >> 1) & 1, (sc >> 1) & 1) &&
+                        keep(t / 9 - 1, (su >> 2) & 1, (sc >> 2) & 1);
+        const int c2 = stencil_cell(B, cx, cy, cz, t);
+        const int n2 = min(a.cell_cnt[cb][c2], cap);
+        const int lo = min(a.cell_sub[cb][8 * (size_t)c2 + su], n2);
+        const int hi = su < 7 ? min(a.cell_sub[cb][8 * (size_t)c2 + su + 1], n2) : n2;
+        rcell[q] = c2;
+        rstart[q] = lo;
+        roff[q + 1] = ok ? max(0, hi - lo) : 0;
+        if (t == 13 && su == sc) { s_c0 = lo; s_mc = max(0, hi - lo); }   // the centre cell is stencil entry 13
     }
-    if (threadIdx.x == 0 && cc == B.c0 && part == 0) c->nfast[0] = c->nfast[1] = c->nfast[2] = 0;
+    if (threadIdx.x == 0 && cc == B.c0 && part == 0 && sc == 0) c->nfast[0] = c->nfast[1] = c->nfast[2] = 0;
     __syncthreads();
-    const int mc = cnt27[13];                    // the centre cell is stencil entry 13
+    if (threadIdx.x == 0) {
+        roff[0] = 0;
+        for (int q = 0; q < kSubRanges; ++q) roff[q + 1] += roff[q];
+    }
+    __syncthreads();
+    const int mc = s_mc;
     if (part * kListWaves >= mc) {               // no centre atoms for this block
-        if (part == 0 && threadIdx.x == 0) a.cell_cnt[cb ^ 1][cc] = 0;
+        if (part == 0 && sc == 0 && threadIdx.x == 0) a.cell_cnt[cb ^ 1][cc] = 0;
         return;
     }
+    const int *crow = a.cell_atoms[cb] + (size_t)cc * cap + s_c0;
     for (int u = threadIdx.x; u < mc; u += blockDim.x) {
-        const int j = a.cell_atoms[cb][(size_t)cidx[13] * cap + u];
+        const int j = crow[u];
         const uint4 q = a.fx[b][j];
         ctr[u] = make_uint4(q.x, q.y, q.z, (unsigned)j);
         ccount[u] = 0;
@@ -668,9 +725,6 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int 
     const unsigned lim = __float_as_uint(rl2) - 1u;
     uint4 far_pad;
     {
-        const int nx = B.ncell[0], ny = B.ncell[1], nz = B.ncell[2];
-        const int lc = cc - B.c0;
-        const int cx = lc % nx, cy = (lc / nx) % ny, cz = lc / (nx * ny);
         auto opposite = [](int c, int n) {   // fixed-point coordinate of the cell centre, plus half the box
             return (unsigned)(((2.0 * c + 1.0) / (2.0 * n)) * 4294967296.0) + 0x80000000u;
         };
@@ -680,28 +734,23 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int 
     const unsigned lim_u = __float_as_uint(rl2u) - 1u;
     const unsigned long long below = (1ull << lane) - 1ull;
     const int ll = a.lanes_log2, lmask = (1 << ll) - 1;
-    int total27 = 0;
-    for (int t = 0; t < 27; ++t) total27 += cnt27[t];
-    const int cpl = total27 <= cand_cap ? 27 : 9;   // cells staged per round (uniform over the block)
-    for (int layer = 0; layer < 27 / cpl; ++layer) {
-        if (threadIdx.x == 0) {
-            int run = 0;
-            for (int t = 0; t < cpl; ++t) { off[t] = run; run += cnt27[cpl * layer + t]; }
-            off[cpl] = run;
-        }
-        __syncthreads();
-        const int total = off[cpl];
-        // one candidate per thread across the round's cells, so that all of
-        // its gathers are in flight at once; its cell is the last one whose
-        // offset does not exceed it (empty cells share their offset)
+    for (int r_lo = 0; r_lo < kSubRanges;) {
+        // the next group of ranges that fits in the staging area (the same
+        // choice in every thread)
+        int r_hi = r_lo + 1;
+        while (r_hi < kSubRanges && roff[r_hi + 1] - roff[r_lo] <= cand_cap) ++r_hi;
+        const int base0 = roff[r_lo], total = roff[r_hi] - base0;
+        // one candidate per thread across the group's ranges, so that all of
+        // its gathers are in flight at once; its range is the last one whose
+        // offset does not exceed it (empty ranges share their offset)
         for (int e = threadIdx.x; e < total; e += blockDim.x) {
-            int lo = 0, hi = cpl - 1;
+            int lo = r_lo, hi = r_hi - 1;
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
-                if (off[mid] <= e) lo = mid;
+                if (roff[mid] - base0 <= e) lo = mid;
                 else hi = mid - 1;
             }
-            const int j = a.cell_atoms[cb][(size_t)cidx[cpl * layer + lo] * cap + (e - off[lo])];
+            const int j = a.cell_atoms[cb][(size_t)rcell[lo] * cap + rstart[lo] + (e - (roff[lo] - base0))];
             const uint4 q = a.fx[b][j];
             cand[e] = make_uint4(q.x, q.y, q.z, (unsigned)j);
         }
@@ -709,58 +758,62 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int 
         // the point opposite the centre cell's centre, at least L/2 - h/2 >= h
         // >= r_list from every centre atom along each axis (3 or more cells
         // per edge)
-        if (threadIdx.x < kWave) cand[off[cpl] + threadIdx.x] = far_pad;
+        if (threadIdx.x < kWave) cand[total + threadIdx.x] = far_pad;
         __syncthreads();
-        for (int t = part * kListWaves + wave; t < mc; t += split * kListWaves) {
-            const uint4 qi = ctr[t];
-            const int wi = (int)qi.w;
-            const int mi = MOL ? a.wmol[wi] : -1;
-            // the working slots of this atom's molecule (its partners in it
-            // are left out), held in registers for the candidate loop
-            int sib0 = -1, sib1 = -1, sib2 = -1;
-            if (MOL && mi >= 0) {
-                const int c0 = B.a0 + 3 * mi;
-                sib0 = a.molw[c0]; sib1 = a.molw[c0 + 1]; sib2 = a.molw[c0 + 2];
-            }
-            int cnt = ccount[t];
-            int *dst = a.nbr + nbr_slot(a, wi, 0);
-            // a cubic box compares squared distances in fixed-point units
-            // (three multiplies fewer per candidate)
-            auto scan = [&](auto cubic_tag) {
-                constexpr bool CUBIC = decltype(cubic_tag)::value;
-                for (int base = 0; base < total; base += kWave) {
-                    const uint4 qj = cand[base + lane];
-                    const int j = (int)qj.w;
-                    float d2;
-                    if constexpr (CUBIC) {
-                        const float ux = (float)(int)(qi.x - qj.x);
-                        const float uy = (float)(int)(qi.y - qj.y);
-                        const float uz = (float)(int)(qi.z - qj.z);
-                        d2 = ux * ux + uy * uy + uz * uz;
-                    } else {
-                        const float dx = (float)(int)(qi.x - qj.x) * sx;
-                        const float dy = (float)(int)(qi.y - qj.y) * sy;
-                        const float dz = (float)(int)(qi.z - qj.z) * sz;
-                        d2 = dx * dx + dy * dy + dz * dz;
-                    }
-                    // 0 < d2 < r_list^2 as one unsigned compare of the float bits
-                    // (monotonic for d2 >= 0); d2 = 0 is the atom itself
-                    bool acc = __float_as_uint(d2) - 1u < (CUBIC ? lim_u : lim);
-                    if (MOL) acc &= (j != sib0) & (j != sib1) & (j != sib2);   // ions carry no molecule (-1)
-                    const unsigned long long msk = __builtin_amdgcn_ballot_w64(acc);
-                    // accepted lanes below this one: the lane's slot after the running count
-                    const unsigned q = (unsigned)cnt + __builtin_amdgcn_mbcnt_hi(
-                                           (unsigned)(msk >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)msk, 0u));
-                    if (acc && q < (unsigned)a.nbr_cap) dst[((q >> ll) << 6) | (q & (unsigned)lmask)] = j;
-                    cnt += __popcll(msk);
+        if (total > 0) {
+            for (int t = part * kListWaves + wave; t < mc; t += split * kListWaves) {
+                const uint4 qi = ctr[t];
+                const int wi = (int)qi.w;
+                const int mi = MOL ? a.wmol[wi] : -1;
+                // the working slots of this atom's molecule (its partners in it
+                // are left out), held in registers for the candidate loop
+                int sib0 = -1, sib1 = -1, sib2 = -1;
+                if (MOL && mi >= 0) {
+                    const int c0 = B.a0 + 3 * mi;
+                    sib0 = a.molw[c0]; sib1 = a.molw[c0 + 1]; sib2 = a.molw[c0 + 2];
                 }
-            };
-            if (cubic) scan(BoolTag<true>{});
-            else scan(BoolTag<false>{});
-            if (lane == 0) ccount[t] = cnt;
+                int cnt = ccount[t];
+                int *dst = a.nbr + nbr_slot(a, wi, 0);
+                // a cubic box compares squared distances in fixed-point units
+                // (three multiplies fewer per candidate)
+                auto scan = [&](auto cubic_tag) {
+                    constexpr bool CUBIC = decltype(cubic_tag)::value;
+                    for (int base = 0; base < total; base += kWave) {
+                        const uint4 qj = cand[base + lane];
+                        const int j = (int)qj.w;
+                        float d2;
+                        if constexpr (CUBIC) {
+                            const float ux = (float)(int)(qi.x - qj.x);
+                            const float uy = (float)(int)(qi.y - qj.y);
+                            const float uz = (float)(int)(qi.z - qj.z);
+                            d2 = ux * ux + uy * uy + uz * uz;
+                        } else {
+                            const float dx = (float)(int)(qi.x - qj.x) * sx;
+                            const float dy = (float)(int)(qi.y - qj.y) * sy;
+                            const float dz = (float)(int)(qi.z - qj.z) * sz;
+                            d2 = dx * dx + dy * dy + dz * dz;
+                        }
+                        // 0 < d2 < r_list^2 as one unsigned compare of the float bits
+                        // (monotonic for d2 >= 0); d2 = 0 is the atom itself
+                        bool acc = __float_as_uint(d2) - 1u < (CUBIC ? lim_u : lim);
+                        if (MOL) acc &= (j != sib0) & (j != sib1) & (j != sib2);   // ions carry no molecule (-1)
+                        const unsigned long long msk = __builtin_amdgcn_ballot_w64(acc);
+                        // accepted lanes below this one: the lane's slot after the running count
+                        const unsigned q = (unsigned)cnt + __builtin_amdgcn_mbcnt_hi(
+                                               (unsigned)(msk >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)msk, 0u));
+                        if (acc && q < (unsigned)a.nbr_cap) dst[((q >> ll) << 6) | (q & (unsigned)lmask)] = j;
+                        cnt += __popcll(msk);
+                    }
+                };
+                if (cubic) scan(BoolTag<true>{});
+                else scan(BoolTag<false>{});
+                if (lane == 0) ccount[t] = cnt;
+            }
         }
         __syncthreads();
+        r_lo = r_hi;
     }
+    (void)below;
     for (int t = threadIdx.x; t < mc; t += blockDim.x) {
         if ((t / kListWaves) % split != part) continue;
         const uint4 qi = ctr[t];
@@ -771,7 +824,7 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int 
         unflag_fast(a, b, wi, a.fx[b][wi].w);
         if (cnt > a.nbr_cap) { atomicOr(&c->err, kErrNbr); atomicMax(&c->max_nbr, cnt); }
     }
-    if (threadIdx.x == 0 && part == 0) a.cell_cnt[cb ^ 1][cc] = 0;
+    if (threadIdx.x == 0 && part == 0 && sc == 0) a.cell_cnt[cb ^ 1][cc] = 0;
 }
 
 // Cell form for cells too large to stage in LDS: L lanes per atom walk the
@@ -1801,6 +1854,32 @@ __global__ __launch_bounds__(kBlock) void k_rattle_mb(KArgs a) {
     for (int i = 0; i < 3; ++i) v[i] = mk(v4[i].x, v4[i].y, v4[i].z);
     rattle_velocities(a.G, ra_, x1, x2, v[0], v[1], v[2]);
     for (int i = 0; i < 3; ++i) a.vel[0][w[i]] = make_double4(v[i].x, v[i].y, v[i].z, 0.0);
+}
+
+// Rigid waters' canonical momenta restricted to the constraint surface (the
+// velocity constraint on the canonical positions), one thread per molecule
+// of every box: at set-up, and (rejected_phase_only) after a rejected
+// equilibrium phase, whose reversed refresh k_commit wrote unrestricted --
+// the restriction is linear, so this gives the reversed momenta the phase's
+// trajectory started from.
+__global__ __launch_bounds__(kBlock) void k_water_cvel(KArgs a, int rejected_phase_only) {
+    const int gm = blockIdx.x * kBlock + threadIdx.x;
+    if (gm >= a.G.n_mol * a.nbox) return;
+    const int bi = gm / a.G.n_mol, m = gm - bi * a.G.n_mol;
+    const Box &B = a.box[bi];
+    const Ctl *c = a.ctl + bi;
+    if (rejected_phase_only && !(c->move == kMoveMD && !c->accepted && !c->retry)) return;
+    const int i0 = B.a0 + 3 * m;
+    const double4 pa = a.cpos[i0];
+    const d3 ra_ = mk(pa.x, pa.y, pa.z);
+    const d3 x1 = unwrap_near(B, a.cpos[i0 + 1], ra_), x2 = unwrap_near(B, a.cpos[i0 + 2], ra_);
+    d3 v[3];
+    for (int q = 0; q < 3; ++q) {
+        const double4 v4 = a.cvel[i0 + q];
+        v[q] = mk(v4.x, v4.y, v4.z);
+    }
+    rattle_velocities(a.G, ra_, x1, x2, v[0], v[1], v[2]);
+    for (int q = 0; q < 3; ++q) a.cvel[i0 + q] = make_double4(v[q].x, v[q].y, v[q].z, 0.0);
 }
 
 // One step k of the rigid waters (after k_step stored their forces F_k):

@@ -41,17 +41,24 @@ typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 struct LearnArgs {
-    int k;                  // candidates per move
+    int k;                  // candidates per move and box
     int use_net;            // 0: every logit is 0 (equal weights)
     double cap;             // log weight = scale * min(logit, cap)
     double scale;
-    double *sites;          // k x 6: cation xyz, anion xyz
-    float *feat;            // k x 64
-    float *logit;           // k
-    float *last_feat;       // 64: features of the inserted / removed pair's site
+    // box b's candidate j is row g = b k + j of the candidate arrays
+    double *sites;          // (boxes x k) x 6: cation xyz, anion xyz
+    float *feat;            // (boxes x k) x 64
+    float *logit;           // boxes x k
+    float *last_feat;       // boxes x 64: features of each box's inserted / removed pair's site
     const float *theta;     // FP32 parameters
     const bf16x4 *wfrag;    // hidden layers in MFMA fragment order (BF16)
 };
+
+// Does box bi take part in the learned step of this phase (0: an insertion
+// before its trajectory; 1: a deletion after it)?
+__device__ __forceinline__ bool learned_phase(const Ctl *c, int phase) {
+    return phase == 0 ? c->move == 1 : c->move == -1;
+}
 
 __device__ __forceinline__ float gelu_f(float x) {
     return 0.5f * x * (1.0f + tanhf(0.7978845608028654f * (x + 0.044715f * x * x * x)));
@@ -93,19 +100,19 @@ __device__ __forceinline__ void pair_parts_f32(const Geo &G, const PairCoef &c, 
 }
 
 // --------------------------------------------------------------------------
-// Candidate sites of the single box (box 0).  phase 0 (insertion, before the
-// trajectory): candidates j = 0..k-1 from the counters (t, 4, j, 0 / 1).
-// phase 1 (deletion, after it): site 0 is the removed pair (fixed in 3D),
-// sites 1..k-1 the candidates 0..k-2.
+// Candidate sites, one thread per (box, candidate).  phase 0 (insertion,
+// before the trajectory): candidates j = 0..k-1 from the box's counters
+// (t, 4, j, 0 / 1).  phase 1 (deletion, after it): site 0 is the removed
+// pair (fixed in 3D), sites 1..k-1 the candidates 0..k-2.
 // --------------------------------------------------------------------------
 __global__ void k_cand_sites(KArgs a, LearnArgs l, int phase) {
-    const Ctl *c = a.ctl;
-    const int move = c->move;
-    if (phase == 0 ? move != 1 : move != -1) return;
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= l.k) return;
-    const Box &B = a.box[0];
-    double *st = l.sites + 6 * (size_t)j;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= a.nbox * l.k) return;
+    const int bi = g / l.k, j = g - bi * l.k;
+    const Ctl *c = a.ctl + bi;
+    if (!learned_phase(c, phase)) return;
+    const Box &B = a.box[bi];
+    double *st = l.sites + 6 * (size_t)g;
     if (phase == 1 && j == 0) {
         const int bf = buf_of(-1, c);
         const double4 pc = a.pos[bf][c->wic], pa = a.pos[bf][c->wia];
@@ -132,12 +139,14 @@ __global__ void k_cand_sites(KArgs a, LearnArgs l, int phase) {
 // (capped) and asinh(beta u) of the pair itself.  Pair terms are scaled by
 // beta, clipped to +-1e6 and summed in fixed point.
 // --------------------------------------------------------------------------
-__device__ __forceinline__ void site_features(const KArgs &a, const LearnArgs &l, int b0, int cb) {
-    const Ctl *c = a.ctl;
+__device__ __forceinline__ void site_features(const KArgs &a, const LearnArgs &l, int phase, int b0, int cb) {
     const int wave = (int)((blockIdx.x * kBlock + threadIdx.x) / kWave), lane = threadIdx.x % kWave;
-    const int j = wave >> 1, ion = wave & 1;
-    if (j >= l.k) return;
-    const Box &B = a.box[0];
+    const int j = wave >> 1, ion = wave & 1;   // j: row of (box, candidate)
+    if (j >= a.nbox * l.k) return;
+    const int bi = j / l.k;
+    const Ctl *c = a.ctl + bi;
+    if (phase >= 0 && !learned_phase(c, phase)) return;
+    const Box &B = a.box[bi];
     const Geo &G = a.G;
     const int b = buf_of(b0, c);
     const double *st = l.sites + 6 * (size_t)j + 3 * ion;
@@ -242,14 +251,12 @@ __device__ __forceinline__ void site_features(const KArgs &a, const LearnArgs &l
 }
 
 __global__ __launch_bounds__(kBlock) void k_site_features(KArgs a, LearnArgs l, int phase, int b0, int cb) {
-    const int move = a.ctl->move;
-    if (phase == 0 ? move != 1 : move != -1) return;
-    site_features(a, l, b0, cb);
+    site_features(a, l, phase, b0, cb);
 }
 
-// test hook: features of given sites on the state sorted into working
-// buffer 0 / cell buffer 0 (h4d_build_neighbors)
-__global__ __launch_bounds__(kBlock) void k_site_features_hook(KArgs a, LearnArgs l) { site_features(a, l, 0, 0); }
+// test hook (one box): features of given sites on the state sorted into
+// working buffer 0 / cell buffer 0 (h4d_build_neighbors)
+__global__ __launch_bounds__(kBlock) void k_site_features_hook(KArgs a, LearnArgs l) { site_features(a, l, -1, 0, 0); }
 
 // --------------------------------------------------------------------------
 // Network inference in BF16 on the matrix cores.  One block of four
@@ -334,58 +341,93 @@ __global__ void k_mlp_pack(const float *theta, bf16x4 *wfrag) {
 }
 
 __global__ void k_zero_logits(KArgs a, LearnArgs l, int phase) {
-    const int move = a.ctl->move;
-    if (phase == 0 ? move != 1 : move != -1) return;
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < l.k) l.logit[j] = 0.0f;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= a.nbox * l.k || !learned_phase(a.ctl + g / l.k, phase)) return;
+    l.logit[g] = 0.0f;
 }
 
-// logits of the move's candidates (after k_site_features)
+// logits of every box's candidates (after k_site_features): one pass over
+// the boxes x k rows; a 64-row tile whose boxes all sit out this phase
+// returns at once
 __global__ __launch_bounds__(256) void k_mlp_infer_move(KArgs a, LearnArgs l, int phase) {
-    const int move = a.ctl->move;
-    if (phase == 0 ? move != 1 : move != -1) return;
-    mlp_tile(l.feat, l.k, l.theta, l.wfrag, l.logit);
+    const int rows = a.nbox * l.k, row0 = blockIdx.x * 64;
+    const int b_lo = row0 / l.k, b_hi = min(row0 + 63, rows - 1) / l.k;
+    bool any = false;
+    for (int bi = b_lo; bi <= b_hi; ++bi) any |= learned_phase(a.ctl + bi, phase);
+    if (!any) return;
+    mlp_tile(l.feat, rows, l.theta, l.wfrag, l.logit);
 }
 
 // --------------------------------------------------------------------------
-// The multiple-try step, one thread, FP64, in a fixed order, with log
-// weights lw = scale min(s, cap).  Insertion: the first candidate whose
-// running weight exceeds u W (uniform (t, 5, 0, 0)); the ghosts move to it;
-// ln q = ln(W/k) - lw(chosen).  Deletion: ln q = lw(removed) - ln(W/k).
-// Weights are taken relative to the largest.
+// The multiple-try step, one block per box, FP64, with log weights
+// lw = scale min(s, cap) taken relative to the largest.  Thread t sums the
+// weights of a contiguous chunk of candidates in order; thread 0 adds the
+// chunks in order (a fixed order for a given k).  Insertion: the first
+// candidate whose running weight exceeds u W (uniform (t, 5, 0, 0)); the
+// ghosts move to it; ln q = ln(W/k) - lw(chosen).  Deletion: ln q =
+// lw(removed) - ln(W/k).
 // --------------------------------------------------------------------------
-__global__ void k_mtm_select(KArgs a, LearnArgs l, int phase) {
-    Ctl *c = a.ctl;
-    const int move = c->move;
-    if (phase == 0 ? move != 1 : move != -1) return;
+constexpr int kMtmBlock = 256;
+
+__global__ __launch_bounds__(kMtmBlock) void k_mtm_select(KArgs a, LearnArgs l, int phase) {
+    const int bi = blockIdx.x, tid = threadIdx.x;
+    Ctl *c = a.ctl + bi;
+    if (!learned_phase(c, phase)) return;
     const int k = l.k;
-    auto lw = [&](int j) { return l.scale * fmin((double)l.logit[j], l.cap); };
-    double mx = lw(0);
-    for (int j = 1; j < k; ++j) mx = fmax(mx, lw(j));
-    double acc = 0.0;
-    for (int j = 0; j < k; ++j) acc += exp(lw(j) - mx);
-    const double lnWk = mx + log(acc) - log((double)k);
-    int sel = 0;
-    if (phase == 0) {
-        const Box &B = a.box[0];
-        const u64x4 r = philox((uint64_t)c->trial, kPurposePick, 0, 0, a.seed, B.stream);
-        const double target = unit_open(r.v[0]) * acc;
-        double run = 0.0;
-        sel = k - 1;
-        for (int j = 0; j < k; ++j) {
-            run += exp(lw(j) - mx);
-            if (run > target) { sel = j; break; }
-        }
-        c->lnq = lnWk - lw(sel);
-        const double *st = l.sites + 6 * (size_t)sel;
-        double4 p = a.cpos[c->ic];
-        a.cpos[c->ic] = with_meta(st[0], st[1], st[2], meta_of(p));
-        p = a.cpos[c->ia];
-        a.cpos[c->ia] = with_meta(st[3], st[4], st[5], meta_of(p));
-    } else {
-        c->lnq = lw(0) - lnWk;
+    const size_t g0 = (size_t)bi * k;
+    __shared__ double s_part[kMtmBlock];
+    __shared__ double s_mx, s_lnWk;
+    __shared__ int s_sel;
+    auto lw = [&](int j) { return l.scale * fmin((double)l.logit[g0 + j], l.cap); };
+    const int chunk = (k + kMtmBlock - 1) / kMtmBlock;
+    const int lo = min(k, tid * chunk), hi = min(k, lo + chunk);
+    double mx = -INFINITY;
+    for (int j = lo; j < hi; ++j) mx = fmax(mx, lw(j));
+    s_part[tid] = mx;
+    __syncthreads();
+    if (tid == 0) {
+        double m = s_part[0];
+        for (int q = 1; q < kMtmBlock; ++q) m = fmax(m, s_part[q]);
+        s_mx = m;
     }
-    for (int q = 0; q < kFeat; ++q) l.last_feat[q] = l.feat[64 * (size_t)sel + q];
+    __syncthreads();
+    mx = s_mx;
+    double acc = 0.0;
+    for (int j = lo; j < hi; ++j) acc += exp(lw(j) - mx);
+    __syncthreads();
+    s_part[tid] = acc;
+    __syncthreads();
+    if (tid == 0) {
+        double W = 0.0;
+        for (int q = 0; q < kMtmBlock; ++q) W += s_part[q];
+        const double lnWk = mx + log(W) - log((double)k);
+        s_lnWk = lnWk;
+        int sel = 0;
+        if (phase == 0) {
+            const Box &B = a.box[bi];
+            const u64x4 r = philox((uint64_t)c->trial, kPurposePick, 0, 0, a.seed, B.stream);
+            const double target = unit_open(r.v[0]) * W;
+            double run = 0.0;
+            int q = 0;
+            while (q < kMtmBlock - 1 && run + s_part[q] <= target) run += s_part[q++];
+            sel = min(k, q * chunk + chunk) - 1;   // rounding at the chunk's end: its last candidate
+            for (int j = min(k, q * chunk); j < min(k, q * chunk + chunk); ++j) {
+                run += exp(lw(j) - mx);
+                if (run > target) { sel = j; break; }
+            }
+            c->lnq = lnWk - lw(sel);
+            const double *st = l.sites + 6 * (g0 + sel);
+            double4 p = a.cpos[c->ic];
+            a.cpos[c->ic] = with_meta(st[0], st[1], st[2], meta_of(p));
+            p = a.cpos[c->ia];
+            a.cpos[c->ia] = with_meta(st[3], st[4], st[5], meta_of(p));
+        } else {
+            c->lnq = lw(0) - lnWk;
+        }
+        s_sel = sel;
+    }
+    __syncthreads();
+    if (tid < kFeat) l.last_feat[(size_t)kFeat * bi + tid] = l.feat[kFeat * (g0 + s_sel) + tid];
 }
 
 // ==========================================================================

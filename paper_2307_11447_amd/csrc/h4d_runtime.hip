@@ -70,6 +70,7 @@ struct h4d_system {
     std::vector<hipEvent_t> ev;
     int64_t step_launches = 0;
     double step_ms = 0.0;
+    double atom_launches = 0.0;   // atoms integrated, summed over the timed step launches
     int trial_rebuilds = 0;
     int64_t retries = 0;
     int trial_M = 1;            // rebuild interval of the round being run
@@ -86,7 +87,7 @@ struct h4d_system {
     };
     std::vector<Stats> stats;
     Stats chain;                   // speculative handles: the chain's statistics
-    // learned proposal (single box): k candidates per move, 0 = uniform
+    // learned proposal: k candidates per move and box, 0 = uniform
     LearnArgs la{};
 
     template <class T>
@@ -144,7 +145,6 @@ int check_params(const h4d_params &p) {
     if (p.schedule < 0 || p.schedule > 2 || (p.schedule != 0 && !(p.schedule_n >= 1.0 && std::isfinite(p.schedule_n))))
         return fail(H4D_EINVAL, "schedule must be 0, 1 or 2, with schedule_n >= 1 for 1 and 2");
     if (p.momenta != 0 && p.momenta != 1) return fail(H4D_EINVAL, "momenta must be 0 or 1");
-    if (p.momenta && p.water) return fail(H4D_EINVAL, "carried momenta need an ion system (water = 0)");
     if (!(p.md_refresh >= 0.0 && p.md_refresh <= 1.0)) return fail(H4D_EINVAL, "md_refresh must lie in [0, 1]");
     if (!(p.w_max_ratio >= 0.0 && std::isfinite(p.w_max_ratio)))
         return fail(H4D_EINVAL, "w_max_ratio must be finite and >= 0 (0: the cation's w_max)");
@@ -326,6 +326,12 @@ int alloc_lists(h4d_system *s) {
         HIPC(hipMemset(s->a.cell_cnt[q], 0, sizeof(int) * s->a.ncell_total));
     }
     if ((rc = s->alloc(&s->a.cell_off, (size_t)s->a.ncell_total))) return rc;
+    for (int q = 0; q < 2; ++q) {
+        if ((rc = s->alloc(&s->a.cell_sub[q], 8 * (size_t)s->a.ncell_total))) return rc;
+        HIPC(hipMemset(s->a.cell_sub[q], 0, sizeof(int) * 8 * s->a.ncell_total));
+    }
+    if ((rc = s->alloc(&s->a.slot_sub, (size_t)s->a.slots))) return rc;
+    HIPC(hipMemset(s->a.slot_sub, 0, sizeof(int) * s->a.slots));
     if ((rc = s->alloc(&s->a.fast, (size_t)s->nbox * 3 * kFastCap))) return rc;
     return H4D_OK;
 }
@@ -345,7 +351,7 @@ int slot_blocks(const h4d_system *s) { return s->a.slots / kBlock; }
 int list_cand_cap(const h4d_system *s) {
     const int cap = s->a.cell_cap;
     const int fixed = (int)(kWave * sizeof(uint4) + (size_t)cap * (sizeof(uint4) + sizeof(int)));
-    constexpr int kStaticLds = 512;   // cidx, cnt27, off (328 bytes) and slack
+    constexpr int kStaticLds = 3072;  // the sub-cell range table (2,612 bytes) and slack
     return std::max(9 * cap, (40 * 1024 - kStaticLds - fixed) / (int)sizeof(uint4));
 }
 
@@ -355,13 +361,15 @@ size_t list_cells_lds(const h4d_system *s) {
     return (size_t)(list_cand_cap(s) + kWave) * sizeof(uint4) + (size_t)s->a.cell_cap * (sizeof(uint4) + sizeof(int));
 }
 
-// blocks per centre cell of the cell-form list build: the autotuner's
+// blocks per centre sub-cell of the cell-form list build: the autotuner's
 // choice, else enough blocks for two per CU (about 512 in all); at most 16
-// and at least two centre atoms of a full cell per wavefront
+// and at least two centre atoms of a full sub-cell (an eighth of a full
+// cell) per wavefront
 int list_split(const h4d_system *s) {
-    const int most = std::max(1, std::min(16, s->a.cell_cap / (2 * kListWaves)));
+    const int most = std::max(1, std::min(16, s->a.cell_cap / (16 * kListWaves)));
     if (s->list_split > 0) return std::min(s->list_split, most);
-    const int want = (512 + s->a.ncell_total - 1) / s->a.ncell_total;
+    const int blocks = 8 * s->a.ncell_total;
+    const int want = (512 + blocks - 1) / blocks;
     return std::max(1, std::min(want, most));
 }
 
@@ -370,7 +378,7 @@ void launch_list(h4d_system *s, int k, int b, int cb, hipStream_t st) {
     KArgs &a = s->a;
     if (s->cells && list_cells_lds(s) <= 56 * 1024) {
         const int split = list_split(s), cand_cap = list_cand_cap(s);
-        const dim3 grid(a.ncell_total * split), block(kListWaves * kWave);
+        const dim3 grid(a.ncell_total * 8 * split), block(kListWaves * kWave);
         const size_t lds = list_cells_lds(s);
         if (a.G.water) hipLaunchKernelGGL(k_list_cells<true>, grid, block, lds, st, a, k, b, cb, split, cand_cap);
         else hipLaunchKernelGGL(k_list_cells<false>, grid, block, lds, st, a, k, b, cb, split, cand_cap);
@@ -430,7 +438,7 @@ int sort_in(h4d_system *s, hipStream_t st) {
     const int nc = a.ncell_total;
     hipLaunchKernelGGL(k_cell_clear, dim3(blocks_for(nc)), dim3(kBlock), 0, st, a, 0);
     hipLaunchKernelGGL(k_bin_canonical, dim3(slot_blocks(s)), dim3(kBlock), 0, st, a, 0);
-    hipLaunchKernelGGL(k_cell_sort, dim3(nc), dim3(kWave), a.cell_cap * sizeof(int), st, a, 0);
+    hipLaunchKernelGGL(k_cell_sort, dim3(nc), dim3(kWave), 2 * a.cell_cap * sizeof(int), st, a, 0);
     hipLaunchKernelGGL(k_cell_scan, dim3(s->nbox), dim3(1024), 0, st, a, 0);
     hipLaunchKernelGGL(k_gather_in, dim3(nc), dim3(kWave), 0, st, a, 0);
     if (a.G.water) hipLaunchKernelGGL(k_rattle_mb, dim3(blocks_for(a.G.n_mol * s->nbox)), dim3(kBlock), 0, st, a);
@@ -446,7 +454,7 @@ int rebuild_mid(h4d_system *s, int k, int b, hipStream_t st) {
     KArgs &a = s->a;
     const int cb = s->cl ^ 1;
     if (s->cells)
-        hipLaunchKernelGGL(k_cell_sort, dim3(a.ncell_total), dim3(kWave), a.cell_cap * sizeof(int), st, a, cb);
+        hipLaunchKernelGGL(k_cell_sort, dim3(a.ncell_total), dim3(kWave), 2 * a.cell_cap * sizeof(int), st, a, cb);
     launch_list(s, k, b, cb, st);
     s->cl = cb;
     HIPC(hipGetLastError());
@@ -461,7 +469,7 @@ int rebuild_final(h4d_system *s, hipStream_t st) {
     if (s->cells) {
         hipLaunchKernelGGL(k_cell_clear, dim3(blocks_for(a.ncell_total)), dim3(kBlock), 0, st, a, cb);
         hipLaunchKernelGGL(k_bin_working, dim3(slot_blocks(s)), dim3(kBlock), 0, st, a, cb);
-        hipLaunchKernelGGL(k_cell_sort, dim3(a.ncell_total), dim3(kWave), a.cell_cap * sizeof(int), st, a, cb);
+        hipLaunchKernelGGL(k_cell_sort, dim3(a.ncell_total), dim3(kWave), 2 * a.cell_cap * sizeof(int), st, a, cb);
     }
     launch_list(s, -2, -1, cb, st);
     s->cl = cb;
@@ -525,13 +533,13 @@ int grow_lists(h4d_system *s, unsigned err, int max_nbr, int max_cell) {
 void enqueue_learned(h4d_system *s, hipStream_t st, int phase, int b, int cb) {
     KArgs &a = s->a;
     const LearnArgs &l = s->la;
-    const int k = l.k;
-    hipLaunchKernelGGL(k_cand_sites, dim3(blocks_for(k)), dim3(kBlock), 0, st, a, l, phase);
-    hipLaunchKernelGGL(k_site_features, dim3((2 * k * kWave + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a, l, phase,
-                       b, cb);
-    if (l.use_net) hipLaunchKernelGGL(k_mlp_infer_move, dim3((k + 63) / 64), dim3(256), 0, st, a, l, phase);
-    else hipLaunchKernelGGL(k_zero_logits, dim3(blocks_for(k)), dim3(kBlock), 0, st, a, l, phase);
-    hipLaunchKernelGGL(k_mtm_select, dim3(1), dim3(1), 0, st, a, l, phase);
+    const int rows = l.k * s->nbox;   // every box's candidates
+    hipLaunchKernelGGL(k_cand_sites, dim3(blocks_for(rows)), dim3(kBlock), 0, st, a, l, phase);
+    hipLaunchKernelGGL(k_site_features, dim3((int)((2 * (int64_t)rows * kWave + kBlock - 1) / kBlock)), dim3(kBlock),
+                       0, st, a, l, phase, b, cb);
+    if (l.use_net) hipLaunchKernelGGL(k_mlp_infer_move, dim3((rows + 63) / 64), dim3(256), 0, st, a, l, phase);
+    else hipLaunchKernelGGL(k_zero_logits, dim3(blocks_for(rows)), dim3(kBlock), 0, st, a, l, phase);
+    hipLaunchKernelGGL(k_mtm_select, dim3(s->nbox), dim3(kMtmBlock), 0, st, a, l, phase);
 }
 
 // Enqueue every kernel of one round (each box's current trial) on st.  The
@@ -571,6 +579,8 @@ int enqueue_round(h4d_system *s, int move, hipStream_t st, int nf, int M, bool t
     if (a.G.bias_alpha > 0.0) hipLaunchKernelGGL(k_bias_end, dim3(s->nbox), dim3(kBlock), 0, st, a);
     hipLaunchKernelGGL(k_metropolis, dim3(blocks_for(s->nbox)), dim3(kBlock), 0, st, a);
     hipLaunchKernelGGL(k_commit, dim3(G1), dim3(kBlock), 0, st, a);
+    if (a.G.water && move == kMoveMD)   // a rejected phase's reversed refresh, restricted
+        hipLaunchKernelGGL(k_water_cvel, dim3(blocks_for(a.G.n_mol * s->nbox)), dim3(kBlock), 0, st, a, 1);
     hipLaunchKernelGGL(k_compact1, dim3(G1), dim3(kBlock), 0, st, a);
     hipLaunchKernelGGL(k_compact2, dim3(G1), dim3(kBlock), 0, st, a);
     hipLaunchKernelGGL(k_commit_ctl, dim3(blocks_for(s->nbox)), dim3(kBlock), 0, st, a);
@@ -630,6 +640,13 @@ int launch_round(h4d_system *s, int move) {
             HIPC(hipEventElapsedTime(&ms, s->ev[2 * k], s->ev[2 * k + 1]));
             s->step_ms += ms;
             s->step_launches += 1;
+        }
+        // a box's trajectory runs in launches k = 0..N_f of the round; its
+        // blocks of the later ones return at once
+        for (int b = 0; b < s->nbox; ++b) {
+            const TrialRec &r = s->h_rec[b];
+            if (r.flags & kFlagIdle) continue;
+            s->atom_launches += (double)r.n_atoms * (double)(std::min(r.n_steps, nf_dev) + 1);
         }
     }
     return H4D_OK;
@@ -1039,8 +1056,12 @@ int create(const h4d_params *params, int nbox, const double *edges, const int32_
     s->rebuild_every = params->rebuild_every > 0
                            ? params->rebuild_every
                            : std::max(1, (int)std::floor(0.5 * params->skin / (vmax * params->dt)));
-    if (!params->water) {   // the state's own momenta (carried momenta, equilibrium phases)
+    {   // the state's own momenta (carried momenta, equilibrium phases); rigid
+        // waters' restricted to the constraint surface
         hipLaunchKernelGGL(k_init_velocities, dim3(slot_blocks(s)), dim3(kBlock), 0, s->stream, s->a);
+        if (params->water)
+            hipLaunchKernelGGL(k_water_cvel, dim3(blocks_for(s->a.G.n_mol * s->nbox)), dim3(kBlock), 0, s->stream,
+                               s->a, 0);
         if (hipGetLastError() != hipSuccess) { delete s; return fail(H4D_EHIP, "velocity set-up failed"); }
         s->vel_canonical = true;
     }
@@ -1172,7 +1193,6 @@ int32_t h4d_init_speculative(const h4d_params *params, int32_t replicas, int32_t
 int32_t h4d_run_md(h4d_system *s, int32_t n_steps, h4d_trial *out) {
     if (!s) return fail(H4D_EINVAL, "null handle");
     if (n_steps < 1) return fail(H4D_EINVAL, "n_steps must be at least 1");
-    if (s->p.water) return fail(H4D_EINVAL, "the equilibrium phase needs an ion system (water = 0)");
     return run_md(s, n_steps, out);
 }
 
@@ -1518,6 +1538,7 @@ int32_t h4d_set_timing(h4d_system *s, int32_t on) {
     s->retries = 0;
     s->step_launches = 0;
     s->step_ms = 0.0;
+    s->atom_launches = 0.0;
     return H4D_OK;
 }
 
@@ -1542,6 +1563,7 @@ int32_t h4d_get_timing(h4d_system *s, h4d_timing *out) {
     out->lanes = s->a.lanes;
     out->cell_cap = s->a.cell_cap;
     out->retries = s->retries;
+    out->atom_launches = s->atom_launches;
     return H4D_OK;
 }
 
@@ -1951,7 +1973,8 @@ int32_t h4d_set_proposal(h4d_system *s, const h4d_mlp *net, int32_t k, double lo
     if (!(logit_cap == logit_cap) || !std::isfinite(weight_scale) || weight_scale < 0.0)
         return fail(H4D_EINVAL, "logit_cap must not be NaN and weight_scale must be finite and >= 0");
     if (k > 65536) return fail(H4D_EINVAL, "at most 65536 candidates");
-    if (k > 0 && s->nbox != 1) return fail(H4D_EINVAL, "the learned proposal serves single-box systems");
+    if (k > 0 && (int64_t)k * s->nbox * 2 * kWave > (int64_t)INT32_MAX)
+        return fail(H4D_EINVAL, "candidates times boxes too large");
     if (k > 0 && s->a.G.bias_alpha > 0.0)
         return fail(H4D_EINVAL, "the bimodal bias and the learned proposal are exclusive");
     if (k > 0 && s->a.G.v_ex_half > 0.0)
@@ -1964,12 +1987,13 @@ int32_t h4d_set_proposal(h4d_system *s, const h4d_mlp *net, int32_t k, double lo
     l.use_net = 0;
     if (k <= 0) return H4D_OK;
     int rc;
-    if ((rc = s->alloc(&l.sites, (size_t)6 * k)) || (rc = s->alloc(&l.feat, (size_t)kFeat * k)) ||
-        (rc = s->alloc(&l.logit, (size_t)k)))
+    const size_t rows = (size_t)k * s->nbox;   // every box has its own candidates
+    if ((rc = s->alloc(&l.sites, 6 * rows)) || (rc = s->alloc(&l.feat, (size_t)kFeat * rows)) ||
+        (rc = s->alloc(&l.logit, rows)))
         return rc;
     if (!l.last_feat) {
-        if ((rc = s->alloc(&l.last_feat, kFeat))) return rc;
-        HIPC(hipMemset(l.last_feat, 0, sizeof(float) * kFeat));
+        if ((rc = s->alloc(&l.last_feat, (size_t)kFeat * s->nbox))) return rc;
+        HIPC(hipMemset(l.last_feat, 0, sizeof(float) * kFeat * s->nbox));
     }
     l.k = k;
     l.cap = logit_cap;
@@ -1988,16 +2012,26 @@ int32_t h4d_last_site_features(h4d_system *s, float *out) {
     return H4D_OK;
 }
 
-int32_t h4d_last_candidates(h4d_system *s, int32_t cap, double *sites, float *features, float *logits) {
+int32_t h4d_last_box_candidates(h4d_system *s, int32_t box, int32_t cap, double *sites, float *features,
+                                float *logits) {
     if (!s) return fail(H4D_EINVAL, "null handle");
+    if (box < 0 || box >= s->nbox) return fail(H4D_EINVAL, "box index out of range");
     const int k = s->la.k;
     if (k <= 0) return fail(H4D_EINVAL, "the uniform proposal has no candidates");
     if (cap < k) return fail(H4D_EINVAL, "cap smaller than the number of candidates");
-    if (sites) HIPC(hipMemcpyAsync(sites, s->la.sites, sizeof(double) * 6 * k, hipMemcpyDeviceToHost, s->stream));
-    if (features) HIPC(hipMemcpyAsync(features, s->la.feat, sizeof(float) * kFeat * k, hipMemcpyDeviceToHost, s->stream));
-    if (logits) HIPC(hipMemcpyAsync(logits, s->la.logit, sizeof(float) * k, hipMemcpyDeviceToHost, s->stream));
+    const size_t g0 = (size_t)box * k;
+    if (sites)
+        HIPC(hipMemcpyAsync(sites, s->la.sites + 6 * g0, sizeof(double) * 6 * k, hipMemcpyDeviceToHost, s->stream));
+    if (features)
+        HIPC(hipMemcpyAsync(features, s->la.feat + kFeat * g0, sizeof(float) * kFeat * k, hipMemcpyDeviceToHost,
+                            s->stream));
+    if (logits) HIPC(hipMemcpyAsync(logits, s->la.logit + g0, sizeof(float) * k, hipMemcpyDeviceToHost, s->stream));
     HIPC(hipStreamSynchronize(s->stream));
     return k;
+}
+
+int32_t h4d_last_candidates(h4d_system *s, int32_t cap, double *sites, float *features, float *logits) {
+    return h4d_last_box_candidates(s, 0, cap, sites, features, logits);
 }
 
 int32_t h4d_site_features(h4d_system *s, int32_t n, const double *sites, float *features) {
@@ -2013,8 +2047,8 @@ int32_t h4d_site_features(h4d_system *s, int32_t n, const double *sites, float *
     l.sites = sd;
     l.feat = fd;
     HIPC(hipMemcpyAsync(sd, sites, sizeof(double) * 6 * n, hipMemcpyHostToDevice, s->stream));
-    // the current state is an N-state for this hook: evaluate as the
-    // insertion phase does (a forced move flag makes the kernel run)
+    // the current state is an N-state for this hook: evaluated as the
+    // insertion phase does (the hook's kernel takes no move flag)
     hipLaunchKernelGGL(k_site_features_hook, dim3((2 * n * kWave + kBlock - 1) / kBlock), dim3(kBlock), 0, s->stream,
                        s->a, l);
     HIPC(hipGetLastError());

@@ -89,7 +89,7 @@ class Observables(C.Structure):
 class Timing(C.Structure):
     _fields_ = [("step_launches", C.c_int64), ("retries", C.c_int64), ("step_ms", C.c_double),
                 ("mean_nbr", C.c_double), ("rebuild_every", C.c_int32), ("nbr_cap", C.c_int32),
-                ("lanes", C.c_int32), ("cell_cap", C.c_int32)]
+                ("lanes", C.c_int32), ("cell_cap", C.c_int32), ("atom_launches", C.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -158,6 +158,7 @@ def lib() -> C.CDLL:
         L.h4d_set_proposal.argtypes = [vp, vp, C.c_int32, C.c_double, C.c_double]
         L.h4d_last_site_features.argtypes = [vp, fp]
         L.h4d_last_candidates.argtypes = [vp, C.c_int32, dp, fp, fp]
+        L.h4d_last_box_candidates.argtypes = [vp, C.c_int32, C.c_int32, dp, fp, fp]
         L.h4d_site_features.argtypes = [vp, C.c_int32, dp, fp]
         L.h4d_set_beta_mu.argtypes = [vp, C.c_double]
         L.h4d_set_bias.argtypes = [vp, C.c_double, C.c_double]
@@ -173,7 +174,7 @@ def lib() -> C.CDLL:
                      "h4d_run_batch", "h4d_get_box_state", "h4d_box_observables", "h4d_autotune",
                      "h4d_mlp_create", "h4d_mlp_destroy", "h4d_mlp_set_weights", "h4d_mlp_get_weights",
                      "h4d_mlp_forward", "h4d_mlp_loss_grad", "h4d_mlp_train", "h4d_set_proposal",
-                     "h4d_last_site_features", "h4d_last_candidates", "h4d_site_features", "h4d_set_beta_mu",
+                     "h4d_last_site_features", "h4d_last_candidates", "h4d_last_box_candidates", "h4d_site_features", "h4d_set_beta_mu",
                      "h4d_init_speculative", "h4d_run_speculative", "h4d_set_bias", "h4d_run_md", "h4d_set_early_rejection",
                      "h4d_save_checkpoint", "h4d_restore_checkpoint", "h4d_save_box_checkpoint",
                      "h4d_restore_box_checkpoint"):
@@ -382,6 +383,25 @@ class _Handle:
         o = Observables()
         _check(lib().h4d_box_observables(self._h, box, C.byref(o)))
         return o.as_dict()
+
+    def set_proposal(self, net=None, k: int = 0, cap: float = 10.0, scale: float = 1.0):
+        """k <= 0: uniform proposal; k >= 1: multiple-try with k candidates
+        per move and box, weighted by exp(scale * min(logit, cap)) of net
+        (None: equal weights)."""
+        _check(lib().h4d_set_proposal(self._h, net._h if net is not None else None, k, cap, scale))
+        self._net = net     # the network must outlive its use
+
+    def last_candidates(self, k: int, box: int = 0):
+        """Sites, features and logits of the last learned move's k
+        candidates in box `box`."""
+        sites = np.zeros((k, 6))
+        feat = np.zeros((k, 64), np.float32)
+        logit = np.zeros(k, np.float32)
+        rc = lib().h4d_last_box_candidates(self._h, box, k, sites.ctypes.data_as(C.POINTER(C.c_double)),
+                                           _fp(feat), _fp(logit))
+        if rc < 0:
+            _check(rc)
+        return sites, feat, logit
 
     @property
     def n_boxes(self) -> int:
@@ -605,26 +625,10 @@ class System(_Chain):
                                    e.ctypes.data_as(C.POINTER(C.c_double))))
         return F[: st["n"]], dict(U=e[0], U_lj=e[1], U_c=e[2])
 
-    def set_proposal(self, net=None, k: int = 0, cap: float = 10.0, scale: float = 1.0):
-        """k <= 0: uniform proposal; k >= 1: multiple-try with k candidates
-        weighted by exp(scale * min(logit, cap)) of net (None: equal weights)."""
-        _check(lib().h4d_set_proposal(self._h, net._h if net is not None else None, k, cap, scale))
-        self._net = net     # the network must outlive its use
-
     def last_site_features(self) -> np.ndarray:
         f = np.zeros(64, np.float32)
         _check(lib().h4d_last_site_features(self._h, _fp(f)))
         return f
-
-    def last_candidates(self, k: int):
-        sites = np.zeros((k, 6))
-        feat = np.zeros((k, 64), np.float32)
-        logit = np.zeros(k, np.float32)
-        rc = lib().h4d_last_candidates(self._h, k, sites.ctypes.data_as(C.POINTER(C.c_double)), _fp(feat),
-                                       _fp(logit))
-        if rc < 0:
-            _check(rc)
-        return sites, feat, logit
 
     def site_features(self, sites) -> np.ndarray:
         st = np.ascontiguousarray(sites, dtype=np.float64).reshape(-1, 6)

@@ -124,11 +124,12 @@ def test_phase_on_speculative_replicas_keeps_them_equal():
     sp.close()
 
 
-def test_phase_refuses_rigid_water():
-    w = W.water_nacl(n_water=300, n_pairs=10, L=21.0, m=7, seed=78)
-    g = h4d.System.from_workload(w, precision="fp64")
+def test_phase_refuses_an_empty_trajectory():
+    # (rigid water runs phases too: tests/test_gpu_water_md.py)
+    w = W.lj_electrolyte(300, 0.3, 77, n_steps=20, precision="fp64")
+    g = h4d.System.from_workload(w)
     with pytest.raises(h4d.H4DError) as e:
-        g.md_phase(5)
+        g.md_phase(0)
     assert e.value.code == h4d.H4D_EINVAL
     g.close()
 
