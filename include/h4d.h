@@ -528,6 +528,22 @@ int32_t h4d_mlp_get_weights(h4d_mlp *net, float *theta);
  * path, 0 the FP32 training forward. */
 int32_t h4d_mlp_forward(h4d_mlp *net, int32_t rows, const float *features, int32_t bf16,
                         float *logits);
+/*
+ * The same logits without any allocation, for callers that cannot allocate:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  features (rows x 64) and logits (rows) are DEVICE pointers on
+ * the device the network was created on (H4D_EINVAL if another device is
+ * current); the kernels are enqueued on the network's stream and the call
+ * returns without waiting (synchronise that stream before reading logits).
+ * bf16 = 1: the matrix-core inference, reading features and writing logits
+ * directly; bf16 = 0: the FP32 forward, its hidden activations in a static
+ * workspace of the library (4 MiB per device, held until the process ends).
+ * rows <= 4096, else H4D_EINVAL before any work.  The results equal
+ * h4d_mlp_forward's bit for bit.  Calls that overlap on one device share the
+ * workspace and race: serialise them (one stream, or events).
+ */
+int32_t h4d_mlp_forward_static(h4d_mlp *net, int32_t rows, const float *features, int32_t bf16,
+                               float *logits);
 /* Mean-squared loss of the FP32 logits against targets and its gradient
  * (grad[41473], host; may be NULL). */
 int32_t h4d_mlp_loss_grad(h4d_mlp *net, int32_t rows, const float *features,

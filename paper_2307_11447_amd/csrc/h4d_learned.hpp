@@ -435,6 +435,7 @@ __global__ __launch_bounds__(kMtmBlock) void k_mtm_select(KArgs a, LearnArgs l, 
 // Every reduction runs in a fixed order (no atomics).
 // ==========================================================================
 // Z = X W + b, A = gelu(Z) (act) or Z; X n x I, W I x O (row-major)
+// (Z may be null: the forward alone keeps only the activations)
 __global__ void k_dense_fwd(const float *X, const float *W, const float *b, float *Z, float *A, int n, int I, int O,
                             int act) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -442,7 +443,7 @@ __global__ void k_dense_fwd(const float *X, const float *W, const float *b, floa
     const int r = idx / O, o = idx % O;
     float z = b[o];
     for (int i = 0; i < I; ++i) z += X[(size_t)r * I + i] * W[(size_t)i * O + o];
-    Z[idx] = z;
+    if (Z) Z[idx] = z;
     A[idx] = act ? gelu_f(z) : z;
 }
 

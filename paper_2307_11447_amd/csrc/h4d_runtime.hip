@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <chrono>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <cmath>
 #include <cstdio>
@@ -1664,8 +1665,46 @@ int32_t h4d_autotune(h4d_system *s, int32_t trials, int32_t *lanes_out, int32_t 
 // ==========================================================================
 // Learned proposal: the network handle and its training.
 // ==========================================================================
+// Workspace of the network forward that allocates nothing
+// (h4d_mlp_forward_static): the FP32 hidden activations of up to
+// kStaticRows rows, two ping-pong layers of kStaticRows x 128 floats (4 MiB).
+// Each device holds its own copy until the process ends; host code reaches it
+// only through the address hipGetSymbolAddress gives on that device.
+constexpr int kStaticRows = 4096;
+static __device__ __align__(256) float scratch[2 * kStaticRows * kHid];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev, resolved once per device with
+// that device current.
+int scratch_address(int dev, float **out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (dev < 0 || dev >= kMaxDevices) return fail(H4D_ENODEV, "device index beyond the workspace table");
+    if (!g_scratch_dev[dev]) {
+        int cur = 0;
+        HIPC(hipGetDevice(&cur));
+        if (cur != dev) HIPC(hipSetDevice(dev));
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !ptr)
+            return fail(H4D_EHIP, std::string("hipGetSymbolAddress of the static workspace: ") + hipGetErrorString(e));
+        g_scratch_dev[dev] = static_cast<float *>(ptr);
+    }
+    *out = g_scratch_dev[dev];
+    return H4D_OK;
+}
+
+}  // namespace
+
 struct h4d_mlp {
     hipStream_t stream = nullptr;
+    int device = 0;                        // the device the parameters live on
+    float *scratch = nullptr;              // that device's static workspace
     float *theta = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
     bf16x4 *wfrag = nullptr;
     long long adam_t = 0;
@@ -1768,6 +1807,9 @@ int32_t h4d_mlp_create(uint64_t seed, void *hip_stream, h4d_mlp **out) {
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(H4D_ENODEV, "no HIP device");
     auto *n = new h4d_mlp();
     n->stream = static_cast<hipStream_t>(hip_stream);
+    int rc0 = hipGetDevice(&n->device) == hipSuccess ? scratch_address(n->device, &n->scratch)
+                                                     : fail(H4D_EHIP, "hipGetDevice failed");
+    if (rc0) { delete n; return rc0; }
     const size_t P = kParams;
     if (hipMalloc((void **)&n->theta, P * 4) != hipSuccess || hipMalloc((void **)&n->m, P * 4) != hipSuccess ||
         hipMalloc((void **)&n->v, P * 4) != hipSuccess || hipMalloc((void **)&n->g, P * 4) != hipSuccess ||
@@ -1836,6 +1878,35 @@ int32_t h4d_mlp_forward(h4d_mlp *n, int32_t rows, const float *features, int32_t
     HIPC(hipGetLastError());
     HIPC(hipMemcpyAsync(logits, n->S, sizeof(float) * rows, hipMemcpyDeviceToHost, n->stream));
     HIPC(hipStreamSynchronize(n->stream));
+    return H4D_OK;
+}
+
+int32_t h4d_mlp_forward_static(h4d_mlp *n, int32_t rows, const float *features, int32_t bf16, float *logits) {
+    if (!n || rows < 0 || (rows && (!features || !logits))) return fail(H4D_EINVAL, "null argument or negative size");
+    if (rows > kStaticRows)
+        return fail(H4D_EINVAL, "rows exceed the static workspace (at most " + std::to_string(kStaticRows) + ")");
+    if (!rows) return H4D_OK;
+    int cur = -1;
+    HIPC(hipGetDevice(&cur));
+    if (cur != n->device) return fail(H4D_EINVAL, "call on the device the network was created on");
+    const hipStream_t st = n->stream;
+    const float *th = n->theta;
+    if (bf16) {
+        hipLaunchKernelGGL(k_mlp_infer, dim3((rows + 63) / 64), dim3(256), 0, st, features, rows, th, n->wfrag,
+                           logits);
+    } else {   // the FP32 forward of mlp_fwd32, activations ping-ponged through the workspace
+        float *h0 = n->scratch, *h1 = n->scratch + (size_t)kStaticRows * kHid;
+        const dim3 grid(blocks_for(rows * kHid));
+        hipLaunchKernelGGL(k_dense_fwd, grid, dim3(kBlock), 0, st, features, th + kOffW1, th + kOffB1, nullptr, h0,
+                           rows, kFeat, kHid, 1);
+        hipLaunchKernelGGL(k_dense_fwd, grid, dim3(kBlock), 0, st, h0, th + kOffW2, th + kOffB2, nullptr, h1, rows,
+                           kHid, kHid, 1);
+        hipLaunchKernelGGL(k_dense_fwd, grid, dim3(kBlock), 0, st, h1, th + kOffW3, th + kOffB3, nullptr, h0, rows,
+                           kHid, kHid, 1);
+        hipLaunchKernelGGL(k_dense_fwd, dim3(blocks_for(rows)), dim3(kBlock), 0, st, h0, th + kOffW4, th + kOffB4,
+                           nullptr, logits, rows, kHid, 1, 0);
+    }
+    HIPC(hipGetLastError());
     return H4D_OK;
 }
 

@@ -152,6 +152,7 @@ def lib() -> C.CDLL:
         L.h4d_mlp_set_weights.argtypes = [vp, fp]
         L.h4d_mlp_get_weights.argtypes = [vp, fp]
         L.h4d_mlp_forward.argtypes = [vp, C.c_int32, fp, C.c_int32, fp]
+        L.h4d_mlp_forward_static.argtypes = [vp, C.c_int32, vp, C.c_int32, vp]
         L.h4d_mlp_loss_grad.argtypes = [vp, C.c_int32, fp, fp, fp, fp]
         L.h4d_mlp_train.argtypes = [vp, C.c_int32, fp, fp, C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_uint64,
                                     fp]
@@ -173,7 +174,7 @@ def lib() -> C.CDLL:
                      "h4d_set_trial_index", "h4d_forces_at", "h4d_destroy", "h4d_init_batch", "h4d_num_boxes",
                      "h4d_run_batch", "h4d_get_box_state", "h4d_box_observables", "h4d_autotune",
                      "h4d_mlp_create", "h4d_mlp_destroy", "h4d_mlp_set_weights", "h4d_mlp_get_weights",
-                     "h4d_mlp_forward", "h4d_mlp_loss_grad", "h4d_mlp_train", "h4d_set_proposal",
+                     "h4d_mlp_forward", "h4d_mlp_forward_static", "h4d_mlp_loss_grad", "h4d_mlp_train", "h4d_set_proposal",
                      "h4d_last_site_features", "h4d_last_candidates", "h4d_last_box_candidates", "h4d_site_features", "h4d_set_beta_mu",
                      "h4d_init_speculative", "h4d_run_speculative", "h4d_set_bias", "h4d_run_md", "h4d_set_early_rejection",
                      "h4d_save_checkpoint", "h4d_restore_checkpoint", "h4d_save_box_checkpoint",
@@ -279,6 +280,13 @@ class Mlp:
         out = np.zeros(max(len(X), 1), np.float32)
         _check(lib().h4d_mlp_forward(self._h, len(X), _fp(X), 1 if bf16 else 0, _fp(out)))
         return out[: len(X)]
+
+    def forward_static(self, rows: int, features_ptr: int, logits_ptr: int, bf16: bool = True):
+        """h4d_mlp_forward_static: logits of rows x 64 device features into
+        device memory (raw device addresses), enqueued on the network's
+        stream without allocating or waiting."""
+        _check(lib().h4d_mlp_forward_static(self._h, rows, C.c_void_p(features_ptr), 1 if bf16 else 0,
+                                            C.c_void_p(logits_ptr)))
 
     def loss_grad(self, X, t):
         X = np.ascontiguousarray(X, dtype=np.float32).reshape(-1, 64)
