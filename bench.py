@@ -14,19 +14,24 @@ chain's records equal to a one-by-one run):
            attempt (Sec. II B 4, Eqs. 15-16, with a learned weight), each
            scored by the network (64 features -> 3 x 128 GELU -> 1) in BF16
            on the matrix cores, the ratio corrected exactly.
-Before the timed region: pilot insertions and deletions on the start state
+Before the timed region: the lattice start relaxes through equilibrium
+phases (generalized hybrid MC); pilot insertions and deletions on that state
 (forced moves that are never accepted, so the state stays fixed) give the
 operating beta mu by Bennett's acceptance ratio (Crooks' relation, the
 supplement's CFT/BAR section) and the network's training data (features and
 work of the method's own moves); the network trains on the GPU (FP32
-forward, backward, Adam).
+forward, backward, Adam); a fixed-state comparison of a few weight scales
+picks one, and a second one on fresh trials compares it with the uniform
+proposal (expected acceptance in log space: at the equilibrium beta mu of
+0.5 ps flights it underflows).
 
 One "step" of this benchmark is one exchange trial of the chain.  value =
 NEMD atom-steps/s of the learned arm (the whole hot path, candidate scoring
 included); the plain arm, accepted exchanges/s of both arms with Wilson
-intervals, and a fixed-state comparison of their insertion and deletion
-acceptance stand beside it.  Extra keys time the 32,000-ion LJ chain and
-the 256-box batch (--no-extras leaves them out).
+intervals, and the fixed-state comparison stand beside it.  Extra keys: the
+32,000-ion LJ chain with the same learned-vs-plain study (there exchanges
+are frequent enough to count), and the 256-box batch (--no-extras leaves
+them out).
 
 Other workloads: --workload lj32k (32,000 LJ ions), --workload batched (256
 independent LJ boxes of 1,000-16,000 ions).
@@ -229,6 +234,20 @@ def timed(torch, fn):
     return out, time.perf_counter() - t0
 
 
+def relaxed(h4d, w, phases, steps):
+    """The workload's start state after `phases` equilibrium phases of
+    `steps` steps (generalized hybrid MC with a full momentum refresh: each
+    phase starts from fresh Maxwell-Boltzmann momenta, so the excess energy
+    of the lattice start leaves with the old ones), as a workload."""
+    import dataclasses
+    g = h4d.System.from_workload(w, md_refresh=0.0)
+    acc = sum(g.md_phase(steps)[0]["accepted"] for _ in range(phases))
+    st = g.state()
+    g.close()
+    note(f"relaxation: {phases} phases of {steps} steps, {acc} accepted")
+    return dataclasses.replace(w, x=st["x"], type=st["type"], mol=st["mol"], tag=st["tag"], nsalt=int(st["nsalt"]))
+
+
 # ---------------------------------------------------------------------------
 # Pilot, chemical potential, network and its weighting
 # ---------------------------------------------------------------------------
@@ -247,15 +266,6 @@ def pilot(sys_, h4d, n_ins, n_del):
         out[key] = (recs, feats, bm)
     sys_.set_proposal(None, 0)
     return out
-
-
-def ln_ratio_at(rec, beta_mu_rec, beta_mu):
-    """ln R of a record moved from the beta mu it ran at to another one
-    (an insertion's ln R rises with beta mu, a deletion's falls)."""
-    lr = rec["ln_ratio"]
-    if rec["flags"] & 0x3 or not math.isfinite(lr):
-        return -math.inf
-    return lr + (beta_mu - beta_mu_rec) * (1.0 if rec["move"] > 0 else -1.0)
 
 
 def train_network(h4d, X, y, epochs, seed=1):
@@ -280,39 +290,14 @@ def out_of_fold(h4d, X, y, epochs, folds=5):
     return oof
 
 
-def choose_scale(s_ins, lr_ins, s_del, lr_del, cap=10.0, scales=(0.25, 0.5, 0.75, 1.0), margin=1.25):
-    """Weight scale of the multiple-try proposal at many candidates, from
-    uniform pilot moves: with k large, the chosen site is drawn from
-    q(y) ~ exp(lw(y)) over uniform sites and ln(W/k) tends to ln Z,
-    Z = E_uniform[exp(lw)], so the mean insertion acceptance is
-    sum_i e^lw_i min(1, e^(lnR_i + lnZ - lw_i)) / sum_i e^lw_i (importance
-    weights over the pilot insertions) and the mean deletion acceptance
-    mean_j min(1, e^(lnR_j + lw_j - lnZ)); lw = scale min(s, cap), s the
-    network's logits (out-of-fold for the insertions).  The uniform proposal
-    (scale 0) is kept unless the best scale beats it by the margin."""
+def log_mean_exp(v):
+    """ln of the mean of exp(v) (entries of -inf count as zeros)."""
     import numpy as np
-    s_ins = np.minimum(np.asarray(s_ins, np.float64), cap)
-    s_del = np.minimum(np.asarray(s_del, np.float64), cap)
-    lr_ins = np.asarray(lr_ins, np.float64)
-    lr_del = np.asarray(lr_del, np.float64)
-
-    def est(scale):
-        lw_i, lw_d = scale * s_ins, scale * s_del
-        m = lw_i.max()
-        wi = np.exp(lw_i - m)
-        lnZ = m + math.log(wi.mean())
-        p_ins = float((wi * np.exp(np.minimum(0.0, lr_ins + lnZ - lw_i))).sum() / wi.sum())
-        p_del = float(np.mean(np.exp(np.minimum(0.0, lr_del + lw_d - lnZ))))
-        return p_ins, p_del
-
-    table = {"uniform": est(0.0)}
-    best, best_v = 0.0, 0.5 * sum(table["uniform"]) * margin
-    for sc in scales:
-        table[f"scale{sc}"] = est(sc)
-        v = 0.5 * sum(table[f"scale{sc}"])
-        if v > best_v:
-            best, best_v = sc, v
-    return best, {k: {"p_ins": v[0], "p_del": v[1]} for k, v in table.items()}
+    v = np.asarray(v, dtype=np.float64)
+    if len(v) == 0 or not np.isfinite(v.max()):
+        return -math.inf
+    m = v.max()
+    return float(m + math.log(np.exp(v - m).sum()) - math.log(len(v)))
 
 
 def proposal_ab(sys_, torch, h4d, arms, beta_mu, n_each, block=50):
@@ -320,15 +305,18 @@ def proposal_ab(sys_, torch, h4d, arms, beta_mu, n_each, block=50):
     state: forced moves at beta mu = -1000 (insertions) and +1000
     (deletions), which are never accepted, so the state does not change;
     each record's ln R is moved to the operating beta mu and the mean of
-    min(1, R) taken.  The arms alternate in blocks so that they share the
-    same state and device conditions.  arms: name -> (net, k, scale)."""
+    min(1, R) taken -- in log space, since at an equilibrium beta mu with
+    short flights it underflows.  The arms alternate in blocks so that they
+    share the same state and device conditions.  arms: name -> (net, k,
+    scale, cap) (k = 0: the uniform proposal)."""
+    import numpy as np
     out = {name: {"ins": [], "del": [], "s": 0.0, "n": 0} for name in arms}
     done = 0
     while done < n_each:
         nb = min(block, n_each - done)
-        for name, (net, k, scale) in arms.items():
+        for name, (net, k, scale, cap) in arms.items():
             if k > 0:
-                sys_.set_proposal(net, k, 10.0, scale)
+                sys_.set_proposal(net, k, cap, scale)
             else:
                 sys_.set_proposal(None, 0)
             for move, bm, key in ((h4d.MOVE_INSERT, -1.0e3, "ins"), (h4d.MOVE_DELETE, 1.0e3, "del")):
@@ -340,161 +328,251 @@ def proposal_ab(sys_, torch, h4d, arms, beta_mu, n_each, block=50):
                 for q in range(nb):
                     r = arr[q]
                     ok = not (r.flags & 0x3) and math.isfinite(r.ln_ratio)
-                    out[name][key].append(math.exp(min(0.0, r.ln_ratio + shift)) if ok else 0.0)
+                    out[name][key].append(min(0.0, r.ln_ratio + shift) if ok else -math.inf)
         done += nb
     sys_.set_proposal(None, 0)
     sys_.set_beta_mu(beta_mu)
     res = {}
+    ln10 = math.log(10.0)
     for name, o in out.items():
-        p_ins = sum(o["ins"]) / max(1, len(o["ins"]))
-        p_del = sum(o["del"]) / max(1, len(o["del"]))
+        li, ld = log_mean_exp(o["ins"]), log_mean_exp(o["del"])
         rate = o["n"] / max(1e-300, o["s"])
-        res[name] = {"p_insert": p_ins, "p_delete": p_del, "trials_per_s": rate,
-                     "expected_exchanges_per_s": 0.5 * (p_ins + p_del) * rate,
+        lx = math.log(0.5) + np.logaddexp(li, ld) + math.log(rate)
+        fi = np.array([v for v in o["ins"] if v > -math.inf])
+        fd = np.array([v for v in o["del"] if v > -math.inf])
+        res[name] = {"log10_p_insert": li / ln10, "log10_p_delete": ld / ln10,
+                     "p_insert": math.exp(li), "p_delete": math.exp(ld), "trials_per_s": rate,
+                     "log10_expected_exchanges_per_s": float(lx / ln10), "expected_exchanges_per_s": float(math.exp(lx)),
+                     "ln_acc_insert_median": float(np.median(fi)) if len(fi) else None,
+                     "ln_acc_delete_median": float(np.median(fd)) if len(fd) else None,
                      "insertions": len(o["ins"]), "deletions": len(o["del"])}
     names = list(arms)
     for other in names[1:]:
-        g, ci = ab_gain(out[names[0]], out[other])
-        res[f"gain_{other}"], res[f"gain_{other}_bootstrap90"] = g, ci
+        g, ci = ab_log_gain(out[names[0]], out[other])
+        res[f"log10_gain_{other}"], res[f"log10_gain_{other}_bootstrap90"] = g, ci
     return res
 
 
-def ab_gain(u, l, reps=2000, seed=11):
-    """Ratio of expected exchanges per second (another proposal over the
-    first) and its 90 % bootstrap interval (moves resampled within each arm
-    and kind); None when the first arm's expected acceptance is below 1e-12
-    (the ratio is then meaningless)."""
+def ab_log_gain(u, l, reps=1000, seed=11):
+    """log10 of the ratio of expected exchanges per second (another proposal
+    over the first) and its 90 % bootstrap interval (moves resampled within
+    each arm and kind); None where an arm accepts nothing at all."""
     import numpy as np
     rng = np.random.default_rng(seed)
-    rate_u, rate_l = u["n"] / u["s"], l["n"] / l["s"]
 
-    def ex(o, rate, pick):
-        return 0.5 * (np.mean(pick(o["ins"])) + np.mean(pick(o["del"]))) * rate
+    def lex(o, pick):
+        return np.logaddexp(log_mean_exp(pick(o["ins"])), log_mean_exp(pick(o["del"]))) + math.log(o["n"] / o["s"])
 
-    ident = np.asarray
-    if ex(u, rate_u, ident) < 1e-12:
+    def ident(x):
+        return np.asarray(x)
+
+    def res(x):
+        x = np.asarray(x)
+        return x[rng.integers(0, len(x), len(x))]
+
+    a, b = lex(u, ident), lex(l, ident)
+    if not (np.isfinite(a) and np.isfinite(b)):
         return None, None
-    g = ex(l, rate_l, ident) / ex(u, rate_u, ident)
     boot = []
     for _ in range(reps):
-        def res(x):
-            x = np.asarray(x)
-            return x[rng.integers(0, len(x), len(x))]
-        den = ex(u, rate_u, res)
-        boot.append(ex(l, rate_l, res) / den if den > 0 else float("inf"))
-    lo, hi = np.percentile(boot, [5, 95])
-    return float(g), [float(lo), float(hi)]
+        d = lex(l, res) - lex(u, res)
+        if np.isfinite(d):
+            boot.append(d)
+    ln10 = math.log(10.0)
+    lo, hi = np.percentile(boot, [5, 95]) if boot else (math.nan, math.nan)
+    return float((b - a) / ln10), [float(lo / ln10), float(hi / ln10)]
+
+
+def learned_study(args, h4d, torch, w, label, n_ins, n_del, n_select, n_ab, candidates, beta_mu=None):
+    """The learned proposal on one state: pilot moves (forced, never
+    accepted), beta mu from BAR over them (unless given), the network
+    trained on the GPU on the pilot insertions, its weight scale chosen by
+    a fixed-state comparison of a few scales, and the final fixed-state
+    comparison against the uniform proposal on fresh trials.
+
+    Target: the insertion work itself, -beta dH, centred on its pilot mean
+    and clipped to 8 standard deviations.  The multiple-try step depends on
+    the log weights only up to a common shift, so the network needs no
+    beta mu; the cap on a logit is the largest training target, so the
+    choice is never steered beyond what the pilot saw."""
+    import numpy as np
+    from paper_2307_11447_amd import analysis
+    beta = 1.0 / w.params["kT"]
+    one = h4d.System.from_workload(w)
+    tuned = one.autotune(2) if args.autotune else None
+    if tuned:
+        note(f"{label}: autotune: {tuned[0]} lanes per atom, rebuild every {tuned[1]} steps")
+    # the tuned lane width; the rebuild interval stays automatic (it adapts to
+    # the trials' fast atoms, where a fixed one would recompute every trial
+    # whose fast list overflows)
+    over = {} if not tuned else dict(lanes_per_atom=tuned[0])
+    if args.lanes:
+        over["lanes_per_atom"] = args.lanes
+    t0 = time.perf_counter()
+    pil = pilot(one, h4d, n_ins, n_del)
+    pilot_s = time.perf_counter() - t0
+    ins_recs, ins_feat, _ = pil["ins"]
+    del_recs, _, _ = pil["del"]
+    note(f"{label}: pilot: {n_ins} insertions and {n_del} deletions in {pilot_s:.1f} s")
+    dM_ins = [r["dM"] for r in ins_recs if not r["flags"] & 0x3]
+    dM_del = [r["dM"] for r in del_recs if not r["flags"] & 0x3]
+    cal = analysis.work_summary(dM_ins, dM_del, beta, 0.0)
+    bmu = beta_mu if beta_mu is not None else cal["beta_mu_bar"]
+    cal = analysis.work_summary(dM_ins, dM_del, beta, bmu)
+    cal["beta_mu_operating"] = bmu
+    cal["note"] = ("uniform forced insertions and deletions on the state (none accepted): beta mu from Bennett's "
+                   "acceptance ratio, P_acc predicted by Eq. (21) at the operating beta mu")
+    note(f"{label}: BAR beta mu = {cal['beta_mu_bar']:.3f} {cal['beta_mu_bar_bootstrap90']}; operating at {bmu:.3f}")
+    X = np.array(ins_feat, dtype=np.float32)
+    ok = np.array([not r["flags"] & 0x3 and math.isfinite(r["dH"]) for r in ins_recs])
+    y = -beta * np.array([r["dH"] for r in ins_recs])[ok]
+    X = X[ok]
+    y = y - y.mean()
+    sd = y.std()
+    y = np.clip(y, -8.0 * sd, 8.0 * sd).astype(np.float32)
+    cap = float(y.max())
+    t0 = time.perf_counter()
+    oof = out_of_fold(h4d, X, y, args.train_epochs)
+    net, steps, losses = train_network(h4d, X, y, args.train_epochs)
+    train_s = time.perf_counter() - t0
+    oof_corr = float(np.corrcoef(oof, y)[0, 1]) if np.std(oof) > 0 else None
+    note(f"{label}: network: out-of-fold correlation {oof_corr}")
+    one.set_beta_mu(bmu)
+    scale = args.scale
+    select = None
+    if scale is None:
+        arms = {"plain": (None, 0, 0.0, cap)}
+        for sc in (0.25, 0.5, 1.0):
+            arms[f"scale{sc}"] = (net, candidates, sc, cap)
+        select = proposal_ab(one, torch, h4d, arms, bmu, n_select)
+        best, best_v = 0.0, select["plain"]["log10_expected_exchanges_per_s"] + math.log10(1.25)
+        for sc in (0.25, 0.5, 1.0):
+            v = select[f"scale{sc}"]["log10_expected_exchanges_per_s"]
+            if v > best_v:
+                best, best_v = sc, v
+        scale = best
+    note(f"{label}: weight scale {scale} at k = {candidates}")
+    ab = None
+    if n_ab > 0:
+        ab = proposal_ab(one, torch, h4d, {"plain": (None, 0, 0.0, cap), "learned": (net, candidates, scale, cap)},
+                         bmu, n_ab)
+    one.close()
+    info = {"candidates": candidates, "weight_scale": scale, "logit_cap": cap,
+            "inference": "BF16 MFMA (v_mfma_f32_16x16x16_bf16), FP32 accumulation",
+            "target": "-beta dH of the pilot insertions, centred, clipped to 8 standard deviations",
+            "out_of_fold_corr_logit_vs_target": oof_corr, "target_sd_kT": float(sd),
+            "pilot_insertions": n_ins, "pilot_deletions": n_del, "pilot_s": pilot_s,
+            "train_rows": int(len(X)), "train_steps": steps, "train_s": train_s,
+            "train_loss_first": float(losses[:10].mean()), "train_loss_last": float(losses[-50:].mean()),
+            "scale_selection": select, "fixed_state": ab}
+    return net, scale, cap, over, info, cal, bmu
 
 
 # ---------------------------------------------------------------------------
 # The default workload: aqueous NaCl, learned vs plain
 # ---------------------------------------------------------------------------
-def bench_nacl(args, h4d, W, torch):
-    import numpy as np
-    from paper_2307_11447_amd import analysis
-    w = W.config_water_nacl()
-    w.params.update(capacity=w.n + 1024)
-    beta = 1.0 / w.params["kT"]
-    V = float(np.prod(w.params["box"]))
-    one = h4d.System.from_workload(w)
-    tuned = one.autotune(2) if args.autotune else None
-    if tuned:
-        note(f"autotune: {tuned[0]} lanes per atom, rebuild every {tuned[1]} steps")
-    over = {}
-    if tuned:
-        over.update(lanes_per_atom=tuned[0], rebuild_every=tuned[1])
-    # pilot on the start state (the autotuner's trials left it unchanged
-    # unless one was accepted: take the state as it is now)
-    st = one.state()
-    t0 = time.perf_counter()
-    pil = pilot(one, h4d, args.pilot, args.pilot_del)
-    pilot_s = time.perf_counter() - t0
-    note(f"pilot: {args.pilot} insertions and {args.pilot_del} deletions in {pilot_s:.1f} s")
-    ins_recs, ins_feat, bm_ins = pil["ins"]
-    del_recs, del_feat, bm_del = pil["del"]
-    dM_ins = [r["dM"] for r in ins_recs if not r["flags"] & 0x3]
-    dM_del = [r["dM"] for r in del_recs if not r["flags"] & 0x3]
-    cal = analysis.work_summary(dM_ins, dM_del, beta, 0.0)
-    beta_mu = args.beta_mu if args.beta_mu is not None else cal["beta_mu_bar"]
-    cal = analysis.work_summary(dM_ins, dM_del, beta, beta_mu)
-    cal["note"] = ("uniform forced insertions and deletions on the start state (none accepted): beta mu from "
-                   "Bennett's acceptance ratio, P_acc predicted by Eq. (21) at the operating beta mu")
-    note(f"BAR: beta mu = {cal['beta_mu_bar']:.3f} {cal['beta_mu_bar_bootstrap90']}; operating at {beta_mu:.3f}")
-    # the network: target the clipped log insertion ratio at the operating
-    # point, c - beta dH with c = beta mu + I
-    c = beta_mu + 2.0 * math.log(V / (st["nsalt"] + 1))
-    X = np.array(ins_feat, dtype=np.float32)
-    bdH = beta * np.array([r["dH"] for r in ins_recs])
-    ok = np.isfinite(bdH) & np.array([not r["flags"] & 0x3 for r in ins_recs])
-    X, bdH = X[ok], bdH[ok]
-    y = np.clip(c - bdH, -100.0, 10.0).astype(np.float32)
-    t0 = time.perf_counter()
-    oof = out_of_fold(h4d, X, y, args.train_epochs)
-    net, steps, losses = train_network(h4d, X, y, args.train_epochs)
-    s_del = net.forward(np.array(del_feat, dtype=np.float32))
-    train_s = time.perf_counter() - t0
-    lr_ins = [ln_ratio_at(r, bm_ins, beta_mu) for r, k in zip(ins_recs, ok) if k]
-    lr_del = [ln_ratio_at(r, bm_del, beta_mu) for r in del_recs]
-    scale, estimates = choose_scale(oof, lr_ins, s_del, lr_del)
-    if args.scale is not None:
-        scale = args.scale
-    oof_corr = float(np.corrcoef(oof, y)[0, 1]) if np.std(oof) > 0 else None
-    note(f"network: out-of-fold correlation {oof_corr}, weight scale {scale} at k = {args.candidates}")
-    # the timed arms: the same chain from the same state on speculative replicas
-    arms = {}
-    learned_timing = None
+def timed_arms(args, h4d, torch, w, beta_mu, over, net, scale, cap, candidates, steps, warmup, timing_trials):
+    """The plain and learned arms, each one chain from the same state on
+    speculative replicas; returns their summaries and the learned arm's
+    step-kernel timing."""
+    arms, timing = {}, None
     for name in ("plain", "learned"):
         spec = h4d.Speculative.from_workload(w, args.replicas, beta_mu=beta_mu, **over)
-        if name == "learned":
-            spec.set_proposal(net, args.candidates, 10.0, scale)
-        if args.warmup:
-            spec.trials(args.warmup)
+        if name == "learned" and scale > 0.0:
+            spec.set_proposal(net, candidates, cap, scale)
+        if warmup:
+            spec.trials(warmup)
         r0 = spec.rounds
-        arr, wall = timed(torch, lambda: spec.trials(args.steps, as_array=True))
-        recs = [arr[q] for q in range(args.steps)]
-        arms[name] = arm_summary(recs, wall, spec.rounds - r0)
-        note(f"{name}: {args.steps} trials in {wall:.2f} s, {arms[name]['accepted']} accepted")
-        if name == "learned":
+        arr, wall = timed(torch, lambda: spec.trials(steps, as_array=True))
+        arms[name] = arm_summary([arr[q] for q in range(steps)], wall, spec.rounds - r0)
+        note(f"{name}: {steps} trials in {wall:.2f} s, {arms[name]['accepted']} accepted")
+        if name == "learned" and timing_trials > 0:
             spec.set_timing(True)
-            spec.trials(args.timing_trials)
-            learned_timing = spec.timing()
+            spec.trials(timing_trials)
+            timing = spec.timing()
             spec.set_timing(False)
         spec.close()
-    # both proposals on the start state, forced moves alternating in blocks
-    ab = None
-    if args.ab_trials > 0:
-        one.set_beta_mu(beta_mu)
-        ab = proposal_ab(one, torch, h4d, {"plain": (None, 0, 0.0), "learned": (net, args.candidates, scale)},
-                         beta_mu, args.ab_trials)
-        note(f"fixed-state comparison: {args.ab_trials} insertions and deletions per proposal")
-    one.close()
-    net.close()
+    return arms, timing
+
+
+def learned_vs_plain(arms, info):
     la, pa = arms["learned"], arms["plain"]
+    return {
+        "accepted_exchanges_per_s_ratio": (la["accepted_exchanges_per_s"] / pa["accepted_exchanges_per_s"]
+                                           if pa["accepted"] > 0 else None),
+        "expected_exchanges_per_s_ratio": (la["expected_exchanges_per_s"] / pa["expected_exchanges_per_s"]
+                                           if pa["expected_exchanges_per_s"] > 1e-300 else None),
+        "atom_steps_per_s_ratio": la["atom_steps_per_s"] / pa["atom_steps_per_s"],
+        "fixed_state_log10_gain": ((info or {}).get("fixed_state") or {}).get("log10_gain_learned"),
+        "fixed_state_log10_gain_bootstrap90": ((info or {}).get("fixed_state") or {}).get(
+            "log10_gain_learned_bootstrap90"),
+    }
+
+
+def gcmd_cycles(args, h4d, torch, w, beta_mu, over, cycles, n_eq):
+    """The grand-canonical cycle of Fig. 1 on one box: an equilibrium phase
+    of n_eq steps (generalized hybrid MC, partial momentum refresh c = 0.5)
+    and one exchange trial that carries the state's momenta with the
+    symmetric two-end reversal (Sec. II A)."""
+    g = h4d.System.from_workload(w, beta_mu=beta_mu, momenta=1, md_refresh=0.5, **over)
+    g.md_phase(n_eq)
+    g.trial()
+    md, tr = [], []
+    t_md = 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(cycles):
+        t1 = time.perf_counter()
+        md.append(g.md_phase(n_eq)[0])
+        torch.cuda.synchronize()
+        t_md += time.perf_counter() - t1
+        tr.append(g.trial())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    g.close()
+    steps = sum(r["n_atoms"] * (r["n_steps"] + 1) for r in md + tr)
+    note(f"gcmd: {cycles} cycles of {n_eq} equilibrium steps and one trial in {wall:.2f} s")
+    return {"cycle": f"equilibrium phase of {n_eq} steps (partial momentum refresh c = 0.5, Metropolis on dH) + "
+                     "one trial with carried momenta and the two-end reversal",
+            "cycles": cycles, "ms_per_cycle": 1e3 * wall / cycles, "atom_steps_per_s": steps / wall,
+            "equilibrium_share_of_wall": t_md / wall,
+            "equilibrium_acceptance": sum(r["accepted"] for r in md) / cycles,
+            "equilibrium_mean_abs_beta_dH": sum(abs(r["dH"]) for r in md) / cycles / w.params["kT"],
+            "trials_accepted": sum(r["accepted"] for r in tr)}
+
+
+def bench_nacl(args, h4d, W, torch):
+    w0 = W.config_water_nacl()
+    w0.params.update(capacity=w0.n + 1024)
+    w = relaxed(h4d, w0, args.relax_phases, 100) if args.relax_phases > 0 else w0
+    if args.pilot > 0:
+        net, scale, cap, over, info, cal, beta_mu = learned_study(
+            args, h4d, torch, w, "nacl", args.pilot, args.pilot_del, args.select_trials, args.ab_trials,
+            args.candidates, beta_mu=args.beta_mu)
+    else:   # no pilot, no network: both arms uniform (a profiling run of the timed configuration)
+        if args.beta_mu is None:
+            raise SystemExit("bench.py: --pilot 0 needs --beta-mu")
+        net, scale, cap, info, cal, beta_mu = None, 0.0, 10.0, None, None, args.beta_mu
+        over = {"lanes_per_atom": args.lanes} if args.lanes else {}
+    arms, timing = timed_arms(args, h4d, torch, w, beta_mu, over, net, scale, cap, args.candidates, args.steps,
+                              args.warmup, args.timing_trials)
+    if net is not None:
+        net.close()
+    gcmd = gcmd_cycles(args, h4d, torch, w, beta_mu, over, args.gcmd_cycles, 1000) if args.gcmd_cycles else None
+    la = arms["learned"]
     out = {
         "value": la["atom_steps_per_s"], "trials_per_s": la["trials_per_s"],
         "accepted_exchanges_per_s": la["accepted_exchanges_per_s"],
         "arms": arms,
-        "learned_vs_plain": {
-            "accepted_exchanges_per_s_ratio": (la["accepted_exchanges_per_s"] / pa["accepted_exchanges_per_s"]
-                                               if pa["accepted"] > 0 else None),
-            "expected_exchanges_per_s_ratio": (la["expected_exchanges_per_s"] / pa["expected_exchanges_per_s"]
-                                               if pa["expected_exchanges_per_s"] > 1e-12 else None),
-            "atom_steps_per_s_ratio": la["atom_steps_per_s"] / pa["atom_steps_per_s"],
-            "fixed_state": ab,
-            "note": "accepted counts are rare at the BAR beta mu with 500-step flights; the expected acceptance "
-                    "(mean of min(1, R) over the trials) and the fixed-state comparison carry the comparison",
-        },
-        "learned": {"candidates": args.candidates, "weight_scale": scale, "logit_cap": 10.0,
-                    "inference": "BF16 MFMA (v_mfma_f32_16x16x16_bf16), FP32 accumulation",
-                    "scale_choice_estimates": estimates, "out_of_fold_corr_logit_vs_target": oof_corr,
-                    "pilot_insertions": args.pilot, "pilot_deletions": args.pilot_del, "pilot_s": pilot_s,
-                    "train_rows": int(len(X)), "train_steps": steps, "train_s": train_s,
-                    "train_loss_first": float(losses[:10].mean()), "train_loss_last": float(losses[-50:].mean()),
-                    "target": "clip(beta mu + I - beta dH, -100, 10) of the pilot insertions"},
+        "learned_vs_plain": dict(learned_vs_plain(arms, info), note=(
+            "at the BAR beta mu with 500-step flights of 0.5 ps, neither proposal's exchanges are accepted in a "
+            "bench-length run; the fixed-state comparison gives their expected acceptance in log space")),
+        "learned": info,
         "mu_calibration": cal,
-        "roofline": roofline(learned_timing, counted_traffic(TRAFFIC_FILES["water"]),
+        "gcmd": gcmd,
+        "roofline": roofline(timing, counted_traffic(TRAFFIC_FILES["water"]),
                              "k_step<1,L> (fused pair force + velocity Verlet), learned arm"),
-        "lanes_per_atom": learned_timing["lanes"], "rebuild_every": learned_timing["rebuild_every"],
+        "lanes_per_atom": timing["lanes"], "rebuild_every": timing["rebuild_every"],
         "execution": {"mode": "speculative", "replicas": args.replicas},
     }
     config = {
@@ -505,6 +583,7 @@ def bench_nacl(args, h4d, W, torch):
                     f"plain arm: uniform; each arm one chain on {args.replicas} speculative replicas",
         "n_atoms": w.n, "n_waters": 8000, "n_pairs": 150, "box_A": 62.0, "n_steps_per_trial": 500,
         "dt_fs": 1.0, "w_max_A": 3.0, "candidates": args.candidates,
+        "start": f"lattice start relaxed by {args.relax_phases} equilibrium phases of 100 steps",
         "beta_mu": beta_mu, "beta_mu_source": "given" if args.beta_mu is not None else
         "Bennett's acceptance ratio over the pilot insertions and deletions",
         "skin": w.params["skin"], "parallelism": f"one chain, {args.replicas} speculative replicas, one GPU",
@@ -518,28 +597,33 @@ def bench_nacl(args, h4d, W, torch):
 # The 32,000-ion LJ chain and the 256-box batch
 # ---------------------------------------------------------------------------
 def leg_lj32k(args, h4d, W, torch, steps, warmup, timing_trials):
-    w = W.config_lj_32k()
-    w.params.update(capacity=w.n + 1024, beta_mu=args.lj_beta_mu)
-    spec = h4d.Speculative.from_workload(w, args.replicas)
-    tuned = spec.autotune(2) if args.autotune else None
-    if warmup:
-        spec.trials(warmup)
-    r0 = spec.rounds
-    arr, wall = timed(torch, lambda: spec.trials(steps, as_array=True))
-    out = arm_summary([arr[q] for q in range(steps)], wall, spec.rounds - r0)
-    spec.set_timing(True)
-    spec.trials(timing_trials)
-    tm = spec.timing()
-    spec.close()
+    """The 32,000-ion LJ chain (relaxed lattice start) at its BAR beta mu:
+    plain and learned arms on speculative replicas, and the learned study
+    behind them."""
+    w0 = W.config_lj_32k()
+    w0.params.update(capacity=w0.n + 1024)
+    w = relaxed(h4d, w0, 10, 200)
+    net, scale, cap, over, info, cal, bmu = learned_study(
+        args, h4d, torch, w, "lj32k", args.lj_pilot, args.lj_pilot // 2, args.select_trials, args.lj_ab_trials,
+        args.candidates, beta_mu=args.lj_beta_mu)
+    arms, tm = timed_arms(args, h4d, torch, w, bmu, over, net, scale, cap, args.candidates, steps, warmup,
+                          timing_trials)
+    net.close()
+    out = dict(arms["plain"])
     out["value"] = out.pop("atom_steps_per_s")
+    out["learned_arm"] = arms["learned"]
+    out["learned_vs_plain"] = learned_vs_plain(arms, info)
+    out["learned"] = info
+    out["mu_calibration"] = cal
     out["roofline"] = roofline(tm, counted_traffic(TRAFFIC_FILES["lj32k"]),
                                "k_step<1,L> (fused pair force + velocity Verlet)")
     out["lanes_per_atom"], out["rebuild_every"] = tm["lanes"], tm["rebuild_every"]
-    out["autotune"] = tuned
     out["config"] = {"workload": "lj32k: 32,000 LJ ions, density 0.3, 200-step NEMD pair insert/delete, FP32 pair "
-                                 "arithmetic / FP64 state, uniform proposal, one chain on speculative replicas",
-                     "replicas": args.replicas, "beta_mu": args.lj_beta_mu}
-    note(f"lj32k: {steps} trials, {out['value']:.3g} atom-steps/s, frac {out['roofline']['frac']:.3f}")
+                                 "arithmetic / FP64 state; value: the uniform proposal, one chain on speculative "
+                                 "replicas; learned_arm: the same chain with the learned multiple-try proposal",
+                     "replicas": args.replicas, "beta_mu": bmu, "start": "lattice start relaxed by 10 equilibrium "
+                     "phases of 200 steps", "candidates": args.candidates}
+    note(f"lj32k: {steps} trials per arm, {out['value']:.3g} atom-steps/s, frac {out['roofline']['frac']:.3f}")
     return out, w
 
 
@@ -547,6 +631,8 @@ def leg_batched(args, h4d, W, torch, steps, warmup, timing_trials, learned_k=0):
     ws = W.config_batched()
     for w in ws:
         w.params.update(beta_mu=args.batch_beta_mu)
+        if args.fixed_nf:     # every trial the same N_f: rounds with no box idle, for comparison
+            w.params.update(n_steps_min=args.fixed_nf, n_steps_max=args.fixed_nf)
         if args.rebuild_every:
             w.params.update(rebuild_every=args.rebuild_every)
         if args.lanes:
@@ -569,7 +655,8 @@ def leg_batched(args, h4d, W, torch, steps, warmup, timing_trials, learned_k=0):
     out["autotune"] = tuned
     out["config"] = {"workload": "batched256: 256 LJ-electrolyte boxes, N even in [1000, 16000] (2,220,126 ions), "
                                  "density U[0.1, 0.4], N_f ~ U{100..400} per trial, FP32 pair arithmetic / FP64 "
-                                 "state, uniform proposal; every box runs its trial in one round of launches",
+                                 "state, uniform proposal; every box runs its trial in one round of launches" +
+                                 (f" (N_f fixed at {args.fixed_nf} for comparison)" if args.fixed_nf else ""),
                      "n_boxes": len(ws), "n_atoms": sum(w.n for w in ws), "trials_per_box": steps,
                      "beta_mu": args.batch_beta_mu}
     note(f"batched256: {steps} trials per box, {out['value']:.3g} atom-steps/s, frac {out['roofline']['frac']:.3f}")
@@ -586,16 +673,28 @@ def main():
     ap.add_argument("--warmup", type=int, default=None, help="untimed trials first (default 5 / 20 / 2)")
     ap.add_argument("--beta-mu", type=float, default=None,
                     help="nacl: beta mu (default: Bennett's acceptance ratio over the pilot moves)")
-    ap.add_argument("--lj-beta-mu", type=float, default=-8.8,
-                    help="lj32k: beta mu (default -8.8, the BAR estimate of the 32,000-ion state)")
+    ap.add_argument("--lj-beta-mu", type=float, default=None,
+                    help="lj32k: beta mu (default: Bennett's acceptance ratio over its pilot moves)")
+    ap.add_argument("--lj-pilot", type=int, default=1000, help="lj32k: pilot insertions (half as many deletions)")
+    ap.add_argument("--lj-ab-trials", type=int, default=300,
+                    help="lj32k: forced insertions and deletions per proposal in the fixed-state comparison")
+    ap.add_argument("--relax-phases", type=int, default=40,
+                    help="nacl: equilibrium phases of 100 steps that relax the lattice start")
+    ap.add_argument("--gcmd-cycles", type=int, default=3,
+                    help="nacl: grand-canonical cycles (1000-step equilibrium phase + one trial) timed after the rest")
+    ap.add_argument("--select-trials", type=int, default=60,
+                    help="forced insertions and deletions per weight scale when choosing it")
     ap.add_argument("--batch-beta-mu", type=float, default=-4.0, help="batched: beta mu")
-    ap.add_argument("--pilot", type=int, default=500, help="nacl: pilot insertions")
+    ap.add_argument("--fixed-nf", type=int, default=0,
+                    help="batched: every trial N_f steps (0: N_f ~ U{100..400} per trial, the workload's own)")
+    ap.add_argument("--pilot", type=int, default=500,
+                    help="nacl: pilot insertions (0: no learned study, both arms uniform; needs --beta-mu)")
     ap.add_argument("--pilot-del", type=int, default=250, help="nacl: pilot deletions")
     ap.add_argument("--train-epochs", type=int, default=30, help="nacl: passes over the pilot data")
     ap.add_argument("--candidates", type=int, default=CANDIDATES, help="nacl: candidate sites per learned move")
     ap.add_argument("--scale", type=float, default=None, help="nacl: weight scale (default: chosen from the pilot)")
     ap.add_argument("--replicas", type=int, default=8, help="speculative replicas of a single chain")
-    ap.add_argument("--ab-trials", type=int, default=150,
+    ap.add_argument("--ab-trials", type=int, default=200,
                     help="nacl: forced insertions and deletions per proposal on the start state (0: none)")
     ap.add_argument("--timing-trials", type=int, default=None,
                     help="trials after the timed region with HIP events on the step kernel (default 4 / 20 / 1)")
@@ -639,16 +738,16 @@ def main():
     if wl == "nacl":
         out, config, base = bench_nacl(args, h4d, W, torch)
         if not args.no_extras:
-            extras["lj32k"], w32 = leg_lj32k(args, h4d, W, torch, 100, 10, 5)
+            extras["lj32k"], w32 = leg_lj32k(args, h4d, W, torch, 200, 10, 5)
             if not args.no_cpu_baseline:
                 extras["lj32k"]["cpu_baseline"] = cpu_baseline(w32, 200, "the 32,000-ion state",
-                                                               args.lj_beta_mu)
+                                                               extras["lj32k"]["config"]["beta_mu"])
             extras["batched256"], _ = leg_batched(args, h4d, W, torch, 2, 1, 1)
     elif wl == "lj32k":
         out, w32 = leg_lj32k(args, h4d, W, torch, args.steps, args.warmup, args.timing_trials)
         config = out.pop("config")
         base = None if args.no_cpu_baseline else cpu_baseline(w32, args.cpu_steps or 200, "the 32,000-ion state",
-                                                              args.lj_beta_mu)
+                                                              config["beta_mu"])
     else:
         out, ws = leg_batched(args, h4d, W, torch, args.steps, args.warmup, args.timing_trials)
         config = out.pop("config")

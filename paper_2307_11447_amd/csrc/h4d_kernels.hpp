@@ -463,30 +463,49 @@ __global__ __launch_bounds__(kBlock) void k_bin_working(KArgs a, int cb) {
     bin_atom(a, B, c, cb, w, a.pos[buf_of(-1, c)][w]);
 }
 
-// dynamic LDS: 2 cell_cap ints (members and their sub-cells)
+// One wavefront per cell: the members grouped by sub-cell (a counting pass,
+// then each member's place in its group by the members of that group with a
+// smaller index), so the order is (sub-cell, index) whatever order the
+// binning atomics left.  Dynamic LDS: 3 cell_cap ints.
 __global__ __launch_bounds__(kWave) void k_cell_sort(KArgs a, int cb) {
     extern __shared__ int buf[];
-    int *sub = buf + a.cell_cap;
+    int *sub = buf + a.cell_cap, *grp = sub + a.cell_cap;
+    __shared__ int gstart[9], gfill[8];
     const int cc = blockIdx.x;
     const int cnt = min(a.cell_cnt[cb][cc], a.cell_cap);
     int *row = a.cell_atoms[cb] + (size_t)cc * a.cell_cap;
+    if (threadIdx.x < 8) gfill[threadIdx.x] = 0;
     for (int q = threadIdx.x; q < cnt; q += kWave) {
         const int e = row[q];
         buf[q] = e;
         sub[q] = a.slot_sub[e];
     }
     __syncthreads();
-    for (int q = threadIdx.x; q < cnt; q += kWave) {
-        const int e = buf[q], se = sub[q];
+    if (threadIdx.x < 8) {   // members of each sub-cell
         int r = 0;
-        for (int p = 0; p < cnt; ++p) r += (sub[p] < se) | ((sub[p] == se) & (buf[p] < e));
+        for (int p = 0; p < cnt; ++p) r += sub[p] == (int)threadIdx.x;
+        gstart[threadIdx.x + 1] = r;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        gstart[0] = 0;
+        for (int q = 0; q < 8; ++q) gstart[q + 1] += gstart[q];
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < cnt; q += kWave) {
+        const int g = sub[q];
+        grp[gstart[g] + atomicAdd(&gfill[g], 1)] = buf[q];
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < cnt; q += kWave) {
+        int g = 0;
+        while (gstart[g + 1] <= q) ++g;
+        const int e = grp[q];
+        int r = gstart[g];
+        for (int p = gstart[g]; p < gstart[g + 1]; ++p) r += grp[p] < e;
         row[r] = e;
     }
-    if (threadIdx.x < 8) {   // sub-cell q's members begin where the smaller sub-cells end
-        int r = 0;
-        for (int p = 0; p < cnt; ++p) r += sub[p] < (int)threadIdx.x;
-        a.cell_sub[cb][8 * (size_t)cc + threadIdx.x] = r;
-    }
+    if (threadIdx.x < 8) a.cell_sub[cb][8 * (size_t)cc + threadIdx.x] = gstart[threadIdx.x];
 }
 
 // exclusive scan of each box's cell counts (one block per box); cell_off

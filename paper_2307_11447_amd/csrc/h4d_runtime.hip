@@ -439,7 +439,7 @@ int sort_in(h4d_system *s, hipStream_t st) {
     const int nc = a.ncell_total;
     hipLaunchKernelGGL(k_cell_clear, dim3(blocks_for(nc)), dim3(kBlock), 0, st, a, 0);
     hipLaunchKernelGGL(k_bin_canonical, dim3(slot_blocks(s)), dim3(kBlock), 0, st, a, 0);
-    hipLaunchKernelGGL(k_cell_sort, dim3(nc), dim3(kWave), 2 * a.cell_cap * sizeof(int), st, a, 0);
+    hipLaunchKernelGGL(k_cell_sort, dim3(nc), dim3(kWave), 3 * a.cell_cap * sizeof(int), st, a, 0);
     hipLaunchKernelGGL(k_cell_scan, dim3(s->nbox), dim3(1024), 0, st, a, 0);
     hipLaunchKernelGGL(k_gather_in, dim3(nc), dim3(kWave), 0, st, a, 0);
     if (a.G.water) hipLaunchKernelGGL(k_rattle_mb, dim3(blocks_for(a.G.n_mol * s->nbox)), dim3(kBlock), 0, st, a);
@@ -455,7 +455,7 @@ int rebuild_mid(h4d_system *s, int k, int b, hipStream_t st) {
     KArgs &a = s->a;
     const int cb = s->cl ^ 1;
     if (s->cells)
-        hipLaunchKernelGGL(k_cell_sort, dim3(a.ncell_total), dim3(kWave), 2 * a.cell_cap * sizeof(int), st, a, cb);
+        hipLaunchKernelGGL(k_cell_sort, dim3(a.ncell_total), dim3(kWave), 3 * a.cell_cap * sizeof(int), st, a, cb);
     launch_list(s, k, b, cb, st);
     s->cl = cb;
     HIPC(hipGetLastError());
@@ -470,7 +470,7 @@ int rebuild_final(h4d_system *s, hipStream_t st) {
     if (s->cells) {
         hipLaunchKernelGGL(k_cell_clear, dim3(blocks_for(a.ncell_total)), dim3(kBlock), 0, st, a, cb);
         hipLaunchKernelGGL(k_bin_working, dim3(slot_blocks(s)), dim3(kBlock), 0, st, a, cb);
-        hipLaunchKernelGGL(k_cell_sort, dim3(a.ncell_total), dim3(kWave), 2 * a.cell_cap * sizeof(int), st, a, cb);
+        hipLaunchKernelGGL(k_cell_sort, dim3(a.ncell_total), dim3(kWave), 3 * a.cell_cap * sizeof(int), st, a, cb);
     }
     launch_list(s, -2, -1, cb, st);
     s->cl = cb;

@@ -1,8 +1,8 @@
 """The bench's arithmetic on made-up inputs (no GPU): the step kernel's
 roofline against HBM with the algorithmic bytes 4 n_list + 36 of the pair
 pass plus 120 of the integration, the FLOP fraction beside it, the
-acceptance summary of trial records, and the choice of the learned
-proposal's weight scale at many candidates."""
+acceptance summary of trial records, and the log-space acceptance and
+gain of the fixed-state comparison."""
 import math
 import os
 import sys
@@ -49,26 +49,17 @@ def test_arm_summary_counts_and_expected_acceptance():
     assert out["n_salt_first"] == 10 and out["n_salt_last"] == 11 and out["rounds"] == 3
 
 
-def test_scale_choice_at_many_candidates():
-    """The multiple-try ratio keeps the uniform ratio's mean, so a weighting
-    gains only where uniform ratios above 1 are cut off.  Here 1 % of the
-    uniform insertion sites have ln R = 5 and the rest -30, and the logits
-    name them: at scale 1 nearly every chosen site is a good one and its
-    ratio is Z e^5 / e^5 = Z > 1, so the insertion acceptance rises from
-    0.01 to about 1; deletions (ln R = 50) are accepted either way.  Zero
-    logits leave every estimate at the uniform one, and logits unrelated to
-    the work keep the uniform proposal."""
-    rng = np.random.default_rng(3)
-    good = rng.random(5000) < 0.01
-    lr_ins = np.where(good, 5.0, -30.0)
-    lr_del = np.full(1000, 50.0)
-    s_del = np.zeros(1000)
-    scale, est = bench.choose_scale(lr_ins, lr_ins, s_del, lr_del)
-    assert est["uniform"]["p_ins"] == pytest.approx(np.mean(np.exp(np.minimum(0.0, lr_ins))))
-    assert est["uniform"]["p_del"] == pytest.approx(1.0)
-    assert est["scale1.0"]["p_ins"] > 0.99 and scale == 1.0
-    _, est0 = bench.choose_scale(np.zeros(5000), lr_ins, s_del, lr_del)
-    for key in ("scale0.5", "scale1.0"):
-        assert est0[key]["p_ins"] == pytest.approx(est0["uniform"]["p_ins"])
-    scale2, _ = bench.choose_scale(rng.normal(0.0, 4.0, size=5000), lr_ins, s_del, lr_del)
-    assert scale2 == 0.0
+def test_log_space_acceptance_and_gain():
+    """The fixed-state comparison averages min(1, R) in log space (an
+    equilibrium beta mu with short flights underflows): zeros count, a
+    tenfold acceptance at the same trial rate is a log10 gain of exactly 1,
+    and an arm that accepts nothing has no ratio."""
+    assert bench.log_mean_exp([0.0, -math.inf]) == pytest.approx(math.log(0.5))
+    assert bench.log_mean_exp([-800.0, -802.0]) == pytest.approx(-800.0 + math.log((1 + math.exp(-2)) / 2))
+    assert bench.log_mean_exp([-math.inf]) == -math.inf
+    u = {"ins": [math.log(1e-30)] * 40, "del": [math.log(3e-31)] * 40, "n": 80, "s": 2.0}
+    l = {"ins": [math.log(1e-29)] * 40, "del": [math.log(3e-30)] * 40, "n": 80, "s": 2.0}
+    g, ci = bench.ab_log_gain(u, l)
+    assert g == pytest.approx(1.0) and ci[0] == pytest.approx(1.0) and ci[1] == pytest.approx(1.0)
+    none = {"ins": [-math.inf] * 4, "del": [-math.inf] * 4, "n": 8, "s": 1.0}
+    assert bench.ab_log_gain(none, l) == (None, None)
