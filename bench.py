@@ -308,17 +308,24 @@ def proposal_ab(sys_, torch, h4d, arms, beta_mu, n_each, block=50):
     min(1, R) taken -- in log space, since at an equilibrium beta mu with
     short flights it underflows.  The arms alternate in blocks so that they
     share the same state and device conditions.  arms: name -> (net, k,
-    scale, cap) (k = 0: the uniform proposal)."""
+    scale, cap[, (x_b, alpha_b, v_ex_edge)]) (k = 0: the uniform proposal;
+    the optional last entry sets the bimodal bias and early rejection)."""
     import numpy as np
-    out = {name: {"ins": [], "del": [], "s": 0.0, "n": 0} for name in arms}
+    out = {name: {"ins": [], "del": [], "s": 0.0, "n": 0, "instant": 0} for name in arms}
     done = 0
     while done < n_each:
         nb = min(block, n_each - done)
-        for name, (net, k, scale, cap) in arms.items():
+        for name, spec in arms.items():
+            net, k, scale, cap = spec[:4]
+            x_b, alpha_b, v_ex = spec[4] if len(spec) > 4 else (0.0, 0.0, 0.0)
+            sys_.set_early_rejection(0.0)
             if k > 0:
+                sys_.set_bias(0.0, 0.0)
                 sys_.set_proposal(net, k, cap, scale)
             else:
                 sys_.set_proposal(None, 0)
+                sys_.set_bias(x_b, alpha_b)
+                sys_.set_early_rejection(v_ex)
             for move, bm, key in ((h4d.MOVE_INSERT, -1.0e3, "ins"), (h4d.MOVE_DELETE, 1.0e3, "del")):
                 sys_.set_beta_mu(bm)
                 arr, dt = timed(torch, lambda: sys_.trials(nb, move, as_array=True))
@@ -329,8 +336,11 @@ def proposal_ab(sys_, torch, h4d, arms, beta_mu, n_each, block=50):
                     r = arr[q]
                     ok = not (r.flags & 0x3) and math.isfinite(r.ln_ratio)
                     out[name][key].append(min(0.0, r.ln_ratio + shift) if ok else -math.inf)
+                    out[name]["instant"] += int(bool(r.flags & 0x10))
         done += nb
     sys_.set_proposal(None, 0)
+    sys_.set_bias(0.0, 0.0)
+    sys_.set_early_rejection(0.0)
     sys_.set_beta_mu(beta_mu)
     res = {}
     ln10 = math.log(10.0)
@@ -345,7 +355,8 @@ def proposal_ab(sys_, torch, h4d, arms, beta_mu, n_each, block=50):
                      "log10_expected_exchanges_per_s": float(lx / ln10), "expected_exchanges_per_s": float(math.exp(lx)),
                      "ln_acc_insert_median": float(np.median(fi)) if len(fi) else None,
                      "ln_acc_delete_median": float(np.median(fd)) if len(fd) else None,
-                     "insertions": len(o["ins"]), "deletions": len(o["del"])}
+                     "insertions": len(o["ins"]), "deletions": len(o["del"]),
+                     "instant_fraction": o["instant"] / max(1, o["n"])}
     names = list(arms)
     for other in names[1:]:
         g, ci = ab_log_gain(out[names[0]], out[other])
@@ -466,6 +477,20 @@ def learned_study(args, h4d, torch, w, label, n_ins, n_del, n_select, n_ab, cand
             "train_loss_first": float(losses[:10].mean()), "train_loss_last": float(losses[-50:].mean()),
             "scale_selection": select, "fixed_state": ab}
     return net, scale, cap, over, info, cal, bmu
+
+
+def bias_study(h4d, torch, w, beta_mu, n_each, x_b, alpha_b, v_ex):
+    """The bimodal bias of the flyers' separation (Sec. II B 4, Eq. 14) and
+    early rejection on top of it, against the uniform proposal, at a fixed
+    state (proposal_ab)."""
+    one = h4d.System.from_workload(w)
+    try:
+        return proposal_ab(one, torch, h4d, {"plain": (None, 0, 0.0, 0.0),
+                                              "bias": (None, 0, 0.0, 0.0, (x_b, alpha_b, 0.0)),
+                                              "bias_early": (None, 0, 0.0, 0.0, (x_b, alpha_b, v_ex))},
+                           beta_mu, n_each)
+    finally:
+        one.close()
 
 
 # ---------------------------------------------------------------------------
@@ -609,12 +634,20 @@ def leg_lj32k(args, h4d, W, torch, steps, warmup, timing_trials):
     arms, tm = timed_arms(args, h4d, torch, w, bmu, over, net, scale, cap, args.candidates, steps, warmup,
                           timing_trials)
     net.close()
+    bias = None
+    if args.lj_bias_trials > 0:
+        # flyers near contact (x_b = 1 sigma, alpha_b = 2 / sigma^2); V_ex edge 1.2 sigma
+        bias = bias_study(h4d, torch, w, bmu, args.lj_bias_trials, 1.0, 2.0, 1.2)
+        bias["settings"] = {"x_b": 1.0, "alpha_b": 2.0, "v_ex_edge": 1.2}
+        note(f"lj32k: bias: log10 gain {bias['log10_gain_bias']} {bias['log10_gain_bias_bootstrap90']}, "
+             f"with early rejection {bias['log10_gain_bias_early']}")
     out = dict(arms["plain"])
     out["value"] = out.pop("atom_steps_per_s")
     out["learned_arm"] = arms["learned"]
     out["learned_vs_plain"] = learned_vs_plain(arms, info)
     out["learned"] = info
     out["mu_calibration"] = cal
+    out["bimodal_bias"] = bias
     out["roofline"] = roofline(tm, counted_traffic(TRAFFIC_FILES["lj32k"]),
                                "k_step<1,L> (fused pair force + velocity Verlet)")
     out["lanes_per_atom"], out["rebuild_every"] = tm["lanes"], tm["rebuild_every"]
@@ -644,6 +677,14 @@ def leg_batched(args, h4d, W, torch, steps, warmup, timing_trials, learned_k=0):
     arr, wall = timed(torch, lambda: bat.run(steps, as_array=True))
     recs = [arr[q] for q in range(len(ws) * steps)]
     out = arm_summary(recs, wall)
+    # lockstep rounds: round q runs trial q of every box for as many steps as
+    # its longest trajectory; the share of those atom-step slots that integrate
+    work = slots = 0
+    for q in range(steps):
+        rr = [arr[b * steps + q] for b in range(len(ws))]
+        work += sum(r.n_steps * r.n_atoms for r in rr)
+        slots += max(r.n_steps for r in rr) * sum(r.n_atoms for r in rr)
+    out["lockstep_slot_utilisation"] = work / max(1, slots)
     bat.set_timing(True)
     bat.run(timing_trials)
     tm = bat.timing()
@@ -676,6 +717,8 @@ def main():
     ap.add_argument("--lj-beta-mu", type=float, default=None,
                     help="lj32k: beta mu (default: Bennett's acceptance ratio over its pilot moves)")
     ap.add_argument("--lj-pilot", type=int, default=1000, help="lj32k: pilot insertions (half as many deletions)")
+    ap.add_argument("--lj-bias-trials", type=int, default=150,
+                    help="lj32k: forced insertions and deletions per arm of the bimodal-bias comparison (0: none)")
     ap.add_argument("--lj-ab-trials", type=int, default=300,
                     help="lj32k: forced insertions and deletions per proposal in the fixed-state comparison")
     ap.add_argument("--relax-phases", type=int, default=40,

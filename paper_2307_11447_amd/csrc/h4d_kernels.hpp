@@ -659,20 +659,25 @@ __global__ __launch_bounds__(kBlock) void k_list_allpairs(KArgs a, int k, int b0
 // eight half-edge octants; cell_sub says where each begins), and `split`
 // blocks of kListWaves wavefronts serve the centre atoms of one sub-cell
 // (block s of the sub-cell takes its centre atoms t with (t / kListWaves) %
-// split == s).  Cells have edge >= r_list, so along each axis the far half
+// split == s); with units = 1 they serve a whole cell instead, every range
+// of the 27 cells staged (sparse cells, where a sub-cell would give the
+// wavefronts too few centre atoms).  Cells have edge >= r_list, so along each axis the far half
 // of a neighbouring cell lies at least one cell edge away from this
 // sub-cell: of the 27 x 8 neighbouring sub-cells only the 5 x 5 x 5 around
 // it can hold partners (125 / 216 of the 27 cells' volume), and only those
 // ranges are staged in LDS -- all at once when they fit in cand_cap entries,
 // else in consecutive groups of ranges (cand_cap >= 9 cell_cap, so every
-// range fits).  Candidates are staged as fixed-point coordinates + working
-// slot in stencil order (cell, then sub-cell, then index); each wavefront
-// takes its centre atoms in turn and tests 64 candidates per ballot (a group
-// is padded to whole wavefronts with entries that never match), appending
-// partners in that order (a centre atom's running count stays in LDS across
-// the groups).  MOL: rigid molecules present (pairs within a molecule are
-// left out).  Dynamic LDS: (cand_cap + cell_cap + 64) * 16 + cell_cap * 4
-// bytes.  Also records the build positions, clears this cell's count in the
+// range fits).  Of those, only the candidates within r_list of the centre
+// sub-cell's box are kept (about half of them: the box grown by r_list is
+// far smaller than the 5 x 5 x 5 block), as fixed-point coordinates +
+// working slot in stencil order (cell, then sub-cell, then index); each
+// wavefront takes its centre atoms in turn and tests 64 candidates per
+// ballot, two ballots per pass (the kept candidates are padded to whole
+// pairs of wavefronts with entries that never match), appending partners in
+// that order (a centre atom's running count stays in LDS across the
+// groups).  The lists are the same as without the box test.  MOL: rigid
+// molecules present (pairs within a molecule are left out).  Dynamic LDS:
+// (cand_cap + 128 + cell_cap) * 16 + cell_cap * 4 bytes.  Also records the build positions, clears this cell's count in the
 // other buffer and the box's fast lists.
 constexpr int kListWaves = 8;
 constexpr int kSubRanges = 27 * 8;
@@ -684,15 +689,17 @@ struct BoolTag {
 
 template <bool MOL>
 __global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int k, int b0, int cb, int split,
-                                                                    int cand_cap) {
+                                                                    int cand_cap, int units) {
     extern __shared__ uint4 lds[];
     __shared__ int roff[kSubRanges + 1], rstart[kSubRanges], rcell[kSubRanges];
     __shared__ int s_c0, s_mc;
     const int cap = a.cell_cap;
-    uint4 *cand = lds;                             // cand_cap + 64 staged candidates
-    uint4 *ctr = lds + (size_t)cand_cap + kWave;   // the sub-cell's centre atoms (at most cap)
+    uint4 *cand = lds;                             // cand_cap + 128 staged candidates
+    uint4 *ctr = lds + (size_t)cand_cap + 2 * kWave;   // the sub-cell's centre atoms (at most cap)
     int *ccount = reinterpret_cast<int *>(ctr + cap);
-    const int part = (int)blockIdx.x % split, sc = ((int)blockIdx.x / split) & 7, cc = (int)blockIdx.x / split / 8;
+    // units 8: one centre sub-cell sc per block group; units 1: the whole cell (sc = -1)
+    const int part = (int)blockIdx.x % split, un = ((int)blockIdx.x / split) % units;
+    const int cc = (int)blockIdx.x / split / units, sc = units == 8 ? un : -1;
     const int bi = box_of_cell(a, cc);
     const Box &B = a.box[bi];
     Ctl *c = a.ctl + bi;
@@ -707,8 +714,9 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int 
         // this sub-cell is the centre cell's half on the neighbour's side
         const int q = threadIdx.x, t = q >> 3, su = q & 7;
         auto keep = [](int d, int h, int hc) { return d == 0 || (d < 0 ? (h == 1 || hc == 0) : (h == 0 || hc == 1)); };
-        const bool ok = keep(t % 3 - 1, su & 1, sc & 1) && keep((t / 3) % 3 - 1, (su >> 1) & 1, (sc >> 1) & 1) &&
-                        keep(t / 9 - 1, (su >> 2) & 1, (sc >> 2) & 1);
+        const bool ok = sc < 0 || (keep(t % 3 - 1, su & 1, sc & 1) &&
+                                   keep((t / 3) % 3 - 1, (su >> 1) & 1, (sc >> 1) & 1) &&
+                                   keep(t / 9 - 1, (su >> 2) & 1, (sc >> 2) & 1));
         const int c2 = stencil_cell(B, cx, cy, cz, t);
         const int n2 = min(a.cell_cnt[cb][c2], cap);
         const int lo = min(a.cell_sub[cb][8 * (size_t)c2 + su], n2);
@@ -716,9 +724,11 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int 
         rcell[q] = c2;
         rstart[q] = lo;
         roff[q + 1] = ok ? max(0, hi - lo) : 0;
-        if (t == 13 && su == sc) { s_c0 = lo; s_mc = max(0, hi - lo); }   // the centre cell is stencil entry 13
+        // the centre cell is stencil entry 13
+        if (t == 13 && sc >= 0 && su == sc) { s_c0 = lo; s_mc = max(0, hi - lo); }
+        if (t == 13 && sc < 0 && su == 0) { s_c0 = 0; s_mc = n2; }
     }
-    if (threadIdx.x == 0 && cc == B.c0 && part == 0 && sc == 0) c->nfast[0] = c->nfast[1] = c->nfast[2] = 0;
+    if (threadIdx.x == 0 && cc == B.c0 && part == 0 && un == 0) c->nfast[0] = c->nfast[1] = c->nfast[2] = 0;
     __syncthreads();
     if (threadIdx.x == 0) {
         roff[0] = 0;
@@ -727,7 +737,7 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int 
     __syncthreads();
     const int mc = s_mc;
     if (part * kListWaves >= mc) {               // no centre atoms for this block
-        if (part == 0 && sc == 0 && threadIdx.x == 0) a.cell_cnt[cb ^ 1][cc] = 0;
+        if (part == 0 && un == 0 && threadIdx.x == 0) a.cell_cnt[cb ^ 1][cc] = 0;
         return;
     }
     const int *crow = a.cell_atoms[cb] + (size_t)cc * cap + s_c0;
@@ -750,9 +760,36 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int 
         far_pad = make_uint4(opposite(cx, nx), opposite(cy, ny), opposite(cz, nz), 0xffffffffu);
     }
     const float rl2u = (float)(a.G.rlist2 / ((double)sx * (double)sx)) * 1.00001f;   // in fixed-point units
+    // the centre sub-cell's (or cell's) box in fixed-point units: its middle
+    // and half its edge (plus a margin for the rounding of the binning), and
+    // r_list^2 with a margin above the FP32 rounding of both distance tests
+    uint3 mid;
+    unsigned hw[3];
+    {
+        const int kc[3] = {cx, cy, cz};
+        unsigned mv[3];
+        for (int d = 0; d < 3; ++d) {
+            const double n = (double)B.ncell[d];
+            const double lo = sc < 0 ? kc[d] : kc[d] + 0.5 * ((sc >> d) & 1), half = sc < 0 ? 0.5 : 0.25;
+            mv[d] = (unsigned)(unsigned long long)((lo + half) / n * 4294967296.0);
+            hw[d] = (unsigned)(half / n * 4294967296.0) + 64u;
+        }
+        mid = make_uint3(mv[0], mv[1], mv[2]);
+    }
+    const float cull2 = (float)a.G.rlist2 * 1.0002f;
+    auto near_box = [&](const uint4 &q) {
+        auto gap = [](unsigned u, unsigned m, unsigned h) {
+            const int d = (int)(u - m);
+            const unsigned ad = d < 0 ? 0u - (unsigned)d : (unsigned)d;
+            return (float)(ad > h ? ad - h : 0u);
+        };
+        const float gx = gap(q.x, mid.x, hw[0]) * sx, gy = gap(q.y, mid.y, hw[1]) * sy;
+        const float gz = gap(q.z, mid.z, hw[2]) * sz;
+        return gx * gx + gy * gy + gz * gz < cull2;
+    };
+    __shared__ int wkept[kListWaves];
     const unsigned lim_u = __float_as_uint(rl2u) - 1u;
-    const unsigned long long below = (1ull << lane) - 1ull;
-    const int ll = a.lanes_log2, lmask = (1 << ll) - 1;
+    const int ll = a.lanes_log2;
     for (int r_lo = 0; r_lo < kSubRanges;) {
         // the next group of ranges that fits in the staging area (the same
         // choice in every thread)
@@ -761,28 +798,54 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int 
         const int base0 = roff[r_lo], total = roff[r_hi] - base0;
         // one candidate per thread across the group's ranges, so that all of
         // its gathers are in flight at once; its range is the last one whose
-        // offset does not exceed it (empty ranges share their offset)
-        for (int e = threadIdx.x; e < total; e += blockDim.x) {
-            int lo = r_lo, hi = r_hi - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (roff[mid] - base0 <= e) lo = mid;
-                else hi = mid - 1;
+        // offset does not exceed it (empty ranges share their offset).  Only
+        // candidates within r_list of the centre sub-cell's box are kept (no
+        // centre atom can pair with the others), compacted in stencil order
+        // by the waves' ballots and counts.
+        int kept = 0;
+        for (int e0 = 0; e0 < total; e0 += (int)blockDim.x) {
+            const int e = e0 + (int)threadIdx.x;
+            bool keep = false;
+            uint4 rec = far_pad;
+            if (e < total) {
+                int lo = r_lo, hi = r_hi - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (roff[mid] - base0 <= e) lo = mid;
+                    else hi = mid - 1;
+                }
+                const int j = a.cell_atoms[cb][(size_t)rcell[lo] * cap + rstart[lo] + (e - (roff[lo] - base0))];
+                const uint4 q = a.fx[b][j];
+                rec = make_uint4(q.x, q.y, q.z, (unsigned)j);
+                keep = near_box(q);
             }
-            const int j = a.cell_atoms[cb][(size_t)rcell[lo] * cap + rstart[lo] + (e - (roff[lo] - base0))];
-            const uint4 q = a.fx[b][j];
-            cand[e] = make_uint4(q.x, q.y, q.z, (unsigned)j);
+            const unsigned long long m = __builtin_amdgcn_ballot_w64(keep);
+            if (lane == 0) wkept[wave] = __popcll(m);
+            __syncthreads();
+            int off = kept, all = kept;
+            for (int v = 0; v < kListWaves; ++v) {
+                off += v < wave ? wkept[v] : 0;
+                all += wkept[v];
+            }
+            if (keep) cand[off + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u))] = rec;
+            kept = all;
+            __syncthreads();
         }
-        // pad to whole wavefronts with entries that never match: slot -1 at
-        // the point opposite the centre cell's centre, at least L/2 - h/2 >= h
-        // >= r_list from every centre atom along each axis (3 or more cells
-        // per edge)
-        if (threadIdx.x < kWave) cand[total + threadIdx.x] = far_pad;
+        // pad to whole pairs of wavefronts with entries that never match: slot
+        // -1 at the point opposite the centre cell's centre, at least
+        // L/2 - h/2 >= h >= r_list from every centre atom along each axis (3 or
+        // more cells per edge)
+        if (threadIdx.x < 2 * kWave) cand[kept + threadIdx.x] = far_pad;
         __syncthreads();
-        if (total > 0) {
+        if (kept > 0) {
             for (int t = part * kListWaves + wave; t < mc; t += split * kListWaves) {
-                const uint4 qi = ctr[t];
-                const int wi = (int)qi.w;
+                // the centre atom is the same in every lane: scalar registers
+                const uint4 qv = ctr[t];
+                const unsigned qx = __builtin_amdgcn_readfirstlane(qv.x);
+                const unsigned qy = __builtin_amdgcn_readfirstlane(qv.y);
+                const unsigned qz = __builtin_amdgcn_readfirstlane(qv.z);
+                const int wi = __builtin_amdgcn_readfirstlane((int)qv.w);
                 const int mi = MOL ? a.wmol[wi] : -1;
                 // the working slots of this atom's molecule (its partners in it
                 // are left out), held in registers for the candidate loop
@@ -791,25 +854,28 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int 
                     const int c0 = B.a0 + 3 * mi;
                     sib0 = a.molw[c0]; sib1 = a.molw[c0 + 1]; sib2 = a.molw[c0 + 2];
                 }
-                int cnt = ccount[t];
-                int *dst = a.nbr + nbr_slot(a, wi, 0);
+                int cnt = __builtin_amdgcn_readfirstlane(ccount[t]);
+                char *dst = reinterpret_cast<char *>(a.nbr + nbr_slot(a, wi, 0));
+                // entry q of the blocked list sits q + (q >> ll) (64 - L) entries in; a
+                // list that overflows keeps rewriting its last entry (the build is
+                // flagged and the trial recomputed with larger lists)
+                const unsigned last = (unsigned)a.nbr_cap - 1u, gap = (unsigned)(kWave - (1 << ll));
                 // a cubic box compares squared distances in fixed-point units
                 // (three multiplies fewer per candidate)
                 auto scan = [&](auto cubic_tag) {
                     constexpr bool CUBIC = decltype(cubic_tag)::value;
-                    for (int base = 0; base < total; base += kWave) {
-                        const uint4 qj = cand[base + lane];
+                    auto test = [&](const uint4 &qj) {
                         const int j = (int)qj.w;
                         float d2;
                         if constexpr (CUBIC) {
-                            const float ux = (float)(int)(qi.x - qj.x);
-                            const float uy = (float)(int)(qi.y - qj.y);
-                            const float uz = (float)(int)(qi.z - qj.z);
+                            const float ux = (float)(int)(qx - qj.x);
+                            const float uy = (float)(int)(qy - qj.y);
+                            const float uz = (float)(int)(qz - qj.z);
                             d2 = ux * ux + uy * uy + uz * uz;
                         } else {
-                            const float dx = (float)(int)(qi.x - qj.x) * sx;
-                            const float dy = (float)(int)(qi.y - qj.y) * sy;
-                            const float dz = (float)(int)(qi.z - qj.z) * sz;
+                            const float dx = (float)(int)(qx - qj.x) * sx;
+                            const float dy = (float)(int)(qy - qj.y) * sy;
+                            const float dz = (float)(int)(qz - qj.z) * sz;
                             d2 = dx * dx + dy * dy + dz * dz;
                         }
                         // 0 < d2 < r_list^2 as one unsigned compare of the float bits
@@ -817,11 +883,17 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int 
                         bool acc = __float_as_uint(d2) - 1u < (CUBIC ? lim_u : lim);
                         if (MOL) acc &= (j != sib0) & (j != sib1) & (j != sib2);   // ions carry no molecule (-1)
                         const unsigned long long msk = __builtin_amdgcn_ballot_w64(acc);
-                        // accepted lanes below this one: the lane's slot after the running count
-                        const unsigned q = (unsigned)cnt + __builtin_amdgcn_mbcnt_hi(
-                                               (unsigned)(msk >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)msk, 0u));
-                        if (acc && q < (unsigned)a.nbr_cap) dst[((q >> ll) << 6) | (q & (unsigned)lmask)] = j;
+                        // the lane's entry: the running count plus the accepted lanes below it
+                        const unsigned q = min(__builtin_amdgcn_mbcnt_hi((unsigned)(msk >> 32),
+                                                   __builtin_amdgcn_mbcnt_lo((unsigned)msk, (unsigned)cnt)), last);
+                        if (acc) *reinterpret_cast<int *>(dst + ((q + __umul24(q >> ll, gap)) << 2)) = j;
                         cnt += __popcll(msk);
+                    };
+                    // two wavefronts of candidates per pass, both read before either is tested
+                    for (int base = 0; base < kept; base += 2 * kWave) {
+                        const uint4 qa = cand[base + lane], qb = cand[base + kWave + lane];
+                        test(qa);
+                        test(qb);
                     }
                 };
                 if (cubic) scan(BoolTag<true>{});
@@ -832,7 +904,6 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int 
         __syncthreads();
         r_lo = r_hi;
     }
-    (void)below;
     for (int t = threadIdx.x; t < mc; t += blockDim.x) {
         if ((t / kListWaves) % split != part) continue;
         const uint4 qi = ctr[t];
@@ -843,7 +914,7 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int 
         unflag_fast(a, b, wi, a.fx[b][wi].w);
         if (cnt > a.nbr_cap) { atomicOr(&c->err, kErrNbr); atomicMax(&c->max_nbr, cnt); }
     }
-    if (threadIdx.x == 0 && part == 0 && sc == 0) a.cell_cnt[cb ^ 1][cc] = 0;
+    if (threadIdx.x == 0 && part == 0 && un == 0) a.cell_cnt[cb ^ 1][cc] = 0;
 }
 
 // Cell form for cells too large to stage in LDS: L lanes per atom walk the

@@ -63,6 +63,7 @@ struct h4d_system {
     bool speculative = false;      // the boxes are replicas of one chain (one Philox key)
     bool vel_canonical = false;    // the state's momenta are the canonical ones (after a phase)
     int list_split = 0;            // list-build blocks per cell (0: automatic)
+    int list_units = 8;            // list-build centre units per cell: 8 sub-cells or 1 cell
     int partial_blocks = 0;
     TrialRec *h_rec = nullptr;  // per box (pinned)
     Ctl *h_ctl = nullptr;       // per box (pinned)
@@ -314,6 +315,12 @@ void initial_capacities(h4d_system *s, const int32_t *n_atoms) {
     }
     s->a.nbr_cap = round_up(nbr, kMaxLanes);
     s->a.cell_cap = s->cells ? std::min(cc, std::max(32, capmax)) : capmax;
+    // list-build blocks per cell: one per sub-cell when a sub-cell holds at
+    // least two atoms per wavefront on average, else one per cell
+    long long n_all = 0;
+    for (int b = 0; b < s->nbox; ++b) n_all += n_atoms[b];
+    const double per_cell = s->a.ncell_total > 0 ? (double)n_all / s->a.ncell_total : 0.0;
+    s->list_units = per_cell >= 8.0 * 2 * kListWaves ? 8 : 1;
 }
 
 size_t nbr_elems(const h4d_system *s) { return (size_t)s->a.slots * (size_t)s->a.nbr_cap; }
@@ -351,7 +358,7 @@ int slot_blocks(const h4d_system *s) { return s->a.slots / kBlock; }
 // never fewer than one z-layer of full cells.
 int list_cand_cap(const h4d_system *s) {
     const int cap = s->a.cell_cap;
-    const int fixed = (int)(kWave * sizeof(uint4) + (size_t)cap * (sizeof(uint4) + sizeof(int)));
+    const int fixed = (int)(2 * kWave * sizeof(uint4) + (size_t)cap * (sizeof(uint4) + sizeof(int)));
     constexpr int kStaticLds = 3072;  // the sub-cell range table (2,612 bytes) and slack
     return std::max(9 * cap, (40 * 1024 - kStaticLds - fixed) / (int)sizeof(uint4));
 }
@@ -359,17 +366,19 @@ int list_cand_cap(const h4d_system *s) {
 // LDS of the cell-form list build: the staged candidates and their padding,
 // the centre atoms and their running counts
 size_t list_cells_lds(const h4d_system *s) {
-    return (size_t)(list_cand_cap(s) + kWave) * sizeof(uint4) + (size_t)s->a.cell_cap * (sizeof(uint4) + sizeof(int));
+    return (size_t)(list_cand_cap(s) + 2 * kWave) * sizeof(uint4) +
+           (size_t)s->a.cell_cap * (sizeof(uint4) + sizeof(int));
 }
 
-// blocks per centre sub-cell of the cell-form list build: the autotuner's
-// choice, else enough blocks for two per CU (about 512 in all); at most 16
-// and at least two centre atoms of a full sub-cell (an eighth of a full
-// cell) per wavefront
+// blocks per centre unit (sub-cell or cell) of the cell-form list build:
+// the autotuner's choice, else enough blocks for two per CU (about 512 in
+// all); at most 16 and at least two centre atoms of a full unit per
+// wavefront
 int list_split(const h4d_system *s) {
-    const int most = std::max(1, std::min(16, s->a.cell_cap / (16 * kListWaves)));
+    const int unit_cap = s->a.cell_cap / s->list_units;
+    const int most = std::max(1, std::min(16, unit_cap / (2 * kListWaves)));
     if (s->list_split > 0) return std::min(s->list_split, most);
-    const int blocks = 8 * s->a.ncell_total;
+    const int blocks = s->list_units * s->a.ncell_total;
     const int want = (512 + blocks - 1) / blocks;
     return std::max(1, std::min(want, most));
 }
@@ -378,11 +387,12 @@ int list_split(const h4d_system *s) {
 void launch_list(h4d_system *s, int k, int b, int cb, hipStream_t st) {
     KArgs &a = s->a;
     if (s->cells && list_cells_lds(s) <= 56 * 1024) {
-        const int split = list_split(s), cand_cap = list_cand_cap(s);
-        const dim3 grid(a.ncell_total * 8 * split), block(kListWaves * kWave);
+        const int split = list_split(s), cand_cap = list_cand_cap(s), units = s->list_units;
+        const dim3 grid(a.ncell_total * units * split), block(kListWaves * kWave);
         const size_t lds = list_cells_lds(s);
-        if (a.G.water) hipLaunchKernelGGL(k_list_cells<true>, grid, block, lds, st, a, k, b, cb, split, cand_cap);
-        else hipLaunchKernelGGL(k_list_cells<false>, grid, block, lds, st, a, k, b, cb, split, cand_cap);
+        if (a.G.water)
+            hipLaunchKernelGGL(k_list_cells<true>, grid, block, lds, st, a, k, b, cb, split, cand_cap, units);
+        else hipLaunchKernelGGL(k_list_cells<false>, grid, block, lds, st, a, k, b, cb, split, cand_cap, units);
     }
     else if (s->cells)
         hipLaunchKernelGGL(k_list_lanes, dim3(a.step_blocks), dim3(kBlock), 0, st, a, k, b, cb);
