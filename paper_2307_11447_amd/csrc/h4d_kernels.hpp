@@ -665,17 +665,16 @@ __global__ __launch_bounds__(kBlock) void k_list_allpairs(KArgs a, int k, int b0
 // of a neighbouring cell lies at least one cell edge away from this
 // sub-cell: of the 27 x 8 neighbouring sub-cells only the 5 x 5 x 5 around
 // it can hold partners (125 / 216 of the 27 cells' volume), and only those
-// ranges are staged in LDS -- all at once when they fit in cand_cap entries,
-// else in consecutive groups of ranges (cand_cap >= 9 cell_cap, so every
-// range fits).  Of those, only the candidates within r_list of the centre
-// sub-cell's box are kept (about half of them: the box grown by r_list is
-// far smaller than the 5 x 5 x 5 block), as fixed-point coordinates +
-// working slot in stencil order (cell, then sub-cell, then index); each
-// wavefront takes its centre atoms in turn and tests 64 candidates per
-// ballot, two ballots per pass (the kept candidates are padded to whole
-// pairs of wavefronts with entries that never match), appending partners in
-// that order (a centre atom's running count stays in LDS across the
-// groups).  The lists are the same as without the box test.  MOL: rigid
+// ranges are read.  Of those, only the candidates within r_list of the
+// centre sub-cell's box are kept in LDS (about half of them: the box grown
+// by r_list is far smaller than the 5 x 5 x 5 block), as fixed-point
+// coordinates + working slot in stencil order (cell, then sub-cell, then
+// index), at most cand_cap at a time; each wavefront takes its centre atoms
+// in turn and tests 64 candidates per ballot, two ballots per pass (the
+// kept candidates are padded to whole pairs of wavefronts with entries that
+// never match), appending partners in that order (a centre atom's running
+// count stays in LDS when the kept candidates come in several batches).
+// The lists are the same as without the box test.  MOL: rigid
 // molecules present (pairs within a molecule are left out).  Dynamic LDS:
 // (cand_cap + 128 + cell_cap) * 16 + cell_cap * 4 bytes.  Also records the build positions, clears this cell's count in the
 // other buffer and the box's fast lists.
@@ -790,48 +789,16 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int 
     __shared__ int wkept[kListWaves];
     const unsigned lim_u = __float_as_uint(rl2u) - 1u;
     const int ll = a.lanes_log2;
-    for (int r_lo = 0; r_lo < kSubRanges;) {
-        // the next group of ranges that fits in the staging area (the same
-        // choice in every thread)
-        int r_hi = r_lo + 1;
-        while (r_hi < kSubRanges && roff[r_hi + 1] - roff[r_lo] <= cand_cap) ++r_hi;
-        const int base0 = roff[r_lo], total = roff[r_hi] - base0;
-        // one candidate per thread across the group's ranges, so that all of
-        // its gathers are in flight at once; its range is the last one whose
-        // offset does not exceed it (empty ranges share their offset).  Only
-        // candidates within r_list of the centre sub-cell's box are kept (no
-        // centre atom can pair with the others), compacted in stencil order
-        // by the waves' ballots and counts.
-        int kept = 0;
-        for (int e0 = 0; e0 < total; e0 += (int)blockDim.x) {
-            const int e = e0 + (int)threadIdx.x;
-            bool keep = false;
-            uint4 rec = far_pad;
-            if (e < total) {
-                int lo = r_lo, hi = r_hi - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (roff[mid] - base0 <= e) lo = mid;
-                    else hi = mid - 1;
-                }
-                const int j = a.cell_atoms[cb][(size_t)rcell[lo] * cap + rstart[lo] + (e - (roff[lo] - base0))];
-                const uint4 q = a.fx[b][j];
-                rec = make_uint4(q.x, q.y, q.z, (unsigned)j);
-                keep = near_box(q);
-            }
-            const unsigned long long m = __builtin_amdgcn_ballot_w64(keep);
-            if (lane == 0) wkept[wave] = __popcll(m);
-            __syncthreads();
-            int off = kept, all = kept;
-            for (int v = 0; v < kListWaves; ++v) {
-                off += v < wave ? wkept[v] : 0;
-                all += wkept[v];
-            }
-            if (keep) cand[off + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
-                                                               __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u))] = rec;
-            kept = all;
-            __syncthreads();
-        }
+    // The candidates within r_list of the centre unit's box (no centre atom
+    // can pair with the others), in stencil order (cell, sub-cell, index),
+    // are kept in LDS: staged in passes of one candidate per thread (its
+    // range is the last whose offset does not exceed its position; empty
+    // ranges share their offset), compacted by the waves' ballots and counts.
+    // When the next pass might not fit, the kept candidates are scanned for
+    // every centre atom first (a centre atom's running count stays in LDS).
+    const int total = roff[kSubRanges];
+    int kept = 0;
+    auto flush = [&]() {
         // pad to whole pairs of wavefronts with entries that never match: slot
         // -1 at the point opposite the centre cell's centre, at least
         // L/2 - h/2 >= h >= r_list from every centre atom along each axis (3 or
@@ -902,8 +869,39 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int 
             }
         }
         __syncthreads();
-        r_lo = r_hi;
+        kept = 0;
+    };
+    for (int e0 = 0; e0 < total; e0 += (int)blockDim.x) {
+        if (kept + min((int)blockDim.x, total - e0) > cand_cap) flush();
+        const int e = e0 + (int)threadIdx.x;
+        bool keep = false;
+        uint4 rec = far_pad;
+        if (e < total) {
+            int lo = 0, hi = kSubRanges - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (roff[mid] <= e) lo = mid;
+                else hi = mid - 1;
+            }
+            const int j = a.cell_atoms[cb][(size_t)rcell[lo] * cap + rstart[lo] + (e - roff[lo])];
+            const uint4 q = a.fx[b][j];
+            rec = make_uint4(q.x, q.y, q.z, (unsigned)j);
+            keep = near_box(q);
+        }
+        const unsigned long long m = __builtin_amdgcn_ballot_w64(keep);
+        if (lane == 0) wkept[wave] = __popcll(m);
+        __syncthreads();
+        int off = kept, all = kept;
+        for (int v = 0; v < kListWaves; ++v) {
+            off += v < wave ? wkept[v] : 0;
+            all += wkept[v];
+        }
+        if (keep) cand[off + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                           __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u))] = rec;
+        kept = all;
+        __syncthreads();
     }
+    flush();
     for (int t = threadIdx.x; t < mc; t += blockDim.x) {
         if ((t / kListWaves) % split != part) continue;
         const uint4 qi = ctr[t];

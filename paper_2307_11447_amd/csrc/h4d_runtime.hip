@@ -352,15 +352,15 @@ void set_lanes(h4d_system *s, int L) {
 
 int slot_blocks(const h4d_system *s) { return s->a.slots / kBlock; }
 
-// Staging entries of the cell-form list build: as many as a quarter of the
-// CU's 160 KB of LDS holds next to the kernel's static arrays (four blocks
-// per CU), enough for all 27 cells of typical occupancy in one round, and
-// never fewer than one z-layer of full cells.
+// Kept candidates of the cell-form list build held at once: as many as a
+// quarter of the CU's 160 KB of LDS holds next to the centre atoms and the
+// kernel's static arrays (four blocks per CU), and at least two passes of
+// one candidate per thread.
 int list_cand_cap(const h4d_system *s) {
     const int cap = s->a.cell_cap;
     const int fixed = (int)(2 * kWave * sizeof(uint4) + (size_t)cap * (sizeof(uint4) + sizeof(int)));
-    constexpr int kStaticLds = 3072;  // the sub-cell range table (2,612 bytes) and slack
-    return std::max(9 * cap, (40 * 1024 - kStaticLds - fixed) / (int)sizeof(uint4));
+    constexpr int kStaticLds = 3072;  // the sub-cell range table (2,640 bytes) and slack
+    return std::max(2 * kListWaves * kWave, (40 * 1024 - kStaticLds - fixed) / (int)sizeof(uint4));
 }
 
 // LDS of the cell-form list build: the staged candidates and their padding,
