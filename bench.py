@@ -628,12 +628,19 @@ def leg_lj32k(args, h4d, W, torch, steps, warmup, timing_trials):
     w0 = W.config_lj_32k()
     w0.params.update(capacity=w0.n + 1024)
     w = relaxed(h4d, w0, 10, 200)
-    net, scale, cap, over, info, cal, bmu = learned_study(
-        args, h4d, torch, w, "lj32k", args.lj_pilot, args.lj_pilot // 2, args.select_trials, args.lj_ab_trials,
-        args.candidates, beta_mu=args.lj_beta_mu)
+    if args.lj_pilot > 0:
+        net, scale, cap, over, info, cal, bmu = learned_study(
+            args, h4d, torch, w, "lj32k", args.lj_pilot, args.lj_pilot // 2, args.select_trials, args.lj_ab_trials,
+            args.candidates, beta_mu=args.lj_beta_mu)
+    else:   # no pilot, no network: both arms uniform (a profiling run of the timed configuration)
+        if args.lj_beta_mu is None:
+            raise SystemExit("bench.py: --lj-pilot 0 needs --lj-beta-mu")
+        net, scale, cap, info, cal, bmu = None, 0.0, 10.0, None, None, args.lj_beta_mu
+        over = {"lanes_per_atom": args.lanes} if args.lanes else {}
     arms, tm = timed_arms(args, h4d, torch, w, bmu, over, net, scale, cap, args.candidates, steps, warmup,
                           timing_trials)
-    net.close()
+    if net is not None:
+        net.close()
     bias = None
     if args.lj_bias_trials > 0:
         # flyers near contact (x_b = 1 sigma, alpha_b = 2 / sigma^2); V_ex edge 1.2 sigma

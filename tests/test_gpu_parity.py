@@ -215,41 +215,19 @@ def test_autotuned_handle_matches_oracle():
     g.close()
 
 
-def sync_oracle_from_gpu(o, st):
-    n = st["n"]
-    o.x[:n] = st["x"]; o.type[:n] = st["type"]; o.mol[:n] = st["mol"]; o.tag[:n] = st["tag"]
-    o.flying[:] = 0
-    o.s.n = n
-    o.s.nsalt = st["nsalt"]
-
-
 def test_fp32_trials_lockstep():
-    say("case trials lj2000 fp32 lockstep")
+    """Ten 200-step FP32 trials of a 2,000-ion box at the library's default
+    lane count, each from the GPU's state against the FP64 oracle, within the
+    FP32 bound |beta d(dH)| <= 1e-6 (N + |beta dH|) on dH and W_prot, with
+    identical decisions outside it (the same check as tests/test_gpu_fp32.py
+    makes at 4 lanes)."""
+    from test_gpu_fp32 import compare_lockstep, lockstep
+    say("case trials lj2000 fp32 lockstep, default lanes")
     w = W.lj_electrolyte(2000, 0.3, 21, n_steps=200, precision="fp32")
     w.params.update(beta_mu=6.0)
     g = h4d.System.from_workload(w)
-    o = O.OracleSystem.from_workload(w, cap=w.n + 200)
-    worst = 0.0
-    for t in range(10):
-        st = g.state()
-        sync_oracle_from_gpu(o, st)
-        rg = g.trial()
-        ro = o.trial(t)
-        assert rg["move"] == ro["move"]
-        if ro["flags"]:
-            continue
-        err = abs(rg["dH"] - ro["dH"]) / max(1.0, abs(ro["dH"]))
-        worst = max(worst, err)
-        margin = abs(ro["ln_u"] - ro["ln_ratio"])
-        if margin > 1e-2:
-            assert rg["accepted"] == ro["accepted"], (t, rg, ro)
-        assert abs(rg["W_prot"] - ro["W_prot"]) <= 1e-3 * max(1.0, abs(ro["W_prot"]))
-        if ro["move"] > 0:   # switched on at the shared start x_0
-            assert rg["E_switch"] == pytest.approx(ro["E_switch"], rel=1e-9, abs=1e-9)
-        else:                # switched off at the end of the FP32 trajectory
-            assert abs(rg["E_switch"] - ro["E_switch"]) <= 1e-3 * max(1.0, abs(ro["E_switch"]))
-    say(f"   worst relative dH difference {worst:.3e}")
-    assert worst < 1e-3
+    pairs = lockstep(g, w.params, (0,) * 10)
+    compare_lockstep(pairs, 1.0, "lj2000/default lanes")
     g.close()
 
 
