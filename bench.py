@@ -627,7 +627,7 @@ def leg_lj32k(args, h4d, W, torch, steps, warmup, timing_trials):
     behind them."""
     w0 = W.config_lj_32k()
     w0.params.update(capacity=w0.n + 1024)
-    w = relaxed(h4d, w0, 10, 200)
+    w = relaxed(h4d, w0, args.lj_relax_phases, 200) if args.lj_relax_phases > 0 else w0
     if args.lj_pilot > 0:
         net, scale, cap, over, info, cal, bmu = learned_study(
             args, h4d, torch, w, "lj32k", args.lj_pilot, args.lj_pilot // 2, args.select_trials, args.lj_ab_trials,
@@ -661,8 +661,8 @@ def leg_lj32k(args, h4d, W, torch, steps, warmup, timing_trials):
     out["config"] = {"workload": "lj32k: 32,000 LJ ions, density 0.3, 200-step NEMD pair insert/delete, FP32 pair "
                                  "arithmetic / FP64 state; value: the uniform proposal, one chain on speculative "
                                  "replicas; learned_arm: the same chain with the learned multiple-try proposal",
-                     "replicas": args.replicas, "beta_mu": bmu, "start": "lattice start relaxed by 10 equilibrium "
-                     "phases of 200 steps", "candidates": args.candidates}
+                     "replicas": args.replicas, "beta_mu": bmu, "start": f"lattice start relaxed by "
+                     f"{args.lj_relax_phases} equilibrium phases of 200 steps", "candidates": args.candidates}
     note(f"lj32k: {steps} trials per arm, {out['value']:.3g} atom-steps/s, frac {out['roofline']['frac']:.3f}")
     return out, w
 
@@ -724,6 +724,8 @@ def main():
     ap.add_argument("--lj-beta-mu", type=float, default=None,
                     help="lj32k: beta mu (default: Bennett's acceptance ratio over its pilot moves)")
     ap.add_argument("--lj-pilot", type=int, default=1000, help="lj32k: pilot insertions (half as many deletions)")
+    ap.add_argument("--lj-relax-phases", type=int, default=10,
+                    help="lj32k: equilibrium phases of 200 steps that relax the lattice start")
     ap.add_argument("--lj-bias-trials", type=int, default=150,
                     help="lj32k: forced insertions and deletions per arm of the bimodal-bias comparison (0: none)")
     ap.add_argument("--lj-ab-trials", type=int, default=300,
