@@ -204,6 +204,30 @@ def test_fp32_batch_lockstep_per_box(lanes):
     bat.close()
 
 
+def test_fp32_full_size_batch_lockstep_sampled_boxes():
+    """The full 256-box batch (2.2 M ions, N in [1000, 16000], density
+    0.1-0.4, N_f ~ U{100..400}) at the 4 lanes per atom the bench tunes to:
+    one round, and for a sample of boxes (the smallest, the largest and
+    three others) the oracle's whole trial from that box's start state
+    within the FP32 bound, with the same move, sites, N_f and decision."""
+    say("case fp32 full-size batch (256 boxes), one round, 5 boxes through the oracle")
+    ws = W.config_batched()
+    for w in ws:
+        w.params.update(lanes_per_atom=4)
+    sizes = [w.n for w in ws]
+    sample = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 0, 77, 254})
+    bat = h4d.Batch.from_workloads(ws)
+    assert bat.timing()["lanes"] == 4
+    states = {b: bat.box_state(b) for b in sample}
+    recs = bat.run(1)
+    jobs = [oracle_pool.job(ws[b].params, states[b], recs[b][0]["trial"]) for b in sample]
+    for b, ro in zip(sample, oracle_pool.run(jobs)):
+        say(f"   box {b}: {sizes[b]} ions, N_f {recs[b][0]['n_steps']}")
+        compare_lockstep([(recs[b][0], ro)], 1.0, f"full batch box {b}")
+    assert all(100 <= r[0]["n_steps"] <= 400 for r in recs)
+    bat.close()
+
+
 def test_fp32_work_distribution_against_fp64():
     """Forced insertions and deletions on one fixed state (beta mu = -+1000:
     never accepted, so the state does not change).  Paired: GPU FP32 and
