@@ -58,6 +58,7 @@ TRAFFIC_FILES = {
     "batched": os.path.join(ROOT, "profiles", "k_step_batched256_traffic.txt"),
 }
 CANDIDATES = 4096
+INSERT_SHIFTS = (0, 20, 40, 60, 80, 100, 120)   # beta mu above the operating point, insertion curves
 
 
 def note(msg):
@@ -290,6 +291,17 @@ def out_of_fold(h4d, X, y, epochs, folds=5):
     return oof
 
 
+def finite_json(x):
+    """x with every non-finite float replaced by None (strict JSON)."""
+    if isinstance(x, dict):
+        return {k: finite_json(v) for k, v in x.items()}
+    if isinstance(x, (list, tuple)):
+        return [finite_json(v) for v in x]
+    if isinstance(x, float) and not math.isfinite(x):
+        return None
+    return x
+
+
 def log_mean_exp(v):
     """ln of the mean of exp(v) (entries of -inf count as zeros)."""
     import numpy as np
@@ -311,7 +323,8 @@ def proposal_ab(sys_, torch, h4d, arms, beta_mu, n_each, block=50):
     scale, cap[, (x_b, alpha_b, v_ex_edge)]) (k = 0: the uniform proposal;
     the optional last entry sets the bimodal bias and early rejection)."""
     import numpy as np
-    out = {name: {"ins": [], "del": [], "s": 0.0, "n": 0, "instant": 0} for name in arms}
+    out = {name: {"ins": [], "del": [], "ins_ln_r": [], "del_ln_r": [], "s": 0.0, "n": 0, "instant": 0}
+           for name in arms}
     done = 0
     while done < n_each:
         nb = min(block, n_each - done)
@@ -336,6 +349,7 @@ def proposal_ab(sys_, torch, h4d, arms, beta_mu, n_each, block=50):
                     r = arr[q]
                     ok = not (r.flags & 0x3) and math.isfinite(r.ln_ratio)
                     out[name][key].append(min(0.0, r.ln_ratio + shift) if ok else -math.inf)
+                    out[name][key + "_ln_r"].append(r.ln_ratio + shift if ok else -math.inf)
                     out[name]["instant"] += int(bool(r.flags & 0x10))
         done += nb
     sys_.set_proposal(None, 0)
@@ -356,7 +370,14 @@ def proposal_ab(sys_, torch, h4d, arms, beta_mu, n_each, block=50):
                      "ln_acc_insert_median": float(np.median(fi)) if len(fi) else None,
                      "ln_acc_delete_median": float(np.median(fd)) if len(fd) else None,
                      "insertions": len(o["ins"]), "deletions": len(o["del"]),
-                     "instant_fraction": o["instant"] / max(1, o["n"])}
+                     "instant_fraction": o["instant"] / max(1, o["n"]),
+                     # insertion acceptance as beta mu rises above the operating
+                     # point (each ln R moves by the shift): where the uniform
+                     # arm accepts insertions at all, the arms compare on many
+                     # values instead of a few extreme ones
+                     "log10_p_insert_at_beta_mu_plus": {
+                         str(sh): log_mean_exp(np.minimum(0.0, np.array(o["ins_ln_r"]) + sh)) / ln10
+                         for sh in INSERT_SHIFTS}}
     names = list(arms)
     for other in names[1:]:
         g, ci = ab_log_gain(out[names[0]], out[other])
@@ -410,7 +431,7 @@ def learned_study(args, h4d, torch, w, label, n_ins, n_del, n_select, n_ab, cand
     from paper_2307_11447_amd import analysis
     beta = 1.0 / w.params["kT"]
     one = h4d.System.from_workload(w)
-    tuned = one.autotune(2) if args.autotune else None
+    tuned = one.autotune(args.autotune_trials) if args.autotune else None
     if tuned:
         note(f"{label}: autotune: {tuned[0]} lanes per atom, rebuild every {tuned[1]} steps")
     # the tuned lane width; the rebuild interval stays automatic (it adapts to
@@ -522,7 +543,13 @@ def timed_arms(args, h4d, torch, w, beta_mu, over, net, scale, cap, candidates, 
 
 def learned_vs_plain(arms, info):
     la, pa = arms["learned"], arms["plain"]
+    fs = (info or {}).get("fixed_state") or {}
+    curve = None
+    if "plain" in fs and "learned" in fs:
+        lp, ll = fs["plain"]["log10_p_insert_at_beta_mu_plus"], fs["learned"]["log10_p_insert_at_beta_mu_plus"]
+        curve = {sh: (ll[sh] - lp[sh] if math.isfinite(ll[sh]) and math.isfinite(lp[sh]) else None) for sh in lp}
     return {
+        "fixed_state_insertion_log10_gain_at_beta_mu_plus": curve,
         "accepted_exchanges_per_s_ratio": (la["accepted_exchanges_per_s"] / pa["accepted_exchanges_per_s"]
                                            if pa["accepted"] > 0 else None),
         "expected_exchanges_per_s_ratio": (la["expected_exchanges_per_s"] / pa["expected_exchanges_per_s"]
@@ -756,6 +783,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="nacl: leave out the lj32k and batched keys")
     ap.add_argument("--rebuild-every", type=int, default=0, help="list rebuild interval (0: library default)")
     ap.add_argument("--lanes", type=int, default=0, help="lanes per atom (0: library default)")
+    ap.add_argument("--autotune-trials", type=int, default=4,
+                    help="trials the autotuner times per choice of the single-chain legs")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="keep the library's lanes per atom and automatic rebuild interval")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -826,7 +855,7 @@ def main():
     line.update(extras)
     if base is not None:
         line["cpu_baseline"] = base
-    print(json.dumps(line), flush=True)
+    print(json.dumps(finite_json(line)), flush=True)
 
 
 if __name__ == "__main__":

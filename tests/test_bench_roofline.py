@@ -63,3 +63,11 @@ def test_log_space_acceptance_and_gain():
     assert g == pytest.approx(1.0) and ci[0] == pytest.approx(1.0) and ci[1] == pytest.approx(1.0)
     none = {"ins": [-math.inf] * 4, "del": [-math.inf] * 4, "n": 8, "s": 1.0}
     assert bench.ab_log_gain(none, l) == (None, None)
+
+
+def test_bench_line_is_strict_json():
+    import json
+    import math
+    line = {"a": -math.inf, "b": [1.0, math.nan, {"c": math.inf}], "d": "x", "e": 2}
+    out = json.dumps(bench.finite_json(line), allow_nan=False)
+    assert json.loads(out) == {"a": None, "b": [1.0, None, {"c": None}], "d": "x", "e": 2}
