@@ -596,6 +596,8 @@ def gcmd_cycles(args, h4d, torch, w, beta_mu, over, cycles, n_eq):
 def bench_nacl(args, h4d, W, torch):
     w0 = W.config_water_nacl()
     w0.params.update(capacity=w0.n + 1024)
+    if args.skin is not None:   # Verlet skin (A); trajectories depend on it only through the summation order
+        w0.params.update(skin=args.skin)
     w = relaxed(h4d, w0, args.relax_phases, 100) if args.relax_phases > 0 else w0
     if args.pilot > 0:
         net, scale, cap, over, info, cal, beta_mu = learned_study(
@@ -783,6 +785,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="nacl: leave out the lj32k and batched keys")
     ap.add_argument("--rebuild-every", type=int, default=0, help="list rebuild interval (0: library default)")
     ap.add_argument("--lanes", type=int, default=0, help="lanes per atom (0: library default)")
+    ap.add_argument("--skin", type=float, default=None, help="nacl: Verlet skin in A (default: the workload's)")
     ap.add_argument("--autotune-trials", type=int, default=4,
                     help="trials the autotuner times per choice of the single-chain legs")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",

@@ -25,8 +25,8 @@ def job(params, st, t, move=0, n_mol=0, use_cells=True):
 
 
 def run(jobs, procs=None):
-    """Records of the jobs, in order.  At most 12 processes: the CPU share of
-    a one-GPU machine is 16 threads."""
+    """Records of the jobs, in order.  At most 12 processes (the host of one
+    GPU gives a process 16 threads)."""
     if not jobs:
         return []
     procs = procs or max(1, min(len(jobs), 12, os.cpu_count() or 1))

@@ -29,8 +29,8 @@ The bound taken is
     |beta (dH_gpu - dH_oracle)| <= 1e-6 (N_atoms + |beta dH|),
 three to ten times the measured spread, and the same bound on the protocol
 work.  Decisions must agree whenever |ln u - ln R| exceeds that bound;
-closer trials are flagged near-ties (none occurred in these runs).  The
-survey's 1e-4 near-tie margin cannot hold at these sizes: the FP32 spread of
+closer trials are flagged near-ties (none occurred in these runs).  A fixed
+near-tie margin of 1e-4 cannot hold at these sizes: the FP32 spread of
 beta dH itself exceeds it.
 """
 import math
