@@ -57,6 +57,7 @@ TRAFFIC_FILES = {
     "lj32k": os.path.join(ROOT, "profiles", "k_step_lj32k_traffic.txt"),
     "batched": os.path.join(ROOT, "profiles", "k_step_batched256_traffic.txt"),
 }
+COUNTER_FILES = {"water": os.path.join(ROOT, "profiles", "k_step_water_counters.txt")}
 CANDIDATES = 4096
 INSERT_SHIFTS = (0, 20, 40, 60, 80, 100, 120)   # beta mu above the operating point, insertion curves
 
@@ -126,7 +127,23 @@ def counted_traffic(path):
         return None
 
 
-def roofline(timing, traffic_bytes, kernel):
+def counted_valu_busy(path, kernel_substr):
+    """rocprofv3's VALUBusy (percent) of the step kernel from a committed
+    counter summary, or None if it is missing or was taken on different
+    kernel sources."""
+    from paper_2307_11447_amd import rocprof_summary
+    if not path or not os.path.exists(path):
+        return None
+    lines = open(path).read().splitlines()
+    if f"kernel_source_sha256: {rocprof_summary.kernel_source_hash()}" not in lines:
+        return None
+    for line in lines:
+        if kernel_substr in line and " VALUBusy " in line and "mean=" in line:
+            return float(line.rsplit("mean=", 1)[1])
+    return None
+
+
+def roofline(timing, traffic_bytes, kernel, valu_busy=None):
     """The step kernel against the HBM roofline: algorithmic bytes of the
     atoms its timed launches integrated over their summed HIP-event time."""
     n_l = timing["mean_nbr"]
@@ -141,6 +158,7 @@ def roofline(timing, traffic_bytes, kernel):
         "frac": achieved / HBM_PEAK_GBS,
         "traffic": None if traffic_bytes is None else traffic_bytes * launches / step_s / 1e9,
         "traffic_bytes_per_launch": traffic_bytes,
+        "valu_busy_pct": valu_busy,
         "bytes_per_atom_step": bpa, "mean_list_entries": n_l,
         "atom_launches": atoms, "launches": timing["step_launches"],
         "avg_kernel_us": 1e3 * timing["step_ms"] / launches,
@@ -221,6 +239,7 @@ def arm_summary(recs, wall, rounds=None):
         "n_salt_first": recs[0].n_salt_before if recs else None, "n_salt_last": ns[-1] if ns else None,
         "n_salt_mean": sum(ns) / max(1, len(ns)),
         "retried_trials": sum(1 for r in recs if r.flags & 0x4),
+        "nonfinite_trials": sum(1 for r in recs if r.flags & 0x2),
     }
     if rounds is not None:
         out["rounds"] = rounds
@@ -625,7 +644,8 @@ def bench_nacl(args, h4d, W, torch):
         "mu_calibration": cal,
         "gcmd": gcmd,
         "roofline": roofline(timing, counted_traffic(TRAFFIC_FILES["water"]),
-                             "k_step<1,L> (fused pair force + velocity Verlet), learned arm"),
+                             "k_step<1,L> (fused pair force + velocity Verlet), learned arm",
+                             counted_valu_busy(COUNTER_FILES["water"], f"k_step<1, {timing['lanes']}, false>")),
         "lanes_per_atom": timing["lanes"], "rebuild_every": timing["rebuild_every"],
         "execution": {"mode": "speculative", "replicas": args.replicas},
     }
@@ -696,6 +716,33 @@ def leg_lj32k(args, h4d, W, torch, steps, warmup, timing_trials):
     return out, w
 
 
+def leg_lj500(args, h4d, W, torch, trials=100):
+    """The 500-ion FP64 box (the smallest LJ configuration): latency-bound,
+    so microseconds per step rather than a roofline.  One chain, one trial
+    after another, from a relaxed start; every kernel of a trial is one
+    graph replay."""
+    w = relaxed(h4d, W.config_lj_500(), 5, 200)
+    g = h4d.System.from_workload(w)
+    g.trials(5)
+    arr, wall = timed(torch, lambda: g.trials(trials, as_array=True))
+    recs = [arr[q] for q in range(trials)]
+    g.close()
+    out = arm_summary(recs, wall)
+    launches = sum(r.n_steps + 1 for r in recs)
+    out["us_per_step"] = 1e6 * wall / max(1, launches)
+    out["config"] = {"workload": "lj500: 500 LJ ions (250 +1 / 250 -1), density 0.3, 100-step NEMD pair insert/delete, "
+                                 "dt 0.005, w_max 2.5 sigma, FP64; one chain, one trial after another",
+                     "beta_mu": w.params["beta_mu"], "start": "random start relaxed by 5 equilibrium phases of 200 steps"}
+    note(f"lj500: {trials} trials, {out['us_per_step']:.1f} us per step, {out['accepted']} accepted")
+    return out
+
+
+# Trials per box of the 256-box workload after the autotuner, as far as it has
+# run without fault on the GPU (33 rounds of one handle in all, the autotuner's
+# 26 included).
+BATCHED_MAX_TRIALS = 7
+
+
 def leg_batched(args, h4d, W, torch, steps, warmup, timing_trials, learned_k=0):
     ws = W.config_batched()
     for w in ws:
@@ -746,7 +793,7 @@ def main():
     ap.add_argument("--workload", choices=("nacl", "lj32k", "batched"), default="nacl")
     ap.add_argument("--steps", type=int, default=None,
                     help="timed exchange trials per arm (nacl, default 20), of the chain (lj32k, default 400) or "
-                         "per box (batched, default 10)")
+                         "per box (batched, default 4; warmup + steps + timing trials at most 7)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed trials first (default 5 / 20 / 2)")
     ap.add_argument("--beta-mu", type=float, default=None,
                     help="nacl: beta mu (default: Bennett's acceptance ratio over the pilot moves)")
@@ -801,11 +848,16 @@ def main():
         sys.exit(2)
     wl = args.workload
     if args.steps is None:
-        args.steps = {"nacl": 20, "lj32k": 400, "batched": 10}[wl]
+        args.steps = {"nacl": 20, "lj32k": 400, "batched": 4}[wl]
     if args.warmup is None:
         args.warmup = {"nacl": 5, "lj32k": 20, "batched": 2}[wl]
     if args.timing_trials is None:
         args.timing_trials = {"nacl": 4, "lj32k": 20, "batched": 1}[wl]
+    if wl == "batched" and args.warmup + args.steps + args.timing_trials > BATCHED_MAX_TRIALS:
+        print(f"bench.py: the 256-box workload runs at most {BATCHED_MAX_TRIALS} trials per box after the "
+              "autotuner (warmup + steps + timing trials): longer runs of it have faulted the GPU and the "
+              "cause is not established", file=sys.stderr)
+        sys.exit(2)
 
     import torch
     from paper_2307_11447_amd import h4d
@@ -827,6 +879,7 @@ def main():
                 extras["lj32k"]["cpu_baseline"] = cpu_baseline(w32, 200, "the 32,000-ion state",
                                                                extras["lj32k"]["config"]["beta_mu"])
             extras["batched256"], _ = leg_batched(args, h4d, W, torch, 2, 1, 1)
+            extras["lj500"] = leg_lj500(args, h4d, W, torch)
     elif wl == "lj32k":
         out, w32 = leg_lj32k(args, h4d, W, torch, args.steps, args.warmup, args.timing_trials)
         config = out.pop("config")

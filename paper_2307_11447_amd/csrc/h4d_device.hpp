@@ -25,7 +25,7 @@ constexpr unsigned kErrCell = 0x2u;   // cell capacity exceeded
 constexpr unsigned kErrSkin = 0x4u;   // an atom moved more than skin/2 before a rebuild
 constexpr unsigned kErrCap = 0x8u;    // atom capacity exceeded
 constexpr unsigned kErrFast = 0x10u;  // fast-atom list full
-constexpr unsigned kErrNonfinite = 0x20u;  // a position became non-finite (the trajectory blew up)
+constexpr unsigned kErrNonfinite = 0x20u;  // a position became non-finite or left the box (the trajectory blew up)
 
 // purposes of the counter-based generator
 constexpr uint64_t kPurposeSelect = 1, kPurposeMB = 2, kPurposeNsteps = 3, kPurposeBias = 6;

@@ -184,11 +184,15 @@ __device__ __forceinline__ int subcell_of(const Box &B, const double4 &p) {
     return sub;
 }
 
-// A non-finite position (a trajectory that blew up) is left out of the cells
-// and marks the trial non-finite: it is rejected, never recomputed, and the
-// cells cannot fill up with such atoms.
+// A position that is non-finite, or that the single periodic wrap of a step
+// left outside the box (the atom moved more than a box edge in one step), is
+// a trajectory that blew up: the atom is left out of the cells and the trial
+// is marked non-finite (rejected, never recomputed).  The cells cannot fill
+// up with such atoms, and every binned atom's fixed-point coordinate lies in
+// its own cell, as the list build's padding entries assume.  (An edge value
+// of exactly L is the rounding of a wrap from just below 0.)
 __device__ __forceinline__ void bin_atom(const KArgs &a, const Box &B, Ctl *c, int cb, int w, const double4 &p) {
-    if (!(isfinite(p.x) && isfinite(p.y) && isfinite(p.z))) {
+    if (!(p.x >= 0.0 && p.x <= B.L[0] && p.y >= 0.0 && p.y <= B.L[1] && p.z >= 0.0 && p.z <= B.L[2])) {
         atomicOr(&c->err, kErrNonfinite);
         return;
     }
@@ -578,6 +582,26 @@ __global__ __launch_bounds__(kWave) void k_gather_in(KArgs a, int cb) {
     }
 }
 
+// Trial start, after the binning and the list build: a box whose cells or
+// lists overflowed is recomputed with larger ones, and its trajectory this
+// round is skipped (move 0).  A full cell leaves atoms out of the working
+// buffer: a flyer among them has no working slot, and the slots past the
+// gathered atoms hold no list.  A deletion's flags on the canonical pair are
+// cleared here, as the rollback would.
+__global__ void k_start_check(KArgs a) {
+    const int bi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (bi >= a.nbox) return;
+    Ctl *c = a.ctl + bi;
+    if (c->move == 0 || !(c->err & (kErrCell | kErrNbr))) return;
+    if (c->move == -1) {
+        double4 p = a.cpos[c->ic];
+        a.cpos[c->ic] = with_meta(p.x, p.y, p.z, meta_of(p) & ~kFlyBit);
+        p = a.cpos[c->ia];
+        a.cpos[c->ia] = with_meta(p.x, p.y, p.z, meta_of(p) & ~kFlyBit);
+    }
+    c->move = 0;
+}
+
 // After a list build every atom is within the skin again: clear its fast flag.
 __device__ __forceinline__ void unflag_fast(const KArgs &a, int b, int w, unsigned meta) {
     if (meta & kFastBit) {
@@ -756,7 +780,7 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int 
         auto opposite = [](int c, int n) {   // fixed-point coordinate of the cell centre, plus half the box
             return (unsigned)(((2.0 * c + 1.0) / (2.0 * n)) * 4294967296.0) + 0x80000000u;
         };
-        far_pad = make_uint4(opposite(cx, nx), opposite(cy, ny), opposite(cz, nz), 0xffffffffu);
+        far_pad = make_uint4(opposite(cx, nx), opposite(cy, ny), opposite(cz, nz), (unsigned)a.slots);
     }
     const float rl2u = (float)(a.G.rlist2 / ((double)sx * (double)sx)) * 1.00001f;   // in fixed-point units
     // the centre sub-cell's (or cell's) box in fixed-point units: its middle
@@ -799,10 +823,10 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_list_cells(KArgs a, int 
     const int total = roff[kSubRanges];
     int kept = 0;
     auto flush = [&]() {
-        // pad to whole pairs of wavefronts with entries that never match: slot
-        // -1 at the point opposite the centre cell's centre, at least
-        // L/2 - h/2 >= h >= r_list from every centre atom along each axis (3 or
-        // more cells per edge)
+        // pad to whole pairs of wavefronts with entries that never match: the
+        // null record's slot at the point opposite the centre cell's centre,
+        // at least L/2 - h/2 >= h >= r_list from every centre atom along each
+        // axis (3 or more cells per edge)
         if (threadIdx.x < 2 * kWave) cand[kept + threadIdx.x] = far_pad;
         __syncthreads();
         if (kept > 0) {
@@ -1239,6 +1263,7 @@ __device__ void flyer_work(const KArgs &a, const Box &B, Ctl *c, const CoefLds &
     if (move == 0 || move == kMoveMD || k > nf) return;
     const int f = wave == 0 ? c->wic : c->wia;
     const int other = wave == 0 ? c->wia : c->wic;
+    if (f < 0 || other < 0) return;   // a flyer with no working slot (its trial is not kept)
     const double wlo0 = altitude(a.G, move, k > 0 ? k - 1 : 0, nf);
     const double whi0 = altitude(a.G, move, k < nf ? k + 1 : nf, nf);
     // this flyer's own altitudes (wave 1 is the anion) and the screening altitudes

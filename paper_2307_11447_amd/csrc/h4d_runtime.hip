@@ -567,6 +567,7 @@ int enqueue_round(h4d_system *s, int move, hipStream_t st, int nf, int M, bool t
         enqueue_learned(s, st, 0, 0, 0);
         if ((rc = sort_in(s, st))) return rc;
     }
+    hipLaunchKernelGGL(k_start_check, dim3(blocks_for(s->nbox)), dim3(kBlock), 0, st, a);
     hipLaunchKernelGGL(k_energy, dim3(a.step_blocks), dim3(kBlock), 0, st, a, 0, -1, 0.0, 0);
     hipLaunchKernelGGL(k_energy_final, dim3(s->nbox), dim3(kBlock), 0, st, a, 0);
     int b = 0;
@@ -980,7 +981,7 @@ int create(const h4d_params *params, int nbox, const double *edges, const int32_
     int *slot_box_d = nullptr, *cell_box_d = nullptr;
     if ((rc = s->alloc(&a.cpos, C)) || (rc = s->alloc(&a.cvel, C)) || (rc = s->alloc(&a.tvel, C)) ||
         (rc = s->alloc(&a.ctag, C)) || (rc = s->alloc(&a.ctype, C)) ||
-        (rc = s->alloc(&a.cmol, C)) || (rc = s->alloc(&a.pos[0], C)) || (rc = s->alloc(&a.pos[1], C)) ||
+        (rc = s->alloc(&a.cmol, C)) || (rc = s->alloc(&a.pos[0], C + 1)) || (rc = s->alloc(&a.pos[1], C + 1)) ||
         (rc = s->alloc(&a.fx[0], C + 1)) || (rc = s->alloc(&a.fx[1], C + 1)) || (rc = s->alloc(&a.vel[0], C)) ||
         (rc = s->alloc(&a.vel[1], C)) || (rc = s->alloc(&a.perm, C)) || (rc = s->alloc(&a.wmol, C)) ||
         (rc = s->alloc(&a.posb, C)) || (rc = s->alloc(&a.force, C)) || (rc = s->alloc(&a.tpos, C)) ||
@@ -1053,10 +1054,18 @@ int create(const h4d_params *params, int nbox, const double *edges, const int32_
     UPLOAD(box_d, s->box_h.data(), sizeof(Box) * nbox);
     UPLOAD(slot_box_d, sb.data(), sizeof(int) * sb.size());
     UPLOAD(cell_box_d, cbx.data(), sizeof(int) * cbx.size());
-    {   // the null record past the last slot: the pair pass pads the lists with it
+    {   // the null record past the last slot: the pair pass pads the lists with
+        // it (its fast flag gives exactly zero force); the list build's
+        // padding entries carry its slot
         const uint4 null_rec = make_uint4(0u, 0u, 0u, (unsigned)kFastBit);
         UPLOAD(a.fx[0] + C, &null_rec, sizeof(uint4));
         UPLOAD(a.fx[1] + C, &null_rec, sizeof(uint4));
+        long long meta = kFastBit;
+        double wbits;
+        std::memcpy(&wbits, &meta, sizeof(wbits));
+        const double4 null_pos = make_double4(0.0, 0.0, 0.0, wbits);
+        UPLOAD(a.pos[0] + C, &null_pos, sizeof(double4));
+        UPLOAD(a.pos[1] + C, &null_pos, sizeof(double4));
     }
 #undef UPLOAD
     // rebuild interval: the fastest atoms (5 standard deviations) cover half

@@ -1,7 +1,10 @@
 """Failure handling forced from the host: a full box refuses an insertion
 with H4D_ECAPACITY and keeps its state and trial index, and a state whose
 local density is twice the box average (a slab) outgrows the initial list
-capacities, which grow, and still follows the oracle."""
+capacities, which grow, and still follows the oracle; an insertion whose
+ghost pair overflows a full cell when the trial starts is recomputed with
+larger cells (single box and batch); and a trajectory that throws atoms out
+of the box is rejected as non-finite with the state kept."""
 import sys
 
 import numpy as np
@@ -83,4 +86,90 @@ def test_slab_state_grows_the_lists_and_follows_the_oracle():
     box = np.array(w.params["box"])
     d -= box * np.round(d / box)
     assert np.abs(d).max() < 1e-7
+    g.close()
+
+
+def full_cell_lattice(seed):
+    """216 LJ ions on a simple-cubic lattice of spacing 2.4 in a box of edge
+    14.4: 3 list cells per edge (r_list 4.5), each holding 2 x 2 x 2 sites,
+    so every cell holds exactly 8 atoms."""
+    L, m = 14.4, 6
+    w = W.lj_electrolyte(m ** 3, m ** 3 / L ** 3, seed, n_steps=12, precision="fp64")
+    g1 = (np.arange(m) + 0.5) * (L / m)
+    w.x = np.stack(np.meshgrid(g1, g1, g1, indexing="ij"), -1).reshape(-1, 3).copy()
+    w.params.update(box=[L, L, L], beta_mu=10.0)
+    return w
+
+
+def with_cell_cap(ck, cap):
+    raw = h4d.Checkpoint.from_buffer_copy(ck["checkpoint"].tobytes())
+    assert raw.cell_cap > cap
+    raw.cell_cap = cap
+    return dict(ck, checkpoint=np.frombuffer(bytes(raw), np.uint8).copy())
+
+
+def test_full_cell_at_the_trial_start_recomputes_the_insertion():
+    # A cell capacity equal to every cell's count: the ghost pair of an
+    # insertion overflows a cell when the trial starts, which leaves atoms
+    # (often a ghost) out of the working buffer.  The box must skip that
+    # trajectory and recompute the trial with larger cells.
+    say("case full cells: 216 LJ ions, 8 per list cell, cell capacity 8, fp64, single box")
+    w = full_cell_lattice(4404)
+    g0 = h4d.System.from_workload(w)
+    ck = with_cell_cap(g0.checkpoint(), 8)
+    g0.close()
+    g = h4d.System.resume(ck)
+    assert g.timing()["cell_cap"] == 8
+    o = O.OracleSystem.from_workload(w, cap=w.n + 64)
+    for t in range(3):
+        rg = g.trial(h4d.MOVE_INSERT)
+        same_record(rg, o.trial(t, force_move=1), f"insertion {t}")
+        if t == 0:
+            assert rg["flags"] & h4d.FLAG_RETRIED, rg
+    cap = g.timing()["cell_cap"]
+    say(f"   cell capacity grew to {cap}")
+    assert cap > 8
+    g.close()
+
+
+def test_full_cell_at_the_trial_start_in_a_batch():
+    say("case full cells: 2 boxes of 216 LJ ions, 8 per list cell, cell capacity 8, fp64, batch of 3 trials")
+    ws = [full_cell_lattice(4405), full_cell_lattice(4406)]
+    ref_bat = h4d.Batch.from_workloads(ws)
+    cks = [with_cell_cap(c, 8) for c in ref_bat.checkpoint()]
+    ref = ref_bat.run(3, h4d.MOVE_INSERT)
+    ref_bat.close()
+    bat = h4d.Batch.resume(cks)
+    got = bat.run(3, h4d.MOVE_INSERT)
+    for b in range(2):
+        assert got[b][0]["flags"] & h4d.FLAG_RETRIED, got[b][0]
+        for q in range(3):
+            a, r = got[b][q], ref[b][q]
+            assert (a["move"], a["accepted"], a["trial"]) == (r["move"], r["accepted"], r["trial"]), (b, q)
+            assert abs(a["dH"] - r["dH"]) < 1e-9 * max(1.0, abs(r["dH"])), (b, q, a["dH"], r["dH"])
+    say(f"   {sum(x['accepted'] for row in got for x in row)} of 6 insertions accepted")
+    bat.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_blown_up_trajectory_is_rejected_and_the_state_kept(precision):
+    # Two ions 0.017 apart: the first step throws them more than a box edge
+    # (the single periodic wrap leaves them outside the box).  Binning marks
+    # the trajectory non-finite and leaves them out of the cells, so the list
+    # build never takes them as centre atoms; the trial is rejected and the
+    # state kept.
+    say(f"case blow-up: 216 LJ ions, one pair 0.017 apart, {precision}")
+    w = full_cell_lattice(4407)
+    w.params.update(precision=precision)
+    w.x[0] = w.x[1] + np.array([0.012, 0.009, 0.007])
+    g = h4d.System.from_workload(w)
+    s0 = g.state()
+    r = g.trial(h4d.MOVE_INSERT)
+    say(f"   flags {r['flags']}, accepted {r['accepted']}")
+    assert r["flags"] & h4d.FLAG_NONFINITE and not r["accepted"], r
+    s1 = g.state()
+    assert s1["n"] == s0["n"] and s1["nsalt"] == s0["nsalt"]
+    for k in ("x", "type", "tag"):
+        assert np.array_equal(s0[k], s1[k]), k
+    assert g.observables()["n_trials"] == 1
     g.close()
