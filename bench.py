@@ -52,12 +52,18 @@ sys.path.insert(0, ROOT)
 METRIC = "accepted salt-pair exchanges/s + NEMD atom-steps/s (1 GPU), learned vs plain"
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # published vector FP32 rate (packed FP32 counted)
+# committed counter summaries of the step kernel, one per workload and lanes
+# per atom (the autotuner's choice decides which instantiation the bench times)
 TRAFFIC_FILES = {
-    "water": os.path.join(ROOT, "profiles", "k_step_water_traffic.txt"),
-    "lj32k": os.path.join(ROOT, "profiles", "k_step_lj32k_traffic.txt"),
-    "batched": os.path.join(ROOT, "profiles", "k_step_batched256_traffic.txt"),
+    ("water", 16): os.path.join(ROOT, "profiles", "k_step_water_traffic.txt"),
+    ("water", 8): os.path.join(ROOT, "profiles", "k_step_water_l8_traffic.txt"),
+    ("lj32k", 8): os.path.join(ROOT, "profiles", "k_step_lj32k_traffic.txt"),
+    ("batched", 4): os.path.join(ROOT, "profiles", "k_step_batched256_traffic.txt"),
 }
-COUNTER_FILES = {"water": os.path.join(ROOT, "profiles", "k_step_water_counters.txt")}
+COUNTER_FILES = {
+    ("water", 16): os.path.join(ROOT, "profiles", "k_step_water_counters.txt"),
+    ("water", 8): os.path.join(ROOT, "profiles", "k_step_water_l8_counters.txt"),
+}
 CANDIDATES = 4096
 INSERT_SHIFTS = (0, 20, 40, 60, 80, 100, 120)   # beta mu above the operating point, insertion curves
 
@@ -108,10 +114,12 @@ def step_flop_per_atom(mean_nbr):
     return 46.0 * mean_nbr + 18.0
 
 
-def counted_traffic(path):
-    """HBM bytes per step launch from a committed rocprofv3 counter summary,
-    or None if it is missing or was taken on different kernel sources."""
+def counted_traffic(workload, lanes):
+    """HBM bytes per step launch from the committed rocprofv3 counter summary
+    of this workload's step kernel at these lanes per atom, or None if there
+    is none or it was taken on different kernel sources."""
     from paper_2307_11447_amd import rocprof_summary
+    path = TRAFFIC_FILES.get((workload, lanes))
     if not path or not os.path.exists(path):
         return None
     kv = {}
@@ -119,7 +127,8 @@ def counted_traffic(path):
         if ":" in line:
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip().split()[0] if v.strip() else ""
-    if kv.get("kernel_source_sha256") != rocprof_summary.kernel_source_hash():
+    if kv.get("kernel_source_sha256") != rocprof_summary.kernel_source_hash() or \
+            kv.get("lanes_per_atom") != str(lanes):
         return None
     try:
         return float(kv["traffic_bytes_per_launch"])
@@ -127,11 +136,13 @@ def counted_traffic(path):
         return None
 
 
-def counted_valu_busy(path, kernel_substr):
-    """rocprofv3's VALUBusy (percent) of the step kernel from a committed
-    counter summary, or None if it is missing or was taken on different
-    kernel sources."""
+def counted_valu_busy(workload, lanes):
+    """rocprofv3's VALUBusy (percent) of the step kernel at these lanes per
+    atom from the committed counter summary, or None if there is none or it
+    was taken on different kernel sources."""
     from paper_2307_11447_amd import rocprof_summary
+    path = COUNTER_FILES.get((workload, lanes))
+    kernel_substr = f"k_step<1, {lanes}, false>"
     if not path or not os.path.exists(path):
         return None
     lines = open(path).read().splitlines()
@@ -643,9 +654,9 @@ def bench_nacl(args, h4d, W, torch):
         "learned": info,
         "mu_calibration": cal,
         "gcmd": gcmd,
-        "roofline": roofline(timing, counted_traffic(TRAFFIC_FILES["water"]),
+        "roofline": roofline(timing, counted_traffic("water", timing["lanes"]),
                              "k_step<1,L> (fused pair force + velocity Verlet), learned arm",
-                             counted_valu_busy(COUNTER_FILES["water"], f"k_step<1, {timing['lanes']}, false>")),
+                             counted_valu_busy("water", timing["lanes"])),
         "lanes_per_atom": timing["lanes"], "rebuild_every": timing["rebuild_every"],
         "execution": {"mode": "speculative", "replicas": args.replicas},
     }
@@ -704,7 +715,7 @@ def leg_lj32k(args, h4d, W, torch, steps, warmup, timing_trials):
     out["learned"] = info
     out["mu_calibration"] = cal
     out["bimodal_bias"] = bias
-    out["roofline"] = roofline(tm, counted_traffic(TRAFFIC_FILES["lj32k"]),
+    out["roofline"] = roofline(tm, counted_traffic("lj32k", tm["lanes"]),
                                "k_step<1,L> (fused pair force + velocity Verlet)")
     out["lanes_per_atom"], out["rebuild_every"] = tm["lanes"], tm["rebuild_every"]
     out["config"] = {"workload": "lj32k: 32,000 LJ ions, density 0.3, 200-step NEMD pair insert/delete, FP32 pair "
@@ -773,7 +784,7 @@ def leg_batched(args, h4d, W, torch, steps, warmup, timing_trials, learned_k=0):
     tm = bat.timing()
     bat.close()
     out["value"] = out.pop("atom_steps_per_s")
-    out["roofline"] = roofline(tm, counted_traffic(TRAFFIC_FILES["batched"]),
+    out["roofline"] = roofline(tm, counted_traffic("batched", tm["lanes"]),
                                "k_step<1,L> (fused pair force + velocity Verlet)")
     out["lanes_per_atom"], out["rebuild_every"] = tm["lanes"], tm["rebuild_every"]
     out["autotune"] = tuned

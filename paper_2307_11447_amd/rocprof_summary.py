@@ -2,6 +2,8 @@
 
     python3 -m paper_2307_11447_amd.rocprof_summary stats RUN_results.db
         per-kernel calls, total, average, min and max duration
+    python3 -m paper_2307_11447_amd.rocprof_summary shapes RUN_results.db KERNEL
+        the same per launch shape (grid size) of the kernels matching KERNEL
     python3 -m paper_2307_11447_amd.rocprof_summary counters RUN_results.db ...
         per-kernel mean of every collected hardware counter
     python3 -m paper_2307_11447_amd.rocprof_summary traffic KERNEL FETCH.db WRITE.db COPYF.db COPYW.db MIB
@@ -43,6 +45,31 @@ def stats(path: str) -> str:
     span = list(db.execute("select min(start), max(end) from kernels"))[0]
     if span[0] is not None:
         out.append(f"kernel span {(span[1] - span[0]) / 1e6:.3f} ms, kernels busy {tot / 1e6:.3f} ms")
+    return "\n".join(out)
+
+
+def _grid_column(db) -> str:
+    cols = [r[1] for r in db.execute("pragma table_info(kernels)")]
+    for c in ("grid_size", "grid_x", "grid_size_x"):
+        if c in cols:
+            return c
+    grid = [c for c in cols if "grid" in c.lower()]
+    if not grid:
+        raise SystemExit(f"no grid column among {cols}")
+    return grid[0]
+
+
+def shapes(path: str, kernel_substr: str) -> str:
+    """Per launch shape (grid size) of the kernels whose name contains
+    kernel_substr: calls, total, average, min and max duration."""
+    db = sqlite3.connect(path)
+    g = _grid_column(db)
+    rows = list(db.execute(
+        f"select name, {g}, count(*), sum(duration), avg(duration), min(duration), max(duration) "
+        f"from kernels where instr(name, ?) > 0 group by name, {g} order by sum(duration) desc", (kernel_substr,)))
+    out = [f"{'kernel':48s} {g:>12s} {'calls':>8s} {'total_ms':>10s} {'avg_us':>9s} {'min_us':>8s} {'max_us':>8s}"]
+    for name, grid, n, s, a, mn, mx in rows:
+        out.append(f"{name[:48]:48s} {grid!s:>12s} {n:8d} {s / 1e6:10.3f} {a / 1e3:9.2f} {mn / 1e3:8.2f} {mx / 1e3:8.2f}")
     return "\n".join(out)
 
 
@@ -102,6 +129,8 @@ def main(argv):
     mode = argv[0]
     if mode == "stats":
         print(stats(argv[1]))
+    elif mode == "shapes" and len(argv) == 3:
+        print(shapes(argv[1], argv[2]))
     elif mode == "counters":
         print(counters(argv[1:]))
     elif mode == "traffic" and len(argv) == 7:
