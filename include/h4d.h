@@ -444,6 +444,10 @@ typedef struct h4d_timing {
     double atom_launches;  /* atoms the timed step launches integrated: over
                               every trajectory timed, (N_f + 1) launches times
                               the atoms of its state                           */
+    int64_t nonfinite;     /* trials rejected as non-finite (a trajectory that
+                              blew up) since the handle was created, every box
+                              and the autotuner's trials included              */
+    int64_t retries_total; /* trials recomputed since the handle was created   */
 } h4d_timing;
 
 int32_t h4d_set_timing(h4d_system *sys, int32_t on);

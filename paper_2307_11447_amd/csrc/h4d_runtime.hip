@@ -75,6 +75,7 @@ struct h4d_system {
     double atom_launches = 0.0;   // atoms integrated, summed over the timed step launches
     int trial_rebuilds = 0;
     int64_t retries = 0;
+    int64_t retries_total = 0, nonfinite = 0;   // over the handle's life
     int trial_M = 1;            // rebuild interval of the round being run
     int cl = 0;                 // cell buffer of the current list (the next binning uses cl ^ 1)
     // captured round graphs, keyed by launch shape; dropped when buffers move
@@ -691,6 +692,7 @@ int handle_retries(h4d_system *s, int &rc) {
     }
     rc = clear_errors(s);
     s->retries += n;
+    s->retries_total += n;
     return n;
 }
 
@@ -701,6 +703,7 @@ void account(h4d_system *s, int b, const h4d_trial &r) {
     s->n_host[b] = c->n;
     s->nsalt_host[b] = c->nsalt;
     st.n_trials += 1;
+    if (r.flags & kFlagNonfinite) s->nonfinite += 1;
     if (r.move > 0) { st.n_ins += 1; st.n_ins_acc += r.accepted; }
     else { st.n_del += 1; st.n_del_acc += r.accepted; }
     st.N_sum += (double)c->nsalt;
@@ -1584,6 +1587,8 @@ int32_t h4d_get_timing(h4d_system *s, h4d_timing *out) {
     out->cell_cap = s->a.cell_cap;
     out->retries = s->retries;
     out->atom_launches = s->atom_launches;
+    out->nonfinite = s->nonfinite;
+    out->retries_total = s->retries_total;
     return H4D_OK;
 }
 
