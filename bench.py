@@ -805,7 +805,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", choices=("nacl", "lj32k", "batched"), default="nacl")
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed exchange trials per arm (nacl, default 20), of the chain (lj32k, default 400) or "
+                    help="timed exchange trials per arm (nacl, default 24), of the chain (lj32k, default 400) or "
                          "per box (batched, default 4; warmup + steps + timing trials at most 7)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed trials first (default 5 / 20 / 2)")
     ap.add_argument("--beta-mu", type=float, default=None,
@@ -861,7 +861,9 @@ def main():
         sys.exit(2)
     wl = args.workload
     if args.steps is None:
-        args.steps = {"nacl": 20, "lj32k": 400, "batched": 4}[wl]
+        # nacl: three whole rounds of the default 8 speculative replicas (a
+        # partial last round would run replicas past the timed trials)
+        args.steps = {"nacl": 24, "lj32k": 400, "batched": 4}[wl]
     if args.warmup is None:
         args.warmup = {"nacl": 5, "lj32k": 20, "batched": 2}[wl]
     if args.timing_trials is None:
