@@ -789,6 +789,7 @@ def leg_batched(args, h4d, W, torch, steps, warmup, timing_trials, learned_k=0):
     out["lanes_per_atom"], out["rebuild_every"] = tm["lanes"], tm["rebuild_every"]
     # over the handle's whole life, the autotuner's trials included
     out["handle_nonfinite_trials"], out["handle_retried_trials"] = tm["nonfinite"], tm["retries_total"]
+    out["list_capacity"] = {"entries_per_atom": tm["nbr_cap"], "atoms_per_cell": tm["cell_cap"]}
     out["autotune"] = tuned
     out["config"] = {"workload": "batched256: 256 LJ-electrolyte boxes, N even in [1000, 16000] (2,220,126 ions), "
                                  "density U[0.1, 0.4], N_f ~ U{100..400} per trial, FP32 pair arithmetic / FP64 "
