@@ -52,18 +52,42 @@ sys.path.insert(0, ROOT)
 METRIC = "accepted salt-pair exchanges/s + NEMD atom-steps/s (1 GPU), learned vs plain"
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # published vector FP32 rate (packed FP32 counted)
-# committed counter summaries of the step kernel, one per workload and lanes
-# per atom (the autotuner's choice decides which instantiation the bench times)
+# committed counter summaries of the step kernel, one per workload, lanes per
+# atom and list-load kind (the autotuner's choices decide which instantiation
+# the bench times; each file names the ones it was taken with)
 TRAFFIC_FILES = {
-    ("water", 16): os.path.join(ROOT, "profiles", "k_step_water_traffic.txt"),
-    ("water", 8): os.path.join(ROOT, "profiles", "k_step_water_l8_traffic.txt"),
-    ("lj32k", 8): os.path.join(ROOT, "profiles", "k_step_lj32k_traffic.txt"),
-    ("batched", 4): os.path.join(ROOT, "profiles", "k_step_batched256_traffic.txt"),
+    "water": [os.path.join(ROOT, "profiles", "k_step_water_traffic.txt"),
+              os.path.join(ROOT, "profiles", "k_step_water_l8_traffic.txt")],
+    "lj32k": [os.path.join(ROOT, "profiles", "k_step_lj32k_traffic.txt")],
+    "batched": [os.path.join(ROOT, "profiles", "k_step_batched256_traffic.txt")],
 }
 COUNTER_FILES = {
-    ("water", 16): os.path.join(ROOT, "profiles", "k_step_water_counters.txt"),
-    ("water", 8): os.path.join(ROOT, "profiles", "k_step_water_l8_counters.txt"),
+    "water": [os.path.join(ROOT, "profiles", "k_step_water_counters.txt"),
+              os.path.join(ROOT, "profiles", "k_step_water_l8_counters.txt")],
 }
+
+
+def _summary_fields(path):
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip().split()[0] if v.strip() else ""
+    return kv
+
+
+def _matching_summary(files, lanes, nt):
+    """The committed summary taken on the current kernel sources with these
+    lanes per atom and list-load kind, or None."""
+    from paper_2307_11447_amd import rocprof_summary
+    for path in files:
+        if not os.path.exists(path):
+            continue
+        kv = _summary_fields(path)
+        if (kv.get("kernel_source_sha256") == rocprof_summary.kernel_source_hash() and
+                kv.get("lanes_per_atom") == str(lanes) and kv.get("nontemporal_lists") == str(nt)):
+            return path
+    return None
 CANDIDATES = 4096
 INSERT_SHIFTS = (0, 20, 40, 60, 80, 100, 120)   # beta mu above the operating point, insertion curves
 
@@ -114,41 +138,28 @@ def step_flop_per_atom(mean_nbr):
     return 46.0 * mean_nbr + 18.0
 
 
-def counted_traffic(workload, lanes):
+def counted_traffic(workload, timing):
     """HBM bytes per step launch from the committed rocprofv3 counter summary
-    of this workload's step kernel at these lanes per atom, or None if there
-    is none or it was taken on different kernel sources."""
-    from paper_2307_11447_amd import rocprof_summary
-    path = TRAFFIC_FILES.get((workload, lanes))
-    if not path or not os.path.exists(path):
-        return None
-    kv = {}
-    for line in open(path):
-        if ":" in line:
-            k, v = line.split(":", 1)
-            kv[k.strip()] = v.strip().split()[0] if v.strip() else ""
-    if kv.get("kernel_source_sha256") != rocprof_summary.kernel_source_hash() or \
-            kv.get("lanes_per_atom") != str(lanes):
+    of this workload's step kernel in the instantiation the timing describes
+    (lanes per atom, list-load kind), or None if there is none or it was
+    taken on different kernel sources."""
+    path = _matching_summary(TRAFFIC_FILES.get(workload, []), timing["lanes"], timing["nt_lists"])
+    if path is None:
         return None
     try:
-        return float(kv["traffic_bytes_per_launch"])
+        return float(_summary_fields(path)["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
 
 
-def counted_valu_busy(workload, lanes):
-    """rocprofv3's VALUBusy (percent) of the step kernel at these lanes per
-    atom from the committed counter summary, or None if there is none or it
-    was taken on different kernel sources."""
-    from paper_2307_11447_amd import rocprof_summary
-    path = COUNTER_FILES.get((workload, lanes))
-    kernel_substr = f"k_step<1, {lanes}, false>"
-    if not path or not os.path.exists(path):
+def counted_valu_busy(workload, timing):
+    """rocprofv3's VALUBusy (percent) of the step kernel in the instantiation
+    the timing describes, from the committed counter summary, or None."""
+    path = _matching_summary(COUNTER_FILES.get(workload, []), timing["lanes"], timing["nt_lists"])
+    if path is None:
         return None
-    lines = open(path).read().splitlines()
-    if f"kernel_source_sha256: {rocprof_summary.kernel_source_hash()}" not in lines:
-        return None
-    for line in lines:
+    kernel_substr = f"k_step<1, {timing['lanes']}, false, {'true' if timing['nt_lists'] else 'false'}>"
+    for line in open(path):
         if kernel_substr in line and " VALUBusy " in line and "mean=" in line:
             return float(line.rsplit("mean=", 1)[1])
     return None
@@ -654,10 +665,11 @@ def bench_nacl(args, h4d, W, torch):
         "learned": info,
         "mu_calibration": cal,
         "gcmd": gcmd,
-        "roofline": roofline(timing, counted_traffic("water", timing["lanes"]),
+        "roofline": roofline(timing, counted_traffic("water", timing),
                              "k_step<1,L> (fused pair force + velocity Verlet), learned arm",
-                             counted_valu_busy("water", timing["lanes"])),
+                             counted_valu_busy("water", timing)),
         "lanes_per_atom": timing["lanes"], "rebuild_every": timing["rebuild_every"],
+        "nontemporal_lists": timing["nt_lists"],
         "execution": {"mode": "speculative", "replicas": args.replicas},
     }
     config = {
@@ -715,9 +727,10 @@ def leg_lj32k(args, h4d, W, torch, steps, warmup, timing_trials):
     out["learned"] = info
     out["mu_calibration"] = cal
     out["bimodal_bias"] = bias
-    out["roofline"] = roofline(tm, counted_traffic("lj32k", tm["lanes"]),
+    out["roofline"] = roofline(tm, counted_traffic("lj32k", tm),
                                "k_step<1,L> (fused pair force + velocity Verlet)")
     out["lanes_per_atom"], out["rebuild_every"] = tm["lanes"], tm["rebuild_every"]
+    out["nontemporal_lists"] = tm["nt_lists"]
     out["config"] = {"workload": "lj32k: 32,000 LJ ions, density 0.3, 200-step NEMD pair insert/delete, FP32 pair "
                                  "arithmetic / FP64 state; value: the uniform proposal, one chain on speculative "
                                  "replicas; learned_arm: the same chain with the learned multiple-try proposal",
@@ -784,9 +797,10 @@ def leg_batched(args, h4d, W, torch, steps, warmup, timing_trials, learned_k=0):
     tm = bat.timing()
     bat.close()
     out["value"] = out.pop("atom_steps_per_s")
-    out["roofline"] = roofline(tm, counted_traffic("batched", tm["lanes"]),
+    out["roofline"] = roofline(tm, counted_traffic("batched", tm),
                                "k_step<1,L> (fused pair force + velocity Verlet)")
     out["lanes_per_atom"], out["rebuild_every"] = tm["lanes"], tm["rebuild_every"]
+    out["nontemporal_lists"] = tm["nt_lists"]
     # over the handle's whole life, the autotuner's trials included
     out["handle_nonfinite_trials"], out["handle_retried_trials"] = tm["nonfinite"], tm["retries_total"]
     out["list_capacity"] = {"entries_per_atom": tm["nbr_cap"], "atoms_per_cell": tm["cell_cap"]}

@@ -448,6 +448,12 @@ typedef struct h4d_timing {
                               blew up) since the handle was created, every box
                               and the autotuner's trials included              */
     int64_t retries_total; /* trials recomputed since the handle was created   */
+    int32_t nt_lists;      /* 1: the FP32 pair pass loads its list indices
+                              non-temporally, as it does when a step's list
+                              entries and atom state (estimated from the
+                              densities at set-up) exceed the 256 MB Infinity
+                              Cache (the results are the same either way)     */
+    int32_t reserved;
 } h4d_timing;
 
 int32_t h4d_set_timing(h4d_system *sys, int32_t on);

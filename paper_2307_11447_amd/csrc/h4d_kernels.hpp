@@ -1031,7 +1031,10 @@ __device__ __forceinline__ void build_force_coef(const KArgs &a, ForceCoef *fcf,
     }
 }
 
-template <int PREC, int L, bool SP>
+// NT: the list indices are loaded non-temporally (streamed past the caches),
+// for lists too large to stay in the Infinity Cache between steps, where
+// they would only evict the gathered records.
+template <int PREC, int L, bool SP, bool NT = false>
 __device__ __forceinline__ void group_force(const KArgs &a, const Box &B, const Ctl *c, const CoefLds &cf,
                                             const ForceCoef *fcf, int b, int cl, int w, int s, const double4 &pi,
                                             int mi, double wv, double gscr, const int *flist, int nfast, double &fx,
@@ -1076,9 +1079,13 @@ __device__ __forceinline__ void group_force(const KArgs &a, const Box &B, const 
             const int *base = a.nbr + ((size_t)(w / A) * (size_t)(a.nbr_cap / L)) * kWave + (size_t)(w % A) * L + s;
             const int nq = nn > s ? (nn - s + L - 1) / L : 0;
             const int null_slot = a.slots;
+            auto index_at = [&](int q) {
+                if constexpr (NT) return __builtin_nontemporal_load(base + (size_t)q * kWave);
+                else return base[(size_t)q * kWave];
+            };
             int jn[NB];
 #pragma unroll
-            for (int u = 0; u < NB; ++u) jn[u] = (u < nq) ? base[(size_t)u * kWave] : null_slot;
+            for (int u = 0; u < NB; ++u) jn[u] = (u < nq) ? index_at(u) : null_slot;
             for (int k = 0; k < nq; k += NB) {
                 int j[NB];
                 uint4 q[NB];
@@ -1088,7 +1095,7 @@ __device__ __forceinline__ void group_force(const KArgs &a, const Box &B, const 
                 for (int u = 0; u < NB; ++u) q[u] = F[j[u]];
 #pragma unroll
                 for (int u = 0; u < NB; ++u)
-                    jn[u] = (k + NB + u < nq) ? base[(size_t)(k + NB + u) * kWave] : null_slot;
+                    jn[u] = (k + NB + u < nq) ? index_at(k + NB + u) : null_slot;
 #pragma unroll
                 for (int u = 0; u < NB; ++u) {
                     const float ux = (float)(int)(qi.x - q[u].x);
@@ -1352,7 +1359,7 @@ __device__ void flyer_work(const KArgs &a, const Box &B, Ctl *c, const CoefLds &
 // Blocks [0, step_blocks) cover the atom slots; block step_blocks + b
 // evaluates the flying work of box b.
 // ==========================================================================
-template <int PREC, int L, bool SP>
+template <int PREC, int L, bool SP, bool NT>
 __global__ __launch_bounds__(kBlock) void k_step(KArgs a, int k, int b, int bin, int cl) {
     const bool flyer_block = (int)blockIdx.x >= a.step_blocks;
     const int slot0 = (int)blockIdx.x * (kBlock / L);
@@ -1402,7 +1409,7 @@ __global__ __launch_bounds__(kBlock) void k_step(KArgs a, int k, int b, int bin,
     const int ti = mi & kTypeMask;
     double fx = 0.0, fy = 0.0, fz = 0.0;
     if (act && !fly)
-        group_force<PREC, L, SP>(a, B, c, cf, fcf, b, cl, wc, s, pi, mi, wv, gscr, flist, nfast, fx, fy, fz);
+        group_force<PREC, L, SP, NT>(a, B, c, cf, fcf, b, cl, wc, s, pi, mi, wv, gscr, flist, nfast, fx, fy, fz);
     if (PREC == 1) fast_atoms_wave<SP>(a, B, fcf, b, cl, act && !fly && s == 0 && (mi & kFastBit), wc, lane, wv, gscr,
                                        fx, fy, fz);
     if (!act || s != 0) return;

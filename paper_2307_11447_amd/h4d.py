@@ -90,7 +90,8 @@ class Timing(C.Structure):
     _fields_ = [("step_launches", C.c_int64), ("retries", C.c_int64), ("step_ms", C.c_double),
                 ("mean_nbr", C.c_double), ("rebuild_every", C.c_int32), ("nbr_cap", C.c_int32),
                 ("lanes", C.c_int32), ("cell_cap", C.c_int32), ("atom_launches", C.c_double),
-                ("nonfinite", C.c_int64), ("retries_total", C.c_int64)]
+                ("nonfinite", C.c_int64), ("retries_total", C.c_int64), ("nt_lists", C.c_int32),
+                ("reserved", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
