@@ -1658,7 +1658,7 @@ int32_t h4d_autotune(h4d_system *s, int32_t trials, int32_t *lanes_out, int32_t 
     s->drop_graphs();
     // blocks per cell of the list build (cell form only)
     if (s->cells && list_cells_lds(s) <= 56 * 1024) {
-        const int most = std::max(1, std::min(16, s->a.cell_cap / (2 * kListWaves)));
+        const int most = std::max(1, std::min(16, s->a.cell_cap / s->list_units / (2 * kListWaves)));
         int best_split = list_split(s);
         double best_st = 0.0;
         bool first = true;
