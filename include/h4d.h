@@ -460,6 +460,16 @@ int32_t h4d_set_timing(h4d_system *sys, int32_t on);
 int32_t h4d_get_timing(h4d_system *sys, h4d_timing *out);
 
 /*
+ * How the FP32 pair pass (Sec. II A: the force on every atom at each step of
+ * the trajectory) loads its list indices: mode -1 by the rule of
+ * h4d_timing.nt_lists (non-temporal when a step's list entries and atom
+ * state exceed the 256 MB Infinity Cache; the default), 0 cached, 1
+ * non-temporal.  Records and states are bitwise the same in every mode; only
+ * the time differs.  H4D_EINVAL for a null handle or another mode.
+ */
+int32_t h4d_set_list_loads(h4d_system *sys, int32_t mode);
+
+/*
  * Autotuner of the launch shape: runs `trials` trials (per box) with each
  * lanes-per-atom choice (4, 8, 16) of the list traversals and keeps the one
  * with the least wall time per atom-step; then the number of blocks that

@@ -65,6 +65,7 @@ struct h4d_system {
     int list_split = 0;            // list-build blocks per cell (0: automatic)
     int list_units = 8;            // list-build centre units per cell: 8 sub-cells or 1 cell
     double step_bytes_est = 0.0;   // a step's list entries and own state, from the densities at set-up
+    int list_loads = -1;           // list-index loads of the FP32 pair pass: -1 by size, 0 cached, 1 non-temporal
     int partial_blocks = 0;
     TrialRec *h_rec = nullptr;  // per box (pinned)
     Ctl *h_ctl = nullptr;       // per box (pinned)
@@ -335,7 +336,10 @@ size_t nbr_elems(const h4d_system *s) { return (size_t)s->a.slots * (size_t)s->a
 // from it step after step, data that does not only evicts the gathered
 // records on its way through (measured: the water box 3 % faster, the 256
 // boxes 1 %, the 32k box 12 % slower with them).
-bool nt_lists(const h4d_system *s) { return s->step_bytes_est > 256.0 * 1024 * 1024; }
+bool nt_lists(const h4d_system *s) {
+    if (s->list_loads >= 0) return s->list_loads != 0;
+    return s->step_bytes_est > 256.0 * 1024 * 1024;
+}
 
 int alloc_lists(h4d_system *s) {
     int rc;
@@ -1568,6 +1572,13 @@ int32_t h4d_sample_observables(h4d_system *s, h4d_observables *out) { return box
 
 int32_t h4d_box_observables(h4d_system *s, int32_t box, h4d_observables *out) {
     return box_observables(s, box, out);
+}
+
+int32_t h4d_set_list_loads(h4d_system *s, int32_t mode) {
+    if (!s) return fail(H4D_EINVAL, "null handle");
+    if (mode < -1 || mode > 1) return fail(H4D_EINVAL, "list-load mode must be -1, 0 or 1");
+    s->list_loads = mode;   // the round graphs are keyed by the kind in use
+    return H4D_OK;
 }
 
 int32_t h4d_set_timing(h4d_system *s, int32_t on) {

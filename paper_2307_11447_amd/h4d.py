@@ -132,6 +132,7 @@ def lib() -> C.CDLL:
                                     C.POINTER(C.c_double)]
         L.h4d_destroy.argtypes = [vp]
         L.h4d_set_timing.argtypes = [vp, C.c_int32]
+        L.h4d_set_list_loads.argtypes = [vp, C.c_int32]
         L.h4d_stream_copy.argtypes = [C.c_int64, C.c_int32, C.POINTER(C.c_double)]
         L.h4d_get_timing.argtypes = [vp, C.POINTER(Timing)]
         L.h4d_init_batch.argtypes = [C.POINTER(Params), C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32),
@@ -171,7 +172,7 @@ def lib() -> C.CDLL:
         L.h4d_restore_checkpoint.argtypes = [vp, C.POINTER(Checkpoint), C.c_int32, dp]
         L.h4d_save_box_checkpoint.argtypes = [vp, C.c_int32, C.POINTER(Checkpoint)]
         L.h4d_restore_box_checkpoint.argtypes = [vp, C.c_int32, C.POINTER(Checkpoint), C.c_int32, dp]
-        for name in ("h4d_stream_copy", "h4d_set_timing", "h4d_get_timing", "h4d_init_system", "h4d_build_neighbors",
+        for name in ("h4d_stream_copy", "h4d_set_timing", "h4d_set_list_loads", "h4d_get_timing", "h4d_init_system", "h4d_build_neighbors",
                      "h4d_run_nemd_trial", "h4d_run_trials", "h4d_sample_observables", "h4d_get_state",
                      "h4d_set_trial_index", "h4d_forces_at", "h4d_destroy", "h4d_init_batch", "h4d_num_boxes",
                      "h4d_run_batch", "h4d_get_box_state", "h4d_box_observables", "h4d_autotune",
@@ -361,6 +362,11 @@ class _Handle:
 
     def set_timing(self, on: bool = True):
         _check(lib().h4d_set_timing(self._h, 1 if on else 0))
+
+    def set_list_loads(self, mode: int):
+        """List-index loads of the FP32 pair pass: -1 by the list's size
+        (default), 0 cached, 1 non-temporal; the results are the same."""
+        _check(lib().h4d_set_list_loads(self._h, mode))
 
     def timing(self) -> dict:
         t = Timing()

@@ -151,18 +151,46 @@ def test_fp32_lockstep_lj2000_full_flight():
     g.close()
 
 
-@pytest.mark.parametrize("lanes", [4, 16])
-def test_fp32_lockstep_water_full_size(lanes):
+@pytest.mark.parametrize("lanes,loads", [(4, -1), (16, -1), (8, 1)])
+def test_fp32_lockstep_water_full_size(lanes, loads):
     """The aqueous NaCl box (8,000 rigid waters + 150 pairs, 62 A) with the
-    flight cut to 30 steps of 1 fs: one insertion and one deletion."""
-    say(f"case fp32 lockstep aqueous NaCl full size, {lanes} lanes, N_f = 30")
+    flight cut to 30 steps of 1 fs: one insertion and one deletion.  The
+    third case runs the instantiation the bench times on this machine's eight
+    replicas: 8 lanes per atom with non-temporal list loads."""
+    say(f"case fp32 lockstep aqueous NaCl full size, {lanes} lanes, list loads {loads}, N_f = 30")
     w = W.config_water_nacl()
     w.params.update(n_steps=30, lanes_per_atom=lanes, beta_mu=-120.0)
     beta = 1.0 / w.params["kT"]
     g = h4d.System.from_workload(w)
+    g.set_list_loads(loads)
+    if loads >= 0:
+        assert g.timing()["nt_lists"] == loads
     pairs = lockstep(g, w.params, (1, -1), n_mol=w.n_mol)
-    compare_lockstep(pairs, beta, f"water/L{lanes}")
+    compare_lockstep(pairs, beta, f"water/L{lanes}/loads{loads}")
     g.close()
+
+
+def test_list_load_kinds_give_identical_trials():
+    """The pair pass with cached and with non-temporal list-index loads gives
+    the same records and states, bitwise (an FP32 batch of small boxes,
+    three rounds from the same start)."""
+    from test_gpu_batch import small_boxes
+    say("case list-load kinds, fp32 batch, 3 rounds each")
+    out = []
+    for mode in (0, 1):
+        ws = small_boxes("fp32", 30, 60, seed=2202)
+        bat = h4d.Batch.from_workloads(ws)
+        bat.set_list_loads(mode)
+        assert bat.timing()["nt_lists"] == mode
+        recs = bat.run(3)
+        out.append((recs, [bat.box_state(b) for b in range(len(ws))]))
+        bat.close()
+    (r0, s0), (r1, s1) = out
+    for b in range(len(r0)):
+        for q in range(3):
+            for k in ("move", "accepted", "trial", "n_steps", "dH", "W_prot", "E_switch"):
+                assert r0[b][q][k] == r1[b][q][k], (b, q, k, r0[b][q][k], r1[b][q][k])
+        assert np.array_equal(s0[b]["x"], s1[b]["x"]), b
 
 
 @pytest.mark.parametrize("lanes", [4, 16])
