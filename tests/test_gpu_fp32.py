@@ -234,10 +234,12 @@ def test_fp32_batch_lockstep_per_box(lanes):
 
 def test_fp32_full_size_batch_lockstep_sampled_boxes():
     """The full 256-box batch (2.2 M ions, N in [1000, 16000], density
-    0.1-0.4, N_f ~ U{100..400}) at the 4 lanes per atom the bench tunes to:
-    one round, and for a sample of boxes (the smallest, the largest and
-    three others) the oracle's whole trial from that box's start state
-    within the FP32 bound, with the same move, sites, N_f and decision."""
+    0.1-0.4, N_f ~ U{100..400}) at the 4 lanes per atom the bench tunes to,
+    with the non-temporal list loads its size selects (the instantiation the
+    bench times): one round, and for a sample of boxes (the smallest, the
+    largest and three others) the oracle's whole trial from that box's start
+    state within the FP32 bound, with the same move, sites, N_f and
+    decision."""
     say("case fp32 full-size batch (256 boxes), one round, 5 boxes through the oracle")
     ws = W.config_batched()
     for w in ws:
@@ -245,7 +247,8 @@ def test_fp32_full_size_batch_lockstep_sampled_boxes():
     sizes = [w.n for w in ws]
     sample = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 0, 77, 254})
     bat = h4d.Batch.from_workloads(ws)
-    assert bat.timing()["lanes"] == 4
+    tm = bat.timing()
+    assert tm["lanes"] == 4 and tm["nt_lists"] == 1
     states = {b: bat.box_state(b) for b in sample}
     recs = bat.run(1)
     jobs = [oracle_pool.job(ws[b].params, states[b], recs[b][0]["trial"]) for b in sample]
