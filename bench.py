@@ -843,9 +843,9 @@ def main():
     ap.add_argument("--batch-beta-mu", type=float, default=-4.0, help="batched: beta mu")
     ap.add_argument("--fixed-nf", type=int, default=0,
                     help="batched: every trial N_f steps (0: N_f ~ U{100..400} per trial, the workload's own)")
-    ap.add_argument("--pilot", type=int, default=500,
+    ap.add_argument("--pilot", type=int, default=2000,
                     help="nacl: pilot insertions (0: no learned study, both arms uniform; needs --beta-mu)")
-    ap.add_argument("--pilot-del", type=int, default=250, help="nacl: pilot deletions")
+    ap.add_argument("--pilot-del", type=int, default=1000, help="nacl: pilot deletions")
     ap.add_argument("--train-epochs", type=int, default=30, help="nacl: passes over the pilot data")
     ap.add_argument("--candidates", type=int, default=CANDIDATES, help="nacl: candidate sites per learned move")
     ap.add_argument("--scale", type=float, default=None, help="nacl: weight scale (default: chosen from the pilot)")
