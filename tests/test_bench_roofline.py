@@ -2,7 +2,9 @@
 roofline against HBM with the algorithmic bytes 4 n_list + 36 of the pair
 pass plus 120 of the integration, the FLOP fraction beside it, the
 acceptance summary of trial records, and the log-space acceptance and
-gain of the fixed-state comparison."""
+gain of the fixed-state comparison; the committed counter summaries match
+the kernel sources and the instantiation they name; the refusal of long
+256-box runs; the per-launch-shape kernel summary."""
 import math
 import os
 import sys
@@ -71,3 +73,44 @@ def test_bench_line_is_strict_json():
     line = {"a": -math.inf, "b": [1.0, math.nan, {"c": math.inf}], "d": "x", "e": 2}
     out = json.dumps(bench.finite_json(line), allow_nan=False)
     assert json.loads(out) == {"a": None, "b": [1.0, None, {"c": None}], "d": "x", "e": 2}
+
+
+def test_committed_counter_summaries_describe_the_current_kernels():
+    # every traffic summary the bench reads was taken on the kernel sources as
+    # they are, and names the instantiation (lanes per atom, list-load kind)
+    # it measured; the bench finds each one for exactly that instantiation
+    from paper_2307_11447_amd import rocprof_summary
+    h = rocprof_summary.kernel_source_hash()
+    for workload, files in bench.TRAFFIC_FILES.items():
+        for path in files:
+            kv = bench._summary_fields(path)
+            assert kv["kernel_source_sha256"] == h, path
+            lanes, nt = int(kv["lanes_per_atom"]), int(kv["nontemporal_lists"])
+            timing = {"lanes": lanes, "nt_lists": nt}
+            assert bench.counted_traffic(workload, timing) == float(kv["traffic_bytes_per_launch"]), path
+            assert bench.counted_traffic(workload, {"lanes": lanes, "nt_lists": 1 - nt}) is None, path
+    assert bench.counted_valu_busy("water", {"lanes": 8, "nt_lists": 1}) is not None
+
+
+def test_long_runs_of_the_256_box_workload_are_refused():
+    import subprocess
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--workload", "batched", "--steps", "500",
+                        "--no-cpu-baseline"], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "at most 7 trials per box" in r.stderr, (r.returncode, r.stderr)
+
+
+def test_rocprof_shapes_groups_a_kernel_by_launch_shape(tmp_path):
+    import sqlite3
+    from paper_2307_11447_amd import rocprof_summary
+    path = str(tmp_path / "run_results.db")
+    db = sqlite3.connect(path)
+    db.execute("create table kernels(name text, grid_size int, duration int, start int, end int)")
+    for g, du in [(1000, 5000), (1000, 7000), (2000, 100)]:
+        db.execute("insert into kernels values (?, ?, ?, 0, 1)", ("void h4d::k_step<1, 8, false, true>", g, du))
+    db.execute("insert into kernels values (?, ?, ?, 0, 1)", ("h4d::k_settle", 1000, 9))
+    db.commit()
+    rows = rocprof_summary.shapes(path, "k_step<1").splitlines()
+    assert len(rows) == 3 and "grid_size" in rows[0]
+    first = rows[1].split()
+    assert first[-6:] == ["1000", "2", "0.012", "6.00", "5.00", "7.00"], rows
+    assert rows[2].split()[-5] == "1"
