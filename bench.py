@@ -815,6 +815,66 @@ def leg_batched(args, h4d, W, torch, steps, warmup, timing_trials, learned_k=0):
     return out, ws
 
 
+def batched_learned_vs_plain(args, h4d, W, torch, trials, k=256, scales=(0.5, 1.0), pilot_boxes=16,
+                             pilot_per_box=64):
+    """The 256-box batch with the learned proposal against the uniform one:
+    a network trained on forced uniform insertions in 16 of the boxes (spread
+    over their density range, one box at a time), then one fresh batch per
+    arm from the same start state running `trials` trials per box at the
+    workload's beta mu, where insertions are often accepted: accepted
+    exchanges per second and the insertion and deletion acceptances with
+    their Wilson intervals."""
+    import numpy as np
+    ws = W.config_batched()
+    for w in ws:
+        w.params.update(beta_mu=args.batch_beta_mu, lanes_per_atom=4)
+    beta = 1.0 / ws[0].params["kT"]
+    dens = np.array([w.n / np.prod(w.params["box"]) for w in ws])
+    pick = np.argsort(dens)[np.linspace(0, len(ws) - 1, pilot_boxes).astype(int)]
+    X, y = [], []
+    t0 = time.perf_counter()
+    for b in pick:
+        one = h4d.System.from_workload(ws[int(b)])
+        recs, feats, _ = pilot(one, h4d, pilot_per_box, 0)["ins"]
+        one.close()
+        for r, f in zip(recs, feats):
+            if not r["flags"] & 0x3 and math.isfinite(r["dH"]):
+                X.append(f)
+                y.append(-beta * r["dH"])
+    pilot_s = time.perf_counter() - t0
+    X = np.array(X, dtype=np.float32)
+    y = np.array(y)
+    y = y - y.mean()
+    sd = y.std()
+    y = np.clip(y, -8.0 * sd, 8.0 * sd).astype(np.float32)
+    cap = float(y.max())
+    oof = out_of_fold(h4d, X, y, args.train_epochs)
+    net, _, _ = train_network(h4d, X, y, args.train_epochs)
+    oof_corr = float(np.corrcoef(oof, y)[0, 1]) if np.std(oof) > 0 else None
+    arms = {}
+    for name, scale in [("plain", 0.0)] + [(f"learned_scale{sc}", sc) for sc in scales]:
+        bat = h4d.Batch.from_workloads(ws)
+        if scale > 0.0:
+            bat.set_proposal(net, k, cap, scale)
+        arr, wall = timed(torch, lambda: bat.run(trials, as_array=True))
+        arms[name] = arm_summary([arr[q] for q in range(len(ws) * trials)], wall)
+        arms[name]["value"] = arms[name].pop("atom_steps_per_s")
+        bat.close()
+        note(f"batched256 {name}: {arms[name]['accepted']} of {arms[name]['trials']} accepted, "
+             f"{arms[name]['accepted_exchanges_per_s']:.1f} exchanges/s")
+    net.close()
+    pa = arms["plain"]
+    return {
+        "pilot": {"boxes": [int(b) for b in pick], "insertions": int(len(y)), "seconds": pilot_s,
+                  "out_of_fold_correlation": oof_corr},
+        "candidates": k, "trials_per_box": trials, "beta_mu": args.batch_beta_mu,
+        "arms": arms,
+        "accepted_exchanges_per_s_ratio": {name: (a["accepted_exchanges_per_s"] / pa["accepted_exchanges_per_s"]
+                                                  if pa["accepted"] > 0 else None)
+                                           for name, a in arms.items() if name != "plain"},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -841,6 +901,8 @@ def main():
     ap.add_argument("--select-trials", type=int, default=60,
                     help="forced insertions and deletions per weight scale when choosing it")
     ap.add_argument("--batch-beta-mu", type=float, default=-4.0, help="batched: beta mu")
+    ap.add_argument("--batch-learned-trials", type=int, default=4,
+                    help="batched: trials per box of each arm of the learned-vs-plain comparison (0: none)")
     ap.add_argument("--fixed-nf", type=int, default=0,
                     help="batched: every trial N_f steps (0: N_f ~ U{100..400} per trial, the workload's own)")
     ap.add_argument("--pilot", type=int, default=2000,
@@ -883,7 +945,8 @@ def main():
         args.warmup = {"nacl": 5, "lj32k": 20, "batched": 2}[wl]
     if args.timing_trials is None:
         args.timing_trials = {"nacl": 4, "lj32k": 20, "batched": 1}[wl]
-    if wl == "batched" and args.warmup + args.steps + args.timing_trials > BATCHED_MAX_TRIALS:
+    if args.batch_learned_trials > BATCHED_MAX_TRIALS or (
+            wl == "batched" and args.warmup + args.steps + args.timing_trials > BATCHED_MAX_TRIALS):
         print(f"bench.py: the 256-box workload runs at most {BATCHED_MAX_TRIALS} trials per box after the "
               "autotuner (warmup + steps + timing trials): longer runs of it have faulted the GPU and the "
               "cause is not established", file=sys.stderr)
@@ -909,6 +972,9 @@ def main():
                 extras["lj32k"]["cpu_baseline"] = cpu_baseline(w32, 200, "the 32,000-ion state",
                                                                extras["lj32k"]["config"]["beta_mu"])
             extras["batched256"], _ = leg_batched(args, h4d, W, torch, 2, 1, 1)
+            if args.batch_learned_trials > 0:
+                extras["batched256"]["learned_vs_plain"] = batched_learned_vs_plain(args, h4d, W, torch,
+                                                                                    args.batch_learned_trials)
             extras["lj500"] = leg_lj500(args, h4d, W, torch)
     elif wl == "lj32k":
         out, w32 = leg_lj32k(args, h4d, W, torch, args.steps, args.warmup, args.timing_trials)
@@ -917,6 +983,8 @@ def main():
                                                               config["beta_mu"])
     else:
         out, ws = leg_batched(args, h4d, W, torch, args.steps, args.warmup, args.timing_trials)
+        if args.batch_learned_trials > 0:
+            out["learned_vs_plain"] = batched_learned_vs_plain(args, h4d, W, torch, args.batch_learned_trials)
         config = out.pop("config")
         big = max(ws, key=lambda w: w.n)
         base = None if args.no_cpu_baseline else cpu_baseline(big, args.cpu_steps or 100,
