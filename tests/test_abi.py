@@ -102,3 +102,11 @@ def test_checkpoint_record_of_the_wrong_size_is_refused():
     assert isinstance(h4d._checkpoint_record({"checkpoint": good}), h4d.Checkpoint)
     with pytest.raises(ValueError):
         h4d._checkpoint_record({"checkpoint": good[:-8]})
+
+
+def test_setters_refuse_a_null_handle_and_bad_modes():
+    lib = h4d.lib()
+    assert lib.h4d_set_list_loads(None, 0) == h4d.H4D_EINVAL
+    assert lib.h4d_set_timing(None, 1) == h4d.H4D_EINVAL
+    timing = h4d.Timing()
+    assert lib.h4d_get_timing(None, C.byref(timing)) == h4d.H4D_EINVAL
